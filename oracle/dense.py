@@ -1,0 +1,117 @@
+"""Dense-grid FP64 finite-difference solver (oracle O1).
+
+The same scheme the MPS method discretises, evaluated on the full grid:
+
+* Vlasov equation without collisions, one electron species (Problem
+  Statement, eq. 1 with C = 0):  df/dt = -v df/dx - (q/m) E df/dv.
+* Poisson + E = -dphi/dx (Problem Statement, eqs. 2-3) with an immobile
+  neutralising background: the periodic 3-point Laplacian is singular, so
+  phi = L^+ n (pseudo-inverse; the constant background drops out because
+  L^+ 1 = 0) and E = -Dx phi with the same periodic central difference.
+* Periodic second-order central difference in x (SI, "First Derivative,
+  Centered, Periodic Boundary Conditions").
+* Central difference in v with zero-gradient boundaries by a mirrored ghost
+  point, which makes the derivative vanish at the first and last node (SI,
+  "First Derivative, Centered, Zero Gradient Boundary Conditions").
+* Left Riemann sum for integrals (SI, "Integration").
+* Classic RK4 with a fixed step (SI, "Compressed time evolution algorithm").
+
+TEST INFRASTRUCTURE ONLY -- see ``oracle/__init__``.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def density(F: np.ndarray, dv: float) -> np.ndarray:
+    """n_i = dv * sum_j F_ij  (SI, Integration: left Riemann sum)."""
+    return dv * F.sum(axis=1)
+
+
+def poisson_field(n: np.ndarray, dx: float) -> np.ndarray:
+    """E = -Dx L^+ n on the periodic grid (Problem Statement eqs. 2-3).
+
+    L (periodic 3-point Laplacian) and Dx (periodic central difference) are
+    circulant, so the discrete Fourier transform diagonalises both: mode
+    theta = 2 pi q / N has L -> -4 sin^2(theta/2)/dx^2 and Dx -> i sin(theta)/dx.
+    The pseudo-inverse maps the q = 0 mode (the neutralising background) to 0.
+    """
+    N = n.size
+    nh = np.fft.fft(n)
+    theta = 2.0 * np.pi * np.arange(N) / N
+    lam_L = -4.0 * np.sin(theta / 2.0) ** 2 / dx ** 2
+    lam_D = 1j * np.sin(theta) / dx
+    Eh = np.zeros_like(nh)
+    nz = np.arange(N) != 0
+    Eh[nz] = -lam_D[nz] * nh[nz] / lam_L[nz]
+    return np.real(np.fft.ifft(Eh))
+
+
+def poisson_field_dense(n: np.ndarray, dx: float) -> np.ndarray:
+    """Same field with explicit matrices: E = -Dx pinv(L) n (small N only).
+    The paper's own route for the inverse Laplacian: build the matrix, invert
+    it (SI, "Inverse Laplacian")."""
+    N = n.size
+    L = np.zeros((N, N))
+    Dx = np.zeros((N, N))
+    for i in range(N):
+        L[i, i] = -2.0
+        L[i, (i + 1) % N] += 1.0
+        L[i, (i - 1) % N] += 1.0
+        Dx[i, (i + 1) % N] += 0.5
+        Dx[i, (i - 1) % N] -= 0.5
+    L /= dx ** 2
+    Dx /= dx
+    return -Dx @ np.linalg.pinv(L) @ n
+
+
+def ddx(F: np.ndarray, dx: float) -> np.ndarray:
+    """(F_{i+1,j} - F_{i-1,j}) / (2 dx), i periodic."""
+    return (np.roll(F, -1, axis=0) - np.roll(F, 1, axis=0)) / (2.0 * dx)
+
+
+def ddv(F: np.ndarray, dv: float) -> np.ndarray:
+    """(F_{i,j+1} - F_{i,j-1}) / (2 dv) inside, 0 at j = 0 and j = Nv-1."""
+    out = np.zeros_like(F)
+    out[:, 1:-1] = (F[:, 2:] - F[:, :-2]) / (2.0 * dv)
+    return out
+
+
+def field(F: np.ndarray, p) -> np.ndarray:
+    return poisson_field(density(F, p.dv), p.dx)
+
+
+def rhs(F: np.ndarray, p) -> np.ndarray:
+    """R(F) = -v Dx F - (q/m) E Dv F  (eq. 1, C = 0)."""
+    E = field(F, p)
+    v = p.v()
+    return -v[None, :] * ddx(F, p.dx) - p.qm * E[:, None] * ddv(F, p.dv)
+
+
+def rk4_step(F: np.ndarray, p, dt: float | None = None) -> np.ndarray:
+    """f_{n+1} = f_n + dt/6 (k1 + 2 k2 + 2 k3 + k4)  (SI, RK4)."""
+    h = p.dt if dt is None else dt
+    k1 = rhs(F, p)
+    k2 = rhs(F + 0.5 * h * k1, p)
+    k3 = rhs(F + 0.5 * h * k2, p)
+    k4 = rhs(F + h * k3, p)
+    return F + (h / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+
+
+def initial(ax: np.ndarray, bv: np.ndarray) -> np.ndarray:
+    """f0(x_i, v_j) = sum_r ax[r, i] bv[r, j]."""
+    return np.einsum("ri,rj->ij", ax, bv)
+
+
+def diagnostics(F: np.ndarray, p) -> dict:
+    """Mass, momentum, kinetic energy (left Riemann sums) and field energy
+    W_E = 1/2 dx sum_i E_i^2."""
+    v = p.v()
+    w = p.dx * p.dv
+    E = field(F, p)
+    return {
+        "mass": w * F.sum(),
+        "momentum": w * (F * v[None, :]).sum(),
+        "kinetic": 0.5 * w * (F * (v ** 2)[None, :]).sum(),
+        "field_energy": 0.5 * p.dx * float(np.sum(E ** 2)),
+    }

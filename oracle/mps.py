@@ -1,0 +1,600 @@
+"""CPU MPS reference in FP64 (oracle O2): the method itself, step by step.
+
+An MPS is a list of cores ``A[j]`` with shape (left bond, 2, right bond);
+site 0 is the most significant (coarsest) bit.  An MPO is a list of tensors
+``W[j]`` with shape (left bond, out bit o, in bit i, right bond).
+
+Sections of the paper followed here:
+* Method overview, "MPS Representation of Classical Data": vector -> MPS by
+  iterated SVD (eq. 4); per-bond error eps_j (eq. 5); full-rank bonds
+  r_j = d^min(j, KL-j).
+* SI "Matrix-vector multiplication": C(o) = sum_i B(o, i) A(i), bond product.
+* SI "Addition": block-diagonal cores, bond sum.
+* SI "Derivatives": the printed MPOs for the periodic central first
+  derivative, the non-periodic backbone plus boundary matrices, and the
+  periodic second derivative.
+* SI "Dot Product": MPS -> diagonal MPO, M(o, i) = M(i) delta_{io}.
+* SI "Inverse Laplacian": dense inverse converted into an MPO.
+* SI "Integration": dx [1, 1]^{(x) L}.
+* SI "Canonicalization and Compression": QR sweep then truncated SVD sweep.
+* SI "Compressed time evolution algorithm": RK4 and compression levels C1-C5.
+* Results, "State Compressibility" (eq. 6 context) and Fig. 3 orderings:
+  sequential S1 and interleaved IF maps.
+
+Readings where the paper is silent or garbled (each also listed in the design doc):
+* The printed M_left of the zero-gradient derivative puts its only entry at
+  (o, i) = (N/2-1, N-1); the mirror image of the printed M_right is used
+  instead, P0^{(x)(L-1)} (x) [[0, -c1], [0, 0]], so rows 0 and N-1 vanish.
+* eps_j sums the discarded values i = D+1 .. r_j (keep the D largest).
+* Sweep order: QR left-to-right, then truncated SVD right-to-left; the
+  norm ends in the first core.
+* Rank rule: D = min(chi, min{D' >= 1 : sum_{i>D'} s~_i^2 <= tol^2}) with
+  s~ = s / ||s||; tol = 0 keeps min(chi, len(s)).
+* Compression points: P1 final state, P2 each stage state, P3 the sum of
+  the k's, P4 each k, P5 each term of a k.  Every point truncates with tol;
+  level C_l caps P1..P_l at chi (C1: only the final state is capped).
+* The field MPS is compressed with tol and an optional cap D_F.
+
+TEST INFRASTRUCTURE ONLY -- see ``oracle/__init__``.
+"""
+from __future__ import annotations
+
+import math
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+Mps = List[np.ndarray]
+Mpo = List[np.ndarray]
+
+# ---------------------------------------------------------------- basics
+
+I2 = np.eye(2)
+SP = np.array([[0.0, 0.0], [1.0, 0.0]])   # S+ : (o, i) = (1, 0)
+SM = np.array([[0.0, 1.0], [0.0, 0.0]])   # S- : (o, i) = (0, 1)
+Z2 = np.zeros((2, 2))
+P0 = np.array([[1.0, 0.0], [0.0, 0.0]])
+P1 = np.array([[0.0, 0.0], [0.0, 1.0]])
+
+
+def rank_rule(s: np.ndarray, chi: Optional[int], tol: float) -> int:
+    """Number of singular values kept (eq. 5 with the i = D+1 reading)."""
+    k = len(s)
+    cap = k if chi is None else min(chi, k)
+    norm2 = float(np.sum(s * s))
+    if k == 0 or norm2 == 0.0:
+        return 1
+    if tol <= 0.0:
+        return max(1, cap)
+    t = (s * s) / norm2
+    # tail[D] = sum_{i >= D} t_i (0-based), summed from the smallest value
+    tail = np.cumsum(t[::-1])[::-1]
+    tail = np.append(tail, 0.0)
+    D = k
+    for Dp in range(1, k + 1):
+        if tail[Dp] <= tol * tol:
+            D = Dp
+            break
+    return max(1, min(D, cap))
+
+
+def tt_svd(vec: np.ndarray, dims: Sequence[int], tol: float = 0.0,
+           chi: Optional[int] = None) -> Mps:
+    """Vector -> MPS by iterated SVD from the left (eq. 4, Fig. 1a):
+    reshape (r_{j-1} d_j) x rest, SVD, keep U as core j, carry S V^T."""
+    cores = []
+    r = 1
+    M = np.asarray(vec, dtype=np.float64).reshape(1, -1)
+    for j, d in enumerate(dims[:-1]):
+        M = M.reshape(r * d, -1)
+        U, S, Vt = np.linalg.svd(M, full_matrices=False)
+        D = rank_rule(S, chi, tol)
+        cores.append(U[:, :D].reshape(r, d, D))
+        M = S[:D, None] * Vt[:D]
+        r = D
+    cores.append(M.reshape(r, dims[-1], 1))
+    return cores
+
+
+def to_vector(mps: Mps) -> np.ndarray:
+    """Contract all bonds: the represented vector, site 0 most significant."""
+    v = mps[0].reshape(mps[0].shape[1], -1)
+    for A in mps[1:]:
+        v = (v @ A.reshape(A.shape[0], -1)).reshape(-1, A.shape[2])
+    return v.reshape(-1)
+
+
+def bond_dims(mps: Mps) -> List[int]:
+    return [A.shape[2] for A in mps[:-1]]
+
+
+def scale(mps: Mps, c: float) -> Mps:
+    out = [A.copy() for A in mps]
+    out[0] = out[0] * c
+    return out
+
+
+# ------------------------------------------------- MPO x MPS, sum, diag
+
+def apply(W: Mpo, A: Mps) -> Mps:
+    """SI, Matrix-vector multiplication: C^{(n)}_{(a,b),(a',b')}(o) =
+    sum_i B_{b,b'}(o, i) A_{a,a'}(i); fused bond gamma = (alpha, beta)."""
+    out = []
+    for Wj, Aj in zip(W, A):
+        C = np.einsum("bois,aic->abocs", Wj, Aj)
+        a, b, o, c, s = C.shape
+        out.append(C.reshape(a * b, o, c * s))
+    return out
+
+
+def add(terms: Sequence[Tuple[float, Mps]]) -> Mps:
+    """SI, Addition: block-diagonal cores, bond = sum of bonds.  The scalar
+    of each term is folded into its first core."""
+    n = len(terms[0][1])
+    out = []
+    for j in range(n):
+        blocks = [(c if j == 0 else 1.0) * m[j] for c, m in terms]
+        if n == 1:
+            out.append(sum(blocks))
+            continue
+        if j == 0:
+            out.append(np.concatenate(blocks, axis=2))
+        elif j == n - 1:
+            out.append(np.concatenate(blocks, axis=0))
+        else:
+            L = sum(b.shape[0] for b in blocks)
+            R = sum(b.shape[2] for b in blocks)
+            C = np.zeros((L, 2, R))
+            l0 = r0 = 0
+            for b in blocks:
+                C[l0:l0 + b.shape[0], :, r0:r0 + b.shape[2]] = b
+                l0 += b.shape[0]
+                r0 += b.shape[2]
+            out.append(C)
+    return out
+
+
+def diag_mpo(mps: Mps) -> Mpo:
+    """SI, Dot Product: M_{l,r}(o, i) = M_{l,r}(i) delta_{io}."""
+    out = []
+    for A in mps:
+        a, d, b = A.shape
+        W = np.zeros((a, d, d, b))
+        for s in range(d):
+            W[:, s, s, :] = A[:, s, :]
+        out.append(W)
+    return out
+
+
+def inner(A: Mps, B: Mps) -> float:
+    """<A, B> = sum over all indices of A * B (transfer-matrix contraction)."""
+    E = np.ones((1, 1))
+    for a, b in zip(A, B):
+        E = np.einsum("xy,xsp,ysq->pq", E, a, b)
+    return float(E[0, 0])
+
+
+# ------------------------------------------------------ compression
+
+def compress(mps: Mps, chi: Optional[int], tol: float,
+             return_discarded: bool = False):
+    """SI, Canonicalization and Compression.
+
+    (i) QR sweep left to right: A_j as (a*2) x b = Q R, A_j <- Q,
+        A_{j+1} <- R A_{j+1}.
+    (ii) truncated SVD sweep right to left: A_j as a x (2*b) = U S V^T, keep D
+        by the rank rule, A_j <- V^T_D, A_{j-1} <- A_{j-1} U_D S_D.
+    Returns the compressed MPS (and the relative discarded weight per bond,
+    eps_j of eq. 5, if asked)."""
+    A = [c.copy() for c in mps]
+    n = len(A)
+    for j in range(n - 1):
+        a, d, b = A[j].shape
+        Q, R = np.linalg.qr(A[j].reshape(a * d, b))
+        A[j] = Q.reshape(a, d, Q.shape[1])
+        A[j + 1] = np.tensordot(R, A[j + 1], axes=(1, 0))
+    disc = [0.0] * (n - 1)
+    for j in range(n - 1, 0, -1):
+        a, d, b = A[j].shape
+        U, S, Vt = np.linalg.svd(A[j].reshape(a, d * b), full_matrices=False)
+        D = rank_rule(S, chi, tol)
+        nrm2 = float(np.sum(S * S))
+        disc[j - 1] = math.sqrt(float(np.sum(S[D:] ** 2)) / nrm2) if nrm2 > 0 else 0.0
+        A[j] = Vt[:D].reshape(D, d, b)
+        A[j - 1] = np.tensordot(A[j - 1], U[:, :D] * S[:D], axes=(2, 0))
+    return (A, disc) if return_discarded else A
+
+
+def left_canonicalize(mps: Mps) -> Mps:
+    """Only the QR sweep of `compress` (left canonical form, SI)."""
+    A = [c.copy() for c in mps]
+    for j in range(len(A) - 1):
+        a, d, b = A[j].shape
+        Q, R = np.linalg.qr(A[j].reshape(a * d, b))
+        A[j] = Q.reshape(a, d, Q.shape[1])
+        A[j + 1] = np.tensordot(R, A[j + 1], axes=(1, 0))
+    return A
+
+
+def entanglement_entropy(mps: Mps) -> List[float]:
+    """Eq. 6 at every bond, from the untruncated sweep's singular values."""
+    A = left_canonicalize(mps)
+    n = len(A)
+    out = [0.0] * (n - 1)
+    for j in range(n - 1, 0, -1):
+        a, d, b = A[j].shape
+        U, S, Vt = np.linalg.svd(A[j].reshape(a, d * b), full_matrices=False)
+        t = S * S / np.sum(S * S)
+        t = t[t > 0]
+        out[j - 1] = float(-np.sum(t * np.log2(t)))
+        A[j] = Vt.reshape(-1, d, b)
+        A[j - 1] = np.tensordot(A[j - 1], U * S, axes=(2, 0))
+    return out
+
+
+# ------------------------------------------------------ operator MPOs
+
+def _chain(first, bulk, last, L: int) -> Mpo:
+    """Turn the printed operator-valued row/matrix/column form into MPO
+    tensors W[bl, o, i, br] (site 0 = first factor)."""
+    def tens(rows):
+        rows = [[np.asarray(x, dtype=np.float64) for x in r] for r in rows]
+        bl, br = len(rows), len(rows[0])
+        W = np.zeros((bl, 2, 2, br))
+        for a in range(bl):
+            for b in range(br):
+                W[a, :, :, b] = rows[a][b]
+        return W
+    if L < 2:
+        raise ValueError("operator MPOs need at least two sites")
+    return [tens([first])] + [tens(bulk) for _ in range(L - 2)] + \
+        [tens([[x] for x in last])]
+
+
+def mpo_d1_periodic(L: int, h: float) -> Mpo:
+    """SI, First Derivative, Centered, Periodic: bond 3, c1 = 1/2, 1/h."""
+    c1 = 0.5
+    first = [I2, SP + SM, SP + SM]
+    bulk = [[I2, SM, SP], [Z2, SP, Z2], [Z2, Z2, SM]]
+    last = [c1 * (SM - SP), c1 * SP, -c1 * SM]
+    W = _chain(first, bulk, last, L)
+    W[0] = W[0] / h
+    return W
+
+
+def mpo_d1_zero_gradient(L: int, h: float) -> Mpo:
+    """SI, First Derivative, Centered, Zero Gradient: the non-periodic
+    backbone (bond 3) plus M_left and M_right (bond 1 each) as an MPO sum
+    (bond 5).  M_left is the mirror of the printed M_right (see header)."""
+    c1 = 0.5
+    first = [I2, SM, SP]
+    bulk = [[I2, SM, SP], [Z2, SP, Z2], [Z2, Z2, SM]]
+    last = [c1 * (SM - SP), c1 * SP, -c1 * SM]
+    back = _chain(first, bulk, last, L)
+    right = [P1.reshape(1, 2, 2, 1) for _ in range(L - 1)] + \
+        [np.array([[0.0, 0.0], [c1, 0.0]]).reshape(1, 2, 2, 1)]
+    left = [P0.reshape(1, 2, 2, 1) for _ in range(L - 1)] + \
+        [np.array([[0.0, -c1], [0.0, 0.0]]).reshape(1, 2, 2, 1)]
+    W = mpo_sum([back, left, right])
+    W[0] = W[0] / h
+    return W
+
+
+def mpo_d2_periodic(L: int, h: float) -> Mpo:
+    """SI, Second Derivative, Centered, Periodic: bond 3, c0 = -2, c1 = 1."""
+    c0, c1 = -2.0, 1.0
+    first = [I2, SP + SM, SP + SM]
+    bulk = [[I2, SP, SM], [Z2, SM, Z2], [Z2, Z2, SP]]
+    last = [c0 * I2 + c1 * (SM + SP), c1 * SM, c1 * SP]
+    W = _chain(first, bulk, last, L)
+    W[0] = W[0] / (h * h)
+    return W
+
+
+def mpo_sum(mpos: Sequence[Mpo]) -> Mpo:
+    """Direct sum of MPOs (SI, Addition, applied to operator-valued cores)."""
+    n = len(mpos[0])
+    out = []
+    for j in range(n):
+        blocks = [m[j] for m in mpos]
+        if j == 0:
+            out.append(np.concatenate(blocks, axis=3))
+        elif j == n - 1:
+            out.append(np.concatenate(blocks, axis=0))
+        else:
+            L = sum(b.shape[0] for b in blocks)
+            R = sum(b.shape[3] for b in blocks)
+            C = np.zeros((L, 2, 2, R))
+            l0 = r0 = 0
+            for b in blocks:
+                C[l0:l0 + b.shape[0], :, :, r0:r0 + b.shape[3]] = b
+                l0 += b.shape[0]
+                r0 += b.shape[3]
+            out.append(C)
+    return out
+
+
+def mpo_from_matrix(M: np.ndarray, L: int, tol: float = 1e-14) -> Mpo:
+    """Dense N x N operator -> MPO with the bits of (o, i) paired per site
+    (SI, Inverse Laplacian: build the matrix, then convert it)."""
+    T = M.reshape([2] * (2 * L))
+    perm = [k for j in range(L) for k in (j, L + j)]
+    vec = T.transpose(perm).reshape(-1)
+    cores = tt_svd(vec, [4] * L, tol=tol)
+    return [c.reshape(c.shape[0], 2, 2, c.shape[2]) for c in cores]
+
+
+def mpo_to_matrix(W: Mpo) -> np.ndarray:
+    """Contract an MPO to its dense N x N matrix (brute force, tests)."""
+    L = len(W)
+    T = W[0]
+    for Wj in W[1:]:
+        T = np.tensordot(T, Wj, axes=(T.ndim - 1, 0))
+    T = T.reshape([2] * (2 * L))  # axes o1 i1 o2 i2 ...
+    perm = [2 * j for j in range(L)] + [2 * j + 1 for j in range(L)]
+    N = 2 ** L
+    return T.transpose(perm).reshape(N, N)
+
+
+def poisson_mpo(L: int, dx: float, tol: float = 1e-14) -> Mpo:
+    """G = Dx L^+ as an MPO, E = -G n (Problem Statement eqs. 2-3, SI
+    "Inverse Laplacian").
+
+    The paper builds the dense inverse and converts it; for the periodic
+    central difference and the pseudo-inverse of the periodic 3-point
+    Laplacian that dense matrix has the closed form (discrete Green's
+    function, derived by diagonalising both circulants)
+        G[o, i] = dx * ( sign(o - i) / 2 - (o - i) / N ),  sign(0) = 0,
+    i.e. the sawtooth dx (1/2 - m/N) of m = (o - i) mod N with G(0) = 0.
+    Written element-wise over the paired bits (o_k, i_k), MSB first, it is
+    the sum of a comparison automaton (bond 3: equal / greater / less so
+    far) and a linear function of the bits (bond 2); the direct sum
+    (bond 5) is compressed with `tol` (exact rank 3).  The tests pin this
+    against pinv of the dense Laplacian built from the printed MPOs."""
+    if L < 2:
+        raise ValueError("operator MPOs need at least two sites")
+    N = 2 ** L
+    EQ, GT, LT = 0, 1, 2
+
+    def step(s, o, i):
+        if s != EQ:
+            return s
+        return EQ if o == i else (GT if o > i else LT)
+
+    val = [0.0, 0.5 * dx, -0.5 * dx]
+    sign = []
+    for k in range(L):
+        if k == 0:
+            W = np.zeros((1, 2, 2, 3))
+            for o in range(2):
+                for i in range(2):
+                    W[0, o, i, step(EQ, o, i)] = 1.0
+        elif k < L - 1:
+            W = np.zeros((3, 2, 2, 3))
+            for s in range(3):
+                for o in range(2):
+                    for i in range(2):
+                        W[s, o, i, step(s, o, i)] = 1.0
+        else:
+            W = np.zeros((3, 2, 2, 1))
+            for s in range(3):
+                for o in range(2):
+                    for i in range(2):
+                        W[s, o, i, 0] = val[step(s, o, i)]
+        sign.append(W)
+    lin = []
+    for k in range(L):
+        c = -dx * 2.0 ** (-1 - k)
+        d = np.array([[0.0, -1.0], [1.0, 0.0]]) * c   # c (o - i)
+        one = np.ones((2, 2))
+        if k == 0:
+            W = np.stack([one, d], axis=-1)[None]
+        elif k < L - 1:
+            W = np.zeros((2, 2, 2, 2))
+            W[0, :, :, 0] = one
+            W[0, :, :, 1] = d
+            W[1, :, :, 1] = one
+        else:
+            W = np.stack([d, one], axis=0)[..., None]
+        lin.append(W)
+    G = mpo_sum([sign, lin])
+    as_mps = [w.reshape(w.shape[0], 4, w.shape[3]) for w in G]
+    as_mps = compress(as_mps, None, tol)
+    return [c.reshape(c.shape[0], 2, 2, c.shape[2]) for c in as_mps]
+
+
+def vector_mps(vec: np.ndarray, tol: float = 1e-14) -> Mps:
+    L = int(round(math.log2(vec.size)))
+    return tt_svd(vec, [2] * L, tol=tol)
+
+
+# ------------------------------------------------------ orderings
+
+def site_map(Lx: int, Lv: int, order: int) -> List[Tuple[str, int]]:
+    """Fig. 3 orderings: 0 = S1 (x coarse->fine, then v coarse->fine),
+    1 = IF (x1, v1, x2, v2, ...)."""
+    if order == 0:
+        return [("x", k) for k in range(Lx)] + [("v", k) for k in range(Lv)]
+    if order == 1:
+        if Lx != Lv:
+            raise ValueError("interleaved ordering needs Lx == Lv")
+        out = []
+        for k in range(Lx):
+            out += [("x", k), ("v", k)]
+        return out
+    raise ValueError("unknown ordering")
+
+
+def dense_to_sites(F: np.ndarray, Lx: int, Lv: int, order: int) -> np.ndarray:
+    """F[i, j] -> vector indexed by the site bits in chain order."""
+    T = F.reshape([2] * (Lx + Lv))
+    perm = [k if d == "x" else Lx + k for d, k in site_map(Lx, Lv, order)]
+    return T.transpose(perm).reshape(-1)
+
+
+def sites_to_dense(vec: np.ndarray, Lx: int, Lv: int, order: int) -> np.ndarray:
+    perm = [k if d == "x" else Lx + k for d, k in site_map(Lx, Lv, order)]
+    T = vec.reshape([2] * (Lx + Lv))
+    inv = np.argsort(perm)
+    return T.transpose(inv).reshape(2 ** Lx, 2 ** Lv)
+
+
+def chain_mpo(Wx: Optional[Mpo], Wv: Optional[Mpo], Lx: int, Lv: int,
+              order: int) -> Mpo:
+    """Full-chain MPO of (x-operator) (x) (v-operator).  On a site of the
+    other dimension an operator acts as delta_{bl,br} I_2, so in the
+    interleaved order the bonds multiply (fused index x-major)."""
+    Wx = Wx if Wx is not None else [np.eye(2).reshape(1, 2, 2, 1)] * Lx
+    Wv = Wv if Wv is not None else [np.eye(2).reshape(1, 2, 2, 1)] * Lv
+    bx = 1   # current x bond (right bond of the last x site seen)
+    bv = 1
+    out = []
+    for d, k in site_map(Lx, Lv, order):
+        if d == "x":
+            W = Wx[k]
+            T = np.einsum("aoib,cd->acoibd", W, np.eye(bv))
+            a, c, o, i, b, dd = T.shape
+            out.append(T.reshape(a * c, o, i, b * dd))
+            bx = W.shape[3]
+        else:
+            W = Wv[k]
+            T = np.einsum("cd,aoib->caoidb", np.eye(bx), W)
+            c, a, o, i, d_, b = T.shape
+            out.append(T.reshape(c * a, o, i, d_ * b))
+            bv = W.shape[3]
+    return out
+
+
+def chain_product_mps(ux: Optional[Mps], uv: Optional[Mps], Lx: int, Lv: int,
+                      order: int) -> Mps:
+    """Full-chain MPS of a product function u(x) w(v) (same embedding)."""
+    ux = ux if ux is not None else [np.ones((1, 2, 1))] * Lx
+    uv = uv if uv is not None else [np.ones((1, 2, 1))] * Lv
+    bx = bv = 1
+    out = []
+    for d, k in site_map(Lx, Lv, order):
+        if d == "x":
+            A = ux[k]
+            T = np.einsum("asb,cd->acsbd", A, np.eye(bv))
+            a, c, s, b, e = T.shape
+            out.append(T.reshape(a * c, s, b * e))
+            bx = A.shape[2]
+        else:
+            A = uv[k]
+            T = np.einsum("cd,asb->casdb", np.eye(bx), A)
+            c, a, s, e, b = T.shape
+            out.append(T.reshape(c * a, s, e * b))
+            bv = A.shape[2]
+    return out
+
+
+# ------------------------------------------------------ physics on MPS
+
+def density_mps(f: Mps, Lx: int, Lv: int, order: int, dv: float) -> Mps:
+    """n(x) = <Iv, f>_v with Iv = dv [1,1]^{(x) Lv} (SI, Integration): each
+    v-core summed over its bit; the resulting bond matrix is absorbed into
+    the neighbouring x core.  Returns an Lx-site MPS."""
+    xs: Mps = []
+    pending = None
+    for (d, k), A in zip(site_map(Lx, Lv, order), f):
+        if d == "v":
+            M = A.sum(axis=1)
+            if xs:
+                xs[-1] = np.tensordot(xs[-1], M, axes=(2, 0))
+            else:
+                pending = M if pending is None else pending @ M
+        else:
+            C = A if pending is None else np.tensordot(pending, A, axes=(1, 0))
+            pending = None
+            xs.append(C)
+    xs[0] = xs[0] * dv
+    return xs
+
+
+class Operators:
+    """The fixed operators of one problem (built once, SI Derivatives /
+    Dot Product / Inverse Laplacian / Integration)."""
+
+    def __init__(self, p):
+        self.p = p
+        self.Dx = mpo_d1_periodic(p.Lx, p.dx)
+        self.Dv = mpo_d1_zero_gradient(p.Lv, p.dv)
+        self.V = diag_mpo(vector_mps(p.v()))
+        self.G = poisson_mpo(p.Lx, p.dx)
+        # T1 = -(Dx (x) V) f
+        self.T1 = chain_mpo(self.Dx, self.V, p.Lx, p.Lv, p.order)
+        self.T1[0] = -self.T1[0]
+
+
+def field_mps(g: Mps, ops: Operators) -> Mps:
+    """E = compress(-G n, D_F, tol)."""
+    p = ops.p
+    n = density_mps(g, p.Lx, p.Lv, p.order, p.dv)
+    En = scale(apply(ops.G, n), -1.0)
+    return compress(En, p.df_max if p.df_max > 0 else None, p.tol)
+
+
+def caps(p, point: int) -> Optional[int]:
+    """Level C_l caps compression points P1..P_l at chi."""
+    return p.chi_max if p.level >= point else None
+
+
+def rhs_mps(g: Mps, ops: Operators) -> Mps:
+    """k = R(g): T1 = -(Dx (x) V) g, T2 = -(q/m)(diag(E) (x) Dv) g, each
+    compressed (P5), then their sum compressed (P4)."""
+    p = ops.p
+    E = field_mps(g, ops)
+    WE = diag_mpo(E)
+    WE[0] = WE[0] * (-p.qm)
+    W2 = chain_mpo(WE, ops.Dv, p.Lx, p.Lv, p.order)
+    T1 = compress(apply(ops.T1, g), caps(p, 5), p.tol)
+    T2 = compress(apply(W2, g), caps(p, 5), p.tol)
+    return compress(add([(1.0, T1), (1.0, T2)]), caps(p, 4), p.tol)
+
+
+def rk4_step(f: Mps, ops: Operators) -> Mps:
+    """SI, Compressed time evolution: RK4 with compression points P1-P5."""
+    p = ops.p
+    h = p.dt
+    k1 = rhs_mps(f, ops)
+    f2 = compress(add([(1.0, f), (0.5 * h, k1)]), caps(p, 2), p.tol)
+    k2 = rhs_mps(f2, ops)
+    f3 = compress(add([(1.0, f), (0.5 * h, k2)]), caps(p, 2), p.tol)
+    k3 = rhs_mps(f3, ops)
+    f4 = compress(add([(1.0, f), (h, k3)]), caps(p, 2), p.tol)
+    k4 = rhs_mps(f4, ops)
+    S = compress(add([(1.0, k1), (2.0, k2), (2.0, k3), (1.0, k4)]),
+                 caps(p, 3), p.tol)
+    return compress(add([(1.0, f), (h / 6.0, S)]), p.chi_max, p.tol)
+
+
+def init_mps(p, ax: np.ndarray, bv: np.ndarray) -> Mps:
+    """f0 on the grid -> MPS by iterated SVD in chain order (eq. 4), then
+    compressed to (chi, tol)."""
+    F = np.einsum("ri,rj->ij", ax, bv)
+    vec = dense_to_sites(F, p.Lx, p.Lv, p.order)
+    m = tt_svd(vec, [2] * p.n_sites, tol=p.tol, chi=None)
+    return compress(m, p.chi_max, p.tol)
+
+
+def to_dense(f: Mps, p) -> np.ndarray:
+    return sites_to_dense(to_vector(f), p.Lx, p.Lv, p.order)
+
+
+def field_dense(f: Mps, ops: Operators) -> np.ndarray:
+    return to_vector(field_mps(f, ops))
+
+
+def moments(f: Mps, ops: Operators) -> dict:
+    """Mass, momentum, kinetic energy as full contractions with the product
+    MPS 1(x) w(v) (w = 1, v, v^2/2) times dx dv; field energy from E."""
+    p = ops.p
+    v = p.v()
+    out = {}
+    for name, w in (("mass", np.ones_like(v)), ("momentum", v),
+                    ("kinetic", 0.5 * v * v)):
+        g = chain_product_mps(None, vector_mps(w), p.Lx, p.Lv, p.order)
+        out[name] = p.dx * p.dv * inner(g, f)
+    E = field_dense(f, ops)
+    out["field_energy"] = 0.5 * p.dx * float(np.sum(E * E))
+    return out
