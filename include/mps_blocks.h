@@ -1,0 +1,89 @@
+/*
+ * mps_blocks.h -- the building blocks of the MPS time step, exposed so that
+ * each part of the step can be checked on its own against a CPU reference.
+ * Same conventions as mps_vlasov.h (device/host pointers, stream ordering,
+ * status codes, mps_last_error()).  All matrices are row-major FP64.
+ */
+#ifndef MPS_BLOCKS_H
+#define MPS_BLOCKS_H
+
+#include "mps_vlasov.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* C = alpha A B + beta C on the matrix cores; A: M x K (lda), B: K x N
+ * (ldb), C: M x N (ldc); device pointers. */
+mps_status mpsb_gemm(int32_t M, int32_t N, int32_t K, double alpha,
+                     const double* A, int64_t lda, const double* B,
+                     int64_t ldb, double beta, double* C, int64_t ldc,
+                     hipStream_t stream);
+
+/* Householder QR of A (m x n, device, overwritten): on return the upper
+ * trapezoid of A holds R (min(m,n) x n); if Q is not NULL it receives the
+ * thin factor Q (m x min(m,n), device).  Used by the QR left sweep (SI,
+ * "Canonicalization and Compression"). */
+mps_status mpsb_qr(int32_t m, int32_t n, double* A, double* Q,
+                   hipStream_t stream);
+
+/* Truncated SVD of X (m x c, device, overwritten) with the rank rule of the
+ * compression sweep: D = min(cap, smallest D' with relative discarded weight
+ * <= tol), cap <= 0 meaning no cap (eq. 5).  Outputs (device): Vt (D x c),
+ * US (m x D, columns u_i sigma_i), sig (min(m,c) singular values,
+ * descending, may be NULL); host: *D, *discarded.  Vt and US must hold
+ * min(m, c, cap) rows / columns. */
+mps_status mpsb_svd_truncate(int32_t m, int32_t c, double* X, int32_t cap,
+                             double tol, double* Vt, double* US, double* sig,
+                             int32_t* D, double* discarded, hipStream_t stream);
+
+/* Compress an MPS (SI, "Canonicalization and Compression"): QR sweep left
+ * to right then truncated SVD sweep right to left.  bonds_in / bonds_out:
+ * host int32[n+1]; cores: packed device arrays (see mps_get_cores);
+ * cores_out holds `capacity` doubles; discarded: host double[n-1] or NULL.
+ * If the MPO arguments are given (mpo_bonds host int32[n+1], mpo device
+ * packed W[bl][o][i][br]), the MPO is applied first (SI, "Matrix-vector
+ * multiplication") and the product is compressed without being formed. */
+mps_status mpsb_compress(int32_t n, const int32_t* mpo_bonds,
+                         const double* mpo, const int32_t* bonds_in,
+                         const double* cores_in, int32_t cap, double tol,
+                         int32_t* bonds_out, double* cores_out,
+                         int64_t capacity, double* discarded,
+                         hipStream_t stream);
+
+/* Sum of MPS terms sum_t coef[t] * g_t, compressed (SI, "Addition").
+ * bonds: host int32[nterms*(n+1)]; cores: host array of nterms device
+ * pointers to packed cores. */
+mps_status mpsb_add_compress(int32_t n, int32_t nterms, const double* coef,
+                             const int32_t* bonds, const double* const* cores,
+                             int32_t cap, double tol, int32_t* bonds_out,
+                             double* cores_out, int64_t capacity,
+                             hipStream_t stream);
+
+/* Field of the current state: the charge density n(x) as an Lx-site MPS
+ * and E = -G n compressed to (df_max, tol), both reconstructed on the
+ * grid: device double[Nx] each (n_out / E_out may be NULL). */
+mps_status mpsb_density_field(mps_state* h, double* n_out, double* E_out,
+                              hipStream_t stream);
+
+/* Operator MPOs exactly as the library builds them, for the tests:
+ * which = 0: periodic central d/dx (bond 3), 1: zero-gradient central d/dv
+ * (bond 5), 2: G = Dx L^+ (bond 5), 3: diag(v) (bond 2).  L sites, spacing
+ * h (for which = 3: v_min = h0, dv = h).  bonds: host int32[L+1]; W: host
+ * array of capacity doubles (packed W[bl][o][i][br]) or NULL to query
+ * *count. */
+mps_status mpsb_operator(int32_t which, int32_t L, double h0, double h,
+                         int32_t* bonds, double* W, int64_t* count);
+
+/* Linear-algebra counters since load: QR and SVD calls, Jacobi sweeps. */
+mps_status mpsb_stats(int64_t* qr_calls, int64_t* svd_calls,
+                      int64_t* jacobi_sweeps);
+
+/* Cap on Jacobi sweeps (default 60); a tiny cap forces MPS_ENUMERIC. */
+mps_status mpsb_set_jacobi_max_sweeps(int32_t n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPS_BLOCKS_H */

@@ -1,0 +1,151 @@
+/*
+ * mps_vlasov.h -- C-ABI of the MI355X (gfx950) MPS time stepper for the
+ * 1D1V Vlasov-Poisson equations (Ye & Loureiro, "A quantum-inspired method
+ * for solving the Vlasov-Poisson equations", arXiv:2205.11990).
+ *
+ * The distribution function f(x, v, t) lives on a uniform grid of
+ * Nx = 2^Lx by Nv = 2^Lv points and is stored as a matrix product state
+ * (quantized tensor train) with one binary site per bit (Method Overview,
+ * "MPS Representation of Classical Data", eq. 4):
+ *   x_i = x_min + i dx, dx = (x_max - x_min) / Nx, periodic (half-open);
+ *   v_j = v_min + j dv, dv = (v_max - v_min) / (Nv - 1), closed, with
+ *   zero-gradient boundaries (Methods, "Numerical Experiments").
+ * One call of mps_step advances f by classic RK4 (SI, "Compressed time
+ * evolution algorithm") of the collisionless Vlasov equation for one
+ * species with charge-to-mass ratio qm and a neutralising background
+ * (Problem Statement, eqs. 1-3): df/dt = -v df/dx - qm E df/dv,
+ * E = -d phi/dx, Laplacian(phi) = n - <n>, n = int f dv.
+ * Derivatives are the second-order central MPOs of the SI ("Derivatives"),
+ * products with E and v are diagonal MPOs (SI, "Dot Product"), the field is
+ * an MPO of the inverse Laplacian (SI, "Inverse Laplacian"), integrals are
+ * left Riemann sums (SI, "Integration").  After every operation the MPS is
+ * recompressed by a QR left-canonicalisation sweep followed by a truncated
+ * SVD right-to-left sweep (SI, "Canonicalization and Compression"), keeping
+ * at every bond at most chi values and discarding a relative weight of at
+ * most tol (eq. 5).
+ *
+ * Conventions for every entry point:
+ *  - Pointers documented as "device" are HIP device pointers owned by the
+ *    caller (e.g. torch tensors); they are only accessed during the call.
+ *    "host" pointers are ordinary CPU memory.
+ *  - Work is enqueued on `stream` (0 = the null stream).  Calls return after
+ *    the work is complete unless stated otherwise (the truncation ranks are
+ *    read back during a step, so mps_step is synchronous with `stream`).
+ *  - Errors are reported as mps_status; no C++ exception crosses the ABI.
+ *    mps_last_error() returns a thread-local description of the last
+ *    failure.  On any error the state is unchanged.
+ *  - Handles are not thread-safe: one handle, one thread at a time.
+ *  - FP64 throughout, except the optional FP32 contraction mode.
+ */
+#ifndef MPS_VLASOV_H
+#define MPS_VLASOV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MPS_OK = 0,
+  MPS_EINVAL = -1,   /* invalid argument / problem                     */
+  MPS_ENOMEM = -2,   /* device allocation failed                       */
+  MPS_ENUMERIC = -3, /* non-finite state or a factorisation failed     */
+  MPS_EDEVICE = -4   /* a HIP runtime call failed                      */
+} mps_status;
+
+typedef enum { MPS_ORDER_SEQ = 0, MPS_ORDER_INTERLEAVED = 1 } mps_order;
+
+typedef enum { MPS_PREC_FP64 = 0, MPS_PREC_FP32_CONTRACT = 1 } mps_precision;
+
+/* Problem statement.  Site orderings (Fig. 3): MPS_ORDER_SEQ is x bits
+ * coarse->fine then v bits coarse->fine (S1); MPS_ORDER_INTERLEAVED is
+ * x1, v1, x2, v2, ... (IF; needs Lx == Lv).  Compression level (SI,
+ * compression levels C1..C5): the final state (P1), the stage states (P2),
+ * the sum of the k's (P3), each k (P4) and each term of a k (P5) are all
+ * truncated with `tol`; level l additionally caps P1..Pl at chi_max. */
+typedef struct mps_problem {
+  int32_t Lx, Lv;           /* bits per dimension, each in [2, 14]        */
+  int32_t order;            /* mps_order                                   */
+  double x_min, x_max;      /* periodic interval, x_max > x_min            */
+  double v_min, v_max;      /* closed interval, v_max > v_min              */
+  double qm;                /* charge / mass of the species (-1: electrons)*/
+  double dt;                /* fixed RK4 step, > 0                         */
+  int32_t chi_max;          /* bond cap (paper D), >= 1                    */
+  int32_t level;            /* compression level 1..5 (1 = C1)             */
+  int32_t df_max;           /* cap on the field bond D_F, 0 = uncapped     */
+  double tol;               /* relative discarded weight per bond, >= 0    */
+  int32_t precision;        /* mps_precision                               */
+} mps_problem;
+
+typedef struct mps_state mps_state; /* opaque; owns all device memory */
+
+/* Create a state from f0(x_i, v_j) = sum_{r<rank} ax[r*Nx + i] * bv[r*Nv + j]
+ * (device FP64 arrays).  Each 1-D profile is converted by iterated SVD
+ * (eq. 4), the terms are combined per ordering, summed and compressed to
+ * (chi_max, tol).  Returns MPS_EINVAL for invalid problems or non-finite
+ * profiles. */
+mps_status mps_init(const mps_problem* p, int32_t rank, const double* ax,
+                    const double* bv, hipStream_t stream, mps_state** out);
+
+/* Advance by nsteps RK4 steps.  Each step commits only if the new state is
+ * finite and every factorisation converged; otherwise MPS_ENUMERIC is
+ * returned and the state is the last good one. */
+mps_status mps_step(mps_state* h, int32_t nsteps, hipStream_t stream);
+
+/* Moments of the current state.  n_out, E_out: device double[Nx] or NULL
+ * (density n = int f dv and field E).  scalars: host double[4] or NULL =
+ * {mass, momentum, kinetic energy, field energy} = dx dv sum f,
+ * dx dv sum v f, dx dv sum v^2 f / 2, dx sum E^2 / 2. */
+mps_status mps_moments(mps_state* h, double* n_out, double* E_out,
+                       double* scalars, hipStream_t stream);
+
+/* Reconstruct f on the grid: device double[Nx*Nv], f_out[i*Nv + j]. */
+mps_status mps_to_dense(mps_state* h, double* f_out, hipStream_t stream);
+
+/* Release the state and all its device memory.  NULL is accepted. */
+mps_status mps_free(mps_state* h);
+
+/* Query.  Any output may be NULL.  n_sites: host int32; bond_dims: host
+ * int32[n+1] (bond_dims[0] = bond_dims[n] = 1); discarded: host
+ * double[n-1], relative discarded weight per bond of the last final
+ * compression; t: host double (simulated time); steps: host int64. */
+mps_status mps_info(const mps_state* h, int32_t* n_sites, int32_t* bond_dims,
+                    double* discarded, double* t, int64_t* steps);
+
+/* Export / import the state.  Cores are packed in site order, core j of
+ * shape bond[j] x 2 x bond[j+1] row-major.  mps_get_cores with cores ==
+ * NULL only reports bond_dims (host int32[n+1]) and *count (host int64,
+ * total doubles).  cores: device.  mps_set_cores replaces the state (used
+ * for checkpoint / resume and to start the oracle and the GPU from the same
+ * MPS). */
+mps_status mps_get_cores(const mps_state* h, int32_t* bond_dims,
+                         int64_t* count, double* cores, hipStream_t stream);
+mps_status mps_set_cores(mps_state* h, const int32_t* bond_dims,
+                         const double* cores, hipStream_t stream);
+
+/* f <- compress(f + alpha g, chi_max, tol) for an MPS g given as packed
+ * device cores with host bond_dims[n+1] (SI, "Addition"). */
+mps_status mps_add_scaled(mps_state* h, double alpha, const int32_t* bond_dims,
+                          const double* cores, hipStream_t stream);
+
+/* Upper bound of the device bytes a state of problem p holds between
+ * steps plus the largest per-step workspace when every compression point
+ * is capped at chi_max (for admission control).  Host output. */
+mps_status mps_workspace_bound(const mps_problem* p, size_t* bytes);
+
+/* Advance several independent states by nsteps each (same stream). */
+mps_status mps_step_batched(mps_state* const* hs, int32_t count, int32_t nsteps,
+                            hipStream_t stream);
+
+/* Thread-local text of the last error ("" if none). */
+const char* mps_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPS_VLASOV_H */

@@ -1,0 +1,94 @@
+// Device memory arena: stack-like sub-allocation out of large hipMalloc'd
+// chunks that are kept for the lifetime of the owning state, so that steady
+// state time stepping performs no device allocation at all.
+#pragma once
+#include <vector>
+
+#include "common.hpp"
+
+namespace mpsv {
+
+class Arena {
+ public:
+  struct Mark {
+    size_t chunk, off;
+  };
+
+  explicit Arena(size_t chunk_bytes = (size_t)256 << 20) : chunk_(chunk_bytes) {}
+  ~Arena() { release_all(); }
+  Arena(const Arena&) = delete;
+  Arena& operator=(const Arena&) = delete;
+
+  // 256-byte aligned allocation of n doubles (n may be 0).
+  double* alloc(size_t n) { return (double*)alloc_bytes(n * sizeof(double)); }
+  int* alloc_int(size_t n) { return (int*)alloc_bytes(n * sizeof(int)); }
+
+  void* alloc_bytes(size_t bytes) {
+    bytes = (bytes + 255) & ~(size_t)255;
+    if (bytes == 0) bytes = 256;
+    while (cur_ < chunks_.size()) {
+      if (off_ + bytes <= chunks_[cur_].size) {
+        void* p = (char*)chunks_[cur_].ptr + off_;
+        off_ += bytes;
+        return p;
+      }
+      ++cur_;
+      off_ = 0;
+    }
+    size_t sz = bytes > chunk_ ? bytes : chunk_;
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, sz);
+    if (e != hipSuccess || p == nullptr) {
+      (void)hipGetLastError();
+      throw Error(kEnomem, "device arena: hipMalloc of " + std::to_string(sz) +
+                               " bytes failed");
+    }
+    chunks_.push_back({p, sz});
+    cur_ = chunks_.size() - 1;
+    off_ = bytes;
+    return p;
+  }
+
+  Mark mark() const { return Mark{cur_, off_}; }
+  void release(Mark m) {
+    cur_ = m.chunk;
+    off_ = m.off;
+  }
+  void reset() {
+    cur_ = 0;
+    off_ = 0;
+  }
+  size_t reserved_bytes() const {
+    size_t t = 0;
+    for (auto& c : chunks_) t += c.size;
+    return t;
+  }
+  void release_all() {
+    for (auto& c : chunks_) (void)hipFree(c.ptr);
+    chunks_.clear();
+    cur_ = 0;
+    off_ = 0;
+  }
+
+ private:
+  struct Chunk {
+    void* ptr;
+    size_t size;
+  };
+  std::vector<Chunk> chunks_;
+  size_t chunk_;
+  size_t cur_ = 0, off_ = 0;
+};
+
+// RAII scope: everything allocated inside is released at scope exit.
+class ArenaScope {
+ public:
+  explicit ArenaScope(Arena& a) : a_(a), m_(a.mark()) {}
+  ~ArenaScope() { a_.release(m_); }
+
+ private:
+  Arena& a_;
+  Arena::Mark m_;
+};
+
+}  // namespace mpsv

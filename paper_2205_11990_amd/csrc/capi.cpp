@@ -1,0 +1,457 @@
+// C-ABI of the MPS Vlasov-Poisson library (include/mps_vlasov.h and
+// include/mps_blocks.h).  Converts engine exceptions into status codes and a
+// thread-local message; no exception crosses the boundary.
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <string>
+
+#include "../../include/mps_blocks.h"
+#include "../../include/mps_vlasov.h"
+#include "engine.hpp"
+#include "gemm.hpp"
+#include "linalg.hpp"
+
+struct mps_state {
+  std::unique_ptr<mpsv::Engine> eng;
+  int device = 0;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+mps_status to_status(int code) {
+  switch (code) {
+    case mpsv::kEinval: return MPS_EINVAL;
+    case mpsv::kEnomem: return MPS_ENOMEM;
+    case mpsv::kEnumeric: return MPS_ENUMERIC;
+    default: return MPS_EDEVICE;
+  }
+}
+
+template <class F>
+mps_status guarded(F&& f) {
+  try {
+    g_err.clear();
+    f();
+    return MPS_OK;
+  } catch (const mpsv::Error& e) {
+    g_err = e.what();
+    return to_status(e.code);
+  } catch (const std::bad_alloc&) {
+    g_err = "host allocation failed";
+    return MPS_ENOMEM;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return MPS_EDEVICE;
+  } catch (...) {
+    g_err = "unknown failure";
+    return MPS_EDEVICE;
+  }
+}
+
+mpsv::Problem convert(const mps_problem* p) {
+  MPSV_CHECK(p != nullptr, mpsv::kEinval, "problem is NULL");
+  mpsv::Problem q;
+  q.Lx = p->Lx;
+  q.Lv = p->Lv;
+  q.order = p->order;
+  q.x_min = p->x_min;
+  q.x_max = p->x_max;
+  q.v_min = p->v_min;
+  q.v_max = p->v_max;
+  q.qm = p->qm;
+  q.dt = p->dt;
+  q.chi_max = p->chi_max;
+  q.level = p->level;
+  q.df_max = p->df_max;
+  q.tol = p->tol;
+  q.precision = p->precision;
+  MPSV_CHECK(std::isfinite(q.x_min) && std::isfinite(q.x_max) &&
+                 std::isfinite(q.v_min) && std::isfinite(q.v_max),
+             mpsv::kEinval, "grid bounds must be finite");
+  return q;
+}
+
+void check_handle(const mps_state* h) {
+  MPSV_CHECK(h != nullptr && h->eng, mpsv::kEinval, "state handle is NULL");
+  int dev = -1;
+  MPSV_HIP(hipGetDevice(&dev));
+  MPSV_CHECK(dev == h->device, mpsv::kEinval,
+             "state was created on another device than the current one");
+}
+
+// A small engine whose arenas serve the stand-alone building blocks.
+std::mutex g_blocks_mu;
+std::unique_ptr<mpsv::Engine> g_blocks;
+mpsv::Engine& blocks() {
+  if (!g_blocks) {
+    mpsv::Problem p;
+    p.Lx = p.Lv = 2;
+    p.x_min = 0;
+    p.x_max = 1;
+    p.v_min = -1;
+    p.v_max = 1;
+    g_blocks.reset(new mpsv::Engine(p));
+  }
+  return *g_blocks;
+}
+
+mpsv::DMps unpack(int n, const int32_t* bonds, const double* cores) {
+  MPSV_CHECK(bonds != nullptr && cores != nullptr, mpsv::kEinval,
+             "bonds / cores must not be NULL");
+  MPSV_CHECK(bonds[0] == 1 && bonds[n] == 1, mpsv::kEinval,
+             "end bonds must be 1");
+  mpsv::DMps a(n);
+  long off = 0;
+  for (int j = 0; j < n; ++j) {
+    MPSV_CHECK(bonds[j + 1] >= 1, mpsv::kEinval, "bond dimension must be >= 1");
+    a[j] = mpsv::Core{const_cast<double*>(cores) + off, bonds[j], bonds[j + 1]};
+    off += a[j].size();
+  }
+  return a;
+}
+
+void pack(const mpsv::DMps& a, int32_t* bonds, double* out, int64_t capacity,
+          hipStream_t s) {
+  long tot = 0;
+  for (auto& c : a) tot += c.size();
+  MPSV_CHECK(tot <= capacity, mpsv::kEinval,
+             "output capacity too small: need " + std::to_string(tot));
+  long off = 0;
+  bonds[0] = 1;
+  for (size_t j = 0; j < a.size(); ++j) {
+    bonds[j + 1] = a[j].r;
+    MPSV_HIP(hipMemcpyAsync(out + off, a[j].p, a[j].size() * sizeof(double),
+                            hipMemcpyDeviceToDevice, s));
+    off += a[j].size();
+  }
+  MPSV_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mps_last_error(void) { return g_err.c_str(); }
+
+mps_status mps_init(const mps_problem* p, int32_t rank, const double* ax,
+                    const double* bv, hipStream_t stream, mps_state** out) {
+  return guarded([&] {
+    MPSV_CHECK(out != nullptr, mpsv::kEinval, "out is NULL");
+    *out = nullptr;
+    MPSV_CHECK(ax != nullptr && bv != nullptr, mpsv::kEinval,
+               "profiles must not be NULL");
+    mpsv::Problem q = convert(p);
+    std::unique_ptr<mps_state> h(new mps_state);
+    MPSV_HIP(hipGetDevice(&h->device));
+    h->eng.reset(new mpsv::Engine(q));
+    h->eng->init_from_profiles(rank, ax, bv, stream);
+    *out = h.release();
+  });
+}
+
+mps_status mps_step(mps_state* h, int32_t nsteps, hipStream_t stream) {
+  return guarded([&] {
+    check_handle(h);
+    MPSV_CHECK(nsteps >= 0, mpsv::kEinval, "nsteps must be >= 0");
+    for (int i = 0; i < nsteps; ++i) h->eng->step(stream);
+  });
+}
+
+mps_status mps_moments(mps_state* h, double* n_out, double* E_out,
+                       double* scalars, hipStream_t stream) {
+  return guarded([&] {
+    check_handle(h);
+    h->eng->moments(n_out, E_out, scalars, stream);
+  });
+}
+
+mps_status mps_to_dense(mps_state* h, double* f_out, hipStream_t stream) {
+  return guarded([&] {
+    check_handle(h);
+    MPSV_CHECK(f_out != nullptr, mpsv::kEinval, "f_out is NULL");
+    h->eng->to_dense(f_out, stream);
+    MPSV_HIP(hipStreamSynchronize(stream));
+  });
+}
+
+mps_status mps_free(mps_state* h) {
+  return guarded([&] {
+    if (!h) return;
+    (void)hipDeviceSynchronize();
+    delete h;
+  });
+}
+
+mps_status mps_info(const mps_state* h, int32_t* n_sites, int32_t* bond_dims,
+                    double* discarded, double* t, int64_t* steps) {
+  return guarded([&] {
+    check_handle(h);
+    const mpsv::Engine& e = *h->eng;
+    if (n_sites) *n_sites = e.n();
+    if (bond_dims) {
+      auto b = e.bonds();
+      for (size_t j = 0; j < b.size(); ++j) bond_dims[j] = b[j];
+    }
+    if (discarded) {
+      const auto& d = e.last_discarded();
+      for (int j = 0; j < e.n() - 1; ++j)
+        discarded[j] = j < (int)d.size() ? d[j] : 0.0;
+    }
+    if (t) *t = e.time();
+    if (steps) *steps = e.steps_done();
+  });
+}
+
+mps_status mps_get_cores(const mps_state* h, int32_t* bond_dims,
+                         int64_t* count, double* cores, hipStream_t stream) {
+  return guarded([&] {
+    check_handle(h);
+    std::vector<int> b;
+    h->eng->get_state(b, cores, stream);
+    long tot = 0;
+    for (size_t j = 0; j + 1 < b.size(); ++j) tot += (long)b[j] * 2 * b[j + 1];
+    if (bond_dims)
+      for (size_t j = 0; j < b.size(); ++j) bond_dims[j] = b[j];
+    if (count) *count = tot;
+    MPSV_HIP(hipStreamSynchronize(stream));
+  });
+}
+
+mps_status mps_set_cores(mps_state* h, const int32_t* bond_dims,
+                         const double* cores, hipStream_t stream) {
+  return guarded([&] {
+    check_handle(h);
+    MPSV_CHECK(bond_dims && cores, mpsv::kEinval, "NULL argument");
+    std::vector<int> b(bond_dims, bond_dims + h->eng->n() + 1);
+    h->eng->set_state(b, cores, stream);
+  });
+}
+
+mps_status mps_add_scaled(mps_state* h, double alpha, const int32_t* bond_dims,
+                          const double* cores, hipStream_t stream) {
+  return guarded([&] {
+    check_handle(h);
+    MPSV_CHECK(bond_dims && cores, mpsv::kEinval, "NULL argument");
+    MPSV_CHECK(std::isfinite(alpha), mpsv::kEinval, "alpha must be finite");
+    std::vector<int> b(bond_dims, bond_dims + h->eng->n() + 1);
+    h->eng->add_scaled(alpha, b, cores, stream);
+  });
+}
+
+mps_status mps_workspace_bound(const mps_problem* p, size_t* bytes) {
+  return guarded([&] {
+    MPSV_CHECK(bytes != nullptr, mpsv::kEinval, "bytes is NULL");
+    mpsv::Problem q = convert(p);
+    MPSV_CHECK(q.Lx >= 2 && q.Lx <= 14 && q.Lv >= 2 && q.Lv <= 14,
+               mpsv::kEinval, "Lx and Lv must lie in [2, 14]");
+    MPSV_CHECK(q.chi_max >= 1, mpsv::kEinval, "chi_max must be >= 1");
+    const int n = q.n();
+    const double chi = q.chi_max;
+    // widest MPO: the field term, 5 * D_F (interleaved) or max(D_F, 5)
+    const double df = q.df_max > 0 ? q.df_max : chi;
+    const double w = (q.order == 1) ? 5.0 * df : std::max(df, 5.0);
+    double state = 0, work = 0;
+    for (int j = 0; j < n; ++j) {
+      double bl = std::min(chi, std::ldexp(1.0, std::min(j, n - j)));
+      double br = std::min(chi, std::ldexp(1.0, std::min(j + 1, n - j - 1)));
+      state += bl * 2 * br;
+      double rl = std::min(w * bl, std::ldexp(1.0, std::min(j, n - j)));
+      double rr = std::min(w * br, std::ldexp(1.0, std::min(j + 1, n - j - 1)));
+      work = std::max(work, 4.0 * rl * 2 * rr);
+    }
+    // committed state + ~16 step intermediates + the compression workspace
+    *bytes = (size_t)(8.0 * (17.0 * state + 4.0 * work)) + ((size_t)64 << 20);
+  });
+}
+
+mps_status mps_step_batched(mps_state* const* hs, int32_t count, int32_t nsteps,
+                            hipStream_t stream) {
+  return guarded([&] {
+    MPSV_CHECK(hs != nullptr && count >= 0, mpsv::kEinval, "bad batch");
+    for (int i = 0; i < count; ++i) check_handle(hs[i]);
+    for (int k = 0; k < nsteps; ++k)
+      for (int i = 0; i < count; ++i) hs[i]->eng->step(stream);
+  });
+}
+
+// ------------------------------------------------------------- blocks
+
+mps_status mpsb_gemm(int32_t M, int32_t N, int32_t K, double alpha,
+                     const double* A, int64_t lda, const double* B,
+                     int64_t ldb, double beta, double* C, int64_t ldc,
+                     hipStream_t stream) {
+  return guarded([&] {
+    MPSV_CHECK(M >= 0 && N >= 0 && K >= 0, mpsv::kEinval, "negative size");
+    MPSV_CHECK(lda >= K && ldb >= N && ldc >= N, mpsv::kEinval,
+               "leading dimension too small");
+    mpsv::gemm(stream, M, N, K, alpha, mpsv::CMatView{A, lda, 1, 0},
+               mpsv::CMatView{B, ldb, 1, 0}, beta, mpsv::MatView{C, ldc, 1, 0});
+    MPSV_HIP(hipStreamSynchronize(stream));
+  });
+}
+
+mps_status mpsb_qr(int32_t m, int32_t n, double* A, double* Q,
+                   hipStream_t stream) {
+  return guarded([&] {
+    MPSV_CHECK(m >= 1 && n >= 1 && A, mpsv::kEinval, "bad QR arguments");
+    std::lock_guard<std::mutex> lk(g_blocks_mu);
+    mpsv::Arena& ws = blocks().scratch();
+    mpsv::ArenaScope sc(ws);
+    mpsv::QrFactor f;
+    mpsv::qr_factor(stream, ws, A, m, n, n, f);
+    if (Q) {
+      const int k = std::min(m, n);
+      // Q = H_0 ... H_{k-1} [I_k; 0]
+      double* E = ws.alloc((size_t)m * k);
+      std::vector<double> h((size_t)m * k, 0.0);
+      for (int i = 0; i < k; ++i) h[(size_t)i * k + i] = 1.0;
+      MPSV_HIP(hipMemcpy(E, h.data(), h.size() * sizeof(double),
+                         hipMemcpyHostToDevice));
+      mpsv::qr_apply_q(stream, ws, f, E, k, k);
+      MPSV_HIP(hipMemcpyAsync(Q, E, h.size() * sizeof(double),
+                              hipMemcpyDeviceToDevice, stream));
+    }
+    MPSV_HIP(hipStreamSynchronize(stream));
+  });
+}
+
+mps_status mpsb_svd_truncate(int32_t m, int32_t c, double* X, int32_t cap,
+                             double tol, double* Vt, double* US, double* sig,
+                             int32_t* D, double* discarded,
+                             hipStream_t stream) {
+  return guarded([&] {
+    MPSV_CHECK(m >= 1 && c >= 1 && X && Vt && US && D, mpsv::kEinval,
+               "bad SVD arguments");
+    MPSV_CHECK(tol >= 0, mpsv::kEinval, "tol must be >= 0");
+    std::lock_guard<std::mutex> lk(g_blocks_mu);
+    mpsv::Arena& ws = blocks().scratch();
+    mpsv::ArenaScope sc(ws);
+    double dsc = 0;
+    *D = mpsv::svd_truncate(stream, ws, X, m, c, c, cap > 0 ? cap : INT_MAX,
+                            tol, Vt, US, sig, &dsc);
+    if (discarded) *discarded = dsc;
+    MPSV_HIP(hipStreamSynchronize(stream));
+  });
+}
+
+mps_status mpsb_compress(int32_t n, const int32_t* mpo_bonds,
+                         const double* mpo, const int32_t* bonds_in,
+                         const double* cores_in, int32_t cap, double tol,
+                         int32_t* bonds_out, double* cores_out,
+                         int64_t capacity, double* discarded,
+                         hipStream_t stream) {
+  return guarded([&] {
+    MPSV_CHECK(n >= 2 && n <= 28, mpsv::kEinval, "n must lie in [2, 28]");
+    MPSV_CHECK(tol >= 0, mpsv::kEinval, "tol must be >= 0");
+    MPSV_CHECK(bonds_out && cores_out, mpsv::kEinval, "NULL output");
+    std::lock_guard<std::mutex> lk(g_blocks_mu);
+    mpsv::Engine& e = blocks();
+    mpsv::Arena out;
+    mpsv::DMps a = unpack(n, bonds_in, cores_in);
+    std::vector<double> disc;
+    mpsv::DMps r;
+    if (mpo) {
+      MPSV_CHECK(mpo_bonds && mpo_bonds[0] == 1 && mpo_bonds[n] == 1,
+                 mpsv::kEinval, "bad MPO bonds");
+      std::vector<std::vector<double>> W(n);
+      std::vector<int> wb(mpo_bonds, mpo_bonds + n + 1);
+      long off = 0;
+      for (int j = 0; j < n; ++j) {
+        W[j].resize((size_t)wb[j] * 4 * wb[j + 1]);
+        MPSV_HIP(hipMemcpy(W[j].data(), mpo + off, W[j].size() * sizeof(double),
+                           hipMemcpyDeviceToHost));
+        off += W[j].size();
+      }
+      mpsv::DMpo dW = e.upload_mpo(W, wb, out, stream);
+      r = e.apply_compress(dW, a, cap > 0 ? cap : INT_MAX, tol, out, stream,
+                           &disc);
+    } else {
+      r = e.compress_mps(a, cap > 0 ? cap : INT_MAX, tol, out, stream, &disc);
+    }
+    pack(r, bonds_out, cores_out, capacity, stream);
+    if (discarded)
+      for (int j = 0; j < n - 1; ++j) discarded[j] = disc[j];
+  });
+}
+
+mps_status mpsb_add_compress(int32_t n, int32_t nterms, const double* coef,
+                             const int32_t* bonds, const double* const* cores,
+                             int32_t cap, double tol, int32_t* bonds_out,
+                             double* cores_out, int64_t capacity,
+                             hipStream_t stream) {
+  return guarded([&] {
+    MPSV_CHECK(n >= 2 && nterms >= 1 && coef && bonds && cores, mpsv::kEinval,
+               "bad arguments");
+    std::lock_guard<std::mutex> lk(g_blocks_mu);
+    mpsv::Engine& e = blocks();
+    mpsv::Arena out;
+    std::vector<mpsv::DMps> terms;
+    for (int t = 0; t < nterms; ++t)
+      terms.push_back(unpack(n, bonds + (long)t * (n + 1), cores[t]));
+    std::vector<std::pair<double, const mpsv::DMps*>> tl;
+    for (int t = 0; t < nterms; ++t) tl.push_back({coef[t], &terms[t]});
+    mpsv::DMps r = e.add_terms(tl, cap > 0 ? cap : INT_MAX, out, stream, tol);
+    pack(r, bonds_out, cores_out, capacity, stream);
+  });
+}
+
+mps_status mpsb_density_field(mps_state* h, double* n_out, double* E_out,
+                              hipStream_t stream) {
+  return guarded([&] {
+    check_handle(h);
+    h->eng->density_field(n_out, E_out, stream);
+  });
+}
+
+mps_status mpsb_operator(int32_t which, int32_t L, double h0, double h,
+                         int32_t* bonds, double* W, int64_t* count) {
+  return guarded([&] {
+    MPSV_CHECK(L >= 2 && L <= 14, mpsv::kEinval, "L must lie in [2, 14]");
+    std::vector<int> b;
+    mpsv::ops::HostMpo M;
+    switch (which) {
+      case 0: M = mpsv::ops::d1_periodic(L, h, b); break;
+      case 1: M = mpsv::ops::d1_zero_gradient(L, h, b); break;
+      case 2: M = mpsv::ops::poisson_g(L, h, 1.0, b); break;
+      case 3: M = mpsv::ops::poly_diag(L, h0, h, 0.0, b); break;
+      default: throw mpsv::Error(mpsv::kEinval, "unknown operator");
+    }
+    long tot = 0;
+    for (auto& x : M) tot += (long)x.size();
+    if (count) *count = tot;
+    if (bonds)
+      for (size_t j = 0; j < b.size(); ++j) bonds[j] = b[j];
+    if (W) {
+      long off = 0;
+      for (auto& x : M) {
+        std::memcpy(W + off, x.data(), x.size() * sizeof(double));
+        off += (long)x.size();
+      }
+    }
+  });
+}
+
+mps_status mpsb_stats(int64_t* qr_calls, int64_t* svd_calls,
+                      int64_t* jacobi_sweeps) {
+  return guarded([&] {
+    auto& s = mpsv::linalg_stats();
+    if (qr_calls) *qr_calls = s.qr_calls;
+    if (svd_calls) *svd_calls = s.svd_calls;
+    if (jacobi_sweeps) *jacobi_sweeps = s.jacobi_sweeps;
+  });
+}
+
+mps_status mpsb_set_jacobi_max_sweeps(int32_t n) {
+  return guarded([&] {
+    MPSV_CHECK(n >= 1, mpsv::kEinval, "sweep cap must be >= 1");
+    mpsv::set_jacobi_max_sweeps(n);
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,971 @@
+// MPS engine for the 1D1V Vlasov-Poisson step (Ye & Loureiro,
+// arXiv:2205.11990): operators, compression sweep, field solve and RK4.
+//
+// All device work is enqueued on the caller's stream.  The only host
+// synchronisations inside a step are the read-back of each truncated rank
+// (the shapes of the following operations depend on it) and the final
+// finiteness check that makes a step transactional.
+#include "engine.hpp"
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+
+#include "gemm.hpp"
+#include "mps_kernels.hpp"
+
+namespace mpsv {
+
+// ============================================================ host operators
+namespace ops {
+
+namespace {
+typedef double M2[2][2];
+const M2 I2 = {{1, 0}, {0, 1}};
+const M2 SP = {{0, 0}, {1, 0}};  // S+ : (o, i) = (1, 0)
+const M2 SM = {{0, 1}, {0, 0}};  // S- : (o, i) = (0, 1)
+const M2 P0 = {{1, 0}, {0, 0}};
+const M2 P1 = {{0, 0}, {0, 1}};
+
+inline size_t widx(int br, int b, int o, int i, int bp) {
+  return ((size_t)(b * 2 + o) * 2 + i) * br + bp;
+}
+void put(std::vector<double>& W, int br, int b, int bp, const M2& M,
+         double sc = 1.0) {
+  for (int o = 0; o < 2; ++o)
+    for (int i = 0; i < 2; ++i) W[widx(br, b, o, i, bp)] += sc * M[o][i];
+}
+void put_sum(std::vector<double>& W, int br, int b, int bp, const M2& A,
+             const M2& B, double sa, double sb) {
+  put(W, br, b, bp, A, sa);
+  put(W, br, b, bp, B, sb);
+}
+
+// The printed first-derivative MPO (SI, Derivatives): first row, bulk
+// matrix, last column.  periodic selects the first-site row.
+HostMpo printed_d1(int L, bool periodic, double c1) {
+  HostMpo W(L);
+  for (int k = 0; k < L; ++k) {
+    int bl = (k == 0) ? 1 : 3, br = (k == L - 1) ? 1 : 3;
+    W[k].assign((size_t)bl * 4 * br, 0.0);
+    if (k == 0) {
+      put(W[k], br, 0, 0, I2);
+      if (periodic) {
+        put_sum(W[k], br, 0, 1, SP, SM, 1, 1);
+        put_sum(W[k], br, 0, 2, SP, SM, 1, 1);
+      } else {
+        put(W[k], br, 0, 1, SM);
+        put(W[k], br, 0, 2, SP);
+      }
+      if (L == 1) throw Error(kEinval, "derivative MPO needs L >= 2");
+    } else if (k < L - 1) {
+      put(W[k], br, 0, 0, I2);
+      put(W[k], br, 0, 1, SM);
+      put(W[k], br, 0, 2, SP);
+      put(W[k], br, 1, 1, SP);
+      put(W[k], br, 2, 2, SM);
+    } else {
+      put_sum(W[k], br, 0, 0, SM, SP, c1, -c1);
+      put(W[k], br, 1, 0, SP, c1);
+      put(W[k], br, 2, 0, SM, -c1);
+    }
+  }
+  return W;
+}
+
+}  // namespace
+
+HostMpo d1_periodic(int L, double h, std::vector<int>& bonds) {
+  HostMpo W = printed_d1(L, true, 0.5);
+  // the printed first site already carries bond 1 on the left; if L == 2 the
+  // first row meets the last column directly
+  for (auto& x : W[0]) x /= h;
+  bonds.assign(L + 1, 3);
+  bonds[0] = bonds[L] = 1;
+  return W;
+}
+
+HostMpo d1_zero_gradient(int L, double h, std::vector<int>& bonds) {
+  const double c1 = 0.5;
+  HostMpo back = printed_d1(L, false, c1);
+  // direct sum backbone (3) + M_left (1) + M_right (1): bond 5.
+  // M_left  = P0 x ... x P0 x [[0,-c1],[0,0]]   (mirror of the printed M_right)
+  // M_right = P1 x ... x P1 x [[0,0],[c1,0]]
+  const M2 lastL = {{0, -c1}, {0, 0}};
+  const M2 lastR = {{0, 0}, {c1, 0}};
+  HostMpo W(L);
+  for (int k = 0; k < L; ++k) {
+    int bl = (k == 0) ? 1 : 5, br = (k == L - 1) ? 1 : 5;
+    W[k].assign((size_t)bl * 4 * br, 0.0);
+    int bbl = (k == 0) ? 1 : 3, bbr = (k == L - 1) ? 1 : 3;
+    for (int b = 0; b < bbl; ++b)
+      for (int bp = 0; bp < bbr; ++bp)
+        for (int o = 0; o < 2; ++o)
+          for (int i = 0; i < 2; ++i)
+            W[k][widx(br, b, o, i, bp)] = back[k][widx(bbr, b, o, i, bp)];
+    // extra channels: index 3 (M_left), 4 (M_right) in the middle; on the
+    // first site they are columns 3,4; on the last site rows 3,4.
+    const bool last = (k == L - 1);
+    const M2& ml = last ? lastL : P0;
+    const M2& mr = last ? lastR : P1;
+    int lrow = (k == 0) ? 0 : 3, rrow = (k == 0) ? 0 : 4;
+    int lcol = last ? 0 : 3, rcol = last ? 0 : 4;
+    put(W[k], br, lrow, lcol, ml);
+    put(W[k], br, rrow, rcol, mr);
+  }
+  for (auto& x : W[0]) x /= h;
+  bonds.assign(L + 1, 5);
+  bonds[0] = bonds[L] = 1;
+  return W;
+}
+
+HostMpo poisson_g(int L, double dx, double scale, std::vector<int>& bonds) {
+  // G[o,i] = dx (sign(o-i)/2 - (o-i)/N): comparison automaton over the bit
+  // pairs (bond 3: equal / greater / less so far) plus a linear function of
+  // the bits (bond 2); direct sum, bond 5.
+  if (L < 2) throw Error(kEinval, "Poisson MPO needs L >= 2");
+  auto step = [](int s, int o, int i) {
+    if (s != 0) return s;
+    return o == i ? 0 : (o > i ? 1 : 2);
+  };
+  const double val[3] = {0.0, 0.5 * dx, -0.5 * dx};
+  HostMpo W(L);
+  for (int k = 0; k < L; ++k) {
+    int bl = (k == 0) ? 1 : 5, br = (k == L - 1) ? 1 : 5;
+    W[k].assign((size_t)bl * 4 * br, 0.0);
+    const double ck = -dx * std::ldexp(1.0, -1 - k);
+    for (int o = 0; o < 2; ++o)
+      for (int i = 0; i < 2; ++i) {
+        const double d = ck * (double)(o - i);
+        if (k == 0) {
+          W[k][widx(br, 0, o, i, step(0, o, i))] += 1.0;
+          W[k][widx(br, 0, o, i, 3)] += 1.0;
+          W[k][widx(br, 0, o, i, 4)] += d;
+        } else if (k < L - 1) {
+          for (int s = 0; s < 3; ++s) W[k][widx(br, s, o, i, step(s, o, i))] += 1.0;
+          W[k][widx(br, 3, o, i, 3)] += 1.0;
+          W[k][widx(br, 3, o, i, 4)] += d;
+          W[k][widx(br, 4, o, i, 4)] += 1.0;
+        } else {
+          for (int s = 0; s < 3; ++s) W[k][widx(br, s, o, i, 0)] += val[step(s, o, i)];
+          W[k][widx(br, 3, o, i, 0)] += d;
+          W[k][widx(br, 4, o, i, 0)] += 1.0;
+        }
+      }
+  }
+  for (auto& x : W[0]) x *= scale;
+  bonds.assign(L + 1, 5);
+  bonds[0] = bonds[L] = 1;
+  return W;
+}
+
+std::vector<std::vector<double>> poly_mps(int L, double c0, double c1,
+                                          double c2, std::vector<int>& bonds) {
+  // f(J) = c0 + c1 J + c2 J^2, J = sum_k s_k 2^(L-1-k): carry [1, J, J^2]
+  const int deg = (c2 != 0.0) ? 2 : ((c1 != 0.0) ? 1 : 0);
+  const int B = deg + 1;
+  const double c[3] = {c0, c1, c2};
+  std::vector<std::vector<double>> A(L);
+  auto T = [&](int s, int k, double* M) {  // B x B
+    const double t = s ? std::ldexp(1.0, L - 1 - k) : 0.0;
+    for (int a = 0; a < B * B; ++a) M[a] = 0.0;
+    for (int a = 0; a < B; ++a) M[a * B + a] = 1.0;
+    if (B >= 2) M[0 * B + 1] = t;
+    if (B >= 3) {
+      M[0 * B + 2] = t * t;
+      M[1 * B + 2] = 2.0 * t;
+    }
+  };
+  double M[9];
+  for (int k = 0; k < L; ++k) {
+    int bl = (k == 0) ? 1 : B, br = (k == L - 1) ? 1 : B;
+    A[k].assign((size_t)bl * 2 * br, 0.0);
+    for (int s = 0; s < 2; ++s) {
+      T(s, k, M);
+      for (int a = 0; a < bl; ++a)
+        for (int b = 0; b < br; ++b) {
+          double v;
+          if (k == L - 1) {
+            v = 0.0;
+            for (int q = 0; q < B; ++q) v += M[a * B + q] * c[q];
+            if (L == 1) {  // single site: row 0 only
+              v = 0.0;
+              for (int q = 0; q < B; ++q) v += M[q] * c[q];
+            }
+          } else {
+            v = M[a * B + b];
+          }
+          A[k][((size_t)a * 2 + s) * br + b] = v;
+        }
+    }
+  }
+  bonds.assign(L + 1, B);
+  bonds[0] = bonds[L] = 1;
+  return A;
+}
+
+HostMpo poly_diag(int L, double c0, double c1, double c2,
+                  std::vector<int>& bonds) {
+  auto A = poly_mps(L, c0, c1, c2, bonds);
+  HostMpo W(L);
+  for (int k = 0; k < L; ++k) {
+    int bl = bonds[k], br = bonds[k + 1];
+    W[k].assign((size_t)bl * 4 * br, 0.0);
+    for (int a = 0; a < bl; ++a)
+      for (int s = 0; s < 2; ++s)
+        for (int b = 0; b < br; ++b)
+          W[k][widx(br, a, s, s, b)] = A[k][((size_t)a * 2 + s) * br + b];
+  }
+  return W;
+}
+
+// Full-chain tensor for P physical values per site (4: MPO, 2: MPS).
+static HostMpo chain_generic(const HostMpo& Wx, const std::vector<int>& bx,
+                             const HostMpo& Wv, const std::vector<int>& bv,
+                             int order, int P, std::vector<int>& bonds) {
+  const int Lx = (int)Wx.size(), Lv = (int)Wv.size();
+  std::vector<std::pair<int, int>> sites;  // (0 = x / 1 = v, k)
+  if (order == 0) {
+    for (int k = 0; k < Lx; ++k) sites.push_back({0, k});
+    for (int k = 0; k < Lv; ++k) sites.push_back({1, k});
+  } else {
+    if (Lx != Lv) throw Error(kEinval, "interleaved ordering needs Lx == Lv");
+    for (int k = 0; k < Lx; ++k) {
+      sites.push_back({0, k});
+      sites.push_back({1, k});
+    }
+  }
+  HostMpo out;
+  bonds.assign(1, 1);
+  int cx = 1, cv = 1;
+  for (auto& st : sites) {
+    const int k = st.second;
+    if (st.first == 0) {
+      const int l = bx[k], r = bx[k + 1], d = cv;
+      std::vector<double> T((size_t)l * d * P * r * d, 0.0);
+      for (int a = 0; a < l; ++a)
+        for (int c = 0; c < d; ++c)
+          for (int p = 0; p < P; ++p)
+            for (int b = 0; b < r; ++b)
+              T[(((size_t)(a * d + c) * P + p) * r + b) * d + c] =
+                  Wx[k][((size_t)a * P + p) * r + b];
+      out.push_back(std::move(T));
+      bonds.push_back(r * d);
+      cx = r;
+    } else {
+      const int l = bv[k], r = bv[k + 1], d = cx;
+      std::vector<double> T((size_t)d * l * P * d * r, 0.0);
+      for (int c = 0; c < d; ++c)
+        for (int a = 0; a < l; ++a)
+          for (int p = 0; p < P; ++p)
+            for (int b = 0; b < r; ++b)
+              T[(((size_t)(c * l + a) * P + p) * d + c) * r + b] =
+                  Wv[k][((size_t)a * P + p) * r + b];
+      out.push_back(std::move(T));
+      bonds.push_back(d * r);
+      cv = r;
+    }
+  }
+  return out;
+}
+
+HostMpo chain(const HostMpo& Wx, const std::vector<int>& bx, const HostMpo& Wv,
+              const std::vector<int>& bv, int order, std::vector<int>& bonds) {
+  return chain_generic(Wx, bx, Wv, bv, order, 4, bonds);
+}
+
+HostMpo chain_mps(const HostMpo& Ax, const std::vector<int>& bx,
+                  const HostMpo& Av, const std::vector<int>& bv, int order,
+                  std::vector<int>& bonds) {
+  return chain_generic(Ax, bx, Av, bv, order, 2, bonds);
+}
+
+}  // namespace ops
+
+// ================================================================= engine
+
+static int cap_or_inf(int c) { return c > 0 ? c : INT_MAX; }
+
+Engine::Engine(const Problem& p) : p_(p) {
+  MPSV_CHECK(p.Lx >= 2 && p.Lx <= 14 && p.Lv >= 2 && p.Lv <= 14, kEinval,
+             "Lx and Lv must lie in [2, 14]");
+  MPSV_CHECK(p.order == 0 || p.order == 1, kEinval, "unknown ordering");
+  MPSV_CHECK(p.order == 0 || p.Lx == p.Lv, kEinval,
+             "interleaved ordering needs Lx == Lv");
+  MPSV_CHECK(p.x_max > p.x_min && p.v_max > p.v_min, kEinval,
+             "empty x or v interval");
+  MPSV_CHECK(std::isfinite(p.dt) && p.dt > 0, kEinval, "dt must be > 0");
+  MPSV_CHECK(p.chi_max >= 1, kEinval, "chi_max must be >= 1");
+  MPSV_CHECK(p.level >= 1 && p.level <= 5, kEinval, "level must be in 1..5");
+  MPSV_CHECK(p.df_max >= 0, kEinval, "df_max must be >= 0");
+  MPSV_CHECK(std::isfinite(p.tol) && p.tol >= 0, kEinval, "tol must be >= 0");
+  MPSV_CHECK(p.precision == 0 || p.precision == 1, kEinval,
+             "unknown precision mode");
+  MPSV_CHECK(std::isfinite(p.qm), kEinval, "q/m must be finite");
+
+  hipStream_t s = nullptr;
+  std::vector<int> bdx, bvv, bt1, bg, bdv;
+  auto Dx = ops::d1_periodic(p.Lx, p.dx(), bdx);
+  auto V = ops::poly_diag(p.Lv, p.v_min, p.dv(), 0.0, bvv);
+  auto T1 = ops::chain(Dx, bdx, V, bvv, p.order, bt1);
+  for (auto& x : T1[0]) x = -x;  // T1 = -(Dx (x) V) f
+  t1_ = upload_mpo(T1, bt1, ops_, s);
+  auto G = ops::poisson_g(p.Lx, p.dx(), -1.0, bg);  // E = -G n
+  gneg_ = upload_mpo(G, bg, ops_, s);
+  auto Dv = ops::d1_zero_gradient(p.Lv, p.dv(), bdv);
+  dv_ = upload_mpo(Dv, bdv, ops_, s);
+
+  // moment weights 1(x) w(v), w = 1, v, v^2/2 as full-chain MPS
+  std::vector<int> b1, bw, bc;
+  auto onesx = ops::poly_mps(p.Lx, 1.0, 0.0, 0.0, b1);
+  auto upload_chain = [&](const ops::HostMpo& Av, const std::vector<int>& bv) {
+    auto C = ops::chain_mps(onesx, b1, Av, bv, p.order, bc);
+    DMps out(C.size());
+    for (size_t j = 0; j < C.size(); ++j) {
+      out[j].l = bc[j];
+      out[j].r = bc[j + 1];
+      out[j].p = ops_.alloc(C[j].size());
+      MPSV_HIP(hipMemcpy(out[j].p, C[j].data(), C[j].size() * sizeof(double),
+                         hipMemcpyHostToDevice));
+    }
+    return out;
+  };
+  auto wv = ops::poly_mps(p.Lv, p.v_min, p.dv(), 0.0, bw);
+  vpoly_ = upload_chain(wv, bw);
+  auto wv2 = ops::poly_mps(p.Lv, 0.5 * p.v_min * p.v_min, p.v_min * p.dv(),
+                           0.5 * p.dv() * p.dv(), bw);
+  v2poly_ = upload_chain(wv2, bw);
+  dflag_ = ops_.alloc_int(4);
+  MPSV_HIP(hipDeviceSynchronize());
+}
+
+DMpo Engine::upload_mpo(const std::vector<std::vector<double>>& W,
+                        const std::vector<int>& bonds, Arena& ar,
+                        hipStream_t s) {
+  DMpo out(W.size());
+  for (size_t j = 0; j < W.size(); ++j) {
+    MpoSite& m = out[j];
+    m.wl = bonds[j];
+    m.wr = bonds[j + 1];
+    MPSV_CHECK((long)W[j].size() == (long)m.wl * 4 * m.wr, kEinval,
+               "MPO site size mismatch");
+    m.W = ar.alloc(W[j].size());
+    m.Wmat = ar.alloc(W[j].size());
+    MPSV_HIP(hipMemcpy(m.W, W[j].data(), W[j].size() * sizeof(double),
+                       hipMemcpyHostToDevice));
+    mpo_left_matrix(s, m.W, m.wl, m.wr, m.Wmat);
+  }
+  return out;
+}
+
+int Engine::cap_for(int point) const {
+  return (p_.level >= point) ? cap_or_inf(p_.chi_max) : INT_MAX;
+}
+
+std::vector<int> Engine::bonds() const {
+  std::vector<int> b(n() + 1, 1);
+  for (int j = 0; j < (int)f_.size(); ++j) b[j + 1] = f_[j].r;
+  if (!f_.empty()) b[0] = f_[0].l;
+  return b;
+}
+
+// M (p x 2 x v.r) = R (p x v.l, contiguous) * C_j
+void Engine::absorb_left(const VSite& v, const double* R, int p, double* M,
+                         hipStream_t s) {
+  switch (v.kind) {
+    case VSite::kDense: {
+      gemm(s, p, 2 * v.r, v.l, 1.0, CMatView{R, v.l, 1, 0},
+           CMatView{v.A.p, 2L * v.r, 1, 0}, 0.0, MatView{M, 2L * v.r, 1, 0});
+      break;
+    }
+    case VSite::kApply: {
+      const int wl = v.W.wl, wr = v.W.wr, al = v.A.l, ar = v.A.r;
+      ArenaScope sc(work_);
+      double* X = work_.alloc((size_t)p * wl * 2 * ar);
+      // X[(p,b)][(i,a')] = sum_a R[p][(b,a)] A[a][i][a']
+      gemm(s, p * wl, 2 * ar, al, 1.0, CMatView{R, al, 1, 0},
+           CMatView{v.A.p, 2L * ar, 1, 0}, 0.0, MatView{X, 2L * ar, 1, 0});
+      // M_p[(o,b')][a'] = sum_(b,i) Wmat[(o,b')][(b,i)] X_p[(b,i)][a']
+      gemm(s, 2 * wr, ar, 2 * wl, 1.0, CMatView{v.W.Wmat, 2L * wl, 1, 0},
+           CMatView{X, ar, 1, 2L * wl * ar}, 0.0,
+           MatView{M, ar, 1, 2L * wr * ar}, p);
+      break;
+    }
+    case VSite::kSum: {
+      const int T = (int)v.terms.size();
+      for (int t = 0; t < T; ++t) {
+        const Core& A = v.terms[t];
+        if (v.pos == 0) {
+          // M[p][s][roff+b] = coef * R[p][0] * A[0][s][b]
+          gemm(s, p, A.r, 1, v.coef[t], CMatView{R, 1, 1, 0},
+               CMatView{A.p, 2L * A.r, 1, A.r}, 0.0,
+               MatView{M + v.roff[t], 2L * v.r, 1, v.r}, 2);
+        } else if (v.pos == 1) {
+          gemm(s, p, A.r, A.l, 1.0, CMatView{R + v.loff[t], v.l, 1, 0},
+               CMatView{A.p, 2L * A.r, 1, A.r}, 0.0,
+               MatView{M + v.roff[t], 2L * v.r, 1, v.r}, 2);
+        } else {
+          gemm(s, p, 2, A.l, 1.0, CMatView{R + v.loff[t], v.l, 1, 0},
+               CMatView{A.p, 2, 1, 0}, t == 0 ? 0.0 : 1.0,
+               MatView{M, 2, 1, 0});
+        }
+      }
+      break;
+    }
+  }
+}
+
+DMps Engine::compress_chain(const std::vector<VSite>& ch, int cap, double tol,
+                            Arena& out, hipStream_t s,
+                            std::vector<double>* disc) {
+  const int n = (int)ch.size();
+  MPSV_CHECK(n >= 2, kEinval, "compression needs at least two sites");
+  cap = cap_or_inf(cap);
+  ArenaScope sc(work_);
+  struct Fac {
+    bool ident = true;
+    int rows = 0, cols = 0;
+    QrFactor qf;
+  };
+  std::vector<Fac> fac(n);
+  // ---- (i) QR sweep left to right.  A block with no more rows than
+  // columns keeps Q = I (any orthogonal Q is a valid left-canonical gauge
+  // and the identity is exact); taller blocks are Householder-factored.
+  double* R = work_.alloc(1);
+  fill(s, R, 1, 1.0);
+  int p = 1;
+  for (int j = 0; j < n - 1; ++j) {
+    const int rows = 2 * p, cols = ch[j].r;
+    double* M = work_.alloc((size_t)rows * cols);
+    absorb_left(ch[j], R, p, M, s);
+    fac[j].rows = rows;
+    fac[j].cols = cols;
+    if (rows <= cols) {
+      fac[j].ident = true;
+      R = M;
+      p = rows;
+    } else {
+      fac[j].ident = false;
+      qr_factor(s, work_, M, rows, cols, cols, fac[j].qf);
+      double* Rn = work_.alloc((size_t)cols * cols);
+      extract_r(s, M, cols, cols, cols, Rn, cols);
+      R = Rn;
+      p = cols;
+    }
+  }
+  double* X = work_.alloc((size_t)p * 2);
+  absorb_left(ch[n - 1], R, p, X, s);
+  // ---- (ii) truncated SVD sweep right to left
+  DMps res(n);
+  if (disc) disc->assign(n - 1, 0.0);
+  int m = p, Dr = 1;
+  for (int j = n - 1; j >= 1; --j) {
+    const int c = 2 * Dr;
+    const int Dmax = std::min(std::min(cap, m), c);
+    double* Vt = out.alloc((size_t)Dmax * c);
+    double* US = work_.alloc((size_t)m * Dmax);
+    double dsc = 0.0;
+    const int D = svd_truncate(s, work_, X, m, c, c, cap, tol, Vt, US, nullptr,
+                               &dsc);
+    res[j] = Core{Vt, D, Dr};
+    if (disc) (*disc)[j - 1] = dsc;
+    const Fac& f = fac[j - 1];
+    if (f.ident) {
+      X = US;  // (2 p_{j-2}) x D = p_{j-2} x (2D)
+    } else {
+      // US is f.cols x D; pad to f.rows x D and apply Q
+      double* Y = work_.alloc((size_t)f.rows * D);
+      copy2d(s, f.cols, D, 1.0, US, D, Y, D);
+      fill(s, Y + (long)f.cols * D, (long)(f.rows - f.cols) * D, 0.0);
+      qr_apply_q(s, work_, f.qf, Y, D, D);
+      X = Y;
+    }
+    m = f.rows / 2;
+    Dr = D;
+  }
+  // first core: X is 2 x Dr
+  Core c0{out.alloc((size_t)2 * Dr), 1, Dr};
+  MPSV_HIP(hipMemcpyAsync(c0.p, X, sizeof(double) * 2 * Dr,
+                          hipMemcpyDeviceToDevice, s));
+  res[0] = c0;
+  return res;
+}
+
+DMps Engine::compress_mps(const DMps& a, int cap, double tol, Arena& out,
+                          hipStream_t s, std::vector<double>* disc) {
+  std::vector<VSite> ch(a.size());
+  for (size_t j = 0; j < a.size(); ++j) {
+    ch[j].kind = VSite::kDense;
+    ch[j].A = a[j];
+    ch[j].l = a[j].l;
+    ch[j].r = a[j].r;
+  }
+  return compress_chain(ch, cap, tol, out, s, disc);
+}
+
+DMps Engine::apply_compress(const DMpo& W, const DMps& a, int cap, double tol,
+                            Arena& out, hipStream_t s,
+                            std::vector<double>* disc) {
+  MPSV_CHECK(W.size() == a.size(), kEinval, "MPO/MPS length mismatch");
+  std::vector<VSite> ch(a.size());
+  for (size_t j = 0; j < a.size(); ++j) {
+    ch[j].kind = VSite::kApply;
+    ch[j].A = a[j];
+    ch[j].W = W[j];
+    ch[j].l = W[j].wl * a[j].l;
+    ch[j].r = W[j].wr * a[j].r;
+  }
+  return compress_chain(ch, cap, tol, out, s, disc);
+}
+
+DMps Engine::add_terms(const std::vector<std::pair<double, const DMps*>>& terms,
+                       int cap, Arena& out, hipStream_t s, double tol) {
+  const int n = (int)terms[0].second->size();
+  std::vector<VSite> ch(n);
+  for (int j = 0; j < n; ++j) {
+    VSite& v = ch[j];
+    v.kind = VSite::kSum;
+    v.pos = (j == 0) ? 0 : (j == n - 1 ? 2 : 1);
+    int lo = 0, ro = 0;
+    for (auto& t : terms) {
+      const Core& A = (*t.second)[j];
+      v.terms.push_back(A);
+      v.coef.push_back(t.first);
+      v.loff.push_back(lo);
+      v.roff.push_back(ro);
+      lo += A.l;
+      ro += A.r;
+    }
+    v.l = (j == 0) ? 1 : lo;
+    v.r = (j == n - 1) ? 1 : ro;
+  }
+  std::vector<double> disc;
+  DMps r = compress_chain(ch, cap, tol < 0 ? p_.tol : tol, out, s, &disc);
+  disc_ = disc;
+  return r;
+}
+
+DMps Engine::copy_mps(const DMps& a, Arena& ar, hipStream_t s) {
+  DMps out(a.size());
+  for (size_t j = 0; j < a.size(); ++j) {
+    out[j] = a[j];
+    out[j].p = ar.alloc(a[j].size());
+    MPSV_HIP(hipMemcpyAsync(out[j].p, a[j].p, a[j].size() * sizeof(double),
+                            hipMemcpyDeviceToDevice, s));
+  }
+  return out;
+}
+
+// n(x) = dv * sum_j f(x, v_j): each v core summed over its bit (SI,
+// Integration) and absorbed into the neighbouring x core.
+DMps Engine::density(const DMps& g, Arena& ar, hipStream_t s) {
+  const int Lx = p_.Lx, Lv = p_.Lv;
+  std::vector<std::pair<int, int>> sites;
+  if (p_.order == 0) {
+    for (int k = 0; k < Lx; ++k) sites.push_back({0, k});
+    for (int k = 0; k < Lv; ++k) sites.push_back({1, k});
+  } else {
+    for (int k = 0; k < Lx; ++k) {
+      sites.push_back({0, k});
+      sites.push_back({1, k});
+    }
+  }
+  DMps xs;
+  double* pend = nullptr;
+  int pl = 0, pr = 0;
+  for (size_t j = 0; j < sites.size(); ++j) {
+    const Core& A = g[j];
+    if (sites[j].first == 1) {
+      double* Ms = ar.alloc((size_t)A.l * A.r);
+      sum_physical(s, A.p, A.l, A.r, Ms);
+      if (!xs.empty()) {
+        Core& X = xs.back();
+        double* Y = ar.alloc((size_t)X.l * 2 * A.r);
+        gemm(s, X.l * 2, A.r, X.r, 1.0, CMatView{X.p, X.r, 1, 0},
+             CMatView{Ms, A.r, 1, 0}, 0.0, MatView{Y, A.r, 1, 0});
+        X.p = Y;
+        X.r = A.r;
+      } else if (pend == nullptr) {
+        pend = Ms;
+        pl = A.l;
+        pr = A.r;
+      } else {
+        double* Y = ar.alloc((size_t)pl * A.r);
+        gemm(s, pl, A.r, pr, 1.0, CMatView{pend, pr, 1, 0},
+             CMatView{Ms, A.r, 1, 0}, 0.0, MatView{Y, A.r, 1, 0});
+        pend = Y;
+        pr = A.r;
+      }
+    } else {
+      Core C = A;
+      if (pend) {
+        double* Y = ar.alloc((size_t)pl * 2 * A.r);
+        gemm(s, pl, 2 * A.r, pr, 1.0, CMatView{pend, pr, 1, 0},
+             CMatView{A.p, 2L * A.r, 1, 0}, 0.0, MatView{Y, 2L * A.r, 1, 0});
+        C = Core{Y, pl, A.r};
+        pend = nullptr;
+      } else {
+        double* Y = ar.alloc(A.size());
+        MPSV_HIP(hipMemcpyAsync(Y, A.p, A.size() * sizeof(double),
+                                hipMemcpyDeviceToDevice, s));
+        C.p = Y;
+      }
+      xs.push_back(C);
+    }
+  }
+  // fold dv into the first core
+  copy2d(s, 1, (int)xs[0].size(), p_.dv(), xs[0].p, xs[0].size(), xs[0].p,
+         xs[0].size());
+  return xs;
+}
+
+// E = compress(-G n, D_F, tol)  (Problem Statement eqs. 2-3)
+DMps Engine::field(const DMps& g, Arena& ar, hipStream_t s) {
+  // n lives below the compression's own workspace scope; E goes to `ar`
+  ArenaScope sc(work_);
+  DMps n = density(g, work_, s);
+  return apply_compress(gneg_, n, p_.df_max > 0 ? p_.df_max : INT_MAX, p_.tol,
+                        ar, s);
+}
+
+// Full-chain MPO of -(q/m) diag(E) (x) Dv (SI, Dot Product).
+DMpo Engine::t2_mpo(const DMps& E, Arena& ar, hipStream_t s) {
+  const int Lx = p_.Lx, Lv = p_.Lv;
+  std::vector<std::pair<int, int>> sites;
+  if (p_.order == 0) {
+    for (int k = 0; k < Lx; ++k) sites.push_back({0, k});
+    for (int k = 0; k < Lv; ++k) sites.push_back({1, k});
+  } else {
+    for (int k = 0; k < Lx; ++k) {
+      sites.push_back({0, k});
+      sites.push_back({1, k});
+    }
+  }
+  DMpo W(sites.size());
+  int cx = 1, cv = 1;
+  for (size_t j = 0; j < sites.size(); ++j) {
+    const int k = sites[j].second;
+    MpoSite& m = W[j];
+    if (sites[j].first == 0) {
+      const Core& e = E[k];
+      double* Wd = ar.alloc((size_t)e.l * 4 * e.r);
+      diag_mpo_site(s, e.p, e.l, e.r, k == 0 ? -p_.qm : 1.0, Wd);
+      if (cv == 1) {
+        m.W = Wd;
+      } else {
+        m.W = ar.alloc((size_t)e.l * cv * 4 * e.r * cv);
+        kron_embed(s, Wd, e.l, 4, e.r, cv, 0, m.W);
+      }
+      m.wl = e.l * cv;
+      m.wr = e.r * cv;
+      cx = e.r;
+    } else {
+      const MpoSite& d = dv_[k];
+      if (cx == 1) {
+        m.W = d.W;
+      } else {
+        m.W = ar.alloc((size_t)d.wl * cx * 4 * d.wr * cx);
+        kron_embed(s, d.W, d.wl, 4, d.wr, cx, 1, m.W);
+      }
+      m.wl = d.wl * cx;
+      m.wr = d.wr * cx;
+      cv = d.wr;
+    }
+    m.Wmat = ar.alloc((size_t)m.wl * 4 * m.wr);
+    mpo_left_matrix(s, m.W, m.wl, m.wr, m.Wmat);
+  }
+  return W;
+}
+
+// k = R(g) = -v d/dx g - (q/m) E d/dv g  (eq. 1, C = 0)
+DMps Engine::rhs(const DMps& g, Arena& out, hipStream_t s) {
+  ArenaScope sc(tmp_);
+  DMps E = field(g, tmp_, s);
+  DMpo W2 = t2_mpo(E, tmp_, s);
+  DMps T1 = apply_compress(t1_, g, cap_for(5), p_.tol, tmp_, s);
+  DMps T2 = apply_compress(W2, g, cap_for(5), p_.tol, tmp_, s);
+  return add_terms({{1.0, &T1}, {1.0, &T2}}, cap_for(4), out, s);
+}
+
+void Engine::commit(const DMps& fn, hipStream_t s) {
+  // finiteness check first: the state only changes when the step is clean
+  fill_int(s, dflag_, 1, 0);
+  for (auto& c : fn) count_nonfinite(s, c.p, c.size(), dflag_);
+  int bad = 0;
+  MPSV_HIP(hipMemcpyAsync(&bad, dflag_, sizeof(int), hipMemcpyDeviceToHost, s));
+  MPSV_HIP(hipStreamSynchronize(s));
+  if (bad) throw Error(kEnumeric, "non-finite values in the new state");
+  state_.reset();
+  f_ = copy_mps(fn, state_, s);
+}
+
+void Engine::step(hipStream_t s) {
+  MPSV_CHECK(!f_.empty(), kEinval, "state not initialised");
+  const double h = p_.dt;
+  step_.reset();
+  DMps k1 = rhs(f_, step_, s);
+  DMps f2 = add_terms({{1.0, &f_}, {0.5 * h, &k1}}, cap_for(2), step_, s);
+  DMps k2 = rhs(f2, step_, s);
+  DMps f3 = add_terms({{1.0, &f_}, {0.5 * h, &k2}}, cap_for(2), step_, s);
+  DMps k3 = rhs(f3, step_, s);
+  DMps f4 = add_terms({{1.0, &f_}, {h, &k3}}, cap_for(2), step_, s);
+  DMps k4 = rhs(f4, step_, s);
+  DMps S = add_terms({{1.0, &k1}, {2.0, &k2}, {2.0, &k3}, {1.0, &k4}},
+                     cap_for(3), step_, s);
+  DMps fn = add_terms({{1.0, &f_}, {h / 6.0, &S}}, cap_or_inf(p_.chi_max),
+                      step_, s);
+  commit(fn, s);
+  t_ += h;
+  ++steps_;
+}
+
+// ---------------------------------------------------------------- state io
+
+void Engine::init_from_profiles(int rank, const double* ax, const double* bv,
+                                hipStream_t s) {
+  MPSV_CHECK(rank >= 1, kEinval, "profile rank must be >= 1");
+  // non-finite profiles are rejected
+  fill_int(s, dflag_, 1, 0);
+  count_nonfinite(s, ax, (long)rank * p_.Nx(), dflag_);
+  count_nonfinite(s, bv, (long)rank * p_.Nv(), dflag_);
+  int bad = 0;
+  MPSV_HIP(hipMemcpyAsync(&bad, dflag_, sizeof(int), hipMemcpyDeviceToHost, s));
+  MPSV_HIP(hipStreamSynchronize(s));
+  MPSV_CHECK(bad == 0, kEinval, "non-finite values in the initial profiles");
+
+  step_.reset();
+  // 1-D vector -> MPS by iterated SVD (eq. 4), run from the right end:
+  // X = u as 2^(L-1) x 2, SVD, keep V^T as the last core, carry U S.
+  auto tt = [&](const double* u, int L) {
+    DMps m(L);
+    double* X = work_.alloc((size_t)1 << L);
+    MPSV_HIP(hipMemcpyAsync(X, u, sizeof(double) * ((size_t)1 << L),
+                            hipMemcpyDeviceToDevice, s));
+    int rows = 1 << (L - 1), Dr = 1;
+    for (int j = L - 1; j >= 1; --j) {
+      const int c = 2 * Dr;
+      const int Dmax = std::min(rows, c);
+      double* Vt = step_.alloc((size_t)Dmax * c);
+      double* US = work_.alloc((size_t)rows * Dmax);
+      const int D = svd_truncate(s, work_, X, rows, c, c, INT_MAX,
+                                 std::min(p_.tol, 1e-14) , Vt, US, nullptr,
+                                 nullptr);
+      m[j] = Core{Vt, D, Dr};
+      X = US;
+      rows /= 2;
+      Dr = D;
+    }
+    Core c0{step_.alloc((size_t)2 * Dr), 1, Dr};
+    MPSV_HIP(hipMemcpyAsync(c0.p, X, sizeof(double) * 2 * Dr,
+                            hipMemcpyDeviceToDevice, s));
+    m[0] = c0;
+    return m;
+  };
+  std::vector<DMps> terms;
+  {
+    ArenaScope sc(work_);
+    for (int r = 0; r < rank; ++r) {
+      DMps mx = tt(ax + (long)r * p_.Nx(), p_.Lx);
+      DMps mv = tt(bv + (long)r * p_.Nv(), p_.Lv);
+      DMps full;
+      if (p_.order == 0) {
+        full = mx;
+        full.insert(full.end(), mv.begin(), mv.end());
+      } else {
+        int cx = 1, cv = 1;
+        for (int k = 0; k < p_.Lx; ++k) {
+          const Core& X = mx[k];
+          Core cxk{step_.alloc((size_t)X.l * cv * 2 * X.r * cv), X.l * cv,
+                   X.r * cv};
+          kron_embed(s, X.p, X.l, 2, X.r, cv, 0, cxk.p);
+          full.push_back(cxk);
+          cx = X.r;
+          const Core& V = mv[k];
+          Core cvk{step_.alloc((size_t)V.l * cx * 2 * V.r * cx), V.l * cx,
+                   V.r * cx};
+          kron_embed(s, V.p, V.l, 2, V.r, cx, 1, cvk.p);
+          full.push_back(cvk);
+          cv = V.r;
+        }
+      }
+      terms.push_back(full);
+    }
+  }
+  std::vector<std::pair<double, const DMps*>> tl;
+  for (auto& t : terms) tl.push_back({1.0, &t});
+  DMps f0;
+  if (rank == 1) {
+    f0 = compress_mps(terms[0], cap_or_inf(p_.chi_max), p_.tol, step_, s);
+  } else {
+    f0 = add_terms(tl, cap_or_inf(p_.chi_max), step_, s);
+  }
+  commit(f0, s);
+  t_ = 0.0;
+  steps_ = 0;
+}
+
+void Engine::set_state(const std::vector<int>& bonds, const double* packed,
+                       hipStream_t s) {
+  MPSV_CHECK((int)bonds.size() == n() + 1 && bonds[0] == 1 && bonds[n()] == 1,
+             kEinval, "bond dimensions must have n+1 entries with unit ends");
+  DMps a(n());
+  long off = 0;
+  for (int j = 0; j < n(); ++j) {
+    MPSV_CHECK(bonds[j + 1] >= 1, kEinval, "bond dimension must be >= 1");
+    a[j] = Core{const_cast<double*>(packed) + off, bonds[j], bonds[j + 1]};
+    off += a[j].size();
+  }
+  step_.reset();
+  DMps c = copy_mps(a, step_, s);
+  commit(c, s);
+}
+
+void Engine::get_state(std::vector<int>& bonds, double* packed,
+                       hipStream_t s) const {
+  bonds = this->bonds();
+  long off = 0;
+  for (auto& c : f_) {
+    if (packed)
+      MPSV_HIP(hipMemcpyAsync(packed + off, c.p, c.size() * sizeof(double),
+                              hipMemcpyDeviceToDevice, s));
+    off += c.size();
+  }
+}
+
+void Engine::add_scaled(double alpha, const std::vector<int>& bonds,
+                        const double* packed, hipStream_t s) {
+  MPSV_CHECK((int)bonds.size() == n() + 1 && bonds[0] == 1 && bonds[n()] == 1,
+             kEinval, "bond dimensions must have n+1 entries with unit ends");
+  DMps g(n());
+  long off = 0;
+  for (int j = 0; j < n(); ++j) {
+    g[j] = Core{const_cast<double*>(packed) + off, bonds[j], bonds[j + 1]};
+    off += g[j].size();
+  }
+  step_.reset();
+  DMps fn = add_terms({{1.0, &f_}, {alpha, &g}}, cap_or_inf(p_.chi_max), step_, s);
+  commit(fn, s);
+}
+
+// ---------------------------------------------------------------- outputs
+
+void Engine::dense_of(const DMps& a, double* out, hipStream_t s) {
+  const int n = (int)a.size();
+  ArenaScope sc(tmp_);
+  long maxsz = 2L * a[0].r;
+  long rows = 2;
+  for (int j = 1; j < n; ++j) {
+    rows *= 2;
+    maxsz = std::max(maxsz, rows * (long)a[j].r);
+  }
+  double* b0 = tmp_.alloc(maxsz);
+  double* b1 = tmp_.alloc(maxsz);
+  MPSV_HIP(hipMemcpyAsync(b0, a[0].p, a[0].size() * sizeof(double),
+                          hipMemcpyDeviceToDevice, s));
+  long r = 2;  // rows of the current block
+  double* cur = b0;
+  double* nxt = b1;
+  for (int j = 1; j < n; ++j) {
+    double* dst = (j == n - 1) ? out : nxt;
+    gemm(s, (int)r, 2 * a[j].r, a[j].l, 1.0, CMatView{cur, a[j].l, 1, 0},
+         CMatView{a[j].p, 2L * a[j].r, 1, 0}, 0.0,
+         MatView{dst, 2L * a[j].r, 1, 0});
+    r *= 2;
+    std::swap(cur, nxt);
+  }
+}
+
+void Engine::to_dense(double* out, hipStream_t s) {
+  MPSV_CHECK(!f_.empty(), kEinval, "state not initialised");
+  if (p_.order == 0) {
+    dense_of(f_, out, s);
+  } else {
+    ArenaScope sc(tmp_);
+    double* v = tmp_.alloc((size_t)1 << n());
+    dense_of(f_, v, s);
+    deinterleave(s, v, p_.Lx, out);
+  }
+}
+
+double Engine::full_contract(const DMps& g, const DMps& f, hipStream_t s) {
+  ArenaScope sc(tmp_);
+  double* E = tmp_.alloc(1);
+  fill(s, E, 1, 1.0);
+  int ga = 1, fa = 1;
+  for (size_t j = 0; j < f.size(); ++j) {
+    const Core& G = g[j];
+    const Core& F = f[j];
+    double* T = tmp_.alloc((size_t)ga * 2 * F.r);
+    gemm(s, ga, 2 * F.r, fa, 1.0, CMatView{E, fa, 1, 0},
+         CMatView{F.p, 2L * F.r, 1, 0}, 0.0, MatView{T, 2L * F.r, 1, 0});
+    double* En = tmp_.alloc((size_t)G.r * F.r);
+    for (int sidx = 0; sidx < 2; ++sidx)
+      gemm(s, G.r, F.r, ga, 1.0, CMatView{G.p + sidx * G.r, 1, 2L * G.r, 0},
+           CMatView{T + sidx * F.r, 2L * F.r, 1, 0}, sidx ? 1.0 : 0.0,
+           MatView{En, F.r, 1, 0});
+    E = En;
+    ga = G.r;
+    fa = F.r;
+  }
+  double h = 0.0;
+  MPSV_HIP(hipMemcpyAsync(&h, E, sizeof(double), hipMemcpyDeviceToHost, s));
+  MPSV_HIP(hipStreamSynchronize(s));
+  return h;
+}
+
+void Engine::density_field(double* n_out, double* E_out, hipStream_t s) {
+  MPSV_CHECK(!f_.empty(), kEinval, "state not initialised");
+  ArenaScope sc(step_);
+  DMps nm = density(f_, step_, s);
+  DMps E = field(f_, step_, s);
+  if (n_out) dense_of(nm, n_out, s);
+  if (E_out) dense_of(E, E_out, s);
+  MPSV_HIP(hipStreamSynchronize(s));
+}
+
+void Engine::moments(double* n_out, double* E_out, double* scalars,
+                     hipStream_t s) {
+  MPSV_CHECK(!f_.empty(), kEinval, "state not initialised");
+  ArenaScope sc(step_);
+  DMps nm = density(f_, step_, s);
+  DMps E = field(f_, step_, s);
+  if (n_out) dense_of(nm, n_out, s);
+  double* Ed = nullptr;
+  if (E_out) {
+    dense_of(E, E_out, s);
+    Ed = E_out;
+  }
+  if (scalars) {
+    ArenaScope sc2(tmp_);
+    if (!Ed) {
+      Ed = step_.alloc((size_t)p_.Nx());
+      dense_of(E, Ed, s);
+    }
+    double* we = tmp_.alloc(1);
+    sum_squares(s, Ed, p_.Nx(), 0.5 * p_.dx(), we);
+    double hwe = 0.0;
+    MPSV_HIP(hipMemcpyAsync(&hwe, we, sizeof(double), hipMemcpyDeviceToHost, s));
+    MPSV_HIP(hipStreamSynchronize(s));
+    // mass = dx * sum_i n_i = dx dv <1, f>; momentum / kinetic with v, v^2/2
+    double mass = 0.0;
+    {
+      // <1, n> over the x sites
+      ArenaScope sc3(tmp_);
+      DMps onesx(nm.size());
+      for (size_t j = 0; j < nm.size(); ++j) {
+        onesx[j] = Core{tmp_.alloc(2), 1, 1};
+        fill(s, onesx[j].p, 2, 1.0);
+      }
+      mass = p_.dx() * full_contract(onesx, nm, s);
+    }
+    const double w = p_.dx() * p_.dv();
+    scalars[0] = mass;
+    scalars[1] = w * full_contract(vpoly_, f_, s);
+    scalars[2] = w * full_contract(v2poly_, f_, s);
+    scalars[3] = hwe;
+  }
+  MPSV_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace mpsv

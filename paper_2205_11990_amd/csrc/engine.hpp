@@ -1,0 +1,146 @@
+// MPS engine: device MPS/MPO objects, the compression sweep and the RK4 step.
+#pragma once
+#include <memory>
+#include <vector>
+
+#include "arena.hpp"
+#include "common.hpp"
+#include "linalg.hpp"
+
+namespace mpsv {
+
+struct Problem {
+  int Lx = 6, Lv = 6, order = 0;
+  double x_min = 0, x_max = 1, v_min = -1, v_max = 1;
+  double qm = -1.0, dt = 0.05;
+  int chi_max = 16, level = 1, df_max = 0;
+  double tol = 1e-10;
+  int precision = 0;
+  int n() const { return Lx + Lv; }
+  long Nx() const { return 1L << Lx; }
+  long Nv() const { return 1L << Lv; }
+  double dx() const { return (x_max - x_min) / (double)Nx(); }
+  double dv() const { return (v_max - v_min) / (double)(Nv() - 1); }
+};
+
+// MPS core A[a][s][b], row-major, a < l, s < 2, b < r.
+struct Core {
+  double* p = nullptr;
+  int l = 1, r = 1;
+  long size() const { return (long)l * 2 * r; }
+};
+using DMps = std::vector<Core>;
+
+// MPO site W[b][o][i][b'] and Wmat[(o,b')][(b,i)] (both device).
+struct MpoSite {
+  double* W = nullptr;
+  double* Wmat = nullptr;
+  int wl = 1, wr = 1;
+};
+using DMpo = std::vector<MpoSite>;
+
+// One site of an implicit chain handed to the compression sweep.
+struct VSite {
+  enum Kind { kDense, kApply, kSum } kind = kDense;
+  int l = 1, r = 1;
+  Core A;                                    // kDense, kApply
+  MpoSite W;                                 // kApply
+  std::vector<double> coef;                  // kSum
+  std::vector<Core> terms;                   // kSum
+  std::vector<int> loff, roff;               // kSum block offsets
+  int pos = 1;                               // kSum: 0 first, 1 middle, 2 last
+};
+
+struct StepTimers {
+  double compress_ms = 0;
+};
+
+class Engine {
+ public:
+  explicit Engine(const Problem& p);
+  ~Engine() = default;
+
+  const Problem& problem() const { return p_; }
+  int n() const { return p_.n(); }
+
+  // ---- state
+  void init_from_profiles(int rank, const double* ax, const double* bv,
+                          hipStream_t s);
+  void set_state(const std::vector<int>& bonds, const double* packed,
+                 hipStream_t s);
+  void get_state(std::vector<int>& bonds, double* packed, hipStream_t s) const;
+  void add_scaled(double alpha, const std::vector<int>& bonds,
+                  const double* packed, hipStream_t s);
+  const DMps& state() const { return f_; }
+  std::vector<int> bonds() const;
+  double time() const { return t_; }
+  long steps_done() const { return steps_; }
+  const std::vector<double>& last_discarded() const { return disc_; }
+
+  // ---- the hot path
+  void step(hipStream_t s);
+
+  // ---- outputs
+  void to_dense(double* out, hipStream_t s);
+  void moments(double* n_out, double* E_out, double* scalars, hipStream_t s);
+  void density_field(double* n_out, double* E_out, hipStream_t s);
+
+  // ---- building blocks exposed for tests through the C-ABI
+  DMps compress_chain(const std::vector<VSite>& ch, int cap, double tol,
+                      Arena& out, hipStream_t s, std::vector<double>* disc);
+  DMps compress_mps(const DMps& a, int cap, double tol, Arena& out,
+                    hipStream_t s, std::vector<double>* disc = nullptr);
+  DMps apply_compress(const DMpo& W, const DMps& a, int cap, double tol,
+                      Arena& out, hipStream_t s,
+                      std::vector<double>* disc = nullptr);
+  DMpo upload_mpo(const std::vector<std::vector<double>>& W,
+                  const std::vector<int>& bonds, Arena& ar, hipStream_t s);
+
+  DMps add_terms(const std::vector<std::pair<double, const DMps*>>& terms,
+                 int cap, Arena& out, hipStream_t s, double tol = -1.0);
+  Arena& scratch() { return tmp_; }
+
+ private:
+  void absorb_left(const VSite& v, const double* R, int p, double* M,
+                   hipStream_t s);
+  DMps density(const DMps& g, Arena& ar, hipStream_t s);
+  DMps field(const DMps& g, Arena& ar, hipStream_t s);
+  DMpo t2_mpo(const DMps& E, Arena& ar, hipStream_t s);
+  DMps rhs(const DMps& g, Arena& out, hipStream_t s);
+  DMps copy_mps(const DMps& a, Arena& ar, hipStream_t s);
+  void commit(const DMps& fn, hipStream_t s);
+  double full_contract(const DMps& g, const DMps& f, hipStream_t s);
+  void dense_of(const DMps& a, double* out, hipStream_t s);
+  int cap_for(int point) const;
+
+  Problem p_;
+  Arena ops_{(size_t)16 << 20};    // operators (persistent)
+  Arena state_{(size_t)16 << 20};  // committed state
+  Arena step_;                     // per-step intermediates
+  Arena tmp_;                      // per-RHS intermediates
+  Arena work_;                     // per-compression workspace
+  DMpo t1_, gneg_, dv_;            // T1 chain, -G (x sites), Dv (v sites)
+  DMps vpoly_, v2poly_;            // moment weights (full chain)
+  DMps f_;
+  std::vector<double> disc_;
+  double t_ = 0.0;
+  long steps_ = 0;
+  int* dflag_ = nullptr;
+};
+
+// Host construction of the operators (exact, FP64).  W[bl][o][i][br].
+namespace ops {
+using HostMpo = std::vector<std::vector<double>>;
+HostMpo d1_periodic(int L, double h, std::vector<int>& bonds);
+HostMpo d1_zero_gradient(int L, double h, std::vector<int>& bonds);
+HostMpo poisson_g(int L, double dx, double scale, std::vector<int>& bonds);
+// diag of c0 + c1 J + c2 J^2 with J the integer index (MSB first); J -> v
+HostMpo poly_diag(int L, double c0, double c1, double c2, std::vector<int>& bonds);
+// the matching MPS (values instead of a diagonal operator)
+std::vector<std::vector<double>> poly_mps(int L, double c0, double c1, double c2,
+                                          std::vector<int>& bonds);
+HostMpo chain(const HostMpo& Wx, const std::vector<int>& bx, const HostMpo& Wv,
+              const std::vector<int>& bv, int order, std::vector<int>& bonds);
+}  // namespace ops
+
+}  // namespace mpsv

@@ -1,0 +1,139 @@
+// FP64 general strided batched GEMM on the CDNA4 matrix cores.
+//
+//   C[b] = alpha * A[b] (M x K) * B[b] (K x N) + beta * C[b]
+//
+// Every operand is a strided view (row stride, column stride, batch stride),
+// so transposes, sub-blocks and the fused-bond reshapes of MPS cores are
+// expressed without copies.  Tiles of 64 x 64 x 16 are staged through LDS;
+// each of the 4 waves owns a 32 x 32 sub-tile computed by 2 x 2
+// v_mfma_f64_16x16x4f64 accumulators (64-wide wavefronts).
+#include "gemm.hpp"
+
+namespace mpsv {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int BM = 64, BN = 64, BK = 16, NT = 256;
+
+__global__ __launch_bounds__(NT) void gemm_f64_kernel(
+    int M, int N, int K, double alpha, const double* __restrict__ A, long ars,
+    long acs, long abs_, const double* __restrict__ B, long brs, long bcs,
+    long bbs, double beta, double* __restrict__ C, long crs, long ccs, long cbs,
+    int a_kfast, int b_nfast) {
+  __shared__ double As[BK][BM + 1];
+  __shared__ double Bs[BK][BN + 1];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const long bz = blockIdx.z;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  A += bz * abs_;
+  B += bz * bbs;
+  C += bz * cbs;
+
+  dbl4 acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+
+  for (int k0 = 0; k0 < K; k0 += BK) {
+#pragma unroll
+    for (int q = 0; q < (BM * BK) / NT; ++q) {
+      int e = tid + q * NT;
+      int r, k;
+      if (a_kfast) { r = e / BK; k = e % BK; } else { k = e / BM; r = e % BM; }
+      int gr = m0 + r, gk = k0 + k;
+      As[k][r] = (gr < M && gk < K) ? A[(long)gr * ars + (long)gk * acs] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < (BN * BK) / NT; ++q) {
+      int e = tid + q * NT;
+      int c, k;
+      if (b_nfast) { k = e / BN; c = e % BN; } else { c = e / BK; k = e % BK; }
+      int gc = n0 + c, gk = k0 + k;
+      Bs[k][c] = (gc < N && gk < K) ? B[(long)gk * brs + (long)gc * bcs] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      double a0 = As[kr][wm * 32 + (lane & 15)];
+      double a1 = As[kr][wm * 32 + 16 + (lane & 15)];
+      double b0 = Bs[kr][wn * 32 + (lane & 15)];
+      double b1 = Bs[kr][wn * 32 + 16 + (lane & 15)];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+
+  // D layout of the 16x16 f64 block: lane l, item r -> row 4*r + l/16, col l%16
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int gr = m0 + wm * 32 + i * 16 + 4 * r + (lane >> 4);
+        int gc = n0 + wn * 32 + j * 16 + (lane & 15);
+        if (gr < M && gc < N) {
+          double* cp = C + (long)gr * crs + (long)gc * ccs;
+          double v = alpha * acc[i][j][r];
+          *cp = (beta == 0.0) ? v : v + beta * (*cp);
+        }
+      }
+}
+
+}  // namespace
+
+void gemm(hipStream_t s, int M, int N, int K, double alpha, CMatView A,
+          CMatView B, double beta, MatView C, int batch) {
+  if (M <= 0 || N <= 0 || batch <= 0) return;
+  if (K <= 0) {
+    // C = beta * C
+    scale_matrix(s, M, N, beta, C, batch);
+    return;
+  }
+  const int a_kfast = (A.cs == 1) ? 1 : 0;
+  const int b_nfast = (B.cs == 1) ? 1 : 0;
+  for (int b0 = 0; b0 < batch; b0 += 65535) {
+    int nb = batch - b0 < 65535 ? batch - b0 : 65535;
+    dim3 grid(ceil_div(N, BN), ceil_div(M, BM), nb);
+    hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(NT), 0, s, M, N, K, alpha,
+                       A.p + (long)b0 * A.bs, A.rs, A.cs, A.bs,
+                       B.p + (long)b0 * B.bs, B.rs, B.cs, B.bs, beta,
+                       C.p + (long)b0 * C.bs, C.rs, C.cs, C.bs, a_kfast,
+                       b_nfast);
+    MPSV_LAUNCHED();
+  }
+}
+
+namespace {
+__global__ void scale_matrix_kernel(int M, int N, double beta, double* C,
+                                    long rs, long cs, long bs) {
+  long b = blockIdx.y;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < (long)M * N;
+       e += (long)gridDim.x * blockDim.x) {
+    long i = e / N, j = e % N;
+    double* p = C + b * bs + i * rs + j * cs;
+    *p = (beta == 0.0) ? 0.0 : beta * (*p);
+  }
+}
+}  // namespace
+
+void scale_matrix(hipStream_t s, int M, int N, double beta, MatView C,
+                  int batch) {
+  if (M <= 0 || N <= 0 || batch <= 0) return;
+  long tot = (long)M * N;
+  int blocks = ceil_div(tot, 256);
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(scale_matrix_kernel, dim3(blocks, batch), dim3(256), 0,
+                     s, M, N, beta, C.p, C.rs, C.cs, C.bs);
+  MPSV_LAUNCHED();
+}
+
+}  // namespace mpsv

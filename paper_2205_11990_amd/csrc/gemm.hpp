@@ -1,0 +1,16 @@
+// FP64 strided batched GEMM on MFMA (see gemm.hip).
+#pragma once
+#include "common.hpp"
+
+namespace mpsv {
+
+// C[b] = alpha * A[b] * B[b] + beta * C[b]; A is M x K, B is K x N.
+// beta == 0 never reads C.  Stream-ordered, no synchronisation.
+void gemm(hipStream_t s, int M, int N, int K, double alpha, CMatView A,
+          CMatView B, double beta, MatView C, int batch = 1);
+
+// C[b] = beta * C[b] (beta == 0 writes zeros without reading).
+void scale_matrix(hipStream_t s, int M, int N, double beta, MatView C,
+                  int batch = 1);
+
+}  // namespace mpsv

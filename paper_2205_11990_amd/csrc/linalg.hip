@@ -1,0 +1,550 @@
+// FP64 factorisations for the compression sweeps (SI, "Canonicalization and
+// Compression"): blocked Householder QR and one-sided Jacobi SVD.
+//
+// QR: right-looking blocked Householder.  A panel of jb <= 32 columns is
+// factored by one workgroup (held in LDS when it fits), which also forms the
+// compact-WY factor T and Y = V T; the trailing matrix is updated with two
+// MFMA GEMMs, A2 -= V (Y^T A2).
+//
+// SVD: X (m x c) is first reduced to its c x c triangular factor when tall,
+// then one-sided (Hestenes) Jacobi with the cyclic round-robin ordering is
+// run by one workgroup, columns and accumulated rotations held in LDS when
+// they fit.  Singular values are the final column norms; sorting and the
+// truncation rule (cap chi, relative discarded weight tol, eq. 5) are
+// evaluated on the device.
+#include <algorithm>
+#include <cmath>
+#include <mutex>
+
+#include "gemm.hpp"
+#include "linalg.hpp"
+
+namespace mpsv {
+
+namespace {
+
+constexpr int NT = 256;
+constexpr int MAXJB = 32;
+constexpr size_t kPanelLds = 144 * 1024;
+constexpr size_t kJacobiLds = 144 * 1024;
+
+LinalgStats g_stats;
+int g_max_sweeps = 60;
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum over the workgroup; every thread receives the total.
+__device__ inline double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int i = 0; i < NT / 64; ++i) t += red[i];
+  return t;
+}
+
+// Panel factorisation: P is (m x jb), row stride ld, in global memory.
+__global__ __launch_bounds__(NT) void qr_panel_kernel(double* P, int m, int jb,
+                                                      long ld, double* V,
+                                                      double* Y, int use_lds) {
+  extern __shared__ double smem[];
+  __shared__ double red[NT / 64][MAXJB + 1];
+  __shared__ double tau_s[MAXJB];
+  __shared__ double T[MAXJB][MAXJB];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+
+  double* pp;
+  long pld;
+  if (use_lds) {
+    pp = smem;
+    pld = jb;
+    for (long e = tid; e < (long)m * jb; e += NT) {
+      long i = e / jb, j = e % jb;
+      pp[e] = P[i * ld + j];
+    }
+    __syncthreads();
+  } else {
+    pp = P;
+    pld = ld;
+  }
+
+  for (int c = 0; c < jb; ++c) {
+    double part = 0.0;
+    for (int i = c + 1 + tid; i < m; i += NT) {
+      double x = pp[(long)i * pld + c];
+      part += x * x;
+    }
+    // block reduction of the column norm below the diagonal
+    part = wave_sum(part);
+    __syncthreads();
+    if (lane == 0) red[wv][0] = part;
+    __syncthreads();
+    double xn2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) xn2 += red[i][0];
+    const double alpha = (c < m) ? pp[(long)c * pld + c] : 0.0;
+    double tau = 0.0, beta = alpha, scal = 0.0;
+    if (xn2 > 0.0) {
+      beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+      tau = (beta - alpha) / beta;
+      scal = 1.0 / (alpha - beta);
+    }
+    __syncthreads();
+    if (xn2 > 0.0)
+      for (int i = c + 1 + tid; i < m; i += NT) pp[(long)i * pld + c] *= scal;
+    if (tid == 0) {
+      if (c < m) pp[(long)c * pld + c] = beta;
+      tau_s[c] = tau;
+    }
+    __syncthreads();
+    const int nr = jb - c - 1;
+    if (nr > 0 && tau != 0.0) {
+      double w[MAXJB];
+#pragma unroll
+      for (int j = 0; j < MAXJB; ++j) w[j] = 0.0;
+      for (int i = c + tid; i < m; i += NT) {
+        const double vi = (i == c) ? 1.0 : pp[(long)i * pld + c];
+        const double* row = pp + (long)i * pld + c + 1;
+#pragma unroll
+        for (int j = 0; j < MAXJB; ++j)
+          if (j < nr) w[j] += vi * row[j];
+      }
+#pragma unroll
+      for (int j = 0; j < MAXJB; ++j)
+        if (j < nr) w[j] = wave_sum(w[j]);
+      if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < MAXJB; ++j)
+          if (j < nr) red[wv][j] = w[j];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < MAXJB; ++j)
+        if (j < nr) {
+          double t = 0.0;
+#pragma unroll
+          for (int q = 0; q < NT / 64; ++q) t += red[q][j];
+          w[j] = t * tau;
+        }
+      for (int i = c + tid; i < m; i += NT) {
+        const double vi = (i == c) ? 1.0 : pp[(long)i * pld + c];
+        double* row = pp + (long)i * pld + c + 1;
+#pragma unroll
+        for (int j = 0; j < MAXJB; ++j)
+          if (j < nr) row[j] -= vi * w[j];
+      }
+      __syncthreads();
+    }
+  }
+
+  // explicit V (unit lower trapezoidal)
+  for (long e = tid; e < (long)m * jb; e += NT) {
+    int i = (int)(e / jb), k = (int)(e % jb);
+    V[e] = (i < k) ? 0.0 : (i == k ? 1.0 : pp[(long)i * pld + k]);
+  }
+  __syncthreads();
+  __threadfence_block();
+  // T (upper triangular), column by column: T[0:c,c] = -tau_c T[0:c,0:c] (V^T v_c)
+  for (int c = 0; c < jb; ++c) {
+    double z[MAXJB];
+#pragma unroll
+    for (int k = 0; k < MAXJB; ++k) z[k] = 0.0;
+    for (int i = c + tid; i < m; i += NT) {
+      const double vc = V[(long)i * jb + c];
+#pragma unroll
+      for (int k = 0; k < MAXJB; ++k)
+        if (k < c) z[k] += V[(long)i * jb + k] * vc;
+    }
+#pragma unroll
+    for (int k = 0; k < MAXJB; ++k)
+      if (k < c) z[k] = wave_sum(z[k]);
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+      for (int k = 0; k < MAXJB; ++k)
+        if (k < c) red[wv][k] = z[k];
+    }
+    __syncthreads();
+    if (tid < jb) {
+      if (tid < c) {
+        double acc = 0.0;
+        for (int l = tid; l < c; ++l) {
+          double zl = 0.0;
+          for (int q = 0; q < NT / 64; ++q) zl += red[q][l];
+          acc += T[tid][l] * zl;
+        }
+        T[tid][c] = -tau_s[c] * acc;
+      } else if (tid == c) {
+        T[c][c] = tau_s[c];
+      } else {
+        T[tid][c] = 0.0;
+      }
+    }
+    __syncthreads();
+  }
+  // Y = V T
+  for (long e = tid; e < (long)m * jb; e += NT) {
+    int i = (int)(e / jb), c = (int)(e % jb);
+    double acc = 0.0;
+    for (int k = 0; k <= c; ++k) acc += V[(long)i * jb + k] * T[k][c];
+    Y[e] = acc;
+  }
+  if (use_lds) {
+    for (long e = tid; e < (long)m * jb; e += NT) {
+      long i = e / jb, j = e % jb;
+      P[i * ld + j] = pp[e];
+    }
+  }
+}
+
+__global__ void extract_r_kernel(const double* A, int k, int n, long ld,
+                                 double* R, long ldr) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < (long)k * n;
+       e += (long)gridDim.x * blockDim.x) {
+    long i = e / n, j = e % n;
+    R[i * ldr + j] = (j >= i) ? A[i * ld + j] : 0.0;
+  }
+}
+
+__global__ void fill_rows_zero_kernel(double* X, int r0, int r1, int nc,
+                                      long ld) {
+  long tot = (long)(r1 - r0) * nc;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot;
+       e += (long)gridDim.x * blockDim.x) {
+    long i = r0 + e / nc, j = e % nc;
+    X[i * ld + j] = 0.0;
+  }
+}
+
+// One-sided Jacobi SVD of B (mb x c, row-major, leading dimension ldb).
+// Working copies are column-major: W[j*mb + i] (= B J) and J[j*c + i].
+// info[0] = D, info[1] = discarded weight, info[2] = sweeps, info[3] = 1 if
+// converged.
+__global__ __launch_bounds__(NT) void jacobi_svd_kernel(
+    const double* __restrict__ B, int mb, int c, long ldb, double* Wg,
+    double* Jg, int use_lds, int cap, double tol, int max_sweeps, double* Vt,
+    double* USs, long ldus_rows_limit, double* sig_out, double* info) {
+  extern __shared__ double smem[];
+  __shared__ double red[NT / 64];
+  __shared__ int rotated;
+  __shared__ int Dsh;
+  const int tid = threadIdx.x;
+  double* W = use_lds ? smem : Wg;
+  double* J = use_lds ? smem + (long)mb * c : Jg;
+
+  for (long e = tid; e < (long)mb * c; e += NT) {
+    long j = e / mb, i = e % mb;
+    W[e] = B[i * ldb + j];
+  }
+  for (long e = tid; e < (long)c * c; e += NT) {
+    long j = e / c, i = e % c;
+    J[e] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  double part = 0.0;
+  for (long e = tid; e < (long)mb * c; e += NT) part += W[e] * W[e];
+  const double normF2 = block_sum(part, red);
+  const double abs_floor = 1e-32 * normF2;
+  const double eps = 1e-15;
+
+  const int cc = c + (c & 1);
+  const int np = cc / 2;
+  int G = 1;
+  while (G < 64 && G * 2 * np <= NT) G *= 2;
+  const int ngroups = NT / G;
+  const int grp = tid / G, lig = tid % G;
+
+  int sweep = 0;
+  int converged = 0;
+  for (; sweep < max_sweeps; ++sweep) {
+    if (tid == 0) rotated = 0;
+    __syncthreads();
+    for (int r = 0; r < cc - 1; ++r) {
+      for (int k = grp; k < np; k += ngroups) {
+        int p, q;
+        if (k == 0) {
+          p = cc - 1;
+          q = r;
+        } else {
+          p = (r + k) % (cc - 1);
+          q = (r - k + cc - 1) % (cc - 1);
+        }
+        if (p >= c || q >= c) continue;
+        double* wp = W + (long)p * mb;
+        double* wq = W + (long)q * mb;
+        double a = 0.0, b = 0.0, g = 0.0;
+        for (int i = lig; i < mb; i += G) {
+          double x = wp[i], y = wq[i];
+          a += x * x;
+          b += y * y;
+          g += x * y;
+        }
+        for (int o = G >> 1; o > 0; o >>= 1) {
+          a += __shfl_xor(a, o, 64);
+          b += __shfl_xor(b, o, 64);
+          g += __shfl_xor(g, o, 64);
+        }
+        if (g != 0.0 && fabs(g) > eps * sqrt(a * b) && fabs(g) > abs_floor) {
+          const double z = (b - a) / (2.0 * g);
+          const double t = (z == 0.0) ? 1.0 : copysign(1.0, z) / (fabs(z) + hypot(1.0, z));
+          const double cs = 1.0 / sqrt(1.0 + t * t);
+          const double sn = cs * t;
+          for (int i = lig; i < mb; i += G) {
+            double x = wp[i], y = wq[i];
+            wp[i] = cs * x - sn * y;
+            wq[i] = sn * x + cs * y;
+          }
+          double* jp = J + (long)p * c;
+          double* jq = J + (long)q * c;
+          for (int i = lig; i < c; i += G) {
+            double x = jp[i], y = jq[i];
+            jp[i] = cs * x - sn * y;
+            jq[i] = sn * x + cs * y;
+          }
+          if (lig == 0) rotated = 1;
+        }
+      }
+      __syncthreads();
+    }
+    if (rotated == 0) {
+      converged = 1;
+      ++sweep;
+      break;
+    }
+    __syncthreads();
+  }
+
+  // singular values = column norms, sorted descending (ties by index);
+  // the norms go to the scratch half of sig_out first
+  for (int j = tid; j < c; j += NT) {
+    double s2 = 0.0;
+    const double* wj = W + (long)j * mb;
+    for (int i = 0; i < mb; ++i) s2 += wj[i] * wj[i];
+    sig_out[c + j] = sqrt(s2);  // scratch half of sig_out (length 2c)
+  }
+  __syncthreads();
+  __threadfence_block();
+  int* perm = (int*)(sig_out + 2 * c);  // int scratch after the values
+  for (int j = tid; j < c; j += NT) {
+    const double sj = sig_out[c + j];
+    int rank = 0;
+    for (int k = 0; k < c; ++k) {
+      double sk = sig_out[c + k];
+      rank += (sk > sj || (sk == sj && k < j)) ? 1 : 0;
+    }
+    perm[rank] = j;
+    sig_out[rank] = sj;
+  }
+  __syncthreads();
+  __threadfence_block();
+  const int kmax = mb < c ? mb : c;
+  if (tid == 0) {
+    double tot = 0.0;
+    for (int i = 0; i < c; ++i) tot += sig_out[i] * sig_out[i];
+    int D = kmax;
+    int capd = cap < kmax ? cap : kmax;
+    double disc2 = 0.0;
+    if (tot <= 0.0) {
+      D = 1;
+    } else if (tol <= 0.0) {
+      D = capd;
+    } else {
+      // smallest D' >= 1 with sum_{i >= D'} t_i <= tol^2, tail summed from the end
+      double tail = 0.0;
+      for (int i = c - 1; i >= kmax; --i) tail += sig_out[i] * sig_out[i] / tot;
+      // walk down from kmax accumulating the tail (values beyond kmax are
+      // the numerically zero columns of a wide matrix)
+      int best = kmax;
+      double acc = tail;
+      for (int Dp = kmax - 1; Dp >= 1; --Dp) {
+        acc += sig_out[Dp] * sig_out[Dp] / tot;
+        if (acc <= tol * tol) best = Dp; else break;
+      }
+      D = best;
+      if (D > capd) D = capd;
+    }
+    if (D < 1) D = 1;
+    for (int i = D; i < c; ++i) disc2 += sig_out[i] * sig_out[i];
+    Dsh = D;
+    info[0] = (double)D;
+    info[1] = (tot > 0.0) ? sqrt(disc2 / tot) : 0.0;
+    info[2] = (double)sweep;
+    info[3] = (double)converged;
+  }
+  __syncthreads();
+  const int D = Dsh;
+  // Vt[d][i] = J[i][perm[d]]
+  for (long e = tid; e < (long)D * c; e += NT) {
+    long d = e / c, i = e % c;
+    Vt[e] = J[(long)perm[d] * c + i];
+  }
+  // USs[i][d] = W[i][perm[d]] for i < min(mb, limit)
+  const int rows = (int)(mb < ldus_rows_limit ? mb : ldus_rows_limit);
+  for (long e = tid; e < (long)rows * D; e += NT) {
+    long i = e / D, d = e % D;
+    USs[e] = W[(long)perm[d] * mb + i];
+  }
+}
+
+void* g_pinned = nullptr;
+std::mutex g_pinned_mu;
+
+double* pinned_info() {
+  std::lock_guard<std::mutex> lk(g_pinned_mu);
+  if (!g_pinned) MPSV_HIP(hipHostMalloc(&g_pinned, 4096, hipHostMallocDefault));
+  return (double*)g_pinned;
+}
+
+bool g_attr_done = false;
+void set_attrs() {
+  if (g_attr_done) return;
+  MPSV_HIP(hipFuncSetAttribute((const void*)qr_panel_kernel,
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)kPanelLds));
+  MPSV_HIP(hipFuncSetAttribute((const void*)jacobi_svd_kernel,
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)kJacobiLds));
+  g_attr_done = true;
+}
+
+}  // namespace
+
+LinalgStats& linalg_stats() { return g_stats; }
+void set_jacobi_max_sweeps(int n) { g_max_sweeps = n < 1 ? 1 : n; }
+int jacobi_max_sweeps() { return g_max_sweeps; }
+
+void extract_r(hipStream_t s, const double* A, int k, int n, long ld,
+               double* R, long ldr) {
+  if (k <= 0 || n <= 0) return;
+  int blocks = std::min(1024, ceil_div((long)k * n, 256));
+  hipLaunchKernelGGL(extract_r_kernel, dim3(blocks), dim3(256), 0, s, A, k, n,
+                     ld, R, ldr);
+  MPSV_LAUNCHED();
+}
+
+static void fill_rows_zero(hipStream_t s, double* X, int r0, int r1, int nc,
+                           long ld) {
+  if (r1 <= r0 || nc <= 0) return;
+  int blocks = std::min(1024, ceil_div((long)(r1 - r0) * nc, 256));
+  hipLaunchKernelGGL(fill_rows_zero_kernel, dim3(blocks), dim3(256), 0, s, X,
+                     r0, r1, nc, ld);
+  MPSV_LAUNCHED();
+}
+
+void qr_factor(hipStream_t s, Arena& ws, double* A, int m, int n, long ld,
+               QrFactor& f) {
+  set_attrs();
+  f.m = m;
+  f.n = n;
+  f.k = std::min(m, n);
+  f.panels.clear();
+  g_stats.qr_calls++;
+  for (int k0 = 0; k0 < f.k; ) {
+    const int rows = m - k0;
+    int jb = std::min(MAXJB, f.k - k0);
+    int use_lds = 0;
+    while (jb > 4 && (size_t)rows * jb * sizeof(double) > kPanelLds) jb /= 2;
+    if ((size_t)rows * jb * sizeof(double) <= kPanelLds) use_lds = 1;
+    QrPanel pn;
+    pn.k0 = k0;
+    pn.jb = jb;
+    pn.V = ws.alloc((size_t)rows * jb);
+    pn.Y = ws.alloc((size_t)rows * jb);
+    double* P = A + (long)k0 * ld + k0;
+    size_t lds = use_lds ? (size_t)rows * jb * sizeof(double) : 0;
+    hipLaunchKernelGGL(qr_panel_kernel, dim3(1), dim3(NT), lds, s, P, rows, jb,
+                       ld, pn.V, pn.Y, use_lds);
+    MPSV_LAUNCHED();
+    const int n2 = n - k0 - jb;
+    if (n2 > 0) {
+      ArenaScope sc(ws);
+      double* Wt = ws.alloc((size_t)jb * n2);
+      double* A2 = A + (long)k0 * ld + k0 + jb;
+      // Wt = Y^T A2  (jb x n2)
+      gemm(s, jb, n2, rows, 1.0, CMatView{pn.Y, 1, jb, 0},
+           CMatView{A2, ld, 1, 0}, 0.0, MatView{Wt, n2, 1, 0});
+      // A2 -= V Wt
+      gemm(s, rows, n2, jb, -1.0, CMatView{pn.V, jb, 1, 0},
+           CMatView{Wt, n2, 1, 0}, 1.0, MatView{A2, ld, 1, 0});
+    }
+    f.panels.push_back(pn);
+    k0 += jb;
+  }
+}
+
+void qr_apply_q(hipStream_t s, Arena& ws, const QrFactor& f, double* X, int nc,
+                long ldx) {
+  if (nc <= 0) return;
+  for (int p = (int)f.panels.size() - 1; p >= 0; --p) {
+    const QrPanel& pn = f.panels[p];
+    const int rows = f.m - pn.k0;
+    ArenaScope sc(ws);
+    double* Wt = ws.alloc((size_t)pn.jb * nc);
+    double* X2 = X + (long)pn.k0 * ldx;
+    // Wt = V^T X2 ; X2 -= Y Wt
+    gemm(s, pn.jb, nc, rows, 1.0, CMatView{pn.V, 1, pn.jb, 0},
+         CMatView{X2, ldx, 1, 0}, 0.0, MatView{Wt, nc, 1, 0});
+    gemm(s, rows, nc, pn.jb, -1.0, CMatView{pn.Y, pn.jb, 1, 0},
+         CMatView{Wt, nc, 1, 0}, 1.0, MatView{X2, ldx, 1, 0});
+  }
+}
+
+int svd_truncate(hipStream_t s, Arena& ws, double* X, int m, int c, long ldx,
+                 int cap, double tol, double* Vt, double* US, double* sig,
+                 double* discarded) {
+  set_attrs();
+  g_stats.svd_calls++;
+  MPSV_CHECK(m >= 1 && c >= 1, kEinval, "svd_truncate: empty matrix");
+  ArenaScope sc(ws);
+  const bool tall = m > c;
+  QrFactor qf;
+  const double* B = X;
+  long ldb = ldx;
+  int mb = m;
+  if (tall) {
+    qr_factor(s, ws, X, m, c, ldx, qf);
+    double* R = ws.alloc((size_t)c * c);
+    extract_r(s, X, c, c, ldx, R, c);
+    B = R;
+    ldb = c;
+    mb = c;
+  }
+  const size_t need = ((size_t)mb * c + (size_t)c * c) * sizeof(double);
+  const int use_lds = need <= kJacobiLds ? 1 : 0;
+  double* Wg = use_lds ? nullptr : ws.alloc((size_t)mb * c);
+  double* Jg = use_lds ? nullptr : ws.alloc((size_t)c * c);
+  double* sigbuf = ws.alloc((size_t)3 * c + 8);
+  double* info = ws.alloc(8);
+  hipLaunchKernelGGL(jacobi_svd_kernel, dim3(1), dim3(NT), use_lds ? need : 0,
+                     s, B, mb, c, ldb, Wg, Jg, use_lds, cap, tol, g_max_sweeps,
+                     Vt, US, (long)mb, sigbuf, info);
+  MPSV_LAUNCHED();
+  double* h = pinned_info();
+  MPSV_HIP(hipMemcpyAsync(h, info, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+  MPSV_HIP(hipStreamSynchronize(s));
+  const int D = (int)h[0];
+  if (discarded) *discarded = h[1];
+  g_stats.jacobi_sweeps += (long)h[2];
+  if (h[3] == 0.0)
+    throw Error(kEnumeric, "Jacobi SVD did not converge within " +
+                               std::to_string(g_max_sweeps) + " sweeps");
+  if (sig) {
+    MPSV_HIP(hipMemcpyAsync(sig, sigbuf, (size_t)std::min(m, c) * sizeof(double),
+                            hipMemcpyDeviceToDevice, s));
+  }
+  if (tall) {
+    // US rows [0, c) were written by the kernel with leading dimension D
+    fill_rows_zero(s, US, c, m, D, D);
+    qr_apply_q(s, ws, qf, US, D, D);
+  }
+  return D;
+}
+
+}  // namespace mpsv

@@ -1,0 +1,62 @@
+// FP64 factorisations used by the MPS compression sweeps:
+// blocked Householder QR and one-sided Jacobi SVD with an on-device rank rule.
+#pragma once
+#include <vector>
+
+#include "arena.hpp"
+#include "common.hpp"
+
+namespace mpsv {
+
+// One block of Householder reflectors H = I - V T V^T acting on rows
+// [k0, m) of the factored matrix.  V is (m-k0) x jb (explicit, unit lower
+// trapezoidal), Y = V T.
+struct QrPanel {
+  int k0, jb;
+  double* V;
+  double* Y;
+};
+
+struct QrFactor {
+  int m = 0, n = 0, k = 0;
+  std::vector<QrPanel> panels;
+};
+
+// In-place QR of the row-major m x n matrix A (leading dimension ld):
+// on return the upper trapezoid of A holds R (k = min(m, n) rows) and `f`
+// describes Q = H_0 H_1 ... H_{k-1}.  Reflector storage comes from `ws`.
+void qr_factor(hipStream_t s, Arena& ws, double* A, int m, int n, long ld,
+               QrFactor& f);
+
+// X (m x nc, row-major, leading dimension ldx) <- Q X.
+void qr_apply_q(hipStream_t s, Arena& ws, const QrFactor& f, double* X,
+                int nc, long ldx);
+
+// Copy the k x n upper trapezoid of A (zeros below the diagonal) to R (ldr).
+void extract_r(hipStream_t s, const double* A, int k, int n, long ld,
+               double* R, long ldr);
+
+// Truncated SVD of the row-major m x c matrix X (leading dimension ldx).
+// Keeps D = min(cap, rank rule(tol)) singular triplets, D >= 1.
+// Outputs (device, row-major):
+//   Vt  : D x c,   rows = right singular vectors of the kept values
+//   US  : m x D,   columns = u_i * sigma_i (leading dimension ldus = D)
+//   sig : (optional, length >= min(m,c)) all singular values, descending
+// Returns D (the stream is synchronised to read it back) and the relative
+// discarded weight sqrt(sum_{i>D} s_i^2 / sum s_i^2) in *discarded.
+// X is overwritten.
+int svd_truncate(hipStream_t s, Arena& ws, double* X, int m, int c, long ldx,
+                 int cap, double tol, double* Vt, double* US, double* sig,
+                 double* discarded);
+
+// Device-side counters of the last factorisations (for diagnostics/tests).
+struct LinalgStats {
+  long qr_calls = 0, svd_calls = 0, jacobi_sweeps = 0;
+};
+LinalgStats& linalg_stats();
+
+// Maximum Jacobi sweeps (tests lower it to force a convergence failure).
+void set_jacobi_max_sweeps(int n);
+int jacobi_max_sweeps();
+
+}  // namespace mpsv

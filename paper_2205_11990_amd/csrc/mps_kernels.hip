@@ -1,0 +1,230 @@
+// Data-movement kernels of the MPS engine: block copies for direct sums
+// (SI, Addition), Kronecker embedding of one-dimension operators into the
+// interleaved chain, diagonal MPOs (SI, Dot Product), bit permutations and
+// reductions.  All are memory-bound grid-stride loops.
+#include <algorithm>
+#include <cmath>
+
+#include "mps_kernels.hpp"
+
+namespace mpsv {
+
+namespace {
+
+inline int grid_for(long n) {
+  long b = (n + 255) / 256;
+  if (b < 1) b = 1;
+  if (b > 4096) b = 4096;
+  return (int)b;
+}
+
+#define GRID_STRIDE(e, n)                                                  \
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < (n);      \
+       e += (long)gridDim.x * blockDim.x)
+
+__global__ void swap01_kernel(const double* in, int d0, int d1, long inner,
+                              double* out) {
+  const long n = (long)d0 * d1 * inner;
+  GRID_STRIDE(e, n) {
+    long k = e % inner;
+    long t = e / inner;
+    long i = t % d0;   // out index order: [j][i][k]
+    long j = t / d0;
+    out[e] = in[(i * d1 + j) * inner + k];
+  }
+}
+
+__global__ void copy2d_kernel(int rows, int cols, double alpha,
+                              const double* src, long lds, double* dst,
+                              long ldd) {
+  const long n = (long)rows * cols;
+  GRID_STRIDE(e, n) {
+    long i = e / cols, j = e % cols;
+    dst[i * ldd + j] = alpha * src[i * lds + j];
+  }
+}
+
+__global__ void sum_physical_kernel(const double* in, int l, int r,
+                                    double* out) {
+  const long n = (long)l * r;
+  GRID_STRIDE(e, n) {
+    long a = e / r, b = e % r;
+    out[e] = in[(a * 2) * r + b] + in[(a * 2 + 1) * r + b];
+  }
+}
+
+__global__ void kron_embed_kernel(const double* A, int l, int P, int r, int d,
+                                  int mode, double* out) {
+  // out shape (l*d) x P x (r*d); write all entries (zeros off the identity)
+  const long L = (long)l * d, R = (long)r * d;
+  const long n = L * P * R;
+  GRID_STRIDE(e, n) {
+    long col = e % R;
+    long t = e / R;
+    long p = t % P;
+    long row = t / P;
+    long a, c1, b, c2;
+    if (mode == 0) {
+      a = row / d; c1 = row % d; b = col / d; c2 = col % d;
+    } else {
+      c1 = row / l; a = row % l; c2 = col / r; b = col % r;
+    }
+    out[e] = (c1 == c2) ? A[(a * P + p) * r + b] : 0.0;
+  }
+}
+
+__global__ void diag_mpo_kernel(const double* E, int l, int r, double scale,
+                                double* W) {
+  const long n = (long)l * 4 * r;
+  GRID_STRIDE(e, n) {
+    long b = e % r;
+    long t = e / r;
+    long i = t % 2;
+    long o = (t / 2) % 2;
+    long a = t / 4;
+    W[e] = (o == i) ? scale * E[(a * 2 + i) * r + b] : 0.0;
+  }
+}
+
+__global__ void mpo_left_matrix_kernel(const double* W, int wl, int wr,
+                                       double* Wmat) {
+  const long n = (long)2 * wr * 2 * wl;
+  GRID_STRIDE(e, n) {
+    long col = e % (2 * wl);   // (b, i)
+    long row = e / (2 * wl);   // (o, b')
+    long b = col / 2, i = col % 2;
+    long o = row / wr, bp = row % wr;
+    Wmat[e] = W[((b * 2 + o) * 2 + i) * wr + bp];
+  }
+}
+
+__global__ void deinterleave_kernel(const double* in, int L, double* out) {
+  const long N = 1L << L;
+  const long n = N * N;
+  GRID_STRIDE(e, n) {
+    long i = e / N, j = e % N;
+    long idx = 0;
+    for (int k = 0; k < L; ++k) {
+      long xb = (i >> (L - 1 - k)) & 1;
+      long vb = (j >> (L - 1 - k)) & 1;
+      idx = (idx << 2) | (xb << 1) | vb;
+    }
+    out[e] = in[idx];
+  }
+}
+
+__global__ void count_nonfinite_kernel(const double* x, long n, int* flag) {
+  int bad = 0;
+  GRID_STRIDE(e, n) {
+    if (!isfinite(x[e])) bad = 1;
+  }
+  if (bad) atomicAdd(flag, 1);
+}
+
+__global__ void sum_squares_kernel(const double* x, long n, double scale,
+                                   double* out) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (long e = threadIdx.x; e < n; e += blockDim.x) acc += x[e] * x[e];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = scale * red[0];
+}
+
+__global__ void fill_kernel(double* x, long n, double v) {
+  GRID_STRIDE(e, n) x[e] = v;
+}
+__global__ void fill_int_kernel(int* x, long n, int v) {
+  GRID_STRIDE(e, n) x[e] = v;
+}
+
+}  // namespace
+
+void swap01(hipStream_t s, const double* in, int d0, int d1, long inner,
+            double* out) {
+  long n = (long)d0 * d1 * inner;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(swap01_kernel, dim3(grid_for(n)), dim3(256), 0, s, in, d0,
+                     d1, inner, out);
+  MPSV_LAUNCHED();
+}
+
+void copy2d(hipStream_t s, int rows, int cols, double alpha, const double* src,
+            long lds, double* dst, long ldd) {
+  long n = (long)rows * cols;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(copy2d_kernel, dim3(grid_for(n)), dim3(256), 0, s, rows,
+                     cols, alpha, src, lds, dst, ldd);
+  MPSV_LAUNCHED();
+}
+
+void sum_physical(hipStream_t s, const double* in, int l, int r, double* out) {
+  long n = (long)l * r;
+  hipLaunchKernelGGL(sum_physical_kernel, dim3(grid_for(n)), dim3(256), 0, s,
+                     in, l, r, out);
+  MPSV_LAUNCHED();
+}
+
+void kron_embed(hipStream_t s, const double* A, int l, int P, int r, int d,
+                int mode, double* out) {
+  long n = (long)l * d * P * r * d;
+  hipLaunchKernelGGL(kron_embed_kernel, dim3(grid_for(n)), dim3(256), 0, s, A,
+                     l, P, r, d, mode, out);
+  MPSV_LAUNCHED();
+}
+
+void diag_mpo_site(hipStream_t s, const double* E, int l, int r, double scale,
+                   double* W) {
+  long n = (long)l * 4 * r;
+  hipLaunchKernelGGL(diag_mpo_kernel, dim3(grid_for(n)), dim3(256), 0, s, E, l,
+                     r, scale, W);
+  MPSV_LAUNCHED();
+}
+
+void mpo_left_matrix(hipStream_t s, const double* W, int wl, int wr,
+                     double* Wmat) {
+  long n = (long)4 * wl * wr;
+  hipLaunchKernelGGL(mpo_left_matrix_kernel, dim3(grid_for(n)), dim3(256), 0, s,
+                     W, wl, wr, Wmat);
+  MPSV_LAUNCHED();
+}
+
+void deinterleave(hipStream_t s, const double* in, int L, double* out) {
+  long n = 1L << (2 * L);
+  hipLaunchKernelGGL(deinterleave_kernel, dim3(grid_for(n)), dim3(256), 0, s,
+                     in, L, out);
+  MPSV_LAUNCHED();
+}
+
+void count_nonfinite(hipStream_t s, const double* x, long n, int* flag) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(count_nonfinite_kernel, dim3(grid_for(n)), dim3(256), 0,
+                     s, x, n, flag);
+  MPSV_LAUNCHED();
+}
+
+void sum_squares(hipStream_t s, const double* x, long n, double scale,
+                 double* out) {
+  hipLaunchKernelGGL(sum_squares_kernel, dim3(1), dim3(256), 0, s, x, n, scale,
+                     out);
+  MPSV_LAUNCHED();
+}
+
+void fill(hipStream_t s, double* x, long n, double v) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n)), dim3(256), 0, s, x, n, v);
+  MPSV_LAUNCHED();
+}
+
+void fill_int(hipStream_t s, int* x, long n, int v) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_int_kernel, dim3(grid_for(n)), dim3(256), 0, s, x, n,
+                     v);
+  MPSV_LAUNCHED();
+}
+
+}  // namespace mpsv

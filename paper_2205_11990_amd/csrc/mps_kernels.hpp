@@ -1,0 +1,47 @@
+// Small data-movement kernels of the MPS engine (host wrappers).
+#pragma once
+#include "common.hpp"
+
+namespace mpsv {
+
+// out[j][i][k] = in[i][j][k] for i < d0, j < d1, k < inner  (swap two outer dims)
+void swap01(hipStream_t s, const double* in, int d0, int d1, long inner,
+            double* out);
+
+// dst (rows x cols, ldd) = alpha * src (rows x cols, lds)
+void copy2d(hipStream_t s, int rows, int cols, double alpha, const double* src,
+            long lds, double* dst, long ldd);
+
+// out[a][b] = in[a][0][b] + in[a][1][b]  for an l x 2 x r core
+void sum_physical(hipStream_t s, const double* in, int l, int r, double* out);
+
+// Embed an operator/core of one dimension into the interleaved chain:
+// A has shape (l, P, r) with P = 2 (MPS core) or 4 (MPO core, (o,i) pairs).
+// mode 0 (A-major): out[(a, c), P, (b, c)]  -- fused index a*d + c
+// mode 1 (A-minor): out[(c, a), P, (c, b)]  -- fused index c*l + a
+void kron_embed(hipStream_t s, const double* A, int l, int P, int r, int d,
+                int mode, double* out);
+
+// Diagonal MPO from an MPS core (SI, Dot Product):
+// W[a][o][i][b] = scale * E[a][i][b] * delta(o, i)
+void diag_mpo_site(hipStream_t s, const double* E, int l, int r, double scale,
+                   double* W);
+
+// Wmat[(o*wr + b')][(b*2 + i)] = W[b][o][i][b']   ((2wr) x (2wl))
+void mpo_left_matrix(hipStream_t s, const double* W, int wl, int wr,
+                     double* Wmat);
+
+// Interleaved chain vector (x1 v1 x2 v2 ... MSB first) -> F[i*Nv + j].
+void deinterleave(hipStream_t s, const double* in, int L, double* out);
+
+// flag[0] += number of non-finite entries among n values (flag is int)
+void count_nonfinite(hipStream_t s, const double* x, long n, int* flag);
+
+// out[0] = sum x_i^2 * scale
+void sum_squares(hipStream_t s, const double* x, long n, double scale,
+                 double* out);
+
+void fill(hipStream_t s, double* x, long n, double v);
+void fill_int(hipStream_t s, int* x, long n, int v);
+
+}  // namespace mpsv

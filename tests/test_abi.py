@@ -1,0 +1,95 @@
+"""CPU checks of the C-ABI library: it loads, exports every symbol the
+headers declare, and its host-built operator MPOs decode to the paper's
+stencils and agree with the oracle's independently built MPOs."""
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2205_11990_amd", "libmpsvlasov.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB),
+                                reason="HIP library not built (run __graft_entry__.build())")
+
+
+def _declared():
+    names = set()
+    for h in ("mps_vlasov.h", "mps_blocks.h"):
+        txt = open(os.path.join(ROOT, "include", h)).read()
+        names |= set(re.findall(r"\b(mpsb?_[a-z_]+)\s*\(", txt))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {l.split()[-1] for l in out.splitlines() if " T " in l}
+    declared = _declared()
+    assert declared, "no declarations parsed"
+    missing = declared - exported
+    assert not missing, missing
+
+
+def test_binding_signatures_cover_the_headers():
+    from paper_2205_11990_amd import binding
+    assert set(binding.EXPORTED) == _declared()
+    binding.lib()  # loads without a GPU
+
+
+def _dense(W):
+    from oracle import mps
+    return mps.mpo_to_matrix(W)
+
+
+@pytest.mark.parametrize("L", [2, 3, 5, 7])
+def test_library_operators_decode_to_stencils(L):
+    from paper_2205_11990_amd import binding
+    from oracle import mps
+    N = 2 ** L
+    h = 0.37
+    Dx = _dense(binding.operator(0, L, 0.0, h))
+    Dv = _dense(binding.operator(1, L, 0.0, h))
+    G = _dense(binding.operator(2, L, 0.0, h))
+    V = _dense(binding.operator(3, L, -2.0, h))
+    ref = np.zeros((N, N))
+    for o in range(N):
+        ref[o, (o + 1) % N] += 0.5 / h
+        ref[o, (o - 1) % N] -= 0.5 / h
+    assert np.abs(Dx - ref).max() < 1e-13
+    refv = np.zeros((N, N))
+    for o in range(1, N - 1):
+        refv[o, o + 1] += 0.5 / h
+        refv[o, o - 1] -= 0.5 / h
+    assert np.abs(Dv - refv).max() < 1e-13
+    assert np.abs(V - np.diag(-2.0 + h * np.arange(N))).max() < 1e-13
+    # G = Dx pinv(Laplacian) built from the oracle's printed MPOs
+    Lap = mps.mpo_to_matrix(mps.mpo_d2_periodic(L, h))
+    Dxo = mps.mpo_to_matrix(mps.mpo_d1_periodic(L, h))
+    assert np.abs(G - Dxo @ np.linalg.pinv(Lap)).max() < 1e-12
+    assert np.abs(G - _dense(mps.poisson_mpo(L, h))).max() < 1e-13
+
+
+def test_library_operator_bonds():
+    from paper_2205_11990_amd import binding
+    assert [w.shape[3] for w in binding.operator(0, 6, 0, 1.0)[:-1]] == [3] * 5
+    assert [w.shape[3] for w in binding.operator(1, 6, 0, 1.0)[:-1]] == [5] * 5
+    assert [w.shape[3] for w in binding.operator(3, 6, 0, 1.0)[:-1]] == [2] * 5
+
+
+def test_invalid_arguments_are_rejected_without_a_gpu():
+    from paper_2205_11990_amd import binding
+    with pytest.raises(binding.MpsError) as e:
+        binding.operator(9, 4, 0.0, 1.0)
+    assert e.value.status == binding.MPS_EINVAL
+    with pytest.raises(binding.MpsError):
+        binding.operator(0, 1, 0.0, 1.0)
+    import workloads as wl
+    p = wl.landau_small().problem
+    p.Lx = 20
+    with pytest.raises(binding.MpsError):
+        binding.workspace_bound(p)
+    p = wl.two_stream().problem
+    assert binding.workspace_bound(p) > 0

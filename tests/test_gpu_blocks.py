@@ -1,0 +1,131 @@
+"""GPU parity of the building blocks against NumPy/LAPACK and the CPU MPS
+oracle, through the C-ABI (include/mps_blocks.h)."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import mps as omps
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print("[case] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2205_11990_amd import binding
+    binding.lib()
+    return binding
+
+
+@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (7, 5, 3), (64, 64, 16), (65, 130, 33),
+                                   (300, 17, 129), (16, 1000, 2)])
+def test_gemm_matches_numpy(B, M, N, K):
+    _say("gemm %d %d %d" % (M, N, K))
+    rng = np.random.default_rng(M * 1000 + N * 10 + K)
+    A = rng.standard_normal((M, K))
+    Bm = rng.standard_normal((K, N))
+    C0 = rng.standard_normal((M, N))
+    import torch
+    C = torch.from_numpy(C0.copy()).cuda()
+    out = B.gemm(A, Bm, alpha=0.7, beta=-1.3, C=C).cpu().numpy()
+    ref = 0.7 * A @ Bm - 1.3 * C0
+    assert np.abs(out - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max()) * np.sqrt(K)
+
+
+@pytest.mark.parametrize("m,n", [(1, 1), (5, 3), (3, 5), (40, 40), (130, 70), (257, 33),
+                                 (600, 200), (2048, 8), (64, 300)])
+def test_qr_is_orthogonal_factorisation(B, m, n):
+    _say("qr %d x %d" % (m, n))
+    A = wl.random_matrix(m, n, seed=m + 7 * n, decay=3.0)
+    R, Q = B.qr(A)
+    R = R.cpu().numpy()
+    Q = Q.cpu().numpy()
+    k = min(m, n)
+    assert np.abs(Q.T @ Q - np.eye(k)).max() < 1e-13 * max(1, np.sqrt(m))
+    assert np.abs(Q @ R - A).max() < 1e-13 * np.abs(A).max() * max(1, np.sqrt(m))
+    assert np.allclose(np.tril(R, -1), 0)
+    Rref = np.linalg.qr(A, mode="r")
+    assert np.allclose(np.abs(np.diag(R)), np.abs(np.diag(Rref[:k])), rtol=1e-10, atol=1e-13)
+
+
+@pytest.mark.parametrize("m,c,cap,tol,decay", [
+    (2, 2, 0, 0.0, 0), (10, 4, 0, 0.0, 0), (4, 10, 0, 0.0, 0), (64, 64, 0, 0.0, 6),
+    (96, 96, 40, 0.0, 8), (128, 128, 64, 0.0, 8), (500, 128, 64, 0.0, 12),
+    (300, 60, 0, 1e-10, 14), (33, 90, 0, 1e-6, 10), (1024, 16, 8, 0.0, 2)])
+def test_svd_truncate_matches_lapack_and_rank_rule(B, m, c, cap, tol, decay):
+    _say("svd %d x %d cap %d tol %g" % (m, c, cap, tol))
+    X = wl.random_matrix(m, c, seed=3 * m + c, decay=decay)
+    Vt, US, sig, disc = B.svd_truncate(X, cap=cap, tol=tol)
+    Vt, US, sig = Vt.cpu().numpy(), US.cpu().numpy(), sig.cpu().numpy()
+    s = np.linalg.svd(X, compute_uv=False)
+    assert np.abs(sig - s).max() <= 1e-13 * s[0] * np.sqrt(max(m, c))
+    D = omps.rank_rule(s, cap if cap > 0 else None, tol)
+    assert Vt.shape[0] == D
+    assert np.abs(Vt @ Vt.T - np.eye(D)).max() < 1e-12
+    # truncated reconstruction equals the best rank-D approximation
+    U, S, W = np.linalg.svd(X, full_matrices=False)
+    best = (U[:, :D] * S[:D]) @ W[:D]
+    assert np.abs(US @ Vt - best).max() <= 1e-12 * s[0] * np.sqrt(max(m, c))
+    ref_disc = np.sqrt(np.sum(s[D:] ** 2) / np.sum(s ** 2))
+    assert abs(disc - ref_disc) <= 1e-12 + 1e-8 * ref_disc
+
+
+def _random_mps(n, chi, seed, decay=0.0):
+    cores = wl.random_mps_cores(n, chi, seed=seed)
+    if decay:
+        # graded bonds so that truncation is non-degenerate
+        for j, c in enumerate(cores[:-1]):
+            r = c.shape[2]
+            c *= (10.0 ** (-decay * np.arange(r) / max(r, 1)))[None, None, :]
+    return cores
+
+
+@pytest.mark.parametrize("n,chi,cap,tol", [(6, 8, 0, 0.0), (10, 16, 8, 0.0), (12, 32, 0, 1e-10),
+                                           (9, 12, 5, 0.0), (16, 24, 10, 1e-8)])
+def test_compress_matches_oracle(B, n, chi, cap, tol):
+    _say("compress n=%d chi=%d cap=%d tol=%g" % (n, chi, cap, tol))
+    cores = _random_mps(n, chi, seed=n + chi, decay=3.0)
+    out, disc = B.compress(cores, cap=cap, tol=tol)
+    ref, rdisc = omps.compress(cores, cap if cap > 0 else None, tol, return_discarded=True)
+    assert omps.bond_dims(out) == omps.bond_dims(ref)
+    v, r = omps.to_vector(out), omps.to_vector(ref)
+    assert np.abs(v - r).max() <= 1e-10 * np.abs(r).max()
+    assert np.allclose(disc, rdisc, atol=1e-12, rtol=1e-6)
+
+
+@pytest.mark.parametrize("n,chi,cap", [(6, 4, 0), (10, 8, 12), (12, 16, 0)])
+def test_apply_compress_matches_oracle(B, n, chi, cap):
+    _say("apply+compress n=%d chi=%d cap=%d" % (n, chi, cap))
+    cores = _random_mps(n, chi, seed=2 * n + chi, decay=2.0)
+    W = omps.mpo_d1_periodic(n, 0.3)
+    W = omps.mpo_sum([W, omps.diag_mpo(omps.vector_mps(np.linspace(-1, 2, 2 ** n)))])
+    out, _ = B.compress(cores, cap=cap, tol=0.0, mpo=W)
+    ref = omps.compress(omps.apply(W, cores), cap if cap > 0 else None, 0.0)
+    v, r = omps.to_vector(out), omps.to_vector(ref)
+    assert np.abs(v - r).max() <= 1e-10 * np.abs(r).max()
+    if cap == 0:
+        dense = omps.mpo_to_matrix(W) @ omps.to_vector(cores)
+        assert np.abs(v - dense).max() <= 1e-10 * np.abs(dense).max()
+
+
+def test_add_compress_matches_oracle(B):
+    _say("add+compress")
+    a = _random_mps(10, 8, seed=1, decay=2.0)
+    b = _random_mps(10, 6, seed=2, decay=2.0)
+    c = _random_mps(10, 4, seed=3, decay=2.0)
+    terms = [(1.0, a), (-0.25, b), (2.0, c)]
+    out = B.add_compress(terms, cap=0, tol=0.0)
+    ref = omps.add(terms)
+    v, r = omps.to_vector(out), omps.to_vector(ref)
+    assert np.abs(v - r).max() <= 1e-11 * np.abs(r).max()
+    out5 = B.add_compress(terms, cap=5, tol=0.0)
+    ref5 = omps.compress(ref, 5, 0.0)
+    assert np.abs(omps.to_vector(out5) - omps.to_vector(ref5)).max() <= 1e-10 * np.abs(r).max()

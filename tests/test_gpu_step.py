@@ -1,0 +1,204 @@
+"""GPU parity of the whole time step (include/mps_vlasov.h) against the
+dense-grid oracle (untruncated) and the CPU MPS oracle (truncated)."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import dense as odense
+from oracle import mps as omps
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print("[case] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2205_11990_amd import binding
+    binding.lib()
+    return binding
+
+
+def _untruncated(w):
+    p = w.problem
+    p.tol = 0.0
+    p.chi_max = 1 << 20
+    p.level = 1
+    return w
+
+
+@pytest.mark.parametrize("order,L", [(0, 3), (1, 3), (0, 4), (1, 4)])
+def test_init_equals_dense_profile(B, order, L):
+    _say("init order=%d L=%d" % (order, L))
+    w = _untruncated(wl.landau_small(L=L))
+    w.problem.order = order
+    st = B.MpsState(w.problem, w.ax, w.bv)
+    F = st.to_dense().cpu().numpy()
+    ref = odense.initial(w.ax, w.bv)
+    assert np.abs(F - ref).max() <= 1e-13 * np.abs(ref).max()
+    st.free()
+
+
+@pytest.mark.parametrize("order,L", [(0, 3), (1, 3), (0, 4), (1, 4), (0, 5)])
+def test_untruncated_steps_equal_dense_oracle(B, order, L):
+    """chi unbounded, tol = 0: the MPS step is the dense finite-difference
+    step up to rounding (1e-10 relative after several steps)."""
+    _say("untruncated order=%d L=%d" % (order, L))
+    w = _untruncated(wl.landau_small(L=L))
+    p = w.problem
+    p.order = order
+    st = B.MpsState(p, w.ax, w.bv)
+    F = odense.initial(w.ax, w.bv)
+    for k in range(4):
+        st.step(1)
+        F = odense.rk4_step(F, p)
+        G = st.to_dense().cpu().numpy()
+        err = np.abs(G - F).max() / np.abs(F).max()
+        assert err < 1e-12 * (k + 2), (k, err)
+    n, E = st.density_field()
+    assert np.abs(E.cpu().numpy() - odense.field(F, p)).max() <= 1e-10 * np.abs(odense.field(F, p)).max()
+    assert np.abs(n.cpu().numpy() - odense.density(F, p.dv)).max() <= 1e-12 * np.abs(odense.density(F, p.dv)).max()
+    st.free()
+
+
+def test_untruncated_two_stream_interleaved(B):
+    _say("untruncated two-stream IF L=4")
+    w = wl.two_stream(L=4, chi=0, tol=0.0, dt_cfg=0.1)
+    p = w.problem
+    p.chi_max = 1 << 20
+    st = B.MpsState(p, w.ax, w.bv)
+    F = odense.initial(w.ax, w.bv)
+    for _ in range(3):
+        st.step(1)
+        F = odense.rk4_step(F, p)
+    G = st.to_dense().cpu().numpy()
+    assert np.abs(G - F).max() <= 1e-10 * np.abs(F).max()
+
+
+def _from_same_state(B, w, steps):
+    """Run the GPU and the CPU MPS oracle from the same MPS (exported from the
+    GPU after init) and compare reconstructed f and E."""
+    p = w.problem
+    st = B.MpsState(p, w.ax, w.bv)
+    f = st.get_cores_host()
+    ops = omps.Operators(p)
+    for _ in range(steps):
+        st.step(1)
+        f = omps.rk4_step(f, ops)
+    G = st.to_dense().cpu().numpy()
+    R = omps.to_dense(f, p)
+    n, E = st.density_field()
+    Eref = omps.field_dense(f, ops)
+    info = st.info()
+    st.free()
+    return G, R, E.cpu().numpy(), Eref, info, f
+
+
+@pytest.mark.parametrize("order", [0, 1])
+def test_truncated_landau_matches_mps_oracle(B, order):
+    """64 x 64 Landau, chi = 16, tol = 1e-10 (C1): reconstructed f and E
+    within 1e-8 of the CPU MPS oracle after 3 steps from the same state."""
+    _say("truncated landau 64x64 chi16 order=%d" % order)
+    w = wl.landau_small(L=6, chi=16, tol=1e-10)
+    w.problem.order = order
+    G, R, E, Eref, info, f = _from_same_state(B, w, 3)
+    assert np.abs(G - R).max() <= 1e-8 * np.abs(R).max()
+    assert np.abs(E - Eref).max() <= 1e-8 * np.abs(Eref).max()
+    assert info["bonds"][1:-1] == omps.bond_dims(f)
+
+
+def test_truncated_fixed_chi_level5_matches_mps_oracle(B):
+    """Every compression point capped (C5), chi = 8, perturbed state so that
+    all bonds saturate."""
+    _say("truncated C5 chi8 two-stream L=5 IF")
+    w = wl.two_stream(L=5, chi=8, tol=0.0, level=5, df_max=4, dt_cfg=0.05)
+    p = w.problem
+    st = B.MpsState(p, w.ax, w.bv)
+    pert = wl.random_mps_cores(p.n_sites, 8, seed=2205)
+    st.add_scaled(1e-3, pert)
+    f = st.get_cores_host()
+    ops = omps.Operators(p)
+    for _ in range(2):
+        st.step(1)
+        f = omps.rk4_step(f, ops)
+    G = st.to_dense().cpu().numpy()
+    R = omps.to_dense(f, p)
+    assert np.abs(G - R).max() <= 1e-8 * np.abs(R).max()
+    st.free()
+
+
+def test_moments_match_oracle(B):
+    _say("moments")
+    w = wl.landau_small(L=6, chi=16, tol=1e-10)
+    p = w.problem
+    st = B.MpsState(p, w.ax, w.bv)
+    st.step(2)
+    f = st.get_cores_host()
+    ops = omps.Operators(p)
+    n, E, sc = st.moments()
+    ref = omps.moments(f, ops)
+    for k in ref:
+        assert abs(sc[k] - ref[k]) <= 1e-10 * max(abs(ref[k]), 1e-3), k
+    F = omps.to_dense(f, p)
+    assert np.abs(n.cpu().numpy() - odense.density(F, p.dv)).max() < 1e-12
+    st.free()
+
+
+def test_checkpoint_resume_is_bitwise(B):
+    _say("checkpoint")
+    w = wl.landau_small(L=5, chi=8, tol=1e-10)
+    a = B.MpsState(w.problem, w.ax, w.bv)
+    a.step(2)
+    cores = a.get_cores_host()
+    a.step(2)
+    b = B.MpsState(w.problem, w.ax, w.bv)
+    b.set_cores(cores)
+    b.step(2)
+    assert np.array_equal(a.to_dense().cpu().numpy(), b.to_dense().cpu().numpy())
+
+
+def test_batched_equals_solo(B):
+    _say("batched")
+    ws = wl.landau_sweep(count=3, seed=2205)
+    solo, batch = [], []
+    for w in ws:
+        w.problem.Lx = w.problem.Lv = 6
+        w.problem.dt = 0.05
+        ax, bv = wl.landau_profiles(w.problem, 0.5, 0.01)
+        s1 = B.MpsState(w.problem, ax, bv)
+        s1.step(2)
+        solo.append(s1.to_dense().cpu().numpy())
+        batch.append(B.MpsState(w.problem, ax, bv))
+    B.step_batched(batch, 2)
+    for s, b in zip(solo, batch):
+        assert np.array_equal(s, b.to_dense().cpu().numpy())
+
+
+def test_errors_leave_state_unchanged(B):
+    _say("errors")
+    w = wl.landau_small(L=5, chi=8, tol=1e-10)
+    ax = w.ax.copy()
+    ax[0, 3] = np.nan
+    with pytest.raises(B.MpsError) as e:
+        B.MpsState(w.problem, ax, w.bv)
+    assert e.value.status == B.MPS_EINVAL
+    st = B.MpsState(w.problem, w.ax, w.bv)
+    before = st.to_dense().cpu().numpy()
+    B.set_jacobi_max_sweeps(1)
+    try:
+        with pytest.raises(B.MpsError) as e:
+            st.step(1)
+        assert e.value.status == B.MPS_ENUMERIC
+    finally:
+        B.set_jacobi_max_sweeps(60)
+    assert np.array_equal(before, st.to_dense().cpu().numpy())
+    assert st.info()["steps"] == 0
+    st.step(1)
+    assert st.info()["steps"] == 1
