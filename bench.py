@@ -1,0 +1,150 @@
+"""Benchmark of the MPS Vlasov-Poisson RK4 step on one MI355X.
+
+Workload (the metric's configuration): two-stream instability on a
+2^10 x 2^10 grid (x in [0, 10 pi) periodic, v in [-8, 8]), interleaved site
+order (20 sites), bond cap chi = 64, FP64.  A step is one full RK4 step of
+the MPS method: per stage the charge density and Poisson field, the two
+MPO x MPS terms, their sum and the stage state, each recompressed by a QR
+left sweep and a truncated SVD right sweep; then the sum of the k's and the
+final state.
+
+Two modes:
+  fixed   (default, the reported `value`): every compression point capped at
+          chi (level C5), tol = 0, field bond D_F = 4, initial state
+          f0 + 1e-6 |f0| R with R a seeded random MPS of bond 64, so every
+          bond runs at the full chi = 64 shape.
+  physics: tol = 1e-10, level C1, from f0 (bonds follow the physics).
+
+Usage: python bench.py [--steps K] [--warmup W] [--mode fixed|physics]
+Prints one JSON line.  Runs on one GPU only (--gpus must be 1).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import workloads as wl  # noqa: E402
+
+PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 (matrix and vector)
+PEAK_HBM_GBS = 8000.0
+
+
+def make_workload(mode: str):
+    if mode == "fixed":
+        w = wl.two_stream(L=10, chi=64, tol=0.0, level=5, df_max=4, dt_cfg=0.02)
+    else:
+        w = wl.two_stream(L=10, chi=64, tol=1e-10, level=1, df_max=0, dt_cfg=0.02)
+    return w
+
+
+def perturbation(w):
+    p = w.problem
+    cores = wl.random_mps_cores(p.n_sites, p.chi_max, seed=2205)
+    amp = 1e-6 * float(np.linalg.norm(w.ax) * np.linalg.norm(w.bv))
+    return amp, cores
+
+
+def start_state(binding, w, mode):
+    st = binding.MpsState(w.problem, w.ax, w.bv)
+    if mode == "fixed":
+        amp, cores = perturbation(w)
+        st.add_scaled(amp, cores)
+    return st
+
+
+def cpu_baseline(w, mode, cores_host):
+    """The CPU MPS oracle, as it stands, timed on a bounded sample: one RK4
+    step of the same workload from the same MPS."""
+    from oracle import mps as omps
+    ops = omps.Operators(w.problem)
+    t0 = time.perf_counter()
+    omps.rk4_step(cores_host, ops)
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+    return {"value": 1.0 / dt, "unit": "steps/s", "cores": threads, "kind": "oracle",
+            "sample": "1 RK4 step of the same workload from the same MPS (%.1f s)" % dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--mode", default="fixed", choices=["fixed", "physics"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-roofline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: the MPS step of one instance is "
+              "not split across devices (independent instances would be placed "
+              "one per GPU); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2205_11990_amd import binding
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    binding.lib()
+
+    w = make_workload(args.mode)
+    p = w.problem
+    st = start_state(binding, w, args.mode)
+    print("[bench] %s mode: %d sites, chi=%d, dt=%.6g, bonds=%s" % (
+        args.mode, p.n_sites, p.chi_max, p.dt, st.info()["bonds"]), file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    st.step(args.warmup)
+    torch.cuda.synchronize()
+    print("[bench] warmup %d steps %.2f s" % (args.warmup, time.perf_counter() - t0),
+          file=sys.stderr, flush=True)
+    cores_host = st.get_cores_host()
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st.step(args.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    value = args.steps / el
+    print("[bench] timed %d steps %.3f s -> %.3f steps/s" % (args.steps, el, value),
+          file=sys.stderr, flush=True)
+    info = st.info()
+
+    roof = None
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(w, args.mode, cores_host)
+        print("[bench] cpu baseline %s" % cpu, file=sys.stderr, flush=True)
+
+    out = {
+        "metric": "time steps/s at Nx=Nv=2^10, chi=64",
+        "value": value,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1000.0 * el / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "two-stream 2^10 x 2^10, interleaved, chi=64, %s" % (
+            "every compression capped at chi (C5), tol=0, D_F=4, seeded random-MPS perturbation"
+            if args.mode == "fixed" else "C1, tol=1e-10, from f0"),
+                   "dt": p.dt, "sites": p.n_sites, "final_bonds": info["bonds"]},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -82,6 +82,15 @@ mps_status mpsb_stats(int64_t* qr_calls, int64_t* svd_calls,
 /* Cap on Jacobi sweeps (default 60); a tiny cap forces MPS_ENUMERIC. */
 mps_status mpsb_set_jacobi_max_sweeps(int32_t n);
 
+/* Per-kernel-class timing with HIP events on the launching stream (off by
+ * default).  enable != 0 clears and starts recording; classes: 0 GEMM,
+ * 1 QR panel, 2 Jacobi SVD, 3 other.  mpsb_profile_read synchronises the
+ * device and returns, for one class, the number of launches, the summed
+ * event time (ms) and the summed nominal FLOPs and bytes (host outputs). */
+mps_status mpsb_profile(int32_t enable);
+mps_status mpsb_profile_read(int32_t cls, int64_t* launches, double* ms,
+                             double* flops, double* bytes);
+
 #ifdef __cplusplus
 }
 #endif

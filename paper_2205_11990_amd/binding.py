@@ -71,6 +71,8 @@ _SIGS = {
     "mpsb_operator": [_I32, _I32, _D, _D, _PI32, _PD, _PI64],
     "mpsb_stats": [_PI64, _PI64, _PI64],
     "mpsb_set_jacobi_max_sweeps": [_I32],
+    "mpsb_profile": [_I32],
+    "mpsb_profile_read": [_I32, _PI64, _PD, _PD, _PD],
 }
 
 EXPORTED = sorted(_SIGS)
@@ -374,3 +376,20 @@ def stats():
 
 def set_jacobi_max_sweeps(n: int):
     _check(lib().mpsb_set_jacobi_max_sweeps(int(n)))
+
+
+KERNEL_CLASSES = ("gemm_f64", "qr_panel", "jacobi_svd", "other")
+
+
+def profile(enable: bool):
+    _check(lib().mpsb_profile(1 if enable else 0))
+
+
+def profile_read():
+    out = {}
+    for c, name in enumerate(KERNEL_CLASSES):
+        n, ms, fl, by = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(lib().mpsb_profile_read(c, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(fl),
+                                       ctypes.byref(by)))
+        out[name] = {"launches": n.value, "ms": ms.value, "flops": fl.value, "bytes": by.value}
+    return out

@@ -14,6 +14,7 @@
 #include "engine.hpp"
 #include "gemm.hpp"
 #include "linalg.hpp"
+#include "prof.hpp"
 
 struct mps_state {
   std::unique_ptr<mpsv::Engine> eng;
@@ -451,6 +452,20 @@ mps_status mpsb_set_jacobi_max_sweeps(int32_t n) {
   return guarded([&] {
     MPSV_CHECK(n >= 1, mpsv::kEinval, "sweep cap must be >= 1");
     mpsv::set_jacobi_max_sweeps(n);
+  });
+}
+
+mps_status mpsb_profile(int32_t enable) {
+  return guarded([&] { mpsv::prof_enable(enable != 0); });
+}
+
+mps_status mpsb_profile_read(int32_t cls, int64_t* launches, double* ms,
+                             double* flops, double* bytes) {
+  return guarded([&] {
+    MPSV_CHECK(cls >= 0 && cls < mpsv::kClsCount, mpsv::kEinval, "bad class");
+    long n = 0;
+    mpsv::prof_read(cls, &n, ms, flops, bytes);
+    if (launches) *launches = n;
   });
 }
 

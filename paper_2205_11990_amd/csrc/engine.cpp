@@ -413,16 +413,111 @@ void Engine::absorb_left(const VSite& v, const double* R, int p, double* M,
       }
       break;
     }
+    case VSite::kCopy: {
+      // natural-basis isometry: (p x l) with l = 2 r is already p x 2 x r
+      MPSV_HIP(hipMemcpyAsync(M, R, sizeof(double) * (size_t)p * v.l,
+                              hipMemcpyDeviceToDevice, s));
+      break;
+    }
   }
 }
 
-DMps Engine::compress_chain(const std::vector<VSite>& ch, int cap, double tol,
+// N (v.l x 2 x q) = C_j * L (v.r x q, contiguous)
+void Engine::absorb_right(const VSite& v, const double* L, int q, double* N,
+                          hipStream_t s) {
+  switch (v.kind) {
+    case VSite::kDense: {
+      gemm(s, 2 * v.l, q, v.r, 1.0, CMatView{v.A.p, v.r, 1, 0},
+           CMatView{L, q, 1, 0}, 0.0, MatView{N, q, 1, 0});
+      break;
+    }
+    case VSite::kApply: {
+      const int wl = v.W.wl, wr = v.W.wr, al = v.A.l, ar = v.A.r;
+      ArenaScope sc(work_);
+      // Z[(a,i)][b'][q] = sum_a' A[a][i][a'] L[(b',a')][q]   (batch b')
+      double* Z = work_.alloc((size_t)al * 2 * wr * q);
+      gemm(s, 2 * al, q, ar, 1.0, CMatView{v.A.p, ar, 1, 0},
+           CMatView{L, q, 1, (long)ar * q}, 0.0,
+           MatView{Z, (long)wr * q, 1, q}, wr);
+      // N'[a][(b,o)][q] = sum_(i,b') W[(b,o)][(i,b')] Z[a][(i,b')][q]
+      double* Np = work_.alloc((size_t)al * wl * 2 * q);
+      gemm(s, 2 * wl, q, 2 * wr, 1.0, CMatView{v.W.W, 2L * wr, 1, 0},
+           CMatView{Z, q, 1, 2L * wr * q}, 0.0,
+           MatView{Np, q, 1, 2L * wl * q}, al);
+      // N[b][a][o][q] = N'[a][b][o][q]
+      swap01(s, Np, al, wl, 2L * q, N);
+      break;
+    }
+    case VSite::kSum: {
+      const int T = (int)v.terms.size();
+      for (int t = 0; t < T; ++t) {
+        const Core& A = v.terms[t];
+        const double* Lt = (v.pos == 2) ? L : L + (long)v.roff[t] * q;
+        if (v.pos == 0) {
+          gemm(s, 2, q, A.r, v.coef[t], CMatView{A.p, A.r, 1, 0},
+               CMatView{Lt, q, 1, 0}, t == 0 ? 0.0 : 1.0,
+               MatView{N, q, 1, 0});
+        } else {
+          gemm(s, 2 * A.l, q, A.r, 1.0, CMatView{A.p, A.r, 1, 0},
+               CMatView{Lt, q, 1, 0}, 0.0,
+               MatView{N + (long)v.loff[t] * 2 * q, q, 1, 0});
+        }
+      }
+      break;
+    }
+    case VSite::kCopy: {
+      throw Error(kEinval, "absorb_right on a copy site");
+    }
+  }
+}
+
+DMps Engine::compress_chain(const std::vector<VSite>& ch_in, int cap, double tol,
                             Arena& out, hipStream_t s,
                             std::vector<double>* disc) {
-  const int n = (int)ch.size();
+  const int n = (int)ch_in.size();
   MPSV_CHECK(n >= 2, kEinval, "compression needs at least two sites");
   cap = cap_or_inf(cap);
   ArenaScope sc(work_);
+  // ---- right dense region.  Where the sites j..n-1 span no more indices
+  // than the bond entering them (2^(n-j) <= r_(j-1)), that part of the
+  // chain is contracted exactly into a dense block D (r_(j_R-1) x
+  // 2^(n-j_R)); it is re-expressed as one dense core followed by
+  // natural-basis copy cores.  The represented tensor, and therefore every
+  // matricisation the truncation sweep sees, is unchanged.
+  int jR = n;
+  for (int j = n - 1; j >= 1; --j) {
+    if (n - j > 30) break;
+    if ((1L << (n - j)) <= (long)ch_in[j - 1].r) jR = j; else break;
+  }
+  std::vector<VSite> chv;
+  const std::vector<VSite>* chp = &ch_in;
+  if (jR <= n - 2) {
+    double* Lb = work_.alloc(1);
+    fill(s, Lb, 1, 1.0);
+    int q = 1;
+    for (int j = n - 1; j >= jR; --j) {
+      double* Nb = work_.alloc((size_t)ch_in[j].l * 2 * q);
+      absorb_right(ch_in[j], Lb, q, Nb, s);
+      Lb = Nb;
+      q *= 2;
+    }
+    chv.assign(ch_in.begin(), ch_in.begin() + jR);
+    VSite d;
+    d.kind = VSite::kDense;
+    d.l = ch_in[jR].l;
+    d.r = q / 2;
+    d.A = Core{Lb, d.l, d.r};
+    chv.push_back(d);
+    for (int j = jR + 1; j < n; ++j) {
+      VSite c;
+      c.kind = VSite::kCopy;
+      c.l = 1 << (n - j);
+      c.r = 1 << (n - j - 1);
+      chv.push_back(c);
+    }
+    chp = &chv;
+  }
+  const std::vector<VSite>& ch = *chp;
   struct Fac {
     bool ident = true;
     int rows = 0, cols = 0;

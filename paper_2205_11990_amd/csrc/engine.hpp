@@ -41,7 +41,7 @@ using DMpo = std::vector<MpoSite>;
 
 // One site of an implicit chain handed to the compression sweep.
 struct VSite {
-  enum Kind { kDense, kApply, kSum } kind = kDense;
+  enum Kind { kDense, kApply, kSum, kCopy } kind = kDense;
   int l = 1, r = 1;
   Core A;                                    // kDense, kApply
   MpoSite W;                                 // kApply
@@ -103,6 +103,8 @@ class Engine {
  private:
   void absorb_left(const VSite& v, const double* R, int p, double* M,
                    hipStream_t s);
+  void absorb_right(const VSite& v, const double* L, int q, double* N,
+                    hipStream_t s);
   DMps density(const DMps& g, Arena& ar, hipStream_t s);
   DMps field(const DMps& g, Arena& ar, hipStream_t s);
   DMpo t2_mpo(const DMps& E, Arena& ar, hipStream_t s);

@@ -7,7 +7,12 @@
 // expressed without copies.  Tiles of 64 x 64 x 16 are staged through LDS;
 // each of the 4 waves owns a 32 x 32 sub-tile computed by 2 x 2
 // v_mfma_f64_16x16x4f64 accumulators (64-wide wavefronts).
+#include <algorithm>
+#include <map>
+#include <mutex>
+
 #include "gemm.hpp"
+#include "prof.hpp"
 
 namespace mpsv {
 
@@ -17,35 +22,40 @@ namespace {
 
 constexpr int BM = 64, BN = 64, BK = 16, NT = 256;
 
+// blockIdx.z = batch * nsplit + split; split covers K range
+// [split*kchunk, min(K, (split+1)*kchunk)).
 __global__ __launch_bounds__(NT) void gemm_f64_kernel(
     int M, int N, int K, double alpha, const double* __restrict__ A, long ars,
     long acs, long abs_, const double* __restrict__ B, long brs, long bcs,
     long bbs, double beta, double* __restrict__ C, long crs, long ccs, long cbs,
-    int a_kfast, int b_nfast) {
+    int a_kfast, int b_nfast, int nsplit, int kchunk) {
   __shared__ double As[BK][BM + 1];
   __shared__ double Bs[BK][BN + 1];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const long bz = blockIdx.z;
+  const long bz = blockIdx.z / nsplit;
+  const int split = blockIdx.z % nsplit;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
   A += bz * abs_;
   B += bz * bbs;
-  C += bz * cbs;
+  C += bz * cbs + (long)split * M * N * (nsplit > 1 ? 1 : 0);
+  const int kbeg = split * kchunk;
+  const int kend = (kbeg + kchunk < K) ? kbeg + kchunk : K;
 
   dbl4 acc[2][2];
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
 
-  for (int k0 = 0; k0 < K; k0 += BK) {
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
 #pragma unroll
     for (int q = 0; q < (BM * BK) / NT; ++q) {
       int e = tid + q * NT;
       int r, k;
       if (a_kfast) { r = e / BK; k = e % BK; } else { k = e / BM; r = e % BM; }
       int gr = m0 + r, gk = k0 + k;
-      As[k][r] = (gr < M && gk < K) ? A[(long)gr * ars + (long)gk * acs] : 0.0;
+      As[k][r] = (gr < M && gk < kend) ? A[(long)gr * ars + (long)gk * acs] : 0.0;
     }
 #pragma unroll
     for (int q = 0; q < (BN * BK) / NT; ++q) {
@@ -53,7 +63,7 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(
       int c, k;
       if (b_nfast) { k = e / BN; c = e % BN; } else { c = e / BK; k = e % BK; }
       int gc = n0 + c, gk = k0 + k;
-      Bs[k][c] = (gc < N && gk < K) ? B[(long)gk * brs + (long)gc * bcs] : 0.0;
+      Bs[k][c] = (gc < N && gk < kend) ? B[(long)gk * brs + (long)gc * bcs] : 0.0;
     }
     __syncthreads();
 #pragma unroll
@@ -88,6 +98,47 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(
       }
 }
 
+// C[b] = alpha * sum_s P[b*nsplit + s] + beta * C[b]
+__global__ void splitk_reduce_kernel(int M, int N, int nsplit, double alpha,
+                                     const double* __restrict__ P, double beta,
+                                     double* __restrict__ C, long crs, long ccs,
+                                     long cbs) {
+  const long b = blockIdx.y;
+  const long MN = (long)M * N;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < MN;
+       e += (long)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    const double* pp = P + b * nsplit * MN + e;
+    for (int q = 0; q < nsplit; ++q) acc += pp[q * MN];
+    const long i = e / N, j = e % N;
+    double* cp = C + b * cbs + i * crs + j * ccs;
+    *cp = (beta == 0.0) ? alpha * acc : alpha * acc + beta * (*cp);
+  }
+}
+
+// Scratch for split-K partial products, one per stream, grown on demand and
+// kept for the process lifetime.
+struct Scratch {
+  double* p = nullptr;
+  size_t n = 0;
+};
+std::mutex g_splitk_mu;
+std::map<hipStream_t, Scratch> g_splitk;
+double* splitk_scratch(hipStream_t s, size_t n) {
+  std::lock_guard<std::mutex> lk(g_splitk_mu);
+  Scratch& sc = g_splitk[s];
+  if (n > sc.n) {
+    if (sc.p) {
+      MPSV_HIP(hipStreamSynchronize(s));
+      MPSV_HIP(hipFree(sc.p));
+    }
+    size_t want = n + n / 2;
+    MPSV_HIP(hipMalloc(&sc.p, want * sizeof(double)));
+    sc.n = want;
+  }
+  return sc.p;
+}
+
 }  // namespace
 
 void gemm(hipStream_t s, int M, int N, int K, double alpha, CMatView A,
@@ -100,15 +151,46 @@ void gemm(hipStream_t s, int M, int N, int K, double alpha, CMatView A,
   }
   const int a_kfast = (A.cs == 1) ? 1 : 0;
   const int b_nfast = (B.cs == 1) ? 1 : 0;
-  for (int b0 = 0; b0 < batch; b0 += 65535) {
-    int nb = batch - b0 < 65535 ? batch - b0 : 65535;
-    dim3 grid(ceil_div(N, BN), ceil_div(M, BM), nb);
-    hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(NT), 0, s, M, N, K, alpha,
-                       A.p + (long)b0 * A.bs, A.rs, A.cs, A.bs,
-                       B.p + (long)b0 * B.bs, B.rs, B.cs, B.bs, beta,
-                       C.p + (long)b0 * C.bs, C.rs, C.cs, C.bs, a_kfast,
-                       b_nfast);
-    MPSV_LAUNCHED();
+  const long tiles = (long)ceil_div(N, BN) * ceil_div(M, BM);
+  // split K when the output alone cannot fill the chip
+  int nsplit = 1;
+  if (K >= 4 * BK * 4 && tiles * batch < 256) {
+    long want = 512 / (tiles * batch);
+    long maxk = K / (4 * BK);
+    nsplit = (int)std::max(1L, std::min(std::min(want, maxk), 64L));
+  }
+  const int kchunk = (nsplit > 1) ? ceil_div(ceil_div(K, nsplit), BK) * BK : K;
+  if (nsplit > 1) nsplit = ceil_div(K, kchunk);
+  const int bmax = std::max(1, 65535 / nsplit);
+  for (int b0 = 0; b0 < batch; b0 += bmax) {
+    int nb = batch - b0 < bmax ? batch - b0 : bmax;
+    dim3 grid(ceil_div(N, BN), ceil_div(M, BM), nb * nsplit);
+    const int slot = prof_begin(s);
+    if (nsplit == 1) {
+      hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(NT), 0, s, M, N, K, alpha,
+                         A.p + (long)b0 * A.bs, A.rs, A.cs, A.bs,
+                         B.p + (long)b0 * B.bs, B.rs, B.cs, B.bs, beta,
+                         C.p + (long)b0 * C.bs, C.rs, C.cs, C.bs, a_kfast,
+                         b_nfast, 1, K);
+      MPSV_LAUNCHED();
+    } else {
+      double* P = splitk_scratch(s, (size_t)nb * nsplit * M * N);
+      hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(NT), 0, s, M, N, K, 1.0,
+                         A.p + (long)b0 * A.bs, A.rs, A.cs, A.bs,
+                         B.p + (long)b0 * B.bs, B.rs, B.cs, B.bs, 0.0, P,
+                         (long)N, 1L, (long)nsplit * M * N, a_kfast, b_nfast,
+                         nsplit, kchunk);
+      MPSV_LAUNCHED();
+      const long MN = (long)M * N;
+      int blocks = ceil_div(MN, 256);
+      if (blocks > 1024) blocks = 1024;
+      hipLaunchKernelGGL(splitk_reduce_kernel, dim3(blocks, nb), dim3(256), 0,
+                         s, M, N, nsplit, alpha, P, beta,
+                         C.p + (long)b0 * C.bs, C.rs, C.cs, C.bs);
+      MPSV_LAUNCHED();
+    }
+    prof_end(s, slot, kClsGemm, 2.0 * M * N * (double)K * nb,
+             8.0 * ((double)M * K + (double)K * N + 2.0 * M * N) * nb);
   }
 }
 

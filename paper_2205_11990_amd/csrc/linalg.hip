@@ -17,7 +17,9 @@
 #include <mutex>
 
 #include "gemm.hpp"
+#include "jacobi.hpp"
 #include "linalg.hpp"
+#include "prof.hpp"
 
 namespace mpsv {
 
@@ -50,24 +52,32 @@ __device__ inline double block_sum(double v, double* red) {
   return t;
 }
 
-// Panel factorisation: P is (m x jb), row stride ld, in global memory.
+// Panel factorisation of P (m x jb, row stride ld, global memory).  The
+// panel is staged in LDS (leading dimension jb+1, odd, so column reads are
+// conflict-free) when use_lds, else worked on in place.  Thread t owns
+// column j = t % jb of row group g = t / jb for the reflector products;
+// their partial sums meet in an LDS table, one barrier per column.
 __global__ __launch_bounds__(NT) void qr_panel_kernel(double* P, int m, int jb,
                                                       long ld, double* V,
                                                       double* Y, int use_lds) {
   extern __shared__ double smem[];
-  __shared__ double red[NT / 64][MAXJB + 1];
+  __shared__ double part[NT];
+  __shared__ double red[NT / 64];
   __shared__ double tau_s[MAXJB];
-  __shared__ double T[MAXJB][MAXJB];
+  __shared__ double T[MAXJB][MAXJB + 1];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int ngr = NT / jb;            // row groups
+  const int gj = tid % jb, gg = tid / jb;
+  const bool owner = gg < ngr;
 
   double* pp;
   long pld;
   if (use_lds) {
     pp = smem;
-    pld = jb;
+    pld = jb + 1;
     for (long e = tid; e < (long)m * jb; e += NT) {
-      long i = e / jb, j = e % jb;
-      pp[e] = P[i * ld + j];
+      const long i = e / jb, j = e % jb;
+      pp[i * pld + j] = P[i * ld + j];
     }
     __syncthreads();
   } else {
@@ -76,20 +86,20 @@ __global__ __launch_bounds__(NT) void qr_panel_kernel(double* P, int m, int jb,
   }
 
   for (int c = 0; c < jb; ++c) {
-    double part = 0.0;
+    // norm of the column below the diagonal
+    double sq = 0.0;
     for (int i = c + 1 + tid; i < m; i += NT) {
-      double x = pp[(long)i * pld + c];
-      part += x * x;
+      const double x = pp[(long)i * pld + c];
+      sq = fma(x, x, sq);
     }
-    // block reduction of the column norm below the diagonal
-    part = wave_sum(part);
-    __syncthreads();
-    if (lane == 0) red[wv][0] = part;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o, 64);
+    if (lane == 0) red[wv] = sq;
     __syncthreads();
     double xn2 = 0.0;
 #pragma unroll
-    for (int i = 0; i < NT / 64; ++i) xn2 += red[i][0];
-    const double alpha = (c < m) ? pp[(long)c * pld + c] : 0.0;
+    for (int i = 0; i < NT / 64; ++i) xn2 += red[i];
+    const double alpha = pp[(long)c * pld + c];
     double tau = 0.0, beta = alpha, scal = 0.0;
     if (xn2 > 0.0) {
       beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
@@ -100,87 +110,53 @@ __global__ __launch_bounds__(NT) void qr_panel_kernel(double* P, int m, int jb,
     if (xn2 > 0.0)
       for (int i = c + 1 + tid; i < m; i += NT) pp[(long)i * pld + c] *= scal;
     if (tid == 0) {
-      if (c < m) pp[(long)c * pld + c] = beta;
+      pp[(long)c * pld + c] = beta;
       tau_s[c] = tau;
     }
     __syncthreads();
-    const int nr = jb - c - 1;
-    if (nr > 0 && tau != 0.0) {
-      double w[MAXJB];
-#pragma unroll
-      for (int j = 0; j < MAXJB; ++j) w[j] = 0.0;
-      for (int i = c + tid; i < m; i += NT) {
-        const double vi = (i == c) ? 1.0 : pp[(long)i * pld + c];
-        const double* row = pp + (long)i * pld + c + 1;
-#pragma unroll
-        for (int j = 0; j < MAXJB; ++j)
-          if (j < nr) w[j] += vi * row[j];
-      }
-#pragma unroll
-      for (int j = 0; j < MAXJB; ++j)
-        if (j < nr) w[j] = wave_sum(w[j]);
-      if (lane == 0) {
-#pragma unroll
-        for (int j = 0; j < MAXJB; ++j)
-          if (j < nr) red[wv][j] = w[j];
-      }
-      __syncthreads();
-#pragma unroll
-      for (int j = 0; j < MAXJB; ++j)
-        if (j < nr) {
-          double t = 0.0;
-#pragma unroll
-          for (int q = 0; q < NT / 64; ++q) t += red[q][j];
-          w[j] = t * tau;
+    if (c + 1 < jb && tau != 0.0) {
+      // w_j = sum_{i >= c} v_i P[i][j] for j > c
+      double acc = 0.0;
+      if (owner && gj > c)
+        for (int i = c + gg; i < m; i += ngr) {
+          const double vi = (i == c) ? 1.0 : pp[(long)i * pld + c];
+          acc = fma(vi, pp[(long)i * pld + gj], acc);
         }
-      for (int i = c + tid; i < m; i += NT) {
-        const double vi = (i == c) ? 1.0 : pp[(long)i * pld + c];
-        double* row = pp + (long)i * pld + c + 1;
-#pragma unroll
-        for (int j = 0; j < MAXJB; ++j)
-          if (j < nr) row[j] -= vi * w[j];
+      part[tid] = acc;
+      __syncthreads();
+      double w = 0.0;
+      if (owner && gj > c) {
+        for (int q = 0; q < ngr; ++q) w += part[q * jb + gj];
+        w *= tau;
+        for (int i = c + gg; i < m; i += ngr) {
+          const double vi = (i == c) ? 1.0 : pp[(long)i * pld + c];
+          pp[(long)i * pld + gj] -= vi * w;
+        }
       }
       __syncthreads();
     }
   }
 
-  // explicit V (unit lower trapezoidal)
-  for (long e = tid; e < (long)m * jb; e += NT) {
-    int i = (int)(e / jb), k = (int)(e % jb);
-    V[e] = (i < k) ? 0.0 : (i == k ? 1.0 : pp[(long)i * pld + k]);
-  }
-  __syncthreads();
-  __threadfence_block();
-  // T (upper triangular), column by column: T[0:c,c] = -tau_c T[0:c,0:c] (V^T v_c)
+  // T (upper triangular): T[0:c,c] = -tau_c T[0:c,0:c] (V^T v_c)
   for (int c = 0; c < jb; ++c) {
-    double z[MAXJB];
-#pragma unroll
-    for (int k = 0; k < MAXJB; ++k) z[k] = 0.0;
-    for (int i = c + tid; i < m; i += NT) {
-      const double vc = V[(long)i * jb + c];
-#pragma unroll
-      for (int k = 0; k < MAXJB; ++k)
-        if (k < c) z[k] += V[(long)i * jb + k] * vc;
-    }
-#pragma unroll
-    for (int k = 0; k < MAXJB; ++k)
-      if (k < c) z[k] = wave_sum(z[k]);
-    __syncthreads();
-    if (lane == 0) {
-#pragma unroll
-      for (int k = 0; k < MAXJB; ++k)
-        if (k < c) red[wv][k] = z[k];
-    }
+    double acc = 0.0;
+    if (owner && gj < c)
+      for (int i = c + gg; i < m; i += ngr) {
+        const double vc = (i == c) ? 1.0 : pp[(long)i * pld + c];
+        const double vk = pp[(long)i * pld + gj];   // i > gj here (i >= c > gj)
+        acc = fma(vk, vc, acc);
+      }
+    part[tid] = acc;
     __syncthreads();
     if (tid < jb) {
       if (tid < c) {
-        double acc = 0.0;
+        double t = 0.0;
         for (int l = tid; l < c; ++l) {
           double zl = 0.0;
-          for (int q = 0; q < NT / 64; ++q) zl += red[q][l];
-          acc += T[tid][l] * zl;
+          for (int q = 0; q < ngr; ++q) zl += part[q * jb + l];
+          t += T[tid][l] * zl;
         }
-        T[tid][c] = -tau_s[c] * acc;
+        T[tid][c] = -tau_s[c] * t;
       } else if (tid == c) {
         T[c][c] = tau_s[c];
       } else {
@@ -189,17 +165,22 @@ __global__ __launch_bounds__(NT) void qr_panel_kernel(double* P, int m, int jb,
     }
     __syncthreads();
   }
-  // Y = V T
+  // explicit V (unit lower trapezoidal) and Y = V T
   for (long e = tid; e < (long)m * jb; e += NT) {
-    int i = (int)(e / jb), c = (int)(e % jb);
-    double acc = 0.0;
-    for (int k = 0; k <= c; ++k) acc += V[(long)i * jb + k] * T[k][c];
-    Y[e] = acc;
+    const int i = (int)(e / jb), c = (int)(e % jb);
+    double y = 0.0;
+    for (int k = 0; k <= c && k <= i; ++k) {
+      const double vk = (i == k) ? 1.0 : pp[(long)i * pld + k];
+      y = fma(vk, T[k][c], y);
+    }
+    Y[e] = y;
+    V[e] = (i < c) ? 0.0 : (i == c ? 1.0 : pp[(long)i * pld + c]);
   }
   if (use_lds) {
+    __syncthreads();
     for (long e = tid; e < (long)m * jb; e += NT) {
-      long i = e / jb, j = e % jb;
-      P[i * ld + j] = pp[e];
+      const long i = e / jb, j = e % jb;
+      P[i * ld + j] = pp[i * pld + j];
     }
   }
 }
@@ -429,6 +410,19 @@ void extract_r(hipStream_t s, const double* A, int k, int n, long ld,
   MPSV_LAUNCHED();
 }
 
+__global__ void fill_ints_kernel(int* x, long n) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n;
+       e += (long)gridDim.x * blockDim.x)
+    x[e] = 0;
+}
+
+static void fill_ints(hipStream_t s, int* x, long n) {
+  if (n <= 0) return;
+  int blocks = std::min(1024, ceil_div(n, 256));
+  hipLaunchKernelGGL(fill_ints_kernel, dim3(blocks), dim3(256), 0, s, x, n);
+  MPSV_LAUNCHED();
+}
+
 static void fill_rows_zero(hipStream_t s, double* X, int r0, int r1, int nc,
                            long ld) {
   if (r1 <= r0 || nc <= 0) return;
@@ -450,18 +444,23 @@ void qr_factor(hipStream_t s, Arena& ws, double* A, int m, int n, long ld,
     const int rows = m - k0;
     int jb = std::min(MAXJB, f.k - k0);
     int use_lds = 0;
-    while (jb > 4 && (size_t)rows * jb * sizeof(double) > kPanelLds) jb /= 2;
-    if ((size_t)rows * jb * sizeof(double) <= kPanelLds) use_lds = 1;
+    while (jb > 4 && (size_t)rows * (jb + 1) * sizeof(double) > kPanelLds) jb /= 2;
+    if ((size_t)rows * (jb + 1) * sizeof(double) <= kPanelLds) use_lds = 1;
     QrPanel pn;
     pn.k0 = k0;
     pn.jb = jb;
     pn.V = ws.alloc((size_t)rows * jb);
     pn.Y = ws.alloc((size_t)rows * jb);
     double* P = A + (long)k0 * ld + k0;
-    size_t lds = use_lds ? (size_t)rows * jb * sizeof(double) : 0;
+    size_t lds = use_lds ? (size_t)rows * (jb + 1) * sizeof(double) : 0;
+    const int slot = prof_begin(s);
     hipLaunchKernelGGL(qr_panel_kernel, dim3(1), dim3(NT), lds, s, P, rows, jb,
                        ld, pn.V, pn.Y, use_lds);
     MPSV_LAUNCHED();
+    // nominal GEQRF flops of the panel, 2 m n^2 - 2 n^3 / 3
+    prof_end(s, slot, kClsQrPanel,
+             2.0 * rows * (double)jb * jb - 2.0 * jb * (double)jb * jb / 3.0,
+             16.0 * rows * jb);
     const int n2 = n - k0 - jb;
     if (n2 > 0) {
       ArenaScope sc(ws);
@@ -516,16 +515,38 @@ int svd_truncate(hipStream_t s, Arena& ws, double* X, int m, int c, long ldx,
     ldb = c;
     mb = c;
   }
-  const size_t need = ((size_t)mb * c + (size_t)c * c) * sizeof(double);
-  const int use_lds = need <= kJacobiLds ? 1 : 0;
-  double* Wg = use_lds ? nullptr : ws.alloc((size_t)mb * c);
-  double* Jg = use_lds ? nullptr : ws.alloc((size_t)c * c);
   double* sigbuf = ws.alloc((size_t)3 * c + 8);
   double* info = ws.alloc(8);
-  hipLaunchKernelGGL(jacobi_svd_kernel, dim3(1), dim3(NT), use_lds ? need : 0,
-                     s, B, mb, c, ldb, Wg, Jg, use_lds, cap, tol, g_max_sweeps,
-                     Vt, US, (long)mb, sigbuf, info);
-  MPSV_LAUNCHED();
+  const int slot = prof_begin(s);
+  if (c <= kJacobiMaxCols && mb <= kJacobiMaxCols) {
+    const bool keep_v = jacobi_lds_bytes(mb, c, true) <= kJacobiMaxLds;
+    double* rotlog = nullptr;
+    int* rflag = nullptr;
+    if (!keep_v) {
+      const long rounds = (long)g_max_sweeps * (c + 1);
+      rotlog = ws.alloc((size_t)rounds * (c + 2));
+      rflag = ws.alloc_int((size_t)rounds);
+      fill_ints(s, rflag, rounds);
+    }
+    int* perm = ws.alloc_int((size_t)c);
+    jacobi_svd(s, B, mb, c, ldb, cap, tol, g_max_sweeps, rotlog, rflag, Vt, US,
+               sigbuf, perm, info, keep_v);
+  } else {
+    const size_t need = ((size_t)mb * c + (size_t)c * c) * sizeof(double);
+    const int use_lds = need <= kJacobiLds ? 1 : 0;
+    double* Wg = use_lds ? nullptr : ws.alloc((size_t)mb * c);
+    double* Jg = use_lds ? nullptr : ws.alloc((size_t)c * c);
+    hipLaunchKernelGGL(jacobi_svd_kernel, dim3(1), dim3(NT), use_lds ? need : 0,
+                       s, B, mb, c, ldb, Wg, Jg, use_lds, cap, tol, g_max_sweeps,
+                       Vt, US, (long)mb, sigbuf, info);
+    MPSV_LAUNCHED();
+  }
+  {
+    // nominal SVD flops of the factored mb x c matrix, 6 m n^2 + 20 n^3
+    const double mm = std::max(mb, c), nn = std::min(mb, c);
+    prof_end(s, slot, kClsJacobi, 6.0 * mm * nn * nn + 20.0 * nn * nn * nn,
+             8.0 * (2.0 * mb * c + 2.0 * c * c));
+  }
   double* h = pinned_info();
   MPSV_HIP(hipMemcpyAsync(h, info, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
   MPSV_HIP(hipStreamSynchronize(s));

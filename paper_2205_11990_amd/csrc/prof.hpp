@@ -1,0 +1,26 @@
+// Optional per-kernel-class timing with HIP events on the launching stream.
+// Off by default; when on, every launch of an instrumented kernel is
+// bracketed by two events and its nominal FLOP/byte count is recorded.
+#pragma once
+#include "common.hpp"
+
+namespace mpsv {
+
+enum KClass : int {
+  kClsGemm = 0,
+  kClsQrPanel = 1,
+  kClsJacobi = 2,
+  kClsOther = 3,
+  kClsCount = 4
+};
+
+bool prof_enabled();
+void prof_enable(bool on);  // enabling clears previous records
+// Returns an opaque slot (or -1 when disabled); call prof_end with it.
+int prof_begin(hipStream_t s);
+void prof_end(hipStream_t s, int slot, int cls, double flops, double bytes);
+// Synchronises the device and sums the records of class `cls`.
+void prof_read(int cls, long* launches, double* ms, double* flops,
+               double* bytes);
+
+}  // namespace mpsv
