@@ -61,6 +61,17 @@ def start_state(binding, w, mode):
     return st
 
 
+def _blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        n = [d.get("num_threads", 0) for d in threadpool_info() if d.get("user_api") == "blas"]
+        if n:
+            return int(max(n))
+    except Exception:
+        pass
+    return int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+
+
 def cpu_baseline(w, mode, cores_host):
     """The CPU MPS oracle, as it stands, timed on a bounded sample: one RK4
     step of the same workload from the same MPS."""
@@ -69,9 +80,43 @@ def cpu_baseline(w, mode, cores_host):
     t0 = time.perf_counter()
     omps.rk4_step(cores_host, ops)
     dt = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
-    return {"value": 1.0 / dt, "unit": "steps/s", "cores": threads, "kind": "oracle",
-            "sample": "1 RK4 step of the same workload from the same MPS (%.1f s)" % dt}
+    return {"value": 1.0 / dt, "unit": "steps/s", "cores": _blas_threads(), "kind": "oracle",
+            "sample": "1 RK4 step of the same workload from the same MPS (%.1f s of CPU time)" % dt}
+
+
+# Peak of the unit each kernel class runs on (MI355X, dense FP64).
+_CLASS_BOUND = {
+    "gemm_f64": ("mfma", PEAK_FP64_TFLOPS),     # v_mfma_f64_16x16x4f64
+    "qr_panel": ("alu", PEAK_FP64_TFLOPS),      # FP64 vector FMA
+    "jacobi_svd": ("alu", PEAK_FP64_TFLOPS),    # FP64 vector FMA
+}
+
+
+def roofline(binding, st, cores_host, steps):
+    """Re-run `steps` steps from the same state with every launch of the
+    instrumented kernels bracketed by HIP events on the launching stream;
+    report the class with the largest event time.  achieved = nominal FLOPs
+    of its launches / summed launch time."""
+    import torch
+    st.set_cores(cores_host)
+    torch.cuda.synchronize()
+    binding.profile(True)
+    st.step(steps)
+    torch.cuda.synchronize()
+    rec = binding.profile_read()
+    binding.profile(False)
+    dom = max(_CLASS_BOUND, key=lambda k: rec[k]["ms"])
+    r = rec[dom]
+    bound, peak = _CLASS_BOUND[dom]
+    ach = r["flops"] / (r["ms"] * 1e-3) / 1e12 if r["ms"] > 0 else 0.0
+    classes = {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
+                   "tflops": round(v["flops"] / (v["ms"] * 1e-3) / 1e12, 4) if v["ms"] > 0 else None}
+               for k, v in rec.items() if k in _CLASS_BOUND}
+    return {"bound": bound, "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+            "frac": ach / peak, "traffic": None, "kernel": dom,
+            "launches": r["launches"], "avg_launch_us": 1000.0 * r["ms"] / max(r["launches"], 1),
+            "flops_per_launch": r["flops"] / max(r["launches"], 1),
+            "classes": classes}
 
 
 def main():
@@ -82,7 +127,20 @@ def main():
     ap.add_argument("--mode", default="fixed", choices=["fixed", "physics"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 256 MiB device-to-device copy (calibrates "
+                         "the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        n = (256 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n * 8}))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the MPS step of one instance is "
               "not split across devices (independent instances would be placed "
@@ -119,6 +177,9 @@ def main():
 
     roof = None
     cpu = None
+    if not args.no_roofline:
+        roof = roofline(binding, st, cores_host, min(args.steps, 3))
+        print("[bench] roofline %s" % json.dumps(roof), file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, args.mode, cores_host)
         print("[bench] cpu baseline %s" % cpu, file=sys.stderr, flush=True)

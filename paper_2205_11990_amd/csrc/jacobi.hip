@@ -1,5 +1,11 @@
-// One-sided (Hestenes) Jacobi SVD of a small matrix B (mb x c, mb, c <= 128
-// after the QR reduction of tall inputs) on one workgroup of 1024 threads.
+// One-sided (Hestenes) Jacobi SVD of a small matrix on one workgroup of
+// 1024 threads.  The matrix handed in is X (m x c, m <= c) or the triangular
+// factor R (c x c) of a tall X; the rotations act on the columns of its
+// transpose B = X^T (or R^T), whose k = min(m, c) columns converge to
+// v_i sigma_i while the accumulated rotations converge to U.  Working on the
+// transpose of the triangular factor needs far fewer sweeps than working on
+// the factor itself (about 9 against 22 on the matrices of the compression
+// sweep).
 //
 // Columns are orthogonalised pairwise in the cyclic round-robin ordering:
 // each round pairs all c columns into disjoint pairs; a group of G lanes
@@ -16,8 +22,8 @@
 // On exit: singular values are the column norms, sorted descending (ties by
 // index), the truncation rank D follows the rule min(cap, smallest D' whose
 // relative discarded weight is <= tol) (eq. 5 with the i = D+1 reading),
-// Vt (D x c) holds the kept right singular vectors and USs (mb x D) the
-// columns u_i sigma_i.
+// Vt (D x c) holds the kept right singular vectors (normalised columns) and
+// USs (k x D) the columns u_i sigma_i (accumulated rotations times sigma).
 #include <cmath>
 
 #include "jacobi.hpp"
@@ -119,8 +125,14 @@ __device__ inline double block_sum(double v, double* red) {
 }
 
 // info: [0] D, [1] discarded weight, [2] sweeps, [3] converged, [4] rounds
+// Xr: k x c row-major triangular factor (c == k); the Jacobi columns are
+// its rows: A[j][i] = Xr[j][i], j < k, i < c.  Outputs by mode:
+//   mode 0 (factor of X):   out1 = Vt (D x c), rows A_d / sigma_d
+//                           out2 = (k x D) J[:, d] sigma_d   (= U_R Sigma)
+//   mode 1 (factor of X^T): out1 = (k x D) A_d               (= U Sigma)
+//                           out2 = (k x D) J[:, d]           (V = Q' J)
 __global__ __launch_bounds__(JT) void jacobi_cols_kernel(
-    const double* __restrict__ B, int mb, int c, long ldb, int keep_v,
+    const double* __restrict__ Xr, int k, int c, long ldx, int keep_v, int mode,
     double* __restrict__ rotlog, int* __restrict__ rflag, int max_sweeps,
     int cap, double tol, double* __restrict__ Vt, double* __restrict__ USs,
     double* __restrict__ sigbuf, int* __restrict__ perm_out,
@@ -131,23 +143,24 @@ __global__ __launch_bounds__(JT) void jacobi_cols_kernel(
   __shared__ int round_any[2];
   __shared__ int Dsh;
   const int tid = threadIdx.x;
-  const int lda = mb | 1, ldv = c | 1;
-  double* A = smem;                        // A[j*lda + i]
-  double* V = smem + (long)c * lda;        // V[j*ldv + i] (keep_v only)
+  const int nrow = c, ncol = k;            // Jacobi matrix A = Xr^T: c x k
+  const int lda = nrow | 1, ldv = ncol | 1;
+  double* A = smem;                        // A[j*lda + i], j < k, i < c
+  double* V = smem + (long)ncol * lda;     // accumulated rotations (keep_v)
 
-  for (long e = tid; e < (long)mb * c; e += JT) {
-    const long i = e / c, j = e % c;
-    A[j * lda + i] = B[i * ldb + j];
+  for (long e = tid; e < (long)ncol * nrow; e += JT) {
+    const long j = e / nrow, i = e % nrow;
+    A[j * lda + i] = Xr[j * ldx + i];
   }
   if (keep_v)
-    for (long e = tid; e < (long)c * c; e += JT) {
-      const long j = e / c, i = e % c;
+    for (long e = tid; e < (long)ncol * ncol; e += JT) {
+      const long j = e / ncol, i = e % ncol;
       V[j * ldv + i] = (i == j) ? 1.0 : 0.0;
     }
   __syncthreads();
   double part = 0.0;
-  for (long e = tid; e < (long)mb * c; e += JT) {
-    const long i = e / c, j = e % c;
+  for (long e = tid; e < (long)ncol * nrow; e += JT) {
+    const long j = e / nrow, i = e % nrow;
     const double x = A[j * lda + i];
     part += x * x;
   }
@@ -155,8 +168,8 @@ __global__ __launch_bounds__(JT) void jacobi_cols_kernel(
   const double abs_floor = 1e-30 * normF2;
   const double eps = 1e-14;
 
-  const Pairing P = make_pairing(c);
-  const int k = tid / G, lig = tid % G;   // pair slot of this lane group
+  const Pairing P = make_pairing(ncol);
+  const int kk = tid / G, lig = tid % G;   // pair slot of this lane group
   int sweep = 0, converged = 0, rounds = 0;
   if (tid == 0) round_any[0] = round_any[1] = 0;
   for (; sweep < max_sweeps; ++sweep) {
@@ -164,16 +177,16 @@ __global__ __launch_bounds__(JT) void jacobi_cols_kernel(
     __syncthreads();
     for (int r = 0; r < P.cc - 1; ++r, ++rounds) {
       int p = 0, q = 0;
-      if (k < P.np) pair_of(r, k, P.cc, p, q);
-      if (k < P.np && p < c && q < c) {
+      if (kk < P.np) pair_of(r, kk, P.cc, p, q);
+      if (kk < P.np && p < ncol && q < ncol) {
         double* ap = A + (long)p * lda;
         double* aq = A + (long)q * lda;
         double x[RPT], y[RPT];
 #pragma unroll
         for (int rr = 0; rr < RPT; ++rr) {
           const int i = lig + G * rr;
-          x[rr] = (i < mb) ? ap[i] : 0.0;
-          y[rr] = (i < mb) ? aq[i] : 0.0;
+          x[rr] = (i < nrow) ? ap[i] : 0.0;
+          y[rr] = (i < nrow) ? aq[i] : 0.0;
         }
         double a = 0.0, b = 0.0, g = 0.0;
 #pragma unroll
@@ -192,20 +205,21 @@ __global__ __launch_bounds__(JT) void jacobi_cols_kernel(
 #pragma unroll
           for (int rr = 0; rr < RPT; ++rr) {
             const int i = lig + G * rr;
-            if (i < mb) {
+            if (i < nrow) {
               ap[i] = cs * x[rr] - sn * y[rr];
               aq[i] = sn * x[rr] + cs * y[rr];
             }
           }
-          if (keep_v) rotate_cols(V + (long)p * ldv, V + (long)q * ldv, c, lig, cs, sn);
+          if (keep_v)
+            rotate_cols(V + (long)p * ldv, V + (long)q * ldv, ncol, lig, cs, sn);
           if (lig == 0) {
             sweep_any = 1;
             round_any[rounds & 1] = 1;
           }
         }
         if (!keep_v && lig == 0) {
-          rotlog[(2L * rounds) * P.np + 2 * k] = cs;
-          rotlog[(2L * rounds) * P.np + 2 * k + 1] = sn;
+          rotlog[(2L * rounds) * P.np + 2 * kk] = cs;
+          rotlog[(2L * rounds) * P.np + 2 * kk + 1] = sn;
         }
       }
       __syncthreads();
@@ -224,28 +238,28 @@ __global__ __launch_bounds__(JT) void jacobi_cols_kernel(
   }
 
   // singular values = column norms (scratch half of sigbuf), rank-sorted
-  for (int j = tid; j < c; j += JT) {
+  for (int j = tid; j < ncol; j += JT) {
     double s2 = 0.0;
     const double* aj = A + (long)j * lda;
-    for (int i = 0; i < mb; ++i) s2 += aj[i] * aj[i];
-    sigbuf[c + j] = sqrt(s2);
+    for (int i = 0; i < nrow; ++i) s2 += aj[i] * aj[i];
+    sigbuf[ncol + j] = sqrt(s2);
   }
   __syncthreads();
-  for (int j = tid; j < c; j += JT) {
-    const double sj = sigbuf[c + j];
+  for (int j = tid; j < ncol; j += JT) {
+    const double sj = sigbuf[ncol + j];
     int rank = 0;
-    for (int kk = 0; kk < c; ++kk) {
-      const double sk = sigbuf[c + kk];
-      rank += (sk > sj || (sk == sj && kk < j)) ? 1 : 0;
+    for (int q = 0; q < ncol; ++q) {
+      const double sq = sigbuf[ncol + q];
+      rank += (sq > sj || (sq == sj && q < j)) ? 1 : 0;
     }
     perm_out[rank] = j;
     sigbuf[rank] = sj;
   }
   __syncthreads();
-  const int kmax = mb < c ? mb : c;
+  const int kmax = ncol;
   if (tid == 0) {
     double tot = 0.0;
-    for (int i = 0; i < c; ++i) tot += sigbuf[i] * sigbuf[i];
+    for (int i = 0; i < ncol; ++i) tot += sigbuf[i] * sigbuf[i];
     const int capd = cap < kmax ? cap : kmax;
     int D;
     if (tot <= 0.0) {
@@ -254,10 +268,8 @@ __global__ __launch_bounds__(JT) void jacobi_cols_kernel(
       D = capd;
     } else {
       // smallest D' >= 1 whose discarded tail (summed from the smallest
-      // value) is <= tol^2; values beyond kmax are the zero columns of a
-      // wide matrix
+      // value) is <= tol^2
       double acc = 0.0;
-      for (int i = c - 1; i >= kmax; --i) acc += sigbuf[i] * sigbuf[i] / tot;
       int best = kmax;
       for (int Dp = kmax - 1; Dp >= 1; --Dp) {
         acc += sigbuf[Dp] * sigbuf[Dp] / tot;
@@ -267,7 +279,7 @@ __global__ __launch_bounds__(JT) void jacobi_cols_kernel(
     }
     if (D < 1) D = 1;
     double disc2 = 0.0;
-    for (int i = D; i < c; ++i) disc2 += sigbuf[i] * sigbuf[i];
+    for (int i = D; i < ncol; ++i) disc2 += sigbuf[i] * sigbuf[i];
     Dsh = D;
     info[0] = (double)D;
     info[1] = (tot > 0.0) ? sqrt(disc2 / tot) : 0.0;
@@ -277,24 +289,37 @@ __global__ __launch_bounds__(JT) void jacobi_cols_kernel(
   }
   __syncthreads();
   const int D = Dsh;
-  for (long e = tid; e < (long)mb * D; e += JT) {
-    const long i = e / D, d = e % D;
-    USs[e] = A[(long)perm_out[d] * lda + i];
+  if (mode == 0) {
+    // Vt[d][i] = A[perm d][i] / sigma_d   (right singular vectors)
+    for (long e = tid; e < (long)D * nrow; e += JT) {
+      const long d = e / nrow, i = e % nrow;
+      const double sd = sigbuf[d];
+      Vt[e] = (sd > 0.0) ? A[(long)perm_out[d] * lda + i] / sd : 0.0;
+    }
+  } else {
+    // out1[i][d] = A[perm d][i]   (left singular vectors times sigma)
+    for (long e = tid; e < (long)nrow * D; e += JT) {
+      const long i = e / D, d = e % D;
+      Vt[e] = A[(long)perm_out[d] * lda + i];
+    }
   }
   if (keep_v)
-    for (long e = tid; e < (long)D * c; e += JT) {
-      const long d = e / c, i = e % c;
-      Vt[e] = V[(long)perm_out[d] * ldv + i];
+    for (long e = tid; e < (long)ncol * D; e += JT) {
+      const long i = e / D, d = e % D;
+      const double v = V[(long)perm_out[d] * ldv + i];
+      USs[e] = (mode == 0) ? v * sigbuf[d] : v;
     }
 }
 
 constexpr int kReplayChunk = 16;   // rounds of the log staged in LDS at once
 
-// Replays the logged rotations on V = I (c x c in LDS) and writes Vt.
+// Replays the logged rotations on J = I (c x c in LDS) and writes
+// USs[i][d] = J[i][perm d] * sigma_d.
 __global__ __launch_bounds__(JT) void jacobi_replay_kernel(
-    int c, const double* __restrict__ rotlog, const int* __restrict__ rflag,
-    const int* __restrict__ perm, const double* __restrict__ info,
-    double* __restrict__ Vt) {
+    int c, int mode, const double* __restrict__ rotlog,
+    const int* __restrict__ rflag, const int* __restrict__ perm,
+    const double* __restrict__ info, const double* __restrict__ sig,
+    double* __restrict__ USs) {
   extern __shared__ double smem[];
   __shared__ int fl[kReplayChunk];
   const int tid = threadIdx.x;
@@ -331,9 +356,10 @@ __global__ __launch_bounds__(JT) void jacobi_replay_kernel(
   }
   __syncthreads();
   const int D = (int)info[0];
-  for (long e = tid; e < (long)D * c; e += JT) {
-    const long d = e / c, i = e % c;
-    Vt[e] = V[(long)perm[d] * ldv + i];
+  for (long e = tid; e < (long)c * D; e += JT) {
+    const long i = e / D, d = e % D;
+    const double v = V[(long)perm[d] * ldv + i];
+    USs[e] = (mode == 0) ? v * sig[d] : v;
   }
 }
 
@@ -341,16 +367,16 @@ bool g_attr = false;
 
 }  // namespace
 
-size_t jacobi_lds_bytes(int mb, int c, bool keep_v) {
-  size_t a = (size_t)c * (size_t)(mb | 1);
-  size_t v = keep_v ? (size_t)c * (size_t)(c | 1) : 0;
+size_t jacobi_lds_bytes(int k, int c, bool keep_v) {
+  size_t a = (size_t)k * (size_t)(c | 1);
+  size_t v = keep_v ? (size_t)k * (size_t)(k | 1) : 0;
   return (a + v) * sizeof(double);
 }
 
-void jacobi_svd(hipStream_t s, const double* B, int mb, int c, long ldb,
-                int cap, double tol, int max_sweeps, double* rotlog, int* rflag,
-                double* Vt, double* USs, double* sigbuf, int* perm,
-                double* info, bool keep_v) {
+void jacobi_svd(hipStream_t s, const double* Xr, int k, int c, long ldx,
+                int mode, int cap, double tol, int max_sweeps, double* rotlog,
+                int* rflag, double* out1, double* out2, double* sigbuf,
+                int* perm, double* info, bool keep_v) {
   if (!g_attr) {
     MPSV_HIP(hipFuncSetAttribute((const void*)jacobi_cols_kernel,
                                  hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -360,18 +386,18 @@ void jacobi_svd(hipStream_t s, const double* B, int mb, int c, long ldb,
                                  (int)kJacobiMaxLds));
     g_attr = true;
   }
-  const size_t lds = jacobi_lds_bytes(mb, c, keep_v);
-  MPSV_CHECK(lds <= kJacobiMaxLds && c <= kJacobiMaxCols && mb <= kJacobiMaxCols,
-             kEinval, "Jacobi SVD: matrix does not fit on chip");
-  hipLaunchKernelGGL(jacobi_cols_kernel, dim3(1), dim3(JT), lds, s, B, mb, c,
-                     ldb, keep_v ? 1 : 0, rotlog, rflag, max_sweeps, cap, tol, Vt,
-                     USs, sigbuf, perm, info);
+  const size_t lds = jacobi_lds_bytes(k, c, keep_v);
+  MPSV_CHECK(lds <= kJacobiMaxLds && c <= kJacobiMaxCols && k <= c, kEinval,
+             "Jacobi SVD: matrix does not fit on chip");
+  hipLaunchKernelGGL(jacobi_cols_kernel, dim3(1), dim3(JT), lds, s, Xr, k, c,
+                     ldx, keep_v ? 1 : 0, mode, rotlog, rflag, max_sweeps, cap,
+                     tol, out1, out2, sigbuf, perm, info);
   MPSV_LAUNCHED();
   if (!keep_v) {
-    const size_t lv = ((size_t)c * (size_t)(c | 1) +
-                       (size_t)kReplayChunk * (c + 2)) * sizeof(double);
-    hipLaunchKernelGGL(jacobi_replay_kernel, dim3(1), dim3(JT), lv, s, c,
-                       rotlog, rflag, perm, info, Vt);
+    const size_t lv = ((size_t)k * (size_t)(k | 1) +
+                       (size_t)kReplayChunk * (k + 2)) * sizeof(double);
+    hipLaunchKernelGGL(jacobi_replay_kernel, dim3(1), dim3(JT), lv, s, k, mode,
+                       rotlog, rflag, perm, info, sigbuf, out2);
     MPSV_LAUNCHED();
   }
 }

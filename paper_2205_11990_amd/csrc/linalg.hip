@@ -88,6 +88,7 @@ __global__ __launch_bounds__(NT) void qr_panel_kernel(double* P, int m, int jb,
   for (int c = 0; c < jb; ++c) {
     // norm of the column below the diagonal
     double sq = 0.0;
+#pragma unroll 4
     for (int i = c + 1 + tid; i < m; i += NT) {
       const double x = pp[(long)i * pld + c];
       sq = fma(x, x, sq);
@@ -117,17 +118,30 @@ __global__ __launch_bounds__(NT) void qr_panel_kernel(double* P, int m, int jb,
     if (c + 1 < jb && tau != 0.0) {
       // w_j = sum_{i >= c} v_i P[i][j] for j > c
       double acc = 0.0;
-      if (owner && gj > c)
-        for (int i = c + gg; i < m; i += ngr) {
-          const double vi = (i == c) ? 1.0 : pp[(long)i * pld + c];
-          acc = fma(vi, pp[(long)i * pld + gj], acc);
+      if (owner && gj > c) {
+        // four independent accumulators so that the LDS loads pipeline
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int i = c + gg;
+        if (i == c) {
+          a0 = pp[(long)c * pld + gj];
+          i += ngr;
         }
+        for (; i + 3 * ngr < m; i += 4 * ngr) {
+          a0 = fma(pp[(long)i * pld + c], pp[(long)i * pld + gj], a0);
+          a1 = fma(pp[(long)(i + ngr) * pld + c], pp[(long)(i + ngr) * pld + gj], a1);
+          a2 = fma(pp[(long)(i + 2 * ngr) * pld + c], pp[(long)(i + 2 * ngr) * pld + gj], a2);
+          a3 = fma(pp[(long)(i + 3 * ngr) * pld + c], pp[(long)(i + 3 * ngr) * pld + gj], a3);
+        }
+        for (; i < m; i += ngr) a0 = fma(pp[(long)i * pld + c], pp[(long)i * pld + gj], a0);
+        acc = (a0 + a1) + (a2 + a3);
+      }
       part[tid] = acc;
       __syncthreads();
       double w = 0.0;
       if (owner && gj > c) {
         for (int q = 0; q < ngr; ++q) w += part[q * jb + gj];
         w *= tau;
+#pragma unroll 4
         for (int i = c + gg; i < m; i += ngr) {
           const double vi = (i == c) ? 1.0 : pp[(long)i * pld + c];
           pp[(long)i * pld + gj] -= vi * w;
@@ -140,12 +154,20 @@ __global__ __launch_bounds__(NT) void qr_panel_kernel(double* P, int m, int jb,
   // T (upper triangular): T[0:c,c] = -tau_c T[0:c,0:c] (V^T v_c)
   for (int c = 0; c < jb; ++c) {
     double acc = 0.0;
-    if (owner && gj < c)
-      for (int i = c + gg; i < m; i += ngr) {
-        const double vc = (i == c) ? 1.0 : pp[(long)i * pld + c];
-        const double vk = pp[(long)i * pld + gj];   // i > gj here (i >= c > gj)
-        acc = fma(vk, vc, acc);
+    if (owner && gj < c) {
+      double a0 = 0.0, a1 = 0.0;
+      int i = c + gg;
+      if (i == c) {
+        a0 = pp[(long)c * pld + gj];
+        i += ngr;
       }
+      for (; i + ngr < m; i += 2 * ngr) {
+        a0 = fma(pp[(long)i * pld + gj], pp[(long)i * pld + c], a0);
+        a1 = fma(pp[(long)(i + ngr) * pld + gj], pp[(long)(i + ngr) * pld + c], a1);
+      }
+      for (; i < m; i += ngr) a0 = fma(pp[(long)i * pld + gj], pp[(long)i * pld + c], a0);
+      acc = a0 + a1;   // V[i][gj] V[i][c] over i >= c (V[c][c] = 1)
+    }
     part[tid] = acc;
     __syncthreads();
     if (tid < jb) {
@@ -423,6 +445,41 @@ static void fill_ints(hipStream_t s, int* x, long n) {
   MPSV_LAUNCHED();
 }
 
+__global__ void transpose_kernel(const double* A, int rows, int cols, long lda,
+                                 double* B, long ldb) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+       e < (long)rows * cols; e += (long)gridDim.x * blockDim.x) {
+    const long i = e % rows, j = e / rows;   // consecutive threads: rows of A
+    B[j * ldb + i] = A[i * lda + j];
+  }
+}
+
+// B (cols x rows, ldb) = A^T for A rows x cols (lda)
+static void transpose(hipStream_t s, const double* A, int rows, int cols,
+                      long lda, double* B, long ldb) {
+  if (rows <= 0 || cols <= 0) return;
+  int blocks = std::min(1024, ceil_div((long)rows * cols, 256));
+  hipLaunchKernelGGL(transpose_kernel, dim3(blocks), dim3(256), 0, s, A, rows,
+                     cols, lda, B, ldb);
+  MPSV_LAUNCHED();
+}
+
+__global__ void copy_rows_kernel(const double* A, long n, double* B) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n;
+       e += (long)gridDim.x * blockDim.x)
+    B[e] = A[e];
+}
+
+// B[0:rows, :] = A (rows x cols, both contiguous with leading dim cols)
+static void copy_rows(hipStream_t s, const double* A, int rows, int cols,
+                      double* B) {
+  const long n = (long)rows * cols;
+  if (n <= 0) return;
+  int blocks = std::min(1024, ceil_div(n, 256));
+  hipLaunchKernelGGL(copy_rows_kernel, dim3(blocks), dim3(256), 0, s, A, n, B);
+  MPSV_LAUNCHED();
+}
+
 static void fill_rows_zero(hipStream_t s, double* X, int r0, int r1, int nc,
                            long ld) {
   if (r1 <= r0 || nc <= 0) return;
@@ -502,50 +559,72 @@ int svd_truncate(hipStream_t s, Arena& ws, double* X, int m, int c, long ldx,
   g_stats.svd_calls++;
   MPSV_CHECK(m >= 1 && c >= 1, kEinval, "svd_truncate: empty matrix");
   ArenaScope sc(ws);
-  const bool tall = m > c;
-  QrFactor qf;
-  const double* B = X;
-  long ldb = ldx;
-  int mb = m;
-  if (tall) {
-    qr_factor(s, ws, X, m, c, ldx, qf);
-    double* R = ws.alloc((size_t)c * c);
-    extract_r(s, X, c, c, ldx, R, c);
-    B = R;
-    ldb = c;
-    mb = c;
-  }
-  double* sigbuf = ws.alloc((size_t)3 * c + 8);
   double* info = ws.alloc(8);
-  const int slot = prof_begin(s);
-  if (c <= kJacobiMaxCols && mb <= kJacobiMaxCols) {
-    const bool keep_v = jacobi_lds_bytes(mb, c, true) <= kJacobiMaxLds;
+  double* sigbuf = ws.alloc((size_t)3 * std::max(m, c) + 8);
+  const int k = std::min(m, c);
+  // Preconditioning: Jacobi runs on the transpose of a triangular factor,
+  // of X when m >= c (mode 0) and of X^T when m < c (mode 1).
+  const bool onchip = k <= kJacobiMaxCols;
+  const int mode = (m >= c) ? 0 : 1;
+  QrFactor qf;
+  double* Rk = nullptr;
+  double* Jd = nullptr;
+  int slot = -1;
+  if (onchip) {
+    if (mode == 0) {
+      qr_factor(s, ws, X, m, c, ldx, qf);
+      Rk = ws.alloc((size_t)c * c);
+      extract_r(s, X, c, c, ldx, Rk, c);
+    } else {
+      double* Xt = ws.alloc((size_t)c * m);
+      transpose(s, X, m, c, ldx, Xt, m);
+      qr_factor(s, ws, Xt, c, m, m, qf);
+      Rk = ws.alloc((size_t)m * m);
+      extract_r(s, Xt, m, m, m, Rk, m);
+      Jd = ws.alloc((size_t)k * k);
+    }
+    const bool keep_v = jacobi_lds_bytes(k, k, true) <= kJacobiMaxLds;
     double* rotlog = nullptr;
     int* rflag = nullptr;
     if (!keep_v) {
-      const long rounds = (long)g_max_sweeps * (c + 1);
-      rotlog = ws.alloc((size_t)rounds * (c + 2));
+      const long rounds = (long)g_max_sweeps * (k + 1);
+      rotlog = ws.alloc((size_t)rounds * (k + 2));
       rflag = ws.alloc_int((size_t)rounds);
-      fill_ints(s, rflag, rounds);
     }
-    int* perm = ws.alloc_int((size_t)c);
-    jacobi_svd(s, B, mb, c, ldb, cap, tol, g_max_sweeps, rotlog, rflag, Vt, US,
-               sigbuf, perm, info, keep_v);
+    int* perm = ws.alloc_int((size_t)k);
+    slot = prof_begin(s);
+    jacobi_svd(s, Rk, k, k, k, mode, cap, tol, g_max_sweeps, rotlog, rflag,
+               mode == 0 ? Vt : US, mode == 0 ? US : Jd, sigbuf, perm, info,
+               keep_v);
   } else {
+    // large matrices: unpreconditioned Jacobi on the columns, in global memory
+    const bool tall = m > c;
+    const double* B = X;
+    long ldb = ldx;
+    int mb = m;
+    if (tall) {
+      qr_factor(s, ws, X, m, c, ldx, qf);
+      double* R = ws.alloc((size_t)c * c);
+      extract_r(s, X, c, c, ldx, R, c);
+      B = R;
+      ldb = c;
+      mb = c;
+    }
     const size_t need = ((size_t)mb * c + (size_t)c * c) * sizeof(double);
     const int use_lds = need <= kJacobiLds ? 1 : 0;
     double* Wg = use_lds ? nullptr : ws.alloc((size_t)mb * c);
     double* Jg = use_lds ? nullptr : ws.alloc((size_t)c * c);
+    slot = prof_begin(s);
     hipLaunchKernelGGL(jacobi_svd_kernel, dim3(1), dim3(NT), use_lds ? need : 0,
                        s, B, mb, c, ldb, Wg, Jg, use_lds, cap, tol, g_max_sweeps,
                        Vt, US, (long)mb, sigbuf, info);
     MPSV_LAUNCHED();
   }
   {
-    // nominal SVD flops of the factored mb x c matrix, 6 m n^2 + 20 n^3
-    const double mm = std::max(mb, c), nn = std::min(mb, c);
+    // nominal SVD flops of the factored m x c matrix, 6 m n^2 + 20 n^3
+    const double mm = std::max(m, c), nn = std::min(m, c);
     prof_end(s, slot, kClsJacobi, 6.0 * mm * nn * nn + 20.0 * nn * nn * nn,
-             8.0 * (2.0 * mb * c + 2.0 * c * c));
+             8.0 * (2.0 * m * c + 2.0 * nn * nn));
   }
   double* h = pinned_info();
   MPSV_HIP(hipMemcpyAsync(h, info, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -557,11 +636,18 @@ int svd_truncate(hipStream_t s, Arena& ws, double* X, int m, int c, long ldx,
     throw Error(kEnumeric, "Jacobi SVD did not converge within " +
                                std::to_string(g_max_sweeps) + " sweeps");
   if (sig) {
-    MPSV_HIP(hipMemcpyAsync(sig, sigbuf, (size_t)std::min(m, c) * sizeof(double),
+    MPSV_HIP(hipMemcpyAsync(sig, sigbuf, (size_t)k * sizeof(double),
                             hipMemcpyDeviceToDevice, s));
   }
-  if (tall) {
-    // US rows [0, c) were written by the kernel with leading dimension D
+  if (onchip && mode == 1) {
+    // V = Q' [J; 0] (c x D), Vt = V^T
+    double* Y = ws.alloc((size_t)c * D);
+    copy_rows(s, Jd, k, D, Y);
+    fill_rows_zero(s, Y, k, c, D, D);
+    qr_apply_q(s, ws, qf, Y, D, D);
+    transpose(s, Y, c, D, D, Vt, c);
+  } else if (m > c || (onchip && mode == 0)) {
+    // US rows [0, c) hold U_R Sigma (leading dimension D): US = Q [U_R Sigma; 0]
     fill_rows_zero(s, US, c, m, D, D);
     qr_apply_q(s, ws, qf, US, D, D);
   }
