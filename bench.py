@@ -87,7 +87,7 @@ def cpu_baseline(w, mode, cores_host):
 # Peak of the unit each kernel class runs on (MI355X, dense FP64).
 _CLASS_BOUND = {
     "gemm_f64": ("mfma", PEAK_FP64_TFLOPS),     # v_mfma_f64_16x16x4f64
-    "qr_panel": ("alu", PEAK_FP64_TFLOPS),      # FP64 vector FMA
+    "householder": ("alu", PEAK_FP64_TFLOPS),   # FP64 vector FMA
     "jacobi_svd": ("alu", PEAK_FP64_TFLOPS),    # FP64 vector FMA
 }
 

@@ -20,6 +20,7 @@
 #include "jacobi.hpp"
 #include "linalg.hpp"
 #include "prof.hpp"
+#include "qr_reg.hpp"
 
 namespace mpsv {
 
@@ -497,6 +498,28 @@ void qr_factor(hipStream_t s, Arena& ws, double* A, int m, int n, long ld,
   f.k = std::min(m, n);
   f.panels.clear();
   g_stats.qr_calls++;
+  if (m <= 1024) {
+    // register-resident panels; the trailing columns are updated by the
+    // reflector-application kernel
+    for (int k0 = 0; k0 < f.k;) {
+      const int rows = m - k0;
+      const int jb = std::min(qr_reg_panel_cols(rows), n - k0);
+      const int kk = std::min(rows, jb);
+      QrPanel pn;
+      pn.k0 = k0;
+      pn.jb = kk;
+      pn.reg = true;
+      pn.V = ws.alloc((size_t)rows * kk);
+      pn.tau = ws.alloc((size_t)kk);
+      double* P = A + (long)k0 * ld + k0;
+      qr_reg_factor(s, P, ld, rows, jb, P, ld, pn.V, pn.tau);
+      const int n2 = n - k0 - jb;
+      if (n2 > 0) qr_reg_apply(s, pn.V, pn.tau, rows, kk, P + jb, ld, n2, true);
+      f.panels.push_back(pn);
+      k0 += jb;
+    }
+    return;
+  }
   for (int k0 = 0; k0 < f.k; ) {
     const int rows = m - k0;
     int jb = std::min(MAXJB, f.k - k0);
@@ -541,9 +564,13 @@ void qr_apply_q(hipStream_t s, Arena& ws, const QrFactor& f, double* X, int nc,
   for (int p = (int)f.panels.size() - 1; p >= 0; --p) {
     const QrPanel& pn = f.panels[p];
     const int rows = f.m - pn.k0;
+    double* X2 = X + (long)pn.k0 * ldx;
+    if (pn.reg) {
+      qr_reg_apply(s, pn.V, pn.tau, rows, pn.jb, X2, ldx, nc, false);
+      continue;
+    }
     ArenaScope sc(ws);
     double* Wt = ws.alloc((size_t)pn.jb * nc);
-    double* X2 = X + (long)pn.k0 * ldx;
     // Wt = V^T X2 ; X2 -= Y Wt
     gemm(s, pn.jb, nc, rows, 1.0, CMatView{pn.V, 1, pn.jb, 0},
          CMatView{X2, ldx, 1, 0}, 0.0, MatView{Wt, nc, 1, 0});

@@ -8,13 +8,16 @@
 
 namespace mpsv {
 
-// One block of Householder reflectors H = I - V T V^T acting on rows
-// [k0, m) of the factored matrix.  V is (m-k0) x jb (explicit, unit lower
-// trapezoidal), Y = V T.
+// One block of Householder reflectors acting on rows [k0, m) of the
+// factored matrix.  Register-resident panels (reg) keep the reflectors
+// column-major, V[j*(m-k0) + i], with their tau; the LDS panels keep the
+// compact-WY form H = I - V T V^T with V (m-k0) x jb row-major and Y = V T.
 struct QrPanel {
   int k0, jb;
-  double* V;
-  double* Y;
+  bool reg = false;
+  double* V = nullptr;
+  double* Y = nullptr;
+  double* tau = nullptr;
 };
 
 struct QrFactor {

@@ -1,0 +1,302 @@
+// Householder QR (SI, "Canonicalization and Compression": the left sweep
+// and the triangular preconditioning of the SVD) with the matrix held in the
+// registers of one workgroup.
+//
+// Factorisation: 16 waves; wave w holds the columns j = w + 16 b (b < CPW)
+// and lane l of every wave the rows i = l + 64 a (a < RPL), so each column
+// lives inside one wave and the products v^T A of a reflector with the
+// columns are wave-local sums: no LDS partial tables, one barrier per
+// column.  For column j the owning wave forms the reflector (LAPACK dlarfg
+// conventions: beta = -sign(alpha) |x|, tau = (beta - alpha) / beta,
+// v = x / (alpha - beta), v_j = 1) and publishes v in LDS (double
+// buffered); after the barrier every wave updates its columns right of j.
+// The reflectors go to global memory, column-major, for later application.
+//
+// Application: Q Y or Q^T Y for a block of columns Y; each wave owns CPW
+// columns and streams the reflectors from L2.  There is no dependency
+// between columns, so the kernel has no barrier and spreads over as many
+// workgroups as the column count allows.  Panels of a wider matrix are
+// factored one after the other with the trailing columns updated by the
+// same application kernel (blocked right-looking QR without a T factor).
+#include <algorithm>
+#include <cmath>
+
+#include "prof.hpp"
+#include "qr_reg.hpp"
+#include "wave.hpp"
+
+namespace mpsv {
+
+namespace {
+
+constexpr int FT = 1024;  // factorisation workgroup: 16 waves
+constexpr int AT = 256;   // application workgroup: 4 waves
+
+template <int N>
+__device__ __forceinline__ void sums_any(double (&p)[N]) {
+  if constexpr (N == 1 || N == 2 || N == 4 || N == 8) {
+    wave::sums<N>(p);
+  } else {
+    constexpr int M = N <= 4 ? 4 : 8;
+    double q[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) q[i] = i < N ? p[i] : 0.0;
+    wave::sums<M>(q);
+#pragma unroll
+    for (int i = 0; i < N; ++i) p[i] = q[i];
+  }
+}
+
+// Columns 16 B .. 16 B + 15 of the factorisation (register column B).
+template <int CPW, int RPL, int B>
+__device__ __forceinline__ void factor_block(double (&x)[RPL][CPW], int w,
+                                             int l, int m, int k, double* vb,
+                                             double* tb, double* __restrict__ V,
+                                             double* __restrict__ tau) {
+  constexpr int NB = CPW - B;  // register columns that can still change
+  for (int t = 0; t < 16; ++t) {
+    const int j = 16 * B + t;
+    if (j >= k) return;  // uniform over the workgroup
+    const int buf = j & 1;
+    double* vj = vb + buf * 64 * RPL;
+    if (w == t) {
+      double s2 = 0.0, xa = 0.0;
+      const int aj = j >> 6;
+#pragma unroll
+      for (int a = 0; a < RPL; ++a) {
+        const int i = l + 64 * a;
+        const double xi = x[a][B];
+        if (i > j) s2 = fma(xi, xi, s2);
+        if (a == aj) xa = xi;
+      }
+      s2 = wave::sum64(s2);
+      const double alpha = wave::read_lane(xa, j & 63);
+      double tj = 0.0, beta = alpha, scal = 0.0;
+      if (s2 > 0.0) {
+        beta = -copysign(sqrt(fma(alpha, alpha, s2)), alpha);
+        tj = (beta - alpha) / beta;
+        scal = 1.0 / (alpha - beta);
+      }
+#pragma unroll
+      for (int a = 0; a < RPL; ++a) {
+        const int i = l + 64 * a;
+        const double v = (i > j) ? x[a][B] * scal : (i == j ? 1.0 : 0.0);
+        vj[i] = v;
+        if (i < m) V[(long)j * m + i] = v;
+        x[a][B] = (i == j) ? beta : (i > j ? 0.0 : x[a][B]);
+      }
+      if (l == 0) {
+        tb[buf] = tj;
+        tau[j] = tj;
+      }
+    }
+    __syncthreads();
+    const double tj = tb[buf];
+    if (tj != 0.0) {
+      double v[RPL];
+#pragma unroll
+      for (int a = 0; a < RPL; ++a) v[a] = vj[l + 64 * a];
+      double p[NB];
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        double acc = 0.0;
+#pragma unroll
+        for (int a = 0; a < RPL; ++a) acc = fma(v[a], x[a][B + q], acc);
+        p[q] = acc;
+      }
+      // register column B of this wave is column j itself (w == t) or
+      // already finished (w < t)
+      if (w <= t) p[0] = 0.0;
+      sums_any<NB>(p);
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        const double f = tj * p[q];
+#pragma unroll
+        for (int a = 0; a < RPL; ++a) x[a][B + q] = fma(-v[a], f, x[a][B + q]);
+      }
+    }
+  }
+  if constexpr (B + 1 < CPW)
+    factor_block<CPW, RPL, B + 1>(x, w, l, m, k, vb, tb, V, tau);
+}
+
+template <int CPW, int RPL>
+__global__ __launch_bounds__(FT) void qr_reg_factor_kernel(
+    const double* A, long lda, int m, int n, double* R, long ldr,
+    double* __restrict__ V, double* __restrict__ tau) {
+  __shared__ double vb[2 * 64 * RPL];
+  __shared__ double tb[2];
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int k = m < n ? m : n;
+  double x[RPL][CPW];
+#pragma unroll
+  for (int a = 0; a < RPL; ++a)
+#pragma unroll
+    for (int b = 0; b < CPW; ++b) {
+      const int i = l + 64 * a, j = w + 16 * b;
+      x[a][b] = (i < m && j < n) ? A[(long)i * lda + j] : 0.0;
+    }
+  factor_block<CPW, RPL, 0>(x, w, l, m, k, vb, tb, V, tau);
+  // every wave has passed the first barrier, so A (which R may alias) has
+  // been read completely
+#pragma unroll
+  for (int a = 0; a < RPL; ++a)
+#pragma unroll
+    for (int b = 0; b < CPW; ++b) {
+      const int i = l + 64 * a, j = w + 16 * b;
+      if (i < k && j < n) R[(long)i * ldr + j] = (i <= j) ? x[a][b] : 0.0;
+    }
+}
+
+template <int CPW, int RPL>
+__global__ __launch_bounds__(AT) void qr_reg_apply_kernel(
+    const double* __restrict__ V, const double* __restrict__ tau, int m, int k,
+    double* __restrict__ Y, long ldy, int p, int trans) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int c0 = (blockIdx.x * (AT / 64) + w) * CPW;
+  if (c0 >= p) return;  // whole wave; the kernel has no barrier
+  double y[RPL][CPW];
+#pragma unroll
+  for (int a = 0; a < RPL; ++a)
+#pragma unroll
+    for (int b = 0; b < CPW; ++b) {
+      const int i = l + 64 * a;
+      y[a][b] = (i < m && c0 + b < p) ? Y[(long)i * ldy + c0 + b] : 0.0;
+    }
+  double vn[RPL];
+  {
+    const int j = trans ? 0 : k - 1;
+#pragma unroll
+    for (int a = 0; a < RPL; ++a) {
+      const int i = l + 64 * a;
+      vn[a] = (i < m) ? V[(long)j * m + i] : 0.0;
+    }
+  }
+  for (int s = 0; s < k; ++s) {
+    const int j = trans ? s : k - 1 - s;
+    double v[RPL];
+#pragma unroll
+    for (int a = 0; a < RPL; ++a) v[a] = vn[a];
+    if (s + 1 < k) {
+      const int jn = trans ? s + 1 : k - 2 - s;
+#pragma unroll
+      for (int a = 0; a < RPL; ++a) {
+        const int i = l + 64 * a;
+        vn[a] = (i < m) ? V[(long)jn * m + i] : 0.0;
+      }
+    }
+    const double tj = tau[j];
+    if (tj == 0.0) continue;
+    double d[CPW];
+#pragma unroll
+    for (int b = 0; b < CPW; ++b) {
+      double acc = 0.0;
+#pragma unroll
+      for (int a = 0; a < RPL; ++a) acc = fma(v[a], y[a][b], acc);
+      d[b] = acc;
+    }
+    wave::sums<CPW>(d);
+#pragma unroll
+    for (int b = 0; b < CPW; ++b) {
+      const double f = tj * d[b];
+#pragma unroll
+      for (int a = 0; a < RPL; ++a) y[a][b] = fma(-v[a], f, y[a][b]);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < RPL; ++a)
+#pragma unroll
+    for (int b = 0; b < CPW; ++b) {
+      const int i = l + 64 * a;
+      if (i < m && c0 + b < p) Y[(long)i * ldy + c0 + b] = y[a][b];
+    }
+}
+
+int rows_per_lane(int m) {
+  int r = 1;
+  while (64 * r < m) r *= 2;
+  return r;
+}
+
+int cols_per_wave(int n) {
+  int c = 1;
+  while (16 * c < n) c *= 2;
+  return c;
+}
+
+template <int CPW, int RPL>
+void launch_factor(hipStream_t s, const double* A, long lda, int m, int n,
+                   double* R, long ldr, double* V, double* tau) {
+  hipLaunchKernelGGL((qr_reg_factor_kernel<CPW, RPL>), dim3(1), dim3(FT), 0, s,
+                     A, lda, m, n, R, ldr, V, tau);
+}
+
+template <int CPW, int RPL>
+void launch_apply(hipStream_t s, const double* V, const double* tau, int m,
+                  int k, double* Y, long ldy, int p, int trans) {
+  const int per_block = (AT / 64) * CPW;
+  hipLaunchKernelGGL((qr_reg_apply_kernel<CPW, RPL>), dim3(ceil_div(p, per_block)),
+                     dim3(AT), 0, s, V, tau, m, k, Y, ldy, p, trans);
+}
+
+}  // namespace
+
+// The register budget of 16 waves per CU is 128 VGPRs: at most 32 matrix
+// elements per lane, and 16 once the rows need 16 per lane (the reflector
+// and its prefetch take the rest).
+bool qr_reg_fits(int m, int n) {
+  if (m < 1 || n < 1 || m > 1024 || n > 128) return false;
+  const int rpl = rows_per_lane(m), cpw = cols_per_wave(n);
+  return rpl * cpw <= (rpl == 16 ? 16 : 32);
+}
+
+int qr_reg_panel_cols(int m) {
+  const int rpl = rows_per_lane(m);
+  return 16 * std::min(8, (rpl == 16 ? 16 : 32) / rpl);
+}
+
+void qr_reg_factor(hipStream_t s, const double* A, long lda, int m, int n,
+                   double* R, long ldr, double* V, double* tau) {
+  MPSV_CHECK(qr_reg_fits(m, n), kEinval, "qr_reg_factor: shape does not fit");
+  const int rpl = rows_per_lane(m), cpw = cols_per_wave(n);
+  const int slot = prof_begin(s);
+#define MPSV_F(C, Rr)                                                   \
+  if (cpw == C && rpl == Rr) launch_factor<C, Rr>(s, A, lda, m, n, R, ldr, V, tau); else
+  MPSV_F(1, 1) MPSV_F(2, 1) MPSV_F(4, 1) MPSV_F(8, 1)
+  MPSV_F(1, 2) MPSV_F(2, 2) MPSV_F(4, 2) MPSV_F(8, 2)
+  MPSV_F(1, 4) MPSV_F(2, 4) MPSV_F(4, 4) MPSV_F(8, 4)
+  MPSV_F(1, 8) MPSV_F(2, 8) MPSV_F(4, 8)
+  MPSV_F(1, 16)
+  throw Error(kEinval, "qr_reg_factor: no kernel for this shape");
+#undef MPSV_F
+  MPSV_LAUNCHED();
+  const int k = m < n ? m : n;
+  // nominal GEQRF flops, 2 m n^2 - 2 n^3 / 3 (n = k columns reduced) plus
+  // the update of the n - k columns right of a wide block
+  prof_end(s, slot, kClsQrPanel,
+           2.0 * m * (double)k * k - 2.0 * k * (double)k * k / 3.0 +
+               4.0 * (double)(n - k) * k * (m - k / 2.0),
+           8.0 * (2.0 * m * n + (double)m * k));
+}
+
+void qr_reg_apply(hipStream_t s, const double* V, const double* tau, int m,
+                  int k, double* Y, long ldy, int p, bool trans) {
+  if (p <= 0 || k <= 0) return;
+  MPSV_CHECK(m >= 1 && m <= 1024 && k <= m, kEinval, "qr_reg_apply: bad shape");
+  const int rpl = rows_per_lane(m);
+  const int cpw = p >= 128 ? 2 : 1;
+  const int slot = prof_begin(s);
+  const int tr = trans ? 1 : 0;
+#define MPSV_A(C, Rr)                                                   \
+  if (cpw == C && rpl == Rr) launch_apply<C, Rr>(s, V, tau, m, k, Y, ldy, p, tr); else
+  MPSV_A(1, 1) MPSV_A(2, 1) MPSV_A(1, 2) MPSV_A(2, 2) MPSV_A(1, 4) MPSV_A(2, 4)
+  MPSV_A(1, 8) MPSV_A(2, 8) MPSV_A(1, 16) MPSV_A(2, 16)
+  throw Error(kEinval, "qr_reg_apply: no kernel for this shape");
+#undef MPSV_A
+  MPSV_LAUNCHED();
+  // k reflectors of decreasing length applied to p columns
+  prof_end(s, slot, kClsQrPanel, 4.0 * p * (double)k * (m - (k - 1) / 2.0),
+           8.0 * (2.0 * m * p + (double)m * k));
+}
+
+}  // namespace mpsv

@@ -41,7 +41,9 @@ def test_gemm_matches_numpy(B, M, N, K):
 
 
 @pytest.mark.parametrize("m,n", [(1, 1), (5, 3), (3, 5), (40, 40), (130, 70), (257, 33),
-                                 (600, 200), (2048, 8), (64, 300)])
+                                 (600, 200), (2048, 8), (64, 300), (128, 128), (256, 128),
+                                 (512, 64), (1024, 128), (1000, 100), (200, 129), (700, 700),
+                                 (65, 17), (2048, 40)])
 def test_qr_is_orthogonal_factorisation(B, m, n):
     _say("qr %d x %d" % (m, n))
     A = wl.random_matrix(m, n, seed=m + 7 * n, decay=3.0)
