@@ -589,13 +589,20 @@ int svd_truncate(hipStream_t s, Arena& ws, double* X, int m, int c, long ldx,
   double* info = ws.alloc(8);
   double* sigbuf = ws.alloc((size_t)3 * std::max(m, c) + 8);
   const int k = std::min(m, c);
-  // Preconditioning: Jacobi runs on the transpose of a triangular factor,
-  // of X when m >= c (mode 0) and of X^T when m < c (mode 1).
+  // Preconditioning: Jacobi runs on the transpose of a triangular factor
+  // whose right singular vectors are those of X (or map to them through an
+  // orthogonal factor):
+  //   mode 0 (m >= c): X = Q1 R1, Jacobi on R1^T gives V Sigma, and
+  //                    U Sigma = X V = Q1 (R1 V);
+  //   mode 1 (m < c):  X^T = Q1 R1, R1^T = Q2 R2, so X = Q2 R2 Q1^T; Jacobi
+  //                    on R2^T gives W Sigma with V = Q1 [W; 0] and
+  //                    U Sigma = Q2 (R2 W).
+  // Neither needs the Jacobi rotations accumulated.
   const bool onchip = k <= kJacobiMaxCols;
   const int mode = (m >= c) ? 0 : 1;
-  QrFactor qf;
+  QrFactor qf, qf2;
   double* Rk = nullptr;
-  double* Jd = nullptr;
+  double* Wt = nullptr;
   int slot = -1;
   if (onchip) {
     if (mode == 0) {
@@ -606,23 +613,20 @@ int svd_truncate(hipStream_t s, Arena& ws, double* X, int m, int c, long ldx,
       double* Xt = ws.alloc((size_t)c * m);
       transpose(s, X, m, c, ldx, Xt, m);
       qr_factor(s, ws, Xt, c, m, m, qf);
+      double* R1t = ws.alloc((size_t)m * m);
+      // R1^T (lower triangular): transpose of the upper triangle of Xt
+      double* R1 = ws.alloc((size_t)m * m);
+      extract_r(s, Xt, m, m, m, R1, m);
+      transpose(s, R1, m, m, m, R1t, m);
+      qr_factor(s, ws, R1t, m, m, m, qf2);
       Rk = ws.alloc((size_t)m * m);
-      extract_r(s, Xt, m, m, m, Rk, m);
-      Jd = ws.alloc((size_t)k * k);
-    }
-    const bool keep_v = jacobi_lds_bytes(k, k, true) <= kJacobiMaxLds;
-    double* rotlog = nullptr;
-    int* rflag = nullptr;
-    if (!keep_v) {
-      const long rounds = (long)g_max_sweeps * (k + 1);
-      rotlog = ws.alloc((size_t)rounds * (k + 2));
-      rflag = ws.alloc_int((size_t)rounds);
+      extract_r(s, R1t, m, m, m, Rk, m);
+      Wt = ws.alloc((size_t)k * k);
     }
     int* perm = ws.alloc_int((size_t)k);
     slot = prof_begin(s);
-    jacobi_svd(s, Rk, k, k, k, mode, cap, tol, g_max_sweeps, rotlog, rflag,
-               mode == 0 ? Vt : US, mode == 0 ? US : Jd, sigbuf, perm, info,
-               keep_v);
+    jacobi_svd(s, Rk, k, k, cap, tol, g_max_sweeps, mode == 0 ? Vt : Wt,
+               sigbuf, perm, info);
   } else {
     // large matrices: unpreconditioned Jacobi on the columns, in global memory
     const bool tall = m > c;
@@ -666,14 +670,23 @@ int svd_truncate(hipStream_t s, Arena& ws, double* X, int m, int c, long ldx,
     MPSV_HIP(hipMemcpyAsync(sig, sigbuf, (size_t)k * sizeof(double),
                             hipMemcpyDeviceToDevice, s));
   }
-  if (onchip && mode == 1) {
-    // V = Q' [J; 0] (c x D), Vt = V^T
+  if (onchip && mode == 0) {
+    // US = Q1 [R1 V_D; 0]   (m x D, leading dimension D)
+    gemm(s, c, D, c, 1.0, CMatView{Rk, c, 1, 0}, CMatView{Vt, 1, c, 0}, 0.0,
+         MatView{US, D, 1, 0});
+    fill_rows_zero(s, US, c, m, D, D);
+    qr_apply_q(s, ws, qf, US, D, D);
+  } else if (onchip) {
+    // V = Q1 [W_D; 0] (c x D), Vt = V^T; US = Q2 (R2 W_D) (m x D)
     double* Y = ws.alloc((size_t)c * D);
-    copy_rows(s, Jd, k, D, Y);
+    transpose(s, Wt, D, k, k, Y, D);
     fill_rows_zero(s, Y, k, c, D, D);
     qr_apply_q(s, ws, qf, Y, D, D);
     transpose(s, Y, c, D, D, Vt, c);
-  } else if (m > c || (onchip && mode == 0)) {
+    gemm(s, m, D, m, 1.0, CMatView{Rk, m, 1, 0}, CMatView{Wt, 1, k, 0}, 0.0,
+         MatView{US, D, 1, 0});
+    qr_apply_q(s, ws, qf2, US, D, D);
+  } else if (m > c) {
     // US rows [0, c) hold U_R Sigma (leading dimension D): US = Q [U_R Sigma; 0]
     fill_rows_zero(s, US, c, m, D, D);
     qr_apply_q(s, ws, qf, US, D, D);
