@@ -128,11 +128,18 @@ __global__ __launch_bounds__(JT) void jacobi_cols_kernel(
   }
   const double normF2 = block_sum(part, red);
   // Columns whose squared norm is below `negl` (sigma below 1e-15 of the
-  // Frobenius norm) are numerical zeros: pairs of two of them are not
-  // rotated, and their singular vectors are returned as zero rows, so that
-  // the kept rows of Vt are orthonormal and X V_D is an exact projection.
+  // Frobenius norm) are numerical zeros: they are never rotated (rotating
+  // them against the others only stirs rounding noise and can stall the
+  // convergence to a linear rate), and their singular vectors are returned
+  // as zero rows, so that the kept rows of Vt are orthonormal and X V_D is
+  // a projection that misses at most that noise.
   const double negl = 1e-30 * normF2;
-  const double eps = 1e-14;
+  // A pair is rotated when its cosine |g| / (|a_p| |a_q|) exceeds eps; a
+  // sweep counts as converged when no cosine in it exceeded conv.  The gap
+  // tolerates pairs that stagnate at rounding level (columns near the
+  // numerical null space of a rank-deficient factor) while every other
+  // pair still ends orthogonal to about 1e-15.
+  const double eps = 1e-14, conv = 1e-12;
 
   const Pairing P = make_pairing(ncol);
   const int kk = tid / G, lig = tid % G;   // pair slot of this lane group
@@ -164,7 +171,7 @@ __global__ __launch_bounds__(JT) void jacobi_cols_kernel(
         b = sum16(b);
         g = sum16(g);
         double cs = 1.0, sn = 0.0;
-        const bool rot = g != 0.0 && fabs(g) > eps * sqrt(a) * sqrt(b) && fmax(a, b) > negl;
+        const bool rot = g != 0.0 && fabs(g) > eps * sqrt(a) * sqrt(b) && fmin(a, b) > negl;
         if (rot) {
           rotation(a, b, g, cs, sn);
 #pragma unroll
@@ -175,7 +182,7 @@ __global__ __launch_bounds__(JT) void jacobi_cols_kernel(
               aq[i] = sn * x[rr] + cs * y[rr];
             }
           }
-          if (lig == 0) sweep_any = 1;
+          if (lig == 0 && fabs(g) > conv * sqrt(a) * sqrt(b)) sweep_any = 1;
         }
       }
       __syncthreads();

@@ -14,6 +14,7 @@
 // evaluated on the device.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <mutex>
 
 #include "gemm.hpp"
@@ -33,6 +34,16 @@ constexpr size_t kJacobiLds = 144 * 1024;
 
 LinalgStats g_stats;
 int g_max_sweeps = 60;
+
+// Extra pairs of QR factorisations before the Jacobi sweeps (tuning knob,
+// MPSV_SVD_PRECOND in the environment; default 1).
+int svd_precondition_pairs() {
+  static const int n = [] {
+    const char* e = std::getenv("MPSV_SVD_PRECOND");
+    return e ? std::max(0, std::min(3, std::atoi(e))) : 1;
+  }();
+  return n;
+}
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -590,43 +601,67 @@ int svd_truncate(hipStream_t s, Arena& ws, double* X, int m, int c, long ldx,
   double* sigbuf = ws.alloc((size_t)3 * std::max(m, c) + 8);
   const int k = std::min(m, c);
   // Preconditioning: Jacobi runs on the transpose of a triangular factor
-  // whose right singular vectors are those of X (or map to them through an
-  // orthogonal factor):
-  //   mode 0 (m >= c): X = Q1 R1, Jacobi on R1^T gives V Sigma, and
-  //                    U Sigma = X V = Q1 (R1 V);
-  //   mode 1 (m < c):  X^T = Q1 R1, R1^T = Q2 R2, so X = Q2 R2 Q1^T; Jacobi
-  //                    on R2^T gives W Sigma with V = Q1 [W; 0] and
-  //                    U Sigma = Q2 (R2 W).
-  // Neither needs the Jacobi rotations accumulated.
+  // B obtained by a chain of QR factorisations, first of X (m >= c) or of
+  // X^T (m < c), then alternately of B^T and B, until
+  //   X = L_1 ... L_p  B  (R_1 ... R_q)^T,   B upper triangular (k x k).
+  // Jacobi on B^T gives W Sigma (W: right singular vectors of B), so
+  //   V = R_1 (... (R_q W)),   U Sigma = L_1 (... (L_p (B W))).
+  // Each extra pair of factorisations moves B closer to diagonal and saves
+  // Jacobi sweeps.  The rotations are never accumulated.
   const bool onchip = k <= kJacobiMaxCols;
   const int mode = (m >= c) ? 0 : 1;
-  QrFactor qf, qf2;
+  QrFactor qf;  // used by the large-matrix path
+  std::vector<QrFactor> Lf, Rf;
+  Lf.reserve(4);
+  Rf.reserve(4);
   double* Rk = nullptr;
   double* Wt = nullptr;
   int slot = -1;
   if (onchip) {
+    bool upper;
+    double* Bk = ws.alloc((size_t)k * k);
     if (mode == 0) {
-      qr_factor(s, ws, X, m, c, ldx, qf);
-      Rk = ws.alloc((size_t)c * c);
-      extract_r(s, X, c, c, ldx, Rk, c);
+      Lf.emplace_back();
+      qr_factor(s, ws, X, m, c, ldx, Lf.back());
+      extract_r(s, X, c, c, ldx, Bk, c);
+      upper = true;
     } else {
       double* Xt = ws.alloc((size_t)c * m);
       transpose(s, X, m, c, ldx, Xt, m);
-      qr_factor(s, ws, Xt, c, m, m, qf);
-      double* R1t = ws.alloc((size_t)m * m);
-      // R1^T (lower triangular): transpose of the upper triangle of Xt
+      Rf.emplace_back();
+      qr_factor(s, ws, Xt, c, m, m, Rf.back());
       double* R1 = ws.alloc((size_t)m * m);
       extract_r(s, Xt, m, m, m, R1, m);
-      transpose(s, R1, m, m, m, R1t, m);
-      qr_factor(s, ws, R1t, m, m, m, qf2);
-      Rk = ws.alloc((size_t)m * m);
-      extract_r(s, R1t, m, m, m, Rk, m);
-      Wt = ws.alloc((size_t)k * k);
+      transpose(s, R1, m, m, m, Bk, m);  // B = R1^T, lower
+      upper = false;
     }
+    int extra = 2 * svd_precondition_pairs();
+    while (!upper || extra > 0) {
+      double* T = ws.alloc((size_t)k * k);
+      if (upper) {
+        // B = R: R^T = Q' R'  ->  B = R'^T Q'^T
+        transpose(s, Bk, k, k, k, T, k);
+        Rf.emplace_back();
+        qr_factor(s, ws, T, k, k, k, Rf.back());
+        double* Rn = ws.alloc((size_t)k * k);
+        extract_r(s, T, k, k, k, Rn, k);
+        transpose(s, Rn, k, k, k, Bk, k);
+        upper = false;
+      } else {
+        // B lower: B = Q' R'
+        copy_rows(s, Bk, k, k, T);
+        Lf.emplace_back();
+        qr_factor(s, ws, T, k, k, k, Lf.back());
+        extract_r(s, T, k, k, k, Bk, k);
+        upper = true;
+      }
+      --extra;
+    }
+    Rk = Bk;
+    Wt = ws.alloc((size_t)k * k);
     int* perm = ws.alloc_int((size_t)k);
     slot = prof_begin(s);
-    jacobi_svd(s, Rk, k, k, cap, tol, g_max_sweeps, mode == 0 ? Vt : Wt,
-               sigbuf, perm, info);
+    jacobi_svd(s, Rk, k, k, cap, tol, g_max_sweeps, Wt, sigbuf, perm, info);
   } else {
     // large matrices: unpreconditioned Jacobi on the columns, in global memory
     const bool tall = m > c;
@@ -670,22 +705,22 @@ int svd_truncate(hipStream_t s, Arena& ws, double* X, int m, int c, long ldx,
     MPSV_HIP(hipMemcpyAsync(sig, sigbuf, (size_t)k * sizeof(double),
                             hipMemcpyDeviceToDevice, s));
   }
-  if (onchip && mode == 0) {
-    // US = Q1 [R1 V_D; 0]   (m x D, leading dimension D)
-    gemm(s, c, D, c, 1.0, CMatView{Rk, c, 1, 0}, CMatView{Vt, 1, c, 0}, 0.0,
-         MatView{US, D, 1, 0});
-    fill_rows_zero(s, US, c, m, D, D);
-    qr_apply_q(s, ws, qf, US, D, D);
-  } else if (onchip) {
-    // V = Q1 [W_D; 0] (c x D), Vt = V^T; US = Q2 (R2 W_D) (m x D)
+  if (onchip) {
+    // V = R_1 (... (R_q W_D)): c x D, rows beyond a factor's own size zero
     double* Y = ws.alloc((size_t)c * D);
     transpose(s, Wt, D, k, k, Y, D);
-    fill_rows_zero(s, Y, k, c, D, D);
-    qr_apply_q(s, ws, qf, Y, D, D);
+    for (int i = (int)Rf.size() - 1; i >= 0; --i) {
+      if (Rf[i].m > k) fill_rows_zero(s, Y, k, Rf[i].m, D, D);
+      qr_apply_q(s, ws, Rf[i], Y, D, D);
+    }
     transpose(s, Y, c, D, D, Vt, c);
-    gemm(s, m, D, m, 1.0, CMatView{Rk, m, 1, 0}, CMatView{Wt, 1, k, 0}, 0.0,
+    // U Sigma = L_1 (... (L_p (B W_D))): m x D
+    gemm(s, k, D, k, 1.0, CMatView{Rk, k, 1, 0}, CMatView{Wt, 1, k, 0}, 0.0,
          MatView{US, D, 1, 0});
-    qr_apply_q(s, ws, qf2, US, D, D);
+    for (int i = (int)Lf.size() - 1; i >= 0; --i) {
+      if (Lf[i].m > k) fill_rows_zero(s, US, k, Lf[i].m, D, D);
+      qr_apply_q(s, ws, Lf[i], US, D, D);
+    }
   } else if (m > c) {
     // US rows [0, c) hold U_R Sigma (leading dimension D): US = Q [U_R Sigma; 0]
     fill_rows_zero(s, US, c, m, D, D);

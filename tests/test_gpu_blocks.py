@@ -80,6 +80,29 @@ def test_svd_truncate_matches_lapack_and_rank_rule(B, m, c, cap, tol, decay):
     assert abs(disc - ref_disc) <= 1e-12 + 1e-8 * ref_disc
 
 
+@pytest.mark.parametrize("m,c,r", [(128, 128, 5), (256, 128, 1), (64, 128, 3), (100, 40, 0),
+                                   (96, 128, 60), (512, 128, 17)])
+def test_svd_truncate_rank_deficient(B, m, c, r):
+    """Numerically rank-deficient blocks (as in the TT-SVD of a separable
+    profile): the kept rows of Vt are orthonormal or exactly zero and the
+    product US Vt reproduces X."""
+    _say("svd rank-deficient %d x %d rank %d" % (m, c, r))
+    rng = np.random.default_rng(m + c + r)
+    X = rng.standard_normal((m, r)) @ rng.standard_normal((r, c)) if r else np.zeros((m, c))
+    Vt, US, sig, disc = B.svd_truncate(X, cap=0, tol=0.0)
+    Vt, US, sig = Vt.cpu().numpy(), US.cpu().numpy(), sig.cpu().numpy()
+    scale = max(np.abs(X).max(), 1e-300)
+    assert np.abs(US @ Vt - X).max() <= 1e-13 * scale * np.sqrt(max(m, c))
+    nz = np.abs(Vt).max(axis=1) > 0
+    assert nz.sum() >= r
+    if nz.any():
+        G = Vt[nz] @ Vt[nz].T
+        assert np.abs(G - np.eye(G.shape[0])).max() < 1e-12
+    if r:
+        s = np.linalg.svd(X, compute_uv=False)
+        assert np.abs(sig[:r] - s[:r]).max() <= 1e-13 * s[0] * np.sqrt(max(m, c))
+
+
 def _random_mps(n, chi, seed, decay=0.0):
     cores = wl.random_mps_cores(n, chi, seed=seed)
     if decay:
