@@ -509,7 +509,7 @@ void qr_factor(hipStream_t s, Arena& ws, double* A, int m, int n, long ld,
   f.k = std::min(m, n);
   f.panels.clear();
   g_stats.qr_calls++;
-  if (m <= 1024) {
+  if (m <= 2048) {
     // register-resident panels; the trailing columns are updated by the
     // reflector-application kernel
     for (int k0 = 0; k0 < f.k;) {

@@ -77,13 +77,20 @@ __device__ __forceinline__ void factor_block(double (&x)[RPL][CPW], int w,
         tj = (beta - alpha) / beta;
         scal = 1.0 / (alpha - beta);
       }
+      // The reflector goes to global memory now, or (32 rows per lane,
+      // where the row addresses would not fit in registers) stays below the
+      // diagonal of its column and is written out with R at the end.
 #pragma unroll
       for (int a = 0; a < RPL; ++a) {
         const int i = l + 64 * a;
         const double v = (i > j) ? x[a][B] * scal : (i == j ? 1.0 : 0.0);
         vj[i] = v;
-        if (i < m) V[(long)j * m + i] = v;
-        x[a][B] = (i == j) ? beta : (i > j ? 0.0 : x[a][B]);
+        if constexpr (RPL < 32) {
+          if (i < m) V[(long)j * m + i] = v;
+          x[a][B] = (i == j) ? beta : (i > j ? 0.0 : x[a][B]);
+        } else {
+          x[a][B] = (i == j) ? beta : (i > j ? v : x[a][B]);
+        }
       }
       if (l == 0) {
         tb[buf] = tj;
@@ -93,26 +100,46 @@ __device__ __forceinline__ void factor_block(double (&x)[RPL][CPW], int w,
     __syncthreads();
     const double tj = tb[buf];
     if (tj != 0.0) {
-      double v[RPL];
+      // the reflector is kept in registers unless the rows need 32 per
+      // lane; then it is streamed from LDS in chunks of 8 rows (the empty
+      // asm statements keep the compiler from hoisting all the loads)
+      constexpr bool kVReg = RPL < 32;
+      constexpr int CH = kVReg ? RPL : 8;
+      double v[kVReg ? RPL : 1];
+      if constexpr (kVReg) {
 #pragma unroll
-      for (int a = 0; a < RPL; ++a) v[a] = vj[l + 64 * a];
+        for (int a = 0; a < RPL; ++a) v[a] = vj[l + 64 * a];
+      }
       double p[NB];
 #pragma unroll
-      for (int q = 0; q < NB; ++q) {
-        double acc = 0.0;
+      for (int q = 0; q < NB; ++q) p[q] = 0.0;
 #pragma unroll
-        for (int a = 0; a < RPL; ++a) acc = fma(v[a], x[a][B + q], acc);
-        p[q] = acc;
+      for (int a0 = 0; a0 < RPL; a0 += CH) {
+        double vc[CH];
+#pragma unroll
+        for (int i = 0; i < CH; ++i) vc[i] = kVReg ? v[a0 + i] : vj[l + 64 * (a0 + i)];
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+#pragma unroll
+          for (int i = 0; i < CH; ++i) p[q] = fma(vc[i], x[a0 + i][B + q], p[q]);
+        if constexpr (!kVReg) __asm__ volatile("" ::: "memory");
       }
       // register column B of this wave is column j itself (w == t) or
-      // already finished (w < t)
+      // already finished (w < t); both hold reflectors below the diagonal
       if (w <= t) p[0] = 0.0;
       sums_any<NB>(p);
 #pragma unroll
-      for (int q = 0; q < NB; ++q) {
-        const double f = tj * p[q];
+      for (int q = 0; q < NB; ++q) p[q] *= tj;
 #pragma unroll
-        for (int a = 0; a < RPL; ++a) x[a][B + q] = fma(-v[a], f, x[a][B + q]);
+      for (int a0 = 0; a0 < RPL; a0 += CH) {
+        double vc[CH];
+#pragma unroll
+        for (int i = 0; i < CH; ++i) vc[i] = kVReg ? v[a0 + i] : vj[l + 64 * (a0 + i)];
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+#pragma unroll
+          for (int i = 0; i < CH; ++i) x[a0 + i][B + q] = fma(-vc[i], p[q], x[a0 + i][B + q]);
+        if constexpr (!kVReg) __asm__ volatile("" ::: "memory");
       }
     }
   }
@@ -140,12 +167,17 @@ __global__ __launch_bounds__(FT) void qr_reg_factor_kernel(
   // every wave has passed the first barrier, so A (which R may alias) has
   // been read completely
 #pragma unroll
-  for (int a = 0; a < RPL; ++a)
+  for (int b = 0; b < CPW; ++b) {
+    const int j = w + 16 * b;
+    if (j >= n) continue;
 #pragma unroll
-    for (int b = 0; b < CPW; ++b) {
-      const int i = l + 64 * a, j = w + 16 * b;
-      if (i < k && j < n) R[(long)i * ldr + j] = (i <= j) ? x[a][b] : 0.0;
+    for (int a = 0; a < RPL; ++a) {
+      const int i = l + 64 * a;
+      if (i < k) R[(long)i * ldr + j] = (i <= j) ? x[a][b] : 0.0;
+      if (RPL == 32 && j < k && i < m)
+        V[(long)j * m + i] = (i > j) ? x[a][b] : (i == j ? 1.0 : 0.0);
     }
+  }
 }
 
 template <int CPW, int RPL>
@@ -242,17 +274,20 @@ void launch_apply(hipStream_t s, const double* V, const double* tau, int m,
 }  // namespace
 
 // The register budget of 16 waves per CU is 128 VGPRs: at most 32 matrix
-// elements per lane, and 16 once the rows need 16 per lane (the reflector
-// and its prefetch take the rest).
+// elements per lane, 16 when the rows need 16 per lane (the reflector and
+// its prefetch take the rest), and one column of 32 rows per lane with the
+// reflector read from LDS.
+static int elems_per_lane(int rpl) { return rpl == 16 ? 16 : 32; }
+
 bool qr_reg_fits(int m, int n) {
-  if (m < 1 || n < 1 || m > 1024 || n > 128) return false;
+  if (m < 1 || n < 1 || m > 2048 || n > 128) return false;
   const int rpl = rows_per_lane(m), cpw = cols_per_wave(n);
-  return rpl * cpw <= (rpl == 16 ? 16 : 32);
+  return rpl * cpw <= elems_per_lane(rpl);
 }
 
 int qr_reg_panel_cols(int m) {
   const int rpl = rows_per_lane(m);
-  return 16 * std::min(8, (rpl == 16 ? 16 : 32) / rpl);
+  return 16 * std::min(8, elems_per_lane(rpl) / rpl);
 }
 
 void qr_reg_factor(hipStream_t s, const double* A, long lda, int m, int n,
@@ -266,7 +301,7 @@ void qr_reg_factor(hipStream_t s, const double* A, long lda, int m, int n,
   MPSV_F(1, 2) MPSV_F(2, 2) MPSV_F(4, 2) MPSV_F(8, 2)
   MPSV_F(1, 4) MPSV_F(2, 4) MPSV_F(4, 4) MPSV_F(8, 4)
   MPSV_F(1, 8) MPSV_F(2, 8) MPSV_F(4, 8)
-  MPSV_F(1, 16)
+  MPSV_F(1, 16) MPSV_F(1, 32)
   throw Error(kEinval, "qr_reg_factor: no kernel for this shape");
 #undef MPSV_F
   MPSV_LAUNCHED();
@@ -282,15 +317,15 @@ void qr_reg_factor(hipStream_t s, const double* A, long lda, int m, int n,
 void qr_reg_apply(hipStream_t s, const double* V, const double* tau, int m,
                   int k, double* Y, long ldy, int p, bool trans) {
   if (p <= 0 || k <= 0) return;
-  MPSV_CHECK(m >= 1 && m <= 1024 && k <= m, kEinval, "qr_reg_apply: bad shape");
+  MPSV_CHECK(m >= 1 && m <= 2048 && k <= m, kEinval, "qr_reg_apply: bad shape");
   const int rpl = rows_per_lane(m);
-  const int cpw = p >= 128 ? 2 : 1;
+  const int cpw = (p >= 128 && rpl < 32) ? 2 : 1;
   const int slot = prof_begin(s);
   const int tr = trans ? 1 : 0;
 #define MPSV_A(C, Rr)                                                   \
   if (cpw == C && rpl == Rr) launch_apply<C, Rr>(s, V, tau, m, k, Y, ldy, p, tr); else
   MPSV_A(1, 1) MPSV_A(2, 1) MPSV_A(1, 2) MPSV_A(2, 2) MPSV_A(1, 4) MPSV_A(2, 4)
-  MPSV_A(1, 8) MPSV_A(2, 8) MPSV_A(1, 16) MPSV_A(2, 16)
+  MPSV_A(1, 8) MPSV_A(2, 8) MPSV_A(1, 16) MPSV_A(2, 16) MPSV_A(1, 32)
   throw Error(kEinval, "qr_reg_apply: no kernel for this shape");
 #undef MPSV_A
   MPSV_LAUNCHED();

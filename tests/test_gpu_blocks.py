@@ -43,7 +43,8 @@ def test_gemm_matches_numpy(B, M, N, K):
 @pytest.mark.parametrize("m,n", [(1, 1), (5, 3), (3, 5), (40, 40), (130, 70), (257, 33),
                                  (600, 200), (2048, 8), (64, 300), (128, 128), (256, 128),
                                  (512, 64), (1024, 128), (1000, 100), (200, 129), (700, 700),
-                                 (65, 17), (2048, 40)])
+                                 (65, 17), (2048, 40), (1500, 300), (2048, 512),
+                                 (4000, 64)])
 def test_qr_is_orthogonal_factorisation(B, m, n):
     _say("qr %d x %d" % (m, n))
     A = wl.random_matrix(m, n, seed=m + 7 * n, decay=3.0)
@@ -61,7 +62,8 @@ def test_qr_is_orthogonal_factorisation(B, m, n):
 @pytest.mark.parametrize("m,c,cap,tol,decay", [
     (2, 2, 0, 0.0, 0), (10, 4, 0, 0.0, 0), (4, 10, 0, 0.0, 0), (64, 64, 0, 0.0, 6),
     (96, 96, 40, 0.0, 8), (128, 128, 64, 0.0, 8), (500, 128, 64, 0.0, 12),
-    (300, 60, 0, 1e-10, 14), (33, 90, 0, 1e-6, 10), (1024, 16, 8, 0.0, 2)])
+    (300, 60, 0, 1e-10, 14), (33, 90, 0, 1e-6, 10), (1024, 16, 8, 0.0, 2),
+    (2000, 128, 64, 0.0, 10), (60, 1500, 0, 1e-8, 6)])
 def test_svd_truncate_matches_lapack_and_rank_rule(B, m, c, cap, tol, decay):
     _say("svd %d x %d cap %d tol %g" % (m, c, cap, tol))
     X = wl.random_matrix(m, c, seed=3 * m + c, decay=decay)
