@@ -137,7 +137,16 @@ mps_status mps_add_scaled(mps_state* h, double alpha, const int32_t* bond_dims,
  * is capped at chi_max (for admission control).  Host output. */
 mps_status mps_workspace_bound(const mps_problem* p, size_t* bytes);
 
-/* Advance several independent states by nsteps each (same stream). */
+/* Advance several independent states (parameter sweeps, uneven sizes) by
+ * nsteps each.  Every instance runs on a stream of its own, driven by its
+ * own host thread (at most 16 at a time), so the factorisations of
+ * different instances occupy different compute units at once; the result
+ * of each instance is the same as stepping it alone.  The work is ordered
+ * after prior work on `stream`, and later work on `stream` waits for all
+ * instances.  A handle may appear only once (MPS_EINVAL otherwise).  On a
+ * failure the failing instance keeps the state of its last completed step,
+ * the others complete theirs, and the first failure (lowest index) is
+ * returned, its message naming the instance. */
 mps_status mps_step_batched(mps_state* const* hs, int32_t count, int32_t nsteps,
                             hipStream_t stream);
 

@@ -2,6 +2,10 @@
 // include/mps_blocks.h).  Converts engine exceptions into status codes and a
 // thread-local message; no exception crosses the boundary.
 #include <algorithm>
+#include <atomic>
+#include <exception>
+#include <thread>
+#include <algorithm>
 #include <climits>
 #include <cmath>
 #include <cstring>
@@ -275,9 +279,60 @@ mps_status mps_step_batched(mps_state* const* hs, int32_t count, int32_t nsteps,
                             hipStream_t stream) {
   return guarded([&] {
     MPSV_CHECK(hs != nullptr && count >= 0, mpsv::kEinval, "bad batch");
+    MPSV_CHECK(nsteps >= 0, mpsv::kEinval, "nsteps must be >= 0");
     for (int i = 0; i < count; ++i) check_handle(hs[i]);
-    for (int k = 0; k < nsteps; ++k)
-      for (int i = 0; i < count; ++i) hs[i]->eng->step(stream);
+    {
+      std::vector<const mps_state*> v(hs, hs + count);
+      std::sort(v.begin(), v.end());
+      MPSV_CHECK(std::adjacent_find(v.begin(), v.end()) == v.end(),
+                 mpsv::kEinval, "a batch must not list an instance twice");
+    }
+    if (count == 0 || nsteps == 0) return;
+    int dev = 0;
+    MPSV_HIP(hipGetDevice(&dev));
+    // Every instance runs on its own stream, driven by its own host thread
+    // (at most 16 at a time); the caller's stream is ordered before and
+    // after all of them.
+    hipEvent_t start;
+    MPSV_HIP(hipEventCreateWithFlags(&start, hipEventDisableTiming));
+    MPSV_HIP(hipEventRecord(start, stream));
+    for (int i = 0; i < count; ++i)
+      MPSV_HIP(hipStreamWaitEvent(hs[i]->eng->own_stream(), start, 0));
+    std::vector<std::exception_ptr> errs(count);
+    std::atomic<int> next{0};
+    auto worker = [&] {
+      (void)hipSetDevice(dev);
+      for (;;) {
+        const int i = next++;
+        if (i >= count) break;
+        try {
+          for (int k = 0; k < nsteps; ++k)
+            hs[i]->eng->step(hs[i]->eng->own_stream());
+        } catch (...) {
+          errs[i] = std::current_exception();
+        }
+      }
+    };
+    const int nt = std::min(count, 16);
+    std::vector<std::thread> pool;
+    for (int t = 0; t < nt; ++t) pool.emplace_back(worker);
+    for (auto& t : pool) t.join();
+    for (int i = 0; i < count; ++i) {
+      hipEvent_t done;
+      MPSV_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+      MPSV_HIP(hipEventRecord(done, hs[i]->eng->own_stream()));
+      MPSV_HIP(hipStreamWaitEvent(stream, done, 0));
+      MPSV_HIP(hipEventDestroy(done));
+    }
+    MPSV_HIP(hipEventDestroy(start));
+    for (int i = 0; i < count; ++i)
+      if (errs[i]) {
+        try {
+          std::rethrow_exception(errs[i]);
+        } catch (const mpsv::Error& e) {
+          throw mpsv::Error(e.code, "instance " + std::to_string(i) + ": " + e.what());
+        }
+      }
   });
 }
 

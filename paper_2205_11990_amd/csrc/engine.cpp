@@ -5,6 +5,8 @@
 // synchronisations inside a step are the read-back of each truncated rank
 // (the shapes of the following operations depend on it) and the final
 // finiteness check that makes a step transactional.
+#include <exception>
+#include <thread>
 #include "engine.hpp"
 
 #include <algorithm>
@@ -304,6 +306,12 @@ Engine::Engine(const Problem& p) : p_(p) {
              "unknown precision mode");
   MPSV_CHECK(std::isfinite(p.qm), kEinval, "q/m must be finite");
 
+  MPSV_HIP(hipGetDevice(&device_));
+  MPSV_HIP(hipStreamCreateWithFlags(&own_, hipStreamNonBlocking));
+  MPSV_HIP(hipStreamCreateWithFlags(&side_, hipStreamNonBlocking));
+  MPSV_HIP(hipEventCreateWithFlags(&ev_fork_, hipEventDisableTiming));
+  MPSV_HIP(hipEventCreateWithFlags(&ev_join_, hipEventDisableTiming));
+
   hipStream_t s = nullptr;
   std::vector<int> bdx, bvv, bt1, bg, bdv;
   auto Dx = ops::d1_periodic(p.Lx, p.dx(), bdx);
@@ -339,6 +347,23 @@ Engine::Engine(const Problem& p) : p_(p) {
   dflag_ = ops_.alloc_int(4);
   MPSV_HIP(hipDeviceSynchronize());
 }
+
+Engine::~Engine() {
+  // the side stream may still read buffers owned by the arenas
+  if (side_) (void)hipStreamSynchronize(side_);
+  if (own_) (void)hipStreamSynchronize(own_);
+  if (ev_fork_) (void)hipEventDestroy(ev_fork_);
+  if (ev_join_) (void)hipEventDestroy(ev_join_);
+  if (side_) (void)hipStreamDestroy(side_);
+  if (own_) (void)hipStreamDestroy(own_);
+}
+
+namespace {
+// Set on the side thread of Engine::rhs for its duration.
+thread_local Arena* tl_work = nullptr;
+}  // namespace
+
+Arena& Engine::work() { return tl_work ? *tl_work : work_; }
 
 DMpo Engine::upload_mpo(const std::vector<std::vector<double>>& W,
                         const std::vector<int>& bonds, Arena& ar,
@@ -381,8 +406,8 @@ void Engine::absorb_left(const VSite& v, const double* R, int p, double* M,
     }
     case VSite::kApply: {
       const int wl = v.W.wl, wr = v.W.wr, al = v.A.l, ar = v.A.r;
-      ArenaScope sc(work_);
-      double* X = work_.alloc((size_t)p * wl * 2 * ar);
+      ArenaScope sc(work());
+      double* X = work().alloc((size_t)p * wl * 2 * ar);
       // X[(p,b)][(i,a')] = sum_a R[p][(b,a)] A[a][i][a']
       gemm(s, p * wl, 2 * ar, al, 1.0, CMatView{R, al, 1, 0},
            CMatView{v.A.p, 2L * ar, 1, 0}, 0.0, MatView{X, 2L * ar, 1, 0});
@@ -433,14 +458,14 @@ void Engine::absorb_right(const VSite& v, const double* L, int q, double* N,
     }
     case VSite::kApply: {
       const int wl = v.W.wl, wr = v.W.wr, al = v.A.l, ar = v.A.r;
-      ArenaScope sc(work_);
+      ArenaScope sc(work());
       // Z[(a,i)][b'][q] = sum_a' A[a][i][a'] L[(b',a')][q]   (batch b')
-      double* Z = work_.alloc((size_t)al * 2 * wr * q);
+      double* Z = work().alloc((size_t)al * 2 * wr * q);
       gemm(s, 2 * al, q, ar, 1.0, CMatView{v.A.p, ar, 1, 0},
            CMatView{L, q, 1, (long)ar * q}, 0.0,
            MatView{Z, (long)wr * q, 1, q}, wr);
       // N'[a][(b,o)][q] = sum_(i,b') W[(b,o)][(i,b')] Z[a][(i,b')][q]
-      double* Np = work_.alloc((size_t)al * wl * 2 * q);
+      double* Np = work().alloc((size_t)al * wl * 2 * q);
       gemm(s, 2 * wl, q, 2 * wr, 1.0, CMatView{v.W.W, 2L * wr, 1, 0},
            CMatView{Z, q, 1, 2L * wr * q}, 0.0,
            MatView{Np, q, 1, 2L * wl * q}, al);
@@ -477,7 +502,7 @@ DMps Engine::compress_chain(const std::vector<VSite>& ch_in, int cap, double tol
   const int n = (int)ch_in.size();
   MPSV_CHECK(n >= 2, kEinval, "compression needs at least two sites");
   cap = cap_or_inf(cap);
-  ArenaScope sc(work_);
+  ArenaScope sc(work());
   // ---- right dense region.  Where the sites j..n-1 span no more indices
   // than the bond entering them (2^(n-j) <= r_(j-1)), that part of the
   // chain is contracted exactly into a dense block D (r_(j_R-1) x
@@ -492,11 +517,11 @@ DMps Engine::compress_chain(const std::vector<VSite>& ch_in, int cap, double tol
   std::vector<VSite> chv;
   const std::vector<VSite>* chp = &ch_in;
   if (jR <= n - 2) {
-    double* Lb = work_.alloc(1);
+    double* Lb = work().alloc(1);
     fill(s, Lb, 1, 1.0);
     int q = 1;
     for (int j = n - 1; j >= jR; --j) {
-      double* Nb = work_.alloc((size_t)ch_in[j].l * 2 * q);
+      double* Nb = work().alloc((size_t)ch_in[j].l * 2 * q);
       absorb_right(ch_in[j], Lb, q, Nb, s);
       Lb = Nb;
       q *= 2;
@@ -527,12 +552,12 @@ DMps Engine::compress_chain(const std::vector<VSite>& ch_in, int cap, double tol
   // ---- (i) QR sweep left to right.  A block with no more rows than
   // columns keeps Q = I (any orthogonal Q is a valid left-canonical gauge
   // and the identity is exact); taller blocks are Householder-factored.
-  double* R = work_.alloc(1);
+  double* R = work().alloc(1);
   fill(s, R, 1, 1.0);
   int p = 1;
   for (int j = 0; j < n - 1; ++j) {
     const int rows = 2 * p, cols = ch[j].r;
-    double* M = work_.alloc((size_t)rows * cols);
+    double* M = work().alloc((size_t)rows * cols);
     absorb_left(ch[j], R, p, M, s);
     fac[j].rows = rows;
     fac[j].cols = cols;
@@ -542,14 +567,14 @@ DMps Engine::compress_chain(const std::vector<VSite>& ch_in, int cap, double tol
       p = rows;
     } else {
       fac[j].ident = false;
-      qr_factor(s, work_, M, rows, cols, cols, fac[j].qf);
-      double* Rn = work_.alloc((size_t)cols * cols);
+      qr_factor(s, work(), M, rows, cols, cols, fac[j].qf);
+      double* Rn = work().alloc((size_t)cols * cols);
       extract_r(s, M, cols, cols, cols, Rn, cols);
       R = Rn;
       p = cols;
     }
   }
-  double* X = work_.alloc((size_t)p * 2);
+  double* X = work().alloc((size_t)p * 2);
   absorb_left(ch[n - 1], R, p, X, s);
   // ---- (ii) truncated SVD sweep right to left
   DMps res(n);
@@ -559,9 +584,9 @@ DMps Engine::compress_chain(const std::vector<VSite>& ch_in, int cap, double tol
     const int c = 2 * Dr;
     const int Dmax = std::min(std::min(cap, m), c);
     double* Vt = out.alloc((size_t)Dmax * c);
-    double* US = work_.alloc((size_t)m * Dmax);
+    double* US = work().alloc((size_t)m * Dmax);
     double dsc = 0.0;
-    const int D = svd_truncate(s, work_, X, m, c, c, cap, tol, Vt, US, nullptr,
+    const int D = svd_truncate(s, work(), X, m, c, c, cap, tol, Vt, US, nullptr,
                                &dsc);
     res[j] = Core{Vt, D, Dr};
     if (disc) (*disc)[j - 1] = dsc;
@@ -570,10 +595,10 @@ DMps Engine::compress_chain(const std::vector<VSite>& ch_in, int cap, double tol
       X = US;  // (2 p_{j-2}) x D = p_{j-2} x (2D)
     } else {
       // US is f.cols x D; pad to f.rows x D and apply Q
-      double* Y = work_.alloc((size_t)f.rows * D);
+      double* Y = work().alloc((size_t)f.rows * D);
       copy2d(s, f.cols, D, 1.0, US, D, Y, D);
       fill(s, Y + (long)f.cols * D, (long)(f.rows - f.cols) * D, 0.0);
-      qr_apply_q(s, work_, f.qf, Y, D, D);
+      qr_apply_q(s, work(), f.qf, Y, D, D);
       X = Y;
     }
     m = f.rows / 2;
@@ -718,8 +743,8 @@ DMps Engine::density(const DMps& g, Arena& ar, hipStream_t s) {
 // E = compress(-G n, D_F, tol)  (Problem Statement eqs. 2-3)
 DMps Engine::field(const DMps& g, Arena& ar, hipStream_t s) {
   // n lives below the compression's own workspace scope; E goes to `ar`
-  ArenaScope sc(work_);
-  DMps n = density(g, work_, s);
+  ArenaScope sc(work());
+  DMps n = density(g, work(), s);
   return apply_compress(gneg_, n, p_.df_max > 0 ? p_.df_max : INT_MAX, p_.tol,
                         ar, s);
 }
@@ -776,10 +801,42 @@ DMpo Engine::t2_mpo(const DMps& E, Arena& ar, hipStream_t s) {
 // k = R(g) = -v d/dx g - (q/m) E d/dv g  (eq. 1, C = 0)
 DMps Engine::rhs(const DMps& g, Arena& out, hipStream_t s) {
   ArenaScope sc(tmp_);
-  DMps E = field(g, tmp_, s);
-  DMpo W2 = t2_mpo(E, tmp_, s);
-  DMps T1 = apply_compress(t1_, g, cap_for(5), p_.tol, tmp_, s);
-  DMps T2 = apply_compress(W2, g, cap_for(5), p_.tol, tmp_, s);
+  ArenaScope sc2(tmp2_);
+  // The two terms share only their input g.  T1 = -(Dx V) g is compressed
+  // on the side stream by a second host thread (each factorisation of the
+  // sweep occupies one workgroup, so the two sweeps run side by side on
+  // the chip) while this thread computes the field and compresses T2.
+  MPSV_HIP(hipEventRecord(ev_fork_, s));
+  MPSV_HIP(hipStreamWaitEvent(side_, ev_fork_, 0));
+  DMps T1;
+  std::exception_ptr side_err;
+  std::thread side([&] {
+    (void)hipSetDevice(device_);
+    tl_work = &work2_;
+    try {
+      T1 = apply_compress(t1_, g, cap_for(5), p_.tol, tmp2_, side_);
+      MPSV_HIP(hipEventRecord(ev_join_, side_));
+    } catch (...) {
+      side_err = std::current_exception();
+    }
+    tl_work = nullptr;
+  });
+  DMps T2;
+  try {
+    DMps E = field(g, tmp_, s);
+    DMpo W2 = t2_mpo(E, tmp_, s);
+    T2 = apply_compress(W2, g, cap_for(5), p_.tol, tmp_, s);
+  } catch (...) {
+    side.join();
+    (void)hipStreamSynchronize(side_);
+    throw;
+  }
+  side.join();
+  if (side_err) {
+    (void)hipStreamSynchronize(side_);
+    std::rethrow_exception(side_err);
+  }
+  MPSV_HIP(hipStreamWaitEvent(s, ev_join_, 0));
   return add_terms({{1.0, &T1}, {1.0, &T2}}, cap_for(4), out, s);
 }
 
@@ -834,7 +891,7 @@ void Engine::init_from_profiles(int rank, const double* ax, const double* bv,
   // X = u as 2^(L-1) x 2, SVD, keep V^T as the last core, carry U S.
   auto tt = [&](const double* u, int L) {
     DMps m(L);
-    double* X = work_.alloc((size_t)1 << L);
+    double* X = work().alloc((size_t)1 << L);
     MPSV_HIP(hipMemcpyAsync(X, u, sizeof(double) * ((size_t)1 << L),
                             hipMemcpyDeviceToDevice, s));
     int rows = 1 << (L - 1), Dr = 1;
@@ -842,8 +899,8 @@ void Engine::init_from_profiles(int rank, const double* ax, const double* bv,
       const int c = 2 * Dr;
       const int Dmax = std::min(rows, c);
       double* Vt = step_.alloc((size_t)Dmax * c);
-      double* US = work_.alloc((size_t)rows * Dmax);
-      const int D = svd_truncate(s, work_, X, rows, c, c, INT_MAX,
+      double* US = work().alloc((size_t)rows * Dmax);
+      const int D = svd_truncate(s, work(), X, rows, c, c, INT_MAX,
                                  std::min(p_.tol, 1e-14) , Vt, US, nullptr,
                                  nullptr);
       m[j] = Core{Vt, D, Dr};
@@ -859,7 +916,7 @@ void Engine::init_from_profiles(int rank, const double* ax, const double* bv,
   };
   std::vector<DMps> terms;
   {
-    ArenaScope sc(work_);
+    ArenaScope sc(work());
     for (int r = 0; r < rank; ++r) {
       DMps mx = tt(ax + (long)r * p_.Nx(), p_.Lx);
       DMps mv = tt(bv + (long)r * p_.Nv(), p_.Lv);

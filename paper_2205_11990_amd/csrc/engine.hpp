@@ -58,7 +58,9 @@ struct StepTimers {
 class Engine {
  public:
   explicit Engine(const Problem& p);
-  ~Engine() = default;
+  ~Engine();
+  Engine(const Engine&) = delete;
+  Engine& operator=(const Engine&) = delete;
 
   const Problem& problem() const { return p_; }
   int n() const { return p_.n(); }
@@ -79,6 +81,9 @@ class Engine {
 
   // ---- the hot path
   void step(hipStream_t s);
+  // A stream owned by this instance (batched stepping runs each instance on
+  // its own stream).
+  hipStream_t own_stream() const { return own_; }
 
   // ---- outputs
   void to_dense(double* out, hipStream_t s);
@@ -114,6 +119,9 @@ class Engine {
   double full_contract(const DMps& g, const DMps& f, hipStream_t s);
   void dense_of(const DMps& a, double* out, hipStream_t s);
   int cap_for(int point) const;
+  // Compression workspace of the calling thread: work_ on the thread that
+  // drives the engine, work2_ on the side thread of rhs().
+  Arena& work();
 
   Problem p_;
   Arena ops_{(size_t)16 << 20};    // operators (persistent)
@@ -121,6 +129,12 @@ class Engine {
   Arena step_;                     // per-step intermediates
   Arena tmp_;                      // per-RHS intermediates
   Arena work_;                     // per-compression workspace
+  Arena tmp2_;                     // per-RHS intermediates of the side lane
+  Arena work2_;                    // compression workspace of the side lane
+  int device_ = 0;                 // the device the instance lives on
+  hipStream_t own_ = nullptr;      // this instance's stream (batched mode)
+  hipStream_t side_ = nullptr;     // T1 runs here, beside T2
+  hipEvent_t ev_fork_ = nullptr, ev_join_ = nullptr;
   DMpo t1_, gneg_, dv_;            // T1 chain, -G (x sites), Dv (v sites)
   DMps vpoly_, v2poly_;            // moment weights (full chain)
   DMps f_;

@@ -19,6 +19,7 @@
 // relative discarded weight is <= tol) (eq. 5 with the i = D+1 reading), and
 // Vt (D x k) holds the kept right singular vectors (normalised columns).
 #include <cmath>
+#include <mutex>
 
 #include "jacobi.hpp"
 
@@ -256,8 +257,6 @@ __global__ __launch_bounds__(JT) void jacobi_cols_kernel(
   }
 }
 
-bool g_attr = false;
-
 }  // namespace
 
 size_t jacobi_lds_bytes(int k) {
@@ -267,12 +266,12 @@ size_t jacobi_lds_bytes(int k) {
 void jacobi_svd(hipStream_t s, const double* Xr, int k, long ldx, int cap,
                 double tol, int max_sweeps, double* Vt, double* sigbuf,
                 int* perm, double* info) {
-  if (!g_attr) {
+  static std::once_flag once;
+  std::call_once(once, [] {
     MPSV_HIP(hipFuncSetAttribute((const void*)jacobi_cols_kernel,
                                  hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)kJacobiMaxLds));
-    g_attr = true;
-  }
+  });
   const size_t lds = jacobi_lds_bytes(k);
   MPSV_CHECK(lds <= kJacobiMaxLds && k <= kJacobiMaxCols && k >= 1, kEinval,
              "Jacobi SVD: matrix does not fit on chip");

@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <map>
 #include <mutex>
 
 #include "gemm.hpp"
@@ -408,25 +409,28 @@ __global__ __launch_bounds__(NT) void jacobi_svd_kernel(
   }
 }
 
-void* g_pinned = nullptr;
+// Pinned host words for the rank read-back, one block per stream (several
+// host threads may run sweeps on different streams at once).
 std::mutex g_pinned_mu;
+std::map<hipStream_t, double*> g_pinned;
 
-double* pinned_info() {
+double* pinned_info(hipStream_t s) {
   std::lock_guard<std::mutex> lk(g_pinned_mu);
-  if (!g_pinned) MPSV_HIP(hipHostMalloc(&g_pinned, 4096, hipHostMallocDefault));
-  return (double*)g_pinned;
+  double*& p = g_pinned[s];
+  if (!p) MPSV_HIP(hipHostMalloc((void**)&p, 4096, hipHostMallocDefault));
+  return p;
 }
 
-bool g_attr_done = false;
+std::once_flag g_attr_once;
 void set_attrs() {
-  if (g_attr_done) return;
-  MPSV_HIP(hipFuncSetAttribute((const void*)qr_panel_kernel,
-                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)kPanelLds));
-  MPSV_HIP(hipFuncSetAttribute((const void*)jacobi_svd_kernel,
-                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)kJacobiLds));
-  g_attr_done = true;
+  std::call_once(g_attr_once, [] {
+    MPSV_HIP(hipFuncSetAttribute((const void*)qr_panel_kernel,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)kPanelLds));
+    MPSV_HIP(hipFuncSetAttribute((const void*)jacobi_svd_kernel,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)kJacobiLds));
+  });
 }
 
 }  // namespace
@@ -692,7 +696,7 @@ int svd_truncate(hipStream_t s, Arena& ws, double* X, int m, int c, long ldx,
     prof_end(s, slot, kClsJacobi, 6.0 * mm * nn * nn + 20.0 * nn * nn * nn,
              8.0 * (2.0 * m * c + 2.0 * nn * nn));
   }
-  double* h = pinned_info();
+  double* h = pinned_info(s);
   MPSV_HIP(hipMemcpyAsync(h, info, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
   MPSV_HIP(hipStreamSynchronize(s));
   const int D = (int)h[0];

@@ -1,6 +1,7 @@
 // FP64 factorisations used by the MPS compression sweeps:
 // blocked Householder QR and one-sided Jacobi SVD with an on-device rank rule.
 #pragma once
+#include <atomic>
 #include <vector>
 
 #include "arena.hpp"
@@ -54,7 +55,7 @@ int svd_truncate(hipStream_t s, Arena& ws, double* X, int m, int c, long ldx,
 
 // Device-side counters of the last factorisations (for diagnostics/tests).
 struct LinalgStats {
-  long qr_calls = 0, svd_calls = 0, jacobi_sweeps = 0;
+  std::atomic<long> qr_calls{0}, svd_calls{0}, jacobi_sweeps{0};
 };
 LinalgStats& linalg_stats();
 

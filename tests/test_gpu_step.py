@@ -165,13 +165,18 @@ def test_checkpoint_resume_is_bitwise(B):
 
 
 def test_batched_equals_solo(B):
+    """Uneven instances (grid, chi, k, alpha from the seeded sweep) stepped
+    together, each on its own stream and host thread, give bit-identical
+    states to stepping each alone."""
     _say("batched")
-    ws = wl.landau_sweep(count=3, seed=2205)
+    ws = wl.landau_sweep(count=6, seed=2205)
     solo, batch = [], []
-    for w in ws:
-        w.problem.Lx = w.problem.Lv = 6
+    for i, w in enumerate(ws):
+        L = 5 + (i % 3)
+        w.problem.Lx = w.problem.Lv = L
         w.problem.dt = 0.05
-        ax, bv = wl.landau_profiles(w.problem, 0.5, 0.01)
+        w.problem.chi_max = (8, 12, 16)[i % 3]
+        ax, bv = wl.landau_profiles(w.problem, 0.5, 0.01 * (i + 1))
         s1 = B.MpsState(w.problem, ax, bv)
         s1.step(2)
         solo.append(s1.to_dense().cpu().numpy())
@@ -179,6 +184,9 @@ def test_batched_equals_solo(B):
     B.step_batched(batch, 2)
     for s, b in zip(solo, batch):
         assert np.array_equal(s, b.to_dense().cpu().numpy())
+    with pytest.raises(B.MpsError) as e:
+        B.step_batched([batch[0], batch[1], batch[0]], 1)
+    assert e.value.status == B.MPS_EINVAL
 
 
 def test_errors_leave_state_unchanged(B):
