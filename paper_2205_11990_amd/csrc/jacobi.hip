@@ -1,18 +1,31 @@
 // One-sided (Hestenes) Jacobi SVD of a small square triangular factor on
-// one workgroup of 1024 threads.  The rotations act on the columns of
-// B = R^T; they converge to v_i sigma_i, the right singular vectors of the
-// matrix R came from, scaled by its singular values.  Working on the
-// transpose of the triangular factor needs far fewer sweeps than working on
-// the factor itself (about 9 against 22 on the matrices of the compression
-// sweep).  The rotations themselves are not accumulated: the caller forms
-// the left factor as X V (one GEMM), so the kernel keeps only B on chip.
+// one workgroup.  The rotations act on the columns of B = R^T; they
+// converge to v_i sigma_i, the right singular vectors of the matrix R came
+// from, scaled by its singular values.  Working on the transpose of the
+// triangular factor needs far fewer sweeps than working on the factor
+// itself (about 9 against 22 on the matrices of the compression sweep).
+// The rotations themselves are not accumulated: the caller forms the left
+// factor as X V (one GEMM), so the kernel keeps only B on chip.
 //
-// Columns are orthogonalised pairwise in the cyclic round-robin ordering:
-// each round pairs all columns into disjoint pairs; a group of 16 lanes (one
-// DPP row) owns one pair, accumulates the three inner products over its
-// rows, reduces them with row-local DPP moves and applies the rotation.
-// The columns live in LDS with an odd leading dimension so that the groups
-// of one wave hit distinct banks.
+// Layout: the columns are held in registers.  A node is one DPP row of 16
+// lanes; it owns two columns (a, b), 16 * RPT rows each, RPT per lane.  Each
+// step orthogonalises the pair of every node at once (inner products
+// reduced with row-local DPP moves), then columns move between nodes.
+//
+// Ordering: a hypercube ordering of the N = 2^d nodes that meets every pair
+// exactly once per sweep in 2N - 1 steps, built recursively: pair all
+// columns inside each half-cube, exchange one column per node across the
+// top dimension so that every node holds one column of each half, then
+// let the second columns walk through the cube along a Gray code (one
+// dimension per step), which brings every column of one half next to every
+// column of the other.  Node bits 0 and 1 select the DPP row inside a wave,
+// so moves along those dimensions are register swaps between rows
+// (permlane16/32 swaps); only moves along the wave bits go through LDS.  At
+// 128 columns 96 of the 126 moves of a sweep stay in registers.
+//
+// Squared column norms are carried with the columns and updated with each
+// rotation.  Columns below 1e-15 of the Frobenius norm are numerical zeros
+// and are never rotated.
 //
 // On exit: singular values are the column norms, sorted descending (ties by
 // index), the truncation rank D follows the rule min(cap, smallest D' whose
@@ -22,174 +35,232 @@
 #include <mutex>
 
 #include "jacobi.hpp"
+#include "wave.hpp"
 
 namespace mpsv {
 
 namespace {
 
-constexpr int JT = 1024;
-constexpr int G = 16;    // lanes per column pair (one DPP row)
-constexpr int RPT = 8;   // rows per lane: 16 * 8 = 128 rows
+constexpr int MAXT = 1024;  // 64 nodes of 16 lanes
 
-struct Pairing {
-  int cc, np;
-};
-
-__device__ inline Pairing make_pairing(int c) {
-  Pairing P;
-  P.cc = c + (c & 1);
-  P.np = P.cc / 2;
-  return P;
+// Rotation that orthogonalises columns with Gram [[a,g],[g,b]] (Rutishauser's
+// formulas): t = tan(theta) is the smaller root of t^2 + 2 z t - 1 = 0 with
+// z = (b - a) / (2g), cs = 1 / sqrt(1 + t^2), sn = cs t.  The rotation is
+// orthogonal whatever t is, so t comes from the hardware estimates (about
+// 5e-8 relative, which only leaves a residual cosine of that order times
+// the one removed, cleaned up by the following sweeps); cs must satisfy
+// cs^2 + sn^2 = 1 to rounding and is refined by two Newton steps.
+__device__ inline void rotation(double a, double b, double g, double& cs,
+                                double& sn) {
+  const double z = (b - a) * __builtin_amdgcn_rcp(2.0 * g);
+  const double az = fabs(z);
+  double t;
+  if (az > 1e150) t = 0.5 * __builtin_amdgcn_rcp(z);
+  else t = copysign(__builtin_amdgcn_rcp(az + __builtin_amdgcn_sqrt(fma(z, z, 1.0))), z);
+  const double w = fma(t, t, 1.0);
+  double y = __builtin_amdgcn_rsq(w);
+  y = fma(y, 0.5 * fma(-w * y, y, 1.0), y);
+  y = fma(y, 0.5 * fma(-w * y, y, 1.0), y);
+  cs = y;
+  sn = y * t;
 }
 
-__device__ inline void pair_of(int r, int k, int cc, int& p, int& q) {
-  if (k == 0) {
-    p = cc - 1;
-    q = r;
+// Value of the same lane in the DPP row (node) row ^ (1 << DIM), DIM < 2.
+template <int DIM>
+__device__ inline int row_swap(int v, int row) {
+  if constexpr (DIM == 0) {
+    const auto o = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    return (row & 1) ? o[0] : o[1];
   } else {
-    p = (r + k) % (cc - 1);
-    q = (r - k + cc - 1) % (cc - 1);
+    const auto o = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return (row & 2) ? o[0] : o[1];
   }
 }
 
-template <int CTRL>
-__device__ inline double dpp(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+template <int DIM>
+__device__ inline double row_swap(double v, int row) {
+  const int lo = row_swap<DIM>(__double2loint(v), row);
+  const int hi = row_swap<DIM>(__double2hiint(v), row);
   return __hiloint2double(hi, lo);
 }
 
-// Sum over an aligned group of 16 lanes (one DPP row); every lane gets it.
-__device__ inline double sum16(double v) {
-  v += dpp<0xB1>(v);   // quad_perm [1,0,3,2]
-  v += dpp<0x4E>(v);   // quad_perm [2,3,0,1]
-  v += dpp<0x141>(v);  // row_half_mirror
-  v += dpp<0x140>(v);  // row_mirror
-  return v;
-}
+// A column travelling between nodes: data, squared norm and column index.
+template <int RPT>
+struct Col {
+  double v[RPT];
+  double n;
+  int id;
+};
 
-// 1/x from the hardware estimate refined by two Newton steps.
-__device__ inline double rcp_nr(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  r = fma(r, fma(-x, r, 1.0), r);
-  r = fma(r, fma(-x, r, 1.0), r);
-  return r;
-}
-
-// Rutishauser's rotation that orthogonalises columns with Gram [[a,g],[g,b]].
-__device__ inline void rotation(double a, double b, double g, double& cs,
-                                double& sn) {
-  const double z = (b - a) * rcp_nr(2.0 * g);
-  const double az = fabs(z);
-  double t;
-  if (z == 0.0) t = 1.0;
-  else if (az > 1e150) t = 0.5 * rcp_nr(z);
-  else t = copysign(rcp_nr(az + sqrt(fma(z, z, 1.0))), z);
-  cs = rcp_nr(sqrt(fma(t, t, 1.0)));
-  sn = cs * t;
-}
-
-__device__ inline double block_sum(double v, double* red) {
+// The column `send` of node x goes to node x ^ (1 << dim); returns the one
+// arriving from there.  Along wave bits it passes through the LDS buffer
+// `xb` (one barrier), along row bits through registers.
+template <int DIM, int RPT>
+__device__ inline void swap_rows(const Col<RPT>& send, Col<RPT>& recv, int row) {
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double t = 0.0;
-  for (int i = 0; i < JT / 64; ++i) t += red[i];
-  return t;
+  for (int r = 0; r < RPT; ++r) recv.v[r] = row_swap<DIM>(send.v[r], row);
+  recv.n = row_swap<DIM>(send.n, row);
+  recv.id = row_swap<DIM>(send.id, row);
 }
 
-// info: [0] D, [1] discarded weight, [2] sweeps, [3] converged, [4] rounds
-// Xr: k x k row-major triangular factor; the Jacobi columns are its rows:
-// A[j][i] = Xr[j][i].  Output Vt[d][i] = A[perm d][i] / sigma_d.
-__global__ __launch_bounds__(JT) void jacobi_cols_kernel(
-    const double* __restrict__ Xr, int k, long ldx, int max_sweeps, int cap,
-    double tol, double* __restrict__ Vt, double* __restrict__ sigbuf,
+template <int RPT>
+__device__ inline void exchange(const Col<RPT>& send, Col<RPT>& recv, int dim,
+                                int x, int row, int lig, int N, int& par,
+                                double* xb, double* xn, int* xi) {
+  if (dim == 0) {
+    swap_rows<0, RPT>(send, recv, row);
+    return;
+  }
+  if (dim == 1) {
+    swap_rows<1, RPT>(send, recv, row);
+    return;
+  }
+  const int pb = par;
+  par ^= 1;
+  double* dst = xb + (long)(pb * N + x) * RPT * 16;
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) dst[r * 16 + lig] = send.v[r];
+  if (lig == 0) {
+    xn[pb * 64 + x] = send.n;
+    xi[pb * 64 + x] = send.id;
+  }
+  __syncthreads();
+  const int y = x ^ (1 << dim);
+  const double* src = xb + (long)(pb * N + y) * RPT * 16;
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) recv.v[r] = src[r * 16 + lig];
+  recv.n = xn[pb * 64 + y];
+  recv.id = xi[pb * 64 + y];
+}
+
+// info: [0] D, [1] discarded weight, [2] sweeps, [3] converged, [4] steps
+// Xr: k x k row-major triangular factor; the Jacobi columns are its rows.
+// Output Vt[d][i] = column perm(d) / sigma_d.
+template <int RPT>
+__global__ __launch_bounds__(MAXT) void jacobi_hc_kernel(
+    const double* __restrict__ Xr, int k, long ldx, int d, int max_sweeps,
+    int cap, double tol, double* __restrict__ Vt, double* __restrict__ sigbuf,
     int* __restrict__ perm_out, double* __restrict__ info) {
   extern __shared__ double smem[];
-  __shared__ double red[JT / 64];
+  __shared__ double red[MAXT / 64];
+  __shared__ double xn[2 * 64];
+  __shared__ int xi[2 * 64];
   __shared__ int sweep_any;
   __shared__ int Dsh;
-  const int tid = threadIdx.x;
-  const int nrow = k, ncol = k;            // Jacobi matrix A = Xr^T
-  const int lda = nrow | 1;
-  double* A = smem;                        // A[j*lda + i]
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int x = tid >> 4, lig = tid & 15, row = x & 3;
+  const int N = 1 << d;
 
-  for (long e = tid; e < (long)ncol * nrow; e += JT) {
-    const long j = e / nrow, i = e % nrow;
-    A[j * lda + i] = Xr[j * ldx + i];
+  // node x starts with columns 2x and 2x+1; indices >= k are zero padding
+  Col<RPT> A, B;
+  A.id = 2 * x;
+  B.id = 2 * x + 1;
+  double sa = 0.0, sb = 0.0;
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    const int i = lig + 16 * r;
+    A.v[r] = (A.id < k && i < k) ? Xr[(long)A.id * ldx + i] : 0.0;
+    B.v[r] = (B.id < k && i < k) ? Xr[(long)B.id * ldx + i] : 0.0;
+    sa = fma(A.v[r], A.v[r], sa);
+    sb = fma(B.v[r], B.v[r], sb);
   }
+  A.n = wave::sum16(sa);
+  B.n = wave::sum16(sb);
+  // Frobenius norm of the whole matrix; the columns are scaled to unit
+  // Frobenius norm (undone on the singular values at the end), so that the
+  // products below neither overflow nor underflow
+  double part = (lig == 0) ? A.n + B.n : 0.0;
+  part = wave::sum64(part);
+  if ((tid & 63) == 0) red[tid >> 6] = part;
   __syncthreads();
-  double part = 0.0;
-  for (long e = tid; e < (long)ncol * nrow; e += JT) {
-    const long j = e / nrow, i = e % nrow;
-    const double x = A[j * lda + i];
-    part += x * x;
+  double normF2 = 0.0;
+  for (int w = 0; w < nthr / 64; ++w) normF2 += red[w];
+  const double scale = normF2 > 0.0 ? 1.0 / sqrt(normF2) : 1.0;
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    A.v[r] *= scale;
+    B.v[r] *= scale;
   }
-  const double normF2 = block_sum(part, red);
-  // Columns whose squared norm is below `negl` (sigma below 1e-15 of the
-  // Frobenius norm) are numerical zeros: they are never rotated (rotating
-  // them against the others only stirs rounding noise and can stall the
-  // convergence to a linear rate), and their singular vectors are returned
-  // as zero rows, so that the kept rows of Vt are orthonormal and X V_D is
-  // a projection that misses at most that noise.
-  const double negl = 1e-30 * normF2;
-  // A pair is rotated when its cosine |g| / (|a_p| |a_q|) exceeds eps.  The
+  A.n *= scale * scale;
+  B.n *= scale * scale;
+  const double negl = 1e-30;
+  // A pair is rotated when its cosine |g| / (|a| |b|) exceeds eps.  The
   // iteration stops after the first sweep in which no cosine exceeded conv
   // (its rotations are still applied).  Cyclic Jacobi converges
   // quadratically: once every rotation angle of a sweep is below conv, the
   // rotations that follow the visit of a pair can restore at most about
-  // 2k conv^2 < 3e-14 of its cosine, so the extra sweep that would only
-  // confirm convergence is skipped.  The threshold also tolerates pairs that
+  // 2k conv^2 < 3e-14 of its cosine, so the sweep that would only confirm
+  // convergence is skipped.  The threshold also tolerates pairs that
   // stagnate at rounding level near the numerical null space.
-  const double eps = 1e-14, conv = 1e-8;
+  const double eps2 = 1e-28, conv2 = 1e-16;
 
-  const Pairing P = make_pairing(ncol);
-  const int kk = tid / G, lig = tid % G;   // pair slot of this lane group
-  int sweep = 0, converged = 0, rounds = 0;
+  // Squared norms follow the rotation by formula; where one of them falls
+  // below 1e-8 of the pair's total (its rounding error could then exceed
+  // 1e-8 of it) the column norms are recomputed instead.
+  auto pair_step = [&]() {
+    double g = 0.0;
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) g = fma(A.v[r], B.v[r], g);
+    g = wave::sum16(g);
+    const double ab = A.n * B.n, g2 = g * g;
+    const bool rot = g2 > eps2 * ab && fmin(A.n, B.n) > negl;
+    if (rot) {  // uniform over the 16 lanes of the node
+      double cs, sn;
+      rotation(A.n, B.n, g, cs, sn);
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) {
+        const double u = A.v[r], v = B.v[r];
+        A.v[r] = cs * u - sn * v;
+        B.v[r] = sn * u + cs * v;
+      }
+      // the new squared norms of the rotated pair, exact in exact
+      // arithmetic for the cs, sn applied
+      const double c2 = cs * cs, s2 = sn * sn, csg = 2.0 * cs * sn * g;
+      const double na = fma(c2, A.n, fma(s2, B.n, -csg));
+      const double nb = fma(s2, A.n, fma(c2, B.n, csg));
+      if (fmin(na, nb) < 1e-8 * (A.n + B.n)) {
+        double sa2 = 0.0, sb2 = 0.0;
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+          sa2 = fma(A.v[r], A.v[r], sa2);
+          sb2 = fma(B.v[r], B.v[r], sb2);
+        }
+        A.n = wave::sum16(sa2);
+        B.n = wave::sum16(sb2);
+      } else {
+        A.n = na;
+        B.n = nb;
+      }
+      if (lig == 0 && g2 > conv2 * ab) sweep_any = 1;
+    }
+  };
+
+  double* xb = smem;
+  int par = 0;
+  int sweep = 0, converged = 0, steps = 0;
+  Col<RPT> R;
   for (; sweep < max_sweeps; ++sweep) {
     if (tid == 0) sweep_any = 0;
     __syncthreads();
-    for (int r = 0; r < P.cc - 1; ++r, ++rounds) {
-      int p = 0, q = 0;
-      if (kk < P.np) pair_of(r, kk, P.cc, p, q);
-      if (kk < P.np && p < ncol && q < ncol) {
-        double* ap = A + (long)p * lda;
-        double* aq = A + (long)q * lda;
-        double x[RPT], y[RPT];
-#pragma unroll
-        for (int rr = 0; rr < RPT; ++rr) {
-          const int i = lig + G * rr;
-          x[rr] = (i < nrow) ? ap[i] : 0.0;
-          y[rr] = (i < nrow) ? aq[i] : 0.0;
-        }
-        double a = 0.0, b = 0.0, g = 0.0;
-#pragma unroll
-        for (int rr = 0; rr < RPT; ++rr) {
-          a = fma(x[rr], x[rr], a);
-          b = fma(y[rr], y[rr], b);
-          g = fma(x[rr], y[rr], g);
-        }
-        a = sum16(a);
-        b = sum16(b);
-        g = sum16(g);
-        double cs = 1.0, sn = 0.0;
-        const bool rot = g != 0.0 && fabs(g) > eps * sqrt(a) * sqrt(b) && fmin(a, b) > negl;
-        if (rot) {
-          rotation(a, b, g, cs, sn);
-#pragma unroll
-          for (int rr = 0; rr < RPT; ++rr) {
-            const int i = lig + G * rr;
-            if (i < nrow) {
-              ap[i] = cs * x[rr] - sn * y[rr];
-              aq[i] = sn * x[rr] + cs * y[rr];
-            }
-          }
-          if (lig == 0 && fabs(g) > conv * sqrt(a) * sqrt(b)) sweep_any = 1;
-        }
+    pair_step();
+    ++steps;
+    for (int l = 1; l <= d; ++l) {
+      // across dimension l-1: nodes of the lower half give b, those of the
+      // upper half give a, so afterwards a holds lower-half columns and b
+      // upper-half columns everywhere
+      const int dim = l - 1;
+      const bool up = (x >> dim) & 1;
+      exchange<RPT>(up ? A : B, R, dim, x, row, lig, N, par, xb, xn, xi);
+      if (up) A = R; else B = R;
+      pair_step();
+      ++steps;
+      // the b columns walk along a Gray code over the l lower dimensions
+      for (int t = 1; t < (1 << l); ++t) {
+        exchange<RPT>(B, R, __builtin_ctz(t), x, row, lig, N, par, xb, xn, xi);
+        B = R;
+        pair_step();
+        ++steps;
       }
-      __syncthreads();
     }
     __syncthreads();
     if (sweep_any == 0) {
@@ -200,30 +271,51 @@ __global__ __launch_bounds__(JT) void jacobi_cols_kernel(
     __syncthreads();
   }
 
-  // singular values = column norms (scratch half of sigbuf), rank-sorted
-  for (int j = tid; j < ncol; j += JT) {
-    double s2 = 0.0;
-    const double* aj = A + (long)j * lda;
-    for (int i = 0; i < nrow; ++i) s2 += aj[i] * aj[i];
-    sigbuf[ncol + j] = sqrt(s2);
+  // columns back into LDS by index: M[j][i], odd leading dimension
+  __syncthreads();
+  const int lda = k | 1;
+  double* M = smem;
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    const int i = lig + 16 * r;
+    if (i < k) {
+      if (A.id < k) M[(long)A.id * lda + i] = A.v[r] / scale;
+      if (B.id < k) M[(long)B.id * lda + i] = B.v[r] / scale;
+    }
+  }
+  {
+    // exact final norms, in the units of the input
+    double sa2 = 0.0, sb2 = 0.0;
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      sa2 = fma(A.v[r], A.v[r], sa2);
+      sb2 = fma(B.v[r], B.v[r], sb2);
+    }
+    sa2 = wave::sum16(sa2);
+    sb2 = wave::sum16(sb2);
+    const double inv = 1.0 / scale;
+    if (lig == 0) {
+      if (A.id < k) sigbuf[k + A.id] = sqrt(sa2) * inv;
+      if (B.id < k) sigbuf[k + B.id] = sqrt(sb2) * inv;
+    }
   }
   __syncthreads();
-  for (int j = tid; j < ncol; j += JT) {
-    const double sj = sigbuf[ncol + j];
+  // rank-sort the singular values (ties by index)
+  for (int j = tid; j < k; j += nthr) {
+    const double sj = sigbuf[k + j];
     int rank = 0;
-    for (int q = 0; q < ncol; ++q) {
-      const double sq = sigbuf[ncol + q];
+    for (int q = 0; q < k; ++q) {
+      const double sq = sigbuf[k + q];
       rank += (sq > sj || (sq == sj && q < j)) ? 1 : 0;
     }
     perm_out[rank] = j;
     sigbuf[rank] = sj;
   }
   __syncthreads();
-  const int kmax = ncol;
   if (tid == 0) {
     double tot = 0.0;
-    for (int i = 0; i < ncol; ++i) tot += sigbuf[i] * sigbuf[i];
-    const int capd = cap < kmax ? cap : kmax;
+    for (int i = 0; i < k; ++i) tot += sigbuf[i] * sigbuf[i];
+    const int capd = cap < k ? cap : k;
     int D;
     if (tot <= 0.0) {
       D = 1;
@@ -233,8 +325,8 @@ __global__ __launch_bounds__(JT) void jacobi_cols_kernel(
       // smallest D' >= 1 whose discarded tail (summed from the smallest
       // value) is <= tol^2
       double acc = 0.0;
-      int best = kmax;
-      for (int Dp = kmax - 1; Dp >= 1; --Dp) {
+      int best = k;
+      for (int Dp = k - 1; Dp >= 1; --Dp) {
         acc += sigbuf[Dp] * sigbuf[Dp] / tot;
         if (acc <= tol * tol) best = Dp; else break;
       }
@@ -242,28 +334,44 @@ __global__ __launch_bounds__(JT) void jacobi_cols_kernel(
     }
     if (D < 1) D = 1;
     double disc2 = 0.0;
-    for (int i = D; i < ncol; ++i) disc2 += sigbuf[i] * sigbuf[i];
+    for (int i = D; i < k; ++i) disc2 += sigbuf[i] * sigbuf[i];
     Dsh = D;
     info[0] = (double)D;
     info[1] = (tot > 0.0) ? sqrt(disc2 / tot) : 0.0;
     info[2] = (double)sweep;
     info[3] = (double)converged;
-    info[4] = (double)rounds;
+    info[4] = (double)steps;
   }
   __syncthreads();
   const int D = Dsh;
-  // Vt[d][i] = A[perm d][i] / sigma_d   (right singular vectors)
-  for (long e = tid; e < (long)D * nrow; e += JT) {
-    const long d = e / nrow, i = e % nrow;
-    const double sd = sigbuf[d];
-    Vt[e] = (sd * sd > negl) ? A[(long)perm_out[d] * lda + i] / sd : 0.0;
+  // Vt[d][i] = column perm(d) / sigma_d; numerical zeros give zero rows
+  for (long e = tid; e < (long)D * k; e += nthr) {
+    const long dd = e / k, i = e % k;
+    const double sd = sigbuf[dd];
+    Vt[e] = (sd * sd > negl * normF2) ? M[(long)perm_out[dd] * lda + i] / sd : 0.0;
   }
+}
+
+struct Shape {
+  int d, nodes, rpt;
+};
+
+Shape shape_of(int k) {
+  Shape s;
+  s.d = 2;
+  while ((1 << s.d) * 2 < k) ++s.d;
+  s.nodes = 1 << s.d;
+  s.rpt = k <= 32 ? 2 : (k <= 64 ? 4 : 8);
+  return s;
 }
 
 }  // namespace
 
 size_t jacobi_lds_bytes(int k) {
-  return (size_t)k * (size_t)(k | 1) * sizeof(double);
+  const Shape s = shape_of(k);
+  const size_t xch = (size_t)2 * s.nodes * 16 * s.rpt;
+  const size_t cols = (size_t)k * (size_t)(k | 1);
+  return (xch > cols ? xch : cols) * sizeof(double);
 }
 
 void jacobi_svd(hipStream_t s, const double* Xr, int k, long ldx, int cap,
@@ -271,15 +379,31 @@ void jacobi_svd(hipStream_t s, const double* Xr, int k, long ldx, int cap,
                 int* perm, double* info) {
   static std::once_flag once;
   std::call_once(once, [] {
-    MPSV_HIP(hipFuncSetAttribute((const void*)jacobi_cols_kernel,
+    MPSV_HIP(hipFuncSetAttribute((const void*)jacobi_hc_kernel<2>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)kJacobiMaxLds));
+    MPSV_HIP(hipFuncSetAttribute((const void*)jacobi_hc_kernel<4>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)kJacobiMaxLds));
+    MPSV_HIP(hipFuncSetAttribute((const void*)jacobi_hc_kernel<8>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)kJacobiMaxLds));
   });
-  const size_t lds = jacobi_lds_bytes(k);
-  MPSV_CHECK(lds <= kJacobiMaxLds && k <= kJacobiMaxCols && k >= 1, kEinval,
+  MPSV_CHECK(k >= 1 && k <= kJacobiMaxCols, kEinval,
              "Jacobi SVD: matrix does not fit on chip");
-  hipLaunchKernelGGL(jacobi_cols_kernel, dim3(1), dim3(JT), lds, s, Xr, k, ldx,
-                     max_sweeps, cap, tol, Vt, sigbuf, perm, info);
+  const size_t lds = jacobi_lds_bytes(k);
+  MPSV_CHECK(lds <= kJacobiMaxLds, kEinval, "Jacobi SVD: LDS too small");
+  const Shape sh = shape_of(k);
+  const dim3 block(16 * sh.nodes);
+  if (sh.rpt == 2)
+    hipLaunchKernelGGL(jacobi_hc_kernel<2>, dim3(1), block, lds, s, Xr, k, ldx,
+                       sh.d, max_sweeps, cap, tol, Vt, sigbuf, perm, info);
+  else if (sh.rpt == 4)
+    hipLaunchKernelGGL(jacobi_hc_kernel<4>, dim3(1), block, lds, s, Xr, k, ldx,
+                       sh.d, max_sweeps, cap, tol, Vt, sigbuf, perm, info);
+  else
+    hipLaunchKernelGGL(jacobi_hc_kernel<8>, dim3(1), block, lds, s, Xr, k, ldx,
+                       sh.d, max_sweeps, cap, tol, Vt, sigbuf, perm, info);
   MPSV_LAUNCHED();
 }
 
