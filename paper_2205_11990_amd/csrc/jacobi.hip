@@ -19,9 +19,11 @@
 // let the second columns walk through the cube along a Gray code (one
 // dimension per step), which brings every column of one half next to every
 // column of the other.  Node bits 0 and 1 select the DPP row inside a wave,
-// so moves along those dimensions are register swaps between rows
-// (permlane16/32 swaps); only moves along the wave bits go through LDS.  At
-// 128 columns 96 of the 126 moves of a sweep stay in registers.
+// so moves along those dimensions are lane permutations inside the wave
+// (ds_swizzle / ds_bpermute through the LDS crossbar, which leaves the
+// vector ALU free); only moves along the wave bits go through LDS memory,
+// with a barrier.  At 128 columns 96 of the 126 moves of a sweep stay
+// inside the waves.
 //
 // Squared column norms are carried with the columns and updated with each
 // rotation.  Columns below 1e-15 of the Frobenius norm are numerical zeros
@@ -65,22 +67,25 @@ __device__ inline void rotation(double a, double b, double g, double& cs,
   sn = y * t;
 }
 
-// Value of the same lane in the DPP row (node) row ^ (1 << DIM), DIM < 2.
+// Value of the same lane in the DPP row (node) row ^ (1 << DIM), DIM < 2:
+// a lane permutation through the LDS crossbar (no LDS memory, no VALU
+// issue slots): ds_swizzle with xor mask 16 inside each half-wave, or
+// ds_bpermute to lane ^ 32.
 template <int DIM>
-__device__ inline int row_swap(int v, int row) {
+__device__ inline int row_swap(int v) {
   if constexpr (DIM == 0) {
-    const auto o = __builtin_amdgcn_permlane16_swap(v, v, false, false);
-    return (row & 1) ? o[0] : o[1];
+    // bit mode: and_mask 0x1f, or_mask 0, xor_mask 0x10
+    return __builtin_amdgcn_ds_swizzle(v, 0x401F);
   } else {
-    const auto o = __builtin_amdgcn_permlane32_swap(v, v, false, false);
-    return (row & 2) ? o[0] : o[1];
+    const int lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+    return __builtin_amdgcn_ds_bpermute((lane ^ 32) << 2, v);
   }
 }
 
 template <int DIM>
-__device__ inline double row_swap(double v, int row) {
-  const int lo = row_swap<DIM>(__double2loint(v), row);
-  const int hi = row_swap<DIM>(__double2hiint(v), row);
+__device__ inline double row_swap(double v) {
+  const int lo = row_swap<DIM>(__double2loint(v));
+  const int hi = row_swap<DIM>(__double2hiint(v));
   return __hiloint2double(hi, lo);
 }
 
@@ -96,11 +101,11 @@ struct Col {
 // arriving from there.  Along wave bits it passes through the LDS buffer
 // `xb` (one barrier), along row bits through registers.
 template <int DIM, int RPT>
-__device__ inline void swap_rows(const Col<RPT>& send, Col<RPT>& recv, int row) {
+__device__ inline void swap_rows(const Col<RPT>& send, Col<RPT>& recv) {
 #pragma unroll
-  for (int r = 0; r < RPT; ++r) recv.v[r] = row_swap<DIM>(send.v[r], row);
-  recv.n = row_swap<DIM>(send.n, row);
-  recv.id = row_swap<DIM>(send.id, row);
+  for (int r = 0; r < RPT; ++r) recv.v[r] = row_swap<DIM>(send.v[r]);
+  recv.n = row_swap<DIM>(send.n);
+  recv.id = row_swap<DIM>(send.id);
 }
 
 template <int RPT>
@@ -108,11 +113,11 @@ __device__ inline void exchange(const Col<RPT>& send, Col<RPT>& recv, int dim,
                                 int x, int row, int lig, int N, int& par,
                                 double* xb, double* xn, int* xi) {
   if (dim == 0) {
-    swap_rows<0, RPT>(send, recv, row);
+    swap_rows<0, RPT>(send, recv);
     return;
   }
   if (dim == 1) {
-    swap_rows<1, RPT>(send, recv, row);
+    swap_rows<1, RPT>(send, recv);
     return;
   }
   const int pb = par;
