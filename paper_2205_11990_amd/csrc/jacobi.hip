@@ -203,10 +203,11 @@ __global__ __launch_bounds__(MAXT) void jacobi_hc_kernel(
   // below 1e-8 of the pair's total (its rounding error could then exceed
   // 1e-8 of it) the column norms are recomputed instead.
   auto pair_step = [&]() {
-    double g = 0.0;
+    // four independent partial sums shorten the dependency chain
+    double gp[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int r = 0; r < RPT; ++r) g = fma(A.v[r], B.v[r], g);
-    g = wave::sum16(g);
+    for (int r = 0; r < RPT; ++r) gp[r & 3] = fma(A.v[r], B.v[r], gp[r & 3]);
+    const double g = wave::sum16((gp[0] + gp[1]) + (gp[2] + gp[3]));
     const double ab = A.n * B.n, g2 = g * g;
     const bool rot = g2 > eps2 * ab && fmin(A.n, B.n) > negl;
     if (rot) {  // uniform over the 16 lanes of the node

@@ -97,7 +97,7 @@ __device__ __forceinline__ void factor_block(double (&x)[RPL][CPW], int w,
         tau[j] = tj;
       }
     }
-    __syncthreads();
+    wave::lds_barrier();
     const double tj = tb[buf];
     if (tj != 0.0) {
       // the reflector is kept in registers unless the rows need 32 per
@@ -176,6 +176,99 @@ __global__ __launch_bounds__(FT) void qr_reg_factor_kernel(
       if (i < k) R[(long)i * ldr + j] = (i <= j) ? x[a][b] : 0.0;
       if (RPL == 32 && j < k && i < m)
         V[(long)j * m + i] = (i > j) ? x[a][b] : (i == j ? 1.0 : 0.0);
+    }
+  }
+}
+
+// Factorisation with a column per DPP row: group g (16 lanes) holds the
+// columns c = g + 64 s (s < CPG), lane l of the group the rows l + 16 a
+// (a < RPT).  The products v^T A of a reflector with a column are then
+// reduced over 16 lanes only (row-local DPP moves), four columns per wave
+// at once, which needs fewer cross-lane instructions per column than the
+// wave-per-column layout when the rows fit in 16 * RPT <= 256.
+template <int CPG, int RPT>
+__global__ __launch_bounds__(FT) void qr_g16_factor_kernel(
+    const double* A, long lda, int m, int n, double* R, long ldr,
+    double* __restrict__ V, double* __restrict__ tau) {
+  __shared__ double vb[2 * 16 * RPT];
+  __shared__ double tb[2];
+  const int tid = threadIdx.x, g = tid >> 4, lig = tid & 15;
+  const int k = m < n ? m : n;
+  double x[CPG][RPT];
+#pragma unroll
+  for (int c = 0; c < CPG; ++c)
+#pragma unroll
+    for (int a = 0; a < RPT; ++a) {
+      const int i = lig + 16 * a, j = g + 64 * c;
+      x[c][a] = (i < m && j < n) ? A[(long)i * lda + j] : 0.0;
+    }
+  for (int j = 0; j < k; ++j) {
+    const int og = j & 63, os = j >> 6, buf = j & 1;
+    double* vj = vb + buf * 16 * RPT;
+    if (g == og) {  // the 16 lanes owning column j (register column os)
+#pragma unroll
+      for (int c = 0; c < CPG; ++c) {
+        if (c != os) continue;
+        double s2 = 0.0, xa = 0.0;
+        const int aj = j >> 4;
+#pragma unroll
+        for (int a = 0; a < RPT; ++a) {
+          const int i = lig + 16 * a;
+          if (i > j) s2 = fma(x[c][a], x[c][a], s2);
+          if (a == aj) xa = x[c][a];
+        }
+        s2 = wave::sum16(s2);
+        const double alpha = wave::read_lane(xa, ((g & 3) << 4) + (j & 15));
+        double tj = 0.0, beta = alpha, scal = 0.0;
+        if (s2 > 0.0) {
+          beta = -copysign(sqrt(fma(alpha, alpha, s2)), alpha);
+          tj = (beta - alpha) / beta;
+          scal = 1.0 / (alpha - beta);
+        }
+        double* Vj = V + (long)j * m;
+#pragma unroll
+        for (int a = 0; a < RPT; ++a) {
+          const int i = lig + 16 * a;
+          const double v = (i > j) ? x[c][a] * scal : (i == j ? 1.0 : 0.0);
+          vj[i] = v;
+          if (i < m) Vj[i] = v;
+          x[c][a] = (i == j) ? beta : (i > j ? 0.0 : x[c][a]);
+        }
+        if (lig == 0) {
+          tb[buf] = tj;
+          tau[j] = tj;
+        }
+      }
+    }
+    wave::lds_barrier();
+    const double tj = tb[buf];
+    if (tj != 0.0) {
+      double v[RPT];
+#pragma unroll
+      for (int a = 0; a < RPT; ++a) v[a] = vj[lig + 16 * a];
+#pragma unroll
+      for (int c = 0; c < CPG; ++c) {
+        const int col = g + 64 * c;
+        if (col > j && col < n) {  // uniform over the group
+          // four independent partial sums shorten the dependency chain
+          double d[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int a = 0; a < RPT; ++a) d[a & 3] = fma(v[a], x[c][a], d[a & 3]);
+          const double f = tj * wave::sum16((d[0] + d[1]) + (d[2] + d[3]));
+#pragma unroll
+          for (int a = 0; a < RPT; ++a) x[c][a] = fma(-v[a], f, x[c][a]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < CPG; ++c) {
+    const int j = g + 64 * c;
+    if (j >= n) continue;
+#pragma unroll
+    for (int a = 0; a < RPT; ++a) {
+      const int i = lig + 16 * a;
+      if (i < k) R[(long)i * ldr + j] = (i <= j) ? x[c][a] : 0.0;
     }
   }
 }
@@ -295,8 +388,19 @@ void qr_reg_factor(hipStream_t s, const double* A, long lda, int m, int n,
   MPSV_CHECK(qr_reg_fits(m, n), kEinval, "qr_reg_factor: shape does not fit");
   const int rpl = rows_per_lane(m), cpw = cols_per_wave(n);
   const int slot = prof_begin(s);
+  // column-per-row layout where the rows fit (16 * RPT >= m, <= 32 values)
+  int rpt = 2;
+  while (16 * rpt < m) rpt *= 2;
+  const int cpg = n <= 64 ? 1 : 2;
+  const bool g16 = m <= 256 && n <= 128;
+#define MPSV_G(C, Rr)                                                   \
+  if (g16 && cpg == C && rpt == Rr)                                     \
+    hipLaunchKernelGGL((qr_g16_factor_kernel<C, Rr>), dim3(1), dim3(FT), 0, s, \
+                       A, lda, m, n, R, ldr, V, tau); else
 #define MPSV_F(C, Rr)                                                   \
   if (cpw == C && rpl == Rr) launch_factor<C, Rr>(s, A, lda, m, n, R, ldr, V, tau); else
+  MPSV_G(1, 2) MPSV_G(1, 4) MPSV_G(1, 8) MPSV_G(1, 16)
+  MPSV_G(2, 2) MPSV_G(2, 4) MPSV_G(2, 8) MPSV_G(2, 16)
   MPSV_F(1, 1) MPSV_F(2, 1) MPSV_F(4, 1) MPSV_F(8, 1)
   MPSV_F(1, 2) MPSV_F(2, 2) MPSV_F(4, 2) MPSV_F(8, 2)
   MPSV_F(1, 4) MPSV_F(2, 4) MPSV_F(4, 4) MPSV_F(8, 4)
@@ -304,6 +408,7 @@ void qr_reg_factor(hipStream_t s, const double* A, long lda, int m, int n,
   MPSV_F(1, 16) MPSV_F(1, 32)
   throw Error(kEinval, "qr_reg_factor: no kernel for this shape");
 #undef MPSV_F
+#undef MPSV_G
   MPSV_LAUNCHED();
   const int k = m < n ? m : n;
   // nominal GEQRF flops, 2 m n^2 - 2 n^3 / 3 (n = k columns reduced) plus

@@ -87,5 +87,16 @@ __device__ inline void sums(double (&p)[N]) {
   }
 }
 
+// Workgroup barrier that orders LDS traffic only: waits for this wave's
+// LDS operations (lgkmcnt 0) but not for its global stores, then
+// s_barrier.  Loops whose global stores
+// are read only by later kernels use it so that every step does not wait
+// for the store round trip to memory.
+__device__ inline void lds_barrier() {
+  // the memory clobber keeps the compiler from moving memory accesses
+  // across the barrier
+  __asm__ volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 }  // namespace wave
 }  // namespace mpsv
