@@ -273,6 +273,163 @@ __global__ __launch_bounds__(FT) void qr_g16_factor_kernel(
   }
 }
 
+// Blocked factorisation with panels of eight columns, for m <= 64 * RPL
+// rows and n <= 128 columns.  Wave w holds the columns 8w .. 8w+7 (lane
+// l the rows l + 64 a).  Panel p is factored by wave p alone, without
+// barriers (its reflectors update the rest of the panel in registers); it
+// then publishes the eight reflectors in LDS and every wave to its right
+// applies them to its own columns.  The wave that owns the next panel
+// applies them first and factors its panel straight away, so one barrier
+// per panel suffices and the other waves' updates overlap the next panel.
+template <int RPL>
+__device__ __forceinline__ void blk_factor_panel(double (&x)[RPL][8], int p,
+                                                 int l, int k, double* vb,
+                                                 double* tb,
+                                                 double* __restrict__ tau);
+
+template <int RPL, int B>
+__device__ __forceinline__ void blk_factor_col(double (&x)[RPL][8], int p,
+                                               int l, int k, double* vb,
+                                               double* tb,
+                                               double* __restrict__ tau) {
+  const int j = 8 * p + B;
+  if (j >= k) return;
+  double s2 = 0.0, xa = 0.0;
+  const int aj = j >> 6;
+#pragma unroll
+  for (int a = 0; a < RPL; ++a) {
+    const int i = l + 64 * a;
+    if (i > j) s2 = fma(x[a][B], x[a][B], s2);
+    if (a == aj) xa = x[a][B];
+  }
+  s2 = wave::sum64(s2);
+  const double alpha = wave::read_lane(xa, j & 63);
+  double tj = 0.0, beta = alpha, scal = 0.0;
+  if (s2 > 0.0) {
+    beta = -copysign(sqrt(fma(alpha, alpha, s2)), alpha);
+    tj = (beta - alpha) / beta;
+    scal = 1.0 / (alpha - beta);
+  }
+  double v[RPL];
+#pragma unroll
+  for (int a = 0; a < RPL; ++a) {
+    const int i = l + 64 * a;
+    v[a] = (i > j) ? x[a][B] * scal : (i == j ? 1.0 : 0.0);
+    vb[B * 64 * RPL + i] = v[a];
+    // LAPACK storage: beta on the diagonal, the reflector below
+    x[a][B] = (i == j) ? beta : (i > j ? v[a] : x[a][B]);
+  }
+  if (l == 0) {
+    tb[B] = tj;
+    tau[j] = tj;
+  }
+  if constexpr (B < 7) {
+    if (tj != 0.0) {
+      constexpr int NB = 7 - B;
+      double d[NB];
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        double acc = 0.0;
+#pragma unroll
+        for (int a = 0; a < RPL; ++a) acc = fma(v[a], x[a][B + 1 + q], acc);
+        d[q] = acc;
+      }
+      sums_any<NB>(d);
+      if constexpr (RPL >= 4) {
+        // reread the reflector (this wave's own LDS writes) rather than
+        // keep it live across the reduction
+        __asm__ volatile("" ::: "memory");
+#pragma unroll
+        for (int a = 0; a < RPL; ++a) v[a] = vb[B * 64 * RPL + l + 64 * a];
+      }
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        const double f = tj * d[q];
+#pragma unroll
+        for (int a = 0; a < RPL; ++a) x[a][B + 1 + q] = fma(-v[a], f, x[a][B + 1 + q]);
+      }
+    }
+    blk_factor_col<RPL, B + 1>(x, p, l, k, vb, tb, tau);
+  }
+}
+
+template <int RPL>
+__device__ __forceinline__ void blk_factor_panel(double (&x)[RPL][8], int p,
+                                                 int l, int k, double* vb,
+                                                 double* tb,
+                                                 double* __restrict__ tau) {
+  blk_factor_col<RPL, 0>(x, p, l, k, vb, tb, tau);
+}
+
+template <int RPL>
+__device__ __forceinline__ void blk_apply_panel(double (&x)[RPL][8], int p,
+                                                int l, int k, const double* vb,
+                                                const double* tb) {
+#pragma unroll 1
+  for (int b = 0; b < 8; ++b) {
+    if (8 * p + b >= k) break;
+    const double tj = tb[b];
+    if (tj == 0.0) continue;
+    double v[RPL];
+#pragma unroll
+    for (int a = 0; a < RPL; ++a) v[a] = vb[b * 64 * RPL + l + 64 * a];
+    double d[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      double acc = 0.0;
+#pragma unroll
+      for (int a = 0; a < RPL; ++a) acc = fma(v[a], x[a][c], acc);
+      d[c] = acc;
+    }
+    wave::sums<8>(d);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const double f = tj * d[c];
+#pragma unroll
+      for (int a = 0; a < RPL; ++a) x[a][c] = fma(-v[a], f, x[a][c]);
+    }
+  }
+}
+
+template <int RPL>
+__global__ __launch_bounds__(FT) void qr_blk_factor_kernel(
+    const double* A, long lda, int m, int n, double* R, long ldr,
+    double* __restrict__ V, double* __restrict__ tau) {
+  __shared__ double vb[2 * 8 * 64 * RPL];
+  __shared__ double tb[2 * 8];
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int k = m < n ? m : n;
+  const int npan = (k + 7) / 8;
+  double x[RPL][8];
+#pragma unroll
+  for (int a = 0; a < RPL; ++a)
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const int i = l + 64 * a, j = 8 * w + b;
+      x[a][b] = (i < m && j < n) ? A[(long)i * lda + j] : 0.0;
+    }
+  for (int p = 0; p < npan; ++p) {
+    double* vbp = vb + (p & 1) * 8 * 64 * RPL;
+    double* tbp = tb + (p & 1) * 8;
+    if (w == p) blk_factor_panel<RPL>(x, p, l, k, vbp, tbp, tau);
+    wave::lds_barrier();
+    if (w > p) blk_apply_panel<RPL>(x, p, l, k, vbp, tbp);
+  }
+  // every wave has passed the first barrier, so A (which R may alias) has
+  // been read completely
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const int j = 8 * w + b;
+    if (j >= n) continue;
+#pragma unroll
+    for (int a = 0; a < RPL; ++a) {
+      const int i = l + 64 * a;
+      if (i < k) R[(long)i * ldr + j] = (i <= j) ? x[a][b] : 0.0;
+      if (j < k && i < m) V[(long)j * m + i] = (i > j) ? x[a][b] : (i == j ? 1.0 : 0.0);
+    }
+  }
+}
+
 template <int CPW, int RPL>
 __global__ __launch_bounds__(AT) void qr_reg_apply_kernel(
     const double* __restrict__ V, const double* __restrict__ tau, int m, int k,
@@ -392,13 +549,19 @@ void qr_reg_factor(hipStream_t s, const double* A, long lda, int m, int n,
   int rpt = 2;
   while (16 * rpt < m) rpt *= 2;
   const int cpg = n <= 64 ? 1 : 2;
-  const bool g16 = m <= 256 && n <= 128;
+  // measured fastest per shape: column-per-row layout up to 64 rows,
+  // eight-column wave panels up to 128 rows, wave-per-column layout above
+  const bool g16 = m <= 64 && n <= 128;
+  const bool blk = !g16 && m <= 128 && n <= 128;
 #define MPSV_G(C, Rr)                                                   \
   if (g16 && cpg == C && rpt == Rr)                                     \
     hipLaunchKernelGGL((qr_g16_factor_kernel<C, Rr>), dim3(1), dim3(FT), 0, s, \
                        A, lda, m, n, R, ldr, V, tau); else
 #define MPSV_F(C, Rr)                                                   \
   if (cpw == C && rpl == Rr) launch_factor<C, Rr>(s, A, lda, m, n, R, ldr, V, tau); else
+  if (blk)
+    hipLaunchKernelGGL((qr_blk_factor_kernel<2>), dim3(1), dim3(FT), 0, s, A, lda, m, n, R, ldr, V, tau);
+  else
   MPSV_G(1, 2) MPSV_G(1, 4) MPSV_G(1, 8) MPSV_G(1, 16)
   MPSV_G(2, 2) MPSV_G(2, 4) MPSV_G(2, 8) MPSV_G(2, 16)
   MPSV_F(1, 1) MPSV_F(2, 1) MPSV_F(4, 1) MPSV_F(8, 1)
