@@ -87,9 +87,41 @@ def cpu_baseline(w, mode, cores_host):
 # Peak of the unit each kernel class runs on (MI355X, dense FP64).
 _CLASS_BOUND = {
     "gemm_f64": ("mfma", PEAK_FP64_TFLOPS),     # v_mfma_f64_16x16x4f64
-    "householder": ("alu", PEAK_FP64_TFLOPS),   # FP64 vector FMA
+    "qr_factor": ("alu", PEAK_FP64_TFLOPS),     # FP64 vector FMA
+    "qr_apply": ("alu", PEAK_FP64_TFLOPS),      # FP64 vector FMA
     "jacobi_svd": ("alu", PEAK_FP64_TFLOPS),    # FP64 vector FMA
 }
+
+
+# rocprofv3 FETCH_SIZE / WRITE_SIZE summaries of the kernels (committed under
+# profiles/), valid while the kernel sources they were taken on are unchanged
+_TRAFFIC = {
+    "jacobi_svd": ("profiles/jacobi_svd_hbm_traffic_two_stream_1024_chi64.txt",
+                   ("paper_2205_11990_amd/csrc/jacobi.hip", "paper_2205_11990_amd/csrc/wave.hpp")),
+}
+
+
+def measured_traffic(cls):
+    """HBM bytes per launch from the committed counter summary, or None when
+    there is none or the kernel changed since the counters were taken."""
+    import hashlib
+    if cls not in _TRAFFIC:
+        return None
+    summary, sources = _TRAFFIC[cls]
+    try:
+        text = open(os.path.join(ROOT, summary)).read()
+        h = hashlib.sha256()
+        for f in sources:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+    except OSError:
+        return None
+    vals = dict(l.split(":", 1) for l in text.splitlines() if ":" in l and not l.startswith("#"))
+    try:
+        if vals["source_sha256"].split()[0] != h.hexdigest():
+            return None
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError, IndexError):
+        return None
 
 
 def roofline(binding, st, cores_host, steps):
@@ -113,7 +145,7 @@ def roofline(binding, st, cores_host, steps):
                    "tflops": round(v["flops"] / (v["ms"] * 1e-3) / 1e12, 4) if v["ms"] > 0 else None}
                for k, v in rec.items() if k in _CLASS_BOUND}
     return {"bound": bound, "achieved": ach, "peak": peak, "unit": "TFLOP/s",
-            "frac": ach / peak, "traffic": None, "kernel": dom,
+            "frac": ach / peak, "traffic": measured_traffic(dom), "kernel": dom,
             "launches": r["launches"], "avg_launch_us": 1000.0 * r["ms"] / max(r["launches"], 1),
             "flops_per_launch": r["flops"] / max(r["launches"], 1),
             "classes": classes}

@@ -84,8 +84,8 @@ mps_status mpsb_set_jacobi_max_sweeps(int32_t n);
 
 /* Per-kernel-class timing with HIP events on the launching stream (off by
  * default).  enable != 0 clears and starts recording; classes: 0 GEMM,
- * 1 Householder QR (factorisation and reflector application), 2 Jacobi
- * SVD, 3 other.  mpsb_profile_read synchronises the
+ * 1 Householder QR factorisation, 2 Jacobi SVD, 3 other, 4 application of
+ * Householder reflectors.  mpsb_profile_read synchronises the
  * device and returns, for one class, the number of launches, the summed
  * event time (ms) and the summed nominal FLOPs and bytes (host outputs). */
 mps_status mpsb_profile(int32_t enable);

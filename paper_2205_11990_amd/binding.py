@@ -378,7 +378,7 @@ def set_jacobi_max_sweeps(n: int):
     _check(lib().mpsb_set_jacobi_max_sweeps(int(n)))
 
 
-KERNEL_CLASSES = ("gemm_f64", "householder", "jacobi_svd", "other")
+KERNEL_CLASSES = ("gemm_f64", "qr_factor", "jacobi_svd", "other", "qr_apply")
 
 
 def profile(enable: bool):

@@ -11,7 +11,8 @@ enum KClass : int {
   kClsQrPanel = 1,
   kClsJacobi = 2,
   kClsOther = 3,
-  kClsCount = 4
+  kClsQrApply = 4,
+  kClsCount = 5
 };
 
 bool prof_enabled();

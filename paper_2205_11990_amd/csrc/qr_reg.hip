@@ -562,8 +562,7 @@ void qr_reg_factor(hipStream_t s, const double* A, long lda, int m, int n,
   if (blk)
     hipLaunchKernelGGL((qr_blk_factor_kernel<2>), dim3(1), dim3(FT), 0, s, A, lda, m, n, R, ldr, V, tau);
   else
-  MPSV_G(1, 2) MPSV_G(1, 4) MPSV_G(1, 8) MPSV_G(1, 16)
-  MPSV_G(2, 2) MPSV_G(2, 4) MPSV_G(2, 8) MPSV_G(2, 16)
+  MPSV_G(1, 2) MPSV_G(1, 4) MPSV_G(2, 2) MPSV_G(2, 4)
   MPSV_F(1, 1) MPSV_F(2, 1) MPSV_F(4, 1) MPSV_F(8, 1)
   MPSV_F(1, 2) MPSV_F(2, 2) MPSV_F(4, 2) MPSV_F(8, 2)
   MPSV_F(1, 4) MPSV_F(2, 4) MPSV_F(4, 4) MPSV_F(8, 4)
@@ -598,7 +597,7 @@ void qr_reg_apply(hipStream_t s, const double* V, const double* tau, int m,
 #undef MPSV_A
   MPSV_LAUNCHED();
   // k reflectors of decreasing length applied to p columns
-  prof_end(s, slot, kClsQrPanel, 4.0 * p * (double)k * (m - (k - 1) / 2.0),
+  prof_end(s, slot, kClsQrApply, 4.0 * p * (double)k * (m - (k - 1) / 2.0),
            8.0 * (2.0 * m * p + (double)m * k));
 }
 
