@@ -567,9 +567,9 @@ DMps Engine::compress_chain(const std::vector<VSite>& ch_in, int cap, double tol
       p = rows;
     } else {
       fac[j].ident = false;
-      qr_factor(s, work(), M, rows, cols, cols, fac[j].qf);
       double* Rn = work().alloc((size_t)cols * cols);
-      extract_r(s, M, cols, cols, cols, Rn, cols);
+      qr_factor(s, work(), M, rows, cols, cols, fac[j].qf,
+                MatView{Rn, cols, 1, 0});
       R = Rn;
       p = cols;
     }

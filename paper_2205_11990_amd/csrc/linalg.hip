@@ -221,11 +221,21 @@ __global__ __launch_bounds__(NT) void qr_panel_kernel(double* P, int m, int jb,
 }
 
 __global__ void extract_r_kernel(const double* A, int k, int n, long ld,
-                                 double* R, long ldr) {
+                                 MatView R) {
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < (long)k * n;
        e += (long)gridDim.x * blockDim.x) {
     long i = e / n, j = e % n;
-    R[i * ldr + j] = (j >= i) ? A[i * ld + j] : 0.0;
+    R.p[i * R.rs + j * R.cs] = (j >= i) ? A[i * ld + j] : 0.0;
+  }
+}
+
+// out[0:rows, 0:cols] = in (rows < rows_in), 0 (rows >= rows_in); any strides
+__global__ void copy_view_kernel(CMatView in, int rows_in, MatView out,
+                                 int rows, int cols) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+       e < (long)rows * cols; e += (long)gridDim.x * blockDim.x) {
+    const long i = e / cols, j = e % cols;
+    out.p[i * out.rs + j * out.cs] = (i < rows_in) ? in.p[i * in.rs + j * in.cs] : 0.0;
   }
 }
 
@@ -440,11 +450,20 @@ void set_jacobi_max_sweeps(int n) { g_max_sweeps = n < 1 ? 1 : n; }
 int jacobi_max_sweeps() { return g_max_sweeps; }
 
 void extract_r(hipStream_t s, const double* A, int k, int n, long ld,
-               double* R, long ldr) {
+               MatView R) {
   if (k <= 0 || n <= 0) return;
   int blocks = std::min(1024, ceil_div((long)k * n, 256));
   hipLaunchKernelGGL(extract_r_kernel, dim3(blocks), dim3(256), 0, s, A, k, n,
-                     ld, R, ldr);
+                     ld, R);
+  MPSV_LAUNCHED();
+}
+
+void copy_view(hipStream_t s, CMatView in, int rows_in, MatView out, int rows,
+               int cols) {
+  if (rows <= 0 || cols <= 0) return;
+  int blocks = std::min(1024, ceil_div((long)rows * cols, 256));
+  hipLaunchKernelGGL(copy_view_kernel, dim3(blocks), dim3(256), 0, s, in,
+                     rows_in, out, rows, cols);
   MPSV_LAUNCHED();
 }
 
@@ -506,7 +525,7 @@ static void fill_rows_zero(hipStream_t s, double* X, int r0, int r1, int nc,
 }
 
 void qr_factor(hipStream_t s, Arena& ws, double* A, int m, int n, long ld,
-               QrFactor& f) {
+               QrFactor& f, MatView R) {
   set_attrs();
   f.m = m;
   f.n = n;
@@ -516,6 +535,7 @@ void qr_factor(hipStream_t s, Arena& ws, double* A, int m, int n, long ld,
   if (m <= 2048) {
     // register-resident panels; the trailing columns are updated by the
     // reflector-application kernel
+    const bool single = n <= qr_reg_panel_cols(m);
     for (int k0 = 0; k0 < f.k;) {
       const int rows = m - k0;
       const int jb = std::min(qr_reg_panel_cols(rows), n - k0);
@@ -527,12 +547,17 @@ void qr_factor(hipStream_t s, Arena& ws, double* A, int m, int n, long ld,
       pn.V = ws.alloc((size_t)rows * kk);
       pn.tau = ws.alloc((size_t)kk);
       double* P = A + (long)k0 * ld + k0;
-      qr_reg_factor(s, P, ld, rows, jb, P, ld, pn.V, pn.tau);
+      // one panel with a separate R: written straight there, A untouched
+      const MatView Rout = (single && R.p) ? R : MatView{P, ld, 1, 0};
+      qr_reg_factor(s, CMatView{P, ld, 1, 0}, rows, jb, Rout, pn.V, pn.tau);
       const int n2 = n - k0 - jb;
-      if (n2 > 0) qr_reg_apply(s, pn.V, pn.tau, rows, kk, P + jb, ld, n2, true);
+      if (n2 > 0)
+        qr_reg_apply(s, pn.V, pn.tau, rows, kk, CMatView{P + jb, ld, 1, 0}, rows,
+                     MatView{P + jb, ld, 1, 0}, n2, true);
       f.panels.push_back(pn);
       k0 += jb;
     }
+    if (R.p && !single) extract_r(s, A, f.k, n, ld, R);
     return;
   }
   for (int k0 = 0; k0 < f.k; ) {
@@ -571,6 +596,53 @@ void qr_factor(hipStream_t s, Arena& ws, double* A, int m, int n, long ld,
     f.panels.push_back(pn);
     k0 += jb;
   }
+  if (R.p) extract_r(s, A, f.k, n, ld, R);
+}
+
+void qr_factor_view(hipStream_t s, Arena& ws, CMatView A, int m, int n,
+                    QrFactor& f, MatView R) {
+  if (m <= 2048 && n <= qr_reg_panel_cols(m)) {
+    set_attrs();
+    f.m = m;
+    f.n = n;
+    f.k = std::min(m, n);
+    f.panels.clear();
+    g_stats.qr_calls++;
+    QrPanel pn;
+    pn.k0 = 0;
+    pn.jb = f.k;
+    pn.reg = true;
+    pn.V = ws.alloc((size_t)m * f.k);
+    pn.tau = ws.alloc((size_t)f.k);
+    qr_reg_factor(s, A, m, n, R, pn.V, pn.tau);
+    f.panels.push_back(pn);
+    return;
+  }
+  double* C = ws.alloc((size_t)m * n);
+  copy_view(s, A, m, MatView{C, n, 1, 0}, m, n);
+  qr_factor(s, ws, C, m, n, n, f, R);
+}
+
+void qr_apply_q_view(hipStream_t s, Arena& ws, const QrFactor& f, CMatView Yin,
+                     int rows_in, MatView Yout, int nc) {
+  if (nc <= 0) return;
+  if (f.panels.size() == 1 && f.panels[0].reg) {
+    const QrPanel& pn = f.panels[0];
+    qr_reg_apply(s, pn.V, pn.tau, f.m, pn.jb, Yin, rows_in, Yout, nc, false);
+    return;
+  }
+  if (Yout.cs != 1) {
+    // panelled Q into a strided output: through a row-major buffer
+    ArenaScope sc(ws);
+    double* T = ws.alloc((size_t)f.m * nc);
+    copy_view(s, Yin, rows_in, MatView{T, nc, 1, 0}, f.m, nc);
+    qr_apply_q(s, ws, f, T, nc, nc);
+    copy_view(s, CMatView{T, nc, 1, 0}, f.m, Yout, f.m, nc);
+    return;
+  }
+  if (Yin.p != Yout.p || Yin.rs != Yout.rs || Yin.cs != Yout.cs || rows_in < f.m)
+    copy_view(s, Yin, rows_in, Yout, f.m, nc);
+  qr_apply_q(s, ws, f, Yout.p, nc, Yout.rs);
 }
 
 void qr_apply_q(hipStream_t s, Arena& ws, const QrFactor& f, double* X, int nc,
@@ -581,7 +653,8 @@ void qr_apply_q(hipStream_t s, Arena& ws, const QrFactor& f, double* X, int nc,
     const int rows = f.m - pn.k0;
     double* X2 = X + (long)pn.k0 * ldx;
     if (pn.reg) {
-      qr_reg_apply(s, pn.V, pn.tau, rows, pn.jb, X2, ldx, nc, false);
+      qr_reg_apply(s, pn.V, pn.tau, rows, pn.jb, CMatView{X2, ldx, 1, 0}, rows,
+                   MatView{X2, ldx, 1, 0}, nc, false);
       continue;
     }
     ArenaScope sc(ws);
@@ -622,43 +695,39 @@ int svd_truncate(hipStream_t s, Arena& ws, double* X, int m, int c, long ldx,
   double* Wt = nullptr;
   int slot = -1;
   if (onchip) {
+    // B is kept row-major k x k in Bk; the factorisations read it (or its
+    // transpose) through strided views and write the next B in place of a
+    // second buffer, so no transposes or copies are launched.
     bool upper;
     double* Bk = ws.alloc((size_t)k * k);
+    double* Bn = ws.alloc((size_t)k * k);
     if (mode == 0) {
       Lf.emplace_back();
-      qr_factor(s, ws, X, m, c, ldx, Lf.back());
-      extract_r(s, X, c, c, ldx, Bk, c);
+      qr_factor(s, ws, X, m, c, ldx, Lf.back(), MatView{Bk, k, 1, 0});
       upper = true;
     } else {
-      double* Xt = ws.alloc((size_t)c * m);
-      transpose(s, X, m, c, ldx, Xt, m);
+      // X^T = Q1 R1 read through a transposed view; B = R1^T (lower)
       Rf.emplace_back();
-      qr_factor(s, ws, Xt, c, m, m, Rf.back());
-      double* R1 = ws.alloc((size_t)m * m);
-      extract_r(s, Xt, m, m, m, R1, m);
-      transpose(s, R1, m, m, m, Bk, m);  // B = R1^T, lower
+      qr_factor_view(s, ws, CMatView{X, 1, ldx, 0}, c, m, Rf.back(),
+                     MatView{Bk, 1, k, 0});
       upper = false;
     }
     int extra = 2 * svd_precondition_pairs();
     while (!upper || extra > 0) {
-      double* T = ws.alloc((size_t)k * k);
       if (upper) {
-        // B = R: R^T = Q' R'  ->  B = R'^T Q'^T
-        transpose(s, Bk, k, k, k, T, k);
+        // B = R: R^T = Q' R'  ->  B = R'^T Q'^T; write R'^T
         Rf.emplace_back();
-        qr_factor(s, ws, T, k, k, k, Rf.back());
-        double* Rn = ws.alloc((size_t)k * k);
-        extract_r(s, T, k, k, k, Rn, k);
-        transpose(s, Rn, k, k, k, Bk, k);
+        qr_factor_view(s, ws, CMatView{Bk, 1, k, 0}, k, k, Rf.back(),
+                       MatView{Bn, 1, k, 0});
         upper = false;
       } else {
         // B lower: B = Q' R'
-        copy_rows(s, Bk, k, k, T);
         Lf.emplace_back();
-        qr_factor(s, ws, T, k, k, k, Lf.back());
-        extract_r(s, T, k, k, k, Bk, k);
+        qr_factor_view(s, ws, CMatView{Bk, k, 1, 0}, k, k, Lf.back(),
+                       MatView{Bn, k, 1, 0});
         upper = true;
       }
+      std::swap(Bk, Bn);
       --extra;
     }
     Rk = Bk;
@@ -673,9 +742,8 @@ int svd_truncate(hipStream_t s, Arena& ws, double* X, int m, int c, long ldx,
     long ldb = ldx;
     int mb = m;
     if (tall) {
-      qr_factor(s, ws, X, m, c, ldx, qf);
       double* R = ws.alloc((size_t)c * c);
-      extract_r(s, X, c, c, ldx, R, c);
+      qr_factor(s, ws, X, m, c, ldx, qf, MatView{R, c, 1, 0});
       B = R;
       ldb = c;
       mb = c;
@@ -710,21 +778,23 @@ int svd_truncate(hipStream_t s, Arena& ws, double* X, int m, int c, long ldx,
                             hipMemcpyDeviceToDevice, s));
   }
   if (onchip) {
-    // V = R_1 (... (R_q W_D)): c x D, rows beyond a factor's own size zero
+    // V = R_1 (... (R_q W_D)) (c x D): the first application reads W_D = Wt^T
+    // through a view, the last writes V^T straight into Vt; rows beyond the
+    // k of the triangular factor enter as zeros
+    CMatView in{Wt, 1, k, 0};
     double* Y = ws.alloc((size_t)c * D);
-    transpose(s, Wt, D, k, k, Y, D);
     for (int i = (int)Rf.size() - 1; i >= 0; --i) {
-      if (Rf[i].m > k) fill_rows_zero(s, Y, k, Rf[i].m, D, D);
-      qr_apply_q(s, ws, Rf[i], Y, D, D);
+      const MatView out = (i == 0) ? MatView{Vt, 1, c, 0} : MatView{Y, D, 1, 0};
+      qr_apply_q_view(s, ws, Rf[i], in, k, out, D);
+      in = CMatView{Y, D, 1, 0};
     }
-    transpose(s, Y, c, D, D, Vt, c);
+    if (Rf.empty()) copy_view(s, in, k, MatView{Vt, 1, c, 0}, c, D);
     // U Sigma = L_1 (... (L_p (B W_D))): m x D
     gemm(s, k, D, k, 1.0, CMatView{Rk, k, 1, 0}, CMatView{Wt, 1, k, 0}, 0.0,
          MatView{US, D, 1, 0});
-    for (int i = (int)Lf.size() - 1; i >= 0; --i) {
-      if (Lf[i].m > k) fill_rows_zero(s, US, k, Lf[i].m, D, D);
-      qr_apply_q(s, ws, Lf[i], US, D, D);
-    }
+    for (int i = (int)Lf.size() - 1; i >= 0; --i)
+      qr_apply_q_view(s, ws, Lf[i], CMatView{US, D, 1, 0}, k,
+                      MatView{US, D, 1, 0}, D);
   } else if (m > c) {
     // US rows [0, c) hold U_R Sigma (leading dimension D): US = Q [U_R Sigma; 0]
     fill_rows_zero(s, US, c, m, D, D);

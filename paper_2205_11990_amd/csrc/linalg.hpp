@@ -27,18 +27,34 @@ struct QrFactor {
 };
 
 // In-place QR of the row-major m x n matrix A (leading dimension ld):
-// on return the upper trapezoid of A holds R (k = min(m, n) rows) and `f`
-// describes Q = H_0 H_1 ... H_{k-1}.  Reflector storage comes from `ws`.
+// `f` describes Q = H_0 H_1 ... H_{k-1} (reflector storage from `ws`).  R
+// (k = min(m, n) rows, zeros below the diagonal) goes to the view R when
+// given (then A itself may be left unchanged), else to the upper trapezoid
+// of A.
 void qr_factor(hipStream_t s, Arena& ws, double* A, int m, int n, long ld,
-               QrFactor& f);
+               QrFactor& f, MatView R = MatView{nullptr, 0, 0, 0});
+
+// QR of a read-only strided m x n matrix (a transpose, say); R to the view R.
+void qr_factor_view(hipStream_t s, Arena& ws, CMatView A, int m, int n,
+                    QrFactor& f, MatView R);
 
 // X (m x nc, row-major, leading dimension ldx) <- Q X.
 void qr_apply_q(hipStream_t s, Arena& ws, const QrFactor& f, double* X,
                 int nc, long ldx);
 
-// Copy the k x n upper trapezoid of A (zeros below the diagonal) to R (ldr).
+// Yout (f.m x nc) <- Q [Yin rows 0 .. rows_in-1; 0]; views with any strides
+// when Q is one register panel, row-major Yout otherwise.  Yout may alias
+// Yin with the same strides.
+void qr_apply_q_view(hipStream_t s, Arena& ws, const QrFactor& f, CMatView Yin,
+                     int rows_in, MatView Yout, int nc);
+
+// Copy the k x n upper trapezoid of A (zeros below the diagonal) to R.
 void extract_r(hipStream_t s, const double* A, int k, int n, long ld,
-               double* R, long ldr);
+               MatView R);
+
+// out (rows x cols) <- in for rows < rows_in, 0 below; any strides.
+void copy_view(hipStream_t s, CMatView in, int rows_in, MatView out, int rows,
+               int cols);
 
 // Truncated SVD of the row-major m x c matrix X (leading dimension ldx).
 // Keeps D = min(cap, rank rule(tol)) singular triplets, D >= 1.

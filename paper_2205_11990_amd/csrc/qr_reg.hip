@@ -149,8 +149,8 @@ __device__ __forceinline__ void factor_block(double (&x)[RPL][CPW], int w,
 
 template <int CPW, int RPL>
 __global__ __launch_bounds__(FT) void qr_reg_factor_kernel(
-    const double* A, long lda, int m, int n, double* R, long ldr,
-    double* __restrict__ V, double* __restrict__ tau) {
+    CMatView A, int m, int n, MatView R, double* __restrict__ V,
+    double* __restrict__ tau) {
   __shared__ double vb[2 * 64 * RPL];
   __shared__ double tb[2];
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
@@ -161,7 +161,7 @@ __global__ __launch_bounds__(FT) void qr_reg_factor_kernel(
 #pragma unroll
     for (int b = 0; b < CPW; ++b) {
       const int i = l + 64 * a, j = w + 16 * b;
-      x[a][b] = (i < m && j < n) ? A[(long)i * lda + j] : 0.0;
+      x[a][b] = (i < m && j < n) ? A.p[(long)i * A.rs + (long)j * A.cs] : 0.0;
     }
   factor_block<CPW, RPL, 0>(x, w, l, m, k, vb, tb, V, tau);
   // every wave has passed the first barrier, so A (which R may alias) has
@@ -173,7 +173,7 @@ __global__ __launch_bounds__(FT) void qr_reg_factor_kernel(
 #pragma unroll
     for (int a = 0; a < RPL; ++a) {
       const int i = l + 64 * a;
-      if (i < k) R[(long)i * ldr + j] = (i <= j) ? x[a][b] : 0.0;
+      if (i < k) R.p[(long)i * R.rs + (long)j * R.cs] = (i <= j) ? x[a][b] : 0.0;
       if (RPL == 32 && j < k && i < m)
         V[(long)j * m + i] = (i > j) ? x[a][b] : (i == j ? 1.0 : 0.0);
     }
@@ -188,8 +188,8 @@ __global__ __launch_bounds__(FT) void qr_reg_factor_kernel(
 // wave-per-column layout when the rows fit in 16 * RPT <= 256.
 template <int CPG, int RPT>
 __global__ __launch_bounds__(FT) void qr_g16_factor_kernel(
-    const double* A, long lda, int m, int n, double* R, long ldr,
-    double* __restrict__ V, double* __restrict__ tau) {
+    CMatView A, int m, int n, MatView R, double* __restrict__ V,
+    double* __restrict__ tau) {
   __shared__ double vb[2 * 16 * RPT];
   __shared__ double tb[2];
   const int tid = threadIdx.x, g = tid >> 4, lig = tid & 15;
@@ -200,7 +200,7 @@ __global__ __launch_bounds__(FT) void qr_g16_factor_kernel(
 #pragma unroll
     for (int a = 0; a < RPT; ++a) {
       const int i = lig + 16 * a, j = g + 64 * c;
-      x[c][a] = (i < m && j < n) ? A[(long)i * lda + j] : 0.0;
+      x[c][a] = (i < m && j < n) ? A.p[(long)i * A.rs + (long)j * A.cs] : 0.0;
     }
   for (int j = 0; j < k; ++j) {
     const int og = j & 63, os = j >> 6, buf = j & 1;
@@ -268,7 +268,7 @@ __global__ __launch_bounds__(FT) void qr_g16_factor_kernel(
 #pragma unroll
     for (int a = 0; a < RPT; ++a) {
       const int i = lig + 16 * a;
-      if (i < k) R[(long)i * ldr + j] = (i <= j) ? x[c][a] : 0.0;
+      if (i < k) R.p[(long)i * R.rs + (long)j * R.cs] = (i <= j) ? x[c][a] : 0.0;
     }
   }
 }
@@ -393,8 +393,8 @@ __device__ __forceinline__ void blk_apply_panel(double (&x)[RPL][8], int p,
 
 template <int RPL>
 __global__ __launch_bounds__(FT) void qr_blk_factor_kernel(
-    const double* A, long lda, int m, int n, double* R, long ldr,
-    double* __restrict__ V, double* __restrict__ tau) {
+    CMatView A, int m, int n, MatView R, double* __restrict__ V,
+    double* __restrict__ tau) {
   __shared__ double vb[2 * 8 * 64 * RPL];
   __shared__ double tb[2 * 8];
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
@@ -406,7 +406,7 @@ __global__ __launch_bounds__(FT) void qr_blk_factor_kernel(
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
       const int i = l + 64 * a, j = 8 * w + b;
-      x[a][b] = (i < m && j < n) ? A[(long)i * lda + j] : 0.0;
+      x[a][b] = (i < m && j < n) ? A.p[(long)i * A.rs + (long)j * A.cs] : 0.0;
     }
   for (int p = 0; p < npan; ++p) {
     double* vbp = vb + (p & 1) * 8 * 64 * RPL;
@@ -424,7 +424,7 @@ __global__ __launch_bounds__(FT) void qr_blk_factor_kernel(
 #pragma unroll
     for (int a = 0; a < RPL; ++a) {
       const int i = l + 64 * a;
-      if (i < k) R[(long)i * ldr + j] = (i <= j) ? x[a][b] : 0.0;
+      if (i < k) R.p[(long)i * R.rs + (long)j * R.cs] = (i <= j) ? x[a][b] : 0.0;
       if (j < k && i < m) V[(long)j * m + i] = (i > j) ? x[a][b] : (i == j ? 1.0 : 0.0);
     }
   }
@@ -433,7 +433,7 @@ __global__ __launch_bounds__(FT) void qr_blk_factor_kernel(
 template <int CPW, int RPL>
 __global__ __launch_bounds__(AT) void qr_reg_apply_kernel(
     const double* __restrict__ V, const double* __restrict__ tau, int m, int k,
-    double* __restrict__ Y, long ldy, int p, int trans) {
+    CMatView Yin, int rows_in, MatView Yout, int p, int trans) {
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int c0 = (blockIdx.x * (AT / 64) + w) * CPW;
   if (c0 >= p) return;  // whole wave; the kernel has no barrier
@@ -443,7 +443,8 @@ __global__ __launch_bounds__(AT) void qr_reg_apply_kernel(
 #pragma unroll
     for (int b = 0; b < CPW; ++b) {
       const int i = l + 64 * a;
-      y[a][b] = (i < m && c0 + b < p) ? Y[(long)i * ldy + c0 + b] : 0.0;
+      y[a][b] = (i < rows_in && c0 + b < p)
+                    ? Yin.p[(long)i * Yin.rs + (long)(c0 + b) * Yin.cs] : 0.0;
     }
   double vn[RPL];
   {
@@ -490,7 +491,7 @@ __global__ __launch_bounds__(AT) void qr_reg_apply_kernel(
 #pragma unroll
     for (int b = 0; b < CPW; ++b) {
       const int i = l + 64 * a;
-      if (i < m && c0 + b < p) Y[(long)i * ldy + c0 + b] = y[a][b];
+      if (i < m && c0 + b < p) Yout.p[(long)i * Yout.rs + (long)(c0 + b) * Yout.cs] = y[a][b];
     }
 }
 
@@ -507,18 +508,19 @@ int cols_per_wave(int n) {
 }
 
 template <int CPW, int RPL>
-void launch_factor(hipStream_t s, const double* A, long lda, int m, int n,
-                   double* R, long ldr, double* V, double* tau) {
+void launch_factor(hipStream_t s, CMatView A, int m, int n, MatView R,
+                   double* V, double* tau) {
   hipLaunchKernelGGL((qr_reg_factor_kernel<CPW, RPL>), dim3(1), dim3(FT), 0, s,
-                     A, lda, m, n, R, ldr, V, tau);
+                     A, m, n, R, V, tau);
 }
 
 template <int CPW, int RPL>
 void launch_apply(hipStream_t s, const double* V, const double* tau, int m,
-                  int k, double* Y, long ldy, int p, int trans) {
+                  int k, CMatView Yin, int rows_in, MatView Yout, int p,
+                  int trans) {
   const int per_block = (AT / 64) * CPW;
   hipLaunchKernelGGL((qr_reg_apply_kernel<CPW, RPL>), dim3(ceil_div(p, per_block)),
-                     dim3(AT), 0, s, V, tau, m, k, Y, ldy, p, trans);
+                     dim3(AT), 0, s, V, tau, m, k, Yin, rows_in, Yout, p, trans);
 }
 
 }  // namespace
@@ -540,8 +542,8 @@ int qr_reg_panel_cols(int m) {
   return 16 * std::min(8, elems_per_lane(rpl) / rpl);
 }
 
-void qr_reg_factor(hipStream_t s, const double* A, long lda, int m, int n,
-                   double* R, long ldr, double* V, double* tau) {
+void qr_reg_factor(hipStream_t s, CMatView A, int m, int n, MatView R,
+                   double* V, double* tau) {
   MPSV_CHECK(qr_reg_fits(m, n), kEinval, "qr_reg_factor: shape does not fit");
   const int rpl = rows_per_lane(m), cpw = cols_per_wave(n);
   const int slot = prof_begin(s);
@@ -556,11 +558,11 @@ void qr_reg_factor(hipStream_t s, const double* A, long lda, int m, int n,
 #define MPSV_G(C, Rr)                                                   \
   if (g16 && cpg == C && rpt == Rr)                                     \
     hipLaunchKernelGGL((qr_g16_factor_kernel<C, Rr>), dim3(1), dim3(FT), 0, s, \
-                       A, lda, m, n, R, ldr, V, tau); else
+                       A, m, n, R, V, tau); else
 #define MPSV_F(C, Rr)                                                   \
-  if (cpw == C && rpl == Rr) launch_factor<C, Rr>(s, A, lda, m, n, R, ldr, V, tau); else
+  if (cpw == C && rpl == Rr) launch_factor<C, Rr>(s, A, m, n, R, V, tau); else
   if (blk)
-    hipLaunchKernelGGL((qr_blk_factor_kernel<2>), dim3(1), dim3(FT), 0, s, A, lda, m, n, R, ldr, V, tau);
+    hipLaunchKernelGGL((qr_blk_factor_kernel<2>), dim3(1), dim3(FT), 0, s, A, m, n, R, V, tau);
   else
   MPSV_G(1, 2) MPSV_G(1, 4) MPSV_G(2, 2) MPSV_G(2, 4)
   MPSV_F(1, 1) MPSV_F(2, 1) MPSV_F(4, 1) MPSV_F(8, 1)
@@ -582,7 +584,8 @@ void qr_reg_factor(hipStream_t s, const double* A, long lda, int m, int n,
 }
 
 void qr_reg_apply(hipStream_t s, const double* V, const double* tau, int m,
-                  int k, double* Y, long ldy, int p, bool trans) {
+                  int k, CMatView Yin, int rows_in, MatView Yout, int p,
+                  bool trans) {
   if (p <= 0 || k <= 0) return;
   MPSV_CHECK(m >= 1 && m <= 2048 && k <= m, kEinval, "qr_reg_apply: bad shape");
   const int rpl = rows_per_lane(m);
@@ -590,7 +593,7 @@ void qr_reg_apply(hipStream_t s, const double* V, const double* tau, int m,
   const int slot = prof_begin(s);
   const int tr = trans ? 1 : 0;
 #define MPSV_A(C, Rr)                                                   \
-  if (cpw == C && rpl == Rr) launch_apply<C, Rr>(s, V, tau, m, k, Y, ldy, p, tr); else
+  if (cpw == C && rpl == Rr) launch_apply<C, Rr>(s, V, tau, m, k, Yin, rows_in, Yout, p, tr); else
   MPSV_A(1, 1) MPSV_A(2, 1) MPSV_A(1, 2) MPSV_A(2, 2) MPSV_A(1, 4) MPSV_A(2, 4)
   MPSV_A(1, 8) MPSV_A(2, 8) MPSV_A(1, 16) MPSV_A(2, 16) MPSV_A(1, 32)
   throw Error(kEinval, "qr_reg_apply: no kernel for this shape");

@@ -10,18 +10,23 @@ bool qr_reg_fits(int m, int n);
 // Widest panel qr_reg_factor takes for m rows (m <= 2048).
 int qr_reg_panel_cols(int m);
 
-// Householder QR of A (m x n, row-major, leading dimension lda, read only
-// unless R aliases it).  Writes R (min(m,n) x n, zeros below the diagonal,
-// leading dimension ldr), the reflectors V (column-major m x k, V[j*m + i],
-// unit diagonal, zeros above) and tau (k); A = H_0 ... H_{k-1} [R; 0] with
-// H_j = I - tau_j v_j v_j^T (LAPACK sign conventions).
-void qr_reg_factor(hipStream_t s, const double* A, long lda, int m, int n,
-                   double* R, long ldr, double* V, double* tau);
+// Householder QR of A (m x n, element (i, j) at A.p[i*A.rs + j*A.cs], read
+// only unless R aliases it with the same strides).  Writes R (min(m,n) x n,
+// zeros below the diagonal, element (i, j) at R.p[i*R.rs + j*R.cs]), the
+// reflectors V (column-major m x k, V[j*m + i], unit diagonal, zeros above)
+// and tau (k); A = H_0 ... H_{k-1} [R; 0] with H_j = I - tau_j v_j v_j^T
+// (LAPACK sign conventions).  Strided views let callers factor a transpose
+// or write R^T without a copy.
+void qr_reg_factor(hipStream_t s, CMatView A, int m, int n, MatView R,
+                   double* V, double* tau);
 
-// Y (m x p, row-major, leading dimension ldy) <- Q Y (trans = false) or
-// Q^T Y (trans = true), Q = H_0 ... H_{k-1} from qr_reg_factor (V has m
-// rows).  Columns are spread over as many workgroups as needed; m <= 2048.
+// Yout <- Q Yin (trans = false) or Q^T Yin (trans = true), Q = H_0 ... H_{k-1}
+// from qr_reg_factor (V has m rows); both blocks m x p with element (i, j)
+// at p[i*rs + j*cs]; rows >= rows_in of Yin are taken as zero (not read).
+// Yout may alias Yin with the same strides.  Columns are spread over as
+// many workgroups as needed; m <= 2048.
 void qr_reg_apply(hipStream_t s, const double* V, const double* tau, int m,
-                  int k, double* Y, long ldy, int p, bool trans);
+                  int k, CMatView Yin, int rows_in, MatView Yout, int p,
+                  bool trans);
 
 }  // namespace mpsv

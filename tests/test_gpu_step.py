@@ -210,3 +210,30 @@ def test_errors_leave_state_unchanged(B):
     assert st.info()["steps"] == 0
     st.step(1)
     assert st.info()["steps"] == 1
+
+
+def test_full_size_bench_workload_matches_mps_oracle(B):
+    """The benchmarked configuration itself: two-stream 2^10 x 2^10,
+    interleaved, chi = 64, every compression capped (C5), D_F = 4, from the
+    perturbed state the benchmark uses, stepped exactly as bench.py steps
+    it (side-stream T1).  One RK4 step on the GPU and in the CPU MPS oracle
+    from the same cores: reconstructed f and E within 1e-8 (observed
+    ~3e-13 and ~4e-12), identical bond dimensions."""
+    _say("full size two-stream 2^10 chi64 C5")
+    w = wl.two_stream(L=10, chi=64, tol=0.0, level=5, df_max=4, dt_cfg=0.02)
+    p = w.problem
+    st = B.MpsState(p, w.ax, w.bv)
+    pert = wl.random_mps_cores(p.n_sites, 64, seed=2205)
+    st.add_scaled(1e-6 * float(np.linalg.norm(w.ax) * np.linalg.norm(w.bv)), pert)
+    f0 = st.get_cores_host()
+    st.step(1)
+    G = st.to_dense().cpu().numpy()
+    _, E, _ = st.moments()
+    ops = omps.Operators(p)
+    f = omps.rk4_step(f0, ops)
+    R = omps.to_dense(f, p)
+    Eref = omps.field_dense(f, ops)
+    assert np.abs(G - R).max() <= 1e-8 * np.abs(R).max()
+    assert np.abs(E.cpu().numpy() - Eref).max() <= 1e-8 * np.abs(Eref).max()
+    assert st.info()["bonds"][1:-1] == omps.bond_dims(f)
+    st.free()
