@@ -20,6 +20,14 @@ mps_status mpsb_gemm(int32_t M, int32_t N, int32_t K, double alpha,
                      int64_t ldb, double beta, double* C, int64_t ldc,
                      hipStream_t stream);
 
+/* mpsb_gemm with the precision of the MPO x MPS contractions: MPS_PREC_FP64
+ * or MPS_PREC_FP32_CONTRACT (operands rounded to FP32, FP32 accumulation on
+ * the matrix cores, result stored in FP64).  MPS_EINVAL for other values. */
+mps_status mpsb_gemm_prec(int32_t M, int32_t N, int32_t K, double alpha,
+                          const double* A, int64_t lda, const double* B,
+                          int64_t ldb, double beta, double* C, int64_t ldc,
+                          int32_t precision, hipStream_t stream);
+
 /* Householder QR of A (m x n, device, overwritten): on return the upper
  * trapezoid of A holds R (min(m,n) x n); if Q is not NULL it receives the
  * thin factor Q (m x min(m,n), device).  Used by the QR left sweep (SI,
@@ -74,6 +82,13 @@ mps_status mpsb_density_field(mps_state* h, double* n_out, double* E_out,
  * *count. */
 mps_status mpsb_operator(int32_t which, int32_t L, double h0, double h,
                          int32_t* bonds, double* W, int64_t* count);
+
+/* Device memory of one state, per arena in the order operators, committed
+ * state, step intermediates, right-hand-side intermediates, compression
+ * workspace, and the right-hand-side and compression arenas of the side
+ * lane: reserved[7] gets the bytes each holds, peak[7] the largest extent
+ * each has had in use.  Host outputs. */
+mps_status mpsb_arena_bytes(const mps_state* h, size_t* reserved, size_t* peak);
 
 /* Linear-algebra counters since load: QR and SVD calls, Jacobi sweeps. */
 mps_status mpsb_stats(int64_t* qr_calls, int64_t* svd_calls,

@@ -59,6 +59,10 @@ typedef enum {
 
 typedef enum { MPS_ORDER_SEQ = 0, MPS_ORDER_INTERLEAVED = 1 } mps_order;
 
+/* Arithmetic of the MPO x MPS contractions (SI, "Matrix-vector
+ * multiplication"): FP64, or operands rounded to FP32 with FP32
+ * accumulation on the matrix cores (results kept in FP64).  The QR and SVD
+ * sweeps, the Poisson field and the moments are FP64 in both modes. */
 typedef enum { MPS_PREC_FP64 = 0, MPS_PREC_FP32_CONTRACT = 1 } mps_precision;
 
 /* Problem statement.  Site orderings (Fig. 3): MPS_ORDER_SEQ is x bits
@@ -132,10 +136,21 @@ mps_status mps_set_cores(mps_state* h, const int32_t* bond_dims,
 mps_status mps_add_scaled(mps_state* h, double alpha, const int32_t* bond_dims,
                           const double* cores, hipStream_t stream);
 
-/* Upper bound of the device bytes a state of problem p holds between
- * steps plus the largest per-step workspace when every compression point
- * is capped at chi_max (for admission control).  Host output. */
+/* Device bytes a state of problem p may hold (for admission control of
+ * several states sharing one GPU's memory), host output.  A size model per
+ * arena, from the chi-capped state, the widest contraction of the field
+ * term and the interleaved initial state at full rank, with coefficients
+ * that envelope measured peaks (grids 2^6..2^13, chi 16..128, both
+ * orderings), plus chunk rounding and a fixed allowance; it assumes every
+ * compression point stays within chi_max (level 5, or lower levels whose
+ * tolerance keeps the bonds there).  EINVAL for Lx, Lv outside [2, 14] or
+ * chi_max < 1. */
 mps_status mps_workspace_bound(const mps_problem* p, size_t* bytes);
+
+/* Device bytes the state h holds right now (all of its arenas: operators,
+ * committed state, step and compression workspace), host output.  The
+ * arenas keep their high-water mark between steps. */
+mps_status mps_device_bytes(const mps_state* h, size_t* bytes);
 
 /* Advance several independent states (parameter sweeps, uneven sizes) by
  * nsteps each.  Every instance runs on a stream of its own, driven by its

@@ -59,9 +59,11 @@ _SIGS = {
     "mps_set_cores": [_P, _PI32, _P, _P],
     "mps_add_scaled": [_P, _D, _PI32, _P, _P],
     "mps_workspace_bound": [ctypes.POINTER(CProblem), ctypes.POINTER(ctypes.c_size_t)],
+    "mps_device_bytes": [_P, ctypes.POINTER(ctypes.c_size_t)],
     "mps_step_batched": [ctypes.POINTER(_P), _I32, _I32, _P],
     "mps_last_error": [],
     "mpsb_gemm": [_I32, _I32, _I32, _D, _P, _I64, _P, _I64, _D, _P, _I64, _P],
+    "mpsb_gemm_prec": [_I32, _I32, _I32, _D, _P, _I64, _P, _I64, _D, _P, _I64, _I32, _P],
     "mpsb_qr": [_I32, _I32, _P, _P, _P],
     "mpsb_svd_truncate": [_I32, _I32, _P, _I32, _D, _P, _P, _P, _PI32, _PD, _P],
     "mpsb_compress": [_I32, _PI32, _P, _PI32, _P, _I32, _D, _PI32, _P, _I64, _PD, _P],
@@ -70,6 +72,7 @@ _SIGS = {
     "mpsb_density_field": [_P, _P, _P, _P],
     "mpsb_operator": [_I32, _I32, _D, _D, _PI32, _PD, _PI64],
     "mpsb_stats": [_PI64, _PI64, _PI64],
+    "mpsb_arena_bytes": [_P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)],
     "mpsb_set_jacobi_max_sweeps": [_I32],
     "mpsb_profile": [_I32],
     "mpsb_profile_read": [_I32, _PI64, _PD, _PD, _PD],
@@ -86,6 +89,9 @@ def lib() -> ctypes.CDLL:
             raise RuntimeError("HIP library %s is missing: run "
                                "`python -c 'import __graft_entry__ as g; g.build()'`"
                                % LIB_PATH)
+        # torch first: its HIP runtime is then the one the library binds to,
+        # so the process holds a single runtime whatever the import order
+        _torch()
         L = ctypes.CDLL(LIB_PATH)
         for name, args in _SIGS.items():
             f = getattr(L, name)
@@ -212,6 +218,18 @@ class MpsState:
         return {"n": n, "bonds": list(bonds), "discarded": list(disc)[:n - 1],
                 "t": t.value, "steps": st.value}
 
+    def device_bytes(self) -> int:
+        b = ctypes.c_size_t()
+        _check(lib().mps_device_bytes(self._h, ctypes.byref(b)))
+        return int(b.value)
+
+    def arena_bytes(self):
+        """(reserved, peak) bytes of the state's seven arenas."""
+        r = (ctypes.c_size_t * 7)()
+        p = (ctypes.c_size_t * 7)()
+        _check(lib().mpsb_arena_bytes(self._h, r, p))
+        return list(r), list(p)
+
     def get_cores(self, stream=None):
         torch = _torch()
         n = self.info()["n"]
@@ -263,7 +281,7 @@ def workspace_bound(problem) -> int:
 
 # ------------------------------------------------------------- blocks
 
-def gemm(A, B, alpha=1.0, beta=0.0, C=None, stream=None):
+def gemm(A, B, alpha=1.0, beta=0.0, C=None, stream=None, precision=0):
     torch = _torch()
     A, B = _dev(A), _dev(B)
     M, K = A.shape
@@ -271,8 +289,8 @@ def gemm(A, B, alpha=1.0, beta=0.0, C=None, stream=None):
     assert K == K2
     if C is None:
         C = torch.zeros(M, N, dtype=torch.float64, device="cuda")
-    _check(lib().mpsb_gemm(M, N, K, alpha, _ptr(A), K, _ptr(B), N, beta, _ptr(C), N,
-                           _stream(stream)))
+    _check(lib().mpsb_gemm_prec(M, N, K, alpha, _ptr(A), K, _ptr(B), N, beta, _ptr(C), N,
+                                int(precision), _stream(stream)))
     return C
 
 

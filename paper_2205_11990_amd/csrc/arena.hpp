@@ -30,6 +30,7 @@ class Arena {
       if (off_ + bytes <= chunks_[cur_].size) {
         void* p = (char*)chunks_[cur_].ptr + off_;
         off_ += bytes;
+        note_peak();
         return p;
       }
       ++cur_;
@@ -46,6 +47,7 @@ class Arena {
     chunks_.push_back({p, sz});
     cur_ = chunks_.size() - 1;
     off_ = bytes;
+    note_peak();
     return p;
   }
 
@@ -58,6 +60,9 @@ class Arena {
     cur_ = 0;
     off_ = 0;
   }
+  // largest extent ever in use: whole chunks before the current one plus
+  // the offset into it (chunk tails skipped by a larger request count too)
+  size_t peak_bytes() const { return peak_; }
   size_t reserved_bytes() const {
     size_t t = 0;
     for (auto& c : chunks_) t += c.size;
@@ -75,9 +80,14 @@ class Arena {
     void* ptr;
     size_t size;
   };
+  void note_peak() {
+    size_t used = off_;
+    for (size_t i = 0; i < cur_; ++i) used += chunks_[i].size;
+    if (used > peak_) peak_ = used;
+  }
   std::vector<Chunk> chunks_;
   size_t chunk_;
-  size_t cur_ = 0, off_ = 0;
+  size_t cur_ = 0, off_ = 0, peak_ = 0;
 };
 
 // RAII scope: everything allocated inside is released at scope exit.

@@ -256,22 +256,23 @@ mps_status mps_workspace_bound(const mps_problem* p, size_t* bytes) {
     MPSV_CHECK(q.Lx >= 2 && q.Lx <= 14 && q.Lv >= 2 && q.Lv <= 14,
                mpsv::kEinval, "Lx and Lv must lie in [2, 14]");
     MPSV_CHECK(q.chi_max >= 1, mpsv::kEinval, "chi_max must be >= 1");
-    const int n = q.n();
-    const double chi = q.chi_max;
-    // widest MPO: the field term, 5 * D_F (interleaved) or max(D_F, 5)
-    const double df = q.df_max > 0 ? q.df_max : chi;
-    const double w = (q.order == 1) ? 5.0 * df : std::max(df, 5.0);
-    double state = 0, work = 0;
-    for (int j = 0; j < n; ++j) {
-      double bl = std::min(chi, std::ldexp(1.0, std::min(j, n - j)));
-      double br = std::min(chi, std::ldexp(1.0, std::min(j + 1, n - j - 1)));
-      state += bl * 2 * br;
-      double rl = std::min(w * bl, std::ldexp(1.0, std::min(j, n - j)));
-      double rr = std::min(w * br, std::ldexp(1.0, std::min(j + 1, n - j - 1)));
-      work = std::max(work, 4.0 * rl * 2 * rr);
-    }
-    // committed state + ~16 step intermediates + the compression workspace
-    *bytes = (size_t)(8.0 * (17.0 * state + 4.0 * work)) + ((size_t)64 << 20);
+    *bytes = mpsv::memory_model(q).bound;
+  });
+}
+
+mps_status mps_device_bytes(const mps_state* h, size_t* bytes) {
+  return guarded([&] {
+    check_handle(h);
+    MPSV_CHECK(bytes != nullptr, mpsv::kEinval, "bytes is NULL");
+    *bytes = h->eng->device_bytes();
+  });
+}
+
+mps_status mpsb_arena_bytes(const mps_state* h, size_t* reserved, size_t* peak) {
+  return guarded([&] {
+    check_handle(h);
+    MPSV_CHECK(reserved != nullptr && peak != nullptr, mpsv::kEinval, "NULL argument");
+    h->eng->arena_bytes(reserved, peak);
   });
 }
 
@@ -342,12 +343,23 @@ mps_status mpsb_gemm(int32_t M, int32_t N, int32_t K, double alpha,
                      const double* A, int64_t lda, const double* B,
                      int64_t ldb, double beta, double* C, int64_t ldc,
                      hipStream_t stream) {
+  return mpsb_gemm_prec(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
+                        MPS_PREC_FP64, stream);
+}
+
+mps_status mpsb_gemm_prec(int32_t M, int32_t N, int32_t K, double alpha,
+                          const double* A, int64_t lda, const double* B,
+                          int64_t ldb, double beta, double* C, int64_t ldc,
+                          int32_t precision, hipStream_t stream) {
   return guarded([&] {
     MPSV_CHECK(M >= 0 && N >= 0 && K >= 0, mpsv::kEinval, "negative size");
     MPSV_CHECK(lda >= K && ldb >= N && ldc >= N, mpsv::kEinval,
                "leading dimension too small");
+    MPSV_CHECK(precision == MPS_PREC_FP64 || precision == MPS_PREC_FP32_CONTRACT,
+               mpsv::kEinval, "unknown precision");
     mpsv::gemm(stream, M, N, K, alpha, mpsv::CMatView{A, lda, 1, 0},
-               mpsv::CMatView{B, ldb, 1, 0}, beta, mpsv::MatView{C, ldc, 1, 0});
+               mpsv::CMatView{B, ldb, 1, 0}, beta, mpsv::MatView{C, ldc, 1, 0},
+               1, precision == MPS_PREC_FP32_CONTRACT);
     MPSV_HIP(hipStreamSynchronize(stream));
   });
 }

@@ -289,7 +289,59 @@ HostMpo chain_mps(const HostMpo& Ax, const std::vector<int>& bx,
 
 static int cap_or_inf(int c) { return c > 0 ? c : INT_MAX; }
 
-Engine::Engine(const Problem& p) : p_(p) {
+MemoryModel memory_model(const Problem& q) {
+  const int n = q.n();
+  const double chi = q.chi_max;
+  auto full = [&](int j) { return std::ldexp(1.0, std::min(j, n - j)); };
+  // field bond: the cap D_F, at most the full rank of an Lx-site MPS
+  const double df = std::min(q.df_max > 0 ? (double)q.df_max : chi,
+                             std::ldexp(1.0, q.Lx / 2));
+  const double w = (q.order == 1 ? 5.0 : 3.0) * df;  // field-term MPO bond
+  double S = 0, N = 0, I = 0;
+  for (int j = 0; j < n; ++j) {
+    const double bl = std::min(chi, full(j)), br = std::min(chi, full(j + 1));
+    S += bl * 2 * br;
+    N = std::max(N, std::min(w * bl, full(j)) * w * 2 * br);
+  }
+  if (q.order == 1) {
+    // interleaved initial state: Kronecker products of the x and v cores
+    auto fr = [&](int k) { return std::ldexp(1.0, std::min(k, q.Lx - k)); };
+    for (int k = 0; k < q.Lx; ++k)
+      I += fr(k) * fr(k) * 2 * fr(k + 1) * fr(k) +
+           fr(k) * fr(k + 1) * 2 * fr(k + 1) * fr(k + 1);
+  }
+  S *= 8.0;
+  N *= 8.0;
+  I *= 8.0;
+  const double work = q.order == 1 ? std::max({12.0 * N, 3.5 * I, 60.0 * S}) : 60.0 * S;
+  const double est[7] = {1.0 * (1 << 20), 2.0 * S, 1.5 * I + 12.0 * S, 40.0 * S,
+                         work, 40.0 * S, 80.0 * S};
+  MemoryModel m;
+  m.chunk = (size_t)std::min(64.0 * (1 << 20), std::max(2.0 * (1 << 20), 8.0 * S));
+  m.chunk = (m.chunk + 255) & ~(size_t)255;
+  m.bound = (size_t)32 << 20;
+  for (int i = 0; i < 7; ++i) {
+    m.arena[i] = (size_t)est[i];
+    m.bound += m.arena[i] + 2 * m.chunk;
+  }
+  return m;
+}
+
+size_t Engine::device_bytes() const {
+  return ops_.reserved_bytes() + state_.reserved_bytes() + step_.reserved_bytes() +
+         tmp_.reserved_bytes() + work_.reserved_bytes() + tmp2_.reserved_bytes() +
+         work2_.reserved_bytes();
+}
+
+void Engine::arena_bytes(size_t reserved[7], size_t peak[7]) const {
+  const Arena* a[7] = {&ops_, &state_, &step_, &tmp_, &work_, &tmp2_, &work2_};
+  for (int i = 0; i < 7; ++i) {
+    reserved[i] = a[i]->reserved_bytes();
+    peak[i] = a[i]->peak_bytes();
+  }
+}
+
+Engine::Engine(const Problem& p) : p_(p), chunk_(memory_model(p).chunk) {
   MPSV_CHECK(p.Lx >= 2 && p.Lx <= 14 && p.Lv >= 2 && p.Lv <= 14, kEinval,
              "Lx and Lv must lie in [2, 14]");
   MPSV_CHECK(p.order == 0 || p.order == 1, kEinval, "unknown ordering");
@@ -410,11 +462,12 @@ void Engine::absorb_left(const VSite& v, const double* R, int p, double* M,
       double* X = work().alloc((size_t)p * wl * 2 * ar);
       // X[(p,b)][(i,a')] = sum_a R[p][(b,a)] A[a][i][a']
       gemm(s, p * wl, 2 * ar, al, 1.0, CMatView{R, al, 1, 0},
-           CMatView{v.A.p, 2L * ar, 1, 0}, 0.0, MatView{X, 2L * ar, 1, 0});
+           CMatView{v.A.p, 2L * ar, 1, 0}, 0.0, MatView{X, 2L * ar, 1, 0}, 1,
+           f32_contract());
       // M_p[(o,b')][a'] = sum_(b,i) Wmat[(o,b')][(b,i)] X_p[(b,i)][a']
       gemm(s, 2 * wr, ar, 2 * wl, 1.0, CMatView{v.W.Wmat, 2L * wl, 1, 0},
            CMatView{X, ar, 1, 2L * wl * ar}, 0.0,
-           MatView{M, ar, 1, 2L * wr * ar}, p);
+           MatView{M, ar, 1, 2L * wr * ar}, p, f32_contract());
       break;
     }
     case VSite::kSum: {
@@ -463,12 +516,12 @@ void Engine::absorb_right(const VSite& v, const double* L, int q, double* N,
       double* Z = work().alloc((size_t)al * 2 * wr * q);
       gemm(s, 2 * al, q, ar, 1.0, CMatView{v.A.p, ar, 1, 0},
            CMatView{L, q, 1, (long)ar * q}, 0.0,
-           MatView{Z, (long)wr * q, 1, q}, wr);
+           MatView{Z, (long)wr * q, 1, q}, wr, f32_contract());
       // N'[a][(b,o)][q] = sum_(i,b') W[(b,o)][(i,b')] Z[a][(i,b')][q]
       double* Np = work().alloc((size_t)al * wl * 2 * q);
       gemm(s, 2 * wl, q, 2 * wr, 1.0, CMatView{v.W.W, 2L * wr, 1, 0},
            CMatView{Z, q, 1, 2L * wr * q}, 0.0,
-           MatView{Np, q, 1, 2L * wl * q}, al);
+           MatView{Np, q, 1, 2L * wl * q}, al, f32_contract());
       // N[b][a][o][q] = N'[a][b][o][q]
       swap01(s, Np, al, wl, 2L * q, N);
       break;

@@ -51,6 +51,22 @@ struct VSite {
   int pos = 1;                               // kSum: 0 first, 1 middle, 2 last
 };
 
+// Device-memory model of one instance, for admission control.  Per arena
+// (operators, committed state, step, rhs, compression, side rhs, side
+// compression) `arena[i]` estimates the peak extent in use from three sizes
+// at the bond caps: the state S (sum of the chi-capped cores), the widest
+// MPO x MPS site contraction N of the field term (interleaved ordering) and
+// the size I of the interleaved initial state built from the x and v
+// profiles at full rank.  The coefficients envelope the peaks measured
+// over 2^6..2^13 grids, chi 16..128, both orderings and D_F in {4, chi}.
+// `chunk` is the arena chunk size; `bound` adds two chunks per arena for
+// rounding and a fixed 32 MiB.
+struct MemoryModel {
+  size_t arena[7];
+  size_t chunk, bound;
+};
+MemoryModel memory_model(const Problem& p);
+
 struct StepTimers {
   double compress_ms = 0;
 };
@@ -84,6 +100,11 @@ class Engine {
   // A stream owned by this instance (batched stepping runs each instance on
   // its own stream).
   hipStream_t own_stream() const { return own_; }
+  // device bytes currently held by this state's arenas
+  size_t device_bytes() const;
+  // per arena (operators, state, step, rhs, compression, side rhs, side
+  // compression): reserved bytes and peak extent in use
+  void arena_bytes(size_t reserved[7], size_t peak[7]) const;
 
   // ---- outputs
   void to_dense(double* out, hipStream_t s);
@@ -122,15 +143,20 @@ class Engine {
   // Compression workspace of the calling thread: work_ on the thread that
   // drives the engine, work2_ on the side thread of rhs().
   Arena& work();
+  // MPO x MPS contractions in FP32 on the matrix cores (precision mode 1);
+  // factorisations, Poisson field and moments stay FP64.
+  bool f32_contract() const { return p_.precision == 1; }
 
   Problem p_;
-  Arena ops_{(size_t)16 << 20};    // operators (persistent)
-  Arena state_{(size_t)16 << 20};  // committed state
-  Arena step_;                     // per-step intermediates
-  Arena tmp_;                      // per-RHS intermediates
-  Arena work_;                     // per-compression workspace
-  Arena tmp2_;                     // per-RHS intermediates of the side lane
-  Arena work2_;                    // compression workspace of the side lane
+  // chunk size of the arenas, scaled to the problem (see memory_model)
+  size_t chunk_;
+  Arena ops_{chunk_};              // operators (persistent)
+  Arena state_{chunk_};            // committed state
+  Arena step_{chunk_};             // per-step intermediates
+  Arena tmp_{chunk_};              // per-RHS intermediates
+  Arena work_{chunk_};             // per-compression workspace
+  Arena tmp2_{chunk_};             // per-RHS intermediates of the side lane
+  Arena work2_{chunk_};            // compression workspace of the side lane
   int device_ = 0;                 // the device the instance lives on
   hipStream_t own_ = nullptr;      // this instance's stream (batched mode)
   hipStream_t side_ = nullptr;     // T1 runs here, beside T2

@@ -98,6 +98,87 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(
       }
 }
 
+// FP32-contraction variant (the MPS problem's precision mode 1): the FP64
+// operands are rounded to FP32 as they are staged in LDS, the products are
+// accumulated in FP32 by v_mfma_f32_16x16x4f32, and the result is stored as
+// FP64.  Same tiling and views as gemm_f64_kernel.
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(NT) void gemm_f32acc_kernel(
+    int M, int N, int K, double alpha, const double* __restrict__ A, long ars,
+    long acs, long abs_, const double* __restrict__ B, long brs, long bcs,
+    long bbs, double beta, double* __restrict__ C, long crs, long ccs, long cbs,
+    int a_kfast, int b_nfast, int nsplit, int kchunk) {
+  __shared__ float As[BK][BM + 1];
+  __shared__ float Bs[BK][BN + 1];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const long bz = blockIdx.z / nsplit;
+  const int split = blockIdx.z % nsplit;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  A += bz * abs_;
+  B += bz * bbs;
+  C += bz * cbs + (long)split * M * N * (nsplit > 1 ? 1 : 0);
+  const int kbeg = split * kchunk;
+  const int kend = (kbeg + kchunk < K) ? kbeg + kchunk : K;
+
+  flt4 acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = flt4{0.0f, 0.0f, 0.0f, 0.0f};
+
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+#pragma unroll
+    for (int q = 0; q < (BM * BK) / NT; ++q) {
+      int e = tid + q * NT;
+      int r, k;
+      if (a_kfast) { r = e / BK; k = e % BK; } else { k = e / BM; r = e % BM; }
+      int gr = m0 + r, gk = k0 + k;
+      As[k][r] = (gr < M && gk < kend) ? (float)A[(long)gr * ars + (long)gk * acs] : 0.0f;
+    }
+#pragma unroll
+    for (int q = 0; q < (BN * BK) / NT; ++q) {
+      int e = tid + q * NT;
+      int c, k;
+      if (b_nfast) { k = e / BN; c = e % BN; } else { c = e / BK; k = e % BK; }
+      int gc = n0 + c, gk = k0 + k;
+      Bs[k][c] = (gc < N && gk < kend) ? (float)B[(long)gk * brs + (long)gc * bcs] : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      const float a0 = As[kr][wm * 32 + (lane & 15)];
+      const float a1 = As[kr][wm * 32 + 16 + (lane & 15)];
+      const float b0 = Bs[kr][wn * 32 + (lane & 15)];
+      const float b1 = Bs[kr][wn * 32 + 16 + (lane & 15)];
+      acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+
+  // D layout of the 16x16 f32 block: lane l, item r -> row 4*(l/16) + r,
+  // col l%16
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int gr = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
+        int gc = n0 + wn * 32 + j * 16 + (lane & 15);
+        if (gr < M && gc < N) {
+          double* cp = C + (long)gr * crs + (long)gc * ccs;
+          double v = alpha * (double)acc[i][j][r];
+          *cp = (beta == 0.0) ? v : v + beta * (*cp);
+        }
+      }
+}
+
 // C[b] = alpha * sum_s P[b*nsplit + s] + beta * C[b]
 __global__ void splitk_reduce_kernel(int M, int N, int nsplit, double alpha,
                                      const double* __restrict__ P, double beta,
@@ -142,7 +223,7 @@ double* splitk_scratch(hipStream_t s, size_t n) {
 }  // namespace
 
 void gemm(hipStream_t s, int M, int N, int K, double alpha, CMatView A,
-          CMatView B, double beta, MatView C, int batch) {
+          CMatView B, double beta, MatView C, int batch, bool f32) {
   if (M <= 0 || N <= 0 || batch <= 0) return;
   if (K <= 0) {
     // C = beta * C
@@ -167,7 +248,8 @@ void gemm(hipStream_t s, int M, int N, int K, double alpha, CMatView A,
     dim3 grid(ceil_div(N, BN), ceil_div(M, BM), nb * nsplit);
     const int slot = prof_begin(s);
     if (nsplit == 1) {
-      hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(NT), 0, s, M, N, K, alpha,
+      hipLaunchKernelGGL(f32 ? gemm_f32acc_kernel : gemm_f64_kernel, grid,
+                         dim3(NT), 0, s, M, N, K, alpha,
                          A.p + (long)b0 * A.bs, A.rs, A.cs, A.bs,
                          B.p + (long)b0 * B.bs, B.rs, B.cs, B.bs, beta,
                          C.p + (long)b0 * C.bs, C.rs, C.cs, C.bs, a_kfast,
@@ -175,7 +257,8 @@ void gemm(hipStream_t s, int M, int N, int K, double alpha, CMatView A,
       MPSV_LAUNCHED();
     } else {
       double* P = splitk_scratch(s, (size_t)nb * nsplit * M * N);
-      hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(NT), 0, s, M, N, K, 1.0,
+      hipLaunchKernelGGL(f32 ? gemm_f32acc_kernel : gemm_f64_kernel, grid,
+                         dim3(NT), 0, s, M, N, K, 1.0,
                          A.p + (long)b0 * A.bs, A.rs, A.cs, A.bs,
                          B.p + (long)b0 * B.bs, B.rs, B.cs, B.bs, 0.0, P,
                          (long)N, 1L, (long)nsplit * M * N, a_kfast, b_nfast,

@@ -5,9 +5,11 @@
 namespace mpsv {
 
 // C[b] = alpha * A[b] * B[b] + beta * C[b]; A is M x K, B is K x N.
-// beta == 0 never reads C.  Stream-ordered, no synchronisation.
+// beta == 0 never reads C.  Stream-ordered, no synchronisation.  With f32
+// the products are formed from FP32-rounded operands and accumulated in
+// FP32 on the matrix cores (results stored in FP64).
 void gemm(hipStream_t s, int M, int N, int K, double alpha, CMatView A,
-          CMatView B, double beta, MatView C, int batch = 1);
+          CMatView B, double beta, MatView C, int batch = 1, bool f32 = false);
 
 // C[b] = beta * C[b] (beta == 0 writes zeros without reading).
 void scale_matrix(hipStream_t s, int M, int N, double beta, MatView C,

@@ -40,6 +40,24 @@ def test_gemm_matches_numpy(B, M, N, K):
     assert np.abs(out - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max()) * np.sqrt(K)
 
 
+@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (7, 5, 3), (64, 64, 16), (65, 130, 33),
+                                   (300, 17, 129), (16, 1000, 2)])
+def test_gemm_fp32_contract_matches_fp32_rounded_product(B, M, N, K):
+    """Precision mode 1: the product of the FP32-rounded operands,
+    accumulated in FP32 (checked against the exact product of the rounded
+    operands at FP32 accumulation accuracy)."""
+    _say("gemm fp32 %d %d %d" % (M, N, K))
+    rng = np.random.default_rng(M * 1000 + N * 10 + K + 1)
+    A = rng.standard_normal((M, K))
+    Bm = rng.standard_normal((K, N))
+    out = B.gemm(A, Bm, alpha=0.5, precision=1).cpu().numpy()
+    Ar = A.astype(np.float32).astype(np.float64)
+    Br = Bm.astype(np.float32).astype(np.float64)
+    ref = 0.5 * Ar @ Br
+    scale = 0.5 * (np.abs(Ar) @ np.abs(Br))
+    assert np.all(np.abs(out - ref) <= 4 * K * 6e-8 * scale + 1e-30)
+
+
 @pytest.mark.parametrize("m,n", [(1, 1), (5, 3), (3, 5), (40, 40), (130, 70), (257, 33),
                                  (600, 200), (2048, 8), (64, 300), (128, 128), (256, 128),
                                  (512, 64), (1024, 128), (1000, 100), (200, 129), (700, 700),
