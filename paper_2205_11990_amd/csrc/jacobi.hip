@@ -29,6 +29,16 @@
 // rotation.  Columns below 1e-15 of the Frobenius norm are numerical zeros
 // and are never rotated.
 //
+// From 129 to 256 columns the matrix no longer fits in one compute unit:
+// two workgroups of 64 nodes each hold half of the 128 nodes (rows up to
+// 256, 16 per lane), and the top cube dimension joins them.  Only two moves
+// per sweep (the exchange across the top dimension and one step of its Gray
+// code) cross it; they go through global memory, with a rendezvous of the
+// two workgroups on release/acquire flags at device scope.  Each wait for
+// the partner is bounded; a rendezvous that times out ends both workgroups
+// and is reported instead of a result.  The end-of-sweep decision uses both
+// workgroups' convergence flags, so both run the same number of sweeps.
+//
 // On exit: singular values are the column norms, sorted descending (ties by
 // index), the truncation rank D follows the rule min(cap, smallest D' whose
 // relative discarded weight is <= tol) (eq. 5 with the i = D+1 reading), and
@@ -37,6 +47,7 @@
 #include <mutex>
 
 #include "jacobi.hpp"
+#include "mps_kernels.hpp"
 #include "wave.hpp"
 
 namespace mpsv {
@@ -358,6 +369,399 @@ __global__ __launch_bounds__(MAXT) void jacobi_hc_kernel(
   }
 }
 
+// ------------------------------------------------ two workgroups (k <= 256)
+
+constexpr int kPairRpt = 16;                  // rows per lane: up to 256 rows
+constexpr int kPairNodes = 64;                // nodes per workgroup
+constexpr int kPairStride = 16 * kPairRpt + 16;  // padded LDS column slot
+constexpr long kSpinLimit = 1L << 22;         // polls, about a second
+
+// Global exchange area of the two workgroups (see jacobi_ws_doubles).
+struct PairWs {
+  double* xg;    // [wg][parity][node][256] outgoing columns
+  double* xn;    // [wg][parity][node] their squared norms
+  double* val;   // [wg][parity] rendezvous payload
+  int* xi;       // [wg][parity][node] their indices
+  int* flags;    // [wg] last epoch published (zeroed before the launch)
+};
+
+__device__ inline void flag_publish(int* f, int v) {
+  __hip_atomic_store(f, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline int flag_read(int* f) {
+  return __hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Rendezvous number `e` of the two workgroups: every thread's earlier
+// global stores become visible to the partner, `mine` is published and the
+// partner's value of the same rendezvous returned in `other`.  False (for
+// the whole workgroup) when the partner does not arrive within the spin
+// limit.
+__device__ bool meet(const PairWs& w, int wg, int e, double mine,
+                     double& other, int* sh_ok, double* sh_val) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    w.val[wg * 2 + (e & 1)] = mine;
+    flag_publish(w.flags + wg, e);
+    long spins = 0;
+    int ok = 1;
+    while (flag_read(w.flags + (wg ^ 1)) < e) {
+      if (++spins > kSpinLimit) {
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(8);
+    }
+    *sh_ok = ok;
+    *sh_val = ok ? w.val[(wg ^ 1) * 2 + (e & 1)] : 0.0;
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  other = *sh_val;
+  return *sh_ok != 0;
+}
+
+// Info: [0] D, [1] discarded weight, [2] sweeps, [3] converged, [4] steps,
+// [5] 1 if a rendezvous timed out.  Same inputs and outputs as
+// jacobi_hc_kernel; launched as exactly two workgroups of 1024 threads.
+__global__ __launch_bounds__(MAXT) void jacobi_hc2_kernel(
+    const double* __restrict__ Xr, int k, long ldx, int max_sweeps, int cap,
+    double tol, double* __restrict__ Vt, double* __restrict__ sigbuf,
+    int* __restrict__ perm_out, double* __restrict__ info, PairWs w) {
+  constexpr int RPT = kPairRpt;
+  extern __shared__ double smem[];
+  __shared__ double red[MAXT / 64];
+  __shared__ double lxn[kPairNodes];
+  __shared__ int lxi[kPairNodes];
+  __shared__ int sweep_any;
+  __shared__ int sh_ok;
+  __shared__ double sh_val;
+  __shared__ int Dsh;
+  const int wg = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int x = tid >> 4, lig = tid & 15;
+  const int gx = wg * kPairNodes + x;
+  int epoch = 0;
+  double other = 0.0;
+
+  Col<RPT> A, B;
+  A.id = 2 * gx;
+  B.id = 2 * gx + 1;
+  double sa = 0.0, sb = 0.0;
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    const int i = lig + 16 * r;
+    A.v[r] = (A.id < k && i < k) ? Xr[(long)A.id * ldx + i] : 0.0;
+    B.v[r] = (B.id < k && i < k) ? Xr[(long)B.id * ldx + i] : 0.0;
+    sa = fma(A.v[r], A.v[r], sa);
+    sb = fma(B.v[r], B.v[r], sb);
+  }
+  A.n = wave::sum16(sa);
+  B.n = wave::sum16(sb);
+  double part = (lig == 0) ? A.n + B.n : 0.0;
+  part = wave::sum64(part);
+  if ((tid & 63) == 0) red[tid >> 6] = part;
+  __syncthreads();
+  double mine = 0.0;
+  for (int v = 0; v < MAXT / 64; ++v) mine += red[v];
+  bool ok = meet(w, wg, ++epoch, mine, other, &sh_ok, &sh_val);
+  // the same sum in both workgroups (addition is commutative)
+  const double normF2 = mine + other;
+  const double scale = normF2 > 0.0 ? 1.0 / sqrt(normF2) : 1.0;
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    A.v[r] *= scale;
+    B.v[r] *= scale;
+  }
+  A.n *= scale * scale;
+  B.n *= scale * scale;
+  const double negl = 1e-30;
+  const double eps2 = 1e-28, conv2 = 1e-16;
+
+  auto pair_step = [&]() {
+    double gp[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) gp[r & 3] = fma(A.v[r], B.v[r], gp[r & 3]);
+    const double g = wave::sum16((gp[0] + gp[1]) + (gp[2] + gp[3]));
+    const double ab = A.n * B.n, g2 = g * g;
+    const bool rot = g2 > eps2 * ab && fmin(A.n, B.n) > negl;
+    if (rot) {
+      double cs, sn;
+      rotation(A.n, B.n, g, cs, sn);
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) {
+        const double u = A.v[r], v = B.v[r];
+        A.v[r] = cs * u - sn * v;
+        B.v[r] = sn * u + cs * v;
+      }
+      const double c2 = cs * cs, s2 = sn * sn, csg = 2.0 * cs * sn * g;
+      const double na = fma(c2, A.n, fma(s2, B.n, -csg));
+      const double nb = fma(s2, A.n, fma(c2, B.n, csg));
+      if (fmin(na, nb) < 1e-8 * (A.n + B.n)) {
+        double sa2 = 0.0, sb2 = 0.0;
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+          sa2 = fma(A.v[r], A.v[r], sa2);
+          sb2 = fma(B.v[r], B.v[r], sb2);
+        }
+        A.n = wave::sum16(sa2);
+        B.n = wave::sum16(sb2);
+      } else {
+        A.n = na;
+        B.n = nb;
+      }
+      if (lig == 0 && g2 > conv2 * ab) sweep_any = 1;
+    }
+  };
+
+  double* xb = smem;
+  // Moves along wave bits (through LDS) and across the workgroups (through
+  // global memory) of the column C.
+  auto move_far = [&](Col<RPT>& C, int dim) -> bool {
+    if (dim < 6) {
+      const int y = x ^ (1 << dim);
+      wave::lds_barrier();  // the previous move's reads are done
+      double* dst = xb + x * kPairStride;
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) dst[r * 16 + lig] = C.v[r];
+      if (lig == 0) {
+        lxn[x] = C.n;
+        lxi[x] = C.id;
+      }
+      wave::lds_barrier();
+      const double* src = xb + y * kPairStride;
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) C.v[r] = src[r * 16 + lig];
+      C.n = lxn[y];
+      C.id = lxi[y];
+      return true;
+    }
+    // node x of one workgroup meets node x of the other
+    const int e = epoch + 1;
+    const long mine = (long)(wg * 2 + (e & 1)) * kPairNodes + x;
+    const long theirs = (long)((wg ^ 1) * 2 + (e & 1)) * kPairNodes + x;
+    double* dst = w.xg + mine * (16 * RPT);
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) dst[r * 16 + lig] = C.v[r];
+    if (lig == 0) {
+      w.xn[mine] = C.n;
+      w.xi[mine] = C.id;
+    }
+    double unused;
+    if (!meet(w, wg, ++epoch, 0.0, unused, &sh_ok, &sh_val)) return false;
+    const double* src = w.xg + theirs * (16 * RPT);
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) C.v[r] = src[r * 16 + lig];
+    C.n = w.xn[theirs];
+    C.id = w.xi[theirs];
+    return true;
+  };
+  // Column b of node gx goes to node gx ^ (1 << dim) and is replaced by the
+  // one arriving from there; every thread of the workgroup takes part.
+  auto move_b = [&](int dim) -> bool {
+    if (dim == 0) {
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) B.v[r] = row_swap<0>(B.v[r]);
+      B.n = row_swap<0>(B.n);
+      B.id = row_swap<0>(B.id);
+      return true;
+    }
+    if (dim == 1) {
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) B.v[r] = row_swap<1>(B.v[r]);
+      B.n = row_swap<1>(B.n);
+      B.id = row_swap<1>(B.id);
+      return true;
+    }
+    return move_far(B, dim);
+  };
+
+  // Across the top dimension of a sub-cube: column a of the upper node and
+  // column b of the lower node change places.  The choice differs between
+  // nodes (and waves), so every thread sends and receives in the same
+  // phase, selecting element by element; no second copy of the columns is
+  // held in registers.
+  auto move_top = [&](int dim, bool up) -> bool {
+    if (dim <= 1) {
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) {
+        const double snd = up ? A.v[r] : B.v[r];
+        const double rcv = dim == 0 ? row_swap<0>(snd) : row_swap<1>(snd);
+        A.v[r] = up ? rcv : A.v[r];
+        B.v[r] = up ? B.v[r] : rcv;
+      }
+      const double sn = up ? A.n : B.n;
+      const int si = up ? A.id : B.id;
+      const double rn = dim == 0 ? row_swap<0>(sn) : row_swap<1>(sn);
+      const int ri = dim == 0 ? row_swap<0>(si) : row_swap<1>(si);
+      A.n = up ? rn : A.n;
+      A.id = up ? ri : A.id;
+      B.n = up ? B.n : rn;
+      B.id = up ? B.id : ri;
+      return true;
+    }
+    if (dim < 6) {
+      const int y = x ^ (1 << dim);
+      wave::lds_barrier();
+      double* dst = xb + x * kPairStride;
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) dst[r * 16 + lig] = up ? A.v[r] : B.v[r];
+      if (lig == 0) {
+        lxn[x] = up ? A.n : B.n;
+        lxi[x] = up ? A.id : B.id;
+      }
+      wave::lds_barrier();
+      const double* src = xb + y * kPairStride;
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) {
+        const double rcv = src[r * 16 + lig];
+        A.v[r] = up ? rcv : A.v[r];
+        B.v[r] = up ? B.v[r] : rcv;
+      }
+      const double rn = lxn[y];
+      const int ri = lxi[y];
+      A.n = up ? rn : A.n;
+      A.id = up ? ri : A.id;
+      B.n = up ? B.n : rn;
+      B.id = up ? B.id : ri;
+      return true;
+    }
+    // across the workgroups the choice is uniform: the upper one gives a
+    return up ? move_far(A, dim) : move_far(B, dim);
+  };
+
+  int sweep = 0, converged = 0, steps = 0;
+  for (; ok && sweep < max_sweeps; ++sweep) {
+    if (tid == 0) sweep_any = 0;
+    __syncthreads();
+    pair_step();
+    ++steps;
+    for (int l = 1; ok && l <= 7; ++l) {
+      // across dimension l-1 the lower node gives b and the upper node a,
+      // so that a holds lower-half columns and b upper-half columns
+      // everywhere
+      const int dim = l - 1;
+      ok = move_top(dim, (gx >> dim) & 1);
+      pair_step();
+      ++steps;
+      for (int t = 1; ok && t < (1 << l); ++t) {
+        ok = move_b(__builtin_ctz(t));
+        pair_step();
+        ++steps;
+      }
+    }
+    if (!ok) break;
+    __syncthreads();
+    ok = meet(w, wg, ++epoch, sweep_any ? 1.0 : 0.0, other, &sh_ok, &sh_val);
+    if (!ok) break;
+    if (sweep_any == 0 && other == 0.0) {
+      converged = 1;
+      ++sweep;
+      break;
+    }
+    __syncthreads();
+  }
+
+  // exact final norms in the units of the input, published to the partner
+  {
+    double sa2 = 0.0, sb2 = 0.0;
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      sa2 = fma(A.v[r], A.v[r], sa2);
+      sb2 = fma(B.v[r], B.v[r], sb2);
+    }
+    sa2 = wave::sum16(sa2);
+    sb2 = wave::sum16(sb2);
+    const double inv = 1.0 / scale;
+    if (ok && lig == 0) {
+      if (A.id < k) sigbuf[k + A.id] = sqrt(sa2) * inv;
+      if (B.id < k) sigbuf[k + B.id] = sqrt(sb2) * inv;
+    }
+  }
+  if (ok) ok = meet(w, wg, ++epoch, 0.0, other, &sh_ok, &sh_val);
+  if (!ok) {
+    if (tid == 0) {
+      info[3] = 0.0;
+      info[5] = 1.0;
+    }
+    return;
+  }
+  // both workgroups rank all k values the same way
+  double* sv = smem;                  // k values
+  double* sorted = smem + 256;        // k sorted values
+  int* rk = (int*)(smem + 512);       // rank of each column
+  __syncthreads();
+  for (int j = tid; j < k; j += MAXT) sv[j] = sigbuf[k + j];
+  __syncthreads();
+  for (int j = tid; j < k; j += MAXT) {
+    const double sj = sv[j];
+    int rank = 0;
+    for (int q = 0; q < k; ++q) {
+      const double sq = sv[q];
+      rank += (sq > sj || (sq == sj && q < j)) ? 1 : 0;
+    }
+    rk[j] = rank;
+    sorted[rank] = sj;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double tot = 0.0;
+    for (int i = 0; i < k; ++i) tot += sorted[i] * sorted[i];
+    const int capd = cap < k ? cap : k;
+    int D;
+    if (tot <= 0.0) {
+      D = 1;
+    } else if (tol <= 0.0) {
+      D = capd;
+    } else {
+      double acc = 0.0;
+      int best = k;
+      for (int Dp = k - 1; Dp >= 1; --Dp) {
+        acc += sorted[Dp] * sorted[Dp] / tot;
+        if (acc <= tol * tol) best = Dp; else break;
+      }
+      D = best < capd ? best : capd;
+    }
+    if (D < 1) D = 1;
+    Dsh = D;
+    if (wg == 0) {
+      double disc2 = 0.0;
+      for (int i = D; i < k; ++i) disc2 += sorted[i] * sorted[i];
+      info[0] = (double)D;
+      info[1] = (tot > 0.0) ? sqrt(disc2 / tot) : 0.0;
+      info[2] = (double)sweep;
+      info[3] = (double)converged;
+      info[4] = (double)steps;
+      info[5] = 0.0;
+    }
+  }
+  __syncthreads();
+  const int D = Dsh;
+  if (wg == 0) {
+    for (int j = tid; j < k; j += MAXT) {
+      sigbuf[j] = sorted[j];
+      perm_out[rk[j]] = j;
+    }
+  }
+  // Vt[d][i] = column perm(d) / sigma_d, written by the node holding it
+  const double inv = 1.0 / scale;
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const Col<RPT>& C = c == 0 ? A : B;
+    if (C.id >= k) continue;
+    const int d = rk[C.id];
+    if (d >= D) continue;
+    const double sd = sorted[d];
+    const double f = (sd * sd > negl * normF2) ? inv / sd : 0.0;
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const int i = lig + 16 * r;
+      if (i < k) Vt[(long)d * k + i] = C.v[r] * f;
+    }
+  }
+}
+
 struct Shape {
   int d, nodes, rpt;
 };
@@ -374,17 +778,28 @@ Shape shape_of(int k) {
 }  // namespace
 
 size_t jacobi_lds_bytes(int k) {
+  if (k > kJacobiOneWgCols) return (size_t)kPairNodes * kPairStride * sizeof(double);
   const Shape s = shape_of(k);
   const size_t xch = (size_t)2 * s.nodes * 16 * s.rpt;
   const size_t cols = (size_t)k * (size_t)(k | 1);
   return (xch > cols ? xch : cols) * sizeof(double);
 }
 
+size_t jacobi_ws_doubles(int k) {
+  if (k <= kJacobiOneWgCols) return 0;
+  // xg, xn, val; then xi and flags as ints
+  return (size_t)4 * kPairNodes * 16 * kPairRpt + 4 * kPairNodes + 4 +
+         (4 * kPairNodes + 2 + 1) / 2 + 1;
+}
+
 void jacobi_svd(hipStream_t s, const double* Xr, int k, long ldx, int cap,
                 double tol, int max_sweeps, double* Vt, double* sigbuf,
-                int* perm, double* info) {
+                int* perm, double* info, double* ws) {
   static std::once_flag once;
   std::call_once(once, [] {
+    MPSV_HIP(hipFuncSetAttribute((const void*)jacobi_hc2_kernel,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)kJacobiMaxLds));
     MPSV_HIP(hipFuncSetAttribute((const void*)jacobi_hc_kernel<2>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)kJacobiMaxLds));
@@ -399,6 +814,20 @@ void jacobi_svd(hipStream_t s, const double* Xr, int k, long ldx, int cap,
              "Jacobi SVD: matrix does not fit on chip");
   const size_t lds = jacobi_lds_bytes(k);
   MPSV_CHECK(lds <= kJacobiMaxLds, kEinval, "Jacobi SVD: LDS too small");
+  if (k > kJacobiOneWgCols) {
+    MPSV_CHECK(ws != nullptr, kEinval, "Jacobi SVD: workspace missing");
+    PairWs w;
+    w.xg = ws;
+    w.xn = w.xg + 4 * kPairNodes * 16 * kPairRpt;
+    w.val = w.xn + 4 * kPairNodes;
+    w.xi = (int*)(w.val + 4);
+    w.flags = w.xi + 4 * kPairNodes;
+    fill_int(s, w.flags, 2, 0);
+    hipLaunchKernelGGL(jacobi_hc2_kernel, dim3(2), dim3(MAXT), lds, s, Xr, k,
+                       ldx, max_sweeps, cap, tol, Vt, sigbuf, perm, info, w);
+    MPSV_LAUNCHED();
+    return;
+  }
   const Shape sh = shape_of(k);
   const dim3 block(16 * sh.nodes);
   if (sh.rpt == 2)

@@ -733,8 +733,10 @@ int svd_truncate(hipStream_t s, Arena& ws, double* X, int m, int c, long ldx,
     Rk = Bk;
     Wt = ws.alloc((size_t)k * k);
     int* perm = ws.alloc_int((size_t)k);
+    const size_t jws = jacobi_ws_doubles(k);
+    double* jw = jws ? ws.alloc(jws) : nullptr;
     slot = prof_begin(s);
-    jacobi_svd(s, Rk, k, k, cap, tol, g_max_sweeps, Wt, sigbuf, perm, info);
+    jacobi_svd(s, Rk, k, k, cap, tol, g_max_sweeps, Wt, sigbuf, perm, info, jw);
   } else {
     // large matrices: unpreconditioned Jacobi on the columns, in global memory
     const bool tall = m > c;
@@ -765,11 +767,13 @@ int svd_truncate(hipStream_t s, Arena& ws, double* X, int m, int c, long ldx,
              8.0 * (2.0 * m * c + 2.0 * nn * nn));
   }
   double* h = pinned_info(s);
-  MPSV_HIP(hipMemcpyAsync(h, info, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+  MPSV_HIP(hipMemcpyAsync(h, info, 6 * sizeof(double), hipMemcpyDeviceToHost, s));
   MPSV_HIP(hipStreamSynchronize(s));
   const int D = (int)h[0];
   if (discarded) *discarded = h[1];
   g_stats.jacobi_sweeps += (long)h[2];
+  if (onchip && k > kJacobiOneWgCols && h[5] != 0.0)
+    throw Error(kEdevice, "Jacobi SVD: the two workgroups did not meet in time");
   if (h[3] == 0.0)
     throw Error(kEnumeric, "Jacobi SVD did not converge within " +
                                std::to_string(g_max_sweeps) + " sweeps");

@@ -81,7 +81,10 @@ def test_qr_is_orthogonal_factorisation(B, m, n):
     (2, 2, 0, 0.0, 0), (10, 4, 0, 0.0, 0), (4, 10, 0, 0.0, 0), (64, 64, 0, 0.0, 6),
     (96, 96, 40, 0.0, 8), (128, 128, 64, 0.0, 8), (500, 128, 64, 0.0, 12),
     (300, 60, 0, 1e-10, 14), (33, 90, 0, 1e-6, 10), (1024, 16, 8, 0.0, 2),
-    (2000, 128, 64, 0.0, 10), (60, 1500, 0, 1e-8, 6)])
+    (2000, 128, 64, 0.0, 10), (60, 1500, 0, 1e-8, 6),
+    # 129..256 columns: the two-workgroup Jacobi kernel
+    (129, 129, 0, 0.0, 6), (256, 256, 128, 0.0, 10), (1024, 256, 128, 0.0, 12),
+    (200, 256, 0, 1e-10, 14), (256, 600, 100, 0.0, 8), (3000, 160, 0, 1e-12, 16)])
 def test_svd_truncate_matches_lapack_and_rank_rule(B, m, c, cap, tol, decay):
     _say("svd %d x %d cap %d tol %g" % (m, c, cap, tol))
     X = wl.random_matrix(m, c, seed=3 * m + c, decay=decay)
@@ -101,7 +104,8 @@ def test_svd_truncate_matches_lapack_and_rank_rule(B, m, c, cap, tol, decay):
 
 
 @pytest.mark.parametrize("m,c,r", [(128, 128, 5), (256, 128, 1), (64, 128, 3), (100, 40, 0),
-                                   (96, 128, 60), (512, 128, 17)])
+                                   (96, 128, 60), (512, 128, 17), (256, 256, 7),
+                                   (300, 200, 0), (256, 256, 150), (512, 192, 1)])
 def test_svd_truncate_rank_deficient(B, m, c, r):
     """Numerically rank-deficient blocks (as in the TT-SVD of a separable
     profile): the kept rows of Vt are orthonormal or exactly zero and the

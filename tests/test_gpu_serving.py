@@ -101,8 +101,11 @@ def test_device_bytes_within_workspace_bound(S, case):
         if case.endswith("fp32"):
             w.problem.precision = 1
     else:
+        # a sweep instance with every compression point capped (level 1
+        # with tol = 0 would leave the intermediate bonds uncapped)
         w = [x for x in wl.landau_sweep(64) if x.problem.Lx == 11 and x.problem.chi_max == 64][0]
         w.problem.tol = 0.0
+        w.problem.level = 5
     p = w.problem
     st = binding.MpsState(p, w.ax, w.bv)
     try:

@@ -256,3 +256,29 @@ def test_fp32_contraction_mode_error_against_fp64_oracle(B):
     print("fp32-contraction error: f %.2e, E %.2e" % (err_f, err_E))
     assert err_f <= 1e-5 and err_E <= 1e-3
     assert err_f > 1e-13  # the FP32 path was taken
+
+
+def test_chi128_step_matches_mps_oracle(B):
+    """Bond cap 128 (truncated SVDs of up to 256 columns, on two
+    workgroups): two-stream 2^8 x 2^8 interleaved, C5, D_F = 4, from a state
+    perturbed to bonds of 128.  One RK4 step on the GPU and in the CPU MPS
+    oracle from the same cores: f and E within 1e-8, identical bonds."""
+    _say("two-stream 2^8 chi128 C5")
+    w = wl.two_stream(L=8, chi=128, tol=0.0, level=5, df_max=4, dt_cfg=0.02)
+    p = w.problem
+    st = B.MpsState(p, w.ax, w.bv)
+    pert = wl.random_mps_cores(p.n_sites, 128, seed=2205)
+    st.add_scaled(1e-6 * float(np.linalg.norm(w.ax) * np.linalg.norm(w.bv)), pert)
+    f0 = st.get_cores_host()
+    assert max(c.shape[2] for c in f0) == 128
+    st.step(1)
+    G = st.to_dense().cpu().numpy()
+    _, E, _ = st.moments()
+    ops = omps.Operators(p)
+    f = omps.rk4_step(f0, ops)
+    R = omps.to_dense(f, p)
+    Eref = omps.field_dense(f, ops)
+    assert np.abs(G - R).max() <= 1e-8 * np.abs(R).max()
+    assert np.abs(E.cpu().numpy() - Eref).max() <= 1e-8 * np.abs(Eref).max()
+    assert st.info()["bonds"][1:-1] == omps.bond_dims(f)
+    st.free()
