@@ -30,14 +30,13 @@
 // and are never rotated.
 //
 // From 129 to 256 columns the matrix no longer fits in one compute unit:
-// two workgroups of 64 nodes each hold half of the 128 nodes (rows up to
-// 256, 16 per lane), and the top cube dimension joins them.  Only two moves
-// per sweep (the exchange across the top dimension and one step of its Gray
-// code) cross it; they go through global memory, with a rendezvous of the
-// two workgroups on release/acquire flags at device scope.  Each wait for
-// the partner is bounded; a rendezvous that times out ends both workgroups
-// and is reported instead of a result.  The end-of-sweep decision uses both
-// workgroups' convergence flags, so both run the same number of sweeps.
+// four workgroups of 32 nodes each hold a quarter of the 128 nodes (rows up
+// to 256, 16 per lane), and the two top cube dimensions join them.  Only
+// six moves per sweep cross them; they go through global memory, with a
+// rendezvous of all workgroups on release/acquire flags at device scope.
+// Each wait is bounded; a rendezvous that times out ends every workgroup
+// and is reported instead of a result.  The end-of-sweep decision sums all
+// workgroups' convergence flags, so all of them run the same sweeps.
 //
 // On exit: singular values are the column norms, sorted descending (ties by
 // index), the truncation rank D follows the rule min(cap, smallest D' whose
@@ -369,20 +368,28 @@ __global__ __launch_bounds__(MAXT) void jacobi_hc_kernel(
   }
 }
 
-// ------------------------------------------------ two workgroups (k <= 256)
+// ------------------------------------------ several workgroups (k <= 256)
 
-constexpr int kPairRpt = 16;                  // rows per lane: up to 256 rows
-constexpr int kPairNodes = 64;                // nodes per workgroup
-constexpr int kPairStride = 16 * kPairRpt + 16;  // padded LDS column slot
-constexpr long kSpinLimit = 1L << 22;         // polls, about a second
+constexpr int kMultiWgs = 4;                     // workgroups
+constexpr int kMultiLog = 2;                     // log2(kMultiWgs)
+constexpr int kMultiNodes = 128 / kMultiWgs;     // nodes per workgroup
+constexpr int kMultiLocal = 5;                   // log2(kMultiNodes)
+constexpr int kMultiT = 16 * kMultiNodes;        // threads per workgroup
+constexpr int kMultiRpt = 16;                    // rows per lane: up to 256
+constexpr int kMultiCol = 16 * kMultiRpt;        // doubles per column
+constexpr int kMultiStride = kMultiCol + 16;     // padded LDS column slot
+constexpr long kSpinLimit = 1L << 22;            // polls per wait, ~1 s
+static_assert(kMultiNodes == 1 << kMultiLocal, "nodes per workgroup");
+static_assert(kMultiWgs == 1 << kMultiLog, "workgroups");
 
-// Global exchange area of the two workgroups (see jacobi_ws_doubles).
-struct PairWs {
-  double* xg;    // [wg][parity][node][256] outgoing columns
-  double* xn;    // [wg][parity][node] their squared norms
-  double* val;   // [wg][parity] rendezvous payload
-  int* xi;       // [wg][parity][node] their indices
-  int* flags;    // [wg] last epoch published (zeroed before the launch)
+// Global exchange area of the workgroups (see jacobi_ws_doubles); the
+// slots alternate with the parity of the rendezvous number.
+struct MultiWs {
+  double* xg;   // [wg][parity][node][kMultiCol] outgoing columns
+  double* xn;   // [wg][parity][node] their squared norms
+  double* val;  // [wg][parity] rendezvous payload
+  int* xi;      // [wg][parity][node] their indices
+  int* flags;   // [wg] last rendezvous published (zeroed before the launch)
 };
 
 __device__ inline void flag_publish(int* f, int v) {
@@ -392,48 +399,64 @@ __device__ inline int flag_read(int* f) {
   return __hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Rendezvous number `e` of the two workgroups: every thread's earlier
-// global stores become visible to the partner, `mine` is published and the
-// partner's value of the same rendezvous returned in `other`.  False (for
-// the whole workgroup) when the partner does not arrive within the spin
-// limit.
-__device__ bool meet(const PairWs& w, int wg, int e, double mine,
-                     double& other, int* sh_ok, double* sh_val) {
+// Rendezvous number `e` of all workgroups: every thread's earlier global
+// stores become visible to the others, `mine` is published and the sum of
+// all workgroups' values, taken in workgroup order (the same in each), is
+// returned in `total`.  False, for the whole workgroup, when another
+// workgroup does not arrive within the spin limit.  Since every workgroup
+// waits for all others at each rendezvous, a slot written at rendezvous e
+// has been read by everyone before any workgroup passes e + 1.
+__device__ bool meet_all(const MultiWs& w, int wg, int e, double mine,
+                         double& total, int* sh_ok, double* sh_val) {
   __threadfence();
   __syncthreads();
   if (threadIdx.x == 0) {
     w.val[wg * 2 + (e & 1)] = mine;
     flag_publish(w.flags + wg, e);
-    long spins = 0;
     int ok = 1;
-    while (flag_read(w.flags + (wg ^ 1)) < e) {
-      if (++spins > kSpinLimit) {
-        ok = 0;
-        break;
+    for (int q = 0; q < kMultiWgs && ok; ++q) {
+      if (q == wg) continue;
+      long spins = 0;
+      while (flag_read(w.flags + q) < e) {
+        if (++spins > kSpinLimit) {
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(8);
       }
-      __builtin_amdgcn_s_sleep(8);
     }
+    double t = 0.0;
+    for (int q = 0; q < kMultiWgs && ok; ++q)
+      t += (q == wg) ? mine : w.val[q * 2 + (e & 1)];
     *sh_ok = ok;
-    *sh_val = ok ? w.val[(wg ^ 1) * 2 + (e & 1)] : 0.0;
+    *sh_val = t;
   }
   __syncthreads();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  other = *sh_val;
+  total = *sh_val;
   return *sh_ok != 0;
 }
 
+// A value chosen by a per-lane condition.  Taking the operands by value
+// makes both loads happen, so that a choice between two register-resident
+// arrays never becomes a choice between their addresses (which would move
+// the arrays to scratch memory).
+__device__ inline double pick(bool c, double a, double b) { return c ? a : b; }
+__device__ inline int pick(bool c, int a, int b) { return c ? a : b; }
+
 // Info: [0] D, [1] discarded weight, [2] sweeps, [3] converged, [4] steps,
 // [5] 1 if a rendezvous timed out.  Same inputs and outputs as
-// jacobi_hc_kernel; launched as exactly two workgroups of 1024 threads.
-__global__ __launch_bounds__(MAXT) void jacobi_hc2_kernel(
+// jacobi_hc_kernel; launched as exactly kMultiWgs workgroups of kMultiT
+// threads.  Node bits 0-1 are lane rows, 2-4 waves, 5-6 the workgroup.
+__global__ __launch_bounds__(kMultiT) void jacobi_multi_kernel(
     const double* __restrict__ Xr, int k, long ldx, int max_sweeps, int cap,
     double tol, double* __restrict__ Vt, double* __restrict__ sigbuf,
-    int* __restrict__ perm_out, double* __restrict__ info, PairWs w) {
-  constexpr int RPT = kPairRpt;
+    int* __restrict__ perm_out, double* __restrict__ info, MultiWs w) {
+  constexpr int RPT = kMultiRpt;
   extern __shared__ double smem[];
-  __shared__ double red[MAXT / 64];
-  __shared__ double lxn[kPairNodes];
-  __shared__ int lxi[kPairNodes];
+  __shared__ double red[kMultiT / 64];
+  __shared__ double lxn[kMultiNodes];
+  __shared__ int lxi[kMultiNodes];
   __shared__ int sweep_any;
   __shared__ int sh_ok;
   __shared__ double sh_val;
@@ -441,9 +464,8 @@ __global__ __launch_bounds__(MAXT) void jacobi_hc2_kernel(
   const int wg = blockIdx.x;
   const int tid = threadIdx.x;
   const int x = tid >> 4, lig = tid & 15;
-  const int gx = wg * kPairNodes + x;
+  const int gx = wg * kMultiNodes + x;
   int epoch = 0;
-  double other = 0.0;
 
   Col<RPT> A, B;
   A.id = 2 * gx;
@@ -464,10 +486,9 @@ __global__ __launch_bounds__(MAXT) void jacobi_hc2_kernel(
   if ((tid & 63) == 0) red[tid >> 6] = part;
   __syncthreads();
   double mine = 0.0;
-  for (int v = 0; v < MAXT / 64; ++v) mine += red[v];
-  bool ok = meet(w, wg, ++epoch, mine, other, &sh_ok, &sh_val);
-  // the same sum in both workgroups (addition is commutative)
-  const double normF2 = mine + other;
+  for (int v = 0; v < kMultiT / 64; ++v) mine += red[v];
+  double normF2 = 0.0;
+  bool ok = meet_all(w, wg, ++epoch, mine, normF2, &sh_ok, &sh_val);
   const double scale = normF2 > 0.0 ? 1.0 / sqrt(normF2) : 1.0;
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
@@ -479,7 +500,7 @@ __global__ __launch_bounds__(MAXT) void jacobi_hc2_kernel(
   const double negl = 1e-30;
   const double eps2 = 1e-28, conv2 = 1e-16;
 
-  auto pair_step = [&]() {
+  auto pair_step = [&]() __attribute__((always_inline)) {
     double gp[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int r = 0; r < RPT; ++r) gp[r & 3] = fma(A.v[r], B.v[r], gp[r & 3]);
@@ -516,119 +537,75 @@ __global__ __launch_bounds__(MAXT) void jacobi_hc2_kernel(
   };
 
   double* xb = smem;
-  // Moves along wave bits (through LDS) and across the workgroups (through
-  // global memory) of the column C.
-  auto move_far = [&](Col<RPT>& C, int dim) -> bool {
-    if (dim < 6) {
-      const int y = x ^ (1 << dim);
-      wave::lds_barrier();  // the previous move's reads are done
-      double* dst = xb + x * kPairStride;
+  // Column a where `up`, else column b, of node gx goes to node
+  // gx ^ (1 << dim) and is replaced by the one arriving from there.  The
+  // choice can differ between lanes and waves, so it is made element by
+  // element and every thread sends and receives in the same phase; the
+  // columns never leave the registers except through the exchange buffer.
+  auto send = [&](double* dst, double* dn, int* di, bool up)
+      __attribute__((always_inline)) {
 #pragma unroll
-      for (int r = 0; r < RPT; ++r) dst[r * 16 + lig] = C.v[r];
-      if (lig == 0) {
-        lxn[x] = C.n;
-        lxi[x] = C.id;
-      }
-      wave::lds_barrier();
-      const double* src = xb + y * kPairStride;
-#pragma unroll
-      for (int r = 0; r < RPT; ++r) C.v[r] = src[r * 16 + lig];
-      C.n = lxn[y];
-      C.id = lxi[y];
-      return true;
-    }
-    // node x of one workgroup meets node x of the other
-    const int e = epoch + 1;
-    const long mine = (long)(wg * 2 + (e & 1)) * kPairNodes + x;
-    const long theirs = (long)((wg ^ 1) * 2 + (e & 1)) * kPairNodes + x;
-    double* dst = w.xg + mine * (16 * RPT);
-#pragma unroll
-    for (int r = 0; r < RPT; ++r) dst[r * 16 + lig] = C.v[r];
+    for (int r = 0; r < RPT; ++r) dst[r * 16 + lig] = pick(up, A.v[r], B.v[r]);
     if (lig == 0) {
-      w.xn[mine] = C.n;
-      w.xi[mine] = C.id;
+      *dn = pick(up, A.n, B.n);
+      *di = pick(up, A.id, B.id);
     }
-    double unused;
-    if (!meet(w, wg, ++epoch, 0.0, unused, &sh_ok, &sh_val)) return false;
-    const double* src = w.xg + theirs * (16 * RPT);
-#pragma unroll
-    for (int r = 0; r < RPT; ++r) C.v[r] = src[r * 16 + lig];
-    C.n = w.xn[theirs];
-    C.id = w.xi[theirs];
-    return true;
   };
-  // Column b of node gx goes to node gx ^ (1 << dim) and is replaced by the
-  // one arriving from there; every thread of the workgroup takes part.
-  auto move_b = [&](int dim) -> bool {
-    if (dim == 0) {
+  auto receive = [&](const double* src, const double* sn, const int* si,
+                     bool up) __attribute__((always_inline)) {
 #pragma unroll
-      for (int r = 0; r < RPT; ++r) B.v[r] = row_swap<0>(B.v[r]);
-      B.n = row_swap<0>(B.n);
-      B.id = row_swap<0>(B.id);
-      return true;
+    for (int r = 0; r < RPT; ++r) {
+      const double rcv = src[r * 16 + lig];
+      A.v[r] = pick(up, rcv, A.v[r]);
+      B.v[r] = pick(up, B.v[r], rcv);
     }
-    if (dim == 1) {
-#pragma unroll
-      for (int r = 0; r < RPT; ++r) B.v[r] = row_swap<1>(B.v[r]);
-      B.n = row_swap<1>(B.n);
-      B.id = row_swap<1>(B.id);
-      return true;
-    }
-    return move_far(B, dim);
+    const double rn = *sn;
+    const int ri = *si;
+    A.n = pick(up, rn, A.n);
+    A.id = pick(up, ri, A.id);
+    B.n = pick(up, B.n, rn);
+    B.id = pick(up, B.id, ri);
   };
-
-  // Across the top dimension of a sub-cube: column a of the upper node and
-  // column b of the lower node change places.  The choice differs between
-  // nodes (and waves), so every thread sends and receives in the same
-  // phase, selecting element by element; no second copy of the columns is
-  // held in registers.
-  auto move_top = [&](int dim, bool up) -> bool {
+  auto move = [&](int dim, bool up) __attribute__((always_inline)) -> bool {
     if (dim <= 1) {
+      // lane rows of one wave: a permutation through the LDS crossbar
 #pragma unroll
       for (int r = 0; r < RPT; ++r) {
-        const double snd = up ? A.v[r] : B.v[r];
+        const double snd = pick(up, A.v[r], B.v[r]);
         const double rcv = dim == 0 ? row_swap<0>(snd) : row_swap<1>(snd);
-        A.v[r] = up ? rcv : A.v[r];
-        B.v[r] = up ? B.v[r] : rcv;
+        A.v[r] = pick(up, rcv, A.v[r]);
+        B.v[r] = pick(up, B.v[r], rcv);
       }
-      const double sn = up ? A.n : B.n;
-      const int si = up ? A.id : B.id;
+      const double sn = pick(up, A.n, B.n);
+      const int si = pick(up, A.id, B.id);
       const double rn = dim == 0 ? row_swap<0>(sn) : row_swap<1>(sn);
       const int ri = dim == 0 ? row_swap<0>(si) : row_swap<1>(si);
-      A.n = up ? rn : A.n;
-      A.id = up ? ri : A.id;
-      B.n = up ? B.n : rn;
-      B.id = up ? B.id : ri;
+      A.n = pick(up, rn, A.n);
+      A.id = pick(up, ri, A.id);
+      B.n = pick(up, B.n, rn);
+      B.id = pick(up, B.id, ri);
       return true;
     }
-    if (dim < 6) {
+    if (dim < kMultiLocal) {
+      // waves of one workgroup: through LDS
       const int y = x ^ (1 << dim);
+      wave::lds_barrier();  // the previous move's reads are done
+      send(xb + x * kMultiStride, lxn + x, lxi + x, up);
       wave::lds_barrier();
-      double* dst = xb + x * kPairStride;
-#pragma unroll
-      for (int r = 0; r < RPT; ++r) dst[r * 16 + lig] = up ? A.v[r] : B.v[r];
-      if (lig == 0) {
-        lxn[x] = up ? A.n : B.n;
-        lxi[x] = up ? A.id : B.id;
-      }
-      wave::lds_barrier();
-      const double* src = xb + y * kPairStride;
-#pragma unroll
-      for (int r = 0; r < RPT; ++r) {
-        const double rcv = src[r * 16 + lig];
-        A.v[r] = up ? rcv : A.v[r];
-        B.v[r] = up ? B.v[r] : rcv;
-      }
-      const double rn = lxn[y];
-      const int ri = lxi[y];
-      A.n = up ? rn : A.n;
-      A.id = up ? ri : A.id;
-      B.n = up ? B.n : rn;
-      B.id = up ? B.id : ri;
+      receive(xb + y * kMultiStride, lxn + y, lxi + y, up);
       return true;
     }
-    // across the workgroups the choice is uniform: the upper one gives a
-    return up ? move_far(A, dim) : move_far(B, dim);
+    // node x of this workgroup and node x of workgroup wg ^ (1 << (dim - 5)),
+    // through global memory
+    const int e = epoch + 1;
+    const int pw = wg ^ (1 << (dim - kMultiLocal));
+    const long mine_s = (long)(wg * 2 + (e & 1)) * kMultiNodes + x;
+    const long theirs = (long)(pw * 2 + (e & 1)) * kMultiNodes + x;
+    send(w.xg + mine_s * kMultiCol, w.xn + mine_s, w.xi + mine_s, up);
+    double unused;
+    if (!meet_all(w, wg, ++epoch, 0.0, unused, &sh_ok, &sh_val)) return false;
+    receive(w.xg + theirs * kMultiCol, w.xn + theirs, w.xi + theirs, up);
+    return true;
   };
 
   int sweep = 0, converged = 0, steps = 0;
@@ -637,25 +614,26 @@ __global__ __launch_bounds__(MAXT) void jacobi_hc2_kernel(
     __syncthreads();
     pair_step();
     ++steps;
-    for (int l = 1; ok && l <= 7; ++l) {
+    for (int l = 1; ok && l <= kMultiLocal + kMultiLog; ++l) {
       // across dimension l-1 the lower node gives b and the upper node a,
       // so that a holds lower-half columns and b upper-half columns
-      // everywhere
+      // everywhere; then the b columns walk along a Gray code
       const int dim = l - 1;
-      ok = move_top(dim, (gx >> dim) & 1);
+      ok = move(dim, (gx >> dim) & 1);
       pair_step();
       ++steps;
       for (int t = 1; ok && t < (1 << l); ++t) {
-        ok = move_b(__builtin_ctz(t));
+        ok = move(__builtin_ctz(t), false);
         pair_step();
         ++steps;
       }
     }
     if (!ok) break;
     __syncthreads();
-    ok = meet(w, wg, ++epoch, sweep_any ? 1.0 : 0.0, other, &sh_ok, &sh_val);
+    double any = 0.0;
+    ok = meet_all(w, wg, ++epoch, sweep_any ? 1.0 : 0.0, any, &sh_ok, &sh_val);
     if (!ok) break;
-    if (sweep_any == 0 && other == 0.0) {
+    if (any == 0.0) {
       converged = 1;
       ++sweep;
       break;
@@ -663,7 +641,7 @@ __global__ __launch_bounds__(MAXT) void jacobi_hc2_kernel(
     __syncthreads();
   }
 
-  // exact final norms in the units of the input, published to the partner
+  // exact final norms in the units of the input, published to the others
   {
     double sa2 = 0.0, sb2 = 0.0;
 #pragma unroll
@@ -679,7 +657,8 @@ __global__ __launch_bounds__(MAXT) void jacobi_hc2_kernel(
       if (B.id < k) sigbuf[k + B.id] = sqrt(sb2) * inv;
     }
   }
-  if (ok) ok = meet(w, wg, ++epoch, 0.0, other, &sh_ok, &sh_val);
+  double unused_total;
+  if (ok) ok = meet_all(w, wg, ++epoch, 0.0, unused_total, &sh_ok, &sh_val);
   if (!ok) {
     if (tid == 0) {
       info[3] = 0.0;
@@ -687,14 +666,14 @@ __global__ __launch_bounds__(MAXT) void jacobi_hc2_kernel(
     }
     return;
   }
-  // both workgroups rank all k values the same way
+  // every workgroup ranks all k values the same way
   double* sv = smem;                  // k values
   double* sorted = smem + 256;        // k sorted values
   int* rk = (int*)(smem + 512);       // rank of each column
   __syncthreads();
-  for (int j = tid; j < k; j += MAXT) sv[j] = sigbuf[k + j];
+  for (int j = tid; j < k; j += kMultiT) sv[j] = sigbuf[k + j];
   __syncthreads();
-  for (int j = tid; j < k; j += MAXT) {
+  for (int j = tid; j < k; j += kMultiT) {
     const double sj = sv[j];
     int rank = 0;
     for (int q = 0; q < k; ++q) {
@@ -739,7 +718,7 @@ __global__ __launch_bounds__(MAXT) void jacobi_hc2_kernel(
   __syncthreads();
   const int D = Dsh;
   if (wg == 0) {
-    for (int j = tid; j < k; j += MAXT) {
+    for (int j = tid; j < k; j += kMultiT) {
       sigbuf[j] = sorted[j];
       perm_out[rk[j]] = j;
     }
@@ -748,16 +727,16 @@ __global__ __launch_bounds__(MAXT) void jacobi_hc2_kernel(
   const double inv = 1.0 / scale;
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
-    const Col<RPT>& C = c == 0 ? A : B;
-    if (C.id >= k) continue;
-    const int d = rk[C.id];
+    const int id = pick(c == 0, A.id, B.id);
+    if (id >= k) continue;
+    const int d = rk[id];
     if (d >= D) continue;
     const double sd = sorted[d];
     const double f = (sd * sd > negl * normF2) ? inv / sd : 0.0;
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
       const int i = lig + 16 * r;
-      if (i < k) Vt[(long)d * k + i] = C.v[r] * f;
+      if (i < k) Vt[(long)d * k + i] = pick(c == 0, A.v[r], B.v[r]) * f;
     }
   }
 }
@@ -778,7 +757,7 @@ Shape shape_of(int k) {
 }  // namespace
 
 size_t jacobi_lds_bytes(int k) {
-  if (k > kJacobiOneWgCols) return (size_t)kPairNodes * kPairStride * sizeof(double);
+  if (k > kJacobiOneWgCols) return (size_t)kMultiNodes * kMultiStride * sizeof(double);
   const Shape s = shape_of(k);
   const size_t xch = (size_t)2 * s.nodes * 16 * s.rpt;
   const size_t cols = (size_t)k * (size_t)(k | 1);
@@ -788,8 +767,8 @@ size_t jacobi_lds_bytes(int k) {
 size_t jacobi_ws_doubles(int k) {
   if (k <= kJacobiOneWgCols) return 0;
   // xg, xn, val; then xi and flags as ints
-  return (size_t)4 * kPairNodes * 16 * kPairRpt + 4 * kPairNodes + 4 +
-         (4 * kPairNodes + 2 + 1) / 2 + 1;
+  const size_t slots = (size_t)kMultiWgs * 2 * kMultiNodes;
+  return slots * kMultiCol + slots + 2 * kMultiWgs + (slots + kMultiWgs + 1) / 2 + 1;
 }
 
 void jacobi_svd(hipStream_t s, const double* Xr, int k, long ldx, int cap,
@@ -797,7 +776,7 @@ void jacobi_svd(hipStream_t s, const double* Xr, int k, long ldx, int cap,
                 int* perm, double* info, double* ws) {
   static std::once_flag once;
   std::call_once(once, [] {
-    MPSV_HIP(hipFuncSetAttribute((const void*)jacobi_hc2_kernel,
+    MPSV_HIP(hipFuncSetAttribute((const void*)jacobi_multi_kernel,
                                  hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)kJacobiMaxLds));
     MPSV_HIP(hipFuncSetAttribute((const void*)jacobi_hc_kernel<2>,
@@ -816,15 +795,17 @@ void jacobi_svd(hipStream_t s, const double* Xr, int k, long ldx, int cap,
   MPSV_CHECK(lds <= kJacobiMaxLds, kEinval, "Jacobi SVD: LDS too small");
   if (k > kJacobiOneWgCols) {
     MPSV_CHECK(ws != nullptr, kEinval, "Jacobi SVD: workspace missing");
-    PairWs w;
+    const size_t slots = (size_t)kMultiWgs * 2 * kMultiNodes;
+    MultiWs w;
     w.xg = ws;
-    w.xn = w.xg + 4 * kPairNodes * 16 * kPairRpt;
-    w.val = w.xn + 4 * kPairNodes;
-    w.xi = (int*)(w.val + 4);
-    w.flags = w.xi + 4 * kPairNodes;
-    fill_int(s, w.flags, 2, 0);
-    hipLaunchKernelGGL(jacobi_hc2_kernel, dim3(2), dim3(MAXT), lds, s, Xr, k,
-                       ldx, max_sweeps, cap, tol, Vt, sigbuf, perm, info, w);
+    w.xn = w.xg + slots * kMultiCol;
+    w.val = w.xn + slots;
+    w.xi = (int*)(w.val + 2 * kMultiWgs);
+    w.flags = w.xi + slots;
+    fill_int(s, w.flags, kMultiWgs, 0);
+    hipLaunchKernelGGL(jacobi_multi_kernel, dim3(kMultiWgs), dim3(kMultiT), lds,
+                       s, Xr, k, ldx, max_sweeps, cap, tol, Vt, sigbuf, perm,
+                       info, w);
     MPSV_LAUNCHED();
     return;
   }

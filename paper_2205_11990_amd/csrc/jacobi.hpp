@@ -6,13 +6,13 @@ namespace mpsv {
 
 constexpr size_t kJacobiMaxLds = 150 * 1024;
 constexpr int kJacobiOneWgCols = 128;  // one workgroup up to here
-constexpr int kJacobiMaxCols = 256;    // two workgroups up to here
+constexpr int kJacobiMaxCols = 256;    // four workgroups up to here
 
 // LDS bytes of the kernel for a k x k factor.
 size_t jacobi_lds_bytes(int k);
 
 // Device workspace (doubles) the kernel needs beyond its outputs: zero up
-// to kJacobiOneWgCols columns, the exchange area of the two workgroups
+// to kJacobiOneWgCols columns, the exchange area of the workgroups
 // above.
 size_t jacobi_ws_doubles(int k);
 
@@ -22,7 +22,7 @@ size_t jacobi_ws_doubles(int k);
 // right singular vectors of X times its singular values.  Outputs (device):
 // Vt (D x k, the kept right singular vectors as rows), sigbuf (>= 2k
 // doubles: sorted values first), perm (k ints), info (6 doubles: D,
-// discarded weight, sweeps, converged, steps, 1 if the two workgroups
+// discarded weight, sweeps, converged, steps, 1 if the workgroups
 // failed to meet).  ws: jacobi_ws_doubles(k) doubles of device workspace.
 void jacobi_svd(hipStream_t s, const double* Xr, int k, long ldx, int cap,
                 double tol, int max_sweeps, double* Vt, double* sigbuf,

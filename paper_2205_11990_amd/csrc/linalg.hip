@@ -773,7 +773,7 @@ int svd_truncate(hipStream_t s, Arena& ws, double* X, int m, int c, long ldx,
   if (discarded) *discarded = h[1];
   g_stats.jacobi_sweeps += (long)h[2];
   if (onchip && k > kJacobiOneWgCols && h[5] != 0.0)
-    throw Error(kEdevice, "Jacobi SVD: the two workgroups did not meet in time");
+    throw Error(kEdevice, "Jacobi SVD: the workgroups did not meet in time");
   if (h[3] == 0.0)
     throw Error(kEnumeric, "Jacobi SVD did not converge within " +
                                std::to_string(g_max_sweeps) + " sweeps");
