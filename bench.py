@@ -15,6 +15,22 @@ Two modes:
           bond runs at the full chi = 64 shape.
   physics: tol = 1e-10, level C1, from f0 (bonds follow the physics).
 
+Beside the metric line, three measurements of the same JSON object
+(skipped with --no-extras):
+  mixed    the same workload with the MPO x MPS contractions in FP32 on the
+           matrix cores (QR, SVD, Poisson and moments in FP64): steps/s and
+           the one-step error of f, E and the field energy against an FP64
+           step from the same state.
+  batched  64 Landau instances of a parameter sweep (k, alpha, 2^8..2^11
+           grids, chi in {16, 32, 48, 64}, physics mode) stepped together
+           by mps_step_batched: aggregate steps/s against stepping them one
+           after the other.
+  serving  seeded Poisson arrivals (mean 20 requests/s) of Landau and
+           two-stream solve requests (grids 2^8..2^10, chi in {32, 64},
+           FP32 contraction, tol 1e-6 with every compression capped at chi),
+           admitted by device-memory bound against a budget: p50/p99
+           latency and aggregate steps/s.
+
 Usage: python bench.py [--steps K] [--warmup W] [--mode fixed|physics]
 Prints one JSON line.  Runs on one GPU only (--gpus must be 1).
 """
@@ -151,6 +167,107 @@ def roofline(binding, st, cores_host, steps):
             "classes": classes}
 
 
+def mixed_precision(binding, w, cores_host, steps):
+    """FP32-contraction mode on the benchmarked workload: steps/s from the
+    same state, and the error of one step against an FP64 step."""
+    import copy
+    import torch
+    p64 = w.problem
+    p32 = copy.copy(p64)
+    p32.precision = 1
+    ref = binding.MpsState(p64, w.ax, w.bv)
+    ref.set_cores(cores_host)
+    ref.step(1)
+    f64 = ref.to_dense().cpu().numpy()
+    _, E64, sc64 = ref.moments()
+    E64 = E64.cpu().numpy()
+    ref.free()
+    st = binding.MpsState(p32, w.ax, w.bv)
+    st.set_cores(cores_host)
+    st.step(1)
+    f32 = st.to_dense().cpu().numpy()
+    _, E32, sc32 = st.moments()
+    E32 = E32.cpu().numpy()
+    st.set_cores(cores_host)
+    st.step(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st.step(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    st.free()
+    return {"precision": "fp32 contraction (MFMA f32, FP32 accumulate); QR/SVD/Poisson FP64",
+            "steps_per_s": steps / el, "steps": steps,
+            "f_max_rel_err_one_step": float(np.abs(f32 - f64).max() / np.abs(f64).max()),
+            "E_max_rel_err_one_step": float(np.abs(E32 - E64).max() / np.abs(E64).max()),
+            "field_energy_rel_err_one_step": float(abs(sc32["field_energy"] - sc64["field_energy"])
+                                                   / abs(sc64["field_energy"]))}
+
+
+def batched(binding, count, steps):
+    """Aggregate steps/s of a parameter sweep stepped together, against the
+    same instances stepped one after the other."""
+    import torch
+    ws = wl.landau_sweep(count)
+    states = [binding.MpsState(x.problem, x.ax, x.bv) for x in ws]
+    binding.step_batched(states, 1)  # warm-up (arenas, first factorisations)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    binding.step_batched(states, steps)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for s in states:
+        s.step(steps)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    for s in states:
+        s.free()
+    return {"instances": count, "steps_each": steps,
+            "grids": "2^8..2^11", "chi": "16..64", "mode": "physics (C1, tol=1e-10)",
+            "aggregate_steps_per_s": count * steps / tb,
+            "sequential_steps_per_s": count * steps / ts,
+            "speedup": ts / tb}
+
+
+def serving_run(binding, n_req, steps, seed=11990):
+    """Scaled serving workload: Poisson arrivals, half Landau, half
+    two-stream, physics mode, FP32 contraction, HBM-budget admission."""
+    from paper_2205_11990_amd import serving
+    rng = np.random.default_rng(seed)
+    arrivals = serving.poisson_arrivals(n_req, rate=20.0, seed=seed)
+    reqs = []
+    for i in range(n_req):
+        L = int(rng.integers(8, 11))
+        chi = int(rng.choice([32, 64]))
+        # FP32 contractions leave rounding noise near 1e-7 of the largest
+        # singular value: the truncation tolerance sits above it and every
+        # compression point is capped at chi
+        if rng.random() < 0.5:
+            x = wl.landau_small(L=L, chi=chi, tol=1e-6, level=5)
+            x.problem.dt = wl.stable_dt(x.problem, 0.05)
+            kind = "landau"
+        else:
+            x = wl.two_stream(L=L, chi=chi, tol=1e-6, level=5)
+            kind = "two-stream"
+        x.problem.precision = 1
+        reqs.append(serving.Request(i, x.problem, x.ax, x.bv, steps, float(arrivals[i]), kind))
+    budget = 64 << 30
+    def done(r):
+        print("[bench] serving request %d (%s) %s latency %.3f s" % (
+            r.rid, r.kind, "ok" if r.error is None else r.error, r.latency),
+            file=sys.stderr, flush=True)
+
+    res = serving.Server(budget_bytes=budget, slots=16).run(reqs, on_done=done)
+    out = serving.summary(res)
+    out.update({"arrival_rate_per_s": 20.0, "steps_each": steps, "grids": "2^8..2^10",
+                "chi": "32, 64", "precision": "fp32 contraction",
+                "compression": "every point capped at chi (C5), tol=1e-6",
+                "hbm_budget_bytes": budget,
+                "max_request_bound_bytes": int(max(r.bound for r in res))})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -159,6 +276,8 @@ def main():
     ap.add_argument("--mode", default="fixed", choices=["fixed", "physics"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the mixed-precision, batched and serving measurements")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (calibrates "
                          "the FETCH_SIZE / WRITE_SIZE counters)")
@@ -216,6 +335,15 @@ def main():
         cpu = cpu_baseline(w, args.mode, cores_host)
         print("[bench] cpu baseline %s" % cpu, file=sys.stderr, flush=True)
 
+    extras = {}
+    if not args.no_extras:
+        extras["mixed"] = mixed_precision(binding, w, cores_host, min(args.steps, 5))
+        print("[bench] mixed %s" % json.dumps(extras["mixed"]), file=sys.stderr, flush=True)
+        extras["batched"] = batched(binding, 64, 3)
+        print("[bench] batched %s" % json.dumps(extras["batched"]), file=sys.stderr, flush=True)
+        extras["serving"] = serving_run(binding, 24, 20)
+        print("[bench] serving %s" % json.dumps(extras["serving"]), file=sys.stderr, flush=True)
+
     out = {
         "metric": "time steps/s at Nx=Nv=2^10, chi=64",
         "value": value,
@@ -236,6 +364,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
     }
+    out.update(extras)
     print(json.dumps(out))
 
 

@@ -62,7 +62,11 @@ typedef enum { MPS_ORDER_SEQ = 0, MPS_ORDER_INTERLEAVED = 1 } mps_order;
 /* Arithmetic of the MPO x MPS contractions (SI, "Matrix-vector
  * multiplication"): FP64, or operands rounded to FP32 with FP32
  * accumulation on the matrix cores (results kept in FP64).  The QR and SVD
- * sweeps, the Poisson field and the moments are FP64 in both modes. */
+ * sweeps, the Poisson field and the moments are FP64 in both modes.  FP32
+ * contraction leaves rounding noise near 1e-7 of the largest singular
+ * value in every contracted term: with a tolerance below that, compression
+ * points without a chi cap keep the noise and their bonds grow towards full
+ * rank, so FP32 runs use tol >= 1e-6 or cap every point (level 5). */
 typedef enum { MPS_PREC_FP64 = 0, MPS_PREC_FP32_CONTRACT = 1 } mps_precision;
 
 /* Problem statement.  Site orderings (Fig. 3): MPS_ORDER_SEQ is x bits

@@ -68,9 +68,11 @@ class Server:
         self.budget = int(budget_bytes)
         self.slots = int(slots)
 
-    def run(self, requests: Sequence[Request], realtime: bool = True) -> List[Result]:
+    def run(self, requests: Sequence[Request], realtime: bool = True,
+            on_done: Optional[Callable[[Result], None]] = None) -> List[Result]:
         """Serve the requests; with realtime, a request is not admitted
-        before its arrival time.  Returns the results in request order."""
+        before its arrival time.  on_done is called with each result as it
+        completes.  Returns the results in request order."""
         import torch
         reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
         cv = threading.Condition()
@@ -101,12 +103,15 @@ class Server:
             except Exception as e:  # reported per request
                 err = "%s: %s" % (type(e).__name__, e)
             fin = now()
+            res = Result(req.rid, req.kind, req.arrival, admitted, fin, req.steps, bound,
+                         sc, bonds, err)
             with cv:
-                results[req.rid] = Result(req.rid, req.kind, req.arrival, admitted, fin,
-                                          req.steps, bound, sc, bonds, err)
+                results[req.rid] = res
                 used[0] -= bound
                 used[1] -= 1
                 cv.notify_all()
+            if on_done is not None:
+                on_done(res)
 
         threads = []
         for req in reqs:
