@@ -43,6 +43,7 @@
 // relative discarded weight is <= tol) (eq. 5 with the i = D+1 reading), and
 // Vt (D x k) holds the kept right singular vectors (normalised columns).
 #include <cmath>
+#include <cstdlib>
 #include <mutex>
 
 #include "jacobi.hpp"
@@ -61,14 +62,16 @@ constexpr int MAXT = 1024;  // 64 nodes of 16 lanes
 // orthogonal whatever t is, so t comes from the hardware estimates (about
 // 5e-8 relative, which only leaves a residual cosine of that order times
 // the one removed, cleaned up by the following sweeps); cs must satisfy
-// cs^2 + sn^2 = 1 to rounding and is refined by two Newton steps.
+// cs^2 + sn^2 = 1 to rounding and is refined by two Newton steps.  No
+// branch: for |z| beyond 1e154, z^2 overflows and t becomes 0, an angle
+// below 1e-154 that would not change a double anyway (the rotation test
+// keeps |z| far below that).
 __device__ inline void rotation(double a, double b, double g, double& cs,
                                 double& sn) {
   const double z = (b - a) * __builtin_amdgcn_rcp(2.0 * g);
   const double az = fabs(z);
-  double t;
-  if (az > 1e150) t = 0.5 * __builtin_amdgcn_rcp(z);
-  else t = copysign(__builtin_amdgcn_rcp(az + __builtin_amdgcn_sqrt(fma(z, z, 1.0))), z);
+  const double t =
+      copysign(__builtin_amdgcn_rcp(az + __builtin_amdgcn_sqrt(fma(z, z, 1.0))), z);
   const double w = fma(t, t, 1.0);
   double y = __builtin_amdgcn_rsq(w);
   y = fma(y, 0.5 * fma(-w * y, y, 1.0), y);
@@ -370,22 +373,27 @@ __global__ __launch_bounds__(MAXT) void jacobi_hc_kernel(
 
 // ------------------------------------------ several workgroups (k <= 256)
 
-constexpr int kMultiWgs = 4;                     // workgroups
-constexpr int kMultiLog = 2;                     // log2(kMultiWgs)
-constexpr int kMultiNodes = 128 / kMultiWgs;     // nodes per workgroup
-constexpr int kMultiLocal = 5;                   // log2(kMultiNodes)
-constexpr int kMultiT = 16 * kMultiNodes;        // threads per workgroup
-constexpr int kMultiRpt = 16;                    // rows per lane: up to 256
-constexpr int kMultiCol = 16 * kMultiRpt;        // doubles per column
-constexpr int kMultiStride = kMultiCol + 16;     // padded LDS column slot
+constexpr int kMaxWgs = 8;                       // most workgroups of a split
 constexpr long kSpinLimit = 1L << 22;            // polls per wait, ~1 s
-static_assert(kMultiNodes == 1 << kMultiLocal, "nodes per workgroup");
-static_assert(kMultiWgs == 1 << kMultiLog, "workgroups");
+
+// A split Jacobi: 2^NLOG nodes over 2^GLOG workgroups, RPT rows per lane.
+template <int NLOG, int GLOG, int RPT>
+struct Split {
+  static constexpr int wgs = 1 << GLOG;
+  static constexpr int local = NLOG - GLOG;       // node bits inside a workgroup
+  static constexpr int nodes = 1 << local;        // nodes per workgroup
+  static constexpr int threads = 16 * nodes;
+  static constexpr int col = 16 * RPT;            // doubles per column
+  static constexpr int stride = col + 16;         // padded LDS column slot
+  static constexpr int slots = wgs * 2 * nodes;   // exchange slots
+  static_assert(local >= 2, "lane-row bits stay inside the workgroup");
+  static_assert(wgs <= kMaxWgs, "too many workgroups");
+};
 
 // Global exchange area of the workgroups (see jacobi_ws_doubles); the
 // slots alternate with the parity of the rendezvous number.
 struct MultiWs {
-  double* xg;   // [wg][parity][node][kMultiCol] outgoing columns
+  double* xg;   // [wg][parity][node][col] outgoing columns
   double* xn;   // [wg][parity][node] their squared norms
   double* val;  // [wg][parity] rendezvous payload
   int* xi;      // [wg][parity][node] their indices
@@ -406,7 +414,7 @@ __device__ inline int flag_read(int* f) {
 // workgroup does not arrive within the spin limit.  Since every workgroup
 // waits for all others at each rendezvous, a slot written at rendezvous e
 // has been read by everyone before any workgroup passes e + 1.
-__device__ bool meet_all(const MultiWs& w, int wg, int e, double mine,
+__device__ bool meet_all(const MultiWs& w, int wgs, int wg, int e, double mine,
                          double& total, int* sh_ok, double* sh_val) {
   __threadfence();
   __syncthreads();
@@ -414,7 +422,7 @@ __device__ bool meet_all(const MultiWs& w, int wg, int e, double mine,
     w.val[wg * 2 + (e & 1)] = mine;
     flag_publish(w.flags + wg, e);
     int ok = 1;
-    for (int q = 0; q < kMultiWgs && ok; ++q) {
+    for (int q = 0; q < wgs && ok; ++q) {
       if (q == wg) continue;
       long spins = 0;
       while (flag_read(w.flags + q) < e) {
@@ -426,7 +434,7 @@ __device__ bool meet_all(const MultiWs& w, int wg, int e, double mine,
       }
     }
     double t = 0.0;
-    for (int q = 0; q < kMultiWgs && ok; ++q)
+    for (int q = 0; q < wgs && ok; ++q)
       t += (q == wg) ? mine : w.val[q * 2 + (e & 1)];
     *sh_ok = ok;
     *sh_val = t;
@@ -446,13 +454,22 @@ __device__ inline int pick(bool c, int a, int b) { return c ? a : b; }
 
 // Info: [0] D, [1] discarded weight, [2] sweeps, [3] converged, [4] steps,
 // [5] 1 if a rendezvous timed out.  Same inputs and outputs as
-// jacobi_hc_kernel; launched as exactly kMultiWgs workgroups of kMultiT
-// threads.  Node bits 0-1 are lane rows, 2-4 waves, 5-6 the workgroup.
-__global__ __launch_bounds__(kMultiT) void jacobi_multi_kernel(
+// jacobi_hc_kernel; launched as exactly S::wgs workgroups of S::threads
+// threads.  Node bits 0-1 are lane rows, 2..local-1 waves, the rest the
+// workgroup.
+template <int NLOG, int GLOG, int RPT>
+__global__ __launch_bounds__(16 << (NLOG - GLOG)) void jacobi_multi_kernel(
     const double* __restrict__ Xr, int k, long ldx, int max_sweeps, int cap,
     double tol, double* __restrict__ Vt, double* __restrict__ sigbuf,
     int* __restrict__ perm_out, double* __restrict__ info, MultiWs w) {
-  constexpr int RPT = kMultiRpt;
+  using S = Split<NLOG, GLOG, RPT>;
+  constexpr int kMultiWgs = S::wgs;
+  constexpr int kMultiLog = GLOG;
+  constexpr int kMultiNodes = S::nodes;
+  constexpr int kMultiLocal = S::local;
+  constexpr int kMultiT = S::threads;
+  constexpr int kMultiCol = S::col;
+  constexpr int kMultiStride = S::stride;
   extern __shared__ double smem[];
   __shared__ double red[kMultiT / 64];
   __shared__ double lxn[kMultiNodes];
@@ -488,7 +505,7 @@ __global__ __launch_bounds__(kMultiT) void jacobi_multi_kernel(
   double mine = 0.0;
   for (int v = 0; v < kMultiT / 64; ++v) mine += red[v];
   double normF2 = 0.0;
-  bool ok = meet_all(w, wg, ++epoch, mine, normF2, &sh_ok, &sh_val);
+  bool ok = meet_all(w, kMultiWgs, wg, ++epoch, mine, normF2, &sh_ok, &sh_val);
   const double scale = normF2 > 0.0 ? 1.0 / sqrt(normF2) : 1.0;
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
@@ -603,7 +620,7 @@ __global__ __launch_bounds__(kMultiT) void jacobi_multi_kernel(
     const long theirs = (long)(pw * 2 + (e & 1)) * kMultiNodes + x;
     send(w.xg + mine_s * kMultiCol, w.xn + mine_s, w.xi + mine_s, up);
     double unused;
-    if (!meet_all(w, wg, ++epoch, 0.0, unused, &sh_ok, &sh_val)) return false;
+    if (!meet_all(w, kMultiWgs, wg, ++epoch, 0.0, unused, &sh_ok, &sh_val)) return false;
     receive(w.xg + theirs * kMultiCol, w.xn + theirs, w.xi + theirs, up);
     return true;
   };
@@ -631,7 +648,7 @@ __global__ __launch_bounds__(kMultiT) void jacobi_multi_kernel(
     if (!ok) break;
     __syncthreads();
     double any = 0.0;
-    ok = meet_all(w, wg, ++epoch, sweep_any ? 1.0 : 0.0, any, &sh_ok, &sh_val);
+    ok = meet_all(w, kMultiWgs, wg, ++epoch, sweep_any ? 1.0 : 0.0, any, &sh_ok, &sh_val);
     if (!ok) break;
     if (any == 0.0) {
       converged = 1;
@@ -658,7 +675,7 @@ __global__ __launch_bounds__(kMultiT) void jacobi_multi_kernel(
     }
   }
   double unused_total;
-  if (ok) ok = meet_all(w, wg, ++epoch, 0.0, unused_total, &sh_ok, &sh_val);
+  if (ok) ok = meet_all(w, kMultiWgs, wg, ++epoch, 0.0, unused_total, &sh_ok, &sh_val);
   if (!ok) {
     if (tid == 0) {
       info[3] = 0.0;
@@ -756,8 +773,75 @@ Shape shape_of(int k) {
 
 }  // namespace
 
+namespace {
+
+// Split chosen for k columns: 0 = one workgroup (jacobi_hc_kernel), else
+// log2 of the workgroups.  Up to 128 columns one workgroup unless
+// MPSV_JACOBI_SPLIT128 asks for 1 (2 workgroups) or 2 (4); above, four
+// workgroups unless MPSV_JACOBI_SPLIT256 asks for 3 (8).
+int split_of(int k) {
+  static const int s128 = [] {
+    const char* e = std::getenv("MPSV_JACOBI_SPLIT128");
+    const int v = e ? std::atoi(e) : 0;
+    return (v == 1 || v == 2) ? v : 0;
+  }();
+  static const int s256 = [] {
+    const char* e = std::getenv("MPSV_JACOBI_SPLIT256");
+    const int v = e ? std::atoi(e) : 2;
+    return v == 3 ? 3 : 2;
+  }();
+  if (k > kJacobiOneWgCols) return s256;
+  return k > 64 ? s128 : 0;
+}
+
+template <int NLOG, int GLOG, int RPT>
+size_t split_lds() {
+  using S = Split<NLOG, GLOG, RPT>;
+  return (size_t)S::nodes * S::stride * sizeof(double);
+}
+
+template <int NLOG, int GLOG, int RPT>
+size_t split_ws() {
+  using S = Split<NLOG, GLOG, RPT>;
+  // xg, xn, val; then xi and flags as ints
+  return (size_t)S::slots * S::col + S::slots + 2 * S::wgs + (S::slots + S::wgs + 1) / 2 + 1;
+}
+
+template <int NLOG, int GLOG, int RPT>
+void launch_split(hipStream_t s, const double* Xr, int k, long ldx, int cap,
+                  double tol, int max_sweeps, double* Vt, double* sigbuf,
+                  int* perm, double* info, double* ws) {
+  using S = Split<NLOG, GLOG, RPT>;
+  static std::once_flag once;
+  std::call_once(once, [] {
+    MPSV_HIP(hipFuncSetAttribute((const void*)jacobi_multi_kernel<NLOG, GLOG, RPT>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)kJacobiMaxLds));
+  });
+  MultiWs w;
+  w.xg = ws;
+  w.xn = w.xg + (size_t)S::slots * S::col;
+  w.val = w.xn + S::slots;
+  w.xi = (int*)(w.val + 2 * S::wgs);
+  w.flags = w.xi + S::slots;
+  fill_int(s, w.flags, S::wgs, 0);
+  jacobi_multi_kernel<NLOG, GLOG, RPT><<<dim3(S::wgs), dim3(S::threads),
+                                         split_lds<NLOG, GLOG, RPT>(), s>>>(
+      Xr, k, ldx, max_sweeps, cap, tol, Vt, sigbuf, perm, info, w);
+  MPSV_LAUNCHED();
+}
+
+}  // namespace
+
+int jacobi_split(int k) { return split_of(k); }
+
 size_t jacobi_lds_bytes(int k) {
-  if (k > kJacobiOneWgCols) return (size_t)kMultiNodes * kMultiStride * sizeof(double);
+  switch (split_of(k)) {
+    case 1: return split_lds<6, 1, 8>();
+    case 2: return k > kJacobiOneWgCols ? split_lds<7, 2, 16>() : split_lds<6, 2, 8>();
+    case 3: return split_lds<7, 3, 16>();
+    default: break;
+  }
   const Shape s = shape_of(k);
   const size_t xch = (size_t)2 * s.nodes * 16 * s.rpt;
   const size_t cols = (size_t)k * (size_t)(k | 1);
@@ -765,10 +849,12 @@ size_t jacobi_lds_bytes(int k) {
 }
 
 size_t jacobi_ws_doubles(int k) {
-  if (k <= kJacobiOneWgCols) return 0;
-  // xg, xn, val; then xi and flags as ints
-  const size_t slots = (size_t)kMultiWgs * 2 * kMultiNodes;
-  return slots * kMultiCol + slots + 2 * kMultiWgs + (slots + kMultiWgs + 1) / 2 + 1;
+  switch (split_of(k)) {
+    case 1: return split_ws<6, 1, 8>();
+    case 2: return k > kJacobiOneWgCols ? split_ws<7, 2, 16>() : split_ws<6, 2, 8>();
+    case 3: return split_ws<7, 3, 16>();
+    default: return 0;
+  }
 }
 
 void jacobi_svd(hipStream_t s, const double* Xr, int k, long ldx, int cap,
@@ -776,9 +862,6 @@ void jacobi_svd(hipStream_t s, const double* Xr, int k, long ldx, int cap,
                 int* perm, double* info, double* ws) {
   static std::once_flag once;
   std::call_once(once, [] {
-    MPSV_HIP(hipFuncSetAttribute((const void*)jacobi_multi_kernel,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)kJacobiMaxLds));
     MPSV_HIP(hipFuncSetAttribute((const void*)jacobi_hc_kernel<2>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)kJacobiMaxLds));
@@ -793,20 +876,17 @@ void jacobi_svd(hipStream_t s, const double* Xr, int k, long ldx, int cap,
              "Jacobi SVD: matrix does not fit on chip");
   const size_t lds = jacobi_lds_bytes(k);
   MPSV_CHECK(lds <= kJacobiMaxLds, kEinval, "Jacobi SVD: LDS too small");
-  if (k > kJacobiOneWgCols) {
+  const int split = split_of(k);
+  if (split > 0) {
     MPSV_CHECK(ws != nullptr, kEinval, "Jacobi SVD: workspace missing");
-    const size_t slots = (size_t)kMultiWgs * 2 * kMultiNodes;
-    MultiWs w;
-    w.xg = ws;
-    w.xn = w.xg + slots * kMultiCol;
-    w.val = w.xn + slots;
-    w.xi = (int*)(w.val + 2 * kMultiWgs);
-    w.flags = w.xi + slots;
-    fill_int(s, w.flags, kMultiWgs, 0);
-    hipLaunchKernelGGL(jacobi_multi_kernel, dim3(kMultiWgs), dim3(kMultiT), lds,
-                       s, Xr, k, ldx, max_sweeps, cap, tol, Vt, sigbuf, perm,
-                       info, w);
-    MPSV_LAUNCHED();
+    if (split == 1)
+      launch_split<6, 1, 8>(s, Xr, k, ldx, cap, tol, max_sweeps, Vt, sigbuf, perm, info, ws);
+    else if (split == 2 && k <= kJacobiOneWgCols)
+      launch_split<6, 2, 8>(s, Xr, k, ldx, cap, tol, max_sweeps, Vt, sigbuf, perm, info, ws);
+    else if (split == 2)
+      launch_split<7, 2, 16>(s, Xr, k, ldx, cap, tol, max_sweeps, Vt, sigbuf, perm, info, ws);
+    else
+      launch_split<7, 3, 16>(s, Xr, k, ldx, cap, tol, max_sweeps, Vt, sigbuf, perm, info, ws);
     return;
   }
   const Shape sh = shape_of(k);

@@ -8,6 +8,10 @@ constexpr size_t kJacobiMaxLds = 150 * 1024;
 constexpr int kJacobiOneWgCols = 128;  // one workgroup up to here
 constexpr int kJacobiMaxCols = 256;    // four workgroups up to here
 
+// How a k x k factor is decomposed: 0 on one workgroup, else log2 of the
+// number of workgroups sharing it.
+int jacobi_split(int k);
+
 // LDS bytes of the kernel for a k x k factor.
 size_t jacobi_lds_bytes(int k);
 

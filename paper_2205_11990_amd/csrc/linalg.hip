@@ -1,10 +1,13 @@
 // FP64 factorisations for the compression sweeps (SI, "Canonicalization and
 // Compression"): blocked Householder QR and one-sided Jacobi SVD.
 //
-// QR: right-looking blocked Householder.  A panel of jb <= 32 columns is
-// factored by one workgroup (held in LDS when it fits), which also forms the
-// compact-WY factor T and Y = V T; the trailing matrix is updated with two
-// MFMA GEMMs, A2 -= V (Y^T A2).
+// QR: right-looking blocked Householder with register-resident panels
+// (qr_reg.hip).  Blocks of at most 2048 rows are factored panel by panel on
+// one workgroup each, the trailing columns updated by the reflector
+// application kernel.  Taller blocks factor each 16-column panel as a TSQR:
+// row chunks of at most 2048 rows factored side by side in one launch, then
+// the stacked triangular factors; the trailing columns take the chunk
+// reflectors and then those of the stacked factor on the chunk-top rows.
 //
 // SVD: X (m x c) is first reduced to its c x c triangular factor when tall,
 // then one-sided (Hestenes) Jacobi with the cyclic round-robin ordering is
@@ -29,8 +32,6 @@ namespace mpsv {
 namespace {
 
 constexpr int NT = 256;
-constexpr int MAXJB = 32;
-constexpr size_t kPanelLds = 144 * 1024;
 constexpr size_t kJacobiLds = 144 * 1024;
 
 LinalgStats g_stats;
@@ -63,161 +64,6 @@ __device__ inline double block_sum(double v, double* red) {
 #pragma unroll
   for (int i = 0; i < NT / 64; ++i) t += red[i];
   return t;
-}
-
-// Panel factorisation of P (m x jb, row stride ld, global memory).  The
-// panel is staged in LDS (leading dimension jb+1, odd, so column reads are
-// conflict-free) when use_lds, else worked on in place.  Thread t owns
-// column j = t % jb of row group g = t / jb for the reflector products;
-// their partial sums meet in an LDS table, one barrier per column.
-__global__ __launch_bounds__(NT) void qr_panel_kernel(double* P, int m, int jb,
-                                                      long ld, double* V,
-                                                      double* Y, int use_lds) {
-  extern __shared__ double smem[];
-  __shared__ double part[NT];
-  __shared__ double red[NT / 64];
-  __shared__ double tau_s[MAXJB];
-  __shared__ double T[MAXJB][MAXJB + 1];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int ngr = NT / jb;            // row groups
-  const int gj = tid % jb, gg = tid / jb;
-  const bool owner = gg < ngr;
-
-  double* pp;
-  long pld;
-  if (use_lds) {
-    pp = smem;
-    pld = jb + 1;
-    for (long e = tid; e < (long)m * jb; e += NT) {
-      const long i = e / jb, j = e % jb;
-      pp[i * pld + j] = P[i * ld + j];
-    }
-    __syncthreads();
-  } else {
-    pp = P;
-    pld = ld;
-  }
-
-  for (int c = 0; c < jb; ++c) {
-    // norm of the column below the diagonal
-    double sq = 0.0;
-#pragma unroll 4
-    for (int i = c + 1 + tid; i < m; i += NT) {
-      const double x = pp[(long)i * pld + c];
-      sq = fma(x, x, sq);
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o, 64);
-    if (lane == 0) red[wv] = sq;
-    __syncthreads();
-    double xn2 = 0.0;
-#pragma unroll
-    for (int i = 0; i < NT / 64; ++i) xn2 += red[i];
-    const double alpha = pp[(long)c * pld + c];
-    double tau = 0.0, beta = alpha, scal = 0.0;
-    if (xn2 > 0.0) {
-      beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
-      tau = (beta - alpha) / beta;
-      scal = 1.0 / (alpha - beta);
-    }
-    __syncthreads();
-    if (xn2 > 0.0)
-      for (int i = c + 1 + tid; i < m; i += NT) pp[(long)i * pld + c] *= scal;
-    if (tid == 0) {
-      pp[(long)c * pld + c] = beta;
-      tau_s[c] = tau;
-    }
-    __syncthreads();
-    if (c + 1 < jb && tau != 0.0) {
-      // w_j = sum_{i >= c} v_i P[i][j] for j > c
-      double acc = 0.0;
-      if (owner && gj > c) {
-        // four independent accumulators so that the LDS loads pipeline
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        int i = c + gg;
-        if (i == c) {
-          a0 = pp[(long)c * pld + gj];
-          i += ngr;
-        }
-        for (; i + 3 * ngr < m; i += 4 * ngr) {
-          a0 = fma(pp[(long)i * pld + c], pp[(long)i * pld + gj], a0);
-          a1 = fma(pp[(long)(i + ngr) * pld + c], pp[(long)(i + ngr) * pld + gj], a1);
-          a2 = fma(pp[(long)(i + 2 * ngr) * pld + c], pp[(long)(i + 2 * ngr) * pld + gj], a2);
-          a3 = fma(pp[(long)(i + 3 * ngr) * pld + c], pp[(long)(i + 3 * ngr) * pld + gj], a3);
-        }
-        for (; i < m; i += ngr) a0 = fma(pp[(long)i * pld + c], pp[(long)i * pld + gj], a0);
-        acc = (a0 + a1) + (a2 + a3);
-      }
-      part[tid] = acc;
-      __syncthreads();
-      double w = 0.0;
-      if (owner && gj > c) {
-        for (int q = 0; q < ngr; ++q) w += part[q * jb + gj];
-        w *= tau;
-#pragma unroll 4
-        for (int i = c + gg; i < m; i += ngr) {
-          const double vi = (i == c) ? 1.0 : pp[(long)i * pld + c];
-          pp[(long)i * pld + gj] -= vi * w;
-        }
-      }
-      __syncthreads();
-    }
-  }
-
-  // T (upper triangular): T[0:c,c] = -tau_c T[0:c,0:c] (V^T v_c)
-  for (int c = 0; c < jb; ++c) {
-    double acc = 0.0;
-    if (owner && gj < c) {
-      double a0 = 0.0, a1 = 0.0;
-      int i = c + gg;
-      if (i == c) {
-        a0 = pp[(long)c * pld + gj];
-        i += ngr;
-      }
-      for (; i + ngr < m; i += 2 * ngr) {
-        a0 = fma(pp[(long)i * pld + gj], pp[(long)i * pld + c], a0);
-        a1 = fma(pp[(long)(i + ngr) * pld + gj], pp[(long)(i + ngr) * pld + c], a1);
-      }
-      for (; i < m; i += ngr) a0 = fma(pp[(long)i * pld + gj], pp[(long)i * pld + c], a0);
-      acc = a0 + a1;   // V[i][gj] V[i][c] over i >= c (V[c][c] = 1)
-    }
-    part[tid] = acc;
-    __syncthreads();
-    if (tid < jb) {
-      if (tid < c) {
-        double t = 0.0;
-        for (int l = tid; l < c; ++l) {
-          double zl = 0.0;
-          for (int q = 0; q < ngr; ++q) zl += part[q * jb + l];
-          t += T[tid][l] * zl;
-        }
-        T[tid][c] = -tau_s[c] * t;
-      } else if (tid == c) {
-        T[c][c] = tau_s[c];
-      } else {
-        T[tid][c] = 0.0;
-      }
-    }
-    __syncthreads();
-  }
-  // explicit V (unit lower trapezoidal) and Y = V T
-  for (long e = tid; e < (long)m * jb; e += NT) {
-    const int i = (int)(e / jb), c = (int)(e % jb);
-    double y = 0.0;
-    for (int k = 0; k <= c && k <= i; ++k) {
-      const double vk = (i == k) ? 1.0 : pp[(long)i * pld + k];
-      y = fma(vk, T[k][c], y);
-    }
-    Y[e] = y;
-    V[e] = (i < c) ? 0.0 : (i == c ? 1.0 : pp[(long)i * pld + c]);
-  }
-  if (use_lds) {
-    __syncthreads();
-    for (long e = tid; e < (long)m * jb; e += NT) {
-      const long i = e / jb, j = e % jb;
-      P[i * ld + j] = pp[i * pld + j];
-    }
-  }
 }
 
 __global__ void extract_r_kernel(const double* A, int k, int n, long ld,
@@ -419,6 +265,21 @@ __global__ __launch_bounds__(NT) void jacobi_svd_kernel(
   }
 }
 
+// Chunk-top rows of a TSQR panel: stacked row t of T (t < srows) is row
+// (t / jb) * crows + t % jb of X (leading dimension ld); gathered into T
+// (srows x nc, row-major) or scattered back.
+__global__ void chunk_tops_kernel(double* X, long ld, int crows, int jb,
+                                  int srows, int nc, double* T, int gather) {
+  const long total = (long)srows * nc;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x) {
+    const int t = (int)(e / nc), c = (int)(e % nc);
+    const long row = (long)(t / jb) * crows + t % jb;
+    if (gather) T[e] = X[row * ld + c];
+    else X[row * ld + c] = T[e];
+  }
+}
+
 // Pinned host words for the rank read-back, one block per stream (several
 // host threads may run sweeps on different streams at once).
 std::mutex g_pinned_mu;
@@ -434,9 +295,6 @@ double* pinned_info(hipStream_t s) {
 std::once_flag g_attr_once;
 void set_attrs() {
   std::call_once(g_attr_once, [] {
-    MPSV_HIP(hipFuncSetAttribute((const void*)qr_panel_kernel,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)kPanelLds));
     MPSV_HIP(hipFuncSetAttribute((const void*)jacobi_svd_kernel,
                                  hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)kJacobiLds));
@@ -455,6 +313,15 @@ void extract_r(hipStream_t s, const double* A, int k, int n, long ld,
   int blocks = std::min(1024, ceil_div((long)k * n, 256));
   hipLaunchKernelGGL(extract_r_kernel, dim3(blocks), dim3(256), 0, s, A, k, n,
                      ld, R);
+  MPSV_LAUNCHED();
+}
+
+void chunk_tops(hipStream_t s, double* X, long ld, int crows, int jb, int srows,
+                int nc, double* T, bool gather) {
+  if (srows <= 0 || nc <= 0) return;
+  int blocks = std::min(1024, ceil_div((long)srows * nc, 256));
+  hipLaunchKernelGGL(chunk_tops_kernel, dim3(blocks), dim3(256), 0, s, X, ld,
+                     crows, jb, srows, nc, T, gather ? 1 : 0);
   MPSV_LAUNCHED();
 }
 
@@ -532,22 +399,23 @@ void qr_factor(hipStream_t s, Arena& ws, double* A, int m, int n, long ld,
   f.k = std::min(m, n);
   f.panels.clear();
   g_stats.qr_calls++;
-  if (m <= 2048) {
-    // register-resident panels; the trailing columns are updated by the
-    // reflector-application kernel
-    const bool single = n <= qr_reg_panel_cols(m);
-    for (int k0 = 0; k0 < f.k;) {
-      const int rows = m - k0;
+  // one register panel with a separate R: written straight there, A
+  // untouched
+  const bool single = m <= 2048 && n <= qr_reg_panel_cols(m);
+  for (int k0 = 0; k0 < f.k;) {
+    const int rows = m - k0;
+    double* P = A + (long)k0 * ld + k0;
+    QrPanel pn;
+    pn.k0 = k0;
+    if (rows <= 2048) {
+      // register-resident panel; the trailing columns are updated by the
+      // reflector-application kernel
       const int jb = std::min(qr_reg_panel_cols(rows), n - k0);
       const int kk = std::min(rows, jb);
-      QrPanel pn;
-      pn.k0 = k0;
       pn.jb = kk;
       pn.reg = true;
       pn.V = ws.alloc((size_t)rows * kk);
       pn.tau = ws.alloc((size_t)kk);
-      double* P = A + (long)k0 * ld + k0;
-      // one panel with a separate R: written straight there, A untouched
       const MatView Rout = (single && R.p) ? R : MatView{P, ld, 1, 0};
       qr_reg_factor(s, CMatView{P, ld, 1, 0}, rows, jb, Rout, pn.V, pn.tau);
       const int n2 = n - k0 - jb;
@@ -556,47 +424,46 @@ void qr_factor(hipStream_t s, Arena& ws, double* A, int m, int n, long ld,
                      MatView{P + jb, ld, 1, 0}, n2, true);
       f.panels.push_back(pn);
       k0 += jb;
+      continue;
     }
-    if (R.p && !single) extract_r(s, A, f.k, n, ld, R);
-    return;
-  }
-  for (int k0 = 0; k0 < f.k; ) {
-    const int rows = m - k0;
-    int jb = std::min(MAXJB, f.k - k0);
-    int use_lds = 0;
-    while (jb > 4 && (size_t)rows * (jb + 1) * sizeof(double) > kPanelLds) jb /= 2;
-    if ((size_t)rows * (jb + 1) * sizeof(double) <= kPanelLds) use_lds = 1;
-    QrPanel pn;
-    pn.k0 = k0;
+    // TSQR panel: chunks of at most 2048 rows, each factored on its own
+    // workgroup, their triangular factors stacked (chunk c at rows c*jb) and
+    // factored again; the panel's R lands in the panel's top rows
+    const int jb = std::min(qr_reg_panel_cols(2048), f.k - k0);
+    const int nch = (rows + 2047) / 2048;
+    const int crows = (rows + nch - 1) / nch;
+    const int last = rows - (nch - 1) * crows;
     pn.jb = jb;
-    pn.V = ws.alloc((size_t)rows * jb);
-    pn.Y = ws.alloc((size_t)rows * jb);
-    double* P = A + (long)k0 * ld + k0;
-    size_t lds = use_lds ? (size_t)rows * (jb + 1) * sizeof(double) : 0;
-    const int slot = prof_begin(s);
-    hipLaunchKernelGGL(qr_panel_kernel, dim3(1), dim3(NT), lds, s, P, rows, jb,
-                       ld, pn.V, pn.Y, use_lds);
-    MPSV_LAUNCHED();
-    // nominal GEQRF flops of the panel, 2 m n^2 - 2 n^3 / 3
-    prof_end(s, slot, kClsQrPanel,
-             2.0 * rows * (double)jb * jb - 2.0 * jb * (double)jb * jb / 3.0,
-             16.0 * rows * jb);
+    pn.crows = crows;
+    pn.srows = (nch - 1) * jb + std::min(last, jb);
+    pn.V = ws.alloc((size_t)nch * crows * jb);
+    pn.tau = ws.alloc((size_t)nch * jb);
+    pn.Vt = ws.alloc((size_t)pn.srows * jb);
+    pn.taut = ws.alloc((size_t)jb);
+    {
+      ArenaScope sc(ws);
+      double* S = ws.alloc((size_t)nch * jb * jb);
+      qr_reg_factor_chunks(s, CMatView{P, ld, 1, 0}, rows, jb, crows,
+                           MatView{S, jb, 1, 0}, pn.V, pn.tau);
+      qr_reg_factor(s, CMatView{S, jb, 1, 0}, pn.srows, jb, MatView{P, ld, 1, 0},
+                    pn.Vt, pn.taut);
+    }
     const int n2 = n - k0 - jb;
     if (n2 > 0) {
+      // trailing columns: Q^T = Q_top^T diag(Q_c^T)
+      qr_reg_apply_chunks(s, pn.V, pn.tau, rows, jb, crows,
+                          MatView{P + jb, ld, 1, 0}, n2, true);
       ArenaScope sc(ws);
-      double* Wt = ws.alloc((size_t)jb * n2);
-      double* A2 = A + (long)k0 * ld + k0 + jb;
-      // Wt = Y^T A2  (jb x n2)
-      gemm(s, jb, n2, rows, 1.0, CMatView{pn.Y, 1, jb, 0},
-           CMatView{A2, ld, 1, 0}, 0.0, MatView{Wt, n2, 1, 0});
-      // A2 -= V Wt
-      gemm(s, rows, n2, jb, -1.0, CMatView{pn.V, jb, 1, 0},
-           CMatView{Wt, n2, 1, 0}, 1.0, MatView{A2, ld, 1, 0});
+      double* T = ws.alloc((size_t)pn.srows * n2);
+      chunk_tops(s, P + jb, ld, crows, jb, pn.srows, n2, T, true);
+      qr_reg_apply(s, pn.Vt, pn.taut, pn.srows, jb, CMatView{T, n2, 1, 0},
+                   pn.srows, MatView{T, n2, 1, 0}, n2, true);
+      chunk_tops(s, P + jb, ld, crows, jb, pn.srows, n2, T, false);
     }
     f.panels.push_back(pn);
     k0 += jb;
   }
-  if (R.p) extract_r(s, A, f.k, n, ld, R);
+  if (R.p && !single) extract_r(s, A, f.k, n, ld, R);
 }
 
 void qr_factor_view(hipStream_t s, Arena& ws, CMatView A, int m, int n,
@@ -657,13 +524,16 @@ void qr_apply_q(hipStream_t s, Arena& ws, const QrFactor& f, double* X, int nc,
                    MatView{X2, ldx, 1, 0}, nc, false);
       continue;
     }
+    // TSQR panel: Q = diag(Q_c) Q_top, the stacked factor acting on the
+    // chunk-top rows
     ArenaScope sc(ws);
-    double* Wt = ws.alloc((size_t)pn.jb * nc);
-    // Wt = V^T X2 ; X2 -= Y Wt
-    gemm(s, pn.jb, nc, rows, 1.0, CMatView{pn.V, 1, pn.jb, 0},
-         CMatView{X2, ldx, 1, 0}, 0.0, MatView{Wt, nc, 1, 0});
-    gemm(s, rows, nc, pn.jb, -1.0, CMatView{pn.Y, pn.jb, 1, 0},
-         CMatView{Wt, nc, 1, 0}, 1.0, MatView{X2, ldx, 1, 0});
+    double* T = ws.alloc((size_t)pn.srows * nc);
+    chunk_tops(s, X2, ldx, pn.crows, pn.jb, pn.srows, nc, T, true);
+    qr_reg_apply(s, pn.Vt, pn.taut, pn.srows, pn.jb, CMatView{T, nc, 1, 0},
+                 pn.srows, MatView{T, nc, 1, 0}, nc, false);
+    chunk_tops(s, X2, ldx, pn.crows, pn.jb, pn.srows, nc, T, false);
+    qr_reg_apply_chunks(s, pn.V, pn.tau, rows, pn.jb, pn.crows,
+                        MatView{X2, ldx, 1, 0}, nc, false);
   }
 }
 

@@ -13,12 +13,19 @@ namespace mpsv {
 // factored matrix.  Register-resident panels (reg) keep the reflectors
 // column-major, V[j*(m-k0) + i], with their tau; the LDS panels keep the
 // compact-WY form H = I - V T V^T with V (m-k0) x jb row-major and Y = V T.
+// One panel of a blocked QR: either a register panel (reflectors V, tau
+// over the rows from k0 on) or, for blocks taller than 2048 rows, a TSQR
+// panel: chunks of crows rows with their own reflectors (V at c*crows*jb,
+// tau at c*jb) and the reflectors Vt, taut of the stacked chunk factors
+// (srows rows, chunk c's at rows c*jb).
 struct QrPanel {
-  int k0, jb;
+  int k0 = 0, jb = 0;
   bool reg = false;
   double* V = nullptr;
-  double* Y = nullptr;
   double* tau = nullptr;
+  int crows = 0, srows = 0;
+  double* Vt = nullptr;
+  double* taut = nullptr;
 };
 
 struct QrFactor {
@@ -53,6 +60,12 @@ void extract_r(hipStream_t s, const double* A, int k, int n, long ld,
                MatView R);
 
 // out (rows x cols) <- in for rows < rows_in, 0 below; any strides.
+// Gather (gather = true) the chunk-top rows of a TSQR panel from X into T
+// (srows x nc, row-major), or scatter T back: stacked row t is row
+// (t / jb) * crows + t % jb of X (leading dimension ld).
+void chunk_tops(hipStream_t s, double* X, long ld, int crows, int jb, int srows,
+                int nc, double* T, bool gather);
+
 void copy_view(hipStream_t s, CMatView in, int rows_in, MatView out, int rows,
                int cols);
 

@@ -27,6 +27,15 @@
 
 namespace mpsv {
 
+// Row chunks of a tall block handled by the workgroups y of one launch:
+// chunk y is rows [y * rows, min((y + 1) * rows, m)); its reflectors start
+// at V + y * rows * kstride and tau + y * kstride.  One chunk ({m, k}) is
+// the plain single-block case.
+struct Chunks {
+  int rows;
+  int kstride;
+};
+
 namespace {
 
 constexpr int FT = 1024;  // factorisation workgroup: 16 waves
@@ -150,10 +159,19 @@ __device__ __forceinline__ void factor_block(double (&x)[RPL][CPW], int w,
 template <int CPW, int RPL>
 __global__ __launch_bounds__(FT) void qr_reg_factor_kernel(
     CMatView A, int m, int n, MatView R, double* __restrict__ V,
-    double* __restrict__ tau) {
+    double* __restrict__ tau, Chunks ch) {
   __shared__ double vb[2 * 64 * RPL];
   __shared__ double tb[2];
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  // workgroup y factors rows [y * ch.rows, ...) of A on its own; its R
+  // block goes n rows further down R, its reflectors to its own slots
+  const int cb = blockIdx.y;
+  const int row0 = cb * ch.rows;
+  m = min(ch.rows, m - row0);
+  A.p += (long)row0 * A.rs;
+  R.p += (long)cb * n * R.rs;
+  V += (long)cb * ch.rows * n;
+  tau += (long)cb * n;
   const int k = m < n ? m : n;
   double x[RPL][CPW];
 #pragma unroll
@@ -433,8 +451,22 @@ __global__ __launch_bounds__(FT) void qr_blk_factor_kernel(
 template <int CPW, int RPL>
 __global__ __launch_bounds__(AT) void qr_reg_apply_kernel(
     const double* __restrict__ V, const double* __restrict__ tau, int m, int k,
-    CMatView Yin, int rows_in, MatView Yout, int p, int trans) {
+    CMatView Yin, int rows_in, MatView Yout, int p, int trans, Chunks ch) {
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  // workgroup row y applies the reflectors of chunk y to rows
+  // [y * ch.rows, ...) (see qr_reg_factor_chunks)
+  {
+    const int cb = blockIdx.y;
+    const int row0 = cb * ch.rows;
+    const int mc = min(ch.rows, m - row0);
+    V += (long)cb * ch.rows * ch.kstride;
+    tau += (long)cb * ch.kstride;
+    k = min(k, mc);
+    rows_in = min(rows_in - row0, mc);
+    m = mc;
+    Yin.p += (long)row0 * Yin.rs;
+    Yout.p += (long)row0 * Yout.rs;
+  }
   const int c0 = (blockIdx.x * (AT / 64) + w) * CPW;
   if (c0 >= p) return;  // whole wave; the kernel has no barrier
   double y[RPL][CPW];
@@ -509,18 +541,18 @@ int cols_per_wave(int n) {
 
 template <int CPW, int RPL>
 void launch_factor(hipStream_t s, CMatView A, int m, int n, MatView R,
-                   double* V, double* tau) {
-  hipLaunchKernelGGL((qr_reg_factor_kernel<CPW, RPL>), dim3(1), dim3(FT), 0, s,
-                     A, m, n, R, V, tau);
+                   double* V, double* tau, Chunks ch, int nchunks) {
+  hipLaunchKernelGGL((qr_reg_factor_kernel<CPW, RPL>), dim3(1, nchunks), dim3(FT), 0, s,
+                     A, m, n, R, V, tau, ch);
 }
 
 template <int CPW, int RPL>
 void launch_apply(hipStream_t s, const double* V, const double* tau, int m,
                   int k, CMatView Yin, int rows_in, MatView Yout, int p,
-                  int trans) {
+                  int trans, Chunks ch, int nchunks) {
   const int per_block = (AT / 64) * CPW;
-  hipLaunchKernelGGL((qr_reg_apply_kernel<CPW, RPL>), dim3(ceil_div(p, per_block)),
-                     dim3(AT), 0, s, V, tau, m, k, Yin, rows_in, Yout, p, trans);
+  hipLaunchKernelGGL((qr_reg_apply_kernel<CPW, RPL>), dim3(ceil_div(p, per_block), nchunks),
+                     dim3(AT), 0, s, V, tau, m, k, Yin, rows_in, Yout, p, trans, ch);
 }
 
 }  // namespace
@@ -560,7 +592,7 @@ void qr_reg_factor(hipStream_t s, CMatView A, int m, int n, MatView R,
     hipLaunchKernelGGL((qr_g16_factor_kernel<C, Rr>), dim3(1), dim3(FT), 0, s, \
                        A, m, n, R, V, tau); else
 #define MPSV_F(C, Rr)                                                   \
-  if (cpw == C && rpl == Rr) launch_factor<C, Rr>(s, A, m, n, R, V, tau); else
+  if (cpw == C && rpl == Rr) launch_factor<C, Rr>(s, A, m, n, R, V, tau, Chunks{m, n}, 1); else
   if (blk)
     hipLaunchKernelGGL((qr_blk_factor_kernel<2>), dim3(1), dim3(FT), 0, s, A, m, n, R, V, tau);
   else
@@ -593,7 +625,7 @@ void qr_reg_apply(hipStream_t s, const double* V, const double* tau, int m,
   const int slot = prof_begin(s);
   const int tr = trans ? 1 : 0;
 #define MPSV_A(C, Rr)                                                   \
-  if (cpw == C && rpl == Rr) launch_apply<C, Rr>(s, V, tau, m, k, Yin, rows_in, Yout, p, tr); else
+  if (cpw == C && rpl == Rr) launch_apply<C, Rr>(s, V, tau, m, k, Yin, rows_in, Yout, p, tr, Chunks{m, k}, 1); else
   MPSV_A(1, 1) MPSV_A(2, 1) MPSV_A(1, 2) MPSV_A(2, 2) MPSV_A(1, 4) MPSV_A(2, 4)
   MPSV_A(1, 8) MPSV_A(2, 8) MPSV_A(1, 16) MPSV_A(2, 16) MPSV_A(1, 32)
   throw Error(kEinval, "qr_reg_apply: no kernel for this shape");
@@ -602,6 +634,51 @@ void qr_reg_apply(hipStream_t s, const double* V, const double* tau, int m,
   // k reflectors of decreasing length applied to p columns
   prof_end(s, slot, kClsQrApply, 4.0 * p * (double)k * (m - (k - 1) / 2.0),
            8.0 * (2.0 * m * p + (double)m * k));
+}
+
+void qr_reg_factor_chunks(hipStream_t s, CMatView A, int m, int n, int rows,
+                          MatView S, double* V, double* tau) {
+  const int nch = (m + rows - 1) / rows;
+  MPSV_CHECK(rows >= n && rows <= 2048 && n <= qr_reg_panel_cols(rows) &&
+                 qr_reg_fits(rows, n),
+             kEinval, "qr_reg_factor_chunks: shape does not fit");
+  const int rpl = rows_per_lane(rows), cpw = cols_per_wave(n);
+  const int slot = prof_begin(s);
+  const Chunks ch{rows, n};
+#define MPSV_F(C, Rr)                                                   \
+  if (cpw == C && rpl == Rr) launch_factor<C, Rr>(s, A, m, n, S, V, tau, ch, nch); else
+  MPSV_F(1, 1) MPSV_F(2, 1) MPSV_F(4, 1) MPSV_F(8, 1)
+  MPSV_F(1, 2) MPSV_F(2, 2) MPSV_F(4, 2) MPSV_F(8, 2)
+  MPSV_F(1, 4) MPSV_F(2, 4) MPSV_F(4, 4) MPSV_F(8, 4)
+  MPSV_F(1, 8) MPSV_F(2, 8) MPSV_F(4, 8)
+  MPSV_F(1, 16) MPSV_F(1, 32)
+  throw Error(kEinval, "qr_reg_factor_chunks: no kernel for this shape");
+#undef MPSV_F
+  MPSV_LAUNCHED();
+  prof_end(s, slot, kClsQrPanel,
+           2.0 * m * (double)n * n - 2.0 * nch * n * (double)n * n / 3.0,
+           8.0 * 3.0 * m * n);
+}
+
+void qr_reg_apply_chunks(hipStream_t s, const double* V, const double* tau,
+                         int m, int k, int rows, MatView Y, int p, bool trans) {
+  if (p <= 0 || k <= 0) return;
+  const int nch = (m + rows - 1) / rows;
+  MPSV_CHECK(rows >= k && rows <= 2048, kEinval, "qr_reg_apply_chunks: bad shape");
+  const int rpl = rows_per_lane(rows);
+  const int cpw = (p >= 128 && rpl < 32) ? 2 : 1;
+  const int slot = prof_begin(s);
+  const int tr = trans ? 1 : 0;
+  const Chunks ch{rows, k};
+  const CMatView Yin{Y.p, Y.rs, Y.cs, 0};
+#define MPSV_A(C, Rr)                                                   \
+  if (cpw == C && rpl == Rr) launch_apply<C, Rr>(s, V, tau, m, k, Yin, m, Y, p, tr, ch, nch); else
+  MPSV_A(1, 1) MPSV_A(2, 1) MPSV_A(1, 2) MPSV_A(2, 2) MPSV_A(1, 4) MPSV_A(2, 4)
+  MPSV_A(1, 8) MPSV_A(2, 8) MPSV_A(1, 16) MPSV_A(2, 16) MPSV_A(1, 32)
+  throw Error(kEinval, "qr_reg_apply_chunks: no kernel for this shape");
+#undef MPSV_A
+  MPSV_LAUNCHED();
+  prof_end(s, slot, kClsQrApply, 4.0 * p * (double)k * m, 8.0 * (2.0 * m * p + (double)m * k));
 }
 
 }  // namespace mpsv

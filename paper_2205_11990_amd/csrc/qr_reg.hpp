@@ -29,4 +29,18 @@ void qr_reg_apply(hipStream_t s, const double* V, const double* tau, int m,
                   int k, CMatView Yin, int rows_in, MatView Yout, int p,
                   bool trans);
 
+// Row-chunked factorisation of a tall panel (the first step of a TSQR): A
+// (m x n) is cut into chunks of `rows` rows (the last one may be shorter;
+// rows >= n, rows <= 2048, n <= qr_reg_panel_cols(rows)), each factored on
+// its own workgroup of one launch.  Chunk c writes its R (min(rows_c, n) x
+// n) at rows [c n, c n + min(rows_c, n)) of S, its reflectors (rows_c long,
+// V[j*rows_c + i]) at V + c*rows*n and tau at tau + c*n.
+void qr_reg_factor_chunks(hipStream_t s, CMatView A, int m, int n, int rows,
+                          MatView S, double* V, double* tau);
+
+// Y <- Q_c Y or Q_c^T Y on every chunk c of rows of Y (m x p, in place), with
+// the reflectors of qr_reg_factor_chunks (k per chunk, same rows).
+void qr_reg_apply_chunks(hipStream_t s, const double* V, const double* tau,
+                         int m, int k, int rows, MatView Y, int p, bool trans);
+
 }  // namespace mpsv

@@ -13,10 +13,12 @@
 namespace mpsv {
 namespace wave {
 
+// Row-local DPP move of a double.  The patterns used here read valid lanes
+// everywhere, so no "old" value is needed (and none is initialised).
 template <int CTRL>
 __device__ inline double dpp(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
   return __hiloint2double(hi, lo);
 }
 

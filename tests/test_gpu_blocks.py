@@ -62,7 +62,9 @@ def test_gemm_fp32_contract_matches_fp32_rounded_product(B, M, N, K):
                                  (600, 200), (2048, 8), (64, 300), (128, 128), (256, 128),
                                  (512, 64), (1024, 128), (1000, 100), (200, 129), (700, 700),
                                  (65, 17), (2048, 40), (1500, 300), (2048, 512),
-                                 (4000, 64)])
+                                 # taller than 2048 rows: TSQR panels
+                                 (4000, 64), (2049, 700), (5120, 256), (8200, 48),
+                                 (3000, 3000)])
 def test_qr_is_orthogonal_factorisation(B, m, n):
     _say("qr %d x %d" % (m, n))
     A = wl.random_matrix(m, n, seed=m + 7 * n, decay=3.0)
