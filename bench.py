@@ -17,10 +17,12 @@ Two modes:
 
 Beside the metric line, three measurements of the same JSON object
 (skipped with --no-extras):
-  mixed    the same workload with the MPO x MPS contractions in FP32 on the
-           matrix cores (QR, SVD, Poisson and moments in FP64): steps/s and
-           the one-step error of f, E and the field energy against an FP64
-           step from the same state.
+  mixed    the same workload with the MPO x MPS contractions in FP32 and
+           in BF16 on the matrix cores (FP32 accumulation; QR, SVD, Poisson
+           and moments in FP64): steps/s and the one-step error of f, E and
+           the field energy against an FP64 step from the same state.
+  chi128   bond cap 128 on a 2^12 x 2^12 two-stream grid (fixed-chi mode):
+           FP64 steps/s and the same mixed-precision comparison.
   batched  64 Landau instances of a parameter sweep (k, alpha, 2^8..2^11
            grids, chi in {16, 32, 48, 64}, physics mode) stepped together
            by mps_step_batched: aggregate steps/s against stepping them one
@@ -167,41 +169,81 @@ def roofline(binding, st, cores_host, steps):
             "classes": classes}
 
 
-def mixed_precision(binding, w, cores_host, steps):
-    """FP32-contraction mode on the benchmarked workload: steps/s from the
-    same state, and the error of one step against an FP64 step."""
+_PREC_NAMES = {1: "fp32 contraction (MFMA f32, FP32 accumulate)",
+               2: "bf16 contraction (MFMA bf16, FP32 accumulate)"}
+
+
+def _one_step(binding, problem, w, cores_host, precision):
     import copy
-    import torch
-    p64 = w.problem
-    p32 = copy.copy(p64)
-    p32.precision = 1
-    ref = binding.MpsState(p64, w.ax, w.bv)
-    ref.set_cores(cores_host)
-    ref.step(1)
-    f64 = ref.to_dense().cpu().numpy()
-    _, E64, sc64 = ref.moments()
-    E64 = E64.cpu().numpy()
-    ref.free()
-    st = binding.MpsState(p32, w.ax, w.bv)
+    p = copy.copy(problem)
+    p.precision = precision
+    st = binding.MpsState(p, w.ax, w.bv)
     st.set_cores(cores_host)
     st.step(1)
-    f32 = st.to_dense().cpu().numpy()
-    _, E32, sc32 = st.moments()
-    E32 = E32.cpu().numpy()
-    st.set_cores(cores_host)
+    f = st.to_dense().cpu().numpy()
+    _, E, sc = st.moments()
+    E = E.cpu().numpy()
+    return st, p, f, E, sc
+
+
+def mixed_precision(binding, w, cores_host, steps, fp64_steps_per_s=None):
+    """Reduced-precision contraction modes on a workload: steps/s from the
+    same state, and the error of one step against an FP64 step from it
+    (QR/SVD/Poisson/moments FP64 in every mode)."""
+    import torch
+    ref, _, f64, E64, sc64 = _one_step(binding, w.problem, w, cores_host, 0)
+    out = {}
+    if fp64_steps_per_s is None:
+        ref.set_cores(cores_host)
+        ref.step(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ref.step(steps)
+        torch.cuda.synchronize()
+        fp64_steps_per_s = steps / (time.perf_counter() - t0)
+    out["fp64_steps_per_s"] = fp64_steps_per_s
+    ref.free()
+    for prec in (1, 2):
+        st, _, f, E, sc = _one_step(binding, w.problem, w, cores_host, prec)
+        st.set_cores(cores_host)
+        st.step(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st.step(steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        st.free()
+        out[{1: "fp32", 2: "bf16"}[prec]] = {
+            "precision": _PREC_NAMES[prec] + "; QR/SVD/Poisson/moments FP64",
+            "steps_per_s": steps / el, "steps": steps,
+            "speedup_vs_fp64": (steps / el) / fp64_steps_per_s,
+            "f_max_rel_err_one_step": float(np.abs(f - f64).max() / np.abs(f64).max()),
+            "E_max_rel_err_one_step": float(np.abs(E - E64).max() / np.abs(E64).max()),
+            "field_energy_rel_err_one_step": float(abs(sc["field_energy"] - sc64["field_energy"])
+                                                   / abs(sc64["field_energy"]))}
+    return out
+
+
+def chi128_run(binding, steps):
+    """The bond cap 128 workload: two-stream 2^12 x 2^12, interleaved,
+    every point capped at 128, D_F = 4, tol = 0, seeded perturbation to
+    bond 128; FP64 steps/s and the reduced-precision modes against it."""
+    import torch
+    w = wl.two_stream(L=12, chi=128, tol=0.0, level=5, df_max=4, dt_cfg=0.02)
+    st = start_state(binding, w, "fixed")
     st.step(1)
     torch.cuda.synchronize()
+    cores = st.get_cores_host()
     t0 = time.perf_counter()
     st.step(steps)
     torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+    v = steps / (time.perf_counter() - t0)
     st.free()
-    return {"precision": "fp32 contraction (MFMA f32, FP32 accumulate); QR/SVD/Poisson FP64",
-            "steps_per_s": steps / el, "steps": steps,
-            "f_max_rel_err_one_step": float(np.abs(f32 - f64).max() / np.abs(f64).max()),
-            "E_max_rel_err_one_step": float(np.abs(E32 - E64).max() / np.abs(E64).max()),
-            "field_energy_rel_err_one_step": float(abs(sc32["field_energy"] - sc64["field_energy"])
-                                                   / abs(sc64["field_energy"]))}
+    out = {"workload": "two-stream 2^12 x 2^12, interleaved (24 sites), chi=128, C5, tol=0, "
+                       "D_F=4, seeded random-MPS perturbation",
+           "dt": w.problem.dt}
+    out.update(mixed_precision(binding, w, cores, steps, fp64_steps_per_s=v))
+    return out
 
 
 def batched(binding, count, steps):
@@ -337,12 +379,15 @@ def main():
 
     extras = {}
     if not args.no_extras:
-        extras["mixed"] = mixed_precision(binding, w, cores_host, min(args.steps, 5))
+        extras["mixed"] = mixed_precision(binding, w, cores_host, min(args.steps, 5),
+                                          fp64_steps_per_s=value)
         print("[bench] mixed %s" % json.dumps(extras["mixed"]), file=sys.stderr, flush=True)
         extras["batched"] = batched(binding, 64, 3)
         print("[bench] batched %s" % json.dumps(extras["batched"]), file=sys.stderr, flush=True)
         extras["serving"] = serving_run(binding, 24, 20)
         print("[bench] serving %s" % json.dumps(extras["serving"]), file=sys.stderr, flush=True)
+        extras["chi128"] = chi128_run(binding, 2)
+        print("[bench] chi128 %s" % json.dumps(extras["chi128"]), file=sys.stderr, flush=True)
 
     out = {
         "metric": "time steps/s at Nx=Nv=2^10, chi=64",

@@ -20,9 +20,10 @@ mps_status mpsb_gemm(int32_t M, int32_t N, int32_t K, double alpha,
                      int64_t ldb, double beta, double* C, int64_t ldc,
                      hipStream_t stream);
 
-/* mpsb_gemm with the precision of the MPO x MPS contractions: MPS_PREC_FP64
- * or MPS_PREC_FP32_CONTRACT (operands rounded to FP32, FP32 accumulation on
- * the matrix cores, result stored in FP64).  MPS_EINVAL for other values. */
+/* mpsb_gemm with the precision of the MPO x MPS contractions: MPS_PREC_FP64,
+ * MPS_PREC_FP32_CONTRACT or MPS_PREC_BF16_CONTRACT (operands rounded to FP32,
+ * or to BF16 through FP32, FP32 accumulation on the matrix cores, result
+ * stored in FP64).  MPS_EINVAL for other values. */
 mps_status mpsb_gemm_prec(int32_t M, int32_t N, int32_t K, double alpha,
                           const double* A, int64_t lda, const double* B,
                           int64_t ldb, double beta, double* C, int64_t ldc,

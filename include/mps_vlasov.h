@@ -60,14 +60,20 @@ typedef enum {
 typedef enum { MPS_ORDER_SEQ = 0, MPS_ORDER_INTERLEAVED = 1 } mps_order;
 
 /* Arithmetic of the MPO x MPS contractions (SI, "Matrix-vector
- * multiplication"): FP64, or operands rounded to FP32 with FP32
+ * multiplication"): FP64, or operands rounded to FP32 (mode 1) or to BF16
+ * (mode 2: to FP32, then to the nearest BF16, ties to even) with FP32
  * accumulation on the matrix cores (results kept in FP64).  The QR and SVD
- * sweeps, the Poisson field and the moments are FP64 in both modes.  FP32
- * contraction leaves rounding noise near 1e-7 of the largest singular
- * value in every contracted term: with a tolerance below that, compression
- * points without a chi cap keep the noise and their bonds grow towards full
- * rank, so FP32 runs use tol >= 1e-6 or cap every point (level 5). */
-typedef enum { MPS_PREC_FP64 = 0, MPS_PREC_FP32_CONTRACT = 1 } mps_precision;
+ * sweeps, the Poisson field and the moments are FP64 in every mode.
+ * Reduced precision leaves rounding noise in every contracted term, near
+ * 1e-7 (FP32) or 4e-3 (BF16) of its largest singular value: with a
+ * tolerance below that, compression points without a chi cap keep the
+ * noise and their bonds grow towards full rank, so such runs use a
+ * tolerance above the noise or cap every point (level 5). */
+typedef enum {
+  MPS_PREC_FP64 = 0,
+  MPS_PREC_FP32_CONTRACT = 1,
+  MPS_PREC_BF16_CONTRACT = 2
+} mps_precision;
 
 /* Problem statement.  Site orderings (Fig. 3): MPS_ORDER_SEQ is x bits
  * coarse->fine then v bits coarse->fine (S1); MPS_ORDER_INTERLEAVED is

@@ -355,11 +355,12 @@ mps_status mpsb_gemm_prec(int32_t M, int32_t N, int32_t K, double alpha,
     MPSV_CHECK(M >= 0 && N >= 0 && K >= 0, mpsv::kEinval, "negative size");
     MPSV_CHECK(lda >= K && ldb >= N && ldc >= N, mpsv::kEinval,
                "leading dimension too small");
-    MPSV_CHECK(precision == MPS_PREC_FP64 || precision == MPS_PREC_FP32_CONTRACT,
+    MPSV_CHECK(precision == MPS_PREC_FP64 || precision == MPS_PREC_FP32_CONTRACT ||
+                   precision == MPS_PREC_BF16_CONTRACT,
                mpsv::kEinval, "unknown precision");
     mpsv::gemm(stream, M, N, K, alpha, mpsv::CMatView{A, lda, 1, 0},
                mpsv::CMatView{B, ldb, 1, 0}, beta, mpsv::MatView{C, ldc, 1, 0},
-               1, precision == MPS_PREC_FP32_CONTRACT);
+               1, (int)precision);
     MPSV_HIP(hipStreamSynchronize(stream));
   });
 }

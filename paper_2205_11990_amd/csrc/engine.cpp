@@ -354,7 +354,7 @@ Engine::Engine(const Problem& p) : p_(p), chunk_(memory_model(p).chunk) {
   MPSV_CHECK(p.level >= 1 && p.level <= 5, kEinval, "level must be in 1..5");
   MPSV_CHECK(p.df_max >= 0, kEinval, "df_max must be >= 0");
   MPSV_CHECK(std::isfinite(p.tol) && p.tol >= 0, kEinval, "tol must be >= 0");
-  MPSV_CHECK(p.precision == 0 || p.precision == 1, kEinval,
+  MPSV_CHECK(p.precision >= 0 && p.precision <= 2, kEinval,
              "unknown precision mode");
   MPSV_CHECK(std::isfinite(p.qm), kEinval, "q/m must be finite");
 
@@ -463,11 +463,11 @@ void Engine::absorb_left(const VSite& v, const double* R, int p, double* M,
       // X[(p,b)][(i,a')] = sum_a R[p][(b,a)] A[a][i][a']
       gemm(s, p * wl, 2 * ar, al, 1.0, CMatView{R, al, 1, 0},
            CMatView{v.A.p, 2L * ar, 1, 0}, 0.0, MatView{X, 2L * ar, 1, 0}, 1,
-           f32_contract());
+           contract_prec());
       // M_p[(o,b')][a'] = sum_(b,i) Wmat[(o,b')][(b,i)] X_p[(b,i)][a']
       gemm(s, 2 * wr, ar, 2 * wl, 1.0, CMatView{v.W.Wmat, 2L * wl, 1, 0},
            CMatView{X, ar, 1, 2L * wl * ar}, 0.0,
-           MatView{M, ar, 1, 2L * wr * ar}, p, f32_contract());
+           MatView{M, ar, 1, 2L * wr * ar}, p, contract_prec());
       break;
     }
     case VSite::kSum: {
@@ -516,12 +516,12 @@ void Engine::absorb_right(const VSite& v, const double* L, int q, double* N,
       double* Z = work().alloc((size_t)al * 2 * wr * q);
       gemm(s, 2 * al, q, ar, 1.0, CMatView{v.A.p, ar, 1, 0},
            CMatView{L, q, 1, (long)ar * q}, 0.0,
-           MatView{Z, (long)wr * q, 1, q}, wr, f32_contract());
+           MatView{Z, (long)wr * q, 1, q}, wr, contract_prec());
       // N'[a][(b,o)][q] = sum_(i,b') W[(b,o)][(i,b')] Z[a][(i,b')][q]
       double* Np = work().alloc((size_t)al * wl * 2 * q);
       gemm(s, 2 * wl, q, 2 * wr, 1.0, CMatView{v.W.W, 2L * wr, 1, 0},
            CMatView{Z, q, 1, 2L * wr * q}, 0.0,
-           MatView{Np, q, 1, 2L * wl * q}, al, f32_contract());
+           MatView{Np, q, 1, 2L * wl * q}, al, contract_prec());
       // N[b][a][o][q] = N'[a][b][o][q]
       swap01(s, Np, al, wl, 2L * q, N);
       break;

@@ -143,9 +143,10 @@ class Engine {
   // Compression workspace of the calling thread: work_ on the thread that
   // drives the engine, work2_ on the side thread of rhs().
   Arena& work();
-  // MPO x MPS contractions in FP32 on the matrix cores (precision mode 1);
-  // factorisations, Poisson field and moments stay FP64.
-  bool f32_contract() const { return p_.precision == 1; }
+  // arithmetic of the MPO x MPS contractions: 0 FP64, 1 FP32, 2 BF16 on the
+  // matrix cores (precision mode); factorisations, Poisson field and moments
+  // stay FP64
+  int contract_prec() const { return p_.precision; }
 
   Problem p_;
   // chunk size of the arenas, scaled to the problem (see memory_model)

@@ -98,12 +98,30 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(
       }
 }
 
-// FP32-contraction variant (the MPS problem's precision mode 1): the FP64
-// operands are rounded to FP32 as they are staged in LDS, the products are
-// accumulated in FP32 by v_mfma_f32_16x16x4f32, and the result is stored as
-// FP64.  Same tiling and views as gemm_f64_kernel.
+// Reduced-precision contraction variants (the MPS problem's precision modes
+// 1 and 2): the FP64 operands are rounded as they are staged in LDS, to
+// FP32 (MODE 1) or to BF16 (MODE 2: to FP32, then to the nearest BF16, ties
+// to even), the products are accumulated in FP32 on the matrix cores
+// (v_mfma_f32_16x16x4f32, or v_mfma_f32_16x16x16bf16 whose BF16 products
+// are exact in FP32), and the result is stored as FP64.  Same tiling and
+// views as gemm_f64_kernel.
 typedef float flt4 __attribute__((ext_vector_type(4)));
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
 
+// x rounded to the nearest BF16 (ties to even), as a float; finite inputs
+__device__ inline float round_bf16(float x) {
+  unsigned u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return __uint_as_float(u & 0xFFFF0000u);
+}
+
+template <int MODE>
+__device__ inline float stage(double x) {
+  if constexpr (MODE == 2) return round_bf16((float)x);
+  else return (float)x;
+}
+
+template <int MODE>
 __global__ __launch_bounds__(NT) void gemm_f32acc_kernel(
     int M, int N, int K, double alpha, const double* __restrict__ A, long ars,
     long acs, long abs_, const double* __restrict__ B, long brs, long bcs,
@@ -135,7 +153,7 @@ __global__ __launch_bounds__(NT) void gemm_f32acc_kernel(
       int r, k;
       if (a_kfast) { r = e / BK; k = e % BK; } else { k = e / BM; r = e % BM; }
       int gr = m0 + r, gk = k0 + k;
-      As[k][r] = (gr < M && gk < kend) ? (float)A[(long)gr * ars + (long)gk * acs] : 0.0f;
+      As[k][r] = (gr < M && gk < kend) ? stage<MODE>(A[(long)gr * ars + (long)gk * acs]) : 0.0f;
     }
 #pragma unroll
     for (int q = 0; q < (BN * BK) / NT; ++q) {
@@ -143,20 +161,39 @@ __global__ __launch_bounds__(NT) void gemm_f32acc_kernel(
       int c, k;
       if (b_nfast) { k = e / BN; c = e % BN; } else { c = e / BK; k = e % BK; }
       int gc = n0 + c, gk = k0 + k;
-      Bs[k][c] = (gc < N && gk < kend) ? (float)B[(long)gk * brs + (long)gc * bcs] : 0.0f;
+      Bs[k][c] = (gc < N && gk < kend) ? stage<MODE>(B[(long)gk * brs + (long)gc * bcs]) : 0.0f;
     }
     __syncthreads();
+    if constexpr (MODE == 2) {
+      // one 16 x 16 x 16 step: lane l holds k = 4 (l / 16) + q, q < 4, of
+      // row (A) or column (B) l % 16, as the high halves of the staged floats
+      static_assert(BK == 16, "one BF16 MFMA step per tile");
+      bf16x4 a0, a1, b0, b1;
 #pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      const int kr = kk + (lane >> 4);
-      const float a0 = As[kr][wm * 32 + (lane & 15)];
-      const float a1 = As[kr][wm * 32 + 16 + (lane & 15)];
-      const float b0 = Bs[kr][wn * 32 + (lane & 15)];
-      const float b1 = Bs[kr][wn * 32 + 16 + (lane & 15)];
-      acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+      for (int q = 0; q < 4; ++q) {
+        const int kr = 4 * (lane >> 4) + q;
+        a0[q] = (short)(__float_as_uint(As[kr][wm * 32 + (lane & 15)]) >> 16);
+        a1[q] = (short)(__float_as_uint(As[kr][wm * 32 + 16 + (lane & 15)]) >> 16);
+        b0[q] = (short)(__float_as_uint(Bs[kr][wn * 32 + (lane & 15)]) >> 16);
+        b1[q] = (short)(__float_as_uint(Bs[kr][wn * 32 + 16 + (lane & 15)]) >> 16);
+      }
+      acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b1, acc[1][1], 0, 0, 0);
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 4) {
+        const int kr = kk + (lane >> 4);
+        const float a0 = As[kr][wm * 32 + (lane & 15)];
+        const float a1 = As[kr][wm * 32 + 16 + (lane & 15)];
+        const float b0 = Bs[kr][wn * 32 + (lane & 15)];
+        const float b1 = Bs[kr][wn * 32 + 16 + (lane & 15)];
+        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+      }
     }
     __syncthreads();
   }
@@ -223,7 +260,7 @@ double* splitk_scratch(hipStream_t s, size_t n) {
 }  // namespace
 
 void gemm(hipStream_t s, int M, int N, int K, double alpha, CMatView A,
-          CMatView B, double beta, MatView C, int batch, bool f32) {
+          CMatView B, double beta, MatView C, int batch, int prec) {
   if (M <= 0 || N <= 0 || batch <= 0) return;
   if (K <= 0) {
     // C = beta * C
@@ -248,7 +285,8 @@ void gemm(hipStream_t s, int M, int N, int K, double alpha, CMatView A,
     dim3 grid(ceil_div(N, BN), ceil_div(M, BM), nb * nsplit);
     const int slot = prof_begin(s);
     if (nsplit == 1) {
-      hipLaunchKernelGGL(f32 ? gemm_f32acc_kernel : gemm_f64_kernel, grid,
+      hipLaunchKernelGGL(prec == 2 ? gemm_f32acc_kernel<2>
+                         : prec == 1 ? gemm_f32acc_kernel<1> : gemm_f64_kernel, grid,
                          dim3(NT), 0, s, M, N, K, alpha,
                          A.p + (long)b0 * A.bs, A.rs, A.cs, A.bs,
                          B.p + (long)b0 * B.bs, B.rs, B.cs, B.bs, beta,
@@ -257,7 +295,8 @@ void gemm(hipStream_t s, int M, int N, int K, double alpha, CMatView A,
       MPSV_LAUNCHED();
     } else {
       double* P = splitk_scratch(s, (size_t)nb * nsplit * M * N);
-      hipLaunchKernelGGL(f32 ? gemm_f32acc_kernel : gemm_f64_kernel, grid,
+      hipLaunchKernelGGL(prec == 2 ? gemm_f32acc_kernel<2>
+                         : prec == 1 ? gemm_f32acc_kernel<1> : gemm_f64_kernel, grid,
                          dim3(NT), 0, s, M, N, K, 1.0,
                          A.p + (long)b0 * A.bs, A.rs, A.cs, A.bs,
                          B.p + (long)b0 * B.bs, B.rs, B.cs, B.bs, 0.0, P,

@@ -93,3 +93,24 @@ def test_invalid_arguments_are_rejected_without_a_gpu():
         binding.workspace_bound(p)
     p = wl.two_stream().problem
     assert binding.workspace_bound(p) > 0
+
+
+def test_workspace_bound_grows_with_the_problem():
+    """The admission bound (host arithmetic only) grows with the grid and
+    the bond cap, is larger for the interleaved ordering with an uncapped
+    field bond, and leaves the per-request budget far below one GPU's HBM
+    at the benchmarked size."""
+    from paper_2205_11990_amd import binding
+    import workloads as wl
+    b = {}
+    for L in (6, 8, 10, 12):
+        for chi in (16, 64, 128):
+            b[L, chi] = binding.workspace_bound(wl.two_stream(L=L, chi=chi, df_max=4).problem)
+    for L in (6, 8, 10):
+        for chi in (16, 64):
+            assert b[L, chi] <= b[L + 2, chi]
+            assert b[L, chi] <= b[L, 128]
+    seq = wl.two_stream(L=10, chi=64, df_max=4, order=wl.ORDER_SEQ).problem
+    full_df = wl.two_stream(L=10, chi=64, df_max=0).problem
+    assert binding.workspace_bound(full_df) >= b[10, 64] >= binding.workspace_bound(seq)
+    assert b[10, 64] < (4 << 30)

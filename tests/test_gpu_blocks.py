@@ -58,6 +58,30 @@ def test_gemm_fp32_contract_matches_fp32_rounded_product(B, M, N, K):
     assert np.all(np.abs(out - ref) <= 4 * K * 6e-8 * scale + 1e-30)
 
 
+def _bf16(x):
+    """Round to FP32, then to the nearest BF16 (ties to even), as float64."""
+    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (7, 5, 3), (64, 64, 16), (65, 130, 33),
+                                   (200, 96, 700), (3, 300, 2000)])
+def test_gemm_bf16_contract_matches_bf16_rounded_product(B, M, N, K):
+    """Precision mode 2: the product of the BF16-rounded operands (exact in
+    FP32), accumulated in FP32."""
+    _say("gemm bf16 %d %d %d" % (M, N, K))
+    rng = np.random.default_rng(M * 1000 + N * 10 + K + 2)
+    A = rng.standard_normal((M, K))
+    Bm = rng.standard_normal((K, N))
+    out = B.gemm(A, Bm, alpha=0.5, precision=2).cpu().numpy()
+    Ar, Br = _bf16(A), _bf16(Bm)
+    assert np.all(np.abs(Ar - A) <= 2.0 ** -8 * np.abs(A))
+    ref = 0.5 * Ar @ Br
+    scale = 0.5 * (np.abs(Ar) @ np.abs(Br))
+    assert np.all(np.abs(out - ref) <= 4 * K * 6e-8 * scale + 1e-30)
+
+
 @pytest.mark.parametrize("m,n", [(1, 1), (5, 3), (3, 5), (40, 40), (130, 70), (257, 33),
                                  (600, 200), (2048, 8), (64, 300), (128, 128), (256, 128),
                                  (512, 64), (1024, 128), (1000, 100), (200, 129), (700, 700),

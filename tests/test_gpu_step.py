@@ -258,6 +258,25 @@ def test_fp32_contraction_mode_error_against_fp64_oracle(B):
     assert err_f > 1e-13  # the FP32 path was taken
 
 
+def test_bf16_contraction_mode_error_against_fp64_oracle(B):
+    """Precision mode 2 (MPO x MPS contractions in BF16 on the matrix cores,
+    FP32 accumulation, factorisations FP64), same workload as the FP32 test:
+    the error is that of BF16 operand rounding (2^-8 relative per operand),
+    about 2^16 times the FP32 one: f within 3e-2 (observed ~3e-3) and clearly
+    above the FP32 level.  E is carried by the 1 % density modulation, which
+    BF16 rounding of f (~3e-3 of f) does not resolve: E keeps no correct
+    digit (observed relative error ~1.3) and is only checked to stay
+    finite and of the field's order (relative error <= 10)."""
+    _say("bf16 contraction landau 64x64 chi16")
+    w = wl.landau_small(L=6, chi=16, tol=1e-10)
+    w.problem.precision = 2
+    G, R, E, Eref, info, f = _from_same_state(B, w, 3)
+    err_f = np.abs(G - R).max() / np.abs(R).max()
+    err_E = np.abs(E - Eref).max() / np.abs(Eref).max()
+    print("bf16-contraction error: f %.2e, E %.2e" % (err_f, err_E))
+    assert 1e-6 < err_f <= 3e-2 and np.isfinite(err_E) and err_E <= 10.0
+
+
 def test_chi128_step_matches_mps_oracle(B):
     """Bond cap 128 (truncated SVDs of up to 256 columns, on two
     workgroups): two-stream 2^8 x 2^8 interleaved, C5, D_F = 4, from a state

@@ -25,6 +25,7 @@ ORDER_INTERLEAVED = 1  # interleaved: x1, v1, x2, v2, ... (coarse->fine)
 
 PREC_FP64 = 0
 PREC_FP32_CONTRACT = 1
+PREC_BF16_CONTRACT = 2
 
 
 @dataclasses.dataclass
