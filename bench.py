@@ -319,7 +319,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the mixed-precision, batched and serving measurements")
+                    help="skip the mixed-precision, batched, serving and chi=128 measurements")
+    ap.add_argument("--chi128-only", action="store_true",
+                    help="only time FP64 steps of the chi=128 2^12 configuration (for profiling)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (calibrates "
                          "the FETCH_SIZE / WRITE_SIZE counters)")
@@ -345,6 +347,20 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     binding.lib()
+
+    if args.chi128_only:
+        w = wl.two_stream(L=12, chi=128, tol=0.0, level=5, df_max=4, dt_cfg=0.02)
+        st = start_state(binding, w, "fixed")
+        st.step(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st.step(args.steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        print(json.dumps({"workload": "two-stream 2^12 x 2^12, interleaved, chi=128, C5, tol=0, D_F=4",
+                          "steps": args.steps, "steps_per_s": args.steps / el,
+                          "ms_per_step": 1000.0 * el / args.steps}))
+        return
 
     w = make_workload(args.mode)
     p = w.problem

@@ -120,3 +120,25 @@ def test_device_bytes_within_workspace_bound(S, case):
         assert 0 < used <= bound
     finally:
         st.free()
+
+
+def test_serving_mix_with_bond_cap_128_requests(S):
+    """Requests at bond cap 128 (their SVDs of 129..256 columns run on four
+    workgroups that meet through global memory) served beside small ones:
+    every result bitwise the same as alone, bonds reaching 128."""
+    _say("serving mix with chi 128")
+    reqs = []
+    for i in range(6):
+        if i % 3 == 0:
+            w = wl.two_stream(L=8, chi=128, tol=0.0, level=5, df_max=4)
+            kind = "two-stream chi128"
+        else:
+            w = wl.landau_small(L=6, chi=16, tol=1e-10)
+            kind = "landau"
+        reqs.append(S.Request(i, w.problem, w.ax, w.bv, steps=4, arrival=0.01 * i, kind=kind))
+    alone = [S.run_alone(r) for r in reqs]
+    mixed = S.Server(budget_bytes=64 << 30, slots=6).run(reqs)
+    for a, m in zip(alone, mixed):
+        assert a.error is None and m.error is None, (a.error, m.error)
+        assert m.bonds == a.bonds and m.scalars == a.scalars
+    assert max(mixed[0].bonds) == 128
