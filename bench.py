@@ -398,12 +398,12 @@ def main():
         extras["mixed"] = mixed_precision(binding, w, cores_host, min(args.steps, 5),
                                           fp64_steps_per_s=value)
         print("[bench] mixed %s" % json.dumps(extras["mixed"]), file=sys.stderr, flush=True)
+        extras["chi128"] = chi128_run(binding, 3)
+        print("[bench] chi128 %s" % json.dumps(extras["chi128"]), file=sys.stderr, flush=True)
         extras["batched"] = batched(binding, 64, 3)
         print("[bench] batched %s" % json.dumps(extras["batched"]), file=sys.stderr, flush=True)
         extras["serving"] = serving_run(binding, 24, 20)
         print("[bench] serving %s" % json.dumps(extras["serving"]), file=sys.stderr, flush=True)
-        extras["chi128"] = chi128_run(binding, 2)
-        print("[bench] chi128 %s" % json.dumps(extras["chi128"]), file=sys.stderr, flush=True)
 
     out = {
         "metric": "time steps/s at Nx=Nv=2^10, chi=64",

@@ -647,11 +647,10 @@ DMps Engine::compress_chain(const std::vector<VSite>& ch_in, int cap, double tol
     if (f.ident) {
       X = US;  // (2 p_{j-2}) x D = p_{j-2} x (2D)
     } else {
-      // US is f.cols x D; pad to f.rows x D and apply Q
+      // US is f.cols x D: Y = Q [US; 0] (f.rows x D), the zero rows implied
       double* Y = work().alloc((size_t)f.rows * D);
-      copy2d(s, f.cols, D, 1.0, US, D, Y, D);
-      fill(s, Y + (long)f.cols * D, (long)(f.rows - f.cols) * D, 0.0);
-      qr_apply_q(s, work(), f.qf, Y, D, D);
+      qr_apply_q_view(s, work(), f.qf, CMatView{US, D, 1, 0}, f.cols,
+                      MatView{Y, D, 1, 0}, D);
       X = Y;
     }
     m = f.rows / 2;

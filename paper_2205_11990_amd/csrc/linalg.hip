@@ -544,7 +544,9 @@ int svd_truncate(hipStream_t s, Arena& ws, double* X, int m, int c, long ldx,
   g_stats.svd_calls++;
   MPSV_CHECK(m >= 1 && c >= 1, kEinval, "svd_truncate: empty matrix");
   ArenaScope sc(ws);
-  double* info = ws.alloc(8);
+  // the kernels write their info words straight into this stream's pinned
+  // host block (device-accessible), read after the stream synchronisation
+  double* info = pinned_info(s);
   double* sigbuf = ws.alloc((size_t)3 * std::max(m, c) + 8);
   const int k = std::min(m, c);
   // Preconditioning: Jacobi runs on the transpose of a triangular factor
@@ -636,13 +638,12 @@ int svd_truncate(hipStream_t s, Arena& ws, double* X, int m, int c, long ldx,
     prof_end(s, slot, kClsJacobi, 6.0 * mm * nn * nn + 20.0 * nn * nn * nn,
              8.0 * (2.0 * m * c + 2.0 * nn * nn));
   }
-  double* h = pinned_info(s);
-  MPSV_HIP(hipMemcpyAsync(h, info, 6 * sizeof(double), hipMemcpyDeviceToHost, s));
   MPSV_HIP(hipStreamSynchronize(s));
+  const volatile double* h = info;
   const int D = (int)h[0];
   if (discarded) *discarded = h[1];
   g_stats.jacobi_sweeps += (long)h[2];
-  if (onchip && k > kJacobiOneWgCols && h[5] != 0.0)
+  if (onchip && jacobi_split(k) > 0 && h[5] != 0.0)
     throw Error(kEdevice, "Jacobi SVD: the workgroups did not meet in time");
   if (h[3] == 0.0)
     throw Error(kEnumeric, "Jacobi SVD did not converge within " +
