@@ -426,11 +426,19 @@ void qr_factor(hipStream_t s, Arena& ws, double* A, int m, int n, long ld,
       k0 += jb;
       continue;
     }
-    // TSQR panel: chunks of at most 2048 rows, each factored on its own
-    // workgroup, their triangular factors stacked (chunk c at rows c*jb) and
-    // factored again; the panel's R lands in the panel's top rows
-    const int jb = std::min(qr_reg_panel_cols(2048), f.k - k0);
-    const int nch = (rows + 2047) / 2048;
+    // TSQR panel: row chunks, each factored on its own workgroup, their
+    // triangular factors stacked (chunk c at rows c*jb) and factored again;
+    // the panel's R lands in the panel's top rows.  Chunks of at most 512
+    // rows take 32-column panels (half the panels, and launches, of the
+    // 16-column panels that 2048-row chunks allow) while the stacked
+    // factors still fit one register panel (at most 16 chunks).
+    int chunk_max = 512, jb = 32;
+    if ((rows + chunk_max - 1) / chunk_max * jb > 512) {
+      chunk_max = 2048;
+      jb = qr_reg_panel_cols(2048);
+    }
+    jb = std::min(jb, f.k - k0);
+    const int nch = (rows + chunk_max - 1) / chunk_max;
     const int crows = (rows + nch - 1) / nch;
     const int last = rows - (nch - 1) * crows;
     pn.jb = jb;
