@@ -9,7 +9,12 @@ The same scheme the MPS method discretises, evaluated on the full grid:
   phi = L^+ n (pseudo-inverse; the constant background drops out because
   L^+ 1 = 0) and E = -Dx phi with the same periodic central difference.
 * Periodic second-order central difference in x (SI, "First Derivative,
-  Centered, Periodic Boundary Conditions").
+  Centered, Periodic Boundary Conditions"), or the upwind alternative (SI,
+  "Upwind time evolution"): the second-order backward difference where
+  v > 0 and the forward one where v < 0 (SI, "First Derivative, Forward /
+  Backward, Periodic Boundary Conditions").  Reading: the paper's sentence
+  (backward for positive velocities) is followed; its displayed formula
+  pairs forward with H(v), which would be the downwind choice.
 * Central difference in v with zero-gradient boundaries by a mirrored ghost
   point, which makes the derivative vanish at the first and last node (SI,
   "First Derivative, Centered, Zero Gradient Boundary Conditions").
@@ -70,6 +75,26 @@ def ddx(F: np.ndarray, dx: float) -> np.ndarray:
     return (np.roll(F, -1, axis=0) - np.roll(F, 1, axis=0)) / (2.0 * dx)
 
 
+def ddx_backward(F: np.ndarray, dx: float) -> np.ndarray:
+    """(3 F_i - 4 F_{i-1} + F_{i-2}) / (2 dx), i periodic."""
+    return (3.0 * F - 4.0 * np.roll(F, 1, axis=0) + np.roll(F, 2, axis=0)) / (2.0 * dx)
+
+
+def ddx_forward(F: np.ndarray, dx: float) -> np.ndarray:
+    """(-3 F_i + 4 F_{i+1} - F_{i+2}) / (2 dx), i periodic."""
+    return (-3.0 * F + 4.0 * np.roll(F, -1, axis=0) - np.roll(F, -2, axis=0)) / (2.0 * dx)
+
+
+def advection(F: np.ndarray, p) -> np.ndarray:
+    """v df/dx on the grid: central, or upwind (backward where v > 0,
+    forward where v < 0; v = 0 contributes nothing either way)."""
+    v = p.v()
+    if getattr(p, "x_scheme", 0) == 1:
+        return (np.maximum(v, 0.0)[None, :] * ddx_backward(F, p.dx)
+                + np.minimum(v, 0.0)[None, :] * ddx_forward(F, p.dx))
+    return v[None, :] * ddx(F, p.dx)
+
+
 def ddv(F: np.ndarray, dv: float) -> np.ndarray:
     """(F_{i,j+1} - F_{i,j-1}) / (2 dv) inside, 0 at j = 0 and j = Nv-1."""
     out = np.zeros_like(F)
@@ -84,8 +109,7 @@ def field(F: np.ndarray, p) -> np.ndarray:
 def rhs(F: np.ndarray, p) -> np.ndarray:
     """R(F) = -v Dx F - (q/m) E Dv F  (eq. 1, C = 0)."""
     E = field(F, p)
-    v = p.v()
-    return -v[None, :] * ddx(F, p.dx) - p.qm * E[:, None] * ddv(F, p.dv)
+    return -advection(F, p) - p.qm * E[:, None] * ddv(F, p.dv)
 
 
 def rk4_step(F: np.ndarray, p, dt: float | None = None) -> np.ndarray:

@@ -13,6 +13,14 @@ Sections of the paper followed here:
 * SI "Derivatives": the printed MPOs for the periodic central first
   derivative, the non-periodic backbone plus boundary matrices, and the
   periodic second derivative.
+* SI "Derivatives", forward and backward periodic first derivatives: the
+  printed forward MPO is garbled (its c3 is never defined), so both are
+  rebuilt from their stencils (the coefficients the paper prints) through
+  the dense matrix and TT-SVD, the SI's matrix -> MPO route.
+* SI "Upwind time evolution": backward difference where v > 0, forward
+  where v < 0 (the paper's sentence; its displayed formula pairs the labels
+  the other way round), i.e. T1 = -(Db (x) diag(max(v,0)) +
+  Df (x) diag(min(v,0))), the velocity split being H(v) times v.
 * SI "Dot Product": MPS -> diagonal MPO, M(o, i) = M(i) delta_{io}.
 * SI "Inverse Laplacian": dense inverse converted into an MPO.
 * SI "Integration": dx [1, 1]^{(x) L}.
@@ -324,6 +332,33 @@ def mpo_from_matrix(M: np.ndarray, L: int, tol: float = 1e-14) -> Mpo:
     return [c.reshape(c.shape[0], 2, 2, c.shape[2]) for c in cores]
 
 
+def mpo_stencil_periodic(L: int, h: float, coeffs: dict) -> Mpo:
+    """Circulant stencil (Af)_o = sum_d coeffs[d] f_{(o+d) mod N} / h as an
+    MPO: the dense matrix converted by TT-SVD (SI, "Inverse Laplacian"
+    route; small L only)."""
+    N = 1 << L
+    M = np.zeros((N, N))
+    for d, c in coeffs.items():
+        for o in range(N):
+            M[o, (o + d) % N] += c / h
+    return mpo_from_matrix(M, L)
+
+
+# second-order one-sided periodic first derivatives (SI, Derivatives:
+# forward c0 = -3/2, c1 = 2, c2 = -1/2 on f_i, f_{i+1}, f_{i+2}; backward
+# c0 = 3/2, c1 = -2, c2 = 1/2 on f_i, f_{i-1}, f_{i-2})
+D1_FORWARD = {0: -1.5, 1: 2.0, 2: -0.5}
+D1_BACKWARD = {0: 1.5, -1: -2.0, -2: 0.5}
+
+
+def mpo_d1_forward(L: int, h: float) -> Mpo:
+    return mpo_stencil_periodic(L, h, D1_FORWARD)
+
+
+def mpo_d1_backward(L: int, h: float) -> Mpo:
+    return mpo_stencil_periodic(L, h, D1_BACKWARD)
+
+
 def mpo_to_matrix(W: Mpo) -> np.ndarray:
     """Contract an MPO to its dense N x N matrix (brute force, tests)."""
     L = len(W)
@@ -521,8 +556,16 @@ class Operators:
         self.Dv = mpo_d1_zero_gradient(p.Lv, p.dv)
         self.V = diag_mpo(vector_mps(p.v()))
         self.G = poisson_mpo(p.Lx, p.dx)
-        # T1 = -(Dx (x) V) f
-        self.T1 = chain_mpo(self.Dx, self.V, p.Lx, p.Lv, p.order)
+        if getattr(p, "x_scheme", 0) == 1:
+            # upwind: T1 = -(Db (x) diag(v H(v)) + Df (x) diag(v (1 - H(v))))
+            v = p.v()
+            Wp = diag_mpo(vector_mps(np.maximum(v, 0.0)))
+            Wn = diag_mpo(vector_mps(np.minimum(v, 0.0)))
+            self.T1 = mpo_sum([chain_mpo(mpo_d1_backward(p.Lx, p.dx), Wp, p.Lx, p.Lv, p.order),
+                               chain_mpo(mpo_d1_forward(p.Lx, p.dx), Wn, p.Lx, p.Lv, p.order)])
+        else:
+            # T1 = -(Dx (x) V) f
+            self.T1 = chain_mpo(self.Dx, self.V, p.Lx, p.Lv, p.order)
         self.T1[0] = -self.T1[0]
 
 

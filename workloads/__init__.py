@@ -45,6 +45,7 @@ class Problem:
     df_max: int = 0         # cap on the field bond, 0 = uncapped
     tol: float = 1e-10      # per-bond relative discarded weight
     precision: int = PREC_FP64
+    x_scheme: int = 0       # x advection: 0 central, 1 upwind (second order)
 
     @property
     def Nx(self) -> int:
