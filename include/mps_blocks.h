@@ -77,8 +77,11 @@ mps_status mpsb_density_field(mps_state* h, double* n_out, double* E_out,
 
 /* Operator MPOs exactly as the library builds them, for the tests:
  * which = 0: periodic central d/dx (bond 3), 1: zero-gradient central d/dv
- * (bond 5), 2: G = Dx L^+ (bond 5), 3: diag(v) (bond 2).  L sites, spacing
- * h (for which = 3: v_min = h0, dv = h).  bonds: host int32[L+1]; W: host
+ * (bond 5), 2: G = Dx L^+ (bond 5), 3: diag(v) (bond 2), 4: periodic
+ * second-order backward d/dx and 5: forward d/dx (bond 3, SI Derivatives),
+ * 6: diag(max(v, 0)) and 7: diag(min(v, 0)) (v times H(v) and 1 - H(v), SI
+ * Upwind time evolution; bond <= 4).  L sites, spacing h (for which = 3, 6,
+ * 7: v_j = h0 + j h).  bonds: host int32[L+1]; W: host
  * array of capacity doubles (packed W[bl][o][i][br]) or NULL to query
  * *count. */
 mps_status mpsb_operator(int32_t which, int32_t L, double h0, double h,

@@ -75,6 +75,14 @@ typedef enum {
   MPS_PREC_BF16_CONTRACT = 2
 } mps_precision;
 
+/* x advection (SI, "Upwind time evolution"): the periodic second-order
+ * central difference, or upwind: the second-order backward difference where
+ * v > 0 and the forward one where v < 0 (SI, "First Derivative, Forward /
+ * Backward, Periodic Boundary Conditions"), i.e. T1 = -(Db (x) diag(v H(v))
+ * + Df (x) diag(v (1 - H(v)))).  The paper's sentence is followed where its
+ * displayed formula pairs forward with H(v). */
+typedef enum { MPS_X_CENTRAL = 0, MPS_X_UPWIND = 1 } mps_x_scheme;
+
 /* Problem statement.  Site orderings (Fig. 3): MPS_ORDER_SEQ is x bits
  * coarse->fine then v bits coarse->fine (S1); MPS_ORDER_INTERLEAVED is
  * x1, v1, x2, v2, ... (IF; needs Lx == Lv).  Compression level (SI,
@@ -93,6 +101,7 @@ typedef struct mps_problem {
   int32_t df_max;           /* cap on the field bond D_F, 0 = uncapped     */
   double tol;               /* relative discarded weight per bond, >= 0    */
   int32_t precision;        /* mps_precision                               */
+  int32_t x_scheme;         /* mps_x_scheme                                */
 } mps_problem;
 
 typedef struct mps_state mps_state; /* opaque; owns all device memory */

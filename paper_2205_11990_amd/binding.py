@@ -36,7 +36,7 @@ class CProblem(ctypes.Structure):
         ("qm", ctypes.c_double), ("dt", ctypes.c_double),
         ("chi_max", ctypes.c_int32), ("level", ctypes.c_int32),
         ("df_max", ctypes.c_int32), ("tol", ctypes.c_double),
-        ("precision", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("x_scheme", ctypes.c_int32),
     ]
 
 
@@ -142,6 +142,7 @@ def make_problem(p) -> CProblem:
     c.chi_max = int(p.chi_max) if p.chi_max else 0
     c.level, c.df_max = int(p.level), int(p.df_max)
     c.tol, c.precision = float(p.tol), int(getattr(p, "precision", 0))
+    c.x_scheme = int(getattr(p, "x_scheme", 0))
     return c
 
 

@@ -76,6 +76,7 @@ mpsv::Problem convert(const mps_problem* p) {
   q.df_max = p->df_max;
   q.tol = p->tol;
   q.precision = p->precision;
+  q.x_scheme = p->x_scheme;
   MPSV_CHECK(std::isfinite(q.x_min) && std::isfinite(q.x_max) &&
                  std::isfinite(q.v_min) && std::isfinite(q.v_max),
              mpsv::kEinval, "grid bounds must be finite");
@@ -489,6 +490,10 @@ mps_status mpsb_operator(int32_t which, int32_t L, double h0, double h,
       case 1: M = mpsv::ops::d1_zero_gradient(L, h, b); break;
       case 2: M = mpsv::ops::poisson_g(L, h, 1.0, b); break;
       case 3: M = mpsv::ops::poly_diag(L, h0, h, 0.0, b); break;
+      case 4: M = mpsv::ops::d1_one_sided(L, h, false, b); break;
+      case 5: M = mpsv::ops::d1_one_sided(L, h, true, b); break;
+      case 6: M = mpsv::ops::velocity_part_diag(L, h0, h, true, b); break;
+      case 7: M = mpsv::ops::velocity_part_diag(L, h0, h, false, b); break;
       default: throw mpsv::Error(mpsv::kEinval, "unknown operator");
     }
     long tot = 0;

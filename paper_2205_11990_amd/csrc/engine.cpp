@@ -162,6 +162,47 @@ HostMpo poisson_g(int L, double dx, double scale, std::vector<int>& bonds) {
   return W;
 }
 
+HostMpo d1_one_sided(int L, double h, bool forward, std::vector<int>& bonds) {
+  // (A f)_o = sum_d c_d f_{(o+d) mod N} / h.  Reading the sites from the
+  // least significant bit up, the lower bits must reproduce d up to a carry
+  // q in {-1, 0, 1}: the last site turns (i - o) into q = (i - o - d) / 2,
+  // every other site q_left = (i - o + q_right) / 2; the first site accepts
+  // any final carry (periodic wrap).  Bond 3 (state q + 1).
+  if (L < 2) throw Error(kEinval, "derivative MPO needs L >= 2");
+  const int d[3] = {0, forward ? 1 : -1, forward ? 2 : -2};
+  const double c[3] = {forward ? -1.5 : 1.5, forward ? 2.0 : -2.0,
+                       forward ? -0.5 : 0.5};
+  HostMpo W(L);
+  for (int k = 0; k < L; ++k) {
+    const int bl = (k == 0) ? 1 : 3, br = (k == L - 1) ? 1 : 3;
+    W[k].assign((size_t)bl * 4 * br, 0.0);
+    for (int o = 0; o < 2; ++o)
+      for (int i = 0; i < 2; ++i) {
+        if (k == L - 1) {
+          for (int t = 0; t < 3; ++t) {
+            const int num = i - o - d[t];
+            if (num % 2 != 0) continue;
+            const int q = num / 2;
+            if (q < -1 || q > 1) continue;
+            W[k][widx(br, L == 1 ? 0 : q + 1, o, i, 0)] += c[t];
+          }
+        } else {
+          for (int qr = -1; qr <= 1; ++qr) {
+            const int num = i - o + qr;
+            if (num % 2 != 0) continue;
+            const int ql = num / 2;
+            if (k == 0) W[k][widx(br, 0, o, i, qr + 1)] += 1.0;
+            else if (ql >= -1 && ql <= 1) W[k][widx(br, ql + 1, o, i, qr + 1)] += 1.0;
+          }
+        }
+      }
+  }
+  for (auto& x : W[0]) x /= h;
+  bonds.assign(L + 1, 3);
+  bonds[0] = bonds[L] = 1;
+  return W;
+}
+
 std::vector<std::vector<double>> poly_mps(int L, double c0, double c1,
                                           double c2, std::vector<int>& bonds) {
   // f(J) = c0 + c1 J + c2 J^2, J = sum_k s_k 2^(L-1-k): carry [1, J, J^2]
@@ -218,6 +259,125 @@ HostMpo poly_diag(int L, double c0, double c1, double c2,
       for (int s = 0; s < 2; ++s)
         for (int b = 0; b < br; ++b)
           W[k][widx(br, a, s, s, b)] = A[k][((size_t)a * 2 + s) * br + b];
+  }
+  return W;
+}
+
+namespace {
+
+// MPS of the indicator of j >= t (ge) or j < t (!ge) over the L bits of j,
+// most significant first, 0 < t < 2^L: a comparison with t's bits, states
+// "equal so far" and "decided" (bond 2).
+std::vector<std::vector<double>> compare_mps(int L, long t, bool ge) {
+  std::vector<std::vector<double>> A(L);
+  auto bit = [&](int k) { return (int)((t >> (L - 1 - k)) & 1); };
+  for (int k = 0; k < L; ++k) {
+    const int bl = (k == 0) ? 1 : 2, br = (k == L - 1) ? 1 : 2;
+    A[k].assign((size_t)bl * 2 * br, 0.0);
+    const int b = bit(k);
+    for (int s = 0; s < 2; ++s) {
+      const bool decide = ge ? (s > b) : (s < b);
+      auto at = [&](int a, int c) -> double& { return A[k][((size_t)a * 2 + s) * br + c]; };
+      if (k == L - 1) {
+        at(0, 0) = (decide || (ge && s == b)) ? 1.0 : 0.0;
+        if (bl == 2) at(1, 0) = 1.0;
+      } else {
+        at(0, 0) = (s == b) ? 1.0 : 0.0;
+        at(0, 1) = decide ? 1.0 : 0.0;
+        if (bl == 2) at(1, 1) = 1.0;
+      }
+    }
+  }
+  return A;
+}
+
+// Elementwise product of two MPS (bonds multiply).
+std::vector<std::vector<double>> hadamard(
+    const std::vector<std::vector<double>>& A, const std::vector<int>& ba,
+    const std::vector<std::vector<double>>& B, const std::vector<int>& bb,
+    std::vector<int>& bonds) {
+  const int L = (int)A.size();
+  std::vector<std::vector<double>> C(L);
+  bonds.assign(L + 1, 1);
+  for (int k = 0; k <= L; ++k) bonds[k] = ba[k] * bb[k];
+  for (int k = 0; k < L; ++k) {
+    const int al = ba[k], ar = ba[k + 1], cl = bb[k], cr = bb[k + 1];
+    C[k].assign((size_t)al * cl * 2 * ar * cr, 0.0);
+    for (int a = 0; a < al; ++a)
+      for (int c = 0; c < cl; ++c)
+        for (int s = 0; s < 2; ++s)
+          for (int b = 0; b < ar; ++b)
+            for (int e = 0; e < cr; ++e)
+              C[k][(((size_t)(a * cl + c) * 2 + s) * ar + b) * cr + e] =
+                  A[k][((size_t)a * 2 + s) * ar + b] * B[k][((size_t)c * 2 + s) * cr + e];
+  }
+  return C;
+}
+
+}  // namespace
+
+HostMpo velocity_part_diag(int L, double v0, double dv, bool positive,
+                           std::vector<int>& bonds) {
+  // max(v_j, 0) = v_j [j >= j0], min(v_j, 0) = v_j [j < j1]
+  const long N = 1L << L;
+  auto v = [&](long j) { return v0 + (double)j * dv; };
+  long t = 0;
+  if (positive) {
+    while (t < N && v(t) <= 0.0) ++t;  // first j with v_j > 0
+  } else {
+    while (t < N && v(t) < 0.0) ++t;   // first j with v_j >= 0
+  }
+  const bool empty = positive ? (t >= N) : (t == 0);
+  const bool full = positive ? (t == 0) : (t >= N);
+  std::vector<int> bp;
+  auto P = poly_mps(L, v0, dv, 0.0, bp);
+  std::vector<std::vector<double>> A;
+  if (empty) {
+    bonds.assign(L + 1, 1);
+    A.assign(L, std::vector<double>(2, 0.0));
+  } else if (full) {
+    A = P;
+    bonds = bp;
+  } else {
+    std::vector<int> bc(L + 1, 2);
+    bc[0] = bc[L] = 1;
+    A = hadamard(P, bp, compare_mps(L, t, positive), bc, bonds);
+  }
+  HostMpo W(L);
+  for (int k = 0; k < L; ++k) {
+    const int bl = bonds[k], br = bonds[k + 1];
+    W[k].assign((size_t)bl * 4 * br, 0.0);
+    for (int a = 0; a < bl; ++a)
+      for (int s = 0; s < 2; ++s)
+        for (int b = 0; b < br; ++b)
+          W[k][widx(br, a, s, s, b)] = A[k][((size_t)a * 2 + s) * br + b];
+  }
+  return W;
+}
+
+HostMpo mpo_add(const HostMpo& A, const std::vector<int>& ba, const HostMpo& B,
+                const std::vector<int>& bb, std::vector<int>& bonds) {
+  const int L = (int)A.size();
+  if (L < 2 || (int)B.size() != L) throw Error(kEinval, "mpo_add: bad lengths");
+  bonds.assign(L + 1, 1);
+  for (int k = 1; k < L; ++k) bonds[k] = ba[k] + bb[k];
+  HostMpo W(L);
+  for (int k = 0; k < L; ++k) {
+    const int bl = bonds[k], br = bonds[k + 1];
+    W[k].assign((size_t)bl * 4 * br, 0.0);
+    // block offsets of A and B in the left / right bonds
+    const int al = ba[k], ar = ba[k + 1], cl = bb[k], cr = bb[k + 1];
+    const int offBl = (k == 0) ? 0 : al, offBr = (k == L - 1) ? 0 : ar;
+    for (int a = 0; a < al; ++a)
+      for (int o = 0; o < 2; ++o)
+        for (int i = 0; i < 2; ++i)
+          for (int b = 0; b < ar; ++b)
+            W[k][widx(br, a, o, i, b)] += A[k][widx(ar, a, o, i, b)];
+    for (int a = 0; a < cl; ++a)
+      for (int o = 0; o < 2; ++o)
+        for (int i = 0; i < 2; ++i)
+          for (int b = 0; b < cr; ++b)
+            W[k][widx(br, offBl + a, o, i, offBr + b)] += B[k][widx(cr, a, o, i, b)];
   }
   return W;
 }
@@ -296,7 +456,9 @@ MemoryModel memory_model(const Problem& q) {
   // field bond: the cap D_F, at most the full rank of an Lx-site MPS
   const double df = std::min(q.df_max > 0 ? (double)q.df_max : chi,
                              std::ldexp(1.0, q.Lx / 2));
-  const double w = (q.order == 1 ? 5.0 : 3.0) * df;  // field-term MPO bond
+  // widest MPO: the field term, or the upwind advection term
+  const double w = std::max((q.order == 1 ? 5.0 : 3.0) * df,
+                            q.x_scheme == 1 ? (q.order == 1 ? 24.0 : 8.0) : 0.0);
   double S = 0, N = 0, I = 0;
   for (int j = 0; j < n; ++j) {
     const double bl = std::min(chi, full(j)), br = std::min(chi, full(j + 1));
@@ -356,6 +518,8 @@ Engine::Engine(const Problem& p) : p_(p), chunk_(memory_model(p).chunk) {
   MPSV_CHECK(std::isfinite(p.tol) && p.tol >= 0, kEinval, "tol must be >= 0");
   MPSV_CHECK(p.precision >= 0 && p.precision <= 2, kEinval,
              "unknown precision mode");
+  MPSV_CHECK(p.x_scheme == 0 || p.x_scheme == 1, kEinval,
+             "unknown x advection scheme");
   MPSV_CHECK(std::isfinite(p.qm), kEinval, "q/m must be finite");
 
   MPSV_HIP(hipGetDevice(&device_));
@@ -366,10 +530,23 @@ Engine::Engine(const Problem& p) : p_(p), chunk_(memory_model(p).chunk) {
 
   hipStream_t s = nullptr;
   std::vector<int> bdx, bvv, bt1, bg, bdv;
-  auto Dx = ops::d1_periodic(p.Lx, p.dx(), bdx);
-  auto V = ops::poly_diag(p.Lv, p.v_min, p.dv(), 0.0, bvv);
-  auto T1 = ops::chain(Dx, bdx, V, bvv, p.order, bt1);
-  for (auto& x : T1[0]) x = -x;  // T1 = -(Dx (x) V) f
+  ops::HostMpo T1;
+  if (p.x_scheme == 1) {
+    // upwind: T1 = -(Db (x) diag(max(v,0)) + Df (x) diag(min(v,0))) f
+    std::vector<int> bdb, bdf, bvp, bvn, btp, btn;
+    auto Db = ops::d1_one_sided(p.Lx, p.dx(), false, bdb);
+    auto Df = ops::d1_one_sided(p.Lx, p.dx(), true, bdf);
+    auto Vp = ops::velocity_part_diag(p.Lv, p.v_min, p.dv(), true, bvp);
+    auto Vn = ops::velocity_part_diag(p.Lv, p.v_min, p.dv(), false, bvn);
+    auto Tp = ops::chain(Db, bdb, Vp, bvp, p.order, btp);
+    auto Tn = ops::chain(Df, bdf, Vn, bvn, p.order, btn);
+    T1 = ops::mpo_add(Tp, btp, Tn, btn, bt1);
+  } else {
+    auto Dx = ops::d1_periodic(p.Lx, p.dx(), bdx);
+    auto V = ops::poly_diag(p.Lv, p.v_min, p.dv(), 0.0, bvv);
+    T1 = ops::chain(Dx, bdx, V, bvv, p.order, bt1);
+  }
+  for (auto& x : T1[0]) x = -x;  // T1 = -(advection) f
   t1_ = upload_mpo(T1, bt1, ops_, s);
   auto G = ops::poisson_g(p.Lx, p.dx(), -1.0, bg);  // E = -G n
   gneg_ = upload_mpo(G, bg, ops_, s);

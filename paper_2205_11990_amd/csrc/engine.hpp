@@ -16,6 +16,7 @@ struct Problem {
   int chi_max = 16, level = 1, df_max = 0;
   double tol = 1e-10;
   int precision = 0;
+  int x_scheme = 0;  // 0 central, 1 upwind x advection
   int n() const { return Lx + Lv; }
   long Nx() const { return 1L << Lx; }
   long Nv() const { return 1L << Lv; }
@@ -177,6 +178,15 @@ using HostMpo = std::vector<std::vector<double>>;
 HostMpo d1_periodic(int L, double h, std::vector<int>& bonds);
 HostMpo d1_zero_gradient(int L, double h, std::vector<int>& bonds);
 HostMpo poisson_g(int L, double dx, double scale, std::vector<int>& bonds);
+// periodic second-order one-sided d/dx: forward (-3 f_i + 4 f_{i+1} -
+// f_{i+2}) / 2h or backward (3 f_i - 4 f_{i-1} + f_{i-2}) / 2h, bond 3
+HostMpo d1_one_sided(int L, double h, bool forward, std::vector<int>& bonds);
+// diag(max(v_j, 0)) (positive) or diag(min(v_j, 0)), v_j = v0 + j dv
+HostMpo velocity_part_diag(int L, double v0, double dv, bool positive,
+                           std::vector<int>& bonds);
+// direct sum of two MPOs of the same length (their operators add)
+HostMpo mpo_add(const HostMpo& A, const std::vector<int>& ba, const HostMpo& B,
+                const std::vector<int>& bb, std::vector<int>& bonds);
 // diag of c0 + c1 J + c2 J^2 with J the integer index (MSB first); J -> v
 HostMpo poly_diag(int L, double c0, double c1, double c2, std::vector<int>& bonds);
 // the matching MPS (values instead of a diagonal operator)

@@ -72,6 +72,29 @@ def test_library_operators_decode_to_stencils(L):
     assert np.abs(G - _dense(mps.poisson_mpo(L, h))).max() < 1e-13
 
 
+@pytest.mark.parametrize("L", [2, 3, 5, 7])
+def test_library_upwind_operators_match_the_oracle(L):
+    """The library's one-sided derivatives (exact carry automata, bond 3)
+    equal the oracle's (printed stencils through TT-SVD), and its velocity
+    split diag(max(v,0)), diag(min(v,0)) equals the grid values, for grids
+    symmetric about 0 and not."""
+    from paper_2205_11990_amd import binding
+    from oracle import mps
+    N = 2 ** L
+    h = 0.37
+    Db = _dense(binding.operator(4, L, 0.0, h))
+    Df = _dense(binding.operator(5, L, 0.0, h))
+    assert np.abs(Db - _dense(mps.mpo_d1_backward(L, h))).max() < 1e-12 / h
+    assert np.abs(Df - _dense(mps.mpo_d1_forward(L, h))).max() < 1e-12 / h
+    assert max(w.shape[3] for w in binding.operator(4, L, 0.0, h)) <= 3
+    for v0, dv in ((-1.0, 2.0 / (N - 1)), (-0.3, 0.21), (0.5, 0.1), (-9.0, 0.1)):
+        v = v0 + dv * np.arange(N)
+        P = _dense(binding.operator(6, L, v0, dv))
+        M = _dense(binding.operator(7, L, v0, dv))
+        assert np.abs(P - np.diag(np.maximum(v, 0.0))).max() < 1e-12 * max(1.0, np.abs(v).max())
+        assert np.abs(M - np.diag(np.minimum(v, 0.0))).max() < 1e-12 * max(1.0, np.abs(v).max())
+
+
 def test_library_operator_bonds():
     from paper_2205_11990_amd import binding
     assert [w.shape[3] for w in binding.operator(0, 6, 0, 1.0)[:-1]] == [3] * 5

@@ -301,3 +301,51 @@ def test_chi128_step_matches_mps_oracle(B):
     assert np.abs(E.cpu().numpy() - Eref).max() <= 1e-8 * np.abs(Eref).max()
     assert st.info()["bonds"][1:-1] == omps.bond_dims(f)
     st.free()
+
+
+@pytest.mark.parametrize("order,L", [(0, 3), (1, 3), (0, 4), (1, 4), (0, 5)])
+def test_untruncated_upwind_steps_equal_dense_oracle(B, order, L):
+    """Upwind x advection (backward difference where v > 0, forward where
+    v < 0), chi unbounded, tol = 0: the MPS step is the dense upwind step up
+    to rounding."""
+    _say("untruncated upwind order=%d L=%d" % (order, L))
+    w = _untruncated(wl.landau_small(L=L))
+    p = w.problem
+    p.order = order
+    p.x_scheme = 1
+    st = B.MpsState(p, w.ax, w.bv)
+    F = odense.initial(w.ax, w.bv)
+    for k in range(4):
+        st.step(1)
+        F = odense.rk4_step(F, p)
+        G = st.to_dense().cpu().numpy()
+        err = np.abs(G - F).max() / np.abs(F).max()
+        assert err < 1e-12 * (k + 2), (k, err)
+    st.free()
+
+
+@pytest.mark.parametrize("order", [0, 1])
+def test_truncated_upwind_matches_mps_oracle(B, order):
+    """Upwind x advection with every compression capped (C5, chi = 8,
+    perturbed state): f and E within 1e-8 of the CPU MPS oracle (whose
+    one-sided MPOs come from TT-SVD of the stencils) after 2 steps."""
+    _say("truncated upwind C5 chi8 two-stream L=5 order=%d" % order)
+    w = wl.two_stream(L=5, chi=8, tol=0.0, level=5, df_max=4, dt_cfg=0.05, order=order)
+    p = w.problem
+    p.x_scheme = 1
+    st = B.MpsState(p, w.ax, w.bv)
+    pert = wl.random_mps_cores(p.n_sites, 8, seed=2205)
+    st.add_scaled(1e-3, pert)
+    f = st.get_cores_host()
+    ops = omps.Operators(p)
+    for _ in range(2):
+        st.step(1)
+        f = omps.rk4_step(f, ops)
+    G = st.to_dense().cpu().numpy()
+    R = omps.to_dense(f, p)
+    _, E = st.density_field()
+    Eref = omps.field_dense(f, ops)
+    assert np.abs(G - R).max() <= 1e-8 * np.abs(R).max()
+    assert np.abs(E.cpu().numpy() - Eref).max() <= 1e-8 * np.abs(Eref).max()
+    assert st.info()["bonds"][1:-1] == omps.bond_dims(f)
+    st.free()
