@@ -19,7 +19,11 @@ The same scheme the MPS method discretises, evaluated on the full grid:
   point, which makes the derivative vanish at the first and last node (SI,
   "First Derivative, Centered, Zero Gradient Boundary Conditions").
 * Left Riemann sum for integrals (SI, "Integration").
-* Classic RK4 with a fixed step (SI, "Compressed time evolution algorithm").
+* Classic RK4 with a fixed step (SI, "Compressed time evolution algorithm"),
+  or an adaptive one (Methods, "Time Evolution Procedure", eq. CFL): a
+  fraction cfl of dt_max = (|v|_max / dx + |q/m| |E|_max / dv)^-1 for one
+  collisionless species, |E|_max measured on the state at the start of the
+  step.
 
 TEST INFRASTRUCTURE ONLY -- see ``oracle/__init__``.
 """
@@ -112,9 +116,23 @@ def rhs(F: np.ndarray, p) -> np.ndarray:
     return -advection(F, p) - p.qm * E[:, None] * ddv(F, p.dv)
 
 
+def cfl_dt(F: np.ndarray, p) -> float:
+    """cfl * (|v|_max / dx + |q/m| |E|_max / dv)^-1 (eq. CFL, one species,
+    no collisions)."""
+    vmax = max(abs(p.v_min), abs(p.v_max))
+    emax = float(np.abs(field(F, p)).max())
+    return p.cfl / (vmax / p.dx + abs(p.qm) * emax / p.dv)
+
+
 def rk4_step(F: np.ndarray, p, dt: float | None = None) -> np.ndarray:
-    """f_{n+1} = f_n + dt/6 (k1 + 2 k2 + 2 k3 + k4)  (SI, RK4)."""
-    h = p.dt if dt is None else dt
+    """f_{n+1} = f_n + dt/6 (k1 + 2 k2 + 2 k3 + k4)  (SI, RK4); dt is the
+    fixed p.dt, or the adaptive CFL step when p.cfl > 0."""
+    if dt is not None:
+        h = dt
+    elif getattr(p, "cfl", 0.0) > 0.0:
+        h = cfl_dt(F, p)
+    else:
+        h = p.dt
     k1 = rhs(F, p)
     k2 = rhs(F + 0.5 * h * k1, p)
     k3 = rhs(F + 0.5 * h * k2, p)

@@ -595,10 +595,20 @@ def rhs_mps(g: Mps, ops: Operators) -> Mps:
     return compress(add([(1.0, T1), (1.0, T2)]), caps(p, 4), p.tol)
 
 
-def rk4_step(f: Mps, ops: Operators) -> Mps:
-    """SI, Compressed time evolution: RK4 with compression points P1-P5."""
+def cfl_dt(f: Mps, ops: Operators) -> float:
+    """Adaptive step (Methods, eq. CFL, one collisionless species): cfl *
+    (|v|_max / dx + |q/m| |E|_max / dv)^-1, |E|_max of the field of f."""
     p = ops.p
-    h = p.dt
+    vmax = max(abs(p.v_min), abs(p.v_max))
+    emax = float(np.abs(field_dense(f, ops)).max())
+    return p.cfl / (vmax / p.dx + abs(p.qm) * emax / p.dv)
+
+
+def rk4_step(f: Mps, ops: Operators) -> Mps:
+    """SI, Compressed time evolution: RK4 with compression points P1-P5; the
+    fixed dt, or the adaptive CFL step when p.cfl > 0."""
+    p = ops.p
+    h = cfl_dt(f, ops) if getattr(p, "cfl", 0.0) > 0.0 else p.dt
     k1 = rhs_mps(f, ops)
     f2 = compress(add([(1.0, f), (0.5 * h, k1)]), caps(p, 2), p.tol)
     k2 = rhs_mps(f2, ops)

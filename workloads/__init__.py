@@ -46,6 +46,7 @@ class Problem:
     tol: float = 1e-10      # per-bond relative discarded weight
     precision: int = PREC_FP64
     x_scheme: int = 0       # x advection: 0 central, 1 upwind (second order)
+    cfl: float = 0.0        # > 0: adaptive dt, this fraction of the CFL limit
 
     @property
     def Nx(self) -> int:
