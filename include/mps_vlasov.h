@@ -89,19 +89,27 @@ typedef enum { MPS_X_CENTRAL = 0, MPS_X_UPWIND = 1 } mps_x_scheme;
  * compression levels C1..C5): the final state (P1), the stage states (P2),
  * the sum of the k's (P3), each k (P4) and each term of a k (P5) are all
  * truncated with `tol`; level l additionally caps P1..Pl at chi_max. */
+/* Adaptive time step (Methods, Time Evolution Procedure, eq. CFL), for one
+ * collisionless species: when cfl > 0 every step takes
+ * dt = cfl / (|v|_max / dx + |q/m| |E|_max / dv), |E|_max on the grid of the
+ * state at the start of the step (the paper uses cfl = 0.9; with the upwind
+ * scheme RK4 needs cfl < 0.696, its negative-real-axis limit over the
+ * stencil's extreme eigenvalue -4 v / dx).  dt is then not used; the
+ * elapsed time is reported by mps_info. */
 typedef struct mps_problem {
   int32_t Lx, Lv;           /* bits per dimension, each in [2, 14]        */
   int32_t order;            /* mps_order                                   */
   double x_min, x_max;      /* periodic interval, x_max > x_min            */
   double v_min, v_max;      /* closed interval, v_max > v_min              */
   double qm;                /* charge / mass of the species (-1: electrons)*/
-  double dt;                /* fixed RK4 step, > 0                         */
+  double dt;                /* fixed RK4 step, > 0 (unless cfl > 0)        */
   int32_t chi_max;          /* bond cap (paper D), >= 1                    */
   int32_t level;            /* compression level 1..5 (1 = C1)             */
   int32_t df_max;           /* cap on the field bond D_F, 0 = uncapped     */
   double tol;               /* relative discarded weight per bond, >= 0    */
   int32_t precision;        /* mps_precision                               */
   int32_t x_scheme;         /* mps_x_scheme                                */
+  double cfl;               /* > 0: adaptive dt (see below), 0: fixed dt   */
 } mps_problem;
 
 typedef struct mps_state mps_state; /* opaque; owns all device memory */

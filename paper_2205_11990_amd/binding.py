@@ -37,6 +37,7 @@ class CProblem(ctypes.Structure):
         ("chi_max", ctypes.c_int32), ("level", ctypes.c_int32),
         ("df_max", ctypes.c_int32), ("tol", ctypes.c_double),
         ("precision", ctypes.c_int32), ("x_scheme", ctypes.c_int32),
+        ("cfl", ctypes.c_double),
     ]
 
 
@@ -143,6 +144,7 @@ def make_problem(p) -> CProblem:
     c.level, c.df_max = int(p.level), int(p.df_max)
     c.tol, c.precision = float(p.tol), int(getattr(p, "precision", 0))
     c.x_scheme = int(getattr(p, "x_scheme", 0))
+    c.cfl = float(getattr(p, "cfl", 0.0))
     return c
 
 

@@ -77,6 +77,7 @@ mpsv::Problem convert(const mps_problem* p) {
   q.tol = p->tol;
   q.precision = p->precision;
   q.x_scheme = p->x_scheme;
+  q.cfl = p->cfl;
   MPSV_CHECK(std::isfinite(q.x_min) && std::isfinite(q.x_max) &&
                  std::isfinite(q.v_min) && std::isfinite(q.v_max),
              mpsv::kEinval, "grid bounds must be finite");

@@ -511,7 +511,9 @@ Engine::Engine(const Problem& p) : p_(p), chunk_(memory_model(p).chunk) {
              "interleaved ordering needs Lx == Lv");
   MPSV_CHECK(p.x_max > p.x_min && p.v_max > p.v_min, kEinval,
              "empty x or v interval");
-  MPSV_CHECK(std::isfinite(p.dt) && p.dt > 0, kEinval, "dt must be > 0");
+  MPSV_CHECK(std::isfinite(p.cfl) && p.cfl >= 0, kEinval, "cfl must be >= 0");
+  MPSV_CHECK(p.cfl > 0 || (std::isfinite(p.dt) && p.dt > 0), kEinval,
+             "dt must be > 0");
   MPSV_CHECK(p.chi_max >= 1, kEinval, "chi_max must be >= 1");
   MPSV_CHECK(p.level >= 1 && p.level <= 5, kEinval, "level must be in 1..5");
   MPSV_CHECK(p.df_max >= 0, kEinval, "df_max must be >= 0");
@@ -1081,9 +1083,29 @@ void Engine::commit(const DMps& fn, hipStream_t s) {
   f_ = copy_mps(fn, state_, s);
 }
 
+double Engine::step_size(hipStream_t s) {
+  if (p_.cfl <= 0) return p_.dt;
+  // eq. CFL for one collisionless species, |E|_max of the current state
+  ArenaScope sc(step_);
+  DMps E = field(f_, step_, s);
+  const long nx = p_.Nx();
+  double* Ed = step_.alloc((size_t)nx);
+  dense_of(E, Ed, s);
+  std::vector<double> h((size_t)nx);
+  MPSV_HIP(hipMemcpyAsync(h.data(), Ed, (size_t)nx * sizeof(double),
+                          hipMemcpyDeviceToHost, s));
+  MPSV_HIP(hipStreamSynchronize(s));
+  double emax = 0.0;
+  for (double e : h) emax = std::max(emax, std::fabs(e));
+  MPSV_CHECK(std::isfinite(emax), kEnumeric, "non-finite field");
+  const double vmax = std::max(std::fabs(p_.v_min), std::fabs(p_.v_max));
+  return p_.cfl / (vmax / p_.dx() + std::fabs(p_.qm) * emax / p_.dv());
+}
+
 void Engine::step(hipStream_t s) {
   MPSV_CHECK(!f_.empty(), kEinval, "state not initialised");
-  const double h = p_.dt;
+  step_.reset();
+  const double h = step_size(s);
   step_.reset();
   DMps k1 = rhs(f_, step_, s);
   DMps f2 = add_terms({{1.0, &f_}, {0.5 * h, &k1}}, cap_for(2), step_, s);

@@ -17,6 +17,7 @@ struct Problem {
   double tol = 1e-10;
   int precision = 0;
   int x_scheme = 0;  // 0 central, 1 upwind x advection
+  double cfl = 0.0;  // > 0: adaptive dt, this fraction of the CFL limit
   int n() const { return Lx + Lv; }
   long Nx() const { return 1L << Lx; }
   long Nv() const { return 1L << Lv; }
@@ -93,6 +94,8 @@ class Engine {
   const DMps& state() const { return f_; }
   std::vector<int> bonds() const;
   double time() const { return t_; }
+  // the step the next mps_step takes (the adaptive one needs a sync)
+  double step_size(hipStream_t s);
   long steps_done() const { return steps_; }
   const std::vector<double>& last_discarded() const { return disc_; }
 

@@ -349,3 +349,31 @@ def test_truncated_upwind_matches_mps_oracle(B, order):
     assert np.abs(E.cpu().numpy() - Eref).max() <= 1e-8 * np.abs(Eref).max()
     assert st.info()["bonds"][1:-1] == omps.bond_dims(f)
     st.free()
+
+
+@pytest.mark.parametrize("scheme,cfl", [(0, 0.9), (1, 0.6)])
+def test_adaptive_cfl_steps_match_oracles(B, scheme, cfl):
+    """Adaptive time step (eq. CFL): untruncated, the GPU steps equal the
+    dense adaptive steps and the elapsed time the sum of the dense steps;
+    truncated (C1, chi = 16), the GPU matches the MPS oracle from the same
+    state."""
+    _say("adaptive cfl scheme=%d cfl=%g" % (scheme, cfl))
+    w = _untruncated(wl.landau_small(L=4))
+    p = w.problem
+    p.x_scheme, p.cfl, p.dt = scheme, cfl, 0.0
+    st = B.MpsState(p, w.ax, w.bv)
+    F = odense.initial(w.ax, w.bv)
+    t = 0.0
+    for _ in range(3):
+        t += odense.cfl_dt(F, p)
+        F = odense.rk4_step(F, p)
+        st.step(1)
+    G = st.to_dense().cpu().numpy()
+    assert np.abs(G - F).max() <= 1e-11 * np.abs(F).max()
+    assert abs(st.info()["t"] - t) <= 1e-12 * t
+    st.free()
+    w = wl.landau_small(L=6, chi=16, tol=1e-10)
+    w.problem.x_scheme, w.problem.cfl = scheme, cfl
+    G, R, E, Eref, info, f = _from_same_state(B, w, 3)
+    assert np.abs(G - R).max() <= 1e-8 * np.abs(R).max()
+    assert np.abs(E - Eref).max() <= 1e-8 * np.abs(Eref).max()
