@@ -137,6 +137,14 @@ mps_status mps_moments(mps_state* h, double* n_out, double* E_out,
 /* Reconstruct f on the grid: device double[Nx*Nv], f_out[i*Nv + j]. */
 mps_status mps_to_dense(mps_state* h, double* f_out, hipStream_t stream);
 
+/* Entanglement entropy (Results, State Compressibility): for each of the
+ * n-1 bonds, -sum_i t_i log2 t_i with t_i the squared Schmidt values of the
+ * current state across that bond normalised to sum 1 (0 for a product
+ * cut).  The Schmidt values come from an untruncated canonicalisation (QR
+ * sweep, then SVD sweep) of a copy; the state is unchanged.  ee: host
+ * double[n-1]; synchronises the stream. */
+mps_status mps_entanglement(mps_state* h, double* ee, hipStream_t stream);
+
 /* Release the state and all its device memory.  NULL is accepted. */
 mps_status mps_free(mps_state* h);
 

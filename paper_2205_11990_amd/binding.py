@@ -61,6 +61,7 @@ _SIGS = {
     "mps_add_scaled": [_P, _D, _PI32, _P, _P],
     "mps_workspace_bound": [ctypes.POINTER(CProblem), ctypes.POINTER(ctypes.c_size_t)],
     "mps_device_bytes": [_P, ctypes.POINTER(ctypes.c_size_t)],
+    "mps_entanglement": [_P, _PD, _P],
     "mps_step_batched": [ctypes.POINTER(_P), _I32, _I32, _P],
     "mps_last_error": [],
     "mpsb_gemm": [_I32, _I32, _I32, _D, _P, _I64, _P, _I64, _D, _P, _I64, _P],
@@ -220,6 +221,13 @@ class MpsState:
         _check(lib().mps_info(self._h, None, bonds, disc, ctypes.byref(t), ctypes.byref(st)))
         return {"n": n, "bonds": list(bonds), "discarded": list(disc)[:n - 1],
                 "t": t.value, "steps": st.value}
+
+    def entanglement(self, stream=None) -> List[float]:
+        """Entanglement entropy (log2) at each of the n-1 bonds."""
+        n = self.info()["n"]
+        ee = (ctypes.c_double * max(n - 1, 1))()
+        _check(lib().mps_entanglement(self._h, ee, _stream(stream)))
+        return list(ee)[:n - 1]
 
     def device_bytes(self) -> int:
         b = ctypes.c_size_t()

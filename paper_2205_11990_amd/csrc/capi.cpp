@@ -262,6 +262,15 @@ mps_status mps_workspace_bound(const mps_problem* p, size_t* bytes) {
   });
 }
 
+mps_status mps_entanglement(mps_state* h, double* ee, hipStream_t stream) {
+  return guarded([&] {
+    check_handle(h);
+    MPSV_CHECK(ee != nullptr, mpsv::kEinval, "ee is NULL");
+    auto v = h->eng->entanglement(stream);
+    for (size_t j = 0; j < v.size(); ++j) ee[j] = v[j];
+  });
+}
+
 mps_status mps_device_bytes(const mps_state* h, size_t* bytes) {
   return guarded([&] {
     check_handle(h);

@@ -730,7 +730,8 @@ void Engine::absorb_right(const VSite& v, const double* L, int q, double* N,
 
 DMps Engine::compress_chain(const std::vector<VSite>& ch_in, int cap, double tol,
                             Arena& out, hipStream_t s,
-                            std::vector<double>* disc) {
+                            std::vector<double>* disc,
+                            std::vector<std::vector<double>>* sigmas) {
   const int n = (int)ch_in.size();
   MPSV_CHECK(n >= 2, kEinval, "compression needs at least two sites");
   cap = cap_or_inf(cap);
@@ -811,15 +812,24 @@ DMps Engine::compress_chain(const std::vector<VSite>& ch_in, int cap, double tol
   // ---- (ii) truncated SVD sweep right to left
   DMps res(n);
   if (disc) disc->assign(n - 1, 0.0);
+  if (sigmas) sigmas->assign(n - 1, {});
   int m = p, Dr = 1;
   for (int j = n - 1; j >= 1; --j) {
     const int c = 2 * Dr;
     const int Dmax = std::min(std::min(cap, m), c);
     double* Vt = out.alloc((size_t)Dmax * c);
     double* US = work().alloc((size_t)m * Dmax);
+    double* sg = sigmas ? work().alloc((size_t)std::min(m, c)) : nullptr;
     double dsc = 0.0;
-    const int D = svd_truncate(s, work(), X, m, c, c, cap, tol, Vt, US, nullptr,
+    const int D = svd_truncate(s, work(), X, m, c, c, cap, tol, Vt, US, sg,
                                &dsc);
+    if (sigmas) {
+      auto& h = (*sigmas)[j - 1];
+      h.resize((size_t)std::min(m, c));
+      MPSV_HIP(hipMemcpyAsync(h.data(), sg, h.size() * sizeof(double),
+                              hipMemcpyDeviceToHost, s));
+      MPSV_HIP(hipStreamSynchronize(s));
+    }
     res[j] = Core{Vt, D, Dr};
     if (disc) (*disc)[j - 1] = dsc;
     const Fac& f = fac[j - 1];
@@ -1081,6 +1091,33 @@ void Engine::commit(const DMps& fn, hipStream_t s) {
   if (bad) throw Error(kEnumeric, "non-finite values in the new state");
   state_.reset();
   f_ = copy_mps(fn, state_, s);
+}
+
+std::vector<double> Engine::entanglement(hipStream_t s) {
+  MPSV_CHECK(!f_.empty(), kEinval, "state not initialised");
+  ArenaScope sc(tmp_);
+  std::vector<VSite> ch(f_.size());
+  for (size_t j = 0; j < f_.size(); ++j) {
+    ch[j].kind = VSite::kDense;
+    ch[j].A = f_[j];
+    ch[j].l = f_[j].l;
+    ch[j].r = f_[j].r;
+  }
+  std::vector<std::vector<double>> sig;
+  compress_chain(ch, INT_MAX, 0.0, tmp_, s, nullptr, &sig);
+  std::vector<double> ee(sig.size(), 0.0);
+  for (size_t b = 0; b < sig.size(); ++b) {
+    double tot = 0.0;
+    for (double x : sig[b]) tot += x * x;
+    if (tot <= 0.0) continue;
+    double e = 0.0;
+    for (double x : sig[b]) {
+      const double t = x * x / tot;
+      if (t > 0.0) e -= t * std::log2(t);
+    }
+    ee[b] = e;
+  }
+  return ee;
 }
 
 double Engine::step_size(hipStream_t s) {

@@ -94,6 +94,9 @@ class Engine {
   const DMps& state() const { return f_; }
   std::vector<int> bonds() const;
   double time() const { return t_; }
+  // von Neumann entropy (log2) of the Schmidt values at each of the n-1
+  // bonds of the committed state (an untruncated canonicalisation)
+  std::vector<double> entanglement(hipStream_t s);
   // the step the next mps_step takes (the adaptive one needs a sync)
   double step_size(hipStream_t s);
   long steps_done() const { return steps_; }
@@ -117,7 +120,8 @@ class Engine {
 
   // ---- building blocks exposed for tests through the C-ABI
   DMps compress_chain(const std::vector<VSite>& ch, int cap, double tol,
-                      Arena& out, hipStream_t s, std::vector<double>* disc);
+                      Arena& out, hipStream_t s, std::vector<double>* disc,
+                      std::vector<std::vector<double>>* sigmas = nullptr);
   DMps compress_mps(const DMps& a, int cap, double tol, Arena& out,
                     hipStream_t s, std::vector<double>* disc = nullptr);
   DMps apply_compress(const DMpo& W, const DMps& a, int cap, double tol,

@@ -377,3 +377,30 @@ def test_adaptive_cfl_steps_match_oracles(B, scheme, cfl):
     G, R, E, Eref, info, f = _from_same_state(B, w, 3)
     assert np.abs(G - R).max() <= 1e-8 * np.abs(R).max()
     assert np.abs(E - Eref).max() <= 1e-8 * np.abs(Eref).max()
+
+
+def test_entanglement_entropy_matches_oracle(B):
+    """mps_entanglement on a stepped state equals the oracle's entropies of
+    the same cores; on a state with a known x|v Schmidt spectrum it gives
+    the closed form."""
+    _say("entanglement entropy")
+    w = wl.landau_small(L=5, chi=16, tol=1e-10)
+    st = B.MpsState(w.problem, w.ax, w.bv)
+    st.step(3)
+    ee = st.entanglement()
+    ref = omps.entanglement_entropy(st.get_cores_host())
+    assert np.abs(np.array(ee) - np.array(ref)).max() < 1e-9
+    st.free()
+    p = wl.landau_small(L=4).problem
+    p.Lv, p.chi_max, p.tol = 4, 64, 0.0
+    s = np.array([3.0, 1.0, 0.5])
+    rng = np.random.default_rng(1)
+    u, _ = np.linalg.qr(rng.standard_normal((16, 3)))
+    v, _ = np.linalg.qr(rng.standard_normal((16, 3)))
+    F = (u * s) @ v.T
+    cores = omps.tt_svd(omps.dense_to_sites(F, 4, 4, 0), [2] * 8, tol=0.0)
+    st = B.MpsState(p, u[:, 0], v[:, 0])
+    st.set_cores(cores)
+    t = s ** 2 / np.sum(s ** 2)
+    assert abs(st.entanglement()[3] - float(-np.sum(t * np.log2(t)))) < 1e-10
+    st.free()
