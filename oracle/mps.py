@@ -25,6 +25,8 @@ Sections of the paper followed here:
 * SI "Inverse Laplacian": dense inverse converted into an MPO.
 * SI "Integration": dx [1, 1]^{(x) L}.
 * SI "Canonicalization and Compression": QR sweep then truncated SVD sweep.
+* SI "Modified Compression Scheme": centre-first compression of a sequential
+  ordering (x|v bond first, then each half), optional per problem.
 * SI "Compressed time evolution algorithm": RK4 and compression levels C1-C5.
 * Results, "State Compressibility" (eq. 6 context) and Fig. 3 orderings:
   sequential S1 and interleaved IF maps.
@@ -42,6 +44,14 @@ Readings where the paper is silent or garbled (each also listed in the design doc):
   the k's, P4 each k, P5 each term of a k.  Every point truncates with tol;
   level C_l caps P1..P_l at chi (C1: only the final state is capped).
 * The field MPS is compressed with tol and an optional cap D_F.
+* Centre-first compression: the SVD is of the centre site (first v site)
+  at its left bond, the x|v cut; U S joins the last x site and S V^T becomes
+  the centre site (the printed step that merges S V^T into the next site
+  would drop a site); the centre cut obeys the same rank rule (chi, tol) as
+  every other bond; the x half is swept right to left and the v half left
+  to right; S^-1 goes into the centre site's left bond, with 0 for a value
+  at or below 1e-200 of the largest.  The full-chain compressions P1-P5
+  (and the initial state) use it; the field keeps the plain sweep.
 
 TEST INFRASTRUCTURE ONLY -- see ``oracle/__init__``.
 """
@@ -210,6 +220,74 @@ def compress(mps: Mps, chi: Optional[int], tol: float,
         disc[j - 1] = math.sqrt(float(np.sum(S[D:] ** 2)) / nrm2) if nrm2 > 0 else 0.0
         A[j] = Vt[:D].reshape(D, d, b)
         A[j - 1] = np.tensordot(A[j - 1], U[:, :D] * S[:D], axes=(2, 0))
+    return (A, disc) if return_discarded else A
+
+
+def centre_pinv(S: np.ndarray) -> np.ndarray:
+    """1 / s for the kept centre values; a value at or below 1e-200 of the
+    largest (in practice an exact zero of a rank-deficient cut) carries no
+    weight in either half and gets 0 instead of an overflow."""
+    out = np.zeros_like(S)
+    keep = S > S[0] * 1e-200 if len(S) and S[0] > 0 else np.zeros(len(S), bool)
+    out[keep] = 1.0 / S[keep]
+    return out
+
+
+def compress_centre(mps: Mps, c: int, chi: Optional[int], tol: float,
+                    return_discarded: bool = False):
+    """SI, Modified Compression Scheme, for a sequential ordering whose two
+    dimensions meet at the bond between sites c-1 and c.
+
+    1. Mixed canonical form: sites 0..c-1 left canonical (QR sweep from the
+       left), sites c+1..n-1 right canonical (QR of the transposed cores,
+       sweeping from the right); site c holds the whole norm.
+    2. Site c as (left bond) x (2 * right bond) = U S V^T, D kept by the rank
+       rule.  These are the Schmidt values of the x|v cut: f = sum_r s_r
+       g_r(x) h_r(v).
+    3.-5. A_{c-1} <- A_{c-1} U S and A_c <- S V^T, with S^-1 between them,
+       so the left half holds G = [s_r g_r] and the right half H = [s_r h_r].
+    6. Truncated SVD sweep right to left over sites c-1 .. 1 (bonds inside x).
+    7. Truncated SVD sweep left to right over sites c .. n-2 (bonds inside v).
+    8. S^-1 absorbed into the left bond of site c.
+    The result represents G' S^-1 H'; it is not in canonical form."""
+    A = [x.copy() for x in mps]
+    n = len(A)
+    if not 1 <= c <= n - 1:
+        raise ValueError("centre must lie in [1, n-1]")
+    for j in range(c):
+        a, d, b = A[j].shape
+        Q, R = np.linalg.qr(A[j].reshape(a * d, b))
+        A[j] = Q.reshape(a, d, Q.shape[1])
+        A[j + 1] = np.tensordot(R, A[j + 1], axes=(1, 0))
+    for j in range(n - 1, c, -1):
+        a, d, b = A[j].shape
+        Q, R = np.linalg.qr(A[j].reshape(a, d * b).T)
+        A[j] = Q.T.reshape(Q.shape[1], d, b)
+        A[j - 1] = np.tensordot(A[j - 1], R.T, axes=(2, 0))
+    disc = [0.0] * (n - 1)
+
+    def trunc(M):
+        U, S, Vt = np.linalg.svd(M, full_matrices=False)
+        D = rank_rule(S, chi, tol)
+        nrm2 = float(np.sum(S * S))
+        e = math.sqrt(float(np.sum(S[D:] ** 2)) / nrm2) if nrm2 > 0 else 0.0
+        return U[:, :D], S[:D], Vt[:D], e
+
+    a, d, b = A[c].shape
+    U, S, Vt, disc[c - 1] = trunc(A[c].reshape(a, d * b))
+    A[c - 1] = np.tensordot(A[c - 1], U * S, axes=(2, 0))
+    A[c] = (S[:, None] * Vt).reshape(len(S), d, b)
+    for j in range(c - 1, 0, -1):
+        a, d, b = A[j].shape
+        Uj, Sj, Vj, disc[j - 1] = trunc(A[j].reshape(a, d * b))
+        A[j] = Vj.reshape(len(Sj), d, b)
+        A[j - 1] = np.tensordot(A[j - 1], Uj * Sj, axes=(2, 0))
+    for j in range(c, n - 1):
+        a, d, b = A[j].shape
+        Uj, Sj, Vj, disc[j] = trunc(A[j].reshape(a * d, b))
+        A[j] = Uj.reshape(a, d, len(Sj))
+        A[j + 1] = np.tensordot(Sj[:, None] * Vj, A[j + 1], axes=(1, 0))
+    A[c] = centre_pinv(S)[:, None, None] * A[c]
     return (A, disc) if return_discarded else A
 
 
@@ -577,6 +655,16 @@ def field_mps(g: Mps, ops: Operators) -> Mps:
     return compress(En, p.df_max if p.df_max > 0 else None, p.tol)
 
 
+def compress_state(m: Mps, chi: Optional[int], p) -> Mps:
+    """Compression of a full-chain MPS at one of the points P1-P5: the sweep
+    of SI "Canonicalization and Compression", or, when p.compression == 1
+    (sequential orderings), the centre-first scheme of SI "Modified
+    Compression Scheme" with its centre at the x|v bond."""
+    if getattr(p, "compression", 0) == 1:
+        return compress_centre(m, p.Lx, chi, p.tol)
+    return compress(m, chi, p.tol)
+
+
 def caps(p, point: int) -> Optional[int]:
     """Level C_l caps compression points P1..P_l at chi."""
     return p.chi_max if p.level >= point else None
@@ -590,9 +678,9 @@ def rhs_mps(g: Mps, ops: Operators) -> Mps:
     WE = diag_mpo(E)
     WE[0] = WE[0] * (-p.qm)
     W2 = chain_mpo(WE, ops.Dv, p.Lx, p.Lv, p.order)
-    T1 = compress(apply(ops.T1, g), caps(p, 5), p.tol)
-    T2 = compress(apply(W2, g), caps(p, 5), p.tol)
-    return compress(add([(1.0, T1), (1.0, T2)]), caps(p, 4), p.tol)
+    T1 = compress_state(apply(ops.T1, g), caps(p, 5), p)
+    T2 = compress_state(apply(W2, g), caps(p, 5), p)
+    return compress_state(add([(1.0, T1), (1.0, T2)]), caps(p, 4), p)
 
 
 def cfl_dt(f: Mps, ops: Operators) -> float:
@@ -610,15 +698,15 @@ def rk4_step(f: Mps, ops: Operators) -> Mps:
     p = ops.p
     h = cfl_dt(f, ops) if getattr(p, "cfl", 0.0) > 0.0 else p.dt
     k1 = rhs_mps(f, ops)
-    f2 = compress(add([(1.0, f), (0.5 * h, k1)]), caps(p, 2), p.tol)
+    f2 = compress_state(add([(1.0, f), (0.5 * h, k1)]), caps(p, 2), p)
     k2 = rhs_mps(f2, ops)
-    f3 = compress(add([(1.0, f), (0.5 * h, k2)]), caps(p, 2), p.tol)
+    f3 = compress_state(add([(1.0, f), (0.5 * h, k2)]), caps(p, 2), p)
     k3 = rhs_mps(f3, ops)
-    f4 = compress(add([(1.0, f), (h, k3)]), caps(p, 2), p.tol)
+    f4 = compress_state(add([(1.0, f), (h, k3)]), caps(p, 2), p)
     k4 = rhs_mps(f4, ops)
-    S = compress(add([(1.0, k1), (2.0, k2), (2.0, k3), (1.0, k4)]),
-                 caps(p, 3), p.tol)
-    return compress(add([(1.0, f), (h / 6.0, S)]), p.chi_max, p.tol)
+    S = compress_state(add([(1.0, k1), (2.0, k2), (2.0, k3), (1.0, k4)]),
+                       caps(p, 3), p)
+    return compress_state(add([(1.0, f), (h / 6.0, S)]), p.chi_max, p)
 
 
 def init_mps(p, ax: np.ndarray, bv: np.ndarray) -> Mps:
@@ -627,7 +715,7 @@ def init_mps(p, ax: np.ndarray, bv: np.ndarray) -> Mps:
     F = np.einsum("ri,rj->ij", ax, bv)
     vec = dense_to_sites(F, p.Lx, p.Lv, p.order)
     m = tt_svd(vec, [2] * p.n_sites, tol=p.tol, chi=None)
-    return compress(m, p.chi_max, p.tol)
+    return compress_state(m, p.chi_max, p)
 
 
 def to_dense(f: Mps, p) -> np.ndarray:

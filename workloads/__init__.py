@@ -47,6 +47,7 @@ class Problem:
     precision: int = PREC_FP64
     x_scheme: int = 0       # x advection: 0 central, 1 upwind (second order)
     cfl: float = 0.0        # > 0: adaptive dt, this fraction of the CFL limit
+    compression: int = 0    # 0 sweep, 1 centre-first (sequential orderings)
 
     @property
     def Nx(self) -> int:
