@@ -60,6 +60,20 @@ mps_status mpsb_compress(int32_t n, const int32_t* mpo_bonds,
                          int64_t capacity, double* discarded,
                          hipStream_t stream);
 
+/* Centre-first compression (SI, "Modified Compression Scheme") of an MPS
+ * cut at the bond between sites centre-1 and centre (1 <= centre <= n-1):
+ * the cut is truncated first from the mixed canonical form around it, then
+ * sites 0..centre-1 are compressed by a truncated SVD sweep right to left
+ * and sites centre..n-1 by one left to right, each bond to (cap, tol), and
+ * S^-1 of the cut is folded into the left bond of site `centre`.
+ * Arguments as for mpsb_compress (no MPO); discarded[j] is the relative
+ * discarded weight at bond j | j+1. */
+mps_status mpsb_compress_centre(int32_t n, int32_t centre,
+                                const int32_t* bonds_in, const double* cores_in,
+                                int32_t cap, double tol, int32_t* bonds_out,
+                                double* cores_out, int64_t capacity,
+                                double* discarded, hipStream_t stream);
+
 /* Sum of MPS terms sum_t coef[t] * g_t, compressed (SI, "Addition").
  * bonds: host int32[nterms*(n+1)]; cores: host array of nterms device
  * pointers to packed cores. */

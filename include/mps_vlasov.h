@@ -83,6 +83,23 @@ typedef enum {
  * displayed formula pairs forward with H(v). */
 typedef enum { MPS_X_CENTRAL = 0, MPS_X_UPWIND = 1 } mps_x_scheme;
 
+/* Compression of the full chain at every compression point (SI,
+ * "Canonicalization and Compression" and "Modified Compression Scheme"):
+ * MPS_COMPRESS_SWEEP is a QR sweep left to right, then a truncated SVD sweep
+ * right to left.  MPS_COMPRESS_CENTRE_FIRST (sequential ordering only)
+ * first truncates the x|v bond, f = sum_r s_r g_r(x) h_r(v), from the
+ * mixed canonical form around it, then compresses the x half G = [s_r g_r]
+ * right to left and the v half H = [s_r h_r] left to right, and joins them
+ * through S^-1 (folded into the first v site; a value at or below 1e-200 of
+ * the largest, an exact zero of a rank-deficient cut, gets 0).  The result
+ * is not in canonical form.  The field and the entanglement diagnostic
+ * keep the sweep.  The centre-first scheme also holds the untruncated right
+ * half in its workspace, which mps_workspace_bound does not model. */
+typedef enum {
+  MPS_COMPRESS_SWEEP = 0,
+  MPS_COMPRESS_CENTRE_FIRST = 1
+} mps_compression;
+
 /* Problem statement.  Site orderings (Fig. 3): MPS_ORDER_SEQ is x bits
  * coarse->fine then v bits coarse->fine (S1); MPS_ORDER_INTERLEAVED is
  * x1, v1, x2, v2, ... (IF; needs Lx == Lv).  Compression level (SI,
@@ -110,6 +127,7 @@ typedef struct mps_problem {
   int32_t precision;        /* mps_precision                               */
   int32_t x_scheme;         /* mps_x_scheme                                */
   double cfl;               /* > 0: adaptive dt (see below), 0: fixed dt   */
+  int32_t compression;      /* mps_compression                             */
 } mps_problem;
 
 typedef struct mps_state mps_state; /* opaque; owns all device memory */

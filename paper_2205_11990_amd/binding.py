@@ -37,7 +37,7 @@ class CProblem(ctypes.Structure):
         ("chi_max", ctypes.c_int32), ("level", ctypes.c_int32),
         ("df_max", ctypes.c_int32), ("tol", ctypes.c_double),
         ("precision", ctypes.c_int32), ("x_scheme", ctypes.c_int32),
-        ("cfl", ctypes.c_double),
+        ("cfl", ctypes.c_double), ("compression", ctypes.c_int32),
     ]
 
 
@@ -69,6 +69,7 @@ _SIGS = {
     "mpsb_qr": [_I32, _I32, _P, _P, _P],
     "mpsb_svd_truncate": [_I32, _I32, _P, _I32, _D, _P, _P, _P, _PI32, _PD, _P],
     "mpsb_compress": [_I32, _PI32, _P, _PI32, _P, _I32, _D, _PI32, _P, _I64, _PD, _P],
+    "mpsb_compress_centre": [_I32, _I32, _PI32, _P, _I32, _D, _PI32, _P, _I64, _PD, _P],
     "mpsb_add_compress": [_I32, _I32, _PD, _PI32, ctypes.POINTER(_P), _I32, _D,
                           _PI32, _P, _I64, _P],
     "mpsb_density_field": [_P, _P, _P, _P],
@@ -146,6 +147,7 @@ def make_problem(p) -> CProblem:
     c.tol, c.precision = float(p.tol), int(getattr(p, "precision", 0))
     c.x_scheme = int(getattr(p, "x_scheme", 0))
     c.cfl = float(getattr(p, "cfl", 0.0))
+    c.compression = int(getattr(p, "compression", 0))
     return c
 
 
@@ -356,6 +358,27 @@ def compress(cores: Sequence[np.ndarray], cap=0, tol=0.0, mpo=None, stream=None)
     disc = (ctypes.c_double * (n - 1))()
     _check(lib().mpsb_compress(n, wbp, wp, b.ctypes.data_as(_PI32), _ptr(d), int(cap),
                                float(tol), ob, _ptr(out), capacity, disc, _stream(stream)))
+    return unpack_cores(list(ob), out.cpu().numpy()), list(disc)
+
+
+def compress_centre(cores: Sequence[np.ndarray], centre: int, cap=0, tol=0.0,
+                    stream=None):
+    """Centre-first compression of host MPS cores cut at the bond
+    centre-1 | centre; returns (host cores, discarded)."""
+    torch = _torch()
+    n = len(cores)
+    b, flat = pack_cores(cores)
+    d = _dev(flat)
+    cap_eff = cap if cap and cap > 0 else 1 << 30
+    capacity = sum(min(cap_eff, 2 ** min(j, n - j), int(b[j])) * 2 *
+                   min(cap_eff, 2 ** min(j + 1, n - j - 1), int(b[j + 1]))
+                   for j in range(n))
+    out = torch.empty(capacity, dtype=torch.float64, device="cuda")
+    ob = (ctypes.c_int32 * (n + 1))()
+    disc = (ctypes.c_double * (n - 1))()
+    _check(lib().mpsb_compress_centre(n, int(centre), b.ctypes.data_as(_PI32), _ptr(d),
+                                      int(cap), float(tol), ob, _ptr(out), capacity,
+                                      disc, _stream(stream)))
     return unpack_cores(list(ob), out.cpu().numpy()), list(disc)
 
 

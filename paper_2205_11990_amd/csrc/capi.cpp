@@ -78,6 +78,7 @@ mpsv::Problem convert(const mps_problem* p) {
   q.precision = p->precision;
   q.x_scheme = p->x_scheme;
   q.cfl = p->cfl;
+  q.compression = p->compression;
   MPSV_CHECK(std::isfinite(q.x_min) && std::isfinite(q.x_max) &&
                  std::isfinite(q.v_min) && std::isfinite(q.v_max),
              mpsv::kEinval, "grid bounds must be finite");
@@ -454,6 +455,30 @@ mps_status mpsb_compress(int32_t n, const int32_t* mpo_bonds,
     } else {
       r = e.compress_mps(a, cap > 0 ? cap : INT_MAX, tol, out, stream, &disc);
     }
+    pack(r, bonds_out, cores_out, capacity, stream);
+    if (discarded)
+      for (int j = 0; j < n - 1; ++j) discarded[j] = disc[j];
+  });
+}
+
+mps_status mpsb_compress_centre(int32_t n, int32_t centre,
+                                const int32_t* bonds_in, const double* cores_in,
+                                int32_t cap, double tol, int32_t* bonds_out,
+                                double* cores_out, int64_t capacity,
+                                double* discarded, hipStream_t stream) {
+  return guarded([&] {
+    MPSV_CHECK(n >= 2 && n <= 28, mpsv::kEinval, "n must lie in [2, 28]");
+    MPSV_CHECK(centre >= 1 && centre <= n - 1, mpsv::kEinval,
+               "centre must lie in [1, n-1]");
+    MPSV_CHECK(tol >= 0, mpsv::kEinval, "tol must be >= 0");
+    MPSV_CHECK(bonds_out && cores_out, mpsv::kEinval, "NULL output");
+    std::lock_guard<std::mutex> lk(g_blocks_mu);
+    mpsv::Engine& e = blocks();
+    mpsv::Arena out;
+    mpsv::DMps a = unpack(n, bonds_in, cores_in);
+    std::vector<double> disc;
+    mpsv::DMps r = e.compress_mps(a, cap > 0 ? cap : INT_MAX, tol, out, stream,
+                                  &disc, centre);
     pack(r, bonds_out, cores_out, capacity, stream);
     if (discarded)
       for (int j = 0; j < n - 1; ++j) discarded[j] = disc[j];

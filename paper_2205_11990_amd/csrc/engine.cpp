@@ -523,6 +523,10 @@ Engine::Engine(const Problem& p) : p_(p), chunk_(memory_model(p).chunk) {
   MPSV_CHECK(p.x_scheme == 0 || p.x_scheme == 1, kEinval,
              "unknown x advection scheme");
   MPSV_CHECK(std::isfinite(p.qm), kEinval, "q/m must be finite");
+  MPSV_CHECK(p.compression == 0 || p.compression == 1, kEinval,
+             "unknown compression scheme");
+  MPSV_CHECK(p.compression == 0 || p.order == 0, kEinval,
+             "centre-first compression needs a sequential ordering");
 
   MPSV_HIP(hipGetDevice(&device_));
   MPSV_HIP(hipStreamCreateWithFlags(&own_, hipStreamNonBlocking));
@@ -731,9 +735,13 @@ void Engine::absorb_right(const VSite& v, const double* L, int q, double* N,
 DMps Engine::compress_chain(const std::vector<VSite>& ch_in, int cap, double tol,
                             Arena& out, hipStream_t s,
                             std::vector<double>* disc,
-                            std::vector<std::vector<double>>* sigmas) {
+                            std::vector<std::vector<double>>* sigmas,
+                            int centre) {
   const int n = (int)ch_in.size();
   MPSV_CHECK(n >= 2, kEinval, "compression needs at least two sites");
+  MPSV_CHECK(centre >= 0 && centre < n, kEinval, "centre site out of range");
+  MPSV_CHECK(centre == 0 || !sigmas, kEinval,
+             "Schmidt values come from the plain sweep");
   cap = cap_or_inf(cap);
   ArenaScope sc(work());
   // ---- right dense region.  Where the sites j..n-1 span no more indices
@@ -809,19 +817,32 @@ DMps Engine::compress_chain(const std::vector<VSite>& ch_in, int cap, double tol
   }
   double* X = work().alloc((size_t)p * 2);
   absorb_left(ch[n - 1], R, p, X, s);
-  // ---- (ii) truncated SVD sweep right to left
+  // ---- (ii) truncated SVD sweep right to left.  Centre-first (SI,
+  // Modified Compression Scheme; centre > 0): the sites right of the centre
+  // are only brought to right-canonical form (untruncated SVDs), the centre
+  // SVD truncates the cut between sites centre-1 and centre and its U S
+  // moves left, so the rest of this sweep compresses the left half G = [s_r
+  // g_r]; the right half H = S V^T ... is compressed by a left-to-right
+  // sweep afterwards and S^-1 joins the centre site's left bond.
   DMps res(n);
   if (disc) disc->assign(n - 1, 0.0);
   if (sigmas) sigmas->assign(n - 1, {});
+  double* sig_c = nullptr;  // centre singular values (device, descending)
   int m = p, Dr = 1;
   for (int j = n - 1; j >= 1; --j) {
     const int c = 2 * Dr;
-    const int Dmax = std::min(std::min(cap, m), c);
-    double* Vt = out.alloc((size_t)Dmax * c);
+    const bool exact = centre > 0 && j > centre;
+    const int capj = exact ? INT_MAX : cap;
+    const double tolj = exact ? 0.0 : tol;
+    Arena& dst = (centre > 0 && j >= centre) ? work() : out;
+    const int Dmax = std::min(std::min(capj, m), c);
+    double* Vt = dst.alloc((size_t)Dmax * c);
     double* US = work().alloc((size_t)m * Dmax);
-    double* sg = sigmas ? work().alloc((size_t)std::min(m, c)) : nullptr;
+    const bool want_sg = sigmas || (centre > 0 && j == centre);
+    double* sg = want_sg ? work().alloc((size_t)std::min(m, c)) : nullptr;
+    if (centre > 0 && j == centre) sig_c = sg;
     double dsc = 0.0;
-    const int D = svd_truncate(s, work(), X, m, c, c, cap, tol, Vt, US, sg,
+    const int D = svd_truncate(s, work(), X, m, c, c, capj, tolj, Vt, US, sg,
                                &dsc);
     if (sigmas) {
       auto& h = (*sigmas)[j - 1];
@@ -850,11 +871,76 @@ DMps Engine::compress_chain(const std::vector<VSite>& ch_in, int cap, double tol
   MPSV_HIP(hipMemcpyAsync(c0.p, X, sizeof(double) * 2 * Dr,
                           hipMemcpyDeviceToDevice, s));
   res[0] = c0;
+  if (centre > 0)
+    compress_right_half(res, centre, sig_c, cap, tol, out, s, disc);
   return res;
 }
 
+// Right half of the centre-first scheme.  res[centre] = V_c^T and
+// res[centre+1..n-1] are right-canonical (work arena); sc holds the centre
+// values.  H = diag(sc) res[centre] res[centre+1] ... is swept left to
+// right: the carried C (l x l_j) times core j, as (2 l) x r, is M = U S W^T
+// truncated; core j <- U and C <- S W^T.  The SVD routine factors M^T, so
+// M^T = (US') Vt' gives U = Vt'^T and S W^T = (US')^T.  Last, S^-1 is
+// folded into the left bond of the centre core.
+void Engine::compress_right_half(DMps& res, int centre, const double* sc,
+                                 int cap, double tol, Arena& out, hipStream_t s,
+                                 std::vector<double>* disc) {
+  const int n = (int)res.size();
+  const int Dc = res[centre].l;
+  double* H = work().alloc((size_t)res[centre].size());
+  scale_rows(s, res[centre].p, Dc, 2L * res[centre].r, sc, false, H);
+  Core cur{H, Dc, res[centre].r};
+  const double* C = nullptr;  // carry, (l x cur.l) read through view Cv
+  CMatView Cv{nullptr, 0, 0, 0};
+  int l = Dc;
+  for (int j = centre; j < n - 1; ++j) {
+    const int r = cur.r, rows = 2 * l;
+    // Xt = M^T (r x rows): element (b, 2 i + t) = sum_a C[i][a] A[a][t][b]
+    double* Xt = work().alloc((size_t)r * rows);
+    if (C) {
+      gemm(s, l, r, cur.l, 1.0, Cv, CMatView{cur.p, 2L * r, 1, r}, 0.0,
+           MatView{Xt, 2, rows, 1}, 2);
+    } else {
+      copy_view(s, CMatView{cur.p, 2L * r, 1, 0}, l, MatView{Xt, 2, rows, 0}, l,
+                r);
+      copy_view(s, CMatView{cur.p + r, 2L * r, 1, 0}, l,
+                MatView{Xt + 1, 2, rows, 0}, l, r);
+    }
+    const int Dmax = std::min(std::min(cap, r), rows);
+    double* Vt = work().alloc((size_t)Dmax * rows);
+    double* US = work().alloc((size_t)r * Dmax);
+    double dsc = 0.0;
+    const int D = svd_truncate(s, work(), Xt, r, rows, rows, cap, tol, Vt, US,
+                               nullptr, &dsc);
+    if (disc) (*disc)[j] = dsc;
+    // core j = Vt^T: (rows x D), row 2 i + t
+    Core A{out.alloc((size_t)rows * D), l, D};
+    copy_view(s, CMatView{Vt, 1, rows, 0}, rows, MatView{A.p, D, 1, 0}, rows, D);
+    res[j] = A;
+    C = US;
+    Cv = CMatView{US, 1, D, 0};  // (US)^T, D x r
+    l = D;
+    cur = res[j + 1];
+  }
+  // last core: C (l x cur.l) times res[n-1] (cur.l x 2)
+  Core last{out.alloc((size_t)l * 2), l, 1};
+  if (C) {
+    gemm(s, l, 2, cur.l, 1.0, Cv, CMatView{cur.p, 2, 1, 0}, 0.0,
+         MatView{last.p, 2, 1, 0});
+  } else {
+    MPSV_HIP(hipMemcpyAsync(last.p, cur.p, sizeof(double) * 2 * l,
+                            hipMemcpyDeviceToDevice, s));
+  }
+  res[n - 1] = last;
+  // S^-1 into the centre core's left bond
+  Core& A = res[centre];
+  scale_rows(s, A.p, A.l, 2L * A.r, sc, true, A.p);
+}
+
 DMps Engine::compress_mps(const DMps& a, int cap, double tol, Arena& out,
-                          hipStream_t s, std::vector<double>* disc) {
+                          hipStream_t s, std::vector<double>* disc,
+                          int centre) {
   std::vector<VSite> ch(a.size());
   for (size_t j = 0; j < a.size(); ++j) {
     ch[j].kind = VSite::kDense;
@@ -862,7 +948,8 @@ DMps Engine::compress_mps(const DMps& a, int cap, double tol, Arena& out,
     ch[j].l = a[j].l;
     ch[j].r = a[j].r;
   }
-  return compress_chain(ch, cap, tol, out, s, disc);
+  return compress_chain(ch, cap, tol, out, s, disc, nullptr,
+                        centre < 0 ? centre_for((int)a.size()) : centre);
 }
 
 DMps Engine::apply_compress(const DMpo& W, const DMps& a, int cap, double tol,
@@ -877,7 +964,8 @@ DMps Engine::apply_compress(const DMpo& W, const DMps& a, int cap, double tol,
     ch[j].l = W[j].wl * a[j].l;
     ch[j].r = W[j].wr * a[j].r;
   }
-  return compress_chain(ch, cap, tol, out, s, disc);
+  return compress_chain(ch, cap, tol, out, s, disc, nullptr,
+                        centre_for((int)a.size()));
 }
 
 DMps Engine::add_terms(const std::vector<std::pair<double, const DMps*>>& terms,
@@ -902,7 +990,8 @@ DMps Engine::add_terms(const std::vector<std::pair<double, const DMps*>>& terms,
     v.r = (j == n - 1) ? 1 : ro;
   }
   std::vector<double> disc;
-  DMps r = compress_chain(ch, cap, tol < 0 ? p_.tol : tol, out, s, &disc);
+  DMps r = compress_chain(ch, cap, tol < 0 ? p_.tol : tol, out, s, &disc,
+                          nullptr, centre_for(n));
   disc_ = disc;
   return r;
 }

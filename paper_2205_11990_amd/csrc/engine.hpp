@@ -18,6 +18,7 @@ struct Problem {
   int precision = 0;
   int x_scheme = 0;  // 0 central, 1 upwind x advection
   double cfl = 0.0;  // > 0: adaptive dt, this fraction of the CFL limit
+  int compression = 0;  // 0 sweep, 1 centre-first (sequential orderings)
   int n() const { return Lx + Lv; }
   long Nx() const { return 1L << Lx; }
   long Nv() const { return 1L << Lv; }
@@ -119,11 +120,17 @@ class Engine {
   void density_field(double* n_out, double* E_out, hipStream_t s);
 
   // ---- building blocks exposed for tests through the C-ABI
+  // QR sweep left to right, then truncated SVD sweep right to left; with
+  // centre > 0 the centre-first scheme cut at the bond centre-1 | centre
   DMps compress_chain(const std::vector<VSite>& ch, int cap, double tol,
                       Arena& out, hipStream_t s, std::vector<double>* disc,
-                      std::vector<std::vector<double>>* sigmas = nullptr);
+                      std::vector<std::vector<double>>* sigmas = nullptr,
+                      int centre = 0);
+  // centre < 0: the problem's scheme (centre-first at the x|v bond for a
+  // full chain when the problem asks for it)
   DMps compress_mps(const DMps& a, int cap, double tol, Arena& out,
-                    hipStream_t s, std::vector<double>* disc = nullptr);
+                    hipStream_t s, std::vector<double>* disc = nullptr,
+                    int centre = -1);
   DMps apply_compress(const DMpo& W, const DMps& a, int cap, double tol,
                       Arena& out, hipStream_t s,
                       std::vector<double>* disc = nullptr);
@@ -137,6 +144,13 @@ class Engine {
  private:
   void absorb_left(const VSite& v, const double* R, int p, double* M,
                    hipStream_t s);
+  void compress_right_half(DMps& res, int centre, const double* sc, int cap,
+                           double tol, Arena& out, hipStream_t s,
+                           std::vector<double>* disc);
+  // centre site of the problem's compression scheme for an n-site chain
+  int centre_for(int n) const {
+    return (p_.compression == 1 && n == p_.n()) ? p_.Lx : 0;
+  }
   void absorb_right(const VSite& v, const double* L, int q, double* N,
                     hipStream_t s);
   DMps density(const DMps& g, Arena& ar, hipStream_t s);

@@ -53,6 +53,20 @@ __global__ void sum_physical_kernel(const double* in, int l, int r,
   }
 }
 
+// out[a][t] = in[a][t] * g(d[a]) over rows a < rows, t < len; g(x) = x, or
+// for `inverse` 1/x with 0 where x <= d[0] * 1e-200 (d sorted descending, so
+// d[0] is the largest value: a zero of a rank-deficient cut gets 0)
+__global__ void scale_rows_kernel(const double* in, int rows, long len,
+                                  const double* d, int inverse, double* out) {
+  const long n = (long)rows * len;
+  const double floor = d[0] * 1e-200;
+  GRID_STRIDE(e, n) {
+    const double x = d[e / len];
+    const double g = inverse ? (x > floor ? 1.0 / x : 0.0) : x;
+    out[e] = in[e] * g;
+  }
+}
+
 __global__ void kron_embed_kernel(const double* A, int l, int P, int r, int d,
                                   int mode, double* out) {
   // out shape (l*d) x P x (r*d); write all entries (zeros off the identity)
@@ -166,6 +180,15 @@ void sum_physical(hipStream_t s, const double* in, int l, int r, double* out) {
   long n = (long)l * r;
   hipLaunchKernelGGL(sum_physical_kernel, dim3(grid_for(n)), dim3(256), 0, s,
                      in, l, r, out);
+  MPSV_LAUNCHED();
+}
+
+void scale_rows(hipStream_t s, const double* in, int rows, long len,
+                const double* d, bool inverse, double* out) {
+  const long n = (long)rows * len;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(scale_rows_kernel, dim3(grid_for(n)), dim3(256), 0, s, in,
+                     rows, len, d, inverse ? 1 : 0, out);
   MPSV_LAUNCHED();
 }
 

@@ -15,6 +15,11 @@ void copy2d(hipStream_t s, int rows, int cols, double alpha, const double* src,
 // out[a][b] = in[a][0][b] + in[a][1][b]  for an l x 2 x r core
 void sum_physical(hipStream_t s, const double* in, int l, int r, double* out);
 
+// out (rows x len) = diag(g(d)) in, g(x) = x or, with `inverse`, 1/x and 0
+// for x <= d[0] * 1e-200 (d: device, sorted descending; in may equal out)
+void scale_rows(hipStream_t s, const double* in, int rows, long len,
+                const double* d, bool inverse, double* out);
+
 // Embed an operator/core of one dimension into the interleaved chain:
 // A has shape (l, P, r) with P = 2 (MPS core) or 4 (MPO core, (o,i) pairs).
 // mode 0 (A-major): out[(a, c), P, (b, c)]  -- fused index a*d + c

@@ -176,6 +176,30 @@ def test_compress_matches_oracle(B, n, chi, cap, tol):
     assert np.allclose(disc, rdisc, atol=1e-12, rtol=1e-6)
 
 
+@pytest.mark.parametrize("n,centre,chi,cap,tol", [(8, 4, 8, 0, 0.0), (8, 4, 8, 3, 0.0),
+                                                  (9, 5, 12, 6, 0.0), (10, 5, 16, 0, 1e-3),
+                                                  (7, 2, 6, 4, 1e-6), (7, 6, 6, 3, 0.0),
+                                                  (12, 6, 32, 16, 0.0),
+                                                  (16, 8, 160, 128, 0.0)])
+def test_compress_centre_matches_oracle(B, n, centre, chi, cap, tol):
+    """Centre-first compression (SI, Modified Compression Scheme) through
+    the C-ABI against the oracle: the same represented vector, bonds and
+    per-bond discarded weights; the last case cuts 128-wide factorisations
+    on both sides of the centre."""
+    _say("compress_centre n=%d centre=%d chi=%d cap=%d tol=%g" % (n, centre, chi, cap, tol))
+    cores = _random_mps(n, chi, seed=3 * n + centre + chi, decay=3.0)
+    out, disc = B.compress_centre(cores, centre, cap=cap, tol=tol)
+    ref, rdisc = omps.compress_centre(cores, centre, cap if cap > 0 else None, tol,
+                                      return_discarded=True)
+    assert omps.bond_dims(out) == omps.bond_dims(ref)
+    v, r = omps.to_vector(out), omps.to_vector(ref)
+    assert np.abs(v - r).max() <= 1e-10 * np.abs(r).max()
+    assert np.allclose(disc, rdisc, atol=1e-12, rtol=1e-6)
+    if cap == 0 and tol == 0.0:
+        w = omps.to_vector(cores)
+        assert np.abs(v - w).max() <= 1e-12 * np.abs(w).max()
+
+
 @pytest.mark.parametrize("n,chi,cap", [(6, 4, 0), (10, 8, 12), (12, 16, 0)])
 def test_apply_compress_matches_oracle(B, n, chi, cap):
     _say("apply+compress n=%d chi=%d cap=%d" % (n, chi, cap))

@@ -404,3 +404,60 @@ def test_entanglement_entropy_matches_oracle(B):
     t = s ** 2 / np.sum(s ** 2)
     assert abs(st.entanglement()[3] - float(-np.sum(t * np.log2(t)))) < 1e-10
     st.free()
+
+
+@pytest.mark.parametrize("L", [3, 4])
+def test_untruncated_centre_first_steps_equal_dense_oracle(B, L):
+    """Centre-first compression (SI, Modified Compression Scheme) at every
+    point, chi unbounded, tol = 0: the MPS steps equal the dense steps."""
+    _say("untruncated centre-first L=%d" % L)
+    w = _untruncated(wl.landau_small(L=L))
+    p = w.problem
+    p.compression = 1
+    st = B.MpsState(p, w.ax, w.bv)
+    F = odense.initial(w.ax, w.bv)
+    for k in range(3):
+        st.step(1)
+        F = odense.rk4_step(F, p)
+        G = st.to_dense().cpu().numpy()
+        err = np.abs(G - F).max() / np.abs(F).max()
+        assert err < 1e-12 * (k + 2), (k, err)
+    st.free()
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_truncated_centre_first_matches_mps_oracle(B, scheme):
+    """Centre-first compression with every point capped (C5, chi = 8,
+    perturbed two-stream state), central and upwind x advection: f and E
+    within 1e-8 of the CPU MPS oracle after 2 steps, same bonds."""
+    _say("truncated centre-first C5 chi8 two-stream L=5 scheme=%d" % scheme)
+    w = wl.two_stream(L=5, chi=8, tol=0.0, level=5, df_max=4, dt_cfg=0.05, order=0)
+    p = w.problem
+    p.compression = 1
+    p.x_scheme = scheme
+    st = B.MpsState(p, w.ax, w.bv)
+    pert = wl.random_mps_cores(p.n_sites, 8, seed=2205)
+    st.add_scaled(1e-3, pert)
+    f = st.get_cores_host()
+    ops = omps.Operators(p)
+    for _ in range(2):
+        st.step(1)
+        f = omps.rk4_step(f, ops)
+    G = st.to_dense().cpu().numpy()
+    R = omps.to_dense(f, p)
+    _, E = st.density_field()
+    Eref = omps.field_dense(f, ops)
+    assert np.abs(G - R).max() <= 1e-8 * np.abs(R).max()
+    assert np.abs(E.cpu().numpy() - Eref).max() <= 1e-8 * np.abs(Eref).max()
+    assert st.info()["bonds"][1:-1] == omps.bond_dims(f)
+    st.free()
+
+
+def test_centre_first_needs_a_sequential_ordering(B):
+    _say("centre-first with the interleaved ordering is rejected")
+    w = wl.landau_small(L=4)
+    p = w.problem
+    p.order = 1
+    p.compression = 1
+    with pytest.raises(B.MpsError):
+        B.MpsState(p, w.ax, w.bv)
