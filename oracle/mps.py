@@ -29,7 +29,8 @@ Sections of the paper followed here:
   ordering (x|v bond first, then each half), optional per problem.
 * SI "Compressed time evolution algorithm": RK4 and compression levels C1-C5.
 * Results, "State Compressibility" (eq. 6 context) and Fig. 3 orderings:
-  sequential S1 and interleaved IF maps.
+  sequential S1, S2 (x fine->coarse, v coarse->fine), S3 (x coarse->fine,
+  v fine->coarse) and interleaved IF maps.
 
 Readings where the paper is silent or garbled (each also listed in the design doc):
 * The printed M_left of the zero-gradient derivative puts its only entry at
@@ -524,10 +525,18 @@ def vector_mps(vec: np.ndarray, tol: float = 1e-14) -> Mps:
 # ------------------------------------------------------ orderings
 
 def site_map(Lx: int, Lv: int, order: int) -> List[Tuple[str, int]]:
-    """Fig. 3 orderings: 0 = S1 (x coarse->fine, then v coarse->fine),
-    1 = IF (x1, v1, x2, v2, ...)."""
+    """Fig. 3 orderings, as (dimension, bit k) per site, k = 0 the coarsest
+    bit: 0 = S1 (x coarse->fine, then v coarse->fine), 1 = IF (x1, v1, x2,
+    v2, ...), 2 = S2 (x fine->coarse, then v coarse->fine), 3 = S3 (x
+    coarse->fine, then v fine->coarse)."""
+    xs = [("x", k) for k in range(Lx)]
+    vs = [("v", k) for k in range(Lv)]
     if order == 0:
-        return [("x", k) for k in range(Lx)] + [("v", k) for k in range(Lv)]
+        return xs + vs
+    if order == 2:
+        return xs[::-1] + vs
+    if order == 3:
+        return xs + vs[::-1]
     if order == 1:
         if Lx != Lv:
             raise ValueError("interleaved ordering needs Lx == Lv")
@@ -536,6 +545,19 @@ def site_map(Lx: int, Lv: int, order: int) -> List[Tuple[str, int]]:
             out += [("x", k), ("v", k)]
         return out
     raise ValueError("unknown ordering")
+
+
+def reversed_dims(order: int) -> Tuple[bool, bool]:
+    """Whether the x / v sites run from fine to coarse (S2 / S3).  A
+    dimension visited fine to coarse uses its one-dimensional cores in
+    reverse order with their two bonds swapped."""
+    return order == 2, order == 3
+
+
+def reverse_chain(cores: List[np.ndarray]) -> List[np.ndarray]:
+    """The same tensor with the sites in reverse order: MPS cores (l, 2, r)
+    -> (r, 2, l), MPO cores (l, o, i, r) -> (r, o, i, l)."""
+    return [np.swapaxes(A, 0, A.ndim - 1) for A in cores[::-1]]
 
 
 def dense_to_sites(F: np.ndarray, Lx: int, Lv: int, order: int) -> np.ndarray:
@@ -559,6 +581,11 @@ def chain_mpo(Wx: Optional[Mpo], Wv: Optional[Mpo], Lx: int, Lv: int,
     interleaved order the bonds multiply (fused index x-major)."""
     Wx = Wx if Wx is not None else [np.eye(2).reshape(1, 2, 2, 1)] * Lx
     Wv = Wv if Wv is not None else [np.eye(2).reshape(1, 2, 2, 1)] * Lv
+    rx, rv = reversed_dims(order)
+    if rx:
+        Wx = reverse_chain(Wx)[::-1]   # core k, bonds swapped
+    if rv:
+        Wv = reverse_chain(Wv)[::-1]
     bx = 1   # current x bond (right bond of the last x site seen)
     bv = 1
     out = []
@@ -583,6 +610,11 @@ def chain_product_mps(ux: Optional[Mps], uv: Optional[Mps], Lx: int, Lv: int,
     """Full-chain MPS of a product function u(x) w(v) (same embedding)."""
     ux = ux if ux is not None else [np.ones((1, 2, 1))] * Lx
     uv = uv if uv is not None else [np.ones((1, 2, 1))] * Lv
+    rx, rv = reversed_dims(order)
+    if rx:
+        ux = reverse_chain(ux)[::-1]
+    if rv:
+        uv = reverse_chain(uv)[::-1]
     bx = bv = 1
     out = []
     for d, k in site_map(Lx, Lv, order):
@@ -606,7 +638,8 @@ def chain_product_mps(ux: Optional[Mps], uv: Optional[Mps], Lx: int, Lv: int,
 def density_mps(f: Mps, Lx: int, Lv: int, order: int, dv: float) -> Mps:
     """n(x) = <Iv, f>_v with Iv = dv [1,1]^{(x) Lv} (SI, Integration): each
     v-core summed over its bit; the resulting bond matrix is absorbed into
-    the neighbouring x core.  Returns an Lx-site MPS."""
+    the neighbouring x core.  Returns an Lx-site MPS in the natural bit
+    order (coarsest first) whatever the ordering of f."""
     xs: Mps = []
     pending = None
     for (d, k), A in zip(site_map(Lx, Lv, order), f):
@@ -620,6 +653,8 @@ def density_mps(f: Mps, Lx: int, Lv: int, order: int, dv: float) -> Mps:
             C = A if pending is None else np.tensordot(pending, A, axes=(1, 0))
             pending = None
             xs.append(C)
+    if reversed_dims(order)[0]:
+        xs = reverse_chain(xs)
     xs[0] = xs[0] * dv
     return xs
 

@@ -133,7 +133,7 @@ def test_rank_rule_cases():
     assert mps.rank_rule(np.zeros(3), None, 1e-10) == 1
 
 
-@pytest.mark.parametrize("order", [0, 1])
+@pytest.mark.parametrize("order", [0, 1, 2, 3])
 def test_density_and_moments_equal_dense_riemann_sums(order):
     w = wl.landau_small(L=4, chi=64, tol=0.0)
     p = w.problem
@@ -149,7 +149,7 @@ def test_density_and_moments_equal_dense_riemann_sums(order):
         assert abs(m[k] - d[k]) <= 1e-12 * max(1.0, abs(d[k])), k
 
 
-@pytest.mark.parametrize("order", [0, 1])
+@pytest.mark.parametrize("order", [0, 1, 2, 3])
 def test_untruncated_step_equals_dense(order):
     w = wl.landau_small(L=4, tol=0.0)
     p = w.problem
