@@ -57,7 +57,12 @@ typedef enum {
   MPS_EDEVICE = -4   /* a HIP runtime call failed                      */
 } mps_status;
 
-typedef enum { MPS_ORDER_SEQ = 0, MPS_ORDER_INTERLEAVED = 1 } mps_order;
+typedef enum {
+  MPS_ORDER_SEQ = 0,          /* S1 */
+  MPS_ORDER_INTERLEAVED = 1,  /* IF */
+  MPS_ORDER_S2 = 2,
+  MPS_ORDER_S3 = 3
+} mps_order;
 
 /* Arithmetic of the MPO x MPS contractions (SI, "Matrix-vector
  * multiplication"): FP64, or operands rounded to FP32 (mode 1) or to BF16
@@ -101,8 +106,13 @@ typedef enum {
 } mps_compression;
 
 /* Problem statement.  Site orderings (Fig. 3): MPS_ORDER_SEQ is x bits
- * coarse->fine then v bits coarse->fine (S1); MPS_ORDER_INTERLEAVED is
- * x1, v1, x2, v2, ... (IF; needs Lx == Lv).  Compression level (SI,
+ * coarse->fine then v bits coarse->fine (S1); MPS_ORDER_S2 is x bits
+ * fine->coarse then v bits coarse->fine; MPS_ORDER_S3 is x bits
+ * coarse->fine then v bits fine->coarse; MPS_ORDER_INTERLEAVED is
+ * x1, v1, x2, v2, ... (IF; needs Lx == Lv).  The ordering only changes how
+ * the grid maps to the chain: mps_to_dense, the moments and the field are
+ * on the grid in every ordering, and mps_get_cores / mps_set_cores use
+ * chain order.  Compression level (SI,
  * compression levels C1..C5): the final state (P1), the stage states (P2),
  * the sum of the k's (P3), each k (P4) and each term of a k (P5) are all
  * truncated with `tol`; level l additionally caps P1..Pl at chi_max. */

@@ -19,6 +19,20 @@
 
 namespace mpsv {
 
+std::vector<std::pair<int, int>> site_list(int Lx, int Lv, int order) {
+  std::vector<std::pair<int, int>> sites;
+  if (order == 1) {
+    for (int k = 0; k < std::min(Lx, Lv); ++k) {
+      sites.push_back({0, k});
+      sites.push_back({1, k});
+    }
+    return sites;
+  }
+  for (int k = 0; k < Lx; ++k) sites.push_back({0, order == 2 ? Lx - 1 - k : k});
+  for (int k = 0; k < Lv; ++k) sites.push_back({1, order == 3 ? Lv - 1 - k : k});
+  return sites;
+}
+
 // ============================================================ host operators
 namespace ops {
 
@@ -382,52 +396,72 @@ HostMpo mpo_add(const HostMpo& A, const std::vector<int>& ba, const HostMpo& B,
   return W;
 }
 
-// Full-chain tensor for P physical values per site (4: MPO, 2: MPS).
+// Full-chain tensor for P physical values per site (4: MPO, 2: MPS).  A
+// dimension read fine to coarse (S2: x, S3: v) takes its cores in reverse
+// order with their two bonds swapped.
 static HostMpo chain_generic(const HostMpo& Wx, const std::vector<int>& bx,
                              const HostMpo& Wv, const std::vector<int>& bv,
                              int order, int P, std::vector<int>& bonds) {
   const int Lx = (int)Wx.size(), Lv = (int)Wv.size();
-  std::vector<std::pair<int, int>> sites;  // (0 = x / 1 = v, k)
-  if (order == 0) {
-    for (int k = 0; k < Lx; ++k) sites.push_back({0, k});
-    for (int k = 0; k < Lv; ++k) sites.push_back({1, k});
-  } else {
-    if (Lx != Lv) throw Error(kEinval, "interleaved ordering needs Lx == Lv");
-    for (int k = 0; k < Lx; ++k) {
-      sites.push_back({0, k});
-      sites.push_back({1, k});
-    }
-  }
+  if (order == 1 && Lx != Lv)
+    throw Error(kEinval, "interleaved ordering needs Lx == Lv");
+  const auto sites = site_list(Lx, Lv, order);
   HostMpo out;
   bonds.assign(1, 1);
   int cx = 1, cv = 1;
   for (auto& st : sites) {
     const int k = st.second;
-    if (st.first == 0) {
-      const int l = bx[k], r = bx[k + 1], d = cv;
+    const bool isx = st.first == 0;
+    const bool rev = isx ? order == 2 : order == 3;
+    const std::vector<double>& W = isx ? Wx[k] : Wv[k];
+    const std::vector<int>& bd = isx ? bx : bv;
+    const int l0 = bd[k], r0 = bd[k + 1];
+    const int l = rev ? r0 : l0, r = rev ? l0 : r0;
+    auto val = [&](int a, int p, int b) {
+      return rev ? W[((size_t)b * P + p) * r0 + a] : W[((size_t)a * P + p) * r0 + b];
+    };
+    if (isx) {
+      const int d = cv;
       std::vector<double> T((size_t)l * d * P * r * d, 0.0);
       for (int a = 0; a < l; ++a)
         for (int c = 0; c < d; ++c)
           for (int p = 0; p < P; ++p)
             for (int b = 0; b < r; ++b)
-              T[(((size_t)(a * d + c) * P + p) * r + b) * d + c] =
-                  Wx[k][((size_t)a * P + p) * r + b];
+              T[(((size_t)(a * d + c) * P + p) * r + b) * d + c] = val(a, p, b);
       out.push_back(std::move(T));
       bonds.push_back(r * d);
       cx = r;
     } else {
-      const int l = bv[k], r = bv[k + 1], d = cx;
+      const int d = cx;
       std::vector<double> T((size_t)d * l * P * d * r, 0.0);
       for (int c = 0; c < d; ++c)
         for (int a = 0; a < l; ++a)
           for (int p = 0; p < P; ++p)
             for (int b = 0; b < r; ++b)
-              T[(((size_t)(c * l + a) * P + p) * d + c) * r + b] =
-                  Wv[k][((size_t)a * P + p) * r + b];
+              T[(((size_t)(c * l + a) * P + p) * d + c) * r + b] = val(a, p, b);
       out.push_back(std::move(T));
       bonds.push_back(d * r);
       cv = r;
     }
+  }
+  return out;
+}
+
+HostMpo reverse(const HostMpo& W, const std::vector<int>& bonds, int P,
+                std::vector<int>& out_bonds) {
+  const int L = (int)W.size();
+  HostMpo out(L);
+  out_bonds.assign(L + 1, 1);
+  for (int j = 0; j < L; ++j) {
+    const int k = L - 1 - j;
+    const int l0 = bonds[k], r0 = bonds[k + 1];
+    out[j].assign(W[k].size(), 0.0);
+    for (int a = 0; a < l0; ++a)
+      for (int p = 0; p < P; ++p)
+        for (int b = 0; b < r0; ++b)
+          out[j][((size_t)b * P + p) * l0 + a] = W[k][((size_t)a * P + p) * r0 + b];
+    out_bonds[j] = r0;
+    out_bonds[j + 1] = l0;
   }
   return out;
 }
@@ -506,8 +540,8 @@ void Engine::arena_bytes(size_t reserved[7], size_t peak[7]) const {
 Engine::Engine(const Problem& p) : p_(p), chunk_(memory_model(p).chunk) {
   MPSV_CHECK(p.Lx >= 2 && p.Lx <= 14 && p.Lv >= 2 && p.Lv <= 14, kEinval,
              "Lx and Lv must lie in [2, 14]");
-  MPSV_CHECK(p.order == 0 || p.order == 1, kEinval, "unknown ordering");
-  MPSV_CHECK(p.order == 0 || p.Lx == p.Lv, kEinval,
+  MPSV_CHECK(p.order >= 0 && p.order <= 3, kEinval, "unknown ordering");
+  MPSV_CHECK(p.order != 1 || p.Lx == p.Lv, kEinval,
              "interleaved ordering needs Lx == Lv");
   MPSV_CHECK(p.x_max > p.x_min && p.v_max > p.v_min, kEinval,
              "empty x or v interval");
@@ -525,7 +559,7 @@ Engine::Engine(const Problem& p) : p_(p), chunk_(memory_model(p).chunk) {
   MPSV_CHECK(std::isfinite(p.qm), kEinval, "q/m must be finite");
   MPSV_CHECK(p.compression == 0 || p.compression == 1, kEinval,
              "unknown compression scheme");
-  MPSV_CHECK(p.compression == 0 || p.order == 0, kEinval,
+  MPSV_CHECK(p.compression == 0 || p.order != 1, kEinval,
              "centre-first compression needs a sequential ordering");
 
   MPSV_HIP(hipGetDevice(&device_));
@@ -557,6 +591,12 @@ Engine::Engine(const Problem& p) : p_(p), chunk_(memory_model(p).chunk) {
   auto G = ops::poisson_g(p.Lx, p.dx(), -1.0, bg);  // E = -G n
   gneg_ = upload_mpo(G, bg, ops_, s);
   auto Dv = ops::d1_zero_gradient(p.Lv, p.dv(), bdv);
+  if (p.order == 3) {
+    // v read fine to coarse (S3): Dv in chain order
+    std::vector<int> brev;
+    Dv = ops::reverse(Dv, bdv, 4, brev);
+    bdv = brev;
+  }
   dv_ = upload_mpo(Dv, bdv, ops_, s);
 
   // moment weights 1(x) w(v), w = 1, v, v^2/2 as full-chain MPS
@@ -996,6 +1036,19 @@ DMps Engine::add_terms(const std::vector<std::pair<double, const DMps*>>& terms,
   return r;
 }
 
+// The same tensor with the sites in reverse order: core (l, 2, r) ->
+// (r, 2, l), last core first.
+DMps Engine::reverse_mps(const DMps& a, Arena& ar, hipStream_t s) {
+  const size_t L = a.size();
+  DMps out(L);
+  for (size_t j = 0; j < L; ++j) {
+    const Core& A = a[L - 1 - j];
+    out[j] = Core{ar.alloc(A.size()), A.r, A.l};
+    reverse_core(s, A.p, A.l, A.r, out[j].p);
+  }
+  return out;
+}
+
 DMps Engine::copy_mps(const DMps& a, Arena& ar, hipStream_t s) {
   DMps out(a.size());
   for (size_t j = 0; j < a.size(); ++j) {
@@ -1010,17 +1063,7 @@ DMps Engine::copy_mps(const DMps& a, Arena& ar, hipStream_t s) {
 // n(x) = dv * sum_j f(x, v_j): each v core summed over its bit (SI,
 // Integration) and absorbed into the neighbouring x core.
 DMps Engine::density(const DMps& g, Arena& ar, hipStream_t s) {
-  const int Lx = p_.Lx, Lv = p_.Lv;
-  std::vector<std::pair<int, int>> sites;
-  if (p_.order == 0) {
-    for (int k = 0; k < Lx; ++k) sites.push_back({0, k});
-    for (int k = 0; k < Lv; ++k) sites.push_back({1, k});
-  } else {
-    for (int k = 0; k < Lx; ++k) {
-      sites.push_back({0, k});
-      sites.push_back({1, k});
-    }
-  }
+  const auto sites = site_list(p_.Lx, p_.Lv, p_.order);
   DMps xs;
   double* pend = nullptr;
   int pl = 0, pr = 0;
@@ -1064,6 +1107,8 @@ DMps Engine::density(const DMps& g, Arena& ar, hipStream_t s) {
       xs.push_back(C);
     }
   }
+  // x read fine to coarse (S2): back to the natural bit order
+  if (p_.order == 2) xs = reverse_mps(xs, ar, s);
   // fold dv into the first core
   copy2d(s, 1, (int)xs[0].size(), p_.dv(), xs[0].p, xs[0].size(), xs[0].p,
          xs[0].size());
@@ -1080,27 +1125,19 @@ DMps Engine::field(const DMps& g, Arena& ar, hipStream_t s) {
 }
 
 // Full-chain MPO of -(q/m) diag(E) (x) Dv (SI, Dot Product).
-DMpo Engine::t2_mpo(const DMps& E, Arena& ar, hipStream_t s) {
-  const int Lx = p_.Lx, Lv = p_.Lv;
-  std::vector<std::pair<int, int>> sites;
-  if (p_.order == 0) {
-    for (int k = 0; k < Lx; ++k) sites.push_back({0, k});
-    for (int k = 0; k < Lv; ++k) sites.push_back({1, k});
-  } else {
-    for (int k = 0; k < Lx; ++k) {
-      sites.push_back({0, k});
-      sites.push_back({1, k});
-    }
-  }
+DMpo Engine::t2_mpo(const DMps& En, Arena& ar, hipStream_t s) {
+  const auto sites = site_list(p_.Lx, p_.Lv, p_.order);
+  // E (natural bit order) and Dv (held in chain order) as visited
+  const DMps E = (p_.order == 2) ? reverse_mps(En, ar, s) : En;
   DMpo W(sites.size());
-  int cx = 1, cv = 1;
+  int cx = 1, cv = 1, ix = 0, iv = 0;
   for (size_t j = 0; j < sites.size(); ++j) {
-    const int k = sites[j].second;
     MpoSite& m = W[j];
     if (sites[j].first == 0) {
-      const Core& e = E[k];
+      const Core& e = E[ix];
       double* Wd = ar.alloc((size_t)e.l * 4 * e.r);
-      diag_mpo_site(s, e.p, e.l, e.r, k == 0 ? -p_.qm : 1.0, Wd);
+      diag_mpo_site(s, e.p, e.l, e.r, ix == 0 ? -p_.qm : 1.0, Wd);
+      ++ix;
       if (cv == 1) {
         m.W = Wd;
       } else {
@@ -1111,7 +1148,7 @@ DMpo Engine::t2_mpo(const DMps& E, Arena& ar, hipStream_t s) {
       m.wr = e.r * cv;
       cx = e.r;
     } else {
-      const MpoSite& d = dv_[k];
+      const MpoSite& d = dv_[iv++];
       if (cx == 1) {
         m.W = d.W;
       } else {
@@ -1298,9 +1335,11 @@ void Engine::init_from_profiles(int rank, const double* ax, const double* bv,
       DMps mx = tt(ax + (long)r * p_.Nx(), p_.Lx);
       DMps mv = tt(bv + (long)r * p_.Nv(), p_.Lv);
       DMps full;
-      if (p_.order == 0) {
-        full = mx;
-        full.insert(full.end(), mv.begin(), mv.end());
+      if (p_.order != 1) {
+        // sequential: a dimension read fine to coarse enters reversed
+        full = (p_.order == 2) ? reverse_mps(mx, step_, s) : mx;
+        const DMps v = (p_.order == 3) ? reverse_mps(mv, step_, s) : mv;
+        full.insert(full.end(), v.begin(), v.end());
       } else {
         int cx = 1, cv = 1;
         for (int k = 0; k < p_.Lx; ++k) {
@@ -1413,7 +1452,10 @@ void Engine::to_dense(double* out, hipStream_t s) {
     ArenaScope sc(tmp_);
     double* v = tmp_.alloc((size_t)1 << n());
     dense_of(f_, v, s);
-    deinterleave(s, v, p_.Lx, out);
+    if (p_.order == 1)
+      deinterleave(s, v, p_.Lx, out);
+    else
+      chain_to_grid(s, v, p_.Lx, p_.Lv, p_.order == 2, p_.order == 3, out);
   }
 }
 

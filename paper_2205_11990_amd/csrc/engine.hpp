@@ -26,6 +26,12 @@ struct Problem {
   double dv() const { return (v_max - v_min) / (double)(Nv() - 1); }
 };
 
+// Sites of the chain as (0 = x / 1 = v, bit k; k = 0 the coarsest) for the
+// orderings of Fig. 3: 0 S1 (x then v, both coarse to fine), 1 IF (x1 v1
+// x2 v2 ...), 2 S2 (x fine to coarse, then v), 3 S3 (x, then v fine to
+// coarse).
+std::vector<std::pair<int, int>> site_list(int Lx, int Lv, int order);
+
 // MPS core A[a][s][b], row-major, a < l, s < 2, b < r.
 struct Core {
   double* p = nullptr;
@@ -158,6 +164,7 @@ class Engine {
   DMpo t2_mpo(const DMps& E, Arena& ar, hipStream_t s);
   DMps rhs(const DMps& g, Arena& out, hipStream_t s);
   DMps copy_mps(const DMps& a, Arena& ar, hipStream_t s);
+  DMps reverse_mps(const DMps& a, Arena& ar, hipStream_t s);
   void commit(const DMps& fn, hipStream_t s);
   double full_contract(const DMps& g, const DMps& f, hipStream_t s);
   void dense_of(const DMps& a, double* out, hipStream_t s);
@@ -215,6 +222,9 @@ std::vector<std::vector<double>> poly_mps(int L, double c0, double c1, double c2
                                           std::vector<int>& bonds);
 HostMpo chain(const HostMpo& Wx, const std::vector<int>& bx, const HostMpo& Wv,
               const std::vector<int>& bv, int order, std::vector<int>& bonds);
+// the same chain read from its last site: cores (l, P, r) -> (r, P, l)
+HostMpo reverse(const HostMpo& W, const std::vector<int>& bonds, int P,
+                std::vector<int>& out_bonds);
 }  // namespace ops
 
 }  // namespace mpsv

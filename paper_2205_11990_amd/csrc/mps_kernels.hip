@@ -67,6 +67,37 @@ __global__ void scale_rows_kernel(const double* in, int rows, long len,
   }
 }
 
+// out[b][t][a] = in[a][t][b] for an l x 2 x r core
+__global__ void reverse_core_kernel(const double* in, int l, int r,
+                                    double* out) {
+  const long n = 2L * l * r;
+  GRID_STRIDE(e, n) {
+    const long a = e % l, t = (e / l) % 2, b = e / (2L * l);
+    out[e] = in[(a * 2 + t) * r + b];
+  }
+}
+
+// Chain-order vector of a sequential ordering -> F[i * Nv + j]: the chain
+// position of (i, j) is the x bits then the v bits, each most significant
+// first, or least significant first for a reversed dimension.
+__global__ void chain_to_grid_kernel(const double* in, int Lx, int Lv, int rx,
+                                     int rv, double* out) {
+  const long n = 1L << (Lx + Lv);
+  GRID_STRIDE(e, n) {
+    const long i = e >> Lv, j = e & ((1L << Lv) - 1);
+    long ci = i, cj = j;
+    if (rx) {
+      ci = 0;
+      for (int k = 0; k < Lx; ++k) ci |= ((i >> k) & 1L) << (Lx - 1 - k);
+    }
+    if (rv) {
+      cj = 0;
+      for (int k = 0; k < Lv; ++k) cj |= ((j >> k) & 1L) << (Lv - 1 - k);
+    }
+    out[e] = in[(ci << Lv) | cj];
+  }
+}
+
 __global__ void kron_embed_kernel(const double* A, int l, int P, int r, int d,
                                   int mode, double* out) {
   // out shape (l*d) x P x (r*d); write all entries (zeros off the identity)
@@ -189,6 +220,21 @@ void scale_rows(hipStream_t s, const double* in, int rows, long len,
   if (n <= 0) return;
   hipLaunchKernelGGL(scale_rows_kernel, dim3(grid_for(n)), dim3(256), 0, s, in,
                      rows, len, d, inverse ? 1 : 0, out);
+  MPSV_LAUNCHED();
+}
+
+void reverse_core(hipStream_t s, const double* in, int l, int r, double* out) {
+  const long n = 2L * l * r;
+  hipLaunchKernelGGL(reverse_core_kernel, dim3(grid_for(n)), dim3(256), 0, s,
+                     in, l, r, out);
+  MPSV_LAUNCHED();
+}
+
+void chain_to_grid(hipStream_t s, const double* in, int Lx, int Lv, bool rx,
+                   bool rv, double* out) {
+  const long n = 1L << (Lx + Lv);
+  hipLaunchKernelGGL(chain_to_grid_kernel, dim3(grid_for(n)), dim3(256), 0, s,
+                     in, Lx, Lv, rx ? 1 : 0, rv ? 1 : 0, out);
   MPSV_LAUNCHED();
 }
 

@@ -20,6 +20,15 @@ void sum_physical(hipStream_t s, const double* in, int l, int r, double* out);
 void scale_rows(hipStream_t s, const double* in, int rows, long len,
                 const double* d, bool inverse, double* out);
 
+// out[b][t][a] = in[a][t][b]: an l x 2 x r core read from the right
+void reverse_core(hipStream_t s, const double* in, int l, int r, double* out);
+
+// Chain-order vector of a sequential ordering (x bits, then v bits; a
+// dimension with rx / rv set has its least significant bit first) ->
+// F[i*Nv + j].
+void chain_to_grid(hipStream_t s, const double* in, int Lx, int Lv, bool rx,
+                   bool rv, double* out);
+
 // Embed an operator/core of one dimension into the interleaved chain:
 // A has shape (l, P, r) with P = 2 (MPS core) or 4 (MPO core, (o,i) pairs).
 // mode 0 (A-major): out[(a, c), P, (b, c)]  -- fused index a*d + c

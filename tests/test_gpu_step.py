@@ -34,7 +34,7 @@ def _untruncated(w):
     return w
 
 
-@pytest.mark.parametrize("order,L", [(0, 3), (1, 3), (0, 4), (1, 4)])
+@pytest.mark.parametrize("order,L", [(0, 3), (1, 3), (0, 4), (1, 4), (2, 3), (3, 4)])
 def test_init_equals_dense_profile(B, order, L):
     _say("init order=%d L=%d" % (order, L))
     w = _untruncated(wl.landau_small(L=L))
@@ -46,7 +46,7 @@ def test_init_equals_dense_profile(B, order, L):
     st.free()
 
 
-@pytest.mark.parametrize("order,L", [(0, 3), (1, 3), (0, 4), (1, 4), (0, 5)])
+@pytest.mark.parametrize("order,L", [(0, 3), (1, 3), (0, 4), (1, 4), (0, 5), (2, 4), (3, 4)])
 def test_untruncated_steps_equal_dense_oracle(B, order, L):
     """chi unbounded, tol = 0: the MPS step is the dense finite-difference
     step up to rounding (1e-10 relative after several steps)."""
@@ -101,7 +101,7 @@ def _from_same_state(B, w, steps):
     return G, R, E.cpu().numpy(), Eref, info, f
 
 
-@pytest.mark.parametrize("order", [0, 1])
+@pytest.mark.parametrize("order", [0, 1, 2, 3])
 def test_truncated_landau_matches_mps_oracle(B, order):
     """64 x 64 Landau, chi = 16, tol = 1e-10 (C1): reconstructed f and E
     within 1e-8 of the CPU MPS oracle after 3 steps from the same state."""
@@ -134,10 +134,12 @@ def test_truncated_fixed_chi_level5_matches_mps_oracle(B):
     st.free()
 
 
-def test_moments_match_oracle(B):
-    _say("moments")
+@pytest.mark.parametrize("order", [0, 2, 3])
+def test_moments_match_oracle(B, order):
+    _say("moments order=%d" % order)
     w = wl.landau_small(L=6, chi=16, tol=1e-10)
     p = w.problem
+    p.order = order
     st = B.MpsState(p, w.ax, w.bv)
     st.step(2)
     f = st.get_cores_host()
@@ -425,13 +427,13 @@ def test_untruncated_centre_first_steps_equal_dense_oracle(B, L):
     st.free()
 
 
-@pytest.mark.parametrize("scheme", [0, 1])
-def test_truncated_centre_first_matches_mps_oracle(B, scheme):
+@pytest.mark.parametrize("scheme,order", [(0, 0), (1, 0), (0, 2), (0, 3)])
+def test_truncated_centre_first_matches_mps_oracle(B, scheme, order):
     """Centre-first compression with every point capped (C5, chi = 8,
     perturbed two-stream state), central and upwind x advection: f and E
     within 1e-8 of the CPU MPS oracle after 2 steps, same bonds."""
-    _say("truncated centre-first C5 chi8 two-stream L=5 scheme=%d" % scheme)
-    w = wl.two_stream(L=5, chi=8, tol=0.0, level=5, df_max=4, dt_cfg=0.05, order=0)
+    _say("truncated centre-first C5 chi8 two-stream L=5 scheme=%d order=%d" % (scheme, order))
+    w = wl.two_stream(L=5, chi=8, tol=0.0, level=5, df_max=4, dt_cfg=0.05, order=order)
     p = w.problem
     p.compression = 1
     p.x_scheme = scheme
@@ -461,3 +463,28 @@ def test_centre_first_needs_a_sequential_ordering(B):
     p.compression = 1
     with pytest.raises(B.MpsError):
         B.MpsState(p, w.ax, w.bv)
+
+
+@pytest.mark.parametrize("order", [2, 3])
+def test_untruncated_s2_s3_on_an_unequal_grid_equal_dense_oracle(B, order):
+    """S2 / S3 orderings (Fig. 3) on a 32 x 16 grid, chi unbounded, tol = 0:
+    f, n and E equal the dense steps; the exported cores equal the oracle's
+    chain layout (the same vector under its site map)."""
+    _say("untruncated order=%d Lx=5 Lv=4" % order)
+    w = _untruncated(wl.landau_small(L=5, Lv=4))
+    p = w.problem
+    p.order = order
+    st = B.MpsState(p, w.ax, w.bv)
+    F = odense.initial(w.ax, w.bv)
+    for k in range(3):
+        st.step(1)
+        F = odense.rk4_step(F, p)
+    G = st.to_dense().cpu().numpy()
+    assert np.abs(G - F).max() <= 1e-11 * np.abs(F).max()
+    n, E = st.density_field()
+    Ed = odense.field(F, p)
+    assert np.abs(E.cpu().numpy() - Ed).max() <= 1e-10 * np.abs(Ed).max()
+    assert np.abs(n.cpu().numpy() - odense.density(F, p.dv)).max() <= 1e-12 * np.abs(odense.density(F, p.dv)).max()
+    vec = omps.to_vector(st.get_cores_host())
+    assert np.abs(vec - omps.dense_to_sites(F, p.Lx, p.Lv, order)).max() <= 1e-11 * np.abs(F).max()
+    st.free()
