@@ -246,6 +246,33 @@ def chi128_run(binding, steps):
     return out
 
 
+def orderings(binding, steps):
+    """The fixed-chi workload in the sequential orderings S1, S2, S3 (Fig. 3)
+    and with centre-first compression (SI, Modified Compression Scheme):
+    steps/s from a perturbed state, the x|v cut's entanglement entropy and
+    the largest bond after the timed steps."""
+    import torch
+    out = {}
+    for name, order, comp in (("S1", 0, 0), ("S2", 2, 0), ("S3", 3, 0),
+                              ("S1_centre_first", 0, 1), ("S2_centre_first", 2, 1)):
+        w = make_workload("fixed")
+        p = w.problem
+        p.order, p.compression = order, comp
+        st = start_state(binding, w, "fixed")
+        st.step(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st.step(steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        ee = st.entanglement()
+        out[name] = {"steps_per_s": steps / el, "steps": steps,
+                     "ee_xv_cut": float(ee[p.Lx - 1]),
+                     "max_bond": int(max(st.info()["bonds"]))}
+        st.free()
+    return out
+
+
 def batched(binding, count, steps):
     """Aggregate steps/s of a parameter sweep stepped together, against the
     same instances stepped one after the other."""
@@ -400,6 +427,8 @@ def main():
         print("[bench] mixed %s" % json.dumps(extras["mixed"]), file=sys.stderr, flush=True)
         extras["chi128"] = chi128_run(binding, 3)
         print("[bench] chi128 %s" % json.dumps(extras["chi128"]), file=sys.stderr, flush=True)
+        extras["orderings"] = orderings(binding, 3)
+        print("[bench] orderings %s" % json.dumps(extras["orderings"]), file=sys.stderr, flush=True)
         extras["batched"] = batched(binding, 64, 3)
         print("[bench] batched %s" % json.dumps(extras["batched"]), file=sys.stderr, flush=True)
         extras["serving"] = serving_run(binding, 24, 20)
