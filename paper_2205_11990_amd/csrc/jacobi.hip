@@ -7,10 +7,15 @@
 // The rotations themselves are not accumulated: the caller forms the left
 // factor as X V (one GEMM), so the kernel keeps only B on chip.
 //
-// Layout: the columns are held in registers.  A node is one DPP row of 16
-// lanes; it owns two columns (a, b), 16 * RPT rows each, RPT per lane.  Each
-// step orthogonalises the pair of every node at once (inner products
-// reduced with row-local DPP moves), then columns move between nodes.
+// Layout: the columns are held in registers.  A node is an aligned group of
+// NL lanes (8 above 32 columns, 16 below); it owns two columns (a, b),
+// NL * RPT rows each, RPT per lane.  Each step orthogonalises the pair of
+// every node at once (inner products reduced with DPP moves inside the
+// group), then columns move between nodes.  With 8-lane nodes a 128-column
+// factor takes 8 waves (two per SIMD) and the per-pair work of a step (the
+// reduction, the angle, the moves) is shared by 16 rows per lane: a sweep
+// at 128 columns takes 0.093 ms against 0.104 with 16-lane nodes and 0.104
+// with 4-lane nodes (one wave per SIMD, no latency hiding).
 //
 // Ordering: a hypercube ordering of the N = 2^d nodes that meets every pair
 // exactly once per sweep in 2N - 1 steps, built recursively: pair all
@@ -18,12 +23,12 @@
 // top dimension so that every node holds one column of each half, then
 // let the second columns walk through the cube along a Gray code (one
 // dimension per step), which brings every column of one half next to every
-// column of the other.  Node bits 0 and 1 select the DPP row inside a wave,
-// so moves along those dimensions are lane permutations inside the wave
+// column of the other.  The low log2(64 / NL) node bits select lanes
+// inside a wave, so moves along those dimensions are lane permutations
 // (ds_swizzle / ds_bpermute through the LDS crossbar, which leaves the
 // vector ALU free); only moves along the wave bits go through LDS memory,
-// with a barrier.  At 128 columns 96 of the 126 moves of a sweep stay
-// inside the waves.
+// with a barrier.  At 128 columns and 8-lane nodes 112 of the 126 moves of
+// a sweep stay inside the waves.
 //
 // Squared column norms are carried with the columns and updated with each
 // rotation.  Columns below 1e-15 of the Frobenius norm are numerical zeros
@@ -110,55 +115,101 @@ struct Col {
   int id;
 };
 
-// The column `send` of node x goes to node x ^ (1 << dim); returns the one
-// arriving from there.  Along wave bits it passes through the LDS buffer
-// `xb` (one barrier), along row bits through registers.
-template <int DIM, int RPT>
-__device__ inline void swap_rows(const Col<RPT>& send, Col<RPT>& recv) {
-#pragma unroll
-  for (int r = 0; r < RPT; ++r) recv.v[r] = row_swap<DIM>(send.v[r]);
-  recv.n = row_swap<DIM>(send.n);
-  recv.id = row_swap<DIM>(send.id);
+// Value of lane (lane ^ LX) for LX in {4, 8, 16, 32}: ds_swizzle in bit mode
+// (and mask 0x1f, xor mask LX) inside each half-wave, ds_bpermute across
+// the halves.  Both go through the LDS crossbar and leave the vector ALU
+// free.
+template <int LX>
+__device__ inline int lane_swap(int v) {
+  static_assert(LX == 4 || LX == 8 || LX == 16 || LX == 32, "lane xor 4 .. 32");
+  if constexpr (LX < 32) {
+    return __builtin_amdgcn_ds_swizzle(v, 0x1F | (LX << 10));
+  } else {
+    const int lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+    return __builtin_amdgcn_ds_bpermute((lane ^ 32) << 2, v);
+  }
 }
 
-template <int RPT>
+template <int LX>
+__device__ inline double lane_swap(double v) {
+  const int lo = lane_swap<LX>(__double2loint(v));
+  const int hi = lane_swap<LX>(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
+template <int LX, int RPT>
+__device__ inline void swap_lanes(const Col<RPT>& send, Col<RPT>& recv) {
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) recv.v[r] = lane_swap<LX>(send.v[r]);
+  recv.n = lane_swap<LX>(send.n);
+  recv.id = lane_swap<LX>(send.id);
+}
+
+// Sum over the NL lanes of a node (aligned groups of 4, 8 or 16 lanes).
+template <int NL>
+__device__ inline double node_sum(double v) {
+  if constexpr (NL == 16) return wave::sum16(v);
+  else if constexpr (NL == 8) return wave::sum8(v);
+  else return wave::sum4(v);
+}
+
+// The column `send` of node x goes to node x ^ (1 << dim); returns the one
+// arriving from there.  Nodes of NL lanes: the low log2(64 / NL) node bits
+// select lanes of one wave (lane xor NL << dim, through the crossbar); the
+// others select waves, and the column passes through the LDS buffer `xb`
+// (one barrier).
+template <int RPT, int NL>
 __device__ inline void exchange(const Col<RPT>& send, Col<RPT>& recv, int dim,
-                                int x, int row, int lig, int N, int& par,
-                                double* xb, double* xn, int* xi) {
+                                int x, int lig, int N, int& par, double* xb,
+                                double* xn, int* xi) {
   if (dim == 0) {
-    swap_rows<0, RPT>(send, recv);
+    swap_lanes<NL, RPT>(send, recv);
     return;
   }
   if (dim == 1) {
-    swap_rows<1, RPT>(send, recv);
+    swap_lanes<2 * NL, RPT>(send, recv);
     return;
+  }
+  if constexpr (NL <= 8) {
+    if (dim == 2) {
+      swap_lanes<4 * NL, RPT>(send, recv);
+      return;
+    }
+  }
+  if constexpr (NL == 4) {
+    if (dim == 3) {
+      swap_lanes<32, RPT>(send, recv);
+      return;
+    }
   }
   const int pb = par;
   par ^= 1;
-  double* dst = xb + (long)(pb * N + x) * RPT * 16;
+  double* dst = xb + (long)(pb * N + x) * RPT * NL;
 #pragma unroll
-  for (int r = 0; r < RPT; ++r) dst[r * 16 + lig] = send.v[r];
+  for (int r = 0; r < RPT; ++r) dst[r * NL + lig] = send.v[r];
   if (lig == 0) {
     xn[pb * 64 + x] = send.n;
     xi[pb * 64 + x] = send.id;
   }
   __syncthreads();
   const int y = x ^ (1 << dim);
-  const double* src = xb + (long)(pb * N + y) * RPT * 16;
+  const double* src = xb + (long)(pb * N + y) * RPT * NL;
 #pragma unroll
-  for (int r = 0; r < RPT; ++r) recv.v[r] = src[r * 16 + lig];
+  for (int r = 0; r < RPT; ++r) recv.v[r] = src[r * NL + lig];
   recv.n = xn[pb * 64 + y];
   recv.id = xi[pb * 64 + y];
 }
 
 // info: [0] D, [1] discarded weight, [2] sweeps, [3] converged, [4] steps
 // Xr: k x k row-major triangular factor; the Jacobi columns are its rows.
-// Output Vt[d][i] = column perm(d) / sigma_d.
-template <int RPT>
-__global__ __launch_bounds__(MAXT) void jacobi_hc_kernel(
+// Output Vt[d][i] = column perm(d) / sigma_d.  Nodes of NL lanes, RPT rows
+// per lane (NL * RPT >= k).
+template <int RPT, int NL>
+__global__ __launch_bounds__(64 * NL) void jacobi_hc_kernel(
     const double* __restrict__ Xr, int k, long ldx, int d, int max_sweeps,
     int cap, double tol, double* __restrict__ Vt, double* __restrict__ sigbuf,
     int* __restrict__ perm_out, double* __restrict__ info) {
+  static_assert(NL == 4 || NL == 8 || NL == 16, "nodes of 4, 8 or 16 lanes");
   extern __shared__ double smem[];
   __shared__ double red[MAXT / 64];
   __shared__ double xn[2 * 64];
@@ -166,7 +217,7 @@ __global__ __launch_bounds__(MAXT) void jacobi_hc_kernel(
   __shared__ int sweep_any;
   __shared__ int Dsh;
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int x = tid >> 4, lig = tid & 15, row = x & 3;
+  const int x = tid / NL, lig = tid % NL;
   const int N = 1 << d;
 
   // node x starts with columns 2x and 2x+1; indices >= k are zero padding
@@ -176,14 +227,14 @@ __global__ __launch_bounds__(MAXT) void jacobi_hc_kernel(
   double sa = 0.0, sb = 0.0;
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
-    const int i = lig + 16 * r;
+    const int i = lig + NL * r;
     A.v[r] = (A.id < k && i < k) ? Xr[(long)A.id * ldx + i] : 0.0;
     B.v[r] = (B.id < k && i < k) ? Xr[(long)B.id * ldx + i] : 0.0;
     sa = fma(A.v[r], A.v[r], sa);
     sb = fma(B.v[r], B.v[r], sb);
   }
-  A.n = wave::sum16(sa);
-  B.n = wave::sum16(sb);
+  A.n = node_sum<NL>(sa);
+  B.n = node_sum<NL>(sb);
   // Frobenius norm of the whole matrix; the columns are scaled to unit
   // Frobenius norm (undone on the singular values at the end), so that the
   // products below neither overflow nor underflow
@@ -212,46 +263,50 @@ __global__ __launch_bounds__(MAXT) void jacobi_hc_kernel(
   // stagnate at rounding level near the numerical null space.
   const double eps2 = 1e-28, conv2 = 1e-16;
 
-  // Squared norms follow the rotation by formula; where one of them falls
-  // below 1e-8 of the pair's total (its rounding error could then exceed
-  // 1e-8 of it) the column norms are recomputed instead.
-  auto pair_step = [&]() {
+  // One step on the pair (P, Q) of every node.  The update is skipped by
+  // the whole wave when none of its nodes rotates (a scalar branch); inside
+  // it, nodes that do not rotate apply cs = 1, sn = 0, which leaves their
+  // columns and norms exactly unchanged.  Squared norms follow the rotation
+  // by formula; where one of them falls below 1e-8 of the pair's total (its
+  // rounding error could then exceed 1e-8 of it) the norms are recomputed.
+  auto pair_step = [&](Col<RPT>& P, Col<RPT>& Q) __attribute__((always_inline)) {
     // four independent partial sums shorten the dependency chain
     double gp[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int r = 0; r < RPT; ++r) gp[r & 3] = fma(A.v[r], B.v[r], gp[r & 3]);
-    const double g = wave::sum16((gp[0] + gp[1]) + (gp[2] + gp[3]));
-    const double ab = A.n * B.n, g2 = g * g;
-    const bool rot = g2 > eps2 * ab && fmin(A.n, B.n) > negl;
-    if (rot) {  // uniform over the 16 lanes of the node
-      double cs, sn;
-      rotation(A.n, B.n, g, cs, sn);
+    for (int r = 0; r < RPT; ++r) gp[r & 3] = fma(P.v[r], Q.v[r], gp[r & 3]);
+    const double g = node_sum<NL>((gp[0] + gp[1]) + (gp[2] + gp[3]));
+    const double ab = P.n * Q.n, g2 = g * g;
+    const bool rot = g2 > eps2 * ab && fmin(P.n, Q.n) > negl;
+    if (__builtin_amdgcn_ballot_w64(rot) == 0) return;
+    double cs, sn;
+    rotation(P.n, Q.n, g, cs, sn);
+    cs = rot ? cs : 1.0;
+    sn = rot ? sn : 0.0;
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const double u = P.v[r], v = Q.v[r];
+      P.v[r] = cs * u - sn * v;
+      Q.v[r] = sn * u + cs * v;
+    }
+    // the new squared norms of the rotated pair, exact in exact arithmetic
+    // for the cs, sn applied
+    const double c2 = cs * cs, s2 = sn * sn, csg = 2.0 * cs * sn * g;
+    const double na = fma(c2, P.n, fma(s2, Q.n, -csg));
+    const double nb = fma(s2, P.n, fma(c2, Q.n, csg));
+    if (rot && fmin(na, nb) < 1e-8 * (P.n + Q.n)) {
+      double sa2 = 0.0, sb2 = 0.0;
 #pragma unroll
       for (int r = 0; r < RPT; ++r) {
-        const double u = A.v[r], v = B.v[r];
-        A.v[r] = cs * u - sn * v;
-        B.v[r] = sn * u + cs * v;
+        sa2 = fma(P.v[r], P.v[r], sa2);
+        sb2 = fma(Q.v[r], Q.v[r], sb2);
       }
-      // the new squared norms of the rotated pair, exact in exact
-      // arithmetic for the cs, sn applied
-      const double c2 = cs * cs, s2 = sn * sn, csg = 2.0 * cs * sn * g;
-      const double na = fma(c2, A.n, fma(s2, B.n, -csg));
-      const double nb = fma(s2, A.n, fma(c2, B.n, csg));
-      if (fmin(na, nb) < 1e-8 * (A.n + B.n)) {
-        double sa2 = 0.0, sb2 = 0.0;
-#pragma unroll
-        for (int r = 0; r < RPT; ++r) {
-          sa2 = fma(A.v[r], A.v[r], sa2);
-          sb2 = fma(B.v[r], B.v[r], sb2);
-        }
-        A.n = wave::sum16(sa2);
-        B.n = wave::sum16(sb2);
-      } else {
-        A.n = na;
-        B.n = nb;
-      }
-      if (lig == 0 && g2 > conv2 * ab) sweep_any = 1;
+      P.n = node_sum<NL>(sa2);
+      Q.n = node_sum<NL>(sb2);
+    } else {
+      P.n = na;
+      Q.n = nb;
     }
+    if (rot && lig == 0 && g2 > conv2 * ab) sweep_any = 1;
   };
 
   double* xb = smem;
@@ -261,7 +316,7 @@ __global__ __launch_bounds__(MAXT) void jacobi_hc_kernel(
   for (; sweep < max_sweeps; ++sweep) {
     if (tid == 0) sweep_any = 0;
     __syncthreads();
-    pair_step();
+    pair_step(A, B);
     ++steps;
     for (int l = 1; l <= d; ++l) {
       // across dimension l-1: nodes of the lower half give b, those of the
@@ -269,15 +324,25 @@ __global__ __launch_bounds__(MAXT) void jacobi_hc_kernel(
       // upper-half columns everywhere
       const int dim = l - 1;
       const bool up = (x >> dim) & 1;
-      exchange<RPT>(up ? A : B, R, dim, x, row, lig, N, par, xb, xn, xi);
+      exchange<RPT, NL>(up ? A : B, R, dim, x, lig, N, par, xb, xn, xi);
       if (up) A = R; else B = R;
-      pair_step();
+      pair_step(A, B);
       ++steps;
-      // the b columns walk along a Gray code over the l lower dimensions
-      for (int t = 1; t < (1 << l); ++t) {
-        exchange<RPT>(B, R, __builtin_ctz(t), x, row, lig, N, par, xb, xn, xi);
+      // the b columns walk along a Gray code over the l lower dimensions;
+      // two moves per iteration let B and R trade roles without copies
+      const int last = (1 << l) - 1;
+      int t = 1;
+      for (; t + 1 <= last; t += 2) {
+        exchange<RPT, NL>(B, R, __builtin_ctz(t), x, lig, N, par, xb, xn, xi);
+        pair_step(A, R);
+        exchange<RPT, NL>(R, B, __builtin_ctz(t + 1), x, lig, N, par, xb, xn, xi);
+        pair_step(A, B);
+        steps += 2;
+      }
+      if (t == last) {
+        exchange<RPT, NL>(B, R, __builtin_ctz(t), x, lig, N, par, xb, xn, xi);
         B = R;
-        pair_step();
+        pair_step(A, B);
         ++steps;
       }
     }
@@ -296,7 +361,7 @@ __global__ __launch_bounds__(MAXT) void jacobi_hc_kernel(
   double* M = smem;
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
-    const int i = lig + 16 * r;
+    const int i = lig + NL * r;
     if (i < k) {
       if (A.id < k) M[(long)A.id * lda + i] = A.v[r] / scale;
       if (B.id < k) M[(long)B.id * lda + i] = B.v[r] / scale;
@@ -310,8 +375,8 @@ __global__ __launch_bounds__(MAXT) void jacobi_hc_kernel(
       sa2 = fma(A.v[r], A.v[r], sa2);
       sb2 = fma(B.v[r], B.v[r], sb2);
     }
-    sa2 = wave::sum16(sa2);
-    sb2 = wave::sum16(sb2);
+    sa2 = node_sum<NL>(sa2);
+    sb2 = node_sum<NL>(sb2);
     const double inv = 1.0 / scale;
     if (lig == 0) {
       if (A.id < k) sigbuf[k + A.id] = sqrt(sa2) * inv;
@@ -758,16 +823,30 @@ __global__ __launch_bounds__(16 << (NLOG - GLOG)) void jacobi_multi_kernel(
   }
 }
 
+// One-workgroup layout for k columns: 2^d nodes of nl lanes, rpt rows per
+// lane (nl * rpt = 32, 64 or 128 rows).  Above 32 columns nodes are
+// narrower than a 16-lane row: with nl lanes the per-pair work of a step
+// (the reduction, the rotation angle, the column moves) is shared by
+// 128 / nl rows per lane, fewer waves share each SIMD, and log2(64 / nl)
+// node bits stay inside a wave.  MPSV_JACOBI_NODE_LANES (4, 8 or 16)
+// overrides the default for timing.
 struct Shape {
-  int d, nodes, rpt;
+  int d, nodes, rpt, nl;
 };
 
 Shape shape_of(int k) {
+  static const int lanes = [] {
+    const char* e = std::getenv("MPSV_JACOBI_NODE_LANES");
+    const int v = e ? std::atoi(e) : 8;
+    return (v == 4 || v == 16) ? v : 8;
+  }();
   Shape s;
   s.d = 2;
   while ((1 << s.d) * 2 < k) ++s.d;
   s.nodes = 1 << s.d;
-  s.rpt = k <= 32 ? 2 : (k <= 64 ? 4 : 8);
+  const int rows = k <= 32 ? 32 : (k <= 64 ? 64 : 128);
+  s.nl = k <= 32 ? 16 : lanes;
+  s.rpt = rows / s.nl;
   return s;
 }
 
@@ -843,7 +922,7 @@ size_t jacobi_lds_bytes(int k) {
     default: break;
   }
   const Shape s = shape_of(k);
-  const size_t xch = (size_t)2 * s.nodes * 16 * s.rpt;
+  const size_t xch = (size_t)2 * s.nodes * s.nl * s.rpt;
   const size_t cols = (size_t)k * (size_t)(k | 1);
   return (xch > cols ? xch : cols) * sizeof(double);
 }
@@ -862,15 +941,16 @@ void jacobi_svd(hipStream_t s, const double* Xr, int k, long ldx, int cap,
                 int* perm, double* info, double* ws) {
   static std::once_flag once;
   std::call_once(once, [] {
-    MPSV_HIP(hipFuncSetAttribute((const void*)jacobi_hc_kernel<2>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)kJacobiMaxLds));
-    MPSV_HIP(hipFuncSetAttribute((const void*)jacobi_hc_kernel<4>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)kJacobiMaxLds));
-    MPSV_HIP(hipFuncSetAttribute((const void*)jacobi_hc_kernel<8>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)kJacobiMaxLds));
+    const void* fns[] = {(const void*)jacobi_hc_kernel<2, 16>,
+                         (const void*)jacobi_hc_kernel<4, 16>,
+                         (const void*)jacobi_hc_kernel<8, 16>,
+                         (const void*)jacobi_hc_kernel<8, 8>,
+                         (const void*)jacobi_hc_kernel<16, 8>,
+                         (const void*)jacobi_hc_kernel<16, 4>,
+                         (const void*)jacobi_hc_kernel<32, 4>};
+    for (const void* f : fns)
+      MPSV_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)kJacobiMaxLds));
   });
   MPSV_CHECK(k >= 1 && k <= kJacobiMaxCols, kEinval,
              "Jacobi SVD: matrix does not fit on chip");
@@ -890,16 +970,30 @@ void jacobi_svd(hipStream_t s, const double* Xr, int k, long ldx, int cap,
     return;
   }
   const Shape sh = shape_of(k);
-  const dim3 block(16 * sh.nodes);
-  if (sh.rpt == 2)
-    hipLaunchKernelGGL(jacobi_hc_kernel<2>, dim3(1), block, lds, s, Xr, k, ldx,
-                       sh.d, max_sweeps, cap, tol, Vt, sigbuf, perm, info);
-  else if (sh.rpt == 4)
-    hipLaunchKernelGGL(jacobi_hc_kernel<4>, dim3(1), block, lds, s, Xr, k, ldx,
-                       sh.d, max_sweeps, cap, tol, Vt, sigbuf, perm, info);
+  const dim3 block(sh.nl * sh.nodes);
+  MPSV_CHECK(sh.nl * sh.rpt >= k && (int)block.x <= 64 * sh.nl && block.x % 64 == 0,
+             kEinval, "Jacobi SVD: bad layout");
+  if (sh.nl == 16 && sh.rpt == 2)
+    jacobi_hc_kernel<2, 16><<<dim3(1), block, lds, s>>>(
+        Xr, k, ldx, sh.d, max_sweeps, cap, tol, Vt, sigbuf, perm, info);
+  else if (sh.nl == 16 && sh.rpt == 4)
+    jacobi_hc_kernel<4, 16><<<dim3(1), block, lds, s>>>(
+        Xr, k, ldx, sh.d, max_sweeps, cap, tol, Vt, sigbuf, perm, info);
+  else if (sh.nl == 16)
+    jacobi_hc_kernel<8, 16><<<dim3(1), block, lds, s>>>(
+        Xr, k, ldx, sh.d, max_sweeps, cap, tol, Vt, sigbuf, perm, info);
+  else if (sh.nl == 8 && sh.rpt == 8)
+    jacobi_hc_kernel<8, 8><<<dim3(1), block, lds, s>>>(
+        Xr, k, ldx, sh.d, max_sweeps, cap, tol, Vt, sigbuf, perm, info);
+  else if (sh.nl == 8)
+    jacobi_hc_kernel<16, 8><<<dim3(1), block, lds, s>>>(
+        Xr, k, ldx, sh.d, max_sweeps, cap, tol, Vt, sigbuf, perm, info);
+  else if (sh.rpt == 16)
+    jacobi_hc_kernel<16, 4><<<dim3(1), block, lds, s>>>(
+        Xr, k, ldx, sh.d, max_sweeps, cap, tol, Vt, sigbuf, perm, info);
   else
-    hipLaunchKernelGGL(jacobi_hc_kernel<8>, dim3(1), block, lds, s, Xr, k, ldx,
-                       sh.d, max_sweeps, cap, tol, Vt, sigbuf, perm, info);
+    jacobi_hc_kernel<32, 4><<<dim3(1), block, lds, s>>>(
+        Xr, k, ldx, sh.d, max_sweeps, cap, tol, Vt, sigbuf, perm, info);
   MPSV_LAUNCHED();
 }
 

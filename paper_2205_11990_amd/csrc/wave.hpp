@@ -22,6 +22,21 @@ __device__ inline double dpp(double v) {
   return __hiloint2double(hi, lo);
 }
 
+// Sum over each aligned group of 4 lanes; every lane of the group gets it.
+__device__ inline double sum4(double v) {
+  v += dpp<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp<0x4E>(v);   // quad_perm [2,3,0,1]
+  return v;
+}
+
+// Sum over each aligned group of 8 lanes; every lane of the group gets it.
+__device__ inline double sum8(double v) {
+  v += dpp<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp<0x141>(v);  // row_half_mirror: lane i <-> 7-i within 8
+  return v;
+}
+
 // Sum over each aligned row of 16 lanes; every lane of the row gets it.
 __device__ inline double sum16(double v) {
   v += dpp<0xB1>(v);   // quad_perm [1,0,3,2]
