@@ -589,33 +589,36 @@ __global__ __launch_bounds__(16 << (NLOG - GLOG)) void jacobi_multi_kernel(
     const double g = wave::sum16((gp[0] + gp[1]) + (gp[2] + gp[3]));
     const double ab = A.n * B.n, g2 = g * g;
     const bool rot = g2 > eps2 * ab && fmin(A.n, B.n) > negl;
-    if (rot) {
-      double cs, sn;
-      rotation(A.n, B.n, g, cs, sn);
+    // skipped by the whole wave when none of its nodes rotates; nodes that
+    // do not rotate apply cs = 1, sn = 0 (no change)
+    if (__builtin_amdgcn_ballot_w64(rot) == 0) return;
+    double cs, sn;
+    rotation(A.n, B.n, g, cs, sn);
+    cs = rot ? cs : 1.0;
+    sn = rot ? sn : 0.0;
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const double u = A.v[r], v = B.v[r];
+      A.v[r] = cs * u - sn * v;
+      B.v[r] = sn * u + cs * v;
+    }
+    const double c2 = cs * cs, s2 = sn * sn, csg = 2.0 * cs * sn * g;
+    const double na = fma(c2, A.n, fma(s2, B.n, -csg));
+    const double nb = fma(s2, A.n, fma(c2, B.n, csg));
+    if (rot && fmin(na, nb) < 1e-8 * (A.n + B.n)) {
+      double sa2 = 0.0, sb2 = 0.0;
 #pragma unroll
       for (int r = 0; r < RPT; ++r) {
-        const double u = A.v[r], v = B.v[r];
-        A.v[r] = cs * u - sn * v;
-        B.v[r] = sn * u + cs * v;
+        sa2 = fma(A.v[r], A.v[r], sa2);
+        sb2 = fma(B.v[r], B.v[r], sb2);
       }
-      const double c2 = cs * cs, s2 = sn * sn, csg = 2.0 * cs * sn * g;
-      const double na = fma(c2, A.n, fma(s2, B.n, -csg));
-      const double nb = fma(s2, A.n, fma(c2, B.n, csg));
-      if (fmin(na, nb) < 1e-8 * (A.n + B.n)) {
-        double sa2 = 0.0, sb2 = 0.0;
-#pragma unroll
-        for (int r = 0; r < RPT; ++r) {
-          sa2 = fma(A.v[r], A.v[r], sa2);
-          sb2 = fma(B.v[r], B.v[r], sb2);
-        }
-        A.n = wave::sum16(sa2);
-        B.n = wave::sum16(sb2);
-      } else {
-        A.n = na;
-        B.n = nb;
-      }
-      if (lig == 0 && g2 > conv2 * ab) sweep_any = 1;
+      A.n = wave::sum16(sa2);
+      B.n = wave::sum16(sb2);
+    } else {
+      A.n = na;
+      B.n = nb;
     }
+    if (rot && lig == 0 && g2 > conv2 * ab) sweep_any = 1;
   };
 
   double* xb = smem;
