@@ -40,7 +40,9 @@ Readings where the paper is silent or garbled (each also listed in the design doc):
 * Sweep order: QR left-to-right, then truncated SVD right-to-left; the
   norm ends in the first core.
 * Rank rule: D = min(chi, min{D' >= 1 : sum_{i>D'} s~_i^2 <= tol^2}) with
-  s~ = s / ||s||; tol = 0 keeps min(chi, len(s)).
+  s~ = s / ||s||; tol = 0 keeps min(chi, len(s)), also for an all-zero
+  block (eq. 5 discards nothing by weight then; with tol > 0 a zero block
+  keeps one value).
 * Compression points: P1 final state, P2 each stage state, P3 the sum of
   the k's, P4 each k, P5 each term of a k.  Every point truncates with tol;
   level C_l caps P1..P_l at chi (C1: only the final state is capped).
@@ -80,11 +82,13 @@ def rank_rule(s: np.ndarray, chi: Optional[int], tol: float) -> int:
     """Number of singular values kept (eq. 5 with the i = D+1 reading)."""
     k = len(s)
     cap = k if chi is None else min(chi, k)
+    if tol <= 0.0:
+        # nothing is discarded by weight: the cap alone sets D, whatever
+        # the values (an all-zero block included)
+        return max(1, cap)
     norm2 = float(np.sum(s * s))
     if k == 0 or norm2 == 0.0:
         return 1
-    if tol <= 0.0:
-        return max(1, cap)
     t = (s * s) / norm2
     # tail[D] = sum_{i >= D} t_i (0-based), summed from the smallest value
     tail = np.cumsum(t[::-1])[::-1]

@@ -131,6 +131,9 @@ def test_rank_rule_cases():
     assert mps.rank_rule(s, None, 1e-5) == 2
     assert mps.rank_rule(s, None, 2e-3) == 1
     assert mps.rank_rule(np.zeros(3), None, 1e-10) == 1
+    # tol = 0 discards nothing by weight: the cap alone, even for zeros
+    assert mps.rank_rule(np.zeros(3), None, 0.0) == 3
+    assert mps.rank_rule(np.zeros(3), 2, 0.0) == 2
 
 
 @pytest.mark.parametrize("order", [0, 1, 2, 3])
