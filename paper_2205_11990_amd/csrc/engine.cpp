@@ -881,9 +881,11 @@ DMps Engine::compress_chain(const std::vector<VSite>& ch_in, int cap, double tol
     const bool want_sg = sigmas || (centre > 0 && j == centre);
     double* sg = want_sg ? work().alloc((size_t)std::min(m, c)) : nullptr;
     if (centre > 0 && j == centre) sig_c = sg;
-    double dsc = 0.0;
+    // the discarded weight goes straight to its place (a deferred call
+    // writes it when the deferred section ends)
+    double* dsc = disc ? &(*disc)[j - 1] : nullptr;
     const int D = svd_truncate(s, work(), X, m, c, c, capj, tolj, Vt, US, sg,
-                               &dsc);
+                               dsc);
     if (sigmas) {
       auto& h = (*sigmas)[j - 1];
       h.resize((size_t)std::min(m, c));
@@ -892,7 +894,6 @@ DMps Engine::compress_chain(const std::vector<VSite>& ch_in, int cap, double tol
       MPSV_HIP(hipStreamSynchronize(s));
     }
     res[j] = Core{Vt, D, Dr};
-    if (disc) (*disc)[j - 1] = dsc;
     const Fac& f = fac[j - 1];
     if (f.ident) {
       X = US;  // (2 p_{j-2}) x D = p_{j-2} x (2D)
@@ -950,10 +951,8 @@ void Engine::compress_right_half(DMps& res, int centre, const double* sc,
     const int Dmax = std::min(std::min(cap, r), rows);
     double* Vt = work().alloc((size_t)Dmax * rows);
     double* US = work().alloc((size_t)r * Dmax);
-    double dsc = 0.0;
     const int D = svd_truncate(s, work(), Xt, r, rows, rows, cap, tol, Vt, US,
-                               nullptr, &dsc);
-    if (disc) (*disc)[j] = dsc;
+                               nullptr, disc ? &(*disc)[j] : nullptr);
     // core j = Vt^T: (rows x D), row 2 i + t
     Core A{out.alloc((size_t)rows * D), l, D};
     copy_view(s, CMatView{Vt, 1, rows, 0}, rows, MatView{A.p, D, 1, 0}, rows, D);
@@ -1029,11 +1028,11 @@ DMps Engine::add_terms(const std::vector<std::pair<double, const DMps*>>& terms,
     v.l = (j == 0) ? 1 : lo;
     v.r = (j == n - 1) ? 1 : ro;
   }
-  std::vector<double> disc;
-  DMps r = compress_chain(ch, cap, tol < 0 ? p_.tol : tol, out, s, &disc,
-                          nullptr, centre_for(n));
-  disc_ = disc;
-  return r;
+  // disc_ keeps its storage (same length every time), so deferred
+  // discarded weights can be written into it when the step's deferred
+  // section ends
+  return compress_chain(ch, cap, tol < 0 ? p_.tol : tol, out, s, &disc_,
+                        nullptr, centre_for(n));
 }
 
 // The same tensor with the sites in reverse order: core (l, 2, r) ->
@@ -1270,6 +1269,27 @@ void Engine::step(hipStream_t s) {
   step_.reset();
   const double h = step_size(s);
   step_.reset();
+  // Fixed-rank factorisations (tol = 0) report their outcome at the end of
+  // the step instead of one host round trip each; a failure still fails
+  // the step before anything is committed.
+  svd_defer_begin(s);
+  svd_defer_begin(side_);
+  try {
+    step_stages(h, s);
+    svd_defer_end(side_);
+    svd_defer_end(s);
+  } catch (...) {
+    svd_defer_cancel(side_);
+    svd_defer_cancel(s);
+    throw;
+  }
+  commit(staged_, s);
+  staged_.clear();
+  t_ += h;
+  ++steps_;
+}
+
+void Engine::step_stages(double h, hipStream_t s) {
   DMps k1 = rhs(f_, step_, s);
   DMps f2 = add_terms({{1.0, &f_}, {0.5 * h, &k1}}, cap_for(2), step_, s);
   DMps k2 = rhs(f2, step_, s);
@@ -1279,11 +1299,8 @@ void Engine::step(hipStream_t s) {
   DMps k4 = rhs(f4, step_, s);
   DMps S = add_terms({{1.0, &k1}, {2.0, &k2}, {2.0, &k3}, {1.0, &k4}},
                      cap_for(3), step_, s);
-  DMps fn = add_terms({{1.0, &f_}, {h / 6.0, &S}}, cap_or_inf(p_.chi_max),
+  staged_ = add_terms({{1.0, &f_}, {h / 6.0, &S}}, cap_or_inf(p_.chi_max),
                       step_, s);
-  commit(fn, s);
-  t_ += h;
-  ++steps_;
 }
 
 // ---------------------------------------------------------------- state io

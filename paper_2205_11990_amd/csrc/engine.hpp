@@ -163,6 +163,8 @@ class Engine {
   DMps field(const DMps& g, Arena& ar, hipStream_t s);
   DMpo t2_mpo(const DMps& E, Arena& ar, hipStream_t s);
   DMps rhs(const DMps& g, Arena& out, hipStream_t s);
+  // the four RK4 stages of one step; the new state is left in staged_
+  void step_stages(double h, hipStream_t s);
   DMps copy_mps(const DMps& a, Arena& ar, hipStream_t s);
   DMps reverse_mps(const DMps& a, Arena& ar, hipStream_t s);
   void commit(const DMps& fn, hipStream_t s);
@@ -194,6 +196,7 @@ class Engine {
   DMpo t1_, gneg_, dv_;            // T1 chain, -G (x sites), Dv (v sites)
   DMps vpoly_, v2poly_;            // moment weights (full chain)
   DMps f_;
+  DMps staged_;  // the new state of the step in flight (step_ arena)
   std::vector<double> disc_;
   double t_ = 0.0;
   long steps_ = 0;

@@ -401,10 +401,10 @@ __global__ __launch_bounds__(64 * NL) void jacobi_hc_kernel(
     for (int i = 0; i < k; ++i) tot += sigbuf[i] * sigbuf[i];
     const int capd = cap < k ? cap : k;
     int D;
-    if (tot <= 0.0) {
+    if (tol <= 0.0) {
+      D = capd;  // the cap alone decides, whatever the values (a zero block too)
+    } else if (tot <= 0.0) {
       D = 1;
-    } else if (tol <= 0.0) {
-      D = capd;
     } else {
       // smallest D' >= 1 whose discarded tail (summed from the smallest
       // value) is <= tol^2
@@ -774,10 +774,10 @@ __global__ __launch_bounds__(16 << (NLOG - GLOG)) void jacobi_multi_kernel(
     for (int i = 0; i < k; ++i) tot += sorted[i] * sorted[i];
     const int capd = cap < k ? cap : k;
     int D;
-    if (tot <= 0.0) {
+    if (tol <= 0.0) {
+      D = capd;  // the cap alone decides, whatever the values (a zero block too)
+    } else if (tot <= 0.0) {
       D = 1;
-    } else if (tol <= 0.0) {
-      D = capd;
     } else {
       double acc = 0.0;
       int best = k;

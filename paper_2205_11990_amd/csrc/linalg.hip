@@ -223,10 +223,10 @@ __global__ __launch_bounds__(NT) void jacobi_svd_kernel(
     int D = kmax;
     int capd = cap < kmax ? cap : kmax;
     double disc2 = 0.0;
-    if (tot <= 0.0) {
+    if (tol <= 0.0) {
+      D = capd;  // the cap alone decides, whatever the values (a zero block too)
+    } else if (tot <= 0.0) {
       D = 1;
-    } else if (tol <= 0.0) {
-      D = capd;
     } else {
       // smallest D' >= 1 with sum_{i >= D'} t_i <= tol^2, tail summed from the end
       double tail = 0.0;
@@ -292,6 +292,24 @@ double* pinned_info(hipStream_t s) {
   return p;
 }
 
+// Deferred outcome slots, per stream (see svd_defer_begin).
+constexpr int kDeferSlots = 4096;
+constexpr int kInfoWords = 8;
+struct Deferred {
+  bool on = false;
+  double* ring = nullptr;  // pinned, kDeferSlots x kInfoWords
+  int used = 0;
+  std::vector<std::pair<double*, int>> disc;  // destination, slot
+  std::vector<char> split;                    // slot was a split launch
+};
+std::mutex g_defer_mu;
+std::map<hipStream_t, Deferred> g_defer;
+
+Deferred& defer_of(hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_defer_mu);
+  return g_defer[s];  // map nodes keep their address
+}
+
 std::once_flag g_attr_once;
 void set_attrs() {
   std::call_once(g_attr_once, [] {
@@ -304,6 +322,56 @@ void set_attrs() {
 }  // namespace
 
 LinalgStats& linalg_stats() { return g_stats; }
+
+void svd_defer_begin(hipStream_t s) {
+  Deferred& d = defer_of(s);
+  if (!d.ring)
+    MPSV_HIP(hipHostMalloc((void**)&d.ring,
+                           sizeof(double) * kDeferSlots * kInfoWords,
+                           hipHostMallocDefault));
+  d.used = 0;
+  d.disc.clear();
+  d.split.clear();
+  d.on = true;
+}
+
+void svd_defer_end(hipStream_t s) {
+  Deferred& d = defer_of(s);
+  if (!d.on) return;
+  d.on = false;
+  if (d.used == 0) return;
+  MPSV_HIP(hipStreamSynchronize(s));
+  int code = 0;
+  std::string msg;
+  for (int i = 0; i < d.used; ++i) {
+    const volatile double* h = d.ring + (long)i * kInfoWords;
+    g_stats.jacobi_sweeps += (long)h[2];
+    if (code) continue;
+    if (d.split[i] && h[5] != 0.0) {
+      code = kEdevice;
+      msg = "Jacobi SVD: the workgroups did not meet in time";
+    } else if (h[3] == 0.0) {
+      code = kEnumeric;
+      msg = "Jacobi SVD did not converge within " +
+            std::to_string(g_max_sweeps) + " sweeps";
+    }
+  }
+  for (auto& w : d.disc) *w.first = d.ring[(long)w.second * kInfoWords + 1];
+  d.used = 0;
+  d.disc.clear();
+  d.split.clear();
+  if (code) throw Error(code, msg);
+}
+
+void svd_defer_cancel(hipStream_t s) noexcept {
+  Deferred& d = defer_of(s);
+  if (!d.on) return;
+  d.on = false;
+  (void)hipStreamSynchronize(s);
+  d.used = 0;
+  d.disc.clear();
+  d.split.clear();
+}
 void set_jacobi_max_sweeps(int n) { g_max_sweeps = n < 1 ? 1 : n; }
 int jacobi_max_sweeps() { return g_max_sweeps; }
 
@@ -552,9 +620,19 @@ int svd_truncate(hipStream_t s, Arena& ws, double* X, int m, int c, long ldx,
   g_stats.svd_calls++;
   MPSV_CHECK(m >= 1 && c >= 1, kEinval, "svd_truncate: empty matrix");
   ArenaScope sc(ws);
-  // the kernels write their info words straight into this stream's pinned
-  // host block (device-accessible), read after the stream synchronisation
-  double* info = pinned_info(s);
+  // the kernels write their info words straight into pinned host memory
+  // (device-accessible): this stream's block, read after the stream
+  // synchronisation, or a slot of its deferred record
+  Deferred* df = nullptr;
+  int slot_i = -1;
+  if (tol <= 0.0) {
+    Deferred& d = defer_of(s);
+    if (d.on && d.used < kDeferSlots) {
+      df = &d;
+      slot_i = d.used++;
+    }
+  }
+  double* info = df ? df->ring + (long)slot_i * kInfoWords : pinned_info(s);
   double* sigbuf = ws.alloc((size_t)3 * std::max(m, c) + 8);
   const int k = std::min(m, c);
   // Preconditioning: Jacobi runs on the transpose of a triangular factor
@@ -646,16 +724,24 @@ int svd_truncate(hipStream_t s, Arena& ws, double* X, int m, int c, long ldx,
     prof_end(s, slot, kClsJacobi, 6.0 * mm * nn * nn + 20.0 * nn * nn * nn,
              8.0 * (2.0 * m * c + 2.0 * nn * nn));
   }
-  MPSV_HIP(hipStreamSynchronize(s));
-  const volatile double* h = info;
-  const int D = (int)h[0];
-  if (discarded) *discarded = h[1];
-  g_stats.jacobi_sweeps += (long)h[2];
-  if (onchip && jacobi_split(k) > 0 && h[5] != 0.0)
-    throw Error(kEdevice, "Jacobi SVD: the workgroups did not meet in time");
-  if (h[3] == 0.0)
-    throw Error(kEnumeric, "Jacobi SVD did not converge within " +
-                               std::to_string(g_max_sweeps) + " sweeps");
+  int D;
+  if (df) {
+    // fixed rank: the kernels keep min(cap, k) whatever the values
+    D = cap < k ? cap : k;
+    df->split.push_back(onchip && jacobi_split(k) > 0 ? 1 : 0);
+    if (discarded) df->disc.push_back({discarded, slot_i});
+  } else {
+    MPSV_HIP(hipStreamSynchronize(s));
+    const volatile double* h = info;
+    D = (int)h[0];
+    if (discarded) *discarded = h[1];
+    g_stats.jacobi_sweeps += (long)h[2];
+    if (onchip && jacobi_split(k) > 0 && h[5] != 0.0)
+      throw Error(kEdevice, "Jacobi SVD: the workgroups did not meet in time");
+    if (h[3] == 0.0)
+      throw Error(kEnumeric, "Jacobi SVD did not converge within " +
+                                 std::to_string(g_max_sweeps) + " sweeps");
+  }
   if (sig) {
     MPSV_HIP(hipMemcpyAsync(sig, sigbuf, (size_t)k * sizeof(double),
                             hipMemcpyDeviceToDevice, s));

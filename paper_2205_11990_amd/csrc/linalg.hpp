@@ -77,10 +77,24 @@ void copy_view(hipStream_t s, CMatView in, int rows_in, MatView out, int rows,
 //   sig : (optional, length >= min(m,c)) all singular values, descending
 // Returns D (the stream is synchronised to read it back) and the relative
 // discarded weight sqrt(sum_{i>D} s_i^2 / sum s_i^2) in *discarded.
-// X is overwritten.
+// X is overwritten.  Inside a deferred section of the stream (below) a call
+// with tol <= 0 returns without synchronising: D is then min(cap, m, c)
+// whatever the values, and *discarded is written when the section ends.
 int svd_truncate(hipStream_t s, Arena& ws, double* X, int m, int c, long ldx,
                  int cap, double tol, double* Vt, double* US, double* sig,
                  double* discarded);
+
+// Deferred read-back of the SVD outcomes on stream s.  Between begin and
+// end, fixed-rank calls (tol <= 0) only record where their outcome words
+// land (one pinned slot per call), so the host never waits for the device
+// inside a compression sweep.  svd_defer_end synchronises s, checks every
+// recorded call (convergence; the workgroup rendezvous of split launches),
+// writes the recorded discarded weights and throws the first failure.
+// svd_defer_cancel synchronises and drops the record (error paths).  The
+// pointers given as `discarded` must stay valid until the end.
+void svd_defer_begin(hipStream_t s);
+void svd_defer_end(hipStream_t s);
+void svd_defer_cancel(hipStream_t s) noexcept;
 
 // Device-side counters of the last factorisations (for diagnostics/tests).
 struct LinalgStats {
