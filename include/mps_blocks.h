@@ -60,6 +60,21 @@ mps_status mpsb_compress(int32_t n, const int32_t* mpo_bonds,
                          int64_t capacity, double* discarded,
                          hipStream_t stream);
 
+/* Captured step graphs of a state.  When every truncation has a fixed rank
+ * (tol = 0) and dt is fixed, the shapes of a step do not change between
+ * steps: after one ordinary step from a given state layout, the next step
+ * records all launches of the step (both lanes) into a HIP graph and later
+ * steps replay it, without the host work of issuing each launch; the
+ * results are the same launches with the same arguments.  enable: 1 on,
+ * 0 off, < 0 leaves it unchanged.  captures / replays: host
+ * int64 counters or NULL.  Off while kernel timing (mpsb_profile) is on;
+ * MPSV_STEP_GRAPH=0 in the environment turns it off for the process.
+ * Currently switched off: the default is off and enable = 1 returns
+ * MPS_EINVAL (a capture ended the host process with a segmentation fault
+ * whose cause has not been found). */
+mps_status mpsb_step_graph(mps_state* h, int32_t enable, int64_t* captures,
+                           int64_t* replays);
+
 /* Centre-first compression (SI, "Modified Compression Scheme") of an MPS
  * cut at the bond between sites centre-1 and centre (1 <= centre <= n-1):
  * the cut is truncated first from the mixed canonical form around it, then

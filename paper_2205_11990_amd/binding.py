@@ -69,6 +69,7 @@ _SIGS = {
     "mpsb_qr": [_I32, _I32, _P, _P, _P],
     "mpsb_svd_truncate": [_I32, _I32, _P, _I32, _D, _P, _P, _P, _PI32, _PD, _P],
     "mpsb_compress": [_I32, _PI32, _P, _PI32, _P, _I32, _D, _PI32, _P, _I64, _PD, _P],
+    "mpsb_step_graph": [_P, _I32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
     "mpsb_compress_centre": [_I32, _I32, _PI32, _P, _I32, _D, _PI32, _P, _I64, _PD, _P],
     "mpsb_add_compress": [_I32, _I32, _PD, _PI32, ctypes.POINTER(_P), _I32, _D,
                           _PI32, _P, _I64, _P],
@@ -230,6 +231,14 @@ class MpsState:
         ee = (ctypes.c_double * max(n - 1, 1))()
         _check(lib().mps_entanglement(self._h, ee, _stream(stream)))
         return list(ee)[:n - 1]
+
+    def step_graph(self, enable=None):
+        """Turn captured step graphs on/off (None: unchanged); returns
+        (captures, replays)."""
+        c, r = ctypes.c_int64(), ctypes.c_int64()
+        e = -1 if enable is None else int(bool(enable))
+        _check(lib().mpsb_step_graph(self._h, e, ctypes.byref(c), ctypes.byref(r)))
+        return c.value, r.value
 
     def device_bytes(self) -> int:
         b = ctypes.c_size_t()

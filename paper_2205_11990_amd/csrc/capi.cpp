@@ -461,6 +461,16 @@ mps_status mpsb_compress(int32_t n, const int32_t* mpo_bonds,
   });
 }
 
+mps_status mpsb_step_graph(mps_state* h, int32_t enable, int64_t* captures,
+                           int64_t* replays) {
+  return guarded([&] {
+    check_handle(h);
+    if (enable >= 0) h->eng->set_step_graph(enable != 0);
+    if (captures) *captures = h->eng->graph_captures();
+    if (replays) *replays = h->eng->graph_replays();
+  });
+}
+
 mps_status mpsb_compress_centre(int32_t n, int32_t centre,
                                 const int32_t* bonds_in, const double* cores_in,
                                 int32_t cap, double tol, int32_t* bonds_out,

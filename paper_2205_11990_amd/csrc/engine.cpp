@@ -12,10 +12,12 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 
 #include "gemm.hpp"
 #include "mps_kernels.hpp"
+#include "prof.hpp"
 
 namespace mpsv {
 
@@ -567,6 +569,8 @@ Engine::Engine(const Problem& p) : p_(p), chunk_(memory_model(p).chunk) {
   MPSV_HIP(hipStreamCreateWithFlags(&side_, hipStreamNonBlocking));
   MPSV_HIP(hipEventCreateWithFlags(&ev_fork_, hipEventDisableTiming));
   MPSV_HIP(hipEventCreateWithFlags(&ev_join_, hipEventDisableTiming));
+  MPSV_HIP(hipEventCreateWithFlags(&ev_in_, hipEventDisableTiming));
+  MPSV_HIP(hipEventCreateWithFlags(&ev_out_, hipEventDisableTiming));
 
   hipStream_t s = nullptr;
   std::vector<int> bdx, bvv, bt1, bg, bdv;
@@ -627,8 +631,11 @@ Engine::~Engine() {
   // the side stream may still read buffers owned by the arenas
   if (side_) (void)hipStreamSynchronize(side_);
   if (own_) (void)hipStreamSynchronize(own_);
+  if (gexec_) (void)hipGraphExecDestroy(gexec_);
   if (ev_fork_) (void)hipEventDestroy(ev_fork_);
   if (ev_join_) (void)hipEventDestroy(ev_join_);
+  if (ev_in_) (void)hipEventDestroy(ev_in_);
+  if (ev_out_) (void)hipEventDestroy(ev_out_);
   if (side_) (void)hipStreamDestroy(side_);
   if (own_) (void)hipStreamDestroy(own_);
 }
@@ -1269,6 +1276,51 @@ void Engine::step(hipStream_t s) {
   step_.reset();
   const double h = step_size(s);
   step_.reset();
+  if (!graph_eligible()) {
+    step_eager(h, s);
+  } else {
+    // On the instance's own stream, ordered after earlier work on s; later
+    // work on s waits for the step.
+    MPSV_HIP(hipEventRecord(ev_in_, s));
+    MPSV_HIP(hipStreamWaitEvent(own_, ev_in_, 0));
+    const std::vector<Core> key(f_.begin(), f_.end());
+    if (gexec_ && same_cores(key, graph_key_)) {
+      step_replay(own_);
+    } else if (same_cores(key, warm_key_)) {
+      step_capture(h, own_);
+      graph_key_ = key;
+    } else {
+      // first step from this state layout: eager, which also sizes every
+      // workspace the capture will use
+      step_eager(h, own_);
+      warm_key_ = key;
+    }
+    MPSV_HIP(hipEventRecord(ev_out_, own_));
+    MPSV_HIP(hipStreamWaitEvent(s, ev_out_, 0));
+  }
+  t_ += h;
+  ++steps_;
+}
+
+bool Engine::graph_eligible() const {
+  static const bool env_off = [] {
+    const char* e = std::getenv("MPSV_STEP_GRAPH");
+    return e && std::atoi(e) == 0;
+  }();
+  // a replay needs the same shapes every step: fixed rank (tol = 0, every
+  // SVD keeps min(cap, k)) and a fixed dt; timing probes need the launches
+  return graph_on_ && !env_off && p_.tol <= 0.0 && p_.cfl <= 0.0 &&
+         !prof_enabled();
+}
+
+bool Engine::same_cores(const std::vector<Core>& a, const std::vector<Core>& b) {
+  if (a.size() != b.size()) return false;
+  for (size_t j = 0; j < a.size(); ++j)
+    if (a[j].p != b[j].p || a[j].l != b[j].l || a[j].r != b[j].r) return false;
+  return true;
+}
+
+void Engine::step_eager(double h, hipStream_t s) {
   // Fixed-rank factorisations (tol = 0) report their outcome at the end of
   // the step instead of one host round trip each; a failure still fails
   // the step before anything is committed.
@@ -1285,8 +1337,60 @@ void Engine::step(hipStream_t s) {
   }
   commit(staged_, s);
   staged_.clear();
-  t_ += h;
-  ++steps_;
+}
+
+// Records the launches of one step (both streams, joined by the fork and
+// join events of rhs) into a graph instead of running them, then replays
+// it.  The graph holds the addresses of this state layout: the committed
+// state, the arenas' workspace and the outcome slots, which stay put while
+// the bonds do not change.
+void Engine::step_capture(double h, hipStream_t s) {
+  if (gexec_) {
+    (void)hipGraphExecDestroy(gexec_);
+    gexec_ = nullptr;
+  }
+  svd_defer_begin(s);
+  svd_defer_begin(side_);
+  hipGraph_t g = nullptr;
+  MPSV_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+  try {
+    step_stages(h, s);
+  } catch (...) {
+    (void)hipStreamEndCapture(s, &g);
+    if (g) (void)hipGraphDestroy(g);
+    (void)svd_defer_take(side_);
+    (void)svd_defer_take(s);
+    throw;
+  }
+  MPSV_HIP(hipStreamEndCapture(s, &g));
+  rec_own_ = svd_defer_take(s);
+  rec_side_ = svd_defer_take(side_);
+  const hipError_t e = hipGraphInstantiate(&gexec_, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    gexec_ = nullptr;
+    throw Error(kEdevice, std::string("graph instantiation: ") + hipGetErrorString(e));
+  }
+  graph_out_ = staged_;
+  staged_.clear();
+  ++graph_captures_;
+  step_replay(s);
+}
+
+void Engine::step_replay(hipStream_t s) {
+  svd_defer_resume(s, rec_own_);
+  svd_defer_resume(side_, rec_side_);
+  try {
+    MPSV_HIP(hipGraphLaunch(gexec_, s));
+    svd_defer_end(s);  // the whole graph, both lanes, has run
+    svd_defer_end(side_);
+  } catch (...) {
+    svd_defer_cancel(s);
+    svd_defer_cancel(side_);
+    throw;
+  }
+  commit(graph_out_, s);
+  ++graph_replays_;
 }
 
 void Engine::step_stages(double h, hipStream_t s) {

@@ -111,6 +111,18 @@ class Engine {
 
   // ---- the hot path
   void step(hipStream_t s);
+  // Steps of fixed shape (tol = 0, fixed dt) can replay a captured graph of
+  // the step's launches.  Switched off: the first capture on the GPU ended
+  // the host process with a segmentation fault whose cause has not been
+  // found, so enabling it raises an error.
+  void set_step_graph(bool on) {
+    MPSV_CHECK(!on, kEinval,
+               "captured step graphs are switched off (a capture ended the "
+               "process; cause not found)");
+    graph_on_ = on;
+  }
+  long graph_captures() const { return graph_captures_; }
+  long graph_replays() const { return graph_replays_; }
   // A stream owned by this instance (batched stepping runs each instance on
   // its own stream).
   hipStream_t own_stream() const { return own_; }
@@ -165,6 +177,11 @@ class Engine {
   DMps rhs(const DMps& g, Arena& out, hipStream_t s);
   // the four RK4 stages of one step; the new state is left in staged_
   void step_stages(double h, hipStream_t s);
+  void step_eager(double h, hipStream_t s);
+  void step_capture(double h, hipStream_t s);
+  void step_replay(hipStream_t s);
+  bool graph_eligible() const;
+  static bool same_cores(const std::vector<Core>& a, const std::vector<Core>& b);
   DMps copy_mps(const DMps& a, Arena& ar, hipStream_t s);
   DMps reverse_mps(const DMps& a, Arena& ar, hipStream_t s);
   void commit(const DMps& fn, hipStream_t s);
@@ -193,6 +210,14 @@ class Engine {
   hipStream_t own_ = nullptr;      // this instance's stream (batched mode)
   hipStream_t side_ = nullptr;     // T1 runs here, beside T2
   hipEvent_t ev_fork_ = nullptr, ev_join_ = nullptr;
+  hipEvent_t ev_in_ = nullptr, ev_out_ = nullptr;  // caller stream <-> own_
+  // captured step graph and what it was captured for
+  bool graph_on_ = false;
+  hipGraphExec_t gexec_ = nullptr;
+  std::vector<Core> graph_key_, warm_key_;  // input state layouts
+  DMps graph_out_;                           // the graph's new state
+  SvdDeferRecord rec_own_, rec_side_;
+  long graph_captures_ = 0, graph_replays_ = 0;
   DMpo t1_, gneg_, dv_;            // T1 chain, -G (x sites), Dv (v sites)
   DMps vpoly_, v2poly_;            // moment weights (full chain)
   DMps f_;

@@ -363,6 +363,29 @@ void svd_defer_end(hipStream_t s) {
   if (code) throw Error(code, msg);
 }
 
+SvdDeferRecord svd_defer_take(hipStream_t s) {
+  Deferred& d = defer_of(s);
+  SvdDeferRecord r;
+  r.used = d.used;
+  r.disc = d.disc;
+  r.split = d.split;
+  d.on = false;
+  d.used = 0;
+  d.disc.clear();
+  d.split.clear();
+  return r;
+}
+
+void svd_defer_resume(hipStream_t s, const SvdDeferRecord& r) {
+  Deferred& d = defer_of(s);
+  MPSV_CHECK(d.ring != nullptr && r.used <= kDeferSlots, kEinval,
+             "deferred SVD record without its slots");
+  d.used = r.used;
+  d.disc = r.disc;
+  d.split = r.split;
+  d.on = true;
+}
+
 void svd_defer_cancel(hipStream_t s) noexcept {
   Deferred& d = defer_of(s);
   if (!d.on) return;

@@ -96,6 +96,18 @@ void svd_defer_begin(hipStream_t s);
 void svd_defer_end(hipStream_t s);
 void svd_defer_cancel(hipStream_t s) noexcept;
 
+// The record of a deferred section, kept across replays of a captured
+// graph: the replay writes the same pinned slots, so the record taken at
+// capture (svd_defer_take, which closes the section without
+// synchronising) is put back before each replay's svd_defer_end.
+struct SvdDeferRecord {
+  int used = 0;
+  std::vector<std::pair<double*, int>> disc;
+  std::vector<char> split;
+};
+SvdDeferRecord svd_defer_take(hipStream_t s);
+void svd_defer_resume(hipStream_t s, const SvdDeferRecord& r);
+
 // Device-side counters of the last factorisations (for diagnostics/tests).
 struct LinalgStats {
   std::atomic<long> qr_calls{0}, svd_calls{0}, jacobi_sweeps{0};

@@ -488,3 +488,49 @@ def test_untruncated_s2_s3_on_an_unequal_grid_equal_dense_oracle(B, order):
     vec = omps.to_vector(st.get_cores_host())
     assert np.abs(vec - omps.dense_to_sites(F, p.Lx, p.Lv, order)).max() <= 1e-11 * np.abs(F).max()
     st.free()
+
+
+@pytest.mark.skip(reason="captured step graphs are switched off: the first capture ended the "
+                         "host process with a segmentation fault whose cause has not been found")
+@pytest.mark.parametrize("L,chi,order,comp", [(6, 16, 1, 0), (5, 8, 0, 1), (8, 128, 1, 0)])
+def test_step_graph_replays_equal_eager_steps(B, L, chi, order, comp):
+    """Fixed-rank steps (tol = 0, every point capped) replayed from a
+    captured graph: after each of five steps, with moments, a dense
+    reconstruction and host synchronisations in between, the cores equal
+    those of the same steps issued launch by launch, bit for bit.  The first
+    step runs eagerly, the second captures, the rest replay."""
+    _say("step graph replays L=%d chi=%d order=%d compression=%d" % (L, chi, order, comp))
+    w = wl.two_stream(L=L, chi=chi, tol=0.0, level=5, df_max=4, dt_cfg=0.05, order=order)
+    p = w.problem
+    p.compression = comp
+    a = B.MpsState(p, w.ax, w.bv)
+    a.add_scaled(1e-3, wl.random_mps_cores(p.n_sites, chi, seed=2205))
+    b = B.MpsState(p, w.ax, w.bv)
+    b.set_cores(a.get_cores_host())
+    b.step_graph(False)
+    for k in range(5):
+        a.step(1)
+        b.step(1)
+        ca, cb = a.get_cores_host(), b.get_cores_host()
+        assert [c.shape for c in ca] == [c.shape for c in cb], k
+        for x, y in zip(ca, cb):
+            assert np.array_equal(x, y), k
+        a.moments()
+        a.to_dense()
+    assert a.step_graph() == (1, 4)
+    assert b.step_graph() == (0, 0)
+    a.free()
+    b.free()
+
+
+def test_step_graph_cannot_be_enabled(B):
+    """The captured-graph path is switched off: enabling it is an error and
+    the counters stay at zero after steps."""
+    _say("step graph switched off")
+    w = wl.two_stream(L=5, chi=8, tol=0.0, level=5, df_max=4, dt_cfg=0.05)
+    st = B.MpsState(w.problem, w.ax, w.bv)
+    with pytest.raises(B.MpsError):
+        st.step_graph(True)
+    st.step(3)
+    assert st.step_graph() == (0, 0)
+    st.free()
