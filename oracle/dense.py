@@ -19,6 +19,16 @@ The same scheme the MPS method discretises, evaluated on the full grid:
   point, which makes the derivative vanish at the first and last node (SI,
   "First Derivative, Centered, Zero Gradient Boundary Conditions").
 * Left Riemann sum for integrals (SI, "Integration").
+* Collisions (Methods, "Collision Operator"): the Dougherty operator
+  nu d/dv [(v - v0) f + vth^2 df/dv].  Reading: v0 and vth are fixed
+  parameters of the species (the drift and thermal speed its CFL term
+  uses), not moments recomputed from f, so the operator is linear; both
+  derivatives are the zero-gradient central difference in v.
+* Several species (Methods, the Landau / Buneman / shock set-ups): each
+  species s has its own v grid and q_s/m_s and all share x and E; Poisson
+  reads Laplacian(phi) = -sum_s q_s n_s (normalised units; the
+  pseudo-inverse again drops the mean, i.e. any neutralising background).
+  One species with q = -1 is the single-electron case above.
 * Classic RK4 with a fixed step (SI, "Compressed time evolution algorithm"),
   or an adaptive one (Methods, "Time Evolution Procedure", eq. CFL): a
   fraction cfl of dt_max = (|v|_max / dx + |q/m| |E|_max / dv)^-1 for one
@@ -110,10 +120,42 @@ def field(F: np.ndarray, p) -> np.ndarray:
     return poisson_field(density(F, p.dv), p.dx)
 
 
-def rhs(F: np.ndarray, p) -> np.ndarray:
-    """R(F) = -v Dx F - (q/m) E Dv F  (eq. 1, C = 0)."""
-    E = field(F, p)
-    return -advection(F, p) - p.qm * E[:, None] * ddv(F, p.dv)
+def collision(F: np.ndarray, p) -> np.ndarray:
+    """nu Dv[(v - v0) F + vth^2 Dv F] (Dougherty, fixed v0 and vth)."""
+    v = p.v()
+    G = (v - p.nu_v0)[None, :] * F + p.nu_vth ** 2 * ddv(F, p.dv)
+    return p.nu * ddv(G, p.dv)
+
+
+def rhs(F: np.ndarray, p, E: np.ndarray | None = None) -> np.ndarray:
+    """R(F) = -v Dx F - (q/m) E Dv F + C[F]  (eq. 1); E from F alone (one
+    electron species on a neutralising background) unless given."""
+    if E is None:
+        E = field(F, p)
+    out = -advection(F, p) - p.qm * E[:, None] * ddv(F, p.dv)
+    if getattr(p, "nu", 0.0) != 0.0:
+        out = out + collision(F, p)
+    return out
+
+
+def field_species(Fs, ps, charges) -> np.ndarray:
+    """E of several species: Laplacian(phi) = -sum_s q_s n_s."""
+    rho = sum(-q * density(F, p.dv) for F, p, q in zip(Fs, ps, charges))
+    return poisson_field(rho, ps[0].dx)
+
+
+def rk4_step_species(Fs, ps, charges, dt: float):
+    """One RK4 step of all species together; E of each stage from all of
+    them."""
+    def R(Gs):
+        E = field_species(Gs, ps, charges)
+        return [rhs(G, p, E) for G, p in zip(Gs, ps)]
+    k1 = R(Fs)
+    k2 = R([F + 0.5 * dt * k for F, k in zip(Fs, k1)])
+    k3 = R([F + 0.5 * dt * k for F, k in zip(Fs, k2)])
+    k4 = R([F + dt * k for F, k in zip(Fs, k3)])
+    return [F + (dt / 6.0) * (a + 2.0 * b + 2.0 * c + d)
+            for F, a, b, c, d in zip(Fs, k1, k2, k3, k4)]
 
 
 def cfl_dt(F: np.ndarray, p) -> float:

@@ -47,6 +47,12 @@ Readings where the paper is silent or garbled (each also listed in the design doc):
   the k's, P4 each k, P5 each term of a k.  Every point truncates with tol;
   level C_l caps P1..P_l at chi (C1: only the final state is capped).
 * The field MPS is compressed with tol and an optional cap D_F.
+* Collisions: the Dougherty operator with the species' fixed drift v0 and
+  thermal speed vth, nu Dv (diag(v - v0) + vth^2 Dv) with Dv the
+  zero-gradient central difference (Methods, Collision Operator); its term
+  of a k is compressed at P5 like the other two.
+* Several species: rho = sum_s (-q_s) n_s is formed exactly (direct sum)
+  and E = compress(-G rho) uses the first species' D_F and tol.
 * Centre-first compression: the SVD is of the centre site (first v site)
   at its left bond, the x|v cut; U S joins the last x site and S V^T becomes
   the centre site (the printed step that merges S V^T into the next site
@@ -442,6 +448,17 @@ def mpo_d1_backward(L: int, h: float) -> Mpo:
     return mpo_stencil_periodic(L, h, D1_BACKWARD)
 
 
+def mpo_product(A: Mpo, B: Mpo) -> Mpo:
+    """The operator product A B as an MPO: C(o, i) = sum_m A(o, m) B(m, i)
+    site by site, bonds multiplied (A-major)."""
+    out = []
+    for Wa, Wb in zip(A, B):
+        T = np.einsum("aomb,cmid->acoibd", Wa, Wb)
+        a, c, o, i, b, d = T.shape
+        out.append(T.reshape(a * c, o, i, b * d))
+    return out
+
+
 def mpo_to_matrix(W: Mpo) -> np.ndarray:
     """Contract an MPO to its dense N x N matrix (brute force, tests)."""
     L = len(W)
@@ -684,6 +701,16 @@ class Operators:
             # T1 = -(Dx (x) V) f
             self.T1 = chain_mpo(self.Dx, self.V, p.Lx, p.Lv, p.order)
         self.T1[0] = -self.T1[0]
+        # Dougherty collisions with fixed drift and thermal speed (Methods,
+        # Collision Operator): nu Dv (diag(v - v0) + vth^2 Dv), on v sites
+        self.T3 = None
+        if getattr(p, "nu", 0.0) != 0.0:
+            inner = mpo_sum([diag_mpo(vector_mps(p.v() - p.nu_v0)),
+                             [W * (p.nu_vth ** 2 if j == 0 else 1.0)
+                              for j, W in enumerate(self.Dv)]])
+            Cv = mpo_product(self.Dv, inner)
+            Cv[0] = Cv[0] * p.nu
+            self.T3 = chain_mpo(None, Cv, p.Lx, p.Lv, p.order)
 
 
 def field_mps(g: Mps, ops: Operators) -> Mps:
@@ -709,17 +736,54 @@ def caps(p, point: int) -> Optional[int]:
     return p.chi_max if p.level >= point else None
 
 
-def rhs_mps(g: Mps, ops: Operators) -> Mps:
-    """k = R(g): T1 = -(Dx (x) V) g, T2 = -(q/m)(diag(E) (x) Dv) g, each
-    compressed (P5), then their sum compressed (P4)."""
+def rhs_mps(g: Mps, ops: Operators, E: Optional[Mps] = None) -> Mps:
+    """k = R(g): T1 = -(Dx (x) V) g, T2 = -(q/m)(diag(E) (x) Dv) g and, with
+    collisions, T3 = C g, each compressed (P5), then their sum compressed
+    (P4).  E from g alone (one electron species) unless given."""
     p = ops.p
-    E = field_mps(g, ops)
+    if E is None:
+        E = field_mps(g, ops)
     WE = diag_mpo(E)
     WE[0] = WE[0] * (-p.qm)
     W2 = chain_mpo(WE, ops.Dv, p.Lx, p.Lv, p.order)
-    T1 = compress_state(apply(ops.T1, g), caps(p, 5), p)
-    T2 = compress_state(apply(W2, g), caps(p, 5), p)
-    return compress_state(add([(1.0, T1), (1.0, T2)]), caps(p, 4), p)
+    terms = [compress_state(apply(ops.T1, g), caps(p, 5), p),
+             compress_state(apply(W2, g), caps(p, 5), p)]
+    if ops.T3 is not None:
+        terms.append(compress_state(apply(ops.T3, g), caps(p, 5), p))
+    return compress_state(add([(1.0, T) for T in terms]), caps(p, 4), p)
+
+
+def field_species_mps(gs: Sequence[Mps], opss: Sequence[Operators],
+                      charges: Sequence[float]) -> Mps:
+    """E of several species: rho = sum_s (-q_s) n_s as a direct sum (exact),
+    then E = compress(-G rho, D_F, tol) with the first species' settings."""
+    ns = [density_mps(g, o.p.Lx, o.p.Lv, o.p.order, o.p.dv) for g, o in zip(gs, opss)]
+    rho = add([(-q, n) for q, n in zip(charges, ns)])
+    p = opss[0].p
+    En = scale(apply(opss[0].G, rho), -1.0)
+    return compress(En, p.df_max if p.df_max > 0 else None, p.tol)
+
+
+def rk4_step_species(fs: Sequence[Mps], opss: Sequence[Operators],
+                     charges: Sequence[float], dt: float) -> List[Mps]:
+    """RK4 of all species together (compression points per species as in
+    rk4_step), the field of each stage from all of them."""
+    def R(gs):
+        E = field_species_mps(gs, opss, charges)
+        return [rhs_mps(g, o, E) for g, o in zip(gs, opss)]
+
+    def stage(ks, c):
+        return [compress_state(add([(1.0, f), (c, k)]), caps(o.p, 2), o.p)
+                for f, k, o in zip(fs, ks, opss)]
+    k1 = R(fs)
+    k2 = R(stage(k1, 0.5 * dt))
+    k3 = R(stage(k2, 0.5 * dt))
+    k4 = R(stage(k3, dt))
+    out = []
+    for f, a, b, c, d, o in zip(fs, k1, k2, k3, k4, opss):
+        S = compress_state(add([(1.0, a), (2.0, b), (2.0, c), (1.0, d)]), caps(o.p, 3), o.p)
+        out.append(compress_state(add([(1.0, f), (dt / 6.0, S)]), o.p.chi_max, o.p))
+    return out
 
 
 def cfl_dt(f: Mps, ops: Operators) -> float:

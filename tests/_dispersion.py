@@ -43,3 +43,22 @@ def fit_rate(t, W, t0, t1, peaks=True):
         tt, ww = t[sel], W[sel]
     slope = np.polyfit(tt, np.log(ww), 1)[0]
     return 0.5 * slope, tt
+
+
+def dispersion_species(omega, k, species):
+    """1 + sum_s wp2_s / (k vth_s)^2 [1 + zeta_s Z(zeta_s)], zeta_s =
+    (omega - k u_s) / (sqrt(2) k vth_s), for species (wp2, vth, u)."""
+    eps = 1.0 + 0j
+    for wp2, vth, u in species:
+        z = (omega - k * u) / (np.sqrt(2.0) * k * vth)
+        Z = 1j * np.sqrt(np.pi) * wofz(z)
+        eps += wp2 / (k * vth) ** 2 * (1.0 + z * Z)
+    return eps
+
+
+def root_species(k, species, guess):
+    def f(xy):
+        e = dispersion_species(xy[0] + 1j * xy[1], k, species)
+        return [e.real, e.imag]
+    x, y = fsolve(f, [guess.real, guess.imag], xtol=1e-13)
+    return complex(x, y)

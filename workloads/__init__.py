@@ -50,6 +50,9 @@ class Problem:
     x_scheme: int = 0       # x advection: 0 central, 1 upwind (second order)
     cfl: float = 0.0        # > 0: adaptive dt, this fraction of the CFL limit
     compression: int = 0    # 0 sweep, 1 centre-first (sequential orderings)
+    nu: float = 0.0         # Dougherty collision rate (0: collisionless)
+    nu_v0: float = 0.0      # its drift velocity
+    nu_vth: float = 1.0     # its thermal speed
 
     @property
     def Nx(self) -> int:
@@ -112,6 +115,36 @@ def stable_dt(p: Problem, dt_cfg: Optional[float]) -> float:
         return dt_cfg
     lim = 1.3 * p.dx / vmax
     return lim if dt_cfg is None else min(dt_cfg, lim)
+
+
+def buneman(L: int = 9, Lv: Optional[int] = None, chi: int = 64, tol: float = 0.0,
+            level: int = 5, df_max: int = 0, order: int = ORDER_SEQ, k: float = 0.1,
+            A: float = 1e-3, mass_ratio: float = 25.0, dt_cfg: Optional[float] = None,
+            nu: float = 0.0):
+    """Buneman instability (Methods): electrons drifting at v0 = omega_pe / k
+    (= 1/k in these units) with unit thermal speed and a (1 + A cos kx)
+    perturbation, ions at rest with T_i = T_e (vth_i^2 = m_e / m_i); x in
+    [-pi/k, pi/k) periodic; v in +-6/k (electrons) and +-50 vth_i (ions).
+    Returns ([electron workload, ion workload], [q_e, q_i] = [-1, +1]); both
+    share Lx = L and dt (the electron CFL limit)."""
+    Lv = L if Lv is None else Lv
+    x0, x1 = -math.pi / k, math.pi / k
+    vth_i = math.sqrt(1.0 / mass_ratio)
+    pe = Problem(Lx=L, Lv=Lv, order=order, x_min=x0, x_max=x1, v_min=-6.0 / k,
+                 v_max=6.0 / k, qm=-1.0, chi_max=chi, level=level, df_max=df_max, tol=tol,
+                 nu=nu, nu_v0=1.0 / k, nu_vth=1.0)
+    pe.dt = stable_dt(pe, dt_cfg)
+    pi_ = Problem(Lx=L, Lv=Lv, order=order, x_min=x0, x_max=x1, v_min=-50.0 * vth_i,
+                  v_max=50.0 * vth_i, qm=1.0 / mass_ratio, dt=pe.dt, chi_max=chi,
+                  level=level, df_max=df_max, tol=tol, nu=nu, nu_v0=0.0, nu_vth=vth_i)
+    ve, vi = pe.v(), pi_.v()
+    ax_e = (1.0 + A * np.cos(k * pe.x()))[None, :]
+    bv_e = (np.exp(-0.5 * (ve - 1.0 / k) ** 2) / math.sqrt(2.0 * math.pi))[None, :]
+    ax_i = np.ones((1, pe.Nx))
+    bv_i = (np.exp(-0.5 * (vi / vth_i) ** 2) / math.sqrt(2.0 * math.pi * vth_i ** 2))[None, :]
+    tag = "2^%dx2^%d_chi%d" % (L, Lv, chi)
+    return ([Workload("buneman_electrons_" + tag, pe, ax_e, bv_e, 2000),
+             Workload("buneman_ions_" + tag, pi_, ax_i, bv_i, 2000)], [-1.0, 1.0])
 
 
 def landau_small(chi: int = 16, tol: float = 1e-10, level: int = 1,
