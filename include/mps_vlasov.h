@@ -138,7 +138,18 @@ typedef struct mps_problem {
   int32_t x_scheme;         /* mps_x_scheme                                */
   double cfl;               /* > 0: adaptive dt (see below), 0: fixed dt   */
   int32_t compression;      /* mps_compression                             */
+  double nu;                /* Dougherty collision rate, >= 0 (0: none)    */
+  double nu_v0, nu_vth;     /* its drift velocity and thermal speed        */
 } mps_problem;
+
+/* Collisions (Methods, "Collision Operator"): with nu > 0 the Vlasov
+ * right-hand side gains nu d/dv[(v - nu_v0) f + nu_vth^2 df/dv], the Dougherty
+ * operator with the species' drift and thermal speed taken as fixed
+ * parameters (a linear operator), both derivatives the zero-gradient central
+ * difference; as an MPO it is nu Dv (diag(v - nu_v0) + nu_vth^2 Dv) on the v
+ * sites, and its term of each k is compressed like the other two (P5).  With
+ * cfl > 0 the step adds nu |v|_max / dv + 2 nu nu_vth^2 / dv^2 to the CFL sum
+ * (eq. CFL).  The memory model of mps_workspace_bound does not include it. */
 
 typedef struct mps_state mps_state; /* opaque; owns all device memory */
 
@@ -227,6 +238,35 @@ mps_status mps_device_bytes(const mps_state* h, size_t* bytes);
  * returned, its message naming the instance. */
 mps_status mps_step_batched(mps_state* const* hs, int32_t count, int32_t nsteps,
                             hipStream_t stream);
+
+/* Several species sharing x and E (Methods: the two-species Landau and
+ * Buneman set-ups).  Each species is an mps_problem of its own (its v grid,
+ * q/m, collisions, compression settings); all share Lx, x_min, x_max and a
+ * fixed dt (cfl = 0).  Poisson becomes Laplacian(phi) = -sum_s q_s n_s with
+ * charges[s] = q_s (normalised units; the pseudo-inverse drops the mean,
+ * i.e. a neutralising background), E = -G rho compressed with species 0's
+ * df_max and tol.  One RK4 step advances every species, each stage's E from
+ * all of them; the new states are committed for all species or for none.
+ * mps_plasma_init: species, charges, ranks: host arrays of n_species (1..8);
+ * ax[s], bv[s]: device profiles of species s as for mps_init.  A single
+ * species of charge -1 is the one-species case of mps_step. */
+typedef struct mps_plasma mps_plasma;
+mps_status mps_plasma_init(int32_t n_species, const mps_problem* species,
+                           const double* charges, const int32_t* ranks,
+                           const double* const* ax, const double* const* bv,
+                           hipStream_t stream, mps_plasma** out);
+mps_status mps_plasma_step(mps_plasma* pl, int32_t nsteps, hipStream_t stream);
+/* Species s as a state handle owned by the plasma (NULL if out of range):
+ * mps_to_dense, mps_get_cores / mps_set_cores, mps_info, mps_entanglement and
+ * mps_moments (density and scalars; its field there is of that species alone)
+ * apply; mps_step and mps_free refuse it. */
+mps_state* mps_plasma_species(mps_plasma* pl, int32_t s);
+/* The shared field: E_out device double[Nx] or NULL; field_energy host
+ * double or NULL = dx sum E^2 / 2.  Synchronises the stream. */
+mps_status mps_plasma_field(mps_plasma* pl, double* E_out, double* field_energy,
+                            hipStream_t stream);
+/* Release the plasma and its species.  NULL is accepted. */
+mps_status mps_plasma_free(mps_plasma* pl);
 
 /* Thread-local text of the last error ("" if none). */
 const char* mps_last_error(void);

@@ -163,7 +163,12 @@ def cfl_dt(F: np.ndarray, p) -> float:
     no collisions)."""
     vmax = max(abs(p.v_min), abs(p.v_max))
     emax = float(np.abs(field(F, p)).max())
-    return p.cfl / (vmax / p.dx + abs(p.qm) * emax / p.dv)
+    inv = vmax / p.dx + abs(p.qm) * emax / p.dv
+    nu = getattr(p, "nu", 0.0)
+    if nu != 0.0:
+        # the collision terms of eq. CFL
+        inv += nu * vmax / p.dv + 2.0 * nu * p.nu_vth ** 2 / p.dv ** 2
+    return p.cfl / inv
 
 
 def rk4_step(F: np.ndarray, p, dt: float | None = None) -> np.ndarray:

@@ -792,7 +792,12 @@ def cfl_dt(f: Mps, ops: Operators) -> float:
     p = ops.p
     vmax = max(abs(p.v_min), abs(p.v_max))
     emax = float(np.abs(field_dense(f, ops)).max())
-    return p.cfl / (vmax / p.dx + abs(p.qm) * emax / p.dv)
+    inv = vmax / p.dx + abs(p.qm) * emax / p.dv
+    nu = getattr(p, "nu", 0.0)
+    if nu != 0.0:
+        # the collision terms of eq. CFL
+        inv += nu * vmax / p.dv + 2.0 * nu * p.nu_vth ** 2 / p.dv ** 2
+    return p.cfl / inv
 
 
 def rk4_step(f: Mps, ops: Operators) -> Mps:

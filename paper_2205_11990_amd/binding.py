@@ -38,6 +38,7 @@ class CProblem(ctypes.Structure):
         ("df_max", ctypes.c_int32), ("tol", ctypes.c_double),
         ("precision", ctypes.c_int32), ("x_scheme", ctypes.c_int32),
         ("cfl", ctypes.c_double), ("compression", ctypes.c_int32),
+        ("nu", ctypes.c_double), ("nu_v0", ctypes.c_double), ("nu_vth", ctypes.c_double),
     ]
 
 
@@ -69,6 +70,11 @@ _SIGS = {
     "mpsb_qr": [_I32, _I32, _P, _P, _P],
     "mpsb_svd_truncate": [_I32, _I32, _P, _I32, _D, _P, _P, _P, _PI32, _PD, _P],
     "mpsb_compress": [_I32, _PI32, _P, _PI32, _P, _I32, _D, _PI32, _P, _I64, _PD, _P],
+    "mps_plasma_init": [_I32, _P, _P, _P, _P, _P, _P, _P],
+    "mps_plasma_step": [_P, _I32, _P],
+    "mps_plasma_species": [_P, _I32],
+    "mps_plasma_field": [_P, _P, _PD, _P],
+    "mps_plasma_free": [_P],
     "mpsb_step_graph": [_P, _I32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
     "mpsb_compress_centre": [_I32, _I32, _PI32, _P, _I32, _D, _PI32, _P, _I64, _PD, _P],
     "mpsb_add_compress": [_I32, _I32, _PD, _PI32, ctypes.POINTER(_P), _I32, _D,
@@ -100,7 +106,8 @@ def lib() -> ctypes.CDLL:
         for name, args in _SIGS.items():
             f = getattr(L, name)
             f.argtypes = args
-            f.restype = ctypes.c_char_p if name == "mps_last_error" else ctypes.c_int
+            f.restype = (ctypes.c_char_p if name == "mps_last_error" else
+                         ctypes.c_void_p if name == "mps_plasma_species" else ctypes.c_int)
         _lib = L
     return _lib
 
@@ -149,6 +156,9 @@ def make_problem(p) -> CProblem:
     c.x_scheme = int(getattr(p, "x_scheme", 0))
     c.cfl = float(getattr(p, "cfl", 0.0))
     c.compression = int(getattr(p, "compression", 0))
+    c.nu = float(getattr(p, "nu", 0.0))
+    c.nu_v0 = float(getattr(p, "nu_v0", 0.0))
+    c.nu_vth = float(getattr(p, "nu_vth", 1.0))
     return c
 
 
@@ -278,8 +288,68 @@ class MpsState:
                                     _ptr(d), _stream(stream)))
 
     def free(self):
+        if getattr(self, "_borrowed", False):
+            self._h = ctypes.c_void_p()
+            return
         if getattr(self, "_h", None) is not None and self._h.value:
             _check(lib().mps_free(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Plasma:
+    """Several species sharing x and E (mps_plasma_*): problems, charges
+    and (ax, bv) profiles per species."""
+
+    def __init__(self, problems, charges, profiles, stream=None):
+        L = lib()
+        n = len(problems)
+        self.problems = list(problems)
+        arr = (CProblem * n)(*[make_problem(p) for p in problems])
+        q = (ctypes.c_double * n)(*[float(c) for c in charges])
+        self._dev = [(_dev(np.atleast_2d(a)), _dev(np.atleast_2d(b))) for a, b in profiles]
+        ranks = (ctypes.c_int32 * n)(*[int(a.shape[0]) for a, _ in self._dev])
+        axp = (ctypes.c_void_p * n)(*[a.data_ptr() for a, _ in self._dev])
+        bvp = (ctypes.c_void_p * n)(*[b.data_ptr() for _, b in self._dev])
+        h = ctypes.c_void_p()
+        _check(L.mps_plasma_init(n, ctypes.cast(arr, _P), ctypes.cast(q, _P),
+                                 ctypes.cast(ranks, _P), ctypes.cast(axp, _P),
+                                 ctypes.cast(bvp, _P), _stream(stream), ctypes.byref(h)))
+        self._h = h
+
+    def step(self, nsteps: int = 1, stream=None):
+        _check(lib().mps_plasma_step(self._h, int(nsteps), _stream(stream)))
+
+    def species(self, s: int) -> "MpsState":
+        """Species s as a state (owned by the plasma: not freed by it)."""
+        hp = lib().mps_plasma_species(self._h, int(s))
+        if not hp:
+            raise MpsError("no species %d" % s)
+        st = MpsState.__new__(MpsState)
+        p = self.problems[s]
+        st.problem = p
+        st.Nx, st.Nv = 2 ** int(p.Lx), 2 ** int(p.Lv)
+        st._cp = make_problem(p)
+        st._h = ctypes.c_void_p(hp)
+        st._borrowed = True
+        return st
+
+    def field(self, stream=None):
+        torch = _torch()
+        nx = 2 ** int(self.problems[0].Lx)
+        E = torch.empty(nx, dtype=torch.float64, device="cuda")
+        w = ctypes.c_double()
+        _check(lib().mps_plasma_field(self._h, _ptr(E), ctypes.byref(w), _stream(stream)))
+        return E, w.value
+
+    def free(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(lib().mps_plasma_free(self._h))
             self._h = ctypes.c_void_p()
 
     def __del__(self):

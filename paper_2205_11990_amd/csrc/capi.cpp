@@ -23,6 +23,16 @@
 struct mps_state {
   std::unique_ptr<mpsv::Engine> eng;
   int device = 0;
+  bool in_plasma = false;  // owned by an mps_plasma (mps_free refuses it)
+};
+
+struct mps_plasma {
+  std::vector<mps_state*> species;  // owned
+  std::vector<double> charge;
+  int device = 0;
+  ~mps_plasma() {
+    for (auto* h : species) delete h;
+  }
 };
 
 namespace {
@@ -79,6 +89,9 @@ mpsv::Problem convert(const mps_problem* p) {
   q.x_scheme = p->x_scheme;
   q.cfl = p->cfl;
   q.compression = p->compression;
+  q.nu = p->nu;
+  q.nu_v0 = p->nu_v0;
+  q.nu_vth = p->nu_vth;
   MPSV_CHECK(std::isfinite(q.x_min) && std::isfinite(q.x_max) &&
                  std::isfinite(q.v_min) && std::isfinite(q.v_max),
              mpsv::kEinval, "grid bounds must be finite");
@@ -167,6 +180,8 @@ mps_status mps_step(mps_state* h, int32_t nsteps, hipStream_t stream) {
   return guarded([&] {
     check_handle(h);
     MPSV_CHECK(nsteps >= 0, mpsv::kEinval, "nsteps must be >= 0");
+    MPSV_CHECK(!h->in_plasma, mpsv::kEinval,
+               "a species of a plasma is stepped by mps_plasma_step");
     for (int i = 0; i < nsteps; ++i) h->eng->step(stream);
   });
 }
@@ -191,6 +206,8 @@ mps_status mps_to_dense(mps_state* h, double* f_out, hipStream_t stream) {
 mps_status mps_free(mps_state* h) {
   return guarded([&] {
     if (!h) return;
+    MPSV_CHECK(!h->in_plasma, mpsv::kEinval,
+               "a species of a plasma is released by mps_plasma_free");
     (void)hipDeviceSynchronize();
     delete h;
   });
@@ -588,3 +605,86 @@ mps_status mpsb_profile_read(int32_t cls, int64_t* launches, double* ms,
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------ plasmas
+
+mps_status mps_plasma_init(int32_t n_species, const mps_problem* species,
+                           const double* charges, const int32_t* ranks,
+                           const double* const* ax, const double* const* bv,
+                           hipStream_t stream, mps_plasma** out) {
+  return guarded([&] {
+    MPSV_CHECK(out != nullptr, mpsv::kEinval, "out is NULL");
+    *out = nullptr;
+    MPSV_CHECK(n_species >= 1 && n_species <= 8, mpsv::kEinval,
+               "n_species must lie in [1, 8]");
+    MPSV_CHECK(species && charges && ranks && ax && bv, mpsv::kEinval,
+               "NULL argument");
+    std::unique_ptr<mps_plasma> pl(new mps_plasma);
+    MPSV_HIP(hipGetDevice(&pl->device));
+    std::vector<mpsv::Problem> qs;
+    for (int i = 0; i < n_species; ++i) qs.push_back(convert(&species[i]));
+    const mpsv::Problem& a = qs[0];
+    for (int i = 0; i < n_species; ++i) {
+      const mpsv::Problem& b = qs[i];
+      MPSV_CHECK(b.Lx == a.Lx && b.x_min == a.x_min && b.x_max == a.x_max,
+                 mpsv::kEinval, "species must share the x grid");
+      MPSV_CHECK(b.dt == a.dt && b.cfl == 0.0, mpsv::kEinval,
+                 "species must share a fixed dt (cfl = 0)");
+      MPSV_CHECK(std::isfinite(charges[i]), mpsv::kEinval, "charge must be finite");
+      MPSV_CHECK(ax[i] && bv[i], mpsv::kEinval, "profiles must not be NULL");
+    }
+    for (int i = 0; i < n_species; ++i) {
+      std::unique_ptr<mps_state> h(new mps_state);
+      h->device = pl->device;
+      h->in_plasma = true;
+      h->eng.reset(new mpsv::Engine(qs[i]));
+      h->eng->init_from_profiles(ranks[i], ax[i], bv[i], stream);
+      pl->species.push_back(h.release());
+      pl->charge.push_back(charges[i]);
+    }
+    *out = pl.release();
+  });
+}
+
+namespace {
+std::vector<mpsv::Engine*> engines_of(mps_plasma* pl) {
+  MPSV_CHECK(pl != nullptr && !pl->species.empty(), mpsv::kEinval,
+             "plasma handle is NULL");
+  int dev = -1;
+  MPSV_HIP(hipGetDevice(&dev));
+  MPSV_CHECK(dev == pl->device, mpsv::kEinval,
+             "plasma was created on another device than the current one");
+  std::vector<mpsv::Engine*> es;
+  for (auto* h : pl->species) es.push_back(h->eng.get());
+  return es;
+}
+}  // namespace
+
+mps_status mps_plasma_step(mps_plasma* pl, int32_t nsteps, hipStream_t stream) {
+  return guarded([&] {
+    auto es = engines_of(pl);
+    MPSV_CHECK(nsteps >= 0, mpsv::kEinval, "nsteps must be >= 0");
+    for (int i = 0; i < nsteps; ++i) mpsv::step_species(es, pl->charge, stream);
+  });
+}
+
+mps_state* mps_plasma_species(mps_plasma* pl, int32_t s) {
+  if (!pl || s < 0 || s >= (int32_t)pl->species.size()) return nullptr;
+  return pl->species[(size_t)s];
+}
+
+mps_status mps_plasma_field(mps_plasma* pl, double* E_out, double* field_energy,
+                            hipStream_t stream) {
+  return guarded([&] {
+    auto es = engines_of(pl);
+    mpsv::field_species_dense(es, pl->charge, E_out, field_energy, stream);
+  });
+}
+
+mps_status mps_plasma_free(mps_plasma* pl) {
+  return guarded([&] {
+    if (!pl) return;
+    (void)hipDeviceSynchronize();
+    delete pl;
+  });
+}

@@ -398,6 +398,33 @@ HostMpo mpo_add(const HostMpo& A, const std::vector<int>& ba, const HostMpo& B,
   return W;
 }
 
+HostMpo mpo_product(const HostMpo& A, const std::vector<int>& ba,
+                    const HostMpo& B, const std::vector<int>& bb,
+                    std::vector<int>& bonds) {
+  const int L = (int)A.size();
+  if ((int)B.size() != L) throw Error(kEinval, "mpo_product: bad lengths");
+  bonds.assign(L + 1, 1);
+  for (int k = 0; k <= L; ++k) bonds[k] = ba[k] * bb[k];
+  HostMpo W(L);
+  for (int k = 0; k < L; ++k) {
+    const int al = ba[k], ar = ba[k + 1], cl = bb[k], cr = bb[k + 1];
+    const int br = ar * cr;
+    W[k].assign((size_t)al * cl * 4 * br, 0.0);
+    for (int a = 0; a < al; ++a)
+      for (int c = 0; c < cl; ++c)
+        for (int o = 0; o < 2; ++o)
+          for (int i = 0; i < 2; ++i)
+            for (int b = 0; b < ar; ++b)
+              for (int d = 0; d < cr; ++d) {
+                double t = 0.0;
+                for (int m = 0; m < 2; ++m)
+                  t += A[k][widx(ar, a, o, m, b)] * B[k][widx(cr, c, m, i, d)];
+                W[k][widx(br, a * cl + c, o, i, b * cr + d)] = t;
+              }
+  }
+  return W;
+}
+
 // Full-chain tensor for P physical values per site (4: MPO, 2: MPS).  A
 // dimension read fine to coarse (S2: x, S3: v) takes its cores in reverse
 // order with their two bonds swapped.
@@ -559,6 +586,9 @@ Engine::Engine(const Problem& p) : p_(p), chunk_(memory_model(p).chunk) {
   MPSV_CHECK(p.x_scheme == 0 || p.x_scheme == 1, kEinval,
              "unknown x advection scheme");
   MPSV_CHECK(std::isfinite(p.qm), kEinval, "q/m must be finite");
+  MPSV_CHECK(std::isfinite(p.nu) && p.nu >= 0 && std::isfinite(p.nu_v0) &&
+                 std::isfinite(p.nu_vth),
+             kEinval, "collision parameters must be finite, nu >= 0");
   MPSV_CHECK(p.compression == 0 || p.compression == 1, kEinval,
              "unknown compression scheme");
   MPSV_CHECK(p.compression == 0 || p.order != 1, kEinval,
@@ -594,6 +624,23 @@ Engine::Engine(const Problem& p) : p_(p), chunk_(memory_model(p).chunk) {
   t1_ = upload_mpo(T1, bt1, ops_, s);
   auto G = ops::poisson_g(p.Lx, p.dx(), -1.0, bg);  // E = -G n
   gneg_ = upload_mpo(G, bg, ops_, s);
+  if (p.nu != 0.0) {
+    // Dougherty collisions with the species' fixed drift and thermal speed
+    // (Methods, Collision Operator): nu Dv (diag(v - v0) + vth^2 Dv) on the
+    // v sites, the identity on the x sites
+    std::vector<int> bd, bpd, bin, bcv, bcc;
+    auto D1 = ops::d1_zero_gradient(p.Lv, p.dv(), bd);
+    auto Vd = ops::poly_diag(p.Lv, p.v_min - p.nu_v0, p.dv(), 0.0, bpd);
+    auto Ds = D1;
+    for (auto& x : Ds[0]) x *= p.nu_vth * p.nu_vth;
+    auto inner = ops::mpo_add(Vd, bpd, Ds, bd, bin);
+    auto Cv = ops::mpo_product(D1, bd, inner, bin, bcv);
+    for (auto& x : Cv[0]) x *= p.nu;
+    ops::HostMpo Ix((size_t)p.Lx, std::vector<double>{1.0, 0.0, 0.0, 1.0});
+    std::vector<int> bix((size_t)p.Lx + 1, 1);
+    auto Cc = ops::chain(Ix, bix, Cv, bcv, p.order, bcc);
+    coll_ = upload_mpo(Cc, bcc, ops_, s);
+  }
   auto Dv = ops::d1_zero_gradient(p.Lv, p.dv(), bdv);
   if (p.order == 3) {
     // v read fine to coarse (S3): Dv in chain order
@@ -1172,7 +1219,7 @@ DMpo Engine::t2_mpo(const DMps& En, Arena& ar, hipStream_t s) {
 }
 
 // k = R(g) = -v d/dx g - (q/m) E d/dv g  (eq. 1, C = 0)
-DMps Engine::rhs(const DMps& g, Arena& out, hipStream_t s) {
+DMps Engine::rhs(const DMps& g, Arena& out, hipStream_t s, const DMps* Eext) {
   ArenaScope sc(tmp_);
   ArenaScope sc2(tmp2_);
   // The two terms share only their input g.  T1 = -(Dx V) g is compressed
@@ -1194,11 +1241,13 @@ DMps Engine::rhs(const DMps& g, Arena& out, hipStream_t s) {
     }
     tl_work = nullptr;
   });
-  DMps T2;
+  DMps T2, T3;
   try {
-    DMps E = field(g, tmp_, s);
-    DMpo W2 = t2_mpo(E, tmp_, s);
+    DMps E;
+    if (!Eext) E = field(g, tmp_, s);
+    DMpo W2 = t2_mpo(Eext ? *Eext : E, tmp_, s);
     T2 = apply_compress(W2, g, cap_for(5), p_.tol, tmp_, s);
+    if (!coll_.empty()) T3 = apply_compress(coll_, g, cap_for(5), p_.tol, tmp_, s);
   } catch (...) {
     side.join();
     (void)hipStreamSynchronize(side_);
@@ -1210,19 +1259,160 @@ DMps Engine::rhs(const DMps& g, Arena& out, hipStream_t s) {
     std::rethrow_exception(side_err);
   }
   MPSV_HIP(hipStreamWaitEvent(s, ev_join_, 0));
-  return add_terms({{1.0, &T1}, {1.0, &T2}}, cap_for(4), out, s);
+  if (coll_.empty()) return add_terms({{1.0, &T1}, {1.0, &T2}}, cap_for(4), out, s);
+  return add_terms({{1.0, &T1}, {1.0, &T2}, {1.0, &T3}}, cap_for(4), out, s);
 }
 
 void Engine::commit(const DMps& fn, hipStream_t s) {
   // finiteness check first: the state only changes when the step is clean
+  check_finite(fn, s);
+  install(fn, s);
+}
+
+void Engine::check_finite(const DMps& fn, hipStream_t s) {
   fill_int(s, dflag_, 1, 0);
   for (auto& c : fn) count_nonfinite(s, c.p, c.size(), dflag_);
   int bad = 0;
   MPSV_HIP(hipMemcpyAsync(&bad, dflag_, sizeof(int), hipMemcpyDeviceToHost, s));
   MPSV_HIP(hipStreamSynchronize(s));
   if (bad) throw Error(kEnumeric, "non-finite values in the new state");
+}
+
+void Engine::install(const DMps& fn, hipStream_t s) {
   state_.reset();
   f_ = copy_mps(fn, state_, s);
+}
+
+// Explicit direct sum of MPS of the same length (SI, Addition): block-
+// diagonal cores, each term's scalar in its first core.
+DMps Engine::direct_sum(const std::vector<std::pair<double, const DMps*>>& t,
+                        Arena& ar, hipStream_t s) {
+  const int n = (int)t[0].second->size();
+  DMps out(n);
+  for (int j = 0; j < n; ++j) {
+    int L = 0, R = 0;
+    for (auto& x : t) {
+      L += (*x.second)[j].l;
+      R += (*x.second)[j].r;
+    }
+    if (j == 0) L = 1;
+    if (j == n - 1) R = 1;
+    Core C{ar.alloc((size_t)L * 2 * R), L, R};
+    fill(s, C.p, C.size(), 0.0);
+    int lo = 0, ro = 0;
+    for (auto& x : t) {
+      const Core& A = (*x.second)[j];
+      // A as (2 l) x r rows at row 2 lo, column ro of C as (2 L) x R
+      copy2d(s, 2 * A.l, A.r, j == 0 ? x.first : 1.0, A.p, A.r,
+             C.p + (long)2 * lo * R + ro, R);
+      if (j > 0) lo += A.l;
+      if (j < n - 1) ro += A.r;
+    }
+    out[j] = C;
+  }
+  return out;
+}
+
+// E of several species sharing x (Problem Statement eqs. 2-3 with the
+// charge density of every species): rho = sum_s (-q_s) n_s formed exactly,
+// E = compress(-G rho, D_F, tol) with the first species' settings.  The
+// result and its inputs live in es[0]'s arena `ar`.
+DMps field_of_species(const std::vector<Engine*>& es, const std::vector<double>& q,
+                      const std::vector<const DMps*>& gs, Arena& ar, hipStream_t s) {
+  Engine& e0 = *es[0];
+  std::vector<DMps> ns(es.size());
+  for (size_t i = 0; i < es.size(); ++i) ns[i] = es[i]->density(*gs[i], ar, s);
+  std::vector<std::pair<double, const DMps*>> t;
+  for (size_t i = 0; i < es.size(); ++i) t.push_back({-q[i], &ns[i]});
+  const DMps rho = (es.size() == 1) ? ns[0] : e0.direct_sum(t, ar, s);
+  if (es.size() == 1 && q[0] != -1.0) {
+    // one species of another charge: scale its density instead
+    copy2d(s, 1, (int)rho[0].size(), -q[0], rho[0].p, rho[0].size(), rho[0].p,
+           rho[0].size());
+  }
+  return e0.apply_compress(e0.gneg_, rho, e0.p_.df_max > 0 ? e0.p_.df_max : INT_MAX,
+                           e0.p_.tol, ar, s);
+}
+
+// One RK4 step of several species with a shared field (each stage's E from
+// all of them), every species with its own compression points, committed
+// for all or for none.
+void step_species(const std::vector<Engine*>& es, const std::vector<double>& q,
+                  hipStream_t s) {
+  const size_t S = es.size();
+  for (auto* e : es) MPSV_CHECK(!e->f_.empty(), kEinval, "state not initialised");
+  Engine& e0 = *es[0];
+  const double h = e0.p_.dt;
+  for (auto* e : es) e->step_.reset();
+  svd_defer_begin(s);
+  for (auto* e : es) svd_defer_begin(e->side_);
+  std::vector<DMps> fn(S);
+  try {
+    auto R = [&](const std::vector<const DMps*>& gs) {
+      DMps E = field_of_species(es, q, gs, e0.step_, s);
+      std::vector<DMps> k(S);
+      for (size_t i = 0; i < S; ++i) k[i] = es[i]->rhs(*gs[i], es[i]->step_, s, &E);
+      return k;
+    };
+    auto stage = [&](const std::vector<DMps>& k, double c) {
+      std::vector<DMps> g(S);
+      for (size_t i = 0; i < S; ++i)
+        g[i] = es[i]->add_terms({{1.0, &es[i]->f_}, {c, &k[i]}}, es[i]->cap_for(2),
+                                es[i]->step_, s);
+      return g;
+    };
+    auto ptrs = [](const std::vector<DMps>& v) {
+      std::vector<const DMps*> p;
+      for (auto& x : v) p.push_back(&x);
+      return p;
+    };
+    std::vector<const DMps*> f0;
+    for (auto* e : es) f0.push_back(&e->f_);
+    const auto k1 = R(f0);
+    const auto g2 = stage(k1, 0.5 * h);
+    const auto k2 = R(ptrs(g2));
+    const auto g3 = stage(k2, 0.5 * h);
+    const auto k3 = R(ptrs(g3));
+    const auto g4 = stage(k3, h);
+    const auto k4 = R(ptrs(g4));
+    for (size_t i = 0; i < S; ++i) {
+      Engine& e = *es[i];
+      DMps Sk = e.add_terms({{1.0, &k1[i]}, {2.0, &k2[i]}, {2.0, &k3[i]}, {1.0, &k4[i]}},
+                            e.cap_for(3), e.step_, s);
+      fn[i] = e.add_terms({{1.0, &e.f_}, {h / 6.0, &Sk}}, cap_or_inf(e.p_.chi_max),
+                          e.step_, s);
+    }
+    for (auto* e : es) svd_defer_end(e->side_);
+    svd_defer_end(s);
+  } catch (...) {
+    for (auto* e : es) svd_defer_cancel(e->side_);
+    svd_defer_cancel(s);
+    throw;
+  }
+  for (size_t i = 0; i < S; ++i) es[i]->check_finite(fn[i], s);
+  for (size_t i = 0; i < S; ++i) {
+    es[i]->install(fn[i], s);
+    es[i]->t_ += h;
+    ++es[i]->steps_;
+  }
+}
+
+void field_species_dense(const std::vector<Engine*>& es, const std::vector<double>& q,
+                         double* E_out, double* energy, hipStream_t s) {
+  Engine& e0 = *es[0];
+  ArenaScope sc(e0.tmp_);
+  std::vector<const DMps*> gs;
+  for (auto* e : es) gs.push_back(&e->f_);
+  DMps E = field_of_species(es, q, gs, e0.tmp_, s);
+  const long nx = e0.p_.Nx();
+  double* Ed = E_out ? E_out : e0.tmp_.alloc((size_t)nx);
+  e0.dense_of(E, Ed, s);
+  if (energy) {
+    double* w = e0.tmp_.alloc(1);
+    sum_squares(s, Ed, nx, 0.5 * e0.p_.dx(), w);
+    MPSV_HIP(hipMemcpyAsync(energy, w, sizeof(double), hipMemcpyDeviceToHost, s));
+  }
+  MPSV_HIP(hipStreamSynchronize(s));
 }
 
 std::vector<double> Engine::entanglement(hipStream_t s) {
@@ -1268,7 +1458,10 @@ double Engine::step_size(hipStream_t s) {
   for (double e : h) emax = std::max(emax, std::fabs(e));
   MPSV_CHECK(std::isfinite(emax), kEnumeric, "non-finite field");
   const double vmax = std::max(std::fabs(p_.v_min), std::fabs(p_.v_max));
-  return p_.cfl / (vmax / p_.dx() + std::fabs(p_.qm) * emax / p_.dv());
+  double inv = vmax / p_.dx() + std::fabs(p_.qm) * emax / p_.dv();
+  if (p_.nu != 0.0)
+    inv += p_.nu * vmax / p_.dv() + 2.0 * p_.nu * p_.nu_vth * p_.nu_vth / (p_.dv() * p_.dv());
+  return p_.cfl / inv;
 }
 
 void Engine::step(hipStream_t s) {

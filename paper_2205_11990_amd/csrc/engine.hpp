@@ -19,6 +19,7 @@ struct Problem {
   int x_scheme = 0;  // 0 central, 1 upwind x advection
   double cfl = 0.0;  // > 0: adaptive dt, this fraction of the CFL limit
   int compression = 0;  // 0 sweep, 1 centre-first (sequential orderings)
+  double nu = 0.0, nu_v0 = 0.0, nu_vth = 1.0;  // Dougherty collisions
   int n() const { return Lx + Lv; }
   long Nx() const { return 1L << Lx; }
   long Nv() const { return 1L << Lv; }
@@ -80,7 +81,22 @@ struct StepTimers {
   double compress_ms = 0;
 };
 
+class Engine;
+// several species sharing x and E (see step_species in engine.cpp)
+void step_species(const std::vector<Engine*>& es, const std::vector<double>& q,
+                  hipStream_t s);
+void field_species_dense(const std::vector<Engine*>& es, const std::vector<double>& q,
+                         double* E_out, double* energy, hipStream_t s);
+
 class Engine {
+  friend void step_species(const std::vector<Engine*>&, const std::vector<double>&,
+                           hipStream_t);
+  friend void field_species_dense(const std::vector<Engine*>&,
+                                  const std::vector<double>&, double*, double*,
+                                  hipStream_t);
+  friend DMps field_of_species(const std::vector<Engine*>&, const std::vector<double>&,
+                               const std::vector<const DMps*>&, Arena&, hipStream_t);
+
  public:
   explicit Engine(const Problem& p);
   ~Engine();
@@ -174,7 +190,11 @@ class Engine {
   DMps density(const DMps& g, Arena& ar, hipStream_t s);
   DMps field(const DMps& g, Arena& ar, hipStream_t s);
   DMpo t2_mpo(const DMps& E, Arena& ar, hipStream_t s);
-  DMps rhs(const DMps& g, Arena& out, hipStream_t s);
+  DMps rhs(const DMps& g, Arena& out, hipStream_t s, const DMps* Eext = nullptr);
+  DMps direct_sum(const std::vector<std::pair<double, const DMps*>>& t, Arena& ar,
+                  hipStream_t s);
+  void check_finite(const DMps& fn, hipStream_t s);
+  void install(const DMps& fn, hipStream_t s);
   // the four RK4 stages of one step; the new state is left in staged_
   void step_stages(double h, hipStream_t s);
   void step_eager(double h, hipStream_t s);
@@ -219,6 +239,7 @@ class Engine {
   SvdDeferRecord rec_own_, rec_side_;
   long graph_captures_ = 0, graph_replays_ = 0;
   DMpo t1_, gneg_, dv_;            // T1 chain, -G (x sites), Dv (v sites)
+  DMpo coll_;                      // collision operator chain (nu > 0)
   DMps vpoly_, v2poly_;            // moment weights (full chain)
   DMps f_;
   DMps staged_;  // the new state of the step in flight (step_ arena)
@@ -250,6 +271,9 @@ std::vector<std::vector<double>> poly_mps(int L, double c0, double c1, double c2
                                           std::vector<int>& bonds);
 HostMpo chain(const HostMpo& Wx, const std::vector<int>& bx, const HostMpo& Wv,
               const std::vector<int>& bv, int order, std::vector<int>& bonds);
+// operator product A B, bonds multiplied (A-major)
+HostMpo mpo_product(const HostMpo& A, const std::vector<int>& ba, const HostMpo& B,
+                    const std::vector<int>& bb, std::vector<int>& bonds);
 // the same chain read from its last site: cores (l, P, r) -> (r, P, l)
 HostMpo reverse(const HostMpo& W, const std::vector<int>& bonds, int P,
                 std::vector<int>& out_bonds);

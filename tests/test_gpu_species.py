@@ -1,0 +1,145 @@
+"""GPU parity of collisions and of several species (Methods: Collision
+Operator; the two-species set-ups) through the C-ABI, against the dense and
+MPS oracles."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import dense as odense
+from oracle import mps as omps
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print("[case] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2205_11990_amd import binding
+    binding.lib()
+    return binding
+
+
+@pytest.mark.parametrize("order", [0, 1])
+def test_untruncated_collisional_steps_equal_dense_oracle(B, order):
+    _say("untruncated collisions order=%d" % order)
+    w = wl.landau_small(L=4, tol=0.0)
+    p = w.problem
+    p.order, p.chi_max, p.level = order, 1 << 20, 1
+    p.nu, p.nu_v0, p.nu_vth = 0.3, 0.2, 1.1
+    st = B.MpsState(p, w.ax, w.bv)
+    F = odense.initial(w.ax, w.bv)
+    for k in range(3):
+        st.step(1)
+        F = odense.rk4_step(F, p)
+        G = st.to_dense().cpu().numpy()
+        assert np.abs(G - F).max() <= 1e-12 * (k + 2) * np.abs(F).max(), k
+    st.free()
+
+
+def test_truncated_collisional_steps_match_mps_oracle(B):
+    _say("truncated collisions C5 chi8 two-stream L=5")
+    w = wl.two_stream(L=5, chi=8, tol=0.0, level=5, df_max=4, dt_cfg=0.05, order=0)
+    p = w.problem
+    p.nu, p.nu_v0, p.nu_vth = 0.2, 0.0, 1.0
+    st = B.MpsState(p, w.ax, w.bv)
+    st.add_scaled(1e-3, wl.random_mps_cores(p.n_sites, 8, seed=2205))
+    f = st.get_cores_host()
+    ops = omps.Operators(p)
+    for _ in range(2):
+        st.step(1)
+        f = omps.rk4_step(f, ops)
+    G = st.to_dense().cpu().numpy()
+    R = omps.to_dense(f, p)
+    _, E = st.density_field()
+    Eref = omps.field_dense(f, ops)
+    assert np.abs(G - R).max() <= 1e-8 * np.abs(R).max()
+    assert np.abs(E.cpu().numpy() - Eref).max() <= 1e-8 * np.abs(Eref).max()
+    assert st.info()["bonds"][1:-1] == omps.bond_dims(f)
+    st.free()
+
+
+def test_one_species_plasma_equals_the_single_species_step(B):
+    _say("plasma of one electron species == mps_step")
+    w = wl.landau_small(L=5, chi=16, tol=1e-10)
+    p = w.problem
+    pl = B.Plasma([p], [-1.0], [(w.ax, w.bv)])
+    st = B.MpsState(p, w.ax, w.bv)
+    pl.step(3)
+    st.step(3)
+    a = pl.species(0).get_cores_host()
+    b = st.get_cores_host()
+    assert [x.shape for x in a] == [x.shape for x in b]
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    E, W = pl.field()
+    _, E1 = st.density_field()
+    assert np.array_equal(E.cpu().numpy(), E1.cpu().numpy())
+    st.free()
+    pl.free()
+
+
+def test_untruncated_buneman_plasma_equals_dense_oracle(B):
+    _say("untruncated buneman plasma Lx=3 Lv=4")
+    ws, q = wl.buneman(L=3, Lv=4, chi=1 << 20, tol=0.0, level=1)
+    ps = [w.problem for w in ws]
+    for p in ps:
+        p.nu = 0.05
+    pl = B.Plasma(ps, q, [(w.ax, w.bv) for w in ws])
+    Fs = [odense.initial(w.ax, w.bv) for w in ws]
+    for _ in range(3):
+        pl.step(1)
+        Fs = odense.rk4_step_species(Fs, ps, q, ps[0].dt)
+    for s, (F, p) in enumerate(zip(Fs, ps)):
+        G = pl.species(s).to_dense().cpu().numpy()
+        assert np.abs(G - F).max() <= 1e-11 * np.abs(F).max(), s
+    E, W = pl.field()
+    Ed = odense.field_species(Fs, ps, q)
+    assert np.abs(E.cpu().numpy() - Ed).max() <= 1e-10 * np.abs(Ed).max()
+    assert abs(W - 0.5 * ps[0].dx * np.sum(Ed ** 2)) <= 1e-10 * W
+    pl.free()
+
+
+@pytest.mark.parametrize("order", [0, 1])
+def test_truncated_buneman_plasma_matches_mps_oracle(B, order):
+    """Electrons and ions, every point capped (C5, chi = 8, D_F = 4), the
+    electrons perturbed to full bonds: both species and the shared field
+    within 1e-8 of the MPS oracle after 2 steps from the same states."""
+    _say("truncated buneman plasma L=5 chi8 order=%d" % order)
+    ws, q = wl.buneman(L=5, chi=8, tol=0.0, level=5, df_max=4, order=order)
+    ps = [w.problem for w in ws]
+    pl = B.Plasma(ps, q, [(w.ax, w.bv) for w in ws])
+    pl.species(0).add_scaled(1e-4, wl.random_mps_cores(ps[0].n_sites, 8, seed=2205))
+    fs = [pl.species(s).get_cores_host() for s in range(2)]
+    opss = [omps.Operators(p) for p in ps]
+    for _ in range(2):
+        pl.step(1)
+        fs = omps.rk4_step_species(fs, opss, q, ps[0].dt)
+    for s, (f, p) in enumerate(zip(fs, ps)):
+        st = pl.species(s)
+        G = st.to_dense().cpu().numpy()
+        R = omps.to_dense(f, p)
+        assert np.abs(G - R).max() <= 1e-8 * np.abs(R).max(), s
+        assert st.info()["bonds"][1:-1] == omps.bond_dims(f), s
+    E, _ = pl.field()
+    Eref = omps.to_vector(omps.field_species_mps(fs, opss, q))
+    assert np.abs(E.cpu().numpy() - Eref).max() <= 1e-8 * np.abs(Eref).max()
+    pl.free()
+
+
+def test_plasma_species_cannot_be_stepped_or_freed_alone(B):
+    _say("plasma species handles are owned by the plasma")
+    ws, q = wl.buneman(L=3, Lv=4, chi=8)
+    pl = B.Plasma([w.problem for w in ws], q, [(w.ax, w.bv) for w in ws])
+    st = pl.species(1)
+    with pytest.raises(B.MpsError):
+        st.step(1)
+    assert B.lib().mps_free(st.handle) != 0
+    pl.free()

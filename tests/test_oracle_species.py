@@ -144,3 +144,18 @@ def test_buneman_growth_rate_matches_the_kinetic_dispersion_root():
     sel = (T >= 15.0) & (T <= 35.0)
     rate = np.polyfit(T[sel], np.log(A[sel]), 1)[0]
     assert abs(rate - gamma) < 0.05 * gamma, (rate, gamma)
+
+
+def test_cfl_step_adds_the_collision_terms():
+    w = wl.landau_small(L=4)
+    p = w.problem
+    p.cfl = 0.9
+    F = dense.initial(w.ax, w.bv)
+    dt0 = dense.cfl_dt(F, p)
+    p.nu, p.nu_vth = 0.5, 1.0
+    dt1 = dense.cfl_dt(F, p)
+    vmax = max(abs(p.v_min), abs(p.v_max))
+    extra = p.nu * vmax / p.dv + 2.0 * p.nu / p.dv ** 2
+    assert abs(1.0 / dt1 - (1.0 / dt0 + extra / p.cfl)) < 1e-12 / dt1
+    f = mps.init_mps(p, w.ax, w.bv)
+    assert abs(mps.cfl_dt(f, mps.Operators(p)) - dt1) < 1e-12 * dt1
