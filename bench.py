@@ -273,6 +273,38 @@ def orderings(binding, steps):
     return out
 
 
+def buneman_run(binding, steps):
+    """Electrons and ions (Buneman instability, 2^9 x 2^9 per species, S1,
+    every point capped at chi = 64, D_F = 4, tol = 0), collisionless and
+    with Dougherty collisions (nu = 0.01): plasma steps/s of both species
+    with the shared field, from states perturbed to full bonds, and the
+    field energy after the timed steps."""
+    import torch
+    out = {}
+    for name, nu in (("collisionless", 0.0), ("collisions_nu_0.01", 0.01)):
+        ws, q = wl.buneman(L=9, chi=64, tol=0.0, level=5, df_max=4, nu=nu)
+        ps = [w.problem for w in ws]
+        pl = binding.Plasma(ps, q, [(w.ax, w.bv) for w in ws])
+        for s_, (w, p) in enumerate(zip(ws, ps)):
+            amp = 1e-6 * float(np.linalg.norm(w.ax) * np.linalg.norm(w.bv))
+            pl.species(s_).add_scaled(amp, wl.random_mps_cores(p.n_sites, 64, seed=2205 + s_))
+        pl.step(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pl.step(steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        _, W = pl.field()
+        out[name] = {"steps_per_s": steps / el, "steps": steps, "dt": ps[0].dt,
+                     "field_energy": W,
+                     "max_bond": [int(max(pl.species(i).info()["bonds"])) for i in range(2)]}
+        pl.free()
+    out["workload"] = ("Buneman: electrons drifting at 1/k = 10 (v in +-60) and ions at rest "
+                       "(m_i/m_e = 25, v in +-50 vth_i), k = 0.1, A = 1e-3, 2^9 x 2^9 each, "
+                       "S1, chi = 64, C5, D_F = 4, tol = 0, seeded perturbation to full bonds")
+    return out
+
+
 def batched(binding, count, steps):
     """Aggregate steps/s of a parameter sweep stepped together, against the
     same instances stepped one after the other."""
@@ -427,6 +459,8 @@ def main():
         print("[bench] mixed %s" % json.dumps(extras["mixed"]), file=sys.stderr, flush=True)
         extras["chi128"] = chi128_run(binding, 3)
         print("[bench] chi128 %s" % json.dumps(extras["chi128"]), file=sys.stderr, flush=True)
+        extras["buneman"] = buneman_run(binding, 3)
+        print("[bench] buneman %s" % json.dumps(extras["buneman"]), file=sys.stderr, flush=True)
         extras["orderings"] = orderings(binding, 3)
         print("[bench] orderings %s" % json.dumps(extras["orderings"]), file=sys.stderr, flush=True)
         extras["batched"] = batched(binding, 64, 3)
