@@ -30,7 +30,8 @@ Sections of the paper followed here:
 * SI "Compressed time evolution algorithm": RK4 and compression levels C1-C5.
 * Results, "State Compressibility" (eq. 6 context) and Fig. 3 orderings:
   sequential S1, S2 (x fine->coarse, v coarse->fine), S3 (x coarse->fine,
-  v fine->coarse) and interleaved IF maps.
+  v fine->coarse), interleaved IF and grouped IG (sites of dimension 4
+  holding x_k and v_k).
 
 Readings where the paper is silent or garbled (each also listed in the design doc):
 * The printed M_left of the zero-gradient derivative puts its only entry at
@@ -173,7 +174,7 @@ def add(terms: Sequence[Tuple[float, Mps]]) -> Mps:
         else:
             L = sum(b.shape[0] for b in blocks)
             R = sum(b.shape[2] for b in blocks)
-            C = np.zeros((L, 2, R))
+            C = np.zeros((L, blocks[0].shape[1], R))
             l0 = r0 = 0
             for b in blocks:
                 C[l0:l0 + b.shape[0], :, r0:r0 + b.shape[2]] = b
@@ -401,7 +402,7 @@ def mpo_sum(mpos: Sequence[Mpo]) -> Mpo:
         else:
             L = sum(b.shape[0] for b in blocks)
             R = sum(b.shape[3] for b in blocks)
-            C = np.zeros((L, 2, 2, R))
+            C = np.zeros((L, blocks[0].shape[1], blocks[0].shape[2], R))
             l0 = r0 = 0
             for b in blocks:
                 C[l0:l0 + b.shape[0], :, :, r0:r0 + b.shape[3]] = b
@@ -457,6 +458,18 @@ def mpo_product(A: Mpo, B: Mpo) -> Mpo:
         a, c, o, i, b, d = T.shape
         out.append(T.reshape(a * c, o, i, b * d))
     return out
+
+
+def mpo_to_matrix_d(W: Mpo, d: int) -> np.ndarray:
+    """Dense matrix of an MPO whose sites have dimension d (tests)."""
+    L = len(W)
+    T = W[0]
+    for Wj in W[1:]:
+        T = np.tensordot(T, Wj, axes=(T.ndim - 1, 0))
+    T = T.reshape([d] * (2 * L))
+    perm = [2 * j for j in range(L)] + [2 * j + 1 for j in range(L)]
+    N = d ** L
+    return T.transpose(perm).reshape(N, N)
 
 
 def mpo_to_matrix(W: Mpo) -> np.ndarray:
@@ -549,7 +562,9 @@ def site_map(Lx: int, Lv: int, order: int) -> List[Tuple[str, int]]:
     """Fig. 3 orderings, as (dimension, bit k) per site, k = 0 the coarsest
     bit: 0 = S1 (x coarse->fine, then v coarse->fine), 1 = IF (x1, v1, x2,
     v2, ...), 2 = S2 (x fine->coarse, then v coarse->fine), 3 = S3 (x
-    coarse->fine, then v fine->coarse)."""
+    coarse->fine, then v fine->coarse), 4 = IG (IF with each pair x_k v_k
+    fused into one site of dimension 4; this map lists its bits, which is
+    also the order of the IG vector's base-4 digits)."""
     xs = [("x", k) for k in range(Lx)]
     vs = [("v", k) for k in range(Lv)]
     if order == 0:
@@ -558,7 +573,7 @@ def site_map(Lx: int, Lv: int, order: int) -> List[Tuple[str, int]]:
         return xs[::-1] + vs
     if order == 3:
         return xs + vs[::-1]
-    if order == 1:
+    if order in (1, 4):
         if Lx != Lv:
             raise ValueError("interleaved ordering needs Lx == Lv")
         out = []
@@ -566,6 +581,26 @@ def site_map(Lx: int, Lv: int, order: int) -> List[Tuple[str, int]]:
             out += [("x", k), ("v", k)]
         return out
     raise ValueError("unknown ordering")
+
+
+def site_dims(Lx: int, Lv: int, order: int) -> List[int]:
+    """Physical dimension of each site: 4 for the fused IG sites, else 2."""
+    return [4] * Lx if order == 4 else [2] * (Lx + Lv)
+
+
+def fuse_pairs(cores: List[np.ndarray]) -> List[np.ndarray]:
+    """Contract sites 2k and 2k+1 into one site of dimension 4 (fused index
+    2 a + b, the first site's bit major): MPS cores (l, 2, r), MPO cores
+    (l, o, i, r) with o and i fused alike."""
+    out = []
+    for a, b in zip(cores[0::2], cores[1::2]):
+        if a.ndim == 3:
+            T = np.einsum("lsm,mtr->lstr", a, b)
+            out.append(T.reshape(a.shape[0], 4, b.shape[2]))
+        else:
+            T = np.einsum("loim,mpjr->lopijr", a, b)
+            out.append(T.reshape(a.shape[0], 4, 4, b.shape[3]))
+    return out
 
 
 def reversed_dims(order: int) -> Tuple[bool, bool]:
@@ -597,6 +632,13 @@ def sites_to_dense(vec: np.ndarray, Lx: int, Lv: int, order: int) -> np.ndarray:
 
 def chain_mpo(Wx: Optional[Mpo], Wv: Optional[Mpo], Lx: int, Lv: int,
               order: int) -> Mpo:
+    if order == 4:
+        return fuse_pairs(chain_mpo(Wx, Wv, Lx, Lv, 1))
+    return _chain_mpo_binary(Wx, Wv, Lx, Lv, order)
+
+
+def _chain_mpo_binary(Wx: Optional[Mpo], Wv: Optional[Mpo], Lx: int, Lv: int,
+                      order: int) -> Mpo:
     """Full-chain MPO of (x-operator) (x) (v-operator).  On a site of the
     other dimension an operator acts as delta_{bl,br} I_2, so in the
     interleaved order the bonds multiply (fused index x-major)."""
@@ -628,6 +670,13 @@ def chain_mpo(Wx: Optional[Mpo], Wv: Optional[Mpo], Lx: int, Lv: int,
 
 def chain_product_mps(ux: Optional[Mps], uv: Optional[Mps], Lx: int, Lv: int,
                       order: int) -> Mps:
+    if order == 4:
+        return fuse_pairs(chain_product_mps(ux, uv, Lx, Lv, 1))
+    return _chain_product_binary(ux, uv, Lx, Lv, order)
+
+
+def _chain_product_binary(ux: Optional[Mps], uv: Optional[Mps], Lx: int, Lv: int,
+                          order: int) -> Mps:
     """Full-chain MPS of a product function u(x) w(v) (same embedding)."""
     ux = ux if ux is not None else [np.ones((1, 2, 1))] * Lx
     uv = uv if uv is not None else [np.ones((1, 2, 1))] * Lv
@@ -661,6 +710,11 @@ def density_mps(f: Mps, Lx: int, Lv: int, order: int, dv: float) -> Mps:
     v-core summed over its bit; the resulting bond matrix is absorbed into
     the neighbouring x core.  Returns an Lx-site MPS in the natural bit
     order (coarsest first) whatever the ordering of f."""
+    if order == 4:
+        # each fused site (x_k, v_k): sum over its v bit
+        xs = [A.reshape(A.shape[0], 2, 2, A.shape[2]).sum(axis=2) for A in f]
+        xs[0] = xs[0] * dv
+        return xs
     xs: Mps = []
     pending = None
     for (d, k), A in zip(site_map(Lx, Lv, order), f):
@@ -727,6 +781,8 @@ def compress_state(m: Mps, chi: Optional[int], p) -> Mps:
     (sequential orderings), the centre-first scheme of SI "Modified
     Compression Scheme" with its centre at the x|v bond."""
     if getattr(p, "compression", 0) == 1:
+        if p.order not in (0, 2, 3):
+            raise ValueError("centre-first compression needs a sequential ordering")
         return compress_centre(m, p.Lx, chi, p.tol)
     return compress(m, chi, p.tol)
 
@@ -822,7 +878,7 @@ def init_mps(p, ax: np.ndarray, bv: np.ndarray) -> Mps:
     compressed to (chi, tol)."""
     F = np.einsum("ri,rj->ij", ax, bv)
     vec = dense_to_sites(F, p.Lx, p.Lv, p.order)
-    m = tt_svd(vec, [2] * p.n_sites, tol=p.tol, chi=None)
+    m = tt_svd(vec, site_dims(p.Lx, p.Lv, p.order), tol=p.tol, chi=None)
     return compress_state(m, p.chi_max, p)
 
 

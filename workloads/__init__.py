@@ -24,6 +24,7 @@ ORDER_SEQ = 0          # sequential: x bits (coarse->fine) then v bits
 ORDER_INTERLEAVED = 1  # interleaved: x1, v1, x2, v2, ... (coarse->fine)
 ORDER_S2 = 2           # sequential: x bits fine->coarse, then v coarse->fine
 ORDER_S3 = 3           # sequential: x bits coarse->fine, then v fine->coarse
+ORDER_IG = 4           # interleaved, each (x_k, v_k) pair one site of dimension 4
 
 PREC_FP64 = 0
 PREC_FP32_CONTRACT = 1
