@@ -247,13 +247,14 @@ def chi128_run(binding, steps):
 
 
 def orderings(binding, steps):
-    """The fixed-chi workload in the sequential orderings S1, S2, S3 (Fig. 3)
-    and with centre-first compression (SI, Modified Compression Scheme):
+    """The fixed-chi workload in the sequential orderings S1, S2, S3 and the
+    grouped interleaved IG (Fig. 3; the default is IF), and with centre-first
+    compression (SI, Modified Compression Scheme):
     steps/s from a perturbed state, the x|v cut's entanglement entropy and
     the largest bond after the timed steps."""
     import torch
     out = {}
-    for name, order, comp in (("S1", 0, 0), ("S2", 2, 0), ("S3", 3, 0),
+    for name, order, comp in (("S1", 0, 0), ("S2", 2, 0), ("S3", 3, 0), ("IG", 4, 0),
                               ("S1_centre_first", 0, 1), ("S2_centre_first", 2, 1)):
         w = make_workload("fixed")
         p = w.problem
@@ -267,7 +268,7 @@ def orderings(binding, steps):
         el = time.perf_counter() - t0
         ee = st.entanglement()
         out[name] = {"steps_per_s": steps / el, "steps": steps,
-                     "ee_xv_cut": float(ee[p.Lx - 1]),
+                     "ee_xv_cut": float(ee[p.Lx - 1]) if order != 4 else None,
                      "max_bond": int(max(st.info()["bonds"]))}
         st.free()
     return out

@@ -61,7 +61,8 @@ typedef enum {
   MPS_ORDER_SEQ = 0,          /* S1 */
   MPS_ORDER_INTERLEAVED = 1,  /* IF */
   MPS_ORDER_S2 = 2,
-  MPS_ORDER_S3 = 3
+  MPS_ORDER_S3 = 3,
+  MPS_ORDER_IG = 4            /* IG: IF with x_k v_k fused into one site */
 } mps_order;
 
 /* Arithmetic of the MPO x MPS contractions (SI, "Matrix-vector
@@ -109,7 +110,13 @@ typedef enum {
  * coarse->fine then v bits coarse->fine (S1); MPS_ORDER_S2 is x bits
  * fine->coarse then v bits coarse->fine; MPS_ORDER_S3 is x bits
  * coarse->fine then v bits fine->coarse; MPS_ORDER_INTERLEAVED is
- * x1, v1, x2, v2, ... (IF; needs Lx == Lv).  The ordering only changes how
+ * x1, v1, x2, v2, ... (IF; needs Lx == Lv); MPS_ORDER_IG fuses each pair
+ * (x_k, v_k) into one site of dimension 4 (IG).  An IG state is held as the
+ * IF chain of binary sites in which the bond inside each pair is never
+ * truncated (a dimension-4 site is exactly its two binary sites contracted),
+ * so truncation acts on the bonds between pairs only; bond_dims and the
+ * exported cores are those of the binary sites, and the memory model treats
+ * it as IF.  Centre-first compression needs S1, S2 or S3.  The ordering only changes how
  * the grid maps to the chain: mps_to_dense, the moments and the field are
  * on the grid in every ordering, and mps_get_cores / mps_set_cores use
  * chain order.  Compression level (SI,

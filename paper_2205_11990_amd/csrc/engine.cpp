@@ -23,7 +23,7 @@ namespace mpsv {
 
 std::vector<std::pair<int, int>> site_list(int Lx, int Lv, int order) {
   std::vector<std::pair<int, int>> sites;
-  if (order == 1) {
+  if (order == 1 || order == 4) {
     for (int k = 0; k < std::min(Lx, Lv); ++k) {
       sites.push_back({0, k});
       sites.push_back({1, k});
@@ -432,7 +432,7 @@ static HostMpo chain_generic(const HostMpo& Wx, const std::vector<int>& bx,
                              const HostMpo& Wv, const std::vector<int>& bv,
                              int order, int P, std::vector<int>& bonds) {
   const int Lx = (int)Wx.size(), Lv = (int)Wv.size();
-  if (order == 1 && Lx != Lv)
+  if ((order == 1 || order == 4) && Lx != Lv)
     throw Error(kEinval, "interleaved ordering needs Lx == Lv");
   const auto sites = site_list(Lx, Lv, order);
   HostMpo out;
@@ -520,15 +520,16 @@ MemoryModel memory_model(const Problem& q) {
   const double df = std::min(q.df_max > 0 ? (double)q.df_max : chi,
                              std::ldexp(1.0, q.Lx / 2));
   // widest MPO: the field term, or the upwind advection term
-  const double w = std::max((q.order == 1 ? 5.0 : 3.0) * df,
-                            q.x_scheme == 1 ? (q.order == 1 ? 24.0 : 8.0) : 0.0);
+  const bool il = q.order == 1 || q.order == 4;
+  const double w = std::max((il ? 5.0 : 3.0) * df,
+                            q.x_scheme == 1 ? (il ? 24.0 : 8.0) : 0.0);
   double S = 0, N = 0, I = 0;
   for (int j = 0; j < n; ++j) {
     const double bl = std::min(chi, full(j)), br = std::min(chi, full(j + 1));
     S += bl * 2 * br;
     N = std::max(N, std::min(w * bl, full(j)) * w * 2 * br);
   }
-  if (q.order == 1) {
+  if (il) {
     // interleaved initial state: Kronecker products of the x and v cores
     auto fr = [&](int k) { return std::ldexp(1.0, std::min(k, q.Lx - k)); };
     for (int k = 0; k < q.Lx; ++k)
@@ -538,7 +539,7 @@ MemoryModel memory_model(const Problem& q) {
   S *= 8.0;
   N *= 8.0;
   I *= 8.0;
-  const double work = q.order == 1 ? std::max({12.0 * N, 3.5 * I, 60.0 * S}) : 60.0 * S;
+  const double work = il ? std::max({12.0 * N, 3.5 * I, 60.0 * S}) : 60.0 * S;
   const double est[7] = {1.0 * (1 << 20), 2.0 * S, 1.5 * I + 12.0 * S, 40.0 * S,
                          work, 40.0 * S, 80.0 * S};
   MemoryModel m;
@@ -569,8 +570,8 @@ void Engine::arena_bytes(size_t reserved[7], size_t peak[7]) const {
 Engine::Engine(const Problem& p) : p_(p), chunk_(memory_model(p).chunk) {
   MPSV_CHECK(p.Lx >= 2 && p.Lx <= 14 && p.Lv >= 2 && p.Lv <= 14, kEinval,
              "Lx and Lv must lie in [2, 14]");
-  MPSV_CHECK(p.order >= 0 && p.order <= 3, kEinval, "unknown ordering");
-  MPSV_CHECK(p.order != 1 || p.Lx == p.Lv, kEinval,
+  MPSV_CHECK(p.order >= 0 && p.order <= 4, kEinval, "unknown ordering");
+  MPSV_CHECK((p.order != 1 && p.order != 4) || p.Lx == p.Lv, kEinval,
              "interleaved ordering needs Lx == Lv");
   MPSV_CHECK(p.x_max > p.x_min && p.v_max > p.v_min, kEinval,
              "empty x or v interval");
@@ -591,7 +592,7 @@ Engine::Engine(const Problem& p) : p_(p), chunk_(memory_model(p).chunk) {
              kEinval, "collision parameters must be finite, nu >= 0");
   MPSV_CHECK(p.compression == 0 || p.compression == 1, kEinval,
              "unknown compression scheme");
-  MPSV_CHECK(p.compression == 0 || p.order != 1, kEinval,
+  MPSV_CHECK(p.compression == 0 || (p.order != 1 && p.order != 4), kEinval,
              "centre-first compression needs a sequential ordering");
 
   MPSV_HIP(hipGetDevice(&device_));
@@ -837,6 +838,7 @@ DMps Engine::compress_chain(const std::vector<VSite>& ch_in, int cap, double tol
   MPSV_CHECK(centre == 0 || !sigmas, kEinval,
              "Schmidt values come from the plain sweep");
   cap = cap_or_inf(cap);
+  const bool ig = p_.order == 4 && n == p_.n() && !sigmas;
   ArenaScope sc(work());
   // ---- right dense region.  Where the sites j..n-1 span no more indices
   // than the bond entering them (2^(n-j) <= r_(j-1)), that part of the
@@ -925,7 +927,10 @@ DMps Engine::compress_chain(const std::vector<VSite>& ch_in, int cap, double tol
   int m = p, Dr = 1;
   for (int j = n - 1; j >= 1; --j) {
     const int c = 2 * Dr;
-    const bool exact = centre > 0 && j > centre;
+    // exact (cap and tol off): right of the centre (centre-first), and the
+    // bonds inside a fused x_k v_k pair of the IG ordering (its sites of
+    // dimension 4 are held as two binary sites whose bond is never cut)
+    const bool exact = (centre > 0 && j > centre) || (ig && (j & 1));
     const int capj = exact ? INT_MAX : cap;
     const double tolj = exact ? 0.0 : tol;
     Arena& dst = (centre > 0 && j >= centre) ? work() : out;
@@ -1649,7 +1654,7 @@ void Engine::init_from_profiles(int rank, const double* ax, const double* bv,
       DMps mx = tt(ax + (long)r * p_.Nx(), p_.Lx);
       DMps mv = tt(bv + (long)r * p_.Nv(), p_.Lv);
       DMps full;
-      if (p_.order != 1) {
+      if (p_.order != 1 && p_.order != 4) {
         // sequential: a dimension read fine to coarse enters reversed
         full = (p_.order == 2) ? reverse_mps(mx, step_, s) : mx;
         const DMps v = (p_.order == 3) ? reverse_mps(mv, step_, s) : mv;
@@ -1766,7 +1771,7 @@ void Engine::to_dense(double* out, hipStream_t s) {
     ArenaScope sc(tmp_);
     double* v = tmp_.alloc((size_t)1 << n());
     dense_of(f_, v, s);
-    if (p_.order == 1)
+    if (p_.order == 1 || p_.order == 4)
       deinterleave(s, v, p_.Lx, out);
     else
       chain_to_grid(s, v, p_.Lx, p_.Lv, p_.order == 2, p_.order == 3, out);

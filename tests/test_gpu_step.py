@@ -534,3 +534,51 @@ def test_step_graph_cannot_be_enabled(B):
     st.step(3)
     assert st.step_graph() == (0, 0)
     st.free()
+
+
+@pytest.mark.parametrize("L", [3, 4])
+def test_untruncated_ig_steps_equal_dense_oracle(B, L):
+    """IG ordering (pairs x_k v_k as sites of dimension 4, held as binary
+    sites with the bond inside a pair never cut), untruncated: the steps
+    equal the dense steps."""
+    _say("untruncated IG L=%d" % L)
+    w = _untruncated(wl.landau_small(L=L))
+    p = w.problem
+    p.order = 4
+    st = B.MpsState(p, w.ax, w.bv)
+    F = odense.initial(w.ax, w.bv)
+    assert np.abs(st.to_dense().cpu().numpy() - F).max() <= 1e-13 * np.abs(F).max()
+    for k in range(3):
+        st.step(1)
+        F = odense.rk4_step(F, p)
+        G = st.to_dense().cpu().numpy()
+        assert np.abs(G - F).max() <= 1e-12 * (k + 2) * np.abs(F).max(), k
+    st.free()
+
+
+def test_truncated_ig_matches_the_dimension_four_oracle(B):
+    """IG with every point capped (C5, chi = 8): f and E within 1e-8 of the
+    oracle, which works on fused sites of dimension 4 (started from the GPU
+    state with each pair of binary cores contracted); the GPU's bonds
+    between pairs equal the oracle's bonds and none exceeds chi."""
+    _say("truncated IG C5 chi8 two-stream L=5")
+    w = wl.two_stream(L=5, chi=8, tol=0.0, level=5, df_max=4, dt_cfg=0.05)
+    p = w.problem
+    p.order = 4
+    st = B.MpsState(p, w.ax, w.bv)
+    st.add_scaled(1e-3, wl.random_mps_cores(p.n_sites, 8, seed=2205))
+    f = omps.fuse_pairs(st.get_cores_host())
+    ops = omps.Operators(p)
+    for _ in range(2):
+        st.step(1)
+        f = omps.rk4_step(f, ops)
+    G = st.to_dense().cpu().numpy()
+    R = omps.to_dense(f, p)
+    _, E = st.density_field()
+    Eref = omps.field_dense(f, ops)
+    assert np.abs(G - R).max() <= 1e-8 * np.abs(R).max()
+    assert np.abs(E.cpu().numpy() - Eref).max() <= 1e-8 * np.abs(Eref).max()
+    b = st.info()["bonds"]
+    assert b[2:p.n_sites:2] == omps.bond_dims(f)
+    assert max(b[2:p.n_sites:2]) <= 8
+    st.free()
