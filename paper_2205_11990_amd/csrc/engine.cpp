@@ -943,8 +943,31 @@ DMps Engine::compress_chain(const std::vector<VSite>& ch_in, int cap, double tol
     // the discarded weight goes straight to its place (a deferred call
     // writes it when the deferred section ends)
     double* dsc = disc ? &(*disc)[j - 1] : nullptr;
-    const int D = svd_truncate(s, work(), X, m, c, c, capj, tolj, Vt, US, sg,
-                               dsc);
+    int D;
+    if (tolj <= 0.0 && !want_sg && std::min(m, c) <= capj) {
+      // Nothing to truncate (every value is kept): only the right-canonical
+      // gauge is needed, and an orthogonal factor gives it exactly.  A tall
+      // block (m > c) keeps Vt = I and US = X; a wide one is factored as
+      // X^T = Q R, so Vt = Q^T and US = R^T.  The represented tensor and
+      // every later cut are the same as with the SVD.
+      if (m > c) {
+        D = c;
+        identity(s, Vt, c);
+        US = X;
+      } else {
+        D = m;
+        QrFactor lq;
+        qr_factor_view(s, work(), CMatView{X, 1, c, 0}, c, m, lq,
+                       MatView{US, 1, m, 0});
+        double* I = work().alloc((size_t)m * m);
+        identity(s, I, m);
+        qr_apply_q_view(s, work(), lq, CMatView{I, m, 1, 0}, m,
+                        MatView{Vt, 1, c, 0}, m);
+      }
+      if (dsc) *dsc = 0.0;
+    } else {
+      D = svd_truncate(s, work(), X, m, c, c, capj, tolj, Vt, US, sg, dsc);
+    }
     if (sigmas) {
       auto& h = (*sigmas)[j - 1];
       h.resize((size_t)std::min(m, c));

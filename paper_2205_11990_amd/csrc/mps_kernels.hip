@@ -67,6 +67,11 @@ __global__ void scale_rows_kernel(const double* in, int rows, long len,
   }
 }
 
+__global__ void identity_kernel(double* A, int n) {
+  const long total = (long)n * n;
+  GRID_STRIDE(e, total) A[e] = (e / n == e % n) ? 1.0 : 0.0;
+}
+
 // out[b][t][a] = in[a][t][b] for an l x 2 x r core
 __global__ void reverse_core_kernel(const double* in, int l, int r,
                                     double* out) {
@@ -220,6 +225,13 @@ void scale_rows(hipStream_t s, const double* in, int rows, long len,
   if (n <= 0) return;
   hipLaunchKernelGGL(scale_rows_kernel, dim3(grid_for(n)), dim3(256), 0, s, in,
                      rows, len, d, inverse ? 1 : 0, out);
+  MPSV_LAUNCHED();
+}
+
+void identity(hipStream_t s, double* A, int n) {
+  const long total = (long)n * n;
+  if (total <= 0) return;
+  hipLaunchKernelGGL(identity_kernel, dim3(grid_for(total)), dim3(256), 0, s, A, n);
   MPSV_LAUNCHED();
 }
 

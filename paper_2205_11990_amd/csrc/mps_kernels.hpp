@@ -20,6 +20,9 @@ void sum_physical(hipStream_t s, const double* in, int l, int r, double* out);
 void scale_rows(hipStream_t s, const double* in, int rows, long len,
                 const double* d, bool inverse, double* out);
 
+// A (n x n, row-major) = the identity
+void identity(hipStream_t s, double* A, int n);
+
 // out[b][t][a] = in[a][t][b]: an l x 2 x r core read from the right
 void reverse_core(hipStream_t s, const double* in, int l, int r, double* out);
 
