@@ -143,3 +143,27 @@ def test_plasma_species_cannot_be_stepped_or_freed_alone(B):
         st.step(1)
     assert B.lib().mps_free(st.handle) != 0
     pl.free()
+
+
+def test_plasma_failure_leaves_every_species_unchanged(B):
+    """A forced non-convergence in a plasma step fails it for all species:
+    none of them is committed."""
+    _say("plasma failure is all or none")
+    ws, q = wl.buneman(L=5, chi=8, tol=0.0, level=5, df_max=4)
+    pl = B.Plasma([w.problem for w in ws], q, [(w.ax, w.bv) for w in ws])
+    pl.species(0).add_scaled(1e-4, wl.random_mps_cores(ws[0].problem.n_sites, 8, seed=3))
+    before = [pl.species(s).get_cores_host() for s in range(2)]
+    B.set_jacobi_max_sweeps(1)
+    try:
+        with pytest.raises(B.MpsError) as e:
+            pl.step(1)
+        assert e.value.status == B.MPS_ENUMERIC
+    finally:
+        B.set_jacobi_max_sweeps(60)
+    for s in range(2):
+        after = pl.species(s).get_cores_host()
+        assert all(np.array_equal(x, y) for x, y in zip(before[s], after)), s
+        assert pl.species(s).info()["steps"] == 0
+    pl.step(1)
+    assert all(pl.species(s).info()["steps"] == 1 for s in range(2))
+    pl.free()

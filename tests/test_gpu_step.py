@@ -582,3 +582,70 @@ def test_truncated_ig_matches_the_dimension_four_oracle(B):
     assert b[2:p.n_sites:2] == omps.bond_dims(f)
     assert max(b[2:p.n_sites:2]) <= 8
     st.free()
+
+
+def test_deferred_failure_leaves_state_unchanged(B):
+    """Fixed-rank steps (tol = 0) read the SVD outcomes back only at the end
+    of the step: a forced non-convergence still fails the step with
+    MPS_ENUMERIC and leaves the state as it was."""
+    _say("deferred failure")
+    w = wl.two_stream(L=5, chi=8, tol=0.0, level=5, df_max=4, dt_cfg=0.05)
+    st = B.MpsState(w.problem, w.ax, w.bv)
+    st.add_scaled(1e-3, wl.random_mps_cores(w.problem.n_sites, 8, seed=2205))
+    before = st.get_cores_host()
+    B.set_jacobi_max_sweeps(1)
+    try:
+        with pytest.raises(B.MpsError) as e:
+            st.step(1)
+        assert e.value.status == B.MPS_ENUMERIC
+    finally:
+        B.set_jacobi_max_sweeps(60)
+    after = st.get_cores_host()
+    assert all(np.array_equal(x, y) for x, y in zip(before, after))
+    assert st.info()["steps"] == 0
+    st.step(1)
+    assert st.info()["steps"] == 1
+    st.free()
+
+
+def _sample(cores, p, pts):
+    """f at grid points (i, j), contracting the cores along the bits of each
+    point in chain order (the oracle's site map)."""
+    sm = omps.site_map(p.Lx, p.Lv, p.order)
+    out = []
+    for i, j in pts:
+        v = np.ones(1)
+        for (d, k), A in zip(sm, cores):
+            bit = (i >> (p.Lx - 1 - k)) & 1 if d == "x" else (j >> (p.Lv - 1 - k)) & 1
+            v = v @ A[:, bit, :]
+        out.append(v[0])
+    return np.array(out)
+
+
+def test_largest_grid_matches_mps_oracle_on_samples(B):
+    """The largest grid the library takes, 2^14 x 2^14 (28 sites), chi = 16,
+    every point capped, one step from the same state: 4096 sampled values of
+    f, the whole field E and the moments within 1e-8 of the MPS oracle."""
+    _say("largest grid 2^14 x 2^14 chi 16")
+    w = wl.two_stream(L=14, chi=16, tol=0.0, level=5, df_max=4, dt_cfg=0.02, order=0)
+    p = w.problem
+    st = B.MpsState(p, w.ax, w.bv)
+    st.add_scaled(1e-6, wl.random_mps_cores(p.n_sites, 16, seed=7))
+    f = st.get_cores_host()
+    ops = omps.Operators(p)
+    st.step(1)
+    f = omps.rk4_step(f, ops)
+    g = st.get_cores_host()
+    rng = np.random.default_rng(14)
+    pts = list(zip(rng.integers(0, p.Nx, 4096), rng.integers(0, p.Nv, 4096)))
+    a, r = _sample(g, p, pts), _sample(f, p, pts)
+    scale = np.abs(r).max()
+    assert np.abs(a - r).max() <= 1e-8 * scale
+    _, E = st.density_field()
+    Eref = omps.field_dense(f, ops)
+    assert np.abs(E.cpu().numpy() - Eref).max() <= 1e-8 * np.abs(Eref).max()
+    _, _, sc = st.moments()
+    ref = omps.moments(f, ops)
+    for k in ("mass", "momentum", "kinetic"):
+        assert abs(sc[k] - ref[k]) <= 1e-9 * max(abs(ref["mass"]), 1.0), k
+    st.free()
