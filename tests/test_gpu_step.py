@@ -649,3 +649,19 @@ def test_largest_grid_matches_mps_oracle_on_samples(B):
     for k in ("mass", "momentum", "kinetic"):
         assert abs(sc[k] - ref[k]) <= 1e-9 * max(abs(ref["mass"]), 1.0), k
     st.free()
+
+
+@pytest.mark.parametrize("tol,level", [(1e-10, 1), (0.0, 5)])
+def test_zero_state_stays_zero(B, tol, level):
+    """The degenerate all-zero distribution: every block of every sweep is
+    zero (with tol = 0 the cap sets the ranks, with tol > 0 one value is
+    kept); steps stay finite and exactly zero."""
+    _say("zero state tol=%g level=%d" % (tol, level))
+    w = wl.landau_small(L=5, chi=8, tol=tol, level=level)
+    st = B.MpsState(w.problem, np.zeros_like(w.ax), w.bv)
+    st.step(2)
+    F = st.to_dense().cpu().numpy()
+    assert np.all(F == 0.0)
+    _, E = st.density_field()
+    assert np.all(E.cpu().numpy() == 0.0)
+    st.free()
