@@ -33,7 +33,7 @@ Sections of the paper followed here:
   v fine->coarse), interleaved IF and grouped IG (sites of dimension 4
   holding x_k and v_k).
 
-Readings where the paper is silent or garbled (each also listed in the design doc):
+Readings where the paper is silent or garbled:
 * The printed M_left of the zero-gradient derivative puts its only entry at
   (o, i) = (N/2-1, N-1); the mirror image of the printed M_right is used
   instead, P0^{(x)(L-1)} (x) [[0, -c1], [0, 0]], so rows 0 and N-1 vanish.
