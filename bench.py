@@ -162,11 +162,14 @@ def roofline(binding, st, cores_host, steps):
     classes = {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
                    "tflops": round(v["flops"] / (v["ms"] * 1e-3) / 1e12, 4) if v["ms"] > 0 else None}
                for k, v in rec.items() if k in _CLASS_BOUND}
+    # the whole step: nominal FLOPs of every instrumented launch per step
+    # (GEMM 2mnk, GEQRF, reflector applications, SVD 6mn^2 + 20n^3)
+    step_gflop = sum(v["flops"] for k, v in rec.items() if k in _CLASS_BOUND) / steps / 1e9
     return {"bound": bound, "achieved": ach, "peak": peak, "unit": "TFLOP/s",
             "frac": ach / peak, "traffic": measured_traffic(dom), "kernel": dom,
             "launches": r["launches"], "avg_launch_us": 1000.0 * r["ms"] / max(r["launches"], 1),
             "flops_per_launch": r["flops"] / max(r["launches"], 1),
-            "classes": classes}
+            "classes": classes, "step_gflop": step_gflop}
 
 
 _PREC_NAMES = {1: "fp32 contraction (MFMA f32, FP32 accumulate)",
@@ -448,6 +451,9 @@ def main():
     cpu = None
     if not args.no_roofline:
         roof = roofline(binding, st, cores_host, min(args.steps, 3))
+        # whole-step algorithmic rate at the timed steps/s, against FP64 peak
+        roof["step_tflops"] = roof["step_gflop"] * value / 1e3
+        roof["step_frac"] = roof["step_tflops"] / PEAK_FP64_TFLOPS
         print("[bench] roofline %s" % json.dumps(roof), file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, args.mode, cores_host)

@@ -310,7 +310,11 @@ mps_status mps_step_batched(mps_state* const* hs, int32_t count, int32_t nsteps,
   return guarded([&] {
     MPSV_CHECK(hs != nullptr && count >= 0, mpsv::kEinval, "bad batch");
     MPSV_CHECK(nsteps >= 0, mpsv::kEinval, "nsteps must be >= 0");
-    for (int i = 0; i < count; ++i) check_handle(hs[i]);
+    for (int i = 0; i < count; ++i) {
+      check_handle(hs[i]);
+      MPSV_CHECK(!hs[i]->in_plasma, mpsv::kEinval,
+                 "a species of a plasma is stepped by mps_plasma_step");
+    }
     {
       std::vector<const mps_state*> v(hs, hs + count);
       std::sort(v.begin(), v.end());

@@ -142,6 +142,8 @@ def test_plasma_species_cannot_be_stepped_or_freed_alone(B):
     with pytest.raises(B.MpsError):
         st.step(1)
     assert B.lib().mps_free(st.handle) != 0
+    with pytest.raises(B.MpsError):
+        B.step_batched([st], 1)
     pl.free()
 
 
