@@ -37,12 +37,13 @@ constexpr size_t kJacobiLds = 144 * 1024;
 LinalgStats g_stats;
 int g_max_sweeps = 60;
 
-// Extra pairs of QR factorisations before the Jacobi sweeps (tuning knob,
-// MPSV_SVD_PRECOND in the environment; default 1).
-int svd_precondition_pairs() {
+// Extra QR factorisations of the triangular factor before the Jacobi
+// sweeps, after the first one of X (tuning knob, MPSV_SVD_PRECOND_QR in the
+// environment, 0..6; default 2: B^T, then B).
+int svd_precondition_qrs() {
   static const int n = [] {
-    const char* e = std::getenv("MPSV_SVD_PRECOND");
-    return e ? std::max(0, std::min(3, std::atoi(e))) : 1;
+    const char* e = std::getenv("MPSV_SVD_PRECOND_QR");
+    return e ? std::max(0, std::min(6, std::atoi(e))) : 2;
   }();
   return n;
 }
@@ -693,8 +694,9 @@ int svd_truncate(hipStream_t s, Arena& ws, double* X, int m, int c, long ldx,
                      MatView{Bk, 1, k, 0});
       upper = false;
     }
-    int extra = 2 * svd_precondition_pairs();
-    while (!upper || extra > 0) {
+    // the Jacobi kernel takes any square factor, upper or lower triangular
+    int extra = svd_precondition_qrs();
+    while (extra > 0) {
       if (upper) {
         // B = R: R^T = Q' R'  ->  B = R'^T Q'^T; write R'^T
         Rf.emplace_back();
