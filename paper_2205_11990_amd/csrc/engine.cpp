@@ -1250,32 +1250,34 @@ DMpo Engine::t2_mpo(const DMps& En, Arena& ar, hipStream_t s) {
 DMps Engine::rhs(const DMps& g, Arena& out, hipStream_t s, const DMps* Eext) {
   ArenaScope sc(tmp_);
   ArenaScope sc2(tmp2_);
-  // The two terms share only their input g.  T1 = -(Dx V) g is compressed
-  // on the side stream by a second host thread (each factorisation of the
-  // sweep occupies one workgroup, so the two sweeps run side by side on
-  // the chip) while this thread computes the field and compresses T2.
+  // The terms share only their input g.  T1 = -(Dx V) g (and the collision
+  // term T3 = C g) are compressed on the side stream by a second host thread
+  // (each factorisation of the sweep occupies one workgroup, so the sweeps
+  // run side by side on the chip) while this thread computes the field and
+  // compresses T2.
   MPSV_HIP(hipEventRecord(ev_fork_, s));
   MPSV_HIP(hipStreamWaitEvent(side_, ev_fork_, 0));
-  DMps T1;
+  DMps T1, T3;
   std::exception_ptr side_err;
   std::thread side([&] {
     (void)hipSetDevice(device_);
     tl_work = &work2_;
     try {
       T1 = apply_compress(t1_, g, cap_for(5), p_.tol, tmp2_, side_);
+      // the collision term also needs g alone: the side lane takes it too
+      if (!coll_.empty()) T3 = apply_compress(coll_, g, cap_for(5), p_.tol, tmp2_, side_);
       MPSV_HIP(hipEventRecord(ev_join_, side_));
     } catch (...) {
       side_err = std::current_exception();
     }
     tl_work = nullptr;
   });
-  DMps T2, T3;
+  DMps T2;
   try {
     DMps E;
     if (!Eext) E = field(g, tmp_, s);
     DMpo W2 = t2_mpo(Eext ? *Eext : E, tmp_, s);
     T2 = apply_compress(W2, g, cap_for(5), p_.tol, tmp_, s);
-    if (!coll_.empty()) T3 = apply_compress(coll_, g, cap_for(5), p_.tol, tmp_, s);
   } catch (...) {
     side.join();
     (void)hipStreamSynchronize(side_);
