@@ -107,17 +107,23 @@ def test_untruncated_buneman_plasma_equals_dense_oracle(B):
     pl.free()
 
 
-@pytest.mark.parametrize("order", [0, 1])
-def test_truncated_buneman_plasma_matches_mps_oracle(B, order):
+@pytest.mark.parametrize("order,comp,nu", [(0, 0, 0.0), (1, 0, 0.0), (2, 1, 0.02), (4, 0, 0.02)])
+def test_truncated_buneman_plasma_matches_mps_oracle(B, order, comp, nu):
     """Electrons and ions, every point capped (C5, chi = 8, D_F = 4), the
     electrons perturbed to full bonds: both species and the shared field
-    within 1e-8 of the MPS oracle after 2 steps from the same states."""
-    _say("truncated buneman plasma L=5 chi8 order=%d" % order)
-    ws, q = wl.buneman(L=5, chi=8, tol=0.0, level=5, df_max=4, order=order)
+    within 1e-8 of the MPS oracle after 2 steps from the same states (S1,
+    IF, S2 with centre-first compression and collisions, IG with
+    collisions)."""
+    _say("truncated buneman plasma L=5 chi8 order=%d compression=%d nu=%g" % (order, comp, nu))
+    ws, q = wl.buneman(L=5, chi=8, tol=0.0, level=5, df_max=4, order=order, nu=nu)
     ps = [w.problem for w in ws]
+    for p in ps:
+        p.compression = comp
     pl = B.Plasma(ps, q, [(w.ax, w.bv) for w in ws])
     pl.species(0).add_scaled(1e-4, wl.random_mps_cores(ps[0].n_sites, 8, seed=2205))
     fs = [pl.species(s).get_cores_host() for s in range(2)]
+    if order == 4:
+        fs = [omps.fuse_pairs(f) for f in fs]
     opss = [omps.Operators(p) for p in ps]
     for _ in range(2):
         pl.step(1)
@@ -127,7 +133,8 @@ def test_truncated_buneman_plasma_matches_mps_oracle(B, order):
         G = st.to_dense().cpu().numpy()
         R = omps.to_dense(f, p)
         assert np.abs(G - R).max() <= 1e-8 * np.abs(R).max(), s
-        assert st.info()["bonds"][1:-1] == omps.bond_dims(f), s
+        b = st.info()["bonds"]
+        assert (b[2:p.n_sites:2] if order == 4 else b[1:-1]) == omps.bond_dims(f), s
     E, _ = pl.field()
     Eref = omps.to_vector(omps.field_species_mps(fs, opss, q))
     assert np.abs(E.cpu().numpy() - Eref).max() <= 1e-8 * np.abs(Eref).max()
