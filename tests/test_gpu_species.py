@@ -176,3 +176,56 @@ def test_plasma_failure_leaves_every_species_unchanged(B):
     pl.step(1)
     assert all(pl.species(s).info()["steps"] == 1 for s in range(2))
     pl.free()
+
+
+def test_gpu_landau_damping_rate(B):
+    """Physics end to end on the GPU: 64 x 64 Landau, chi = 16, tol = 1e-10,
+    600 steps (t = 30): the field energy decays at twice the kinetic damping
+    rate (gamma = -0.1534, the root of the dispersion relation)."""
+    _say("GPU Landau damping rate, 600 steps")
+    from tests import _dispersion as disp
+    w0 = disp.root(0.5, [(1.0, 0.0)], 1.4 - 0.15j)
+    w = wl.landau_small(L=6, chi=16, tol=1e-10)
+    p = w.problem
+    st = B.MpsState(p, w.ax, w.bv)
+    t, W = [0.0], [st.moments()[2]["field_energy"]]
+    for s in range(600):
+        st.step(1)
+        t.append((s + 1) * p.dt)
+        W.append(st.moments()[2]["field_energy"])
+        if s % 100 == 99:
+            _say("  step %d" % (s + 1))
+    gamma, tp = disp.fit_rate(t, W, 0.0, 30.0, peaks=True)
+    assert len(tp) >= 10
+    assert abs(gamma - w0.imag) < 0.01, gamma
+    st.free()
+
+
+def test_gpu_buneman_growth_rate(B):
+    """Physics end to end with two species on the GPU: Buneman at 32 x 512
+    per species, chi = 32, tol = 1e-10; the k = 0.1 field mode grows at the
+    root of the two-species kinetic dispersion relation (0.1985) within 5 %."""
+    _say("GPU Buneman growth rate")
+    import math
+    from tests import _dispersion as disp
+    ws, q = wl.buneman(L=5, Lv=9, chi=32, tol=1e-10, level=1)
+    ps = [w.problem for w in ws]
+    mr = 1.0 / ps[1].qm
+    gamma = disp.root_species(0.1, [(1.0, 1.0, 10.0), (1.0 / mr, math.sqrt(1.0 / mr), 0.0)],
+                              0.136 + 0.235j).imag
+    pl = B.Plasma(ps, q, [(w.ax, w.bv) for w in ws])
+    T, A = [], []
+    n_steps = int(36.0 / ps[0].dt)
+    for n in range(n_steps):
+        if n % 10 == 0:
+            E, _ = pl.field()
+            T.append(n * ps[0].dt)
+            A.append(abs(np.fft.fft(E.cpu().numpy())[1]))
+        pl.step(1)
+        if n % 200 == 199:
+            _say("  step %d of %d" % (n + 1, n_steps))
+    T, A = np.array(T), np.array(A)
+    sel = (T >= 15.0) & (T <= 35.0)
+    rate = np.polyfit(T[sel], np.log(A[sel]), 1)[0]
+    assert abs(rate - gamma) < 0.05 * gamma, (rate, gamma)
+    pl.free()
