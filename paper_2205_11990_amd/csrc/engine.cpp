@@ -672,6 +672,8 @@ Engine::Engine(const Problem& p) : p_(p), chunk_(memory_model(p).chunk) {
                            0.5 * p.dv() * p.dv(), bw);
   v2poly_ = upload_chain(wv2, bw);
   dflag_ = ops_.alloc_int(4);
+  ident_ = ops_.alloc((size_t)kIdent * kIdent);
+  identity(s, ident_, kIdent);
   MPSV_HIP(hipDeviceSynchronize());
 }
 
@@ -894,8 +896,12 @@ DMps Engine::compress_chain(const std::vector<VSite>& ch_in, int cap, double tol
   int p = 1;
   for (int j = 0; j < n - 1; ++j) {
     const int rows = 2 * p, cols = ch[j].r;
-    double* M = work().alloc((size_t)rows * cols);
-    absorb_left(ch[j], R, p, M, s);
+    // a natural-basis site leaves R (p x 2r) as it is: no copy
+    double* M = R;
+    if (ch[j].kind != VSite::kCopy) {
+      M = work().alloc((size_t)rows * cols);
+      absorb_left(ch[j], R, p, M, s);
+    }
     fac[j].rows = rows;
     fac[j].cols = cols;
     if (rows <= cols) {
@@ -911,8 +917,11 @@ DMps Engine::compress_chain(const std::vector<VSite>& ch_in, int cap, double tol
       p = cols;
     }
   }
-  double* X = work().alloc((size_t)p * 2);
-  absorb_left(ch[n - 1], R, p, X, s);
+  double* X = R;
+  if (ch[n - 1].kind != VSite::kCopy) {
+    X = work().alloc((size_t)p * 2);
+    absorb_left(ch[n - 1], R, p, X, s);
+  }
   // ---- (ii) truncated SVD sweep right to left.  Centre-first (SI,
   // Modified Compression Scheme; centre > 0): the sites right of the centre
   // are only brought to right-canonical form (untruncated SVDs), the centre
@@ -959,10 +968,15 @@ DMps Engine::compress_chain(const std::vector<VSite>& ch_in, int cap, double tol
         QrFactor lq;
         qr_factor_view(s, work(), CMatView{X, 1, c, 0}, c, m, lq,
                        MatView{US, 1, m, 0});
-        double* I = work().alloc((size_t)m * m);
-        identity(s, I, m);
-        qr_apply_q_view(s, work(), lq, CMatView{I, m, 1, 0}, m,
-                        MatView{Vt, 1, c, 0}, m);
+        // Q^T = (Q [I; 0])^T, the identity read from the state's
+        // persistent copy when it is large enough
+        CMatView I{ident_, kIdent, 1, 0};
+        if (m > kIdent) {
+          double* Ib = work().alloc((size_t)m * m);
+          identity(s, Ib, m);
+          I = CMatView{Ib, m, 1, 0};
+        }
+        qr_apply_q_view(s, work(), lq, I, m, MatView{Vt, 1, c, 0}, m);
       }
       if (dsc) *dsc = 0.0;
     } else {

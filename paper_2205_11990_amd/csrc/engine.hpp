@@ -247,6 +247,9 @@ class Engine {
   double t_ = 0.0;
   long steps_ = 0;
   int* dflag_ = nullptr;
+  // a kIdent x kIdent identity (device), for the exact gauges of the sweep
+  static constexpr int kIdent = 256;
+  double* ident_ = nullptr;
 };
 
 // Host construction of the operators (exact, FP64).  W[bl][o][i][br].
