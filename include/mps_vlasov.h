@@ -224,8 +224,8 @@ mps_status mps_add_scaled(mps_state* h, double alpha, const int32_t* bond_dims,
  * that envelope measured peaks (grids 2^6..2^13, chi 16..128, both
  * orderings), plus chunk rounding and a fixed allowance; it assumes every
  * compression point stays within chi_max (level 5, or lower levels whose
- * tolerance keeps the bonds there).  EINVAL for Lx, Lv outside [2, 14] or
- * chi_max < 1. */
+ * tolerance keeps the bonds there).  EINVAL for every problem that mps_init
+ * rejects on its parameters (the same checks). */
 mps_status mps_workspace_bound(const mps_problem* p, size_t* bytes);
 
 /* Device bytes the state h holds right now (all of its arenas: operators,

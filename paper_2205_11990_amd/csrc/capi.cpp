@@ -273,9 +273,7 @@ mps_status mps_workspace_bound(const mps_problem* p, size_t* bytes) {
   return guarded([&] {
     MPSV_CHECK(bytes != nullptr, mpsv::kEinval, "bytes is NULL");
     mpsv::Problem q = convert(p);
-    MPSV_CHECK(q.Lx >= 2 && q.Lx <= 14 && q.Lv >= 2 && q.Lv <= 14,
-               mpsv::kEinval, "Lx and Lv must lie in [2, 14]");
-    MPSV_CHECK(q.chi_max >= 1, mpsv::kEinval, "chi_max must be >= 1");
+    mpsv::validate_problem(q);
     *bytes = mpsv::memory_model(q).bound;
   });
 }

@@ -567,7 +567,9 @@ void Engine::arena_bytes(size_t reserved[7], size_t peak[7]) const {
   }
 }
 
-Engine::Engine(const Problem& p) : p_(p), chunk_(memory_model(p).chunk) {
+// Parameter checks of a problem (host only; shared by state creation and
+// the admission bound).
+void validate_problem(const Problem& p) {
   MPSV_CHECK(p.Lx >= 2 && p.Lx <= 14 && p.Lv >= 2 && p.Lv <= 14, kEinval,
              "Lx and Lv must lie in [2, 14]");
   MPSV_CHECK(p.order >= 0 && p.order <= 4, kEinval, "unknown ordering");
@@ -594,7 +596,11 @@ Engine::Engine(const Problem& p) : p_(p), chunk_(memory_model(p).chunk) {
              "unknown compression scheme");
   MPSV_CHECK(p.compression == 0 || (p.order != 1 && p.order != 4), kEinval,
              "centre-first compression needs a sequential ordering");
+}
 
+// (the checks run before the size model reads the problem)
+Engine::Engine(const Problem& p)
+    : p_(p), chunk_((validate_problem(p), memory_model(p).chunk)) {
   MPSV_HIP(hipGetDevice(&device_));
   MPSV_HIP(hipStreamCreateWithFlags(&own_, hipStreamNonBlocking));
   MPSV_HIP(hipStreamCreateWithFlags(&side_, hipStreamNonBlocking));

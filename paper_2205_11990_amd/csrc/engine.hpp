@@ -77,6 +77,9 @@ struct MemoryModel {
 };
 MemoryModel memory_model(const Problem& p);
 
+// Throws Error(kEinval) for a problem the engine does not accept.
+void validate_problem(const Problem& p);
+
 struct StepTimers {
   double compress_ms = 0;
 };

@@ -137,3 +137,63 @@ def test_workspace_bound_grows_with_the_problem():
     full_df = wl.two_stream(L=10, chi=64, df_max=0).problem
     assert binding.workspace_bound(full_df) >= b[10, 64] >= binding.workspace_bound(seq)
     assert b[10, 64] < (4 << 30)
+
+
+_BAD = [
+    ("Lx", 1), ("Lv", 1), ("Lx", 15), ("Lv", 0), ("order", 5), ("order", -1),
+    ("dt", 0.0), ("dt", -0.1), ("dt", float("nan")), ("chi_max", 0),
+    ("level", 0), ("level", 6), ("df_max", -1), ("tol", -1e-12),
+    ("tol", float("nan")), ("precision", 3), ("x_scheme", 2), ("cfl", -0.5),
+    ("qm", float("inf")), ("nu", -0.01), ("nu", float("nan")),
+    ("nu_vth", float("nan")), ("compression", 2),
+]
+
+
+@pytest.mark.parametrize("field,value", _BAD)
+def test_every_parameter_check_rejects_without_a_gpu(field, value):
+    """The admission bound runs the same parameter checks as state creation
+    (host only), so each invalid field gives MPS_EINVAL here."""
+    from paper_2205_11990_amd import binding
+    import workloads as wl
+    p = wl.landau_small().problem
+    setattr(p, field, value)
+    with pytest.raises(binding.MpsError) as e:
+        binding.workspace_bound(p)
+    assert e.value.status == binding.MPS_EINVAL
+
+
+def test_parameter_checks_that_couple_fields():
+    from paper_2205_11990_amd import binding
+    import workloads as wl
+
+    def rejected(p):
+        with pytest.raises(binding.MpsError) as e:
+            binding.workspace_bound(p)
+        return e.value.status == binding.MPS_EINVAL
+
+    p = wl.landau_small(L=4, Lv=5).problem
+    for order in (1, 4):                   # interleaved orderings need Lx == Lv
+        p.order = order
+        assert rejected(p)
+    p = wl.landau_small().problem
+    p.x_max = p.x_min                      # empty intervals
+    assert rejected(p)
+    p = wl.landau_small().problem
+    p.v_min = p.v_max + 1.0
+    assert rejected(p)
+    p = wl.landau_small().problem
+    p.compression = 1                      # centre-first needs a sequential order
+    for order in (1, 4):
+        p.order = order
+        assert rejected(p)
+    p = wl.landau_small().problem
+    p.dt = 0.0                             # no fixed dt needed with adaptive dt
+    p.cfl = 0.5
+    assert binding.workspace_bound(p) > 0
+    # the smallest and largest grids of every ordering are accepted
+    for L in (2, 14):
+        for order in range(5):
+            p = wl.landau_small().problem
+            p.Lx = p.Lv = L
+            p.order = order
+            assert binding.workspace_bound(p) > 0

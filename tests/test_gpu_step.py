@@ -665,3 +665,28 @@ def test_zero_state_stays_zero(B, tol, level):
     _, E = st.density_field()
     assert np.all(E.cpu().numpy() == 0.0)
     st.free()
+
+
+@pytest.mark.parametrize("Lx,Lv,order", [(2, 2, 0), (2, 2, 1), (2, 2, 2), (2, 2, 3), (2, 2, 4),
+                                         (2, 5, 0), (5, 2, 0), (2, 5, 2), (5, 2, 3)])
+def test_smallest_grids_equal_dense_oracle(B, Lx, Lv, order):
+    """The smallest accepted grids (two bits in a dimension: chains of four
+    sites, edge sites that are also the neighbours of the junction), chi
+    unbounded, tol = 0: f, n and E equal the dense steps."""
+    _say("smallest grid Lx=%d Lv=%d order=%d" % (Lx, Lv, order))
+    w = _untruncated(wl.landau_small(L=Lx, Lv=Lv))
+    p = w.problem
+    p.order = order
+    st = B.MpsState(p, w.ax, w.bv)
+    F = odense.initial(w.ax, w.bv)
+    for k in range(3):
+        st.step(1)
+        F = odense.rk4_step(F, p)
+    G = st.to_dense().cpu().numpy()
+    assert np.abs(G - F).max() <= 1e-12 * np.abs(F).max()
+    n, E = st.density_field()
+    Ed = odense.field(F, p)
+    assert np.abs(E.cpu().numpy() - Ed).max() <= 1e-10 * max(np.abs(Ed).max(), 1e-300)
+    nd = odense.density(F, p.dv)
+    assert np.abs(n.cpu().numpy() - nd).max() <= 1e-12 * np.abs(nd).max()
+    st.free()
