@@ -13,9 +13,12 @@
 // The reflectors go to global memory, column-major, for later application.
 //
 // Application: Q Y or Q^T Y for a block of columns Y; each wave owns CPW
-// columns and streams the reflectors from L2.  There is no dependency
-// between columns, so the kernel has no barrier and spreads over as many
-// workgroups as the column count allows.  Panels of a wider matrix are
+// columns and streams the reflectors from L2, several steps ahead of their
+// use, with the reflector scalars held in lane registers.  Up to 256 rows
+// the reflectors are applied four at a time as compact-WY blocks (one
+// cross-lane reduction per block instead of one per reflector).  There is
+// no dependency between columns, so the kernel has no barrier and spreads
+// over as many workgroups as the column count allows.  Panels of a wider matrix are
 // factored one after the other with the trailing columns updated by the
 // same application kernel (blocked right-looking QR without a T factor).
 #include <algorithm>
@@ -478,44 +481,208 @@ __global__ __launch_bounds__(AT) void qr_reg_apply_kernel(
       y[a][b] = (i < rows_in && c0 + b < p)
                     ? Yin.p[(long)i * Yin.rs + (long)(c0 + b) * Yin.cs] : 0.0;
     }
-  double vn[RPL];
-  {
-    const int j = trans ? 0 : k - 1;
+  // the scalars of all k <= 128 reflectors in two lane registers, read by
+  // lane index in the loop (no memory round trip per reflector)
+  const double ta = (l < k) ? tau[l] : 0.0;
+  const double tb = (l + 64 < k) ? tau[l + 64] : 0.0;
+  if constexpr (RPL <= 4) {
+    // Blocks of four reflectors as one compact-WY product (forward
+    // accumulation of the triangular factor): Q_B = H_j0 H_j0+1 H_j0+2
+    // H_j0+3 = I - V T V^T with T upper triangular, T_ii = tau_i and
+    // T_{<i,i} = -tau_i T_{<i,<i} (V_{<i}^T v_i).  Q Y applies the blocks
+    // last to first as Y - V (T (V^T Y)), Q^T Y first to last as
+    // Y - V (T^T (V^T Y)).  The products V^T Y and the six V^T V entries
+    // of a block are reduced across the wave together, so a block costs
+    // one reduction instead of four dependent ones.  Reflectors past k
+    // enter as zero with tau = 0 (the identity).  Blocks are loaded PB
+    // ahead into a register ring; rows past m read row m - 1 and are
+    // zeroed when the block is used (no branch around the loads).
+    constexpr int BK = 4;
+    constexpr int PB = RPL <= 2 ? 2 : 1;
+    constexpr int NR = BK * CPW + 6;
+    constexpr int NRP = (NR + 3) / 4 * 4;
+    const int nb = (k + BK - 1) / BK;
+    auto roff = [&](int a) { return (long)min(l + 64 * a, m - 1); };
+    auto blk = [&](int t) { return trans ? t : nb - 1 - t; };
+    double ring[PB][BK][RPL];
 #pragma unroll
-    for (int a = 0; a < RPL; ++a) {
-      const int i = l + 64 * a;
-      vn[a] = (i < m) ? V[(long)j * m + i] : 0.0;
+    for (int q = 0; q < PB; ++q) {
+      const int B = blk(min(q, nb - 1));
+#pragma unroll
+      for (int i = 0; i < BK; ++i) {
+        const long j = min(BK * B + i, k - 1);
+#pragma unroll
+        for (int a = 0; a < RPL; ++a) ring[q][i][a] = V[j * m + roff(a)];
+      }
     }
-  }
-  for (int s = 0; s < k; ++s) {
-    const int j = trans ? s : k - 1 - s;
-    double v[RPL];
+    for (int t0 = 0; t0 < nb; t0 += PB) {
 #pragma unroll
-    for (int a = 0; a < RPL; ++a) v[a] = vn[a];
-    if (s + 1 < k) {
-      const int jn = trans ? s + 1 : k - 2 - s;
+      for (int q = 0; q < PB; ++q) {
+        const int t = t0 + q;
+        if (t >= nb) break;  // uniform
+        const int B = blk(t);
+        double v[BK][RPL];
+        double tq[BK];
+#pragma unroll
+        for (int i = 0; i < BK; ++i) {
+          const int j = BK * B + i;
+          const bool ok = j < k;
+#pragma unroll
+          for (int a = 0; a < RPL; ++a)
+            v[i][a] = (ok && l + 64 * a < m) ? ring[q][i][a] : 0.0;
+          const double tj = wave::read_lane(j < 64 ? ta : tb, j & 63);
+          tq[i] = ok ? tj : 0.0;
+        }
+        {
+          const int Bn = blk(min(t + PB, nb - 1));
+#pragma unroll
+          for (int i = 0; i < BK; ++i) {
+            const long j = min(BK * Bn + i, k - 1);
+#pragma unroll
+            for (int a = 0; a < RPL; ++a) ring[q][i][a] = V[j * m + roff(a)];
+          }
+        }
+        // r = [V^T y (BK x CPW), v0.v1, v0.v2, v0.v3, v1.v2, v1.v3, v2.v3, 0..]
+        double r[NRP];
+#pragma unroll
+        for (int e = 0; e < NRP; ++e) r[e] = 0.0;
+#pragma unroll
+        for (int a = 0; a < RPL; ++a) {
+#pragma unroll
+          for (int i = 0; i < BK; ++i)
+#pragma unroll
+            for (int b = 0; b < CPW; ++b) r[i * CPW + b] = fma(v[i][a], y[a][b], r[i * CPW + b]);
+          r[BK * CPW + 0] = fma(v[0][a], v[1][a], r[BK * CPW + 0]);
+          r[BK * CPW + 1] = fma(v[0][a], v[2][a], r[BK * CPW + 1]);
+          r[BK * CPW + 2] = fma(v[0][a], v[3][a], r[BK * CPW + 2]);
+          r[BK * CPW + 3] = fma(v[1][a], v[2][a], r[BK * CPW + 3]);
+          r[BK * CPW + 4] = fma(v[1][a], v[3][a], r[BK * CPW + 4]);
+          r[BK * CPW + 5] = fma(v[2][a], v[3][a], r[BK * CPW + 5]);
+        }
+        wave::sums<NRP>(r);
+        const double g01 = r[BK * CPW + 0], g02 = r[BK * CPW + 1], g03 = r[BK * CPW + 2];
+        const double g12 = r[BK * CPW + 3], g13 = r[BK * CPW + 4], g23 = r[BK * CPW + 5];
+        const double T00 = tq[0], T11 = tq[1], T22 = tq[2], T33 = tq[3];
+        const double T01 = -tq[1] * (T00 * g01);
+        const double T12 = -tq[2] * (T11 * g12);
+        const double T02 = -tq[2] * fma(T00, g02, T01 * g12);
+        const double T23 = -tq[3] * (T22 * g23);
+        const double T13 = -tq[3] * fma(T11, g13, T12 * g23);
+        const double T03 = -tq[3] * fma(T00, g03, fma(T01, g13, T02 * g23));
+#pragma unroll
+        for (int b = 0; b < CPW; ++b) {
+          const double w0 = r[0 * CPW + b], w1 = r[1 * CPW + b];
+          const double w2 = r[2 * CPW + b], w3 = r[3 * CPW + b];
+          double u0, u1, u2, u3;
+          if (trans) {
+            u0 = T00 * w0;
+            u1 = fma(T01, w0, T11 * w1);
+            u2 = fma(T02, w0, fma(T12, w1, T22 * w2));
+            u3 = fma(T03, w0, fma(T13, w1, fma(T23, w2, T33 * w3)));
+          } else {
+            u0 = fma(T00, w0, fma(T01, w1, fma(T02, w2, T03 * w3)));
+            u1 = fma(T11, w1, fma(T12, w2, T13 * w3));
+            u2 = fma(T22, w2, T23 * w3);
+            u3 = T33 * w3;
+          }
+#pragma unroll
+          for (int a = 0; a < RPL; ++a)
+            y[a][b] -= fma(v[0][a], u0, fma(v[1][a], u1, fma(v[2][a], u2, v[3][a] * u3)));
+        }
+      }
+    }
+  } else if constexpr (RPL <= 16) {
+    // reflectors in flight: a ring of PF register slots, slot q holding the
+    // reflector of step s0 + q and refilled with that of step s0 + q + PF as
+    // soon as it is consumed, so each load has PF steps to arrive.  The loads
+    // are unconditional (rows past m read row m - 1, steps past k the last
+    // reflector) so that no branch makes the compiler wait for all of them;
+    // rows past m are zeroed when a reflector is used.
+    constexpr int PF = RPL <= 2 ? 8 : (RPL <= 4 ? 4 : 2);
+    auto roff = [&](int a) { return (long)min(l + 64 * a, m - 1); };
+    double ring[PF][RPL];
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+      const int sq = min(q, k - 1);
+      const long j = trans ? sq : k - 1 - sq;
+#pragma unroll
+      for (int a = 0; a < RPL; ++a) ring[q][a] = V[j * m + roff(a)];
+    }
+    for (int s0 = 0; s0 < k; s0 += PF) {
+#pragma unroll
+      for (int q = 0; q < PF; ++q) {
+        const int s = s0 + q;
+        if (s >= k) break;  // uniform
+        double v[RPL];
+#pragma unroll
+        for (int a = 0; a < RPL; ++a) v[a] = (l + 64 * a < m) ? ring[q][a] : 0.0;
+        {
+          const int sn = min(s + PF, k - 1);
+          const long jn = trans ? sn : k - 1 - sn;
+#pragma unroll
+          for (int a = 0; a < RPL; ++a) ring[q][a] = V[jn * m + roff(a)];
+        }
+        const int j = trans ? s : k - 1 - s;
+        const double tj = wave::read_lane(j < 64 ? ta : tb, j & 63);
+        if (tj == 0.0) continue;
+        double d[CPW];
+#pragma unroll
+        for (int b = 0; b < CPW; ++b) {
+          double acc = 0.0;
+#pragma unroll
+          for (int a = 0; a < RPL; ++a) acc = fma(v[a], y[a][b], acc);
+          d[b] = acc;
+        }
+        wave::sums<CPW>(d);
+#pragma unroll
+        for (int b = 0; b < CPW; ++b) {
+          const double f = tj * d[b];
+#pragma unroll
+          for (int a = 0; a < RPL; ++a) y[a][b] = fma(-v[a], f, y[a][b]);
+        }
+      }
+    }
+  } else {
+    // many rows per lane: one reflector ahead (the registers hold no more)
+    double vn[RPL];
+    {
+      const int j = trans ? 0 : k - 1;
 #pragma unroll
       for (int a = 0; a < RPL; ++a) {
         const int i = l + 64 * a;
-        vn[a] = (i < m) ? V[(long)jn * m + i] : 0.0;
+        vn[a] = (i < m) ? V[(long)j * m + i] : 0.0;
       }
     }
-    const double tj = tau[j];
-    if (tj == 0.0) continue;
-    double d[CPW];
+    for (int s = 0; s < k; ++s) {
+      const int j = trans ? s : k - 1 - s;
+      double v[RPL];
 #pragma unroll
-    for (int b = 0; b < CPW; ++b) {
-      double acc = 0.0;
+      for (int a = 0; a < RPL; ++a) v[a] = vn[a];
+      if (s + 1 < k) {
+        const int jn = trans ? s + 1 : k - 2 - s;
 #pragma unroll
-      for (int a = 0; a < RPL; ++a) acc = fma(v[a], y[a][b], acc);
-      d[b] = acc;
-    }
-    wave::sums<CPW>(d);
+        for (int a = 0; a < RPL; ++a) {
+          const int i = l + 64 * a;
+          vn[a] = (i < m) ? V[(long)jn * m + i] : 0.0;
+        }
+      }
+      const double tj = wave::read_lane(j < 64 ? ta : tb, j & 63);
+      if (tj == 0.0) continue;
+      double d[CPW];
 #pragma unroll
-    for (int b = 0; b < CPW; ++b) {
-      const double f = tj * d[b];
+      for (int b = 0; b < CPW; ++b) {
+        double acc = 0.0;
 #pragma unroll
-      for (int a = 0; a < RPL; ++a) y[a][b] = fma(-v[a], f, y[a][b]);
+        for (int a = 0; a < RPL; ++a) acc = fma(v[a], y[a][b], acc);
+        d[b] = acc;
+      }
+      wave::sums<CPW>(d);
+#pragma unroll
+      for (int b = 0; b < CPW; ++b) {
+        const double f = tj * d[b];
+#pragma unroll
+        for (int a = 0; a < RPL; ++a) y[a][b] = fma(-v[a], f, y[a][b]);
+      }
     }
   }
 #pragma unroll
@@ -619,7 +786,8 @@ void qr_reg_apply(hipStream_t s, const double* V, const double* tau, int m,
                   int k, CMatView Yin, int rows_in, MatView Yout, int p,
                   bool trans) {
   if (p <= 0 || k <= 0) return;
-  MPSV_CHECK(m >= 1 && m <= 2048 && k <= m, kEinval, "qr_reg_apply: bad shape");
+  MPSV_CHECK(m >= 1 && m <= 2048 && k <= m && k <= 128, kEinval,
+             "qr_reg_apply: bad shape");
   const int rpl = rows_per_lane(m);
   const int cpw = (p >= 128 && rpl < 32) ? 2 : 1;
   const int slot = prof_begin(s);
@@ -664,7 +832,8 @@ void qr_reg_apply_chunks(hipStream_t s, const double* V, const double* tau,
                          int m, int k, int rows, MatView Y, int p, bool trans) {
   if (p <= 0 || k <= 0) return;
   const int nch = (m + rows - 1) / rows;
-  MPSV_CHECK(rows >= k && rows <= 2048, kEinval, "qr_reg_apply_chunks: bad shape");
+  MPSV_CHECK(rows >= k && rows <= 2048 && k <= 128, kEinval,
+             "qr_reg_apply_chunks: bad shape");
   const int rpl = rows_per_lane(rows);
   const int cpw = (p >= 128 && rpl < 32) ? 2 : 1;
   const int slot = prof_begin(s);
