@@ -53,6 +53,7 @@ import numpy as np  # noqa: E402
 import workloads as wl  # noqa: E402
 
 PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 (matrix and vector)
+MI355X_CUS = 256
 PEAK_HBM_GBS = 8000.0
 
 
@@ -142,7 +143,7 @@ def measured_traffic(cls):
         return None
 
 
-def roofline(binding, st, cores_host, steps):
+def roofline(binding, st, cores_host, steps, jacobi_cols):
     """Re-run `steps` steps from the same state with every launch of the
     instrumented kernels bracketed by HIP events on the launching stream;
     report the class with the largest event time.  achieved = nominal FLOPs
@@ -165,11 +166,18 @@ def roofline(binding, st, cores_host, steps):
     # the whole step: nominal FLOPs of every instrumented launch per step
     # (GEMM 2mnk, GEQRF, reflector applications, SVD 6mn^2 + 20n^3)
     step_gflop = sum(v["flops"] for k, v in rec.items() if k in _CLASS_BOUND) / steps / 1e9
-    return {"bound": bound, "achieved": ach, "peak": peak, "unit": "TFLOP/s",
-            "frac": ach / peak, "traffic": measured_traffic(dom), "kernel": dom,
-            "launches": r["launches"], "avg_launch_us": 1000.0 * r["ms"] / max(r["launches"], 1),
-            "flops_per_launch": r["flops"] / max(r["launches"], 1),
-            "classes": classes, "step_gflop": step_gflop}
+    out = {"bound": bound, "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+           "frac": ach / peak, "traffic": measured_traffic(dom), "kernel": dom,
+           "launches": r["launches"], "avg_launch_us": 1000.0 * r["ms"] / max(r["launches"], 1),
+           "flops_per_launch": r["flops"] / max(r["launches"], 1),
+           "classes": classes, "step_gflop": step_gflop}
+    if dom == "jacobi_svd":
+        # a Jacobi SVD of up to 128 columns runs as one workgroup (one CU),
+        # of up to 256 as four: its rate against the peak of the CUs it holds
+        wgs = 1 if jacobi_cols <= 128 else 4
+        out["workgroups_per_launch"] = wgs
+        out["frac_of_its_cus"] = ach / (peak * wgs / MI355X_CUS)
+    return out
 
 
 _PREC_NAMES = {1: "fp32 contraction (MFMA f32, FP32 accumulate)",
@@ -450,7 +458,7 @@ def main():
     roof = None
     cpu = None
     if not args.no_roofline:
-        roof = roofline(binding, st, cores_host, min(args.steps, 3))
+        roof = roofline(binding, st, cores_host, min(args.steps, 3), 2 * p.chi_max)
         # whole-step algorithmic rate at the timed steps/s, against FP64 peak
         roof["step_tflops"] = roof["step_gflop"] * value / 1e3
         roof["step_frac"] = roof["step_tflops"] / PEAK_FP64_TFLOPS
