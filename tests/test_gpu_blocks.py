@@ -103,6 +103,27 @@ def test_qr_is_orthogonal_factorisation(B, m, n):
     assert np.allclose(np.abs(np.diag(R)), np.abs(np.diag(Rref[:k])), rtol=1e-10, atol=1e-13)
 
 
+@pytest.mark.parametrize("m,n", [(63, 21), (128, 127), (250, 101), (500, 77), (1000, 45)])
+def test_qr_with_zero_and_repeated_columns(B, m, n):
+    """Exactly rank-deficient columns give reflectors with tau = 0 (the
+    identity) in the middle of the factor; the numbers of reflectors are
+    not multiples of the application's block of four.  Q stays orthogonal
+    and QR = A."""
+    _say("qr rank-deficient columns %d x %d" % (m, n))
+    A = wl.random_matrix(m, n, seed=5 * m + n, decay=2.0)
+    A[:, 3] = 0.0
+    A[:, 4] = 0.0
+    A[:, 10] = A[:, 9]
+    A[:, n - 1] = 0.0
+    R, Q = B.qr(A)
+    R = R.cpu().numpy()
+    Q = Q.cpu().numpy()
+    k = min(m, n)
+    assert np.abs(Q.T @ Q - np.eye(k)).max() < 1e-13 * max(1, np.sqrt(m))
+    assert np.abs(Q @ R - A).max() < 1e-13 * np.abs(A).max() * max(1, np.sqrt(m))
+    assert np.allclose(np.tril(R, -1), 0)
+
+
 @pytest.mark.parametrize("m,c,cap,tol,decay", [
     (2, 2, 0, 0.0, 0), (10, 4, 0, 0.0, 0), (4, 10, 0, 0.0, 0), (64, 64, 0, 0.0, 6),
     (96, 96, 40, 0.0, 8), (128, 128, 64, 0.0, 8), (500, 128, 64, 0.0, 12),
