@@ -44,6 +44,18 @@ namespace {
 constexpr int FT = 1024;  // factorisation workgroup: 16 waves
 constexpr int AT = 256;   // application workgroup: 4 waves
 
+// 1 / x from the hardware reciprocal estimate refined by two Newton steps
+// (e = 1 - x y, y <- y + y e), within about one unit in the last place;
+// shorter than the correctly rounded division on the reflector's critical
+// path.  x is finite and non-zero where it is used.
+__device__ __forceinline__ double recip(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+
 template <int N>
 __device__ __forceinline__ void sums_any(double (&p)[N]) {
   if constexpr (N == 1 || N == 2 || N == 4 || N == 8) {
@@ -86,8 +98,8 @@ __device__ __forceinline__ void factor_block(double (&x)[RPL][CPW], int w,
       double tj = 0.0, beta = alpha, scal = 0.0;
       if (s2 > 0.0) {
         beta = -copysign(sqrt(fma(alpha, alpha, s2)), alpha);
-        tj = (beta - alpha) / beta;
-        scal = 1.0 / (alpha - beta);
+        tj = (beta - alpha) * recip(beta);
+        scal = recip(alpha - beta);
       }
       // The reflector goes to global memory now, or (32 rows per lane,
       // where the row addresses would not fit in registers) stays below the
@@ -243,8 +255,8 @@ __global__ __launch_bounds__(FT) void qr_g16_factor_kernel(
         double tj = 0.0, beta = alpha, scal = 0.0;
         if (s2 > 0.0) {
           beta = -copysign(sqrt(fma(alpha, alpha, s2)), alpha);
-          tj = (beta - alpha) / beta;
-          scal = 1.0 / (alpha - beta);
+          tj = (beta - alpha) * recip(beta);
+          scal = recip(alpha - beta);
         }
         double* Vj = V + (long)j * m;
 #pragma unroll
@@ -328,8 +340,8 @@ __device__ __forceinline__ void blk_factor_col(double (&x)[RPL][8], int p,
   double tj = 0.0, beta = alpha, scal = 0.0;
   if (s2 > 0.0) {
     beta = -copysign(sqrt(fma(alpha, alpha, s2)), alpha);
-    tj = (beta - alpha) / beta;
-    scal = 1.0 / (alpha - beta);
+    tj = (beta - alpha) * recip(beta);
+    scal = recip(alpha - beta);
   }
   double v[RPL];
 #pragma unroll
