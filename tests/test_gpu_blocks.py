@@ -131,7 +131,10 @@ def test_qr_with_zero_and_repeated_columns(B, m, n):
     (2000, 128, 64, 0.0, 10), (60, 1500, 0, 1e-8, 6),
     # 129..256 columns: the two-workgroup Jacobi kernel
     (129, 129, 0, 0.0, 6), (256, 256, 128, 0.0, 10), (1024, 256, 128, 0.0, 12),
-    (200, 256, 0, 1e-10, 14), (256, 600, 100, 0.0, 8), (3000, 160, 0, 1e-12, 16)])
+    (200, 256, 0, 1e-10, 14), (256, 600, 100, 0.0, 8), (3000, 160, 0, 1e-12, 16),
+    # more than 256 columns in the smaller dimension: the global-memory Jacobi
+    (300, 300, 0, 0.0, 8), (600, 300, 150, 0.0, 10), (300, 700, 0, 1e-10, 12),
+    (512, 512, 0, 1e-10, 12), (1000, 1000, 300, 0.0, 10)])
 def test_svd_truncate_matches_lapack_and_rank_rule(B, m, c, cap, tol, decay):
     _say("svd %d x %d cap %d tol %g" % (m, c, cap, tol))
     X = wl.random_matrix(m, c, seed=3 * m + c, decay=decay)

@@ -9,6 +9,7 @@ import pytest
 import workloads as wl
 from oracle import dense as odense
 from oracle import mps as omps
+from tests import _start as S
 
 pytestmark = pytest.mark.gpu
 
@@ -49,9 +50,8 @@ def test_truncated_collisional_steps_match_mps_oracle(B):
     w = wl.two_stream(L=5, chi=8, tol=0.0, level=5, df_max=4, dt_cfg=0.05, order=0)
     p = w.problem
     p.nu, p.nu_v0, p.nu_vth = 0.2, 0.0, 1.0
-    st = B.MpsState(p, w.ax, w.bv)
-    st.add_scaled(1e-3, wl.random_mps_cores(p.n_sites, 8, seed=2205))
-    f = st.get_cores_host()
+    f = S.oracle_start(w, pert_chi=8, amp=1e-3)
+    st = S.gpu_state(B, w, f)
     ops = omps.Operators(p)
     for _ in range(2):
         st.step(1)
@@ -111,7 +111,8 @@ def test_untruncated_buneman_plasma_equals_dense_oracle(B):
 def test_truncated_buneman_plasma_matches_mps_oracle(B, order, comp, nu):
     """Electrons and ions, every point capped (C5, chi = 8, D_F = 4), the
     electrons perturbed to full bonds: both species and the shared field
-    within 1e-8 of the MPS oracle after 2 steps from the same states (S1,
+    within 1e-8 of the MPS oracle after 2 steps from the same states (the
+    oracle's, handed to the GPU; S1,
     IF, S2 with centre-first compression and collisions, IG with
     collisions)."""
     _say("truncated buneman plasma L=5 chi8 order=%d compression=%d nu=%g" % (order, comp, nu))
@@ -120,10 +121,9 @@ def test_truncated_buneman_plasma_matches_mps_oracle(B, order, comp, nu):
     for p in ps:
         p.compression = comp
     pl = B.Plasma(ps, q, [(w.ax, w.bv) for w in ws])
-    pl.species(0).add_scaled(1e-4, wl.random_mps_cores(ps[0].n_sites, 8, seed=2205))
-    fs = [pl.species(s).get_cores_host() for s in range(2)]
-    if order == 4:
-        fs = [omps.fuse_pairs(f) for f in fs]
+    fs = [S.oracle_start(ws[0], pert_chi=8, amp=1e-4), S.oracle_start(ws[1])]
+    for s, (f, p) in enumerate(zip(fs, ps)):
+        pl.species(s).set_cores(S.binary_cores(f, p))
     opss = [omps.Operators(p) for p in ps]
     for _ in range(2):
         pl.step(1)

@@ -8,6 +8,7 @@ import pytest
 import workloads as wl
 from oracle import dense as odense
 from oracle import mps as omps
+from tests import _start as S
 
 pytestmark = pytest.mark.gpu
 
@@ -83,11 +84,11 @@ def test_untruncated_two_stream_interleaved(B):
 
 
 def _from_same_state(B, w, steps):
-    """Run the GPU and the CPU MPS oracle from the same MPS (exported from the
-    GPU after init) and compare reconstructed f and E."""
+    """Run the GPU and the CPU MPS oracle from the same MPS (the oracle's
+    initial state, handed to the GPU) and compare reconstructed f and E."""
     p = w.problem
-    st = B.MpsState(p, w.ax, w.bv)
-    f = st.get_cores_host()
+    f = S.oracle_start(w)
+    st = S.gpu_state(B, w, f)
     ops = omps.Operators(p)
     for _ in range(steps):
         st.step(1)
@@ -120,10 +121,8 @@ def test_truncated_fixed_chi_level5_matches_mps_oracle(B):
     _say("truncated C5 chi8 two-stream L=5 IF")
     w = wl.two_stream(L=5, chi=8, tol=0.0, level=5, df_max=4, dt_cfg=0.05)
     p = w.problem
-    st = B.MpsState(p, w.ax, w.bv)
-    pert = wl.random_mps_cores(p.n_sites, 8, seed=2205)
-    st.add_scaled(1e-3, pert)
-    f = st.get_cores_host()
+    f = S.oracle_start(w, pert_chi=8, amp=1e-3)
+    st = S.gpu_state(B, w, f)
     ops = omps.Operators(p)
     for _ in range(2):
         st.step(1)
@@ -134,22 +133,125 @@ def test_truncated_fixed_chi_level5_matches_mps_oracle(B):
     st.free()
 
 
+@pytest.mark.parametrize("level", [2, 3, 4])
+def test_truncated_levels_2_to_4_match_mps_oracle(B, level):
+    """Compression levels C2, C3 and C4 (SI, Compressed time evolution
+    algorithm): the stage states, then also the sum of the k's, then also
+    each k cut to chi = 8; every other point compressed with tol = 0, i.e.
+    exactly.  Two steps from the same perturbed state: f and E within 1e-8
+    of the CPU MPS oracle, identical bonds."""
+    _say("truncated level C%d chi8 two-stream L=5 IF" % level)
+    w = wl.two_stream(L=5, chi=8, tol=0.0, level=level, df_max=4, dt_cfg=0.05)
+    p = w.problem
+    f = S.oracle_start(w, pert_chi=8, amp=1e-3)
+    st = S.gpu_state(B, w, f)
+    ops = omps.Operators(p)
+    for _ in range(2):
+        st.step(1)
+        f = omps.rk4_step(f, ops)
+    G = st.to_dense().cpu().numpy()
+    R = omps.to_dense(f, p)
+    _, E = st.density_field()
+    Eref = omps.field_dense(f, ops)
+    assert np.abs(G - R).max() <= 1e-8 * np.abs(R).max()
+    assert np.abs(E.cpu().numpy() - Eref).max() <= 1e-8 * np.abs(Eref).max()
+    assert st.info()["bonds"][1:-1] == omps.bond_dims(f)
+    st.free()
+
+
+def test_physics_mode_metric_grid_matches_mps_oracle(B):
+    """The paper's default schedule at the metric's grid: two-stream
+    2^10 x 2^10, interleaved, C1 (only the new state capped at chi = 64),
+    per-bond tolerance 1e-10 at every point, uncapped field, from f0.  One
+    RK4 step on the GPU and in the CPU MPS oracle from the same state: f
+    and E within 1e-8, identical bonds."""
+    _say("physics mode two-stream 2^10 chi64 C1 tol 1e-10")
+    w = wl.two_stream(L=10, chi=64, tol=1e-10, level=1, df_max=0, dt_cfg=0.02)
+    p = w.problem
+    f0 = S.oracle_start(w)
+    st = S.gpu_state(B, w, f0)
+    st.step(1)
+    G = st.to_dense().cpu().numpy()
+    _, E = st.density_field()
+    ops = omps.Operators(p)
+    f = omps.rk4_step(f0, ops)
+    R = omps.to_dense(f, p)
+    Eref = omps.field_dense(f, ops)
+    assert np.abs(G - R).max() <= 1e-8 * np.abs(R).max()
+    assert np.abs(E.cpu().numpy() - Eref).max() <= 1e-8 * np.abs(Eref).max()
+    assert st.info()["bonds"][1:-1] == omps.bond_dims(f)
+    st.free()
+
+
+@pytest.mark.timeout(900)
+def test_chi128_metric_size_step_matches_mps_oracle(B):
+    """The bond-cap-128 configuration at its full size: two-stream
+    2^12 x 2^12, interleaved (24 sites), every point capped at 128 (C5),
+    D_F = 4, tol = 0, from the seeded state perturbed to bonds of 128.  Its
+    field term meets QR blocks taller than 2048 rows (the TSQR panels) and
+    SVDs of 256 columns inside the step.  One RK4 step on the GPU and in
+    the CPU MPS oracle (about a minute of CPU time) from the same state: f
+    on 4096 sampled grid points, the whole field E and the moments within
+    1e-8, identical bonds."""
+    _say("two-stream 2^12 chi128 C5 against the oracle (slow)")
+    w = wl.two_stream(L=12, chi=128, tol=0.0, level=5, df_max=4, dt_cfg=0.02)
+    p = w.problem
+    f0 = S.oracle_start(w, pert_chi=128,
+                        amp=1e-6 * float(np.linalg.norm(w.ax) * np.linalg.norm(w.bv)))
+    st = S.gpu_state(B, w, f0)
+    st.step(1)
+    g = st.get_cores_host()
+    _, E = st.density_field()
+    _, _, sc = st.moments()
+    ops = omps.Operators(p)
+    f = omps.rk4_step(f0, ops)
+    assert st.info()["bonds"][1:-1] == omps.bond_dims(f)
+    rng = np.random.default_rng(4096)
+    pts = list(zip(rng.integers(0, p.Nx, 4096), rng.integers(0, p.Nv, 4096)))
+    a, r = _sample_if(g, p, pts), _sample_if(f, p, pts)
+    assert np.abs(a - r).max() <= 1e-8 * np.abs(r).max()
+    Eref = omps.field_dense(f, ops)
+    assert np.abs(E.cpu().numpy() - Eref).max() <= 1e-8 * np.abs(Eref).max()
+    ref = omps.moments(f, ops)
+    for k in ("mass", "momentum", "kinetic"):
+        assert abs(sc[k] - ref[k]) <= 1e-9 * max(abs(ref["mass"]), 1.0), k
+    st.free()
+
+
+def _sample_if(cores, p, pts):
+    """f at grid points (i, j) of an interleaved (IF) chain: site 2k takes
+    x bit k, site 2k+1 v bit k (coarsest first)."""
+    assert p.order == 1 and p.Lx == p.Lv
+    out = []
+    for i, j in pts:
+        v = np.ones(1)
+        for s, A in enumerate(cores):
+            k = s // 2
+            bit = ((i >> (p.Lx - 1 - k)) & 1) if s % 2 == 0 else ((j >> (p.Lv - 1 - k)) & 1)
+            v = v @ A[:, bit, :]
+        out.append(v[0])
+    return np.array(out)
+
+
 @pytest.mark.parametrize("order", [0, 2, 3])
 def test_moments_match_oracle(B, order):
     _say("moments order=%d" % order)
     w = wl.landau_small(L=6, chi=16, tol=1e-10)
     p = w.problem
     p.order = order
-    st = B.MpsState(p, w.ax, w.bv)
+    f = S.oracle_start(w)
+    st = S.gpu_state(B, w, f)
     st.step(2)
-    f = st.get_cores_host()
     ops = omps.Operators(p)
+    f = omps.rk4_step(omps.rk4_step(f, ops), ops)
     n, E, sc = st.moments()
     ref = omps.moments(f, ops)
+    # two steps apart the states agree to the truncation tolerance; the
+    # moments are compared on the scale of the mass (momentum is ~0 here)
     for k in ref:
-        assert abs(sc[k] - ref[k]) <= 1e-10 * max(abs(ref[k]), 1e-3), k
+        assert abs(sc[k] - ref[k]) <= 1e-10 * max(abs(ref[k]), abs(ref["mass"])), k
     F = omps.to_dense(f, p)
-    assert np.abs(n.cpu().numpy() - odense.density(F, p.dv)).max() < 1e-12
+    assert np.abs(n.cpu().numpy() - odense.density(F, p.dv)).max() < 1e-10
     st.free()
 
 
@@ -224,10 +326,9 @@ def test_full_size_bench_workload_matches_mps_oracle(B):
     _say("full size two-stream 2^10 chi64 C5")
     w = wl.two_stream(L=10, chi=64, tol=0.0, level=5, df_max=4, dt_cfg=0.02)
     p = w.problem
-    st = B.MpsState(p, w.ax, w.bv)
-    pert = wl.random_mps_cores(p.n_sites, 64, seed=2205)
-    st.add_scaled(1e-6 * float(np.linalg.norm(w.ax) * np.linalg.norm(w.bv)), pert)
-    f0 = st.get_cores_host()
+    f0 = S.oracle_start(w, pert_chi=64,
+                        amp=1e-6 * float(np.linalg.norm(w.ax) * np.linalg.norm(w.bv)))
+    st = S.gpu_state(B, w, f0)
     st.step(1)
     G = st.to_dense().cpu().numpy()
     _, E, _ = st.moments()
@@ -287,10 +388,9 @@ def test_chi128_step_matches_mps_oracle(B):
     _say("two-stream 2^8 chi128 C5")
     w = wl.two_stream(L=8, chi=128, tol=0.0, level=5, df_max=4, dt_cfg=0.02)
     p = w.problem
-    st = B.MpsState(p, w.ax, w.bv)
-    pert = wl.random_mps_cores(p.n_sites, 128, seed=2205)
-    st.add_scaled(1e-6 * float(np.linalg.norm(w.ax) * np.linalg.norm(w.bv)), pert)
-    f0 = st.get_cores_host()
+    f0 = S.oracle_start(w, pert_chi=128,
+                        amp=1e-6 * float(np.linalg.norm(w.ax) * np.linalg.norm(w.bv)))
+    st = S.gpu_state(B, w, f0)
     assert max(c.shape[2] for c in f0) == 128
     st.step(1)
     G = st.to_dense().cpu().numpy()
@@ -335,10 +435,8 @@ def test_truncated_upwind_matches_mps_oracle(B, order):
     w = wl.two_stream(L=5, chi=8, tol=0.0, level=5, df_max=4, dt_cfg=0.05, order=order)
     p = w.problem
     p.x_scheme = 1
-    st = B.MpsState(p, w.ax, w.bv)
-    pert = wl.random_mps_cores(p.n_sites, 8, seed=2205)
-    st.add_scaled(1e-3, pert)
-    f = st.get_cores_host()
+    f = S.oracle_start(w, pert_chi=8, amp=1e-3)
+    st = S.gpu_state(B, w, f)
     ops = omps.Operators(p)
     for _ in range(2):
         st.step(1)
@@ -387,10 +485,10 @@ def test_entanglement_entropy_matches_oracle(B):
     the closed form."""
     _say("entanglement entropy")
     w = wl.landau_small(L=5, chi=16, tol=1e-10)
-    st = B.MpsState(w.problem, w.ax, w.bv)
-    st.step(3)
+    f = S.oracle_start(w, pert_chi=16, amp=1e-2)
+    st = S.gpu_state(B, w, f)
     ee = st.entanglement()
-    ref = omps.entanglement_entropy(st.get_cores_host())
+    ref = omps.entanglement_entropy(f)
     assert np.abs(np.array(ee) - np.array(ref)).max() < 1e-9
     st.free()
     p = wl.landau_small(L=4).problem
@@ -437,10 +535,8 @@ def test_truncated_centre_first_matches_mps_oracle(B, scheme, order):
     p = w.problem
     p.compression = 1
     p.x_scheme = scheme
-    st = B.MpsState(p, w.ax, w.bv)
-    pert = wl.random_mps_cores(p.n_sites, 8, seed=2205)
-    st.add_scaled(1e-3, pert)
-    f = st.get_cores_host()
+    f = S.oracle_start(w, pert_chi=8, amp=1e-3)
+    st = S.gpu_state(B, w, f)
     ops = omps.Operators(p)
     for _ in range(2):
         st.step(1)
@@ -485,7 +581,7 @@ def test_untruncated_s2_s3_on_an_unequal_grid_equal_dense_oracle(B, order):
     Ed = odense.field(F, p)
     assert np.abs(E.cpu().numpy() - Ed).max() <= 1e-10 * np.abs(Ed).max()
     assert np.abs(n.cpu().numpy() - odense.density(F, p.dv)).max() <= 1e-12 * np.abs(odense.density(F, p.dv)).max()
-    vec = omps.to_vector(st.get_cores_host())
+    vec = _contract(st.get_cores_host())
     assert np.abs(vec - omps.dense_to_sites(F, p.Lx, p.Lv, order)).max() <= 1e-11 * np.abs(F).max()
     st.free()
 
@@ -558,16 +654,16 @@ def test_untruncated_ig_steps_equal_dense_oracle(B, L):
 
 def test_truncated_ig_matches_the_dimension_four_oracle(B):
     """IG with every point capped (C5, chi = 8): f and E within 1e-8 of the
-    oracle, which works on fused sites of dimension 4 (started from the GPU
-    state with each pair of binary cores contracted); the GPU's bonds
+    oracle, which works on fused sites of dimension 4 (the GPU starts from
+    the oracle's state, each fused site split into its two binary sites);
+    the GPU's bonds
     between pairs equal the oracle's bonds and none exceeds chi."""
     _say("truncated IG C5 chi8 two-stream L=5")
     w = wl.two_stream(L=5, chi=8, tol=0.0, level=5, df_max=4, dt_cfg=0.05)
     p = w.problem
     p.order = 4
-    st = B.MpsState(p, w.ax, w.bv)
-    st.add_scaled(1e-3, wl.random_mps_cores(p.n_sites, 8, seed=2205))
-    f = omps.fuse_pairs(st.get_cores_host())
+    f = S.oracle_start(w, pert_chi=8, amp=1e-3)
+    st = S.gpu_state(B, w, f)
     ops = omps.Operators(p)
     for _ in range(2):
         st.step(1)
@@ -608,15 +704,24 @@ def test_deferred_failure_leaves_state_unchanged(B):
     st.free()
 
 
+def _contract(cores):
+    """The vector an MPS of binary sites represents (site 0 most
+    significant)."""
+    v = np.ones((1, 1))
+    for A in cores:
+        v = (v @ A.reshape(A.shape[0], -1)).reshape(-1, A.shape[2])
+    return v.reshape(-1)
+
+
 def _sample(cores, p, pts):
-    """f at grid points (i, j), contracting the cores along the bits of each
-    point in chain order (the oracle's site map)."""
-    sm = omps.site_map(p.Lx, p.Lv, p.order)
+    """f at grid points (i, j) of a sequential-order (S1) chain: the x bits
+    (coarsest first) then the v bits pick one matrix per core."""
+    assert p.order == 0
     out = []
     for i, j in pts:
         v = np.ones(1)
-        for (d, k), A in zip(sm, cores):
-            bit = (i >> (p.Lx - 1 - k)) & 1 if d == "x" else (j >> (p.Lv - 1 - k)) & 1
+        for k, A in enumerate(cores):
+            bit = (i >> (p.Lx - 1 - k)) & 1 if k < p.Lx else (j >> (p.Lv - 1 - (k - p.Lx))) & 1
             v = v @ A[:, bit, :]
         out.append(v[0])
     return np.array(out)
@@ -629,9 +734,8 @@ def test_largest_grid_matches_mps_oracle_on_samples(B):
     _say("largest grid 2^14 x 2^14 chi 16")
     w = wl.two_stream(L=14, chi=16, tol=0.0, level=5, df_max=4, dt_cfg=0.02, order=0)
     p = w.problem
-    st = B.MpsState(p, w.ax, w.bv)
-    st.add_scaled(1e-6, wl.random_mps_cores(p.n_sites, 16, seed=7))
-    f = st.get_cores_host()
+    f = S.oracle_start(w, pert_chi=16, amp=1e-6, seed=7)
+    st = S.gpu_state(B, w, f)
     ops = omps.Operators(p)
     st.step(1)
     f = omps.rk4_step(f, ops)
