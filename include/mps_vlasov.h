@@ -246,6 +246,47 @@ mps_status mps_device_bytes(const mps_state* h, size_t* bytes);
 mps_status mps_step_batched(mps_state* const* hs, int32_t count, int32_t nsteps,
                             hipStream_t stream);
 
+/* Lock-step batch: count instances of one problem shape advanced together,
+ * every kernel launch of a step covering all of them (the method's cost is a
+ * long chain of small factorisations, SI "Canonicalization and Compression";
+ * one instance occupies a few compute units, a batch spreads the same chain
+ * over one workgroup per instance).  The instances share Lx, Lv, order,
+ * chi_max, level, df_max, precision, x_scheme, compression, qm and dt, have
+ * tol = 0 and cfl = 0 (fixed ranks: every compression keeps min(chi, k)
+ * values, so their shapes never differ) and are all collisional or all
+ * collisionless; intervals, collision constants and data may differ.  Each
+ * instance's result equals that of a stand-alone state stepped from the
+ * same cores, bit for bit.
+ * mps_batch_init: problems, ranks: host arrays of count (1..1024); ax[i],
+ * bv[i]: device profiles of instance i as for mps_init.  Every instance's
+ * initial state must come out with the same bond dimensions (MPS_EINVAL
+ * otherwise).  Device memory: the workspace of one instance times count
+ * (each arena chunk is allocated once for all instances). */
+typedef struct mps_batch mps_batch;
+mps_status mps_batch_init(int32_t count, const mps_problem* problems,
+                          const int32_t* ranks, const double* const* ax,
+                          const double* const* bv, hipStream_t stream,
+                          mps_batch** out);
+/* Replace every instance's state: bond_dims host (n + 1 entries, unit
+ * ends), cores[i] device, packed as mps_set_cores, one array per instance. */
+mps_status mps_batch_set_cores(mps_batch* b, const int32_t* bond_dims,
+                               const double* const* cores, hipStream_t stream);
+/* f_i <- compress(f_i + alpha[i] g_i) for every instance (alpha host,
+ * count values; g_i device cores of one set of bonds). */
+mps_status mps_batch_add_scaled(mps_batch* b, const double* alpha,
+                                const int32_t* bond_dims,
+                                const double* const* cores, hipStream_t stream);
+/* nsteps RK4 steps of every instance, committed for all of them or for
+ * none (a failure names its instance). */
+mps_status mps_batch_step(mps_batch* b, int32_t nsteps, hipStream_t stream);
+/* Instance i as a state handle owned by the batch (NULL if out of range):
+ * mps_to_dense, mps_get_cores, mps_info, mps_moments, mps_entanglement and
+ * mps_device_bytes (the whole batch) apply; mps_step, mps_set_cores,
+ * mps_add_scaled and mps_free refuse it. */
+mps_state* mps_batch_instance(mps_batch* b, int32_t i);
+/* Release the batch and its instance handles.  NULL is accepted. */
+mps_status mps_batch_free(mps_batch* b);
+
 /* Several species sharing x and E (Methods: the two-species Landau and
  * Buneman set-ups).  Each species is an mps_problem of its own (its v grid,
  * q/m, collisions, compression settings); all share Lx, x_min, x_max and a

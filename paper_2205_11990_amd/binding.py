@@ -75,6 +75,12 @@ _SIGS = {
     "mps_plasma_species": [_P, _I32],
     "mps_plasma_field": [_P, _P, _PD, _P],
     "mps_plasma_free": [_P],
+    "mps_batch_init": [_I32, _P, _P, _P, _P, _P, _P],
+    "mps_batch_set_cores": [_P, _PI32, _P, _P],
+    "mps_batch_add_scaled": [_P, _PD, _PI32, _P, _P],
+    "mps_batch_step": [_P, _I32, _P],
+    "mps_batch_instance": [_P, _I32],
+    "mps_batch_free": [_P],
     "mpsb_step_graph": [_P, _I32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
     "mpsb_compress_centre": [_I32, _I32, _PI32, _P, _I32, _D, _PI32, _P, _I64, _PD, _P],
     "mpsb_add_compress": [_I32, _I32, _PD, _PI32, ctypes.POINTER(_P), _I32, _D,
@@ -107,7 +113,8 @@ def lib() -> ctypes.CDLL:
             f = getattr(L, name)
             f.argtypes = args
             f.restype = (ctypes.c_char_p if name == "mps_last_error" else
-                         ctypes.c_void_p if name == "mps_plasma_species" else ctypes.c_int)
+                         ctypes.c_void_p if name in ("mps_plasma_species", "mps_batch_instance")
+                         else ctypes.c_int)
         _lib = L
     return _lib
 
@@ -293,6 +300,80 @@ class MpsState:
             return
         if getattr(self, "_h", None) is not None and self._h.value:
             _check(lib().mps_free(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Lock-step instances of one problem shape (mps_batch_*): problems and
+    (ax, bv) profiles per instance; each launch of a step covers them all."""
+
+    def __init__(self, problems, profiles, stream=None):
+        L = lib()
+        n = len(problems)
+        self.problems = list(problems)
+        arr = (CProblem * n)(*[make_problem(p) for p in problems])
+        self._dev = [(_dev(np.atleast_2d(a)), _dev(np.atleast_2d(b))) for a, b in profiles]
+        ranks = (ctypes.c_int32 * n)(*[int(a.shape[0]) for a, _ in self._dev])
+        axp = (ctypes.c_void_p * n)(*[a.data_ptr() for a, _ in self._dev])
+        bvp = (ctypes.c_void_p * n)(*[b.data_ptr() for _, b in self._dev])
+        h = ctypes.c_void_p()
+        _check(L.mps_batch_init(n, ctypes.cast(arr, _P), ctypes.cast(ranks, _P),
+                                ctypes.cast(axp, _P), ctypes.cast(bvp, _P),
+                                _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self.count = n
+
+    def step(self, nsteps: int = 1, stream=None):
+        _check(lib().mps_batch_step(self._h, int(nsteps), _stream(stream)))
+
+    def _packed(self, cores_list):
+        bonds, devs = None, []
+        for cores in cores_list:
+            b, flat = pack_cores(cores)
+            if bonds is None:
+                bonds = b
+            assert np.array_equal(b, bonds), "instances need one set of bonds"
+            devs.append(_dev(flat))
+        ptrs = (ctypes.c_void_p * len(devs))(*[d.data_ptr() for d in devs])
+        return bonds, devs, ptrs
+
+    def set_cores(self, cores_list, stream=None):
+        """Every instance's cores (host lists of (l, 2, r) arrays, one set of
+        bonds)."""
+        b, keep, ptrs = self._packed(cores_list)
+        _check(lib().mps_batch_set_cores(self._h, b.ctypes.data_as(_PI32),
+                                         ctypes.cast(ptrs, _P), _stream(stream)))
+
+    def add_scaled(self, alphas, cores_list, stream=None):
+        b, keep, ptrs = self._packed(cores_list)
+        al = (ctypes.c_double * len(alphas))(*[float(a) for a in alphas])
+        _check(lib().mps_batch_add_scaled(self._h, al, b.ctypes.data_as(_PI32),
+                                          ctypes.cast(ptrs, _P), _stream(stream)))
+
+    def instance(self, i: int) -> "MpsState":
+        """Instance i as a state owned by the batch (read-only: dense
+        values, cores, moments, info)."""
+        hp = lib().mps_batch_instance(self._h, int(i))
+        if not hp:
+            raise MpsError(MPS_EINVAL, "no instance %d" % i)
+        st = MpsState.__new__(MpsState)
+        p = self.problems[i]
+        st.problem = p
+        st.Nx, st.Nv = 2 ** int(p.Lx), 2 ** int(p.Lv)
+        st._cp = make_problem(p)
+        st._h = ctypes.c_void_p(hp)
+        st._borrowed = True
+        return st
+
+    def free(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(lib().mps_batch_free(self._h))
             self._h = ctypes.c_void_p()
 
     def __del__(self):

@@ -1,7 +1,14 @@
 // Device memory arena: stack-like sub-allocation out of large hipMalloc'd
 // chunks that are kept for the lifetime of the owning state, so that steady
 // state time stepping performs no device allocation at all.
+//
+// For lock-step instances (see Lanes) each chunk is allocated once for all
+// of them, chunk_bytes per instance: instance i's copy of any buffer lies
+// i * chunk_bytes after instance 0's, the same stride in every arena that
+// shares the chunk size.  A request larger than one chunk would break that
+// stride and is refused then.
 #pragma once
+#include <cstdint>
 #include <vector>
 
 #include "common.hpp"
@@ -14,7 +21,8 @@ class Arena {
     size_t chunk, off;
   };
 
-  explicit Arena(size_t chunk_bytes = (size_t)256 << 20) : chunk_(chunk_bytes) {}
+  explicit Arena(size_t chunk_bytes = (size_t)256 << 20, int instances = 1)
+      : chunk_(chunk_bytes), inst_(instances < 1 ? 1 : instances) {}
   ~Arena() { release_all(); }
   Arena(const Arena&) = delete;
   Arena& operator=(const Arena&) = delete;
@@ -36,13 +44,17 @@ class Arena {
       ++cur_;
       off_ = 0;
     }
+    if (inst_ > 1 && bytes > chunk_)
+      throw Error(kEnomem, "device arena: a request of " + std::to_string(bytes) +
+                               " bytes exceeds the per-instance chunk of " +
+                               std::to_string(chunk_) + " bytes");
     size_t sz = bytes > chunk_ ? bytes : chunk_;
     void* p = nullptr;
-    hipError_t e = hipMalloc(&p, sz);
+    hipError_t e = hipMalloc(&p, sz * (size_t)inst_);
     if (e != hipSuccess || p == nullptr) {
       (void)hipGetLastError();
-      throw Error(kEnomem, "device arena: hipMalloc of " + std::to_string(sz) +
-                               " bytes failed");
+      throw Error(kEnomem, "device arena: hipMalloc of " +
+                               std::to_string(sz * (size_t)inst_) + " bytes failed");
     }
     chunks_.push_back({p, sz});
     cur_ = chunks_.size() - 1;
@@ -63,10 +75,25 @@ class Arena {
   // largest extent ever in use: whole chunks before the current one plus
   // the offset into it (chunk tails skipped by a larger request count too)
   size_t peak_bytes() const { return peak_; }
+  // all instances together
   size_t reserved_bytes() const {
     size_t t = 0;
     for (auto& c : chunks_) t += c.size;
-    return t;
+    return t * (size_t)inst_;
+  }
+  // largest single request (one chunk for lock-step instances)
+  size_t max_alloc_bytes() const { return inst_ > 1 ? chunk_ : SIZE_MAX; }
+  int instances() const { return inst_; }
+  // bytes between two instances' copies of a buffer
+  long instance_stride() const { return (long)chunk_; }
+  // whether p points into instance 0's part of a chunk of this arena
+  bool owns(const void* p) const {
+    const char* c = static_cast<const char*>(p);
+    for (auto& k : chunks_) {
+      const char* b = static_cast<const char*>(k.ptr);
+      if (c >= b && c < b + k.size) return true;
+    }
+    return false;
   }
   void release_all() {
     for (auto& c : chunks_) (void)hipFree(c.ptr);
@@ -87,6 +114,7 @@ class Arena {
   }
   std::vector<Chunk> chunks_;
   size_t chunk_;
+  int inst_;
   size_t cur_ = 0, off_ = 0, peak_ = 0;
 };
 

@@ -21,9 +21,20 @@
 #include "prof.hpp"
 
 struct mps_state {
-  std::unique_ptr<mpsv::Engine> eng;
+  std::shared_ptr<mpsv::Engine> eng;
   int device = 0;
   bool in_plasma = false;  // owned by an mps_plasma (mps_free refuses it)
+  bool in_batch = false;   // a view of one instance of an mps_batch
+  int inst = 0;            // its instance index
+};
+
+struct mps_batch {
+  std::shared_ptr<mpsv::Engine> eng;
+  std::vector<mps_state*> views;  // owned, one per instance
+  int device = 0;
+  ~mps_batch() {
+    for (auto* h : views) delete h;
+  }
 };
 
 struct mps_plasma {
@@ -182,6 +193,8 @@ mps_status mps_step(mps_state* h, int32_t nsteps, hipStream_t stream) {
     MPSV_CHECK(nsteps >= 0, mpsv::kEinval, "nsteps must be >= 0");
     MPSV_CHECK(!h->in_plasma, mpsv::kEinval,
                "a species of a plasma is stepped by mps_plasma_step");
+    MPSV_CHECK(!h->in_batch, mpsv::kEinval,
+               "an instance of a batch is stepped by mps_batch_step");
     for (int i = 0; i < nsteps; ++i) h->eng->step(stream);
   });
 }
@@ -190,7 +203,7 @@ mps_status mps_moments(mps_state* h, double* n_out, double* E_out,
                        double* scalars, hipStream_t stream) {
   return guarded([&] {
     check_handle(h);
-    h->eng->moments(n_out, E_out, scalars, stream);
+    h->eng->moments(n_out, E_out, scalars, stream, h->inst);
   });
 }
 
@@ -198,7 +211,7 @@ mps_status mps_to_dense(mps_state* h, double* f_out, hipStream_t stream) {
   return guarded([&] {
     check_handle(h);
     MPSV_CHECK(f_out != nullptr, mpsv::kEinval, "f_out is NULL");
-    h->eng->to_dense(f_out, stream);
+    h->eng->to_dense(f_out, stream, h->inst);
     MPSV_HIP(hipStreamSynchronize(stream));
   });
 }
@@ -208,6 +221,8 @@ mps_status mps_free(mps_state* h) {
     if (!h) return;
     MPSV_CHECK(!h->in_plasma, mpsv::kEinval,
                "a species of a plasma is released by mps_plasma_free");
+    MPSV_CHECK(!h->in_batch, mpsv::kEinval,
+               "an instance of a batch is released by mps_batch_free");
     (void)hipDeviceSynchronize();
     delete h;
   });
@@ -224,7 +239,7 @@ mps_status mps_info(const mps_state* h, int32_t* n_sites, int32_t* bond_dims,
       for (size_t j = 0; j < b.size(); ++j) bond_dims[j] = b[j];
     }
     if (discarded) {
-      const auto& d = e.last_discarded();
+      const auto d = e.last_discarded(h->inst);
       for (int j = 0; j < e.n() - 1; ++j)
         discarded[j] = j < (int)d.size() ? d[j] : 0.0;
     }
@@ -238,7 +253,7 @@ mps_status mps_get_cores(const mps_state* h, int32_t* bond_dims,
   return guarded([&] {
     check_handle(h);
     std::vector<int> b;
-    h->eng->get_state(b, cores, stream);
+    h->eng->get_state(b, cores, stream, h->inst);
     long tot = 0;
     for (size_t j = 0; j + 1 < b.size(); ++j) tot += (long)b[j] * 2 * b[j + 1];
     if (bond_dims)
@@ -253,6 +268,8 @@ mps_status mps_set_cores(mps_state* h, const int32_t* bond_dims,
   return guarded([&] {
     check_handle(h);
     MPSV_CHECK(bond_dims && cores, mpsv::kEinval, "NULL argument");
+    MPSV_CHECK(!h->in_batch, mpsv::kEinval,
+               "the instances of a batch take their cores by mps_batch_set_cores");
     std::vector<int> b(bond_dims, bond_dims + h->eng->n() + 1);
     h->eng->set_state(b, cores, stream);
   });
@@ -264,6 +281,8 @@ mps_status mps_add_scaled(mps_state* h, double alpha, const int32_t* bond_dims,
     check_handle(h);
     MPSV_CHECK(bond_dims && cores, mpsv::kEinval, "NULL argument");
     MPSV_CHECK(std::isfinite(alpha), mpsv::kEinval, "alpha must be finite");
+    MPSV_CHECK(!h->in_batch, mpsv::kEinval,
+               "the instances of a batch are perturbed by mps_batch_add_scaled");
     std::vector<int> b(bond_dims, bond_dims + h->eng->n() + 1);
     h->eng->add_scaled(alpha, b, cores, stream);
   });
@@ -282,7 +301,7 @@ mps_status mps_entanglement(mps_state* h, double* ee, hipStream_t stream) {
   return guarded([&] {
     check_handle(h);
     MPSV_CHECK(ee != nullptr, mpsv::kEinval, "ee is NULL");
-    auto v = h->eng->entanglement(stream);
+    auto v = h->eng->entanglement(stream, h->inst);
     for (size_t j = 0; j < v.size(); ++j) ee[j] = v[j];
   });
 }
@@ -312,6 +331,8 @@ mps_status mps_step_batched(mps_state* const* hs, int32_t count, int32_t nsteps,
       check_handle(hs[i]);
       MPSV_CHECK(!hs[i]->in_plasma, mpsv::kEinval,
                  "a species of a plasma is stepped by mps_plasma_step");
+      MPSV_CHECK(!hs[i]->in_batch, mpsv::kEinval,
+                 "an instance of a batch is stepped by mps_batch_step");
     }
     {
       std::vector<const mps_state*> v(hs, hs + count);
@@ -389,9 +410,10 @@ mps_status mpsb_gemm_prec(int32_t M, int32_t N, int32_t K, double alpha,
     MPSV_CHECK(precision == MPS_PREC_FP64 || precision == MPS_PREC_FP32_CONTRACT ||
                    precision == MPS_PREC_BF16_CONTRACT,
                mpsv::kEinval, "unknown precision");
+    std::lock_guard<std::mutex> lk(g_blocks_mu);
     mpsv::gemm(stream, M, N, K, alpha, mpsv::CMatView{A, lda, 1, 0},
                mpsv::CMatView{B, ldb, 1, 0}, beta, mpsv::MatView{C, ldc, 1, 0},
-               1, (int)precision);
+               1, (int)precision, &blocks().scratch());
     MPSV_HIP(hipStreamSynchronize(stream));
   });
 }
@@ -484,6 +506,8 @@ mps_status mpsb_step_graph(mps_state* h, int32_t enable, int64_t* captures,
                            int64_t* replays) {
   return guarded([&] {
     check_handle(h);
+    MPSV_CHECK(!h->in_plasma && !h->in_batch, mpsv::kEinval,
+               "step graphs belong to stand-alone states");
     if (enable >= 0) h->eng->set_step_graph(enable != 0);
     if (captures) *captures = h->eng->graph_captures();
     if (replays) *replays = h->eng->graph_replays();
@@ -539,7 +563,7 @@ mps_status mpsb_density_field(mps_state* h, double* n_out, double* E_out,
                               hipStream_t stream) {
   return guarded([&] {
     check_handle(h);
-    h->eng->density_field(n_out, E_out, stream);
+    h->eng->density_field(n_out, E_out, stream, h->inst);
   });
 }
 
@@ -607,6 +631,101 @@ mps_status mpsb_profile_read(int32_t cls, int64_t* launches, double* ms,
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------- batches
+
+mps_status mps_batch_init(int32_t count, const mps_problem* problems,
+                          const int32_t* ranks, const double* const* ax,
+                          const double* const* bv, hipStream_t stream,
+                          mps_batch** out) {
+  return guarded([&] {
+    MPSV_CHECK(out != nullptr, mpsv::kEinval, "out is NULL");
+    *out = nullptr;
+    MPSV_CHECK(count >= 1 && count <= 1024, mpsv::kEinval, "count must lie in [1, 1024]");
+    MPSV_CHECK(problems && ranks && ax && bv, mpsv::kEinval, "NULL argument");
+    std::vector<mpsv::Problem> qs;
+    std::vector<int> rk;
+    std::vector<const double*> a, b;
+    for (int i = 0; i < count; ++i) {
+      qs.push_back(convert(&problems[i]));
+      MPSV_CHECK(ax[i] && bv[i], mpsv::kEinval, "profiles must not be NULL");
+      rk.push_back(ranks[i]);
+      a.push_back(ax[i]);
+      b.push_back(bv[i]);
+    }
+    std::unique_ptr<mps_batch> bt(new mps_batch);
+    MPSV_HIP(hipGetDevice(&bt->device));
+    bt->eng = std::make_shared<mpsv::Engine>(qs);
+    bt->eng->init_batch(rk, a, b, stream);
+    for (int i = 0; i < count; ++i) {
+      std::unique_ptr<mps_state> h(new mps_state);
+      h->eng = bt->eng;
+      h->device = bt->device;
+      h->in_batch = true;
+      h->inst = i;
+      bt->views.push_back(h.release());
+    }
+    *out = bt.release();
+  });
+}
+
+namespace {
+mpsv::Engine& batch_engine(mps_batch* b) {
+  MPSV_CHECK(b != nullptr && b->eng, mpsv::kEinval, "batch handle is NULL");
+  int dev = -1;
+  MPSV_HIP(hipGetDevice(&dev));
+  MPSV_CHECK(dev == b->device, mpsv::kEinval,
+             "batch was created on another device than the current one");
+  return *b->eng;
+}
+}  // namespace
+
+mps_status mps_batch_set_cores(mps_batch* b, const int32_t* bond_dims,
+                               const double* const* cores, hipStream_t stream) {
+  return guarded([&] {
+    mpsv::Engine& e = batch_engine(b);
+    MPSV_CHECK(bond_dims && cores, mpsv::kEinval, "NULL argument");
+    std::vector<int> bd(bond_dims, bond_dims + e.n() + 1);
+    std::vector<const double*> c(cores, cores + e.instances());
+    for (auto* p : c) MPSV_CHECK(p != nullptr, mpsv::kEinval, "cores must not be NULL");
+    e.set_states(bd, c, stream);
+  });
+}
+
+mps_status mps_batch_add_scaled(mps_batch* b, const double* alpha,
+                                const int32_t* bond_dims,
+                                const double* const* cores, hipStream_t stream) {
+  return guarded([&] {
+    mpsv::Engine& e = batch_engine(b);
+    MPSV_CHECK(alpha && bond_dims && cores, mpsv::kEinval, "NULL argument");
+    std::vector<int> bd(bond_dims, bond_dims + e.n() + 1);
+    std::vector<const double*> c(cores, cores + e.instances());
+    for (auto* p : c) MPSV_CHECK(p != nullptr, mpsv::kEinval, "cores must not be NULL");
+    std::vector<double> al(alpha, alpha + e.instances());
+    e.add_scaled_all(al, bd, c, stream);
+  });
+}
+
+mps_status mps_batch_step(mps_batch* b, int32_t nsteps, hipStream_t stream) {
+  return guarded([&] {
+    mpsv::Engine& e = batch_engine(b);
+    MPSV_CHECK(nsteps >= 0, mpsv::kEinval, "nsteps must be >= 0");
+    for (int i = 0; i < nsteps; ++i) e.step(stream);
+  });
+}
+
+mps_state* mps_batch_instance(mps_batch* b, int32_t i) {
+  if (!b || i < 0 || i >= (int32_t)b->views.size()) return nullptr;
+  return b->views[(size_t)i];
+}
+
+mps_status mps_batch_free(mps_batch* b) {
+  return guarded([&] {
+    if (!b) return;
+    (void)hipDeviceSynchronize();
+    delete b;
+  });
+}
 
 // ------------------------------------------------------------ plasmas
 

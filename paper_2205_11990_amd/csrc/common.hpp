@@ -51,4 +51,59 @@ struct CMatView {
 inline MatView row_major(double* p, long ld) { return MatView{p, ld, 1, 0}; }
 inline CMatView crow_major(const double* p, long ld) { return CMatView{p, ld, 1, 0}; }
 
+// ---- lock-step instances
+//
+// A batch of instances of one problem shape keeps every device buffer of
+// instance i exactly i * stride bytes after instance 0's copy: each chunk of
+// its arenas is allocated once for all instances, `stride` bytes per
+// instance.  The engine issues each step's launches once, for instance 0's
+// addresses, and every launch covers the instances of the current Lanes:
+// instance z of the launch is instance `first + z`, and a kernel shifts each
+// of its pointer arguments by InstOff::of(blockIdx.z) bytes (the GEMM folds
+// the instance into its batch index).  Outside a batch there is one
+// instance and no shift.
+struct Lanes {
+  int n = 1;         // instances covered by a launch
+  long first = 0;    // bytes: offset of the launch's instance 0
+  long stride = 0;   // bytes between consecutive instances
+};
+// The calling thread's current lanes (one instance, no shift by default).
+Lanes& lanes();
+// Sets the calling thread's lanes for its lifetime, restoring them after.
+class LanesScope {
+ public:
+  explicit LanesScope(const Lanes& l) : saved_(lanes()) { lanes() = l; }
+  ~LanesScope() { lanes() = saved_; }
+  LanesScope(const LanesScope&) = delete;
+  LanesScope& operator=(const LanesScope&) = delete;
+
+ private:
+  Lanes saved_;
+};
+
+// Kernel-side view of the lanes of one launch.
+struct InstOff {
+  long first, stride;
+  __host__ __device__ long of(long z) const { return first + z * stride; }
+};
+inline InstOff inst_off() { return InstOff{lanes().first, lanes().stride}; }
+inline int inst_count() { return lanes().n; }
+
+template <class T>
+__host__ __device__ inline T* shifted(T* p, long off) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(p) + off);
+}
+template <class T>
+__host__ __device__ inline const T* shifted(const T* p, long off) {
+  return reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + off);
+}
+__host__ __device__ inline MatView shifted(MatView v, long off) {
+  v.p = shifted(v.p, off);
+  return v;
+}
+__host__ __device__ inline CMatView shifted(CMatView v, long off) {
+  v.p = shifted(v.p, off);
+  return v;
+}
+
 }  // namespace mpsv

@@ -13,6 +13,7 @@
 #include <climits>
 #include <cmath>
 #include <cstdlib>
+#include <cstdint>
 #include <cstring>
 
 #include "gemm.hpp"
@@ -598,20 +599,18 @@ void validate_problem(const Problem& p) {
              "centre-first compression needs a sequential ordering");
 }
 
-// (the checks run before the size model reads the problem)
-Engine::Engine(const Problem& p)
-    : p_(p), chunk_((validate_problem(p), memory_model(p).chunk)) {
-  MPSV_HIP(hipGetDevice(&device_));
-  MPSV_HIP(hipStreamCreateWithFlags(&own_, hipStreamNonBlocking));
-  MPSV_HIP(hipStreamCreateWithFlags(&side_, hipStreamNonBlocking));
-  MPSV_HIP(hipEventCreateWithFlags(&ev_fork_, hipEventDisableTiming));
-  MPSV_HIP(hipEventCreateWithFlags(&ev_join_, hipEventDisableTiming));
-  MPSV_HIP(hipEventCreateWithFlags(&ev_in_, hipEventDisableTiming));
-  MPSV_HIP(hipEventCreateWithFlags(&ev_out_, hipEventDisableTiming));
+namespace {
 
-  hipStream_t s = nullptr;
-  std::vector<int> bdx, bvv, bt1, bg, bdv;
-  ops::HostMpo T1;
+// The host-built operators of one problem (exact, FP64).
+struct HostOps {
+  ops::HostMpo T1, G, coll, Dv;
+  std::vector<int> bt1, bg, bcoll, bdv;
+  std::vector<std::vector<double>> vpoly, v2poly;
+  std::vector<int> bpoly, bpoly2;
+};
+
+HostOps host_operators(const Problem& p) {
+  HostOps h;
   if (p.x_scheme == 1) {
     // upwind: T1 = -(Db (x) diag(max(v,0)) + Df (x) diag(min(v,0))) f
     std::vector<int> bdb, bdf, bvp, bvn, btp, btn;
@@ -621,21 +620,20 @@ Engine::Engine(const Problem& p)
     auto Vn = ops::velocity_part_diag(p.Lv, p.v_min, p.dv(), false, bvn);
     auto Tp = ops::chain(Db, bdb, Vp, bvp, p.order, btp);
     auto Tn = ops::chain(Df, bdf, Vn, bvn, p.order, btn);
-    T1 = ops::mpo_add(Tp, btp, Tn, btn, bt1);
+    h.T1 = ops::mpo_add(Tp, btp, Tn, btn, h.bt1);
   } else {
+    std::vector<int> bdx, bvv;
     auto Dx = ops::d1_periodic(p.Lx, p.dx(), bdx);
     auto V = ops::poly_diag(p.Lv, p.v_min, p.dv(), 0.0, bvv);
-    T1 = ops::chain(Dx, bdx, V, bvv, p.order, bt1);
+    h.T1 = ops::chain(Dx, bdx, V, bvv, p.order, h.bt1);
   }
-  for (auto& x : T1[0]) x = -x;  // T1 = -(advection) f
-  t1_ = upload_mpo(T1, bt1, ops_, s);
-  auto G = ops::poisson_g(p.Lx, p.dx(), -1.0, bg);  // E = -G n
-  gneg_ = upload_mpo(G, bg, ops_, s);
+  for (auto& x : h.T1[0]) x = -x;  // T1 = -(advection) f
+  h.G = ops::poisson_g(p.Lx, p.dx(), -1.0, h.bg);  // E = -G n
   if (p.nu != 0.0) {
     // Dougherty collisions with the species' fixed drift and thermal speed
     // (Methods, Collision Operator): nu Dv (diag(v - v0) + vth^2 Dv) on the
     // v sites, the identity on the x sites
-    std::vector<int> bd, bpd, bin, bcv, bcc;
+    std::vector<int> bd, bpd, bin, bcv;
     auto D1 = ops::d1_zero_gradient(p.Lv, p.dv(), bd);
     auto Vd = ops::poly_diag(p.Lv, p.v_min - p.nu_v0, p.dv(), 0.0, bpd);
     auto Ds = D1;
@@ -645,42 +643,139 @@ Engine::Engine(const Problem& p)
     for (auto& x : Cv[0]) x *= p.nu;
     ops::HostMpo Ix((size_t)p.Lx, std::vector<double>{1.0, 0.0, 0.0, 1.0});
     std::vector<int> bix((size_t)p.Lx + 1, 1);
-    auto Cc = ops::chain(Ix, bix, Cv, bcv, p.order, bcc);
-    coll_ = upload_mpo(Cc, bcc, ops_, s);
+    h.coll = ops::chain(Ix, bix, Cv, bcv, p.order, h.bcoll);
   }
-  auto Dv = ops::d1_zero_gradient(p.Lv, p.dv(), bdv);
+  h.Dv = ops::d1_zero_gradient(p.Lv, p.dv(), h.bdv);
   if (p.order == 3) {
     // v read fine to coarse (S3): Dv in chain order
     std::vector<int> brev;
-    Dv = ops::reverse(Dv, bdv, 4, brev);
-    bdv = brev;
+    h.Dv = ops::reverse(h.Dv, h.bdv, 4, brev);
+    h.bdv = brev;
   }
-  dv_ = upload_mpo(Dv, bdv, ops_, s);
-
-  // moment weights 1(x) w(v), w = 1, v, v^2/2 as full-chain MPS
-  std::vector<int> b1, bw, bc;
+  // moment weights 1(x) w(v), w = v, v^2/2 as full-chain MPS
+  std::vector<int> b1, bw, bw2;
   auto onesx = ops::poly_mps(p.Lx, 1.0, 0.0, 0.0, b1);
-  auto upload_chain = [&](const ops::HostMpo& Av, const std::vector<int>& bv) {
-    auto C = ops::chain_mps(onesx, b1, Av, bv, p.order, bc);
-    DMps out(C.size());
-    for (size_t j = 0; j < C.size(); ++j) {
+  auto wv = ops::poly_mps(p.Lv, p.v_min, p.dv(), 0.0, bw);
+  h.vpoly = ops::chain_mps(onesx, b1, wv, bw, p.order, h.bpoly);
+  auto wv2 = ops::poly_mps(p.Lv, 0.5 * p.v_min * p.v_min, p.v_min * p.dv(),
+                           0.5 * p.dv() * p.dv(), bw2);
+  h.v2poly = ops::chain_mps(onesx, b1, wv2, bw2, p.order, h.bpoly2);
+  return h;
+}
+
+// Parameter checks of a batch of lock-step instances: one shape, one time
+// step, fixed ranks.
+void validate_batch(const std::vector<Problem>& ps) {
+  MPSV_CHECK(!ps.empty(), kEinval, "a batch needs at least one instance");
+  for (auto& q : ps) validate_problem(q);
+  if (ps.size() == 1) return;
+  const Problem& a = ps[0];
+  for (auto& b : ps) {
+    MPSV_CHECK(b.Lx == a.Lx && b.Lv == a.Lv && b.order == a.order &&
+                   b.chi_max == a.chi_max && b.level == a.level &&
+                   b.df_max == a.df_max && b.precision == a.precision &&
+                   b.x_scheme == a.x_scheme && b.compression == a.compression,
+               kEinval, "lock-step instances must share the problem shape");
+    MPSV_CHECK(b.tol == 0.0 && b.cfl == 0.0 && b.dt == a.dt && b.qm == a.qm,
+               kEinval,
+               "lock-step instances need tol = 0, a fixed and common dt and q/m");
+    MPSV_CHECK((b.nu != 0.0) == (a.nu != 0.0), kEinval,
+               "lock-step instances are all collisional or all collisionless");
+  }
+}
+
+// Arena chunk of a batch: every single request must fit one chunk (the
+// widest MPO x MPS contraction of the field term dominates).
+size_t batch_chunk(const Problem& p, int n) {
+  const MemoryModel m = memory_model(p);
+  if (n == 1) return m.chunk;
+  const int L = p.n();
+  const double chi = p.chi_max;
+  const double df = std::min(p.df_max > 0 ? (double)p.df_max : chi,
+                             std::ldexp(1.0, p.Lx / 2));
+  const bool il = p.order == 1 || p.order == 4;
+  const double w = std::max((il ? 5.0 : 3.0) * df, p.x_scheme == 1 ? 24.0 : 6.0);
+  double big = 0;
+  for (int j = 0; j <= L; ++j) {
+    const double full = std::ldexp(1.0, std::min(j, L - j));
+    const double b = std::min(chi, full);
+    big = std::max(big, std::min(w * b, std::ldexp(1.0, std::min(j, 30))) * w * 2 * b);
+  }
+  size_t c = (size_t)(8.0 * big * 1.25) + ((size_t)1 << 20);
+  c = std::max(c, m.chunk);
+  c = std::max(c, (size_t)64 << 20);
+  return (c + 255) & ~(size_t)255;
+}
+
+}  // namespace
+
+Engine::Engine(const Problem& p) : Engine(std::vector<Problem>{p}) {}
+
+// (the checks run before the size model reads the problem)
+Engine::Engine(const std::vector<Problem>& batch)
+    : p_((validate_batch(batch), batch[0])), ps_(batch), nin_((int)batch.size()),
+      chunk_(batch_chunk(batch[0], (int)batch.size())) {
+  MPSV_HIP(hipGetDevice(&device_));
+  MPSV_HIP(hipStreamCreateWithFlags(&own_, hipStreamNonBlocking));
+  MPSV_HIP(hipStreamCreateWithFlags(&side_, hipStreamNonBlocking));
+  MPSV_HIP(hipEventCreateWithFlags(&ev_fork_, hipEventDisableTiming));
+  MPSV_HIP(hipEventCreateWithFlags(&ev_join_, hipEventDisableTiming));
+  MPSV_HIP(hipEventCreateWithFlags(&ev_in_, hipEventDisableTiming));
+  MPSV_HIP(hipEventCreateWithFlags(&ev_out_, hipEventDisableTiming));
+  LanesScope ls(all_lanes());
+
+  hipStream_t s = nullptr;
+  std::vector<HostOps> h;
+  for (auto& q : ps_) h.push_back(host_operators(q));
+  for (auto& x : h)
+    MPSV_CHECK(x.bt1 == h[0].bt1 && x.bg == h[0].bg && x.bcoll == h[0].bcoll &&
+                   x.bdv == h[0].bdv && x.bpoly == h[0].bpoly &&
+                   x.bpoly2 == h[0].bpoly2,
+               kEinval, "lock-step instances need operators of the same bonds");
+  auto pick = [&](ops::HostMpo HostOps::*m) {
+    std::vector<const ops::HostMpo*> v;
+    for (auto& x : h) v.push_back(&(x.*m));
+    return v;
+  };
+  t1_ = upload_mpo(pick(&HostOps::T1), h[0].bt1, ops_, s);
+  gneg_ = upload_mpo(pick(&HostOps::G), h[0].bg, ops_, s);
+  if (p_.nu != 0.0) coll_ = upload_mpo(pick(&HostOps::coll), h[0].bcoll, ops_, s);
+  dv_ = upload_mpo(pick(&HostOps::Dv), h[0].bdv, ops_, s);
+  auto upload_chain = [&](std::vector<std::vector<double>> HostOps::*m,
+                          const std::vector<int>& bc) {
+    DMps out((h[0].*m).size());
+    for (size_t j = 0; j < out.size(); ++j) {
       out[j].l = bc[j];
       out[j].r = bc[j + 1];
-      out[j].p = ops_.alloc(C[j].size());
-      MPSV_HIP(hipMemcpy(out[j].p, C[j].data(), C[j].size() * sizeof(double),
-                         hipMemcpyHostToDevice));
+      out[j].p = ops_.alloc((h[0].*m)[j].size());
+      for (int i = 0; i < nin_; ++i)
+        MPSV_HIP(hipMemcpy(shifted(out[j].p, (long)i * (long)chunk_),
+                           (h[i].*m)[j].data(), (h[i].*m)[j].size() * sizeof(double),
+                           hipMemcpyHostToDevice));
     }
     return out;
   };
-  auto wv = ops::poly_mps(p.Lv, p.v_min, p.dv(), 0.0, bw);
-  vpoly_ = upload_chain(wv, bw);
-  auto wv2 = ops::poly_mps(p.Lv, 0.5 * p.v_min * p.v_min, p.v_min * p.dv(),
-                           0.5 * p.dv() * p.dv(), bw);
-  v2poly_ = upload_chain(wv2, bw);
+  vpoly_ = upload_chain(&HostOps::vpoly, h[0].bpoly);
+  v2poly_ = upload_chain(&HostOps::v2poly, h[0].bpoly2);
   dflag_ = ops_.alloc_int(4);
   ident_ = ops_.alloc((size_t)kIdent * kIdent);
   identity(s, ident_, kIdent);
+  out_main_.bind(ops_.alloc((size_t)SvdOutcomes::kSlots * SvdOutcomes::kInfoWords));
+  out_side_.bind(ops_.alloc((size_t)SvdOutcomes::kSlots * SvdOutcomes::kInfoWords));
+  disc_.assign((size_t)(n() - 1) * nin_, 0.0);
   MPSV_HIP(hipDeviceSynchronize());
+}
+
+void Engine::check_instance(int i) const {
+  MPSV_CHECK(i >= 0 && i < nin_, kEinval, "instance index out of range");
+}
+
+std::vector<double> Engine::last_discarded(int inst) const {
+  check_instance(inst);
+  std::vector<double> d((size_t)n() - 1, 0.0);
+  const size_t off = (size_t)inst * (size_t)(n() - 1);
+  for (size_t j = 0; j < d.size() && off + j < disc_.size(); ++j) d[j] = disc_[off + j];
+  return d;
 }
 
 Engine::~Engine() {
@@ -703,20 +798,62 @@ thread_local Arena* tl_work = nullptr;
 
 Arena& Engine::work() { return tl_work ? *tl_work : work_; }
 
+namespace {
+// Host <-> device copies of the one instance the calling thread's lanes
+// cover: the device side is shifted to that instance.
+void d2h(hipStream_t s, void* h, const void* d, size_t bytes) {
+  MPSV_CHECK(inst_count() == 1, kEinval, "a read-back covers one instance");
+  MPSV_HIP(hipMemcpyAsync(h, shifted(d, lanes().first), bytes,
+                          hipMemcpyDeviceToHost, s));
+}
+void d2d_out(hipStream_t s, void* dst, const void* src, size_t bytes) {
+  MPSV_CHECK(inst_count() == 1, kEinval, "a copy out covers one instance");
+  MPSV_HIP(hipMemcpyAsync(dst, shifted(src, lanes().first), bytes,
+                          hipMemcpyDeviceToDevice, s));
+}
+void d2d_in(hipStream_t s, void* dst, const void* src, size_t bytes) {
+  MPSV_CHECK(inst_count() == 1, kEinval, "a copy in covers one instance");
+  MPSV_HIP(hipMemcpyAsync(shifted(dst, lanes().first), src, bytes,
+                          hipMemcpyDeviceToDevice, s));
+}
+// A caller's device buffer handed to a kernel under the lanes of one
+// instance: kernels shift every pointer to their instance, so the caller's
+// pointer enters with that shift taken off.
+template <class T>
+T* foreign(T* p) {
+  return reinterpret_cast<T*>(reinterpret_cast<uintptr_t>(p) - (uintptr_t)lanes().first);
+}
+}  // namespace
+
 DMpo Engine::upload_mpo(const std::vector<std::vector<double>>& W,
                         const std::vector<int>& bonds, Arena& ar,
                         hipStream_t s) {
+  LanesScope ls(one_lane(0));
+  return upload_mpo(std::vector<const ops::HostMpo*>{&W}, bonds, ar, s);
+}
+
+// One MPO per instance of the calling thread's lanes (same bonds).
+DMpo Engine::upload_mpo(const std::vector<const ops::HostMpo*>& Ws,
+                        const std::vector<int>& bonds, Arena& ar,
+                        hipStream_t s) {
+  MPSV_CHECK((int)Ws.size() == inst_count(), kEinval,
+             "one MPO per instance expected");
+  const ops::HostMpo& W = *Ws[0];
   DMpo out(W.size());
   for (size_t j = 0; j < W.size(); ++j) {
     MpoSite& m = out[j];
     m.wl = bonds[j];
     m.wr = bonds[j + 1];
-    MPSV_CHECK((long)W[j].size() == (long)m.wl * 4 * m.wr, kEinval,
-               "MPO site size mismatch");
     m.W = ar.alloc(W[j].size());
     m.Wmat = ar.alloc(W[j].size());
-    MPSV_HIP(hipMemcpy(m.W, W[j].data(), W[j].size() * sizeof(double),
-                       hipMemcpyHostToDevice));
+    for (size_t i = 0; i < Ws.size(); ++i) {
+      const auto& Wi = (*Ws[i])[j];
+      MPSV_CHECK((long)Wi.size() == (long)m.wl * 4 * m.wr, kEinval,
+                 "MPO site size mismatch");
+      MPSV_HIP(hipMemcpy(shifted(m.W, lanes().first + (long)i * lanes().stride),
+                         Wi.data(), Wi.size() * sizeof(double),
+                         hipMemcpyHostToDevice));
+    }
     mpo_left_matrix(s, m.W, m.wl, m.wr, m.Wmat);
   }
   return out;
@@ -739,7 +876,8 @@ void Engine::absorb_left(const VSite& v, const double* R, int p, double* M,
   switch (v.kind) {
     case VSite::kDense: {
       gemm(s, p, 2 * v.r, v.l, 1.0, CMatView{R, v.l, 1, 0},
-           CMatView{v.A.p, 2L * v.r, 1, 0}, 0.0, MatView{M, 2L * v.r, 1, 0});
+           CMatView{v.A.p, 2L * v.r, 1, 0}, 0.0, MatView{M, 2L * v.r, 1, 0}, 1, 0,
+           &work());
       break;
     }
     case VSite::kApply: {
@@ -749,7 +887,7 @@ void Engine::absorb_left(const VSite& v, const double* R, int p, double* M,
       // X[(p,b)][(i,a')] = sum_a R[p][(b,a)] A[a][i][a']
       gemm(s, p * wl, 2 * ar, al, 1.0, CMatView{R, al, 1, 0},
            CMatView{v.A.p, 2L * ar, 1, 0}, 0.0, MatView{X, 2L * ar, 1, 0}, 1,
-           contract_prec());
+           contract_prec(), &work());
       // M_p[(o,b')][a'] = sum_(b,i) Wmat[(o,b')][(b,i)] X_p[(b,i)][a']
       gemm(s, 2 * wr, ar, 2 * wl, 1.0, CMatView{v.W.Wmat, 2L * wl, 1, 0},
            CMatView{X, ar, 1, 2L * wl * ar}, 0.0,
@@ -779,8 +917,7 @@ void Engine::absorb_left(const VSite& v, const double* R, int p, double* M,
     }
     case VSite::kCopy: {
       // natural-basis isometry: (p x l) with l = 2 r is already p x 2 x r
-      MPSV_HIP(hipMemcpyAsync(M, R, sizeof(double) * (size_t)p * v.l,
-                              hipMemcpyDeviceToDevice, s));
+      copy_doubles(s, M, R, (long)p * v.l);
       break;
     }
   }
@@ -792,7 +929,7 @@ void Engine::absorb_right(const VSite& v, const double* L, int q, double* N,
   switch (v.kind) {
     case VSite::kDense: {
       gemm(s, 2 * v.l, q, v.r, 1.0, CMatView{v.A.p, v.r, 1, 0},
-           CMatView{L, q, 1, 0}, 0.0, MatView{N, q, 1, 0});
+           CMatView{L, q, 1, 0}, 0.0, MatView{N, q, 1, 0}, 1, 0, &work());
       break;
     }
     case VSite::kApply: {
@@ -936,7 +1073,9 @@ DMps Engine::compress_chain(const std::vector<VSite>& ch_in, int cap, double tol
   // g_r]; the right half H = S V^T ... is compressed by a left-to-right
   // sweep afterwards and S^-1 joins the centre site's left bond.
   DMps res(n);
-  if (disc) disc->assign(n - 1, 0.0);
+  // discarded weights: n - 1 per instance (instance i's at i * (n - 1))
+  const long dstride = n - 1;
+  if (disc) disc->assign((size_t)(n - 1) * inst_count(), 0.0);
   if (sigmas) sigmas->assign(n - 1, {});
   double* sig_c = nullptr;  // centre singular values (device, descending)
   int m = p, Dr = 1;
@@ -984,15 +1123,16 @@ DMps Engine::compress_chain(const std::vector<VSite>& ch_in, int cap, double tol
         }
         qr_apply_q_view(s, work(), lq, I, m, MatView{Vt, 1, c, 0}, m);
       }
-      if (dsc) *dsc = 0.0;
+      if (dsc)
+        for (int i = 0; i < inst_count(); ++i) dsc[i * dstride] = 0.0;
     } else {
-      D = svd_truncate(s, work(), X, m, c, c, capj, tolj, Vt, US, sg, dsc);
+      D = svd_truncate(s, work(), X, m, c, c, capj, tolj, Vt, US, sg, dsc,
+                       outcomes(s), dstride);
     }
     if (sigmas) {
       auto& h = (*sigmas)[j - 1];
       h.resize((size_t)std::min(m, c));
-      MPSV_HIP(hipMemcpyAsync(h.data(), sg, h.size() * sizeof(double),
-                              hipMemcpyDeviceToHost, s));
+      d2h(s, h.data(), sg, h.size() * sizeof(double));
       MPSV_HIP(hipStreamSynchronize(s));
     }
     res[j] = Core{Vt, D, Dr};
@@ -1011,8 +1151,7 @@ DMps Engine::compress_chain(const std::vector<VSite>& ch_in, int cap, double tol
   }
   // first core: X is 2 x Dr
   Core c0{out.alloc((size_t)2 * Dr), 1, Dr};
-  MPSV_HIP(hipMemcpyAsync(c0.p, X, sizeof(double) * 2 * Dr,
-                          hipMemcpyDeviceToDevice, s));
+  copy_doubles(s, c0.p, X, 2L * Dr);
   res[0] = c0;
   if (centre > 0)
     compress_right_half(res, centre, sig_c, cap, tol, out, s, disc);
@@ -1054,7 +1193,8 @@ void Engine::compress_right_half(DMps& res, int centre, const double* sc,
     double* Vt = work().alloc((size_t)Dmax * rows);
     double* US = work().alloc((size_t)r * Dmax);
     const int D = svd_truncate(s, work(), Xt, r, rows, rows, cap, tol, Vt, US,
-                               nullptr, disc ? &(*disc)[j] : nullptr);
+                               nullptr, disc ? &(*disc)[j] : nullptr,
+                               outcomes(s), n - 1);
     // core j = Vt^T: (rows x D), row 2 i + t
     Core A{out.alloc((size_t)rows * D), l, D};
     copy_view(s, CMatView{Vt, 1, rows, 0}, rows, MatView{A.p, D, 1, 0}, rows, D);
@@ -1070,8 +1210,7 @@ void Engine::compress_right_half(DMps& res, int centre, const double* sc,
     gemm(s, l, 2, cur.l, 1.0, Cv, CMatView{cur.p, 2, 1, 0}, 0.0,
          MatView{last.p, 2, 1, 0});
   } else {
-    MPSV_HIP(hipMemcpyAsync(last.p, cur.p, sizeof(double) * 2 * l,
-                            hipMemcpyDeviceToDevice, s));
+    copy_doubles(s, last.p, cur.p, 2L * l);
   }
   res[n - 1] = last;
   // S^-1 into the centre core's left bond
@@ -1155,8 +1294,7 @@ DMps Engine::copy_mps(const DMps& a, Arena& ar, hipStream_t s) {
   for (size_t j = 0; j < a.size(); ++j) {
     out[j] = a[j];
     out[j].p = ar.alloc(a[j].size());
-    MPSV_HIP(hipMemcpyAsync(out[j].p, a[j].p, a[j].size() * sizeof(double),
-                            hipMemcpyDeviceToDevice, s));
+    copy_doubles(s, out[j].p, a[j].p, a[j].size());
   }
   return out;
 }
@@ -1201,8 +1339,7 @@ DMps Engine::density(const DMps& g, Arena& ar, hipStream_t s) {
         pend = nullptr;
       } else {
         double* Y = ar.alloc(A.size());
-        MPSV_HIP(hipMemcpyAsync(Y, A.p, A.size() * sizeof(double),
-                                hipMemcpyDeviceToDevice, s));
+        copy_doubles(s, Y, A.p, A.size());
         C.p = Y;
       }
       xs.push_back(C);
@@ -1279,8 +1416,10 @@ DMps Engine::rhs(const DMps& g, Arena& out, hipStream_t s, const DMps* Eext) {
   MPSV_HIP(hipStreamWaitEvent(side_, ev_fork_, 0));
   DMps T1, T3;
   std::exception_ptr side_err;
-  std::thread side([&] {
-    (void)hipSetDevice(device_);
+  const Lanes lanes_here = lanes();
+  auto side_lane = [&] {
+    LanesScope ls(lanes_here);
+    Arena* saved = tl_work;
     tl_work = &work2_;
     try {
       T1 = apply_compress(t1_, g, cap_for(5), p_.tol, tmp2_, side_);
@@ -1290,8 +1429,23 @@ DMps Engine::rhs(const DMps& g, Arena& out, hipStream_t s, const DMps* Eext) {
     } catch (...) {
       side_err = std::current_exception();
     }
-    tl_work = nullptr;
-  });
+    tl_work = saved;
+  };
+  // While a step graph is recorded, one host thread issues both lanes (the
+  // side lane first): the recording gains nothing from a second thread,
+  // and two threads must not add nodes to one capture at once.
+  std::thread side;
+  if (capturing_) {
+    side_lane();
+  } else {
+    side = std::thread([&] {
+      (void)hipSetDevice(device_);
+      side_lane();
+    });
+  }
+  auto join_side = [&] {
+    if (side.joinable()) side.join();
+  };
   DMps T2;
   try {
     DMps E;
@@ -1299,13 +1453,13 @@ DMps Engine::rhs(const DMps& g, Arena& out, hipStream_t s, const DMps* Eext) {
     DMpo W2 = t2_mpo(Eext ? *Eext : E, tmp_, s);
     T2 = apply_compress(W2, g, cap_for(5), p_.tol, tmp_, s);
   } catch (...) {
-    side.join();
-    (void)hipStreamSynchronize(side_);
+    join_side();
+    if (!capturing_) (void)hipStreamSynchronize(side_);
     throw;
   }
-  side.join();
+  join_side();
   if (side_err) {
-    (void)hipStreamSynchronize(side_);
+    if (!capturing_) (void)hipStreamSynchronize(side_);
     std::rethrow_exception(side_err);
   }
   MPSV_HIP(hipStreamWaitEvent(s, ev_join_, 0));
@@ -1322,10 +1476,17 @@ void Engine::commit(const DMps& fn, hipStream_t s) {
 void Engine::check_finite(const DMps& fn, hipStream_t s) {
   fill_int(s, dflag_, 1, 0);
   for (auto& c : fn) count_nonfinite(s, c.p, c.size(), dflag_);
-  int bad = 0;
-  MPSV_HIP(hipMemcpyAsync(&bad, dflag_, sizeof(int), hipMemcpyDeviceToHost, s));
+  // one flag per instance of the lanes
+  const int ni = inst_count();
+  std::vector<int> bad((size_t)ni, 0);
+  for (int i = 0; i < ni; ++i)
+    MPSV_HIP(hipMemcpyAsync(&bad[i], shifted(dflag_, lanes().first + (long)i * lanes().stride),
+                            sizeof(int), hipMemcpyDeviceToHost, s));
   MPSV_HIP(hipStreamSynchronize(s));
-  if (bad) throw Error(kEnumeric, "non-finite values in the new state");
+  for (int i = 0; i < ni; ++i)
+    if (bad[i])
+      throw Error(kEnumeric, (ni > 1 ? "instance " + std::to_string(i) + ": " : std::string()) +
+                                 "non-finite values in the new state");
 }
 
 void Engine::install(const DMps& fn, hipStream_t s) {
@@ -1394,8 +1555,11 @@ void step_species(const std::vector<Engine*>& es, const std::vector<double>& q,
   Engine& e0 = *es[0];
   const double h = e0.p_.dt;
   for (auto* e : es) e->step_.reset();
-  svd_defer_begin(s);
-  for (auto* e : es) svd_defer_begin(e->side_);
+  for (auto* e : es) {
+    MPSV_CHECK(e->nin_ == 1, kEinval, "species are single instances");
+    e->out_main_.begin();
+    e->out_side_.begin();
+  }
   std::vector<DMps> fn(S);
   try {
     auto R = [&](const std::vector<const DMps*>& gs) {
@@ -1432,11 +1596,11 @@ void step_species(const std::vector<Engine*>& es, const std::vector<double>& q,
       fn[i] = e.add_terms({{1.0, &e.f_}, {h / 6.0, &Sk}}, cap_or_inf(e.p_.chi_max),
                           e.step_, s);
     }
-    for (auto* e : es) svd_defer_end(e->side_);
-    svd_defer_end(s);
+    for (auto* e : es) e->out_side_.end(e->side_);
+    for (auto* e : es) e->out_main_.end(s);
   } catch (...) {
-    for (auto* e : es) svd_defer_cancel(e->side_);
-    svd_defer_cancel(s);
+    for (auto* e : es) e->out_side_.cancel(e->side_);
+    for (auto* e : es) e->out_main_.cancel(s);
     throw;
   }
   for (size_t i = 0; i < S; ++i) es[i]->check_finite(fn[i], s);
@@ -1460,13 +1624,15 @@ void field_species_dense(const std::vector<Engine*>& es, const std::vector<doubl
   if (energy) {
     double* w = e0.tmp_.alloc(1);
     sum_squares(s, Ed, nx, 0.5 * e0.p_.dx(), w);
-    MPSV_HIP(hipMemcpyAsync(energy, w, sizeof(double), hipMemcpyDeviceToHost, s));
+    d2h(s, energy, w, sizeof(double));
   }
   MPSV_HIP(hipStreamSynchronize(s));
 }
 
-std::vector<double> Engine::entanglement(hipStream_t s) {
+std::vector<double> Engine::entanglement(hipStream_t s, int inst) {
   MPSV_CHECK(!f_.empty(), kEinval, "state not initialised");
+  check_instance(inst);
+  LanesScope ls(one_lane(inst));
   ArenaScope sc(tmp_);
   std::vector<VSite> ch(f_.size());
   for (size_t j = 0; j < f_.size(); ++j) {
@@ -1494,6 +1660,7 @@ std::vector<double> Engine::entanglement(hipStream_t s) {
 
 double Engine::step_size(hipStream_t s) {
   if (p_.cfl <= 0) return p_.dt;
+  LanesScope ls(one_lane(0));  // adaptive steps: one instance (checked at creation)
   // eq. CFL for one collisionless species, |E|_max of the current state
   ArenaScope sc(step_);
   DMps E = field(f_, step_, s);
@@ -1501,8 +1668,7 @@ double Engine::step_size(hipStream_t s) {
   double* Ed = step_.alloc((size_t)nx);
   dense_of(E, Ed, s);
   std::vector<double> h((size_t)nx);
-  MPSV_HIP(hipMemcpyAsync(h.data(), Ed, (size_t)nx * sizeof(double),
-                          hipMemcpyDeviceToHost, s));
+  d2h(s, h.data(), Ed, (size_t)nx * sizeof(double));
   MPSV_HIP(hipStreamSynchronize(s));
   double emax = 0.0;
   for (double e : h) emax = std::max(emax, std::fabs(e));
@@ -1519,6 +1685,8 @@ void Engine::step(hipStream_t s) {
   step_.reset();
   const double h = step_size(s);
   step_.reset();
+  // every instance of a batch in lock-step: each launch covers them all
+  LanesScope ls(all_lanes());
   if (!graph_eligible()) {
     step_eager(h, s);
   } else {
@@ -1567,15 +1735,15 @@ void Engine::step_eager(double h, hipStream_t s) {
   // Fixed-rank factorisations (tol = 0) report their outcome at the end of
   // the step instead of one host round trip each; a failure still fails
   // the step before anything is committed.
-  svd_defer_begin(s);
-  svd_defer_begin(side_);
+  out_main_.begin();
+  out_side_.begin();
   try {
     step_stages(h, s);
-    svd_defer_end(side_);
-    svd_defer_end(s);
+    out_side_.end(side_);
+    out_main_.end(s);
   } catch (...) {
-    svd_defer_cancel(side_);
-    svd_defer_cancel(s);
+    out_side_.cancel(side_);
+    out_main_.cancel(s);
     throw;
   }
   commit(staged_, s);
@@ -1592,22 +1760,25 @@ void Engine::step_capture(double h, hipStream_t s) {
     (void)hipGraphExecDestroy(gexec_);
     gexec_ = nullptr;
   }
-  svd_defer_begin(s);
-  svd_defer_begin(side_);
+  out_main_.begin();
+  out_side_.begin();
   hipGraph_t g = nullptr;
   MPSV_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+  capturing_ = true;
   try {
     step_stages(h, s);
   } catch (...) {
+    capturing_ = false;
     (void)hipStreamEndCapture(s, &g);
     if (g) (void)hipGraphDestroy(g);
-    (void)svd_defer_take(side_);
-    (void)svd_defer_take(s);
+    (void)out_side_.take();
+    (void)out_main_.take();
     throw;
   }
+  capturing_ = false;
   MPSV_HIP(hipStreamEndCapture(s, &g));
-  rec_own_ = svd_defer_take(s);
-  rec_side_ = svd_defer_take(side_);
+  rec_own_ = out_main_.take();
+  rec_side_ = out_side_.take();
   const hipError_t e = hipGraphInstantiate(&gexec_, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (e != hipSuccess) {
@@ -1621,15 +1792,15 @@ void Engine::step_capture(double h, hipStream_t s) {
 }
 
 void Engine::step_replay(hipStream_t s) {
-  svd_defer_resume(s, rec_own_);
-  svd_defer_resume(side_, rec_side_);
+  out_main_.resume(rec_own_);
+  out_side_.resume(rec_side_);
   try {
     MPSV_HIP(hipGraphLaunch(gexec_, s));
-    svd_defer_end(s);  // the whole graph, both lanes, has run
-    svd_defer_end(side_);
+    out_main_.end(s);  // the whole graph, both lanes, has run
+    out_side_.end(side_);
   } catch (...) {
-    svd_defer_cancel(s);
-    svd_defer_cancel(side_);
+    out_main_.cancel(s);
+    out_side_.cancel(side_);
     throw;
   }
   commit(graph_out_, s);
@@ -1652,43 +1823,52 @@ void Engine::step_stages(double h, hipStream_t s) {
 
 // ---------------------------------------------------------------- state io
 
-void Engine::init_from_profiles(int rank, const double* ax, const double* bv,
-                                hipStream_t s) {
+// f0 = sum_r ax[r] (x) bv[r] as an MPS in the step arena (one instance):
+// each 1-D profile by iterated SVD (eq. 4), then the separable terms
+// merged in chain order and compressed to (chi, tol).
+DMps Engine::initial_state(int rank, const double* ax, const double* bv,
+                           hipStream_t s) {
   MPSV_CHECK(rank >= 1, kEinval, "profile rank must be >= 1");
+  MPSV_CHECK(inst_count() == 1, kEinval, "one instance at a time");
+  // the caller's profiles enter the instance's workspace first (the
+  // kernels below address instance-local buffers only)
+  const long nx = (long)rank * p_.Nx(), nv = (long)rank * p_.Nv();
+  double* axl = step_.alloc((size_t)nx);
+  double* bvl = step_.alloc((size_t)nv);
+  d2d_in(s, axl, ax, (size_t)nx * sizeof(double));
+  d2d_in(s, bvl, bv, (size_t)nv * sizeof(double));
   // non-finite profiles are rejected
   fill_int(s, dflag_, 1, 0);
-  count_nonfinite(s, ax, (long)rank * p_.Nx(), dflag_);
-  count_nonfinite(s, bv, (long)rank * p_.Nv(), dflag_);
+  count_nonfinite(s, axl, nx, dflag_);
+  count_nonfinite(s, bvl, nv, dflag_);
   int bad = 0;
-  MPSV_HIP(hipMemcpyAsync(&bad, dflag_, sizeof(int), hipMemcpyDeviceToHost, s));
+  d2h(s, &bad, dflag_, sizeof(int));
   MPSV_HIP(hipStreamSynchronize(s));
   MPSV_CHECK(bad == 0, kEinval, "non-finite values in the initial profiles");
 
-  step_.reset();
   // 1-D vector -> MPS by iterated SVD (eq. 4), run from the right end:
-  // X = u as 2^(L-1) x 2, SVD, keep V^T as the last core, carry U S.
+  // X = u as 2^(L-1) x 2, SVD, keep V^T as the last core, carry U S.  The
+  // relative floor 1e-14 drops only numerically zero directions (a smooth
+  // profile keeps a handful), whatever the problem's tolerance.
   auto tt = [&](const double* u, int L) {
     DMps m(L);
     double* X = work().alloc((size_t)1 << L);
-    MPSV_HIP(hipMemcpyAsync(X, u, sizeof(double) * ((size_t)1 << L),
-                            hipMemcpyDeviceToDevice, s));
+    copy_doubles(s, X, u, 1L << L);
     int rows = 1 << (L - 1), Dr = 1;
     for (int j = L - 1; j >= 1; --j) {
       const int c = 2 * Dr;
       const int Dmax = std::min(rows, c);
       double* Vt = step_.alloc((size_t)Dmax * c);
       double* US = work().alloc((size_t)rows * Dmax);
-      const int D = svd_truncate(s, work(), X, rows, c, c, INT_MAX,
-                                 std::min(p_.tol, 1e-14) , Vt, US, nullptr,
-                                 nullptr);
+      const int D = svd_truncate(s, work(), X, rows, c, c, INT_MAX, 1e-14, Vt, US,
+                                 nullptr, nullptr);
       m[j] = Core{Vt, D, Dr};
       X = US;
       rows /= 2;
       Dr = D;
     }
     Core c0{step_.alloc((size_t)2 * Dr), 1, Dr};
-    MPSV_HIP(hipMemcpyAsync(c0.p, X, sizeof(double) * 2 * Dr,
-                            hipMemcpyDeviceToDevice, s));
+    copy_doubles(s, c0.p, X, 2L * Dr);
     m[0] = c0;
     return m;
   };
@@ -1696,8 +1876,8 @@ void Engine::init_from_profiles(int rank, const double* ax, const double* bv,
   {
     ArenaScope sc(work());
     for (int r = 0; r < rank; ++r) {
-      DMps mx = tt(ax + (long)r * p_.Nx(), p_.Lx);
-      DMps mv = tt(bv + (long)r * p_.Nv(), p_.Lv);
+      DMps mx = tt(axl + (long)r * p_.Nx(), p_.Lx);
+      DMps mv = tt(bvl + (long)r * p_.Nv(), p_.Lv);
       DMps full;
       if (p_.order != 1 && p_.order != 4) {
         // sequential: a dimension read fine to coarse enters reversed
@@ -1726,61 +1906,183 @@ void Engine::init_from_profiles(int rank, const double* ax, const double* bv,
   }
   std::vector<std::pair<double, const DMps*>> tl;
   for (auto& t : terms) tl.push_back({1.0, &t});
-  DMps f0;
-  if (rank == 1) {
-    f0 = compress_mps(terms[0], cap_or_inf(p_.chi_max), p_.tol, step_, s);
-  } else {
-    f0 = add_terms(tl, cap_or_inf(p_.chi_max), step_, s);
-  }
+  if (rank == 1) return compress_mps(terms[0], cap_or_inf(p_.chi_max), p_.tol, step_, s);
+  return add_terms(tl, cap_or_inf(p_.chi_max), step_, s);
+}
+
+void Engine::init_from_profiles(int rank, const double* ax, const double* bv,
+                                hipStream_t s, int inst) {
+  check_instance(inst);
+  MPSV_CHECK(nin_ == 1, kEinval, "a batch is initialised by init_batch");
+  LanesScope ls(one_lane(0));
+  step_.reset();
+  DMps f0 = initial_state(rank, ax, bv, s);
   commit(f0, s);
   t_ = 0.0;
   steps_ = 0;
 }
 
-void Engine::set_state(const std::vector<int>& bonds, const double* packed,
-                       hipStream_t s) {
-  MPSV_CHECK((int)bonds.size() == n() + 1 && bonds[0] == 1 && bonds[n()] == 1,
-             kEinval, "bond dimensions must have n+1 entries with unit ends");
+// Every instance's own initial state, then all of them committed at once:
+// they must come out with the same bond dimensions (profiles of the same
+// kind; with tol = 0 only numerically zero directions are dropped).
+void Engine::init_batch(const std::vector<int>& ranks,
+                        const std::vector<const double*>& ax,
+                        const std::vector<const double*>& bv, hipStream_t s) {
+  MPSV_CHECK((int)ranks.size() == nin_ && (int)ax.size() == nin_ &&
+                 (int)bv.size() == nin_,
+             kEinval, "one profile pair per instance expected");
+  std::vector<int> b0;
+  std::vector<std::vector<double>> host((size_t)nin_);
+  for (int i = 0; i < nin_; ++i) {
+    LanesScope ls(one_lane(i));
+    step_.reset();
+    DMps f0 = initial_state(ranks[i], ax[i], bv[i], s);
+    std::vector<int> b(f0.size() + 1, 1);
+    long tot = 0;
+    for (size_t j = 0; j < f0.size(); ++j) {
+      b[j + 1] = f0[j].r;
+      tot += f0[j].size();
+    }
+    b[0] = f0[0].l;
+    if (i == 0) b0 = b;
+    MPSV_CHECK(b == b0, kEinval,
+               "instance " + std::to_string(i) +
+                   ": its initial state has other bond dimensions than instance 0's");
+    host[i].resize((size_t)tot);
+    long off = 0;
+    for (auto& c : f0) {
+      d2h(s, host[i].data() + off, c.p, c.size() * sizeof(double));
+      off += c.size();
+    }
+    MPSV_HIP(hipStreamSynchronize(s));
+  }
+  set_states_host(b0, host, s);
+  t_ = 0.0;
+  steps_ = 0;
+}
+
+// Cores of every instance (same bonds; host arrays, packed core by core)
+// staged in the step arena at common addresses, then committed together.
+void Engine::set_states_host(const std::vector<int>& bonds,
+                             const std::vector<std::vector<double>>& packed,
+                             hipStream_t s) {
+  LanesScope ls(all_lanes());
+  step_.reset();
   DMps a(n());
-  long off = 0;
   for (int j = 0; j < n(); ++j) {
+    a[j] = Core{nullptr, bonds[j], bonds[j + 1]};
+    a[j].p = step_.alloc(a[j].size());
+  }
+  for (int i = 0; i < nin_; ++i) {
+    long off = 0;
+    for (auto& c : a) {
+      MPSV_HIP(hipMemcpyAsync(shifted(c.p, (long)i * (long)chunk_), packed[i].data() + off,
+                              c.size() * sizeof(double), hipMemcpyHostToDevice, s));
+      off += c.size();
+    }
+  }
+  commit(a, s);
+}
+
+static std::vector<Core> view_packed(const std::vector<int>& bonds, const double* packed,
+                                     int n) {
+  MPSV_CHECK((int)bonds.size() == n + 1 && bonds[0] == 1 && bonds[n] == 1, kEinval,
+             "bond dimensions must have n+1 entries with unit ends");
+  std::vector<Core> a((size_t)n);
+  long off = 0;
+  for (int j = 0; j < n; ++j) {
     MPSV_CHECK(bonds[j + 1] >= 1, kEinval, "bond dimension must be >= 1");
     a[j] = Core{const_cast<double*>(packed) + off, bonds[j], bonds[j + 1]};
     off += a[j].size();
   }
-  step_.reset();
-  DMps c = copy_mps(a, step_, s);
-  commit(c, s);
+  return a;
 }
 
-void Engine::get_state(std::vector<int>& bonds, double* packed,
-                       hipStream_t s) const {
+// Packed device cores of every instance (same bonds) staged in the step
+// arena at common addresses.
+DMps Engine::stage_packed(const std::vector<int>& bonds,
+                          const std::vector<const double*>& packed, hipStream_t s) {
+  MPSV_CHECK((int)packed.size() == nin_, kEinval, "one set of cores per instance expected");
+  const DMps v = view_packed(bonds, packed[0], n());
+  DMps a(n());
+  for (int j = 0; j < n(); ++j) {
+    a[j] = v[j];
+    a[j].p = step_.alloc(v[j].size());
+  }
+  for (int i = 0; i < nin_; ++i) {
+    LanesScope ls(one_lane(i));
+    const DMps vi = view_packed(bonds, packed[i], n());
+    for (int j = 0; j < n(); ++j) d2d_in(s, a[j].p, vi[j].p, vi[j].size() * sizeof(double));
+  }
+  return a;
+}
+
+void Engine::set_state(const std::vector<int>& bonds, const double* packed,
+                       hipStream_t s, int inst) {
+  check_instance(inst);
+  MPSV_CHECK(nin_ == 1, kEinval, "a batch takes its cores by set_states");
+  set_states(bonds, {packed}, s);
+}
+
+void Engine::set_states(const std::vector<int>& bonds,
+                        const std::vector<const double*>& packed, hipStream_t s) {
+  LanesScope ls(all_lanes());
+  step_.reset();
+  DMps a = stage_packed(bonds, packed, s);
+  commit(a, s);
+}
+
+void Engine::get_state(std::vector<int>& bonds, double* packed, hipStream_t s,
+                       int inst) const {
+  check_instance(inst);
+  LanesScope ls(one_lane(inst));
   bonds = this->bonds();
   long off = 0;
   for (auto& c : f_) {
-    if (packed)
-      MPSV_HIP(hipMemcpyAsync(packed + off, c.p, c.size() * sizeof(double),
-                              hipMemcpyDeviceToDevice, s));
+    if (packed) d2d_out(s, packed + off, c.p, c.size() * sizeof(double));
     off += c.size();
   }
 }
 
 void Engine::add_scaled(double alpha, const std::vector<int>& bonds,
-                        const double* packed, hipStream_t s) {
-  MPSV_CHECK((int)bonds.size() == n() + 1 && bonds[0] == 1 && bonds[n()] == 1,
-             kEinval, "bond dimensions must have n+1 entries with unit ends");
-  DMps g(n());
-  long off = 0;
-  for (int j = 0; j < n(); ++j) {
-    g[j] = Core{const_cast<double*>(packed) + off, bonds[j], bonds[j + 1]};
-    off += g[j].size();
-  }
-  step_.reset();
-  DMps fn = add_terms({{1.0, &f_}, {alpha, &g}}, cap_or_inf(p_.chi_max), step_, s);
-  commit(fn, s);
+                        const double* packed, hipStream_t s, int inst) {
+  check_instance(inst);
+  MPSV_CHECK(nin_ == 1, kEinval, "a batch adds by add_scaled_all");
+  add_scaled_all({alpha}, bonds, {packed}, s);
 }
 
-// ---------------------------------------------------------------- outputs
+// f_i <- compress(f_i + alpha_i g_i) for every instance (one set of bonds
+// for all g_i).  One instance keeps the scalar in the sum's coefficient; a
+// batch scales each g_i's first core by its alpha_i instead (the sum's
+// coefficients are common to all instances).
+void Engine::add_scaled_all(const std::vector<double>& alpha,
+                            const std::vector<int>& bonds,
+                            const std::vector<const double*>& packed, hipStream_t s) {
+  MPSV_CHECK((int)alpha.size() == nin_, kEinval, "one scalar per instance expected");
+  for (double a : alpha) MPSV_CHECK(std::isfinite(a), kEinval, "alpha must be finite");
+  LanesScope ls(all_lanes());
+  step_.reset();
+  DMps g = stage_packed(bonds, packed, s);
+  double coef = alpha[0];
+  if (nin_ > 1) {
+    coef = 1.0;
+    for (int i = 0; i < nin_; ++i) {
+      LanesScope l1(one_lane(i));
+      copy2d(s, 1, (int)g[0].size(), alpha[i], g[0].p, g[0].size(), g[0].p, g[0].size());
+    }
+  }
+  // a batch's truncations (tol = 0) report their outcomes at the end
+  DMps fn;
+  out_main_.begin();
+  try {
+    fn = add_terms({{1.0, &f_}, {coef, &g}}, cap_or_inf(p_.chi_max), step_, s);
+    out_main_.end(s);
+  } catch (...) {
+    out_main_.cancel(s);
+    throw;
+  }
+  commit(fn, s);
+}
 
 void Engine::dense_of(const DMps& a, double* out, hipStream_t s) {
   const int n = (int)a.size();
@@ -1793,8 +2095,7 @@ void Engine::dense_of(const DMps& a, double* out, hipStream_t s) {
   }
   double* b0 = tmp_.alloc(maxsz);
   double* b1 = tmp_.alloc(maxsz);
-  MPSV_HIP(hipMemcpyAsync(b0, a[0].p, a[0].size() * sizeof(double),
-                          hipMemcpyDeviceToDevice, s));
+  copy_doubles(s, b0, a[0].p, a[0].size());
   long r = 2;  // rows of the current block
   double* cur = b0;
   double* nxt = b1;
@@ -1808,8 +2109,11 @@ void Engine::dense_of(const DMps& a, double* out, hipStream_t s) {
   }
 }
 
-void Engine::to_dense(double* out, hipStream_t s) {
+void Engine::to_dense(double* out_caller, hipStream_t s, int inst) {
   MPSV_CHECK(!f_.empty(), kEinval, "state not initialised");
+  check_instance(inst);
+  LanesScope ls(one_lane(inst));
+  double* out = foreign(out_caller);
   if (p_.order == 0) {
     dense_of(f_, out, s);
   } else {
@@ -1844,32 +2148,36 @@ double Engine::full_contract(const DMps& g, const DMps& f, hipStream_t s) {
     fa = F.r;
   }
   double h = 0.0;
-  MPSV_HIP(hipMemcpyAsync(&h, E, sizeof(double), hipMemcpyDeviceToHost, s));
+  d2h(s, &h, E, sizeof(double));
   MPSV_HIP(hipStreamSynchronize(s));
   return h;
 }
 
-void Engine::density_field(double* n_out, double* E_out, hipStream_t s) {
+void Engine::density_field(double* n_out, double* E_out, hipStream_t s, int inst) {
   MPSV_CHECK(!f_.empty(), kEinval, "state not initialised");
+  check_instance(inst);
+  LanesScope ls(one_lane(inst));
   ArenaScope sc(step_);
   DMps nm = density(f_, step_, s);
   DMps E = field(f_, step_, s);
-  if (n_out) dense_of(nm, n_out, s);
-  if (E_out) dense_of(E, E_out, s);
+  if (n_out) dense_of(nm, foreign(n_out), s);
+  if (E_out) dense_of(E, foreign(E_out), s);
   MPSV_HIP(hipStreamSynchronize(s));
 }
 
 void Engine::moments(double* n_out, double* E_out, double* scalars,
-                     hipStream_t s) {
+                     hipStream_t s, int inst) {
   MPSV_CHECK(!f_.empty(), kEinval, "state not initialised");
+  check_instance(inst);
+  LanesScope ls(one_lane(inst));
   ArenaScope sc(step_);
   DMps nm = density(f_, step_, s);
   DMps E = field(f_, step_, s);
-  if (n_out) dense_of(nm, n_out, s);
+  if (n_out) dense_of(nm, foreign(n_out), s);
   double* Ed = nullptr;
   if (E_out) {
-    dense_of(E, E_out, s);
-    Ed = E_out;
+    Ed = foreign(E_out);
+    dense_of(E, Ed, s);
   }
   if (scalars) {
     ArenaScope sc2(tmp_);
@@ -1880,7 +2188,7 @@ void Engine::moments(double* n_out, double* E_out, double* scalars,
     double* we = tmp_.alloc(1);
     sum_squares(s, Ed, p_.Nx(), 0.5 * p_.dx(), we);
     double hwe = 0.0;
-    MPSV_HIP(hipMemcpyAsync(&hwe, we, sizeof(double), hipMemcpyDeviceToHost, s));
+    d2h(s, &hwe, we, sizeof(double));
     MPSV_HIP(hipStreamSynchronize(s));
     // mass = dx * sum_i n_i = dx dv <1, f>; momentum / kinetic with v, v^2/2
     double mass = 0.0;

@@ -91,6 +91,12 @@ void step_species(const std::vector<Engine*>& es, const std::vector<double>& q,
 void field_species_dense(const std::vector<Engine*>& es, const std::vector<double>& q,
                          double* E_out, double* energy, hipStream_t s);
 
+// An engine holds one instance, or a batch of lock-step instances of one
+// problem shape (see Lanes): the same grid sizes, ordering, caps, level,
+// precision, schemes and time step, tol = 0 and a fixed dt, so that every
+// compression keeps the same ranks in all of them; their physical
+// parameters (intervals, collision constants) and data may differ.  A
+// batched step issues each launch once for all instances.
 class Engine {
   friend void step_species(const std::vector<Engine*>&, const std::vector<double>&,
                            hipStream_t);
@@ -102,31 +108,47 @@ class Engine {
 
  public:
   explicit Engine(const Problem& p);
+  explicit Engine(const std::vector<Problem>& batch);
   ~Engine();
   Engine(const Engine&) = delete;
   Engine& operator=(const Engine&) = delete;
 
   const Problem& problem() const { return p_; }
   int n() const { return p_.n(); }
+  int instances() const { return nin_; }
 
-  // ---- state
+  // ---- state (per instance; instance 0 of a batch fixes the bond
+  // dimensions that every other instance must then have)
   void init_from_profiles(int rank, const double* ax, const double* bv,
-                          hipStream_t s);
+                          hipStream_t s, int inst = 0);
   void set_state(const std::vector<int>& bonds, const double* packed,
-                 hipStream_t s);
-  void get_state(std::vector<int>& bonds, double* packed, hipStream_t s) const;
+                 hipStream_t s, int inst = 0);
+  void get_state(std::vector<int>& bonds, double* packed, hipStream_t s,
+                 int inst = 0) const;
   void add_scaled(double alpha, const std::vector<int>& bonds,
-                  const double* packed, hipStream_t s);
+                  const double* packed, hipStream_t s, int inst = 0);
+  // ---- state of every instance of a batch at once
+  // each instance's initial state from its profiles (device, rank x N)
+  void init_batch(const std::vector<int>& ranks, const std::vector<const double*>& ax,
+                  const std::vector<const double*>& bv, hipStream_t s);
+  // packed device cores per instance, one set of bonds
+  void set_states(const std::vector<int>& bonds, const std::vector<const double*>& packed,
+                  hipStream_t s);
+  // f_i <- compress(f_i + alpha_i g_i), packed device cores g_i per instance
+  void add_scaled_all(const std::vector<double>& alpha, const std::vector<int>& bonds,
+                      const std::vector<const double*>& packed, hipStream_t s);
   const DMps& state() const { return f_; }
   std::vector<int> bonds() const;
   double time() const { return t_; }
   // von Neumann entropy (log2) of the Schmidt values at each of the n-1
   // bonds of the committed state (an untruncated canonicalisation)
-  std::vector<double> entanglement(hipStream_t s);
+  std::vector<double> entanglement(hipStream_t s, int inst = 0);
   // the step the next mps_step takes (the adaptive one needs a sync)
   double step_size(hipStream_t s);
   long steps_done() const { return steps_; }
-  const std::vector<double>& last_discarded() const { return disc_; }
+  // relative discarded weight per bond of the last compression of instance
+  // inst (n - 1 values)
+  std::vector<double> last_discarded(int inst = 0) const;
 
   // ---- the hot path
   void step(hipStream_t s);
@@ -151,10 +173,12 @@ class Engine {
   // compression): reserved bytes and peak extent in use
   void arena_bytes(size_t reserved[7], size_t peak[7]) const;
 
-  // ---- outputs
-  void to_dense(double* out, hipStream_t s);
-  void moments(double* n_out, double* E_out, double* scalars, hipStream_t s);
-  void density_field(double* n_out, double* E_out, hipStream_t s);
+  // ---- outputs (per instance)
+  void to_dense(double* out, hipStream_t s, int inst = 0);
+  void moments(double* n_out, double* E_out, double* scalars, hipStream_t s,
+               int inst = 0);
+  void density_field(double* n_out, double* E_out, hipStream_t s,
+                     int inst = 0);
 
   // ---- building blocks exposed for tests through the C-ABI
   // QR sweep left to right, then truncated SVD sweep right to left; with
@@ -173,6 +197,9 @@ class Engine {
                       std::vector<double>* disc = nullptr);
   DMpo upload_mpo(const std::vector<std::vector<double>>& W,
                   const std::vector<int>& bonds, Arena& ar, hipStream_t s);
+  // one host MPO per instance of the calling thread's lanes
+  DMpo upload_mpo(const std::vector<const std::vector<std::vector<double>>*>& Ws,
+                  const std::vector<int>& bonds, Arena& ar, hipStream_t s);
 
   DMps add_terms(const std::vector<std::pair<double, const DMps*>>& terms,
                  int cap, Arena& out, hipStream_t s, double tol = -1.0);
@@ -181,6 +208,11 @@ class Engine {
  private:
   void absorb_left(const VSite& v, const double* R, int p, double* M,
                    hipStream_t s);
+  DMps initial_state(int rank, const double* ax, const double* bv, hipStream_t s);
+  void set_states_host(const std::vector<int>& bonds,
+                       const std::vector<std::vector<double>>& packed, hipStream_t s);
+  DMps stage_packed(const std::vector<int>& bonds, const std::vector<const double*>& packed,
+                    hipStream_t s);
   void compress_right_half(DMps& res, int centre, const double* sc, int cap,
                            double tol, Arena& out, hipStream_t s,
                            std::vector<double>* disc);
@@ -214,21 +246,30 @@ class Engine {
   // Compression workspace of the calling thread: work_ on the thread that
   // drives the engine, work2_ on the side thread of rhs().
   Arena& work();
+  // the SVD outcome record of the lane whose stream is s
+  SvdOutcomes* outcomes(hipStream_t s) { return s == side_ ? &out_side_ : &out_main_; }
+  // launches over every instance, or over instance i alone
+  Lanes all_lanes() const { return Lanes{nin_, 0, (long)chunk_}; }
+  Lanes one_lane(int i) const { return Lanes{1, (long)i * (long)chunk_, (long)chunk_}; }
+  void check_instance(int i) const;
   // arithmetic of the MPO x MPS contractions: 0 FP64, 1 FP32, 2 BF16 on the
   // matrix cores (precision mode); factorisations, Poisson field and moments
   // stay FP64
   int contract_prec() const { return p_.precision; }
 
-  Problem p_;
-  // chunk size of the arenas, scaled to the problem (see memory_model)
+  Problem p_;                      // instance 0's problem
+  std::vector<Problem> ps_;        // every instance's problem
+  int nin_;                        // lock-step instances
+  // chunk size of the arenas, scaled to the problem (see memory_model);
+  // also the distance between two instances' copies of every buffer
   size_t chunk_;
-  Arena ops_{chunk_};              // operators (persistent)
-  Arena state_{chunk_};            // committed state
-  Arena step_{chunk_};             // per-step intermediates
-  Arena tmp_{chunk_};              // per-RHS intermediates
-  Arena work_{chunk_};             // per-compression workspace
-  Arena tmp2_{chunk_};             // per-RHS intermediates of the side lane
-  Arena work2_{chunk_};            // compression workspace of the side lane
+  Arena ops_{chunk_, nin_};        // operators (persistent)
+  Arena state_{chunk_, nin_};      // committed state
+  Arena step_{chunk_, nin_};       // per-step intermediates
+  Arena tmp_{chunk_, nin_};        // per-RHS intermediates
+  Arena work_{chunk_, nin_};       // per-compression workspace
+  Arena tmp2_{chunk_, nin_};       // per-RHS intermediates of the side lane
+  Arena work2_{chunk_, nin_};      // compression workspace of the side lane
   int device_ = 0;                 // the device the instance lives on
   hipStream_t own_ = nullptr;      // this instance's stream (batched mode)
   hipStream_t side_ = nullptr;     // T1 runs here, beside T2
@@ -239,7 +280,10 @@ class Engine {
   hipGraphExec_t gexec_ = nullptr;
   std::vector<Core> graph_key_, warm_key_;  // input state layouts
   DMps graph_out_;                           // the graph's new state
-  SvdDeferRecord rec_own_, rec_side_;
+  // SVD outcomes of the two lanes and their records kept for graph replays
+  SvdOutcomes out_main_, out_side_;
+  SvdOutcomes::Record rec_own_, rec_side_;
+  bool capturing_ = false;         // a step graph is being recorded
   long graph_captures_ = 0, graph_replays_ = 0;
   DMpo t1_, gneg_, dv_;            // T1 chain, -G (x sites), Dv (v sites)
   DMpo coll_;                      // collision operator chain (nu > 0)

@@ -8,8 +8,6 @@
 // each of the 4 waves owns a 32 x 32 sub-tile computed by 2 x 2
 // v_mfma_f64_16x16x4f64 accumulators (64-wide wavefronts).
 #include <algorithm>
-#include <map>
-#include <mutex>
 
 #include "gemm.hpp"
 #include "prof.hpp"
@@ -28,15 +26,21 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(
     int M, int N, int K, double alpha, const double* __restrict__ A, long ars,
     long acs, long abs_, const double* __restrict__ B, long brs, long bcs,
     long bbs, double beta, double* __restrict__ C, long crs, long ccs, long cbs,
-    int a_kfast, int b_nfast, int nsplit, int kchunk) {
+    int a_kfast, int b_nfast, int nsplit, int kchunk, int zper, InstOff io) {
   __shared__ double As[BK][BM + 1];
   __shared__ double Bs[BK][BN + 1];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const long bz = blockIdx.z / nsplit;
-  const int split = blockIdx.z % nsplit;
+  // blockIdx.z = instance * zper + batch * nsplit + split
+  const long o_ = io.of(blockIdx.z / zper);
+  A = shifted(A, o_);
+  B = shifted(B, o_);
+  C = shifted(C, o_);
+  const int zb = blockIdx.z % zper;
+  const long bz = zb / nsplit;
+  const int split = zb % nsplit;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
   A += bz * abs_;
   B += bz * bbs;
@@ -126,15 +130,21 @@ __global__ __launch_bounds__(NT) void gemm_f32acc_kernel(
     int M, int N, int K, double alpha, const double* __restrict__ A, long ars,
     long acs, long abs_, const double* __restrict__ B, long brs, long bcs,
     long bbs, double beta, double* __restrict__ C, long crs, long ccs, long cbs,
-    int a_kfast, int b_nfast, int nsplit, int kchunk) {
+    int a_kfast, int b_nfast, int nsplit, int kchunk, int zper, InstOff io) {
   __shared__ float As[BK][BM + 1];
   __shared__ float Bs[BK][BN + 1];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const long bz = blockIdx.z / nsplit;
-  const int split = blockIdx.z % nsplit;
+  // blockIdx.z = instance * zper + batch * nsplit + split
+  const long o_ = io.of(blockIdx.z / zper);
+  A = shifted(A, o_);
+  B = shifted(B, o_);
+  C = shifted(C, o_);
+  const int zb = blockIdx.z % zper;
+  const long bz = zb / nsplit;
+  const int split = zb % nsplit;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
   A += bz * abs_;
   B += bz * bbs;
@@ -220,7 +230,10 @@ __global__ __launch_bounds__(NT) void gemm_f32acc_kernel(
 __global__ void splitk_reduce_kernel(int M, int N, int nsplit, double alpha,
                                      const double* __restrict__ P, double beta,
                                      double* __restrict__ C, long crs, long ccs,
-                                     long cbs) {
+                                     long cbs, InstOff io) {
+  const long o_ = io.of(blockIdx.z);
+  P = shifted(P, o_);
+  C = shifted(C, o_);
   const long b = blockIdx.y;
   const long MN = (long)M * N;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < MN;
@@ -234,33 +247,10 @@ __global__ void splitk_reduce_kernel(int M, int N, int nsplit, double alpha,
   }
 }
 
-// Scratch for split-K partial products, one per stream, grown on demand and
-// kept for the process lifetime.
-struct Scratch {
-  double* p = nullptr;
-  size_t n = 0;
-};
-std::mutex g_splitk_mu;
-std::map<hipStream_t, Scratch> g_splitk;
-double* splitk_scratch(hipStream_t s, size_t n) {
-  std::lock_guard<std::mutex> lk(g_splitk_mu);
-  Scratch& sc = g_splitk[s];
-  if (n > sc.n) {
-    if (sc.p) {
-      MPSV_HIP(hipStreamSynchronize(s));
-      MPSV_HIP(hipFree(sc.p));
-    }
-    size_t want = n + n / 2;
-    MPSV_HIP(hipMalloc(&sc.p, want * sizeof(double)));
-    sc.n = want;
-  }
-  return sc.p;
-}
-
 }  // namespace
 
 void gemm(hipStream_t s, int M, int N, int K, double alpha, CMatView A,
-          CMatView B, double beta, MatView C, int batch, int prec) {
+          CMatView B, double beta, MatView C, int batch, int prec, Arena* ws) {
   if (M <= 0 || N <= 0 || batch <= 0) return;
   if (K <= 0) {
     // C = beta * C
@@ -270,19 +260,26 @@ void gemm(hipStream_t s, int M, int N, int K, double alpha, CMatView A,
   const int a_kfast = (A.cs == 1) ? 1 : 0;
   const int b_nfast = (B.cs == 1) ? 1 : 0;
   const long tiles = (long)ceil_div(N, BN) * ceil_div(M, BM);
-  // split K when the output alone cannot fill the chip
+  const int ninst = inst_count();
+  // split K when the output alone cannot fill the chip; the partial
+  // products live in the caller's workspace (none given: no split).  The
+  // choice ignores lock-step instances, so that every instance sums in the
+  // order a stand-alone state does.
   int nsplit = 1;
-  if (K >= 4 * BK * 4 && tiles * batch < 256) {
+  if (ws && K >= 4 * BK * 4 && tiles * batch < 256) {
     long want = 512 / (tiles * batch);
     long maxk = K / (4 * BK);
-    nsplit = (int)std::max(1L, std::min(std::min(want, maxk), 64L));
+    const long fit = (long)(ws->max_alloc_bytes() / sizeof(double)) /
+                     std::max(1L, (long)batch * M * N);
+    nsplit = (int)std::max(1L, std::min(std::min(std::min(want, maxk), 64L), fit));
   }
   const int kchunk = (nsplit > 1) ? ceil_div(ceil_div(K, nsplit), BK) * BK : K;
   if (nsplit > 1) nsplit = ceil_div(K, kchunk);
-  const int bmax = std::max(1, 65535 / nsplit);
+  const int bmax = std::max(1, 65535 / (nsplit * ninst));
   for (int b0 = 0; b0 < batch; b0 += bmax) {
     int nb = batch - b0 < bmax ? batch - b0 : bmax;
-    dim3 grid(ceil_div(N, BN), ceil_div(M, BM), nb * nsplit);
+    const int zper = nb * nsplit;
+    dim3 grid(ceil_div(N, BN), ceil_div(M, BM), zper * ninst);
     const int slot = prof_begin(s);
     if (nsplit == 1) {
       hipLaunchKernelGGL(prec == 2 ? gemm_f32acc_kernel<2>
@@ -291,24 +288,25 @@ void gemm(hipStream_t s, int M, int N, int K, double alpha, CMatView A,
                          A.p + (long)b0 * A.bs, A.rs, A.cs, A.bs,
                          B.p + (long)b0 * B.bs, B.rs, B.cs, B.bs, beta,
                          C.p + (long)b0 * C.bs, C.rs, C.cs, C.bs, a_kfast,
-                         b_nfast, 1, K);
+                         b_nfast, 1, K, zper, inst_off());
       MPSV_LAUNCHED();
     } else {
-      double* P = splitk_scratch(s, (size_t)nb * nsplit * M * N);
+      ArenaScope sc(*ws);
+      double* P = ws->alloc((size_t)nb * nsplit * M * N);
       hipLaunchKernelGGL(prec == 2 ? gemm_f32acc_kernel<2>
                          : prec == 1 ? gemm_f32acc_kernel<1> : gemm_f64_kernel, grid,
                          dim3(NT), 0, s, M, N, K, 1.0,
                          A.p + (long)b0 * A.bs, A.rs, A.cs, A.bs,
                          B.p + (long)b0 * B.bs, B.rs, B.cs, B.bs, 0.0, P,
                          (long)N, 1L, (long)nsplit * M * N, a_kfast, b_nfast,
-                         nsplit, kchunk);
+                         nsplit, kchunk, zper, inst_off());
       MPSV_LAUNCHED();
       const long MN = (long)M * N;
       int blocks = ceil_div(MN, 256);
       if (blocks > 1024) blocks = 1024;
-      hipLaunchKernelGGL(splitk_reduce_kernel, dim3(blocks, nb), dim3(256), 0,
+      hipLaunchKernelGGL(splitk_reduce_kernel, dim3(blocks, nb, ninst), dim3(256), 0,
                          s, M, N, nsplit, alpha, P, beta,
-                         C.p + (long)b0 * C.bs, C.rs, C.cs, C.bs);
+                         C.p + (long)b0 * C.bs, C.rs, C.cs, C.bs, inst_off());
       MPSV_LAUNCHED();
     }
     prof_end(s, slot, kClsGemm, 2.0 * M * N * (double)K * nb,
@@ -318,7 +316,8 @@ void gemm(hipStream_t s, int M, int N, int K, double alpha, CMatView A,
 
 namespace {
 __global__ void scale_matrix_kernel(int M, int N, double beta, double* C,
-                                    long rs, long cs, long bs) {
+                                    long rs, long cs, long bs, InstOff io) {
+  C = shifted(C, io.of(blockIdx.z));
   long b = blockIdx.y;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < (long)M * N;
        e += (long)gridDim.x * blockDim.x) {
@@ -335,8 +334,8 @@ void scale_matrix(hipStream_t s, int M, int N, double beta, MatView C,
   long tot = (long)M * N;
   int blocks = ceil_div(tot, 256);
   if (blocks > 1024) blocks = 1024;
-  hipLaunchKernelGGL(scale_matrix_kernel, dim3(blocks, batch), dim3(256), 0,
-                     s, M, N, beta, C.p, C.rs, C.cs, C.bs);
+  hipLaunchKernelGGL(scale_matrix_kernel, dim3(blocks, batch, inst_count()), dim3(256), 0,
+                     s, M, N, beta, C.p, C.rs, C.cs, C.bs, inst_off());
   MPSV_LAUNCHED();
 }
 

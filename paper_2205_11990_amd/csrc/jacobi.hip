@@ -208,8 +208,16 @@ template <int RPT, int NL>
 __global__ __launch_bounds__(64 * NL) void jacobi_hc_kernel(
     const double* __restrict__ Xr, int k, long ldx, int d, int max_sweeps,
     int cap, double tol, double* __restrict__ Vt, double* __restrict__ sigbuf,
-    int* __restrict__ perm_out, double* __restrict__ info) {
+    int* __restrict__ perm_out, double* __restrict__ info, InstOff io) {
   static_assert(NL == 4 || NL == 8 || NL == 16, "nodes of 4, 8 or 16 lanes");
+  {
+    const long o_ = io.of(blockIdx.z);
+    Xr = shifted(Xr, o_);
+    Vt = shifted(Vt, o_);
+    sigbuf = shifted(sigbuf, o_);
+    perm_out = shifted(perm_out, o_);
+    info = shifted(info, o_);
+  }
   extern __shared__ double smem[];
   __shared__ double red[MAXT / 64];
   __shared__ double xn[2 * 64];
@@ -526,8 +534,23 @@ template <int NLOG, int GLOG, int RPT>
 __global__ __launch_bounds__(16 << (NLOG - GLOG)) void jacobi_multi_kernel(
     const double* __restrict__ Xr, int k, long ldx, int max_sweeps, int cap,
     double tol, double* __restrict__ Vt, double* __restrict__ sigbuf,
-    int* __restrict__ perm_out, double* __restrict__ info, MultiWs w) {
+    int* __restrict__ perm_out, double* __restrict__ info, MultiWs w,
+    InstOff io) {
   using S = Split<NLOG, GLOG, RPT>;
+  {
+    // the workgroups of instance z meet in that instance's exchange area
+    const long o_ = io.of(blockIdx.z);
+    Xr = shifted(Xr, o_);
+    Vt = shifted(Vt, o_);
+    sigbuf = shifted(sigbuf, o_);
+    perm_out = shifted(perm_out, o_);
+    info = shifted(info, o_);
+    w.xg = shifted(w.xg, o_);
+    w.xn = shifted(w.xn, o_);
+    w.val = shifted(w.val, o_);
+    w.xi = shifted(w.xi, o_);
+    w.flags = shifted(w.flags, o_);
+  }
   constexpr int kMultiWgs = S::wgs;
   constexpr int kMultiLog = GLOG;
   constexpr int kMultiNodes = S::nodes;
@@ -907,9 +930,9 @@ void launch_split(hipStream_t s, const double* Xr, int k, long ldx, int cap,
   w.xi = (int*)(w.val + 2 * S::wgs);
   w.flags = w.xi + S::slots;
   fill_int(s, w.flags, S::wgs, 0);
-  jacobi_multi_kernel<NLOG, GLOG, RPT><<<dim3(S::wgs), dim3(S::threads),
+  jacobi_multi_kernel<NLOG, GLOG, RPT><<<dim3(S::wgs, 1, inst_count()), dim3(S::threads),
                                          split_lds<NLOG, GLOG, RPT>(), s>>>(
-      Xr, k, ldx, max_sweeps, cap, tol, Vt, sigbuf, perm, info, w);
+      Xr, k, ldx, max_sweeps, cap, tol, Vt, sigbuf, perm, info, w, inst_off());
   MPSV_LAUNCHED();
 }
 
@@ -977,26 +1000,26 @@ void jacobi_svd(hipStream_t s, const double* Xr, int k, long ldx, int cap,
   MPSV_CHECK(sh.nl * sh.rpt >= k && (int)block.x <= 64 * sh.nl && block.x % 64 == 0,
              kEinval, "Jacobi SVD: bad layout");
   if (sh.nl == 16 && sh.rpt == 2)
-    jacobi_hc_kernel<2, 16><<<dim3(1), block, lds, s>>>(
-        Xr, k, ldx, sh.d, max_sweeps, cap, tol, Vt, sigbuf, perm, info);
+    jacobi_hc_kernel<2, 16><<<dim3(1, 1, inst_count()), block, lds, s>>>(
+        Xr, k, ldx, sh.d, max_sweeps, cap, tol, Vt, sigbuf, perm, info, inst_off());
   else if (sh.nl == 16 && sh.rpt == 4)
-    jacobi_hc_kernel<4, 16><<<dim3(1), block, lds, s>>>(
-        Xr, k, ldx, sh.d, max_sweeps, cap, tol, Vt, sigbuf, perm, info);
+    jacobi_hc_kernel<4, 16><<<dim3(1, 1, inst_count()), block, lds, s>>>(
+        Xr, k, ldx, sh.d, max_sweeps, cap, tol, Vt, sigbuf, perm, info, inst_off());
   else if (sh.nl == 16)
-    jacobi_hc_kernel<8, 16><<<dim3(1), block, lds, s>>>(
-        Xr, k, ldx, sh.d, max_sweeps, cap, tol, Vt, sigbuf, perm, info);
+    jacobi_hc_kernel<8, 16><<<dim3(1, 1, inst_count()), block, lds, s>>>(
+        Xr, k, ldx, sh.d, max_sweeps, cap, tol, Vt, sigbuf, perm, info, inst_off());
   else if (sh.nl == 8 && sh.rpt == 8)
-    jacobi_hc_kernel<8, 8><<<dim3(1), block, lds, s>>>(
-        Xr, k, ldx, sh.d, max_sweeps, cap, tol, Vt, sigbuf, perm, info);
+    jacobi_hc_kernel<8, 8><<<dim3(1, 1, inst_count()), block, lds, s>>>(
+        Xr, k, ldx, sh.d, max_sweeps, cap, tol, Vt, sigbuf, perm, info, inst_off());
   else if (sh.nl == 8)
-    jacobi_hc_kernel<16, 8><<<dim3(1), block, lds, s>>>(
-        Xr, k, ldx, sh.d, max_sweeps, cap, tol, Vt, sigbuf, perm, info);
+    jacobi_hc_kernel<16, 8><<<dim3(1, 1, inst_count()), block, lds, s>>>(
+        Xr, k, ldx, sh.d, max_sweeps, cap, tol, Vt, sigbuf, perm, info, inst_off());
   else if (sh.rpt == 16)
-    jacobi_hc_kernel<16, 4><<<dim3(1), block, lds, s>>>(
-        Xr, k, ldx, sh.d, max_sweeps, cap, tol, Vt, sigbuf, perm, info);
+    jacobi_hc_kernel<16, 4><<<dim3(1, 1, inst_count()), block, lds, s>>>(
+        Xr, k, ldx, sh.d, max_sweeps, cap, tol, Vt, sigbuf, perm, info, inst_off());
   else
-    jacobi_hc_kernel<32, 4><<<dim3(1), block, lds, s>>>(
-        Xr, k, ldx, sh.d, max_sweeps, cap, tol, Vt, sigbuf, perm, info);
+    jacobi_hc_kernel<32, 4><<<dim3(1, 1, inst_count()), block, lds, s>>>(
+        Xr, k, ldx, sh.d, max_sweeps, cap, tol, Vt, sigbuf, perm, info, inst_off());
   MPSV_LAUNCHED();
 }
 

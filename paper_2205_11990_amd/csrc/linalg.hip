@@ -18,7 +18,6 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
-#include <map>
 #include <mutex>
 
 #include "gemm.hpp"
@@ -68,7 +67,10 @@ __device__ inline double block_sum(double v, double* red) {
 }
 
 __global__ void extract_r_kernel(const double* A, int k, int n, long ld,
-                                 MatView R) {
+                                 MatView R, InstOff io) {
+  const long o_ = io.of(blockIdx.z);
+  A = shifted(A, o_);
+  R = shifted(R, o_);
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < (long)k * n;
        e += (long)gridDim.x * blockDim.x) {
     long i = e / n, j = e % n;
@@ -78,7 +80,10 @@ __global__ void extract_r_kernel(const double* A, int k, int n, long ld,
 
 // out[0:rows, 0:cols] = in (rows < rows_in), 0 (rows >= rows_in); any strides
 __global__ void copy_view_kernel(CMatView in, int rows_in, MatView out,
-                                 int rows, int cols) {
+                                 int rows, int cols, InstOff io) {
+  const long o_ = io.of(blockIdx.z);
+  in = shifted(in, o_);
+  out = shifted(out, o_);
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
        e < (long)rows * cols; e += (long)gridDim.x * blockDim.x) {
     const long i = e / cols, j = e % cols;
@@ -87,7 +92,8 @@ __global__ void copy_view_kernel(CMatView in, int rows_in, MatView out,
 }
 
 __global__ void fill_rows_zero_kernel(double* X, int r0, int r1, int nc,
-                                      long ld) {
+                                      long ld, InstOff io) {
+  X = shifted(X, io.of(blockIdx.z));
   long tot = (long)(r1 - r0) * nc;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot;
        e += (long)gridDim.x * blockDim.x) {
@@ -103,7 +109,18 @@ __global__ void fill_rows_zero_kernel(double* X, int r0, int r1, int nc,
 __global__ __launch_bounds__(NT) void jacobi_svd_kernel(
     const double* __restrict__ B, int mb, int c, long ldb, double* Wg,
     double* Jg, int use_lds, int cap, double tol, int max_sweeps, double* Vt,
-    double* USs, long ldus_rows_limit, double* sig_out, double* info) {
+    double* USs, long ldus_rows_limit, double* sig_out, double* info,
+    InstOff io) {
+  {
+    const long o_ = io.of(blockIdx.z);
+    B = shifted(B, o_);
+    if (Wg) Wg = shifted(Wg, o_);
+    if (Jg) Jg = shifted(Jg, o_);
+    Vt = shifted(Vt, o_);
+    USs = shifted(USs, o_);
+    sig_out = shifted(sig_out, o_);
+    info = shifted(info, o_);
+  }
   extern __shared__ double smem[];
   __shared__ double red[NT / 64];
   __shared__ int rotated;
@@ -270,7 +287,11 @@ __global__ __launch_bounds__(NT) void jacobi_svd_kernel(
 // (t / jb) * crows + t % jb of X (leading dimension ld); gathered into T
 // (srows x nc, row-major) or scattered back.
 __global__ void chunk_tops_kernel(double* X, long ld, int crows, int jb,
-                                  int srows, int nc, double* T, int gather) {
+                                  int srows, int nc, double* T, int gather,
+                                  InstOff io) {
+  const long o_ = io.of(blockIdx.z);
+  X = shifted(X, o_);
+  T = shifted(T, o_);
   const long total = (long)srows * nc;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
        e += (long)gridDim.x * blockDim.x) {
@@ -279,36 +300,6 @@ __global__ void chunk_tops_kernel(double* X, long ld, int crows, int jb,
     if (gather) T[e] = X[row * ld + c];
     else X[row * ld + c] = T[e];
   }
-}
-
-// Pinned host words for the rank read-back, one block per stream (several
-// host threads may run sweeps on different streams at once).
-std::mutex g_pinned_mu;
-std::map<hipStream_t, double*> g_pinned;
-
-double* pinned_info(hipStream_t s) {
-  std::lock_guard<std::mutex> lk(g_pinned_mu);
-  double*& p = g_pinned[s];
-  if (!p) MPSV_HIP(hipHostMalloc((void**)&p, 4096, hipHostMallocDefault));
-  return p;
-}
-
-// Deferred outcome slots, per stream (see svd_defer_begin).
-constexpr int kDeferSlots = 4096;
-constexpr int kInfoWords = 8;
-struct Deferred {
-  bool on = false;
-  double* ring = nullptr;  // pinned, kDeferSlots x kInfoWords
-  int used = 0;
-  std::vector<std::pair<double*, int>> disc;  // destination, slot
-  std::vector<char> split;                    // slot was a split launch
-};
-std::mutex g_defer_mu;
-std::map<hipStream_t, Deferred> g_defer;
-
-Deferred& defer_of(hipStream_t s) {
-  std::lock_guard<std::mutex> lk(g_defer_mu);
-  return g_defer[s];  // map nodes keep their address
 }
 
 std::once_flag g_attr_once;
@@ -324,78 +315,82 @@ void set_attrs() {
 
 LinalgStats& linalg_stats() { return g_stats; }
 
-void svd_defer_begin(hipStream_t s) {
-  Deferred& d = defer_of(s);
-  if (!d.ring)
-    MPSV_HIP(hipHostMalloc((void**)&d.ring,
-                           sizeof(double) * kDeferSlots * kInfoWords,
-                           hipHostMallocDefault));
-  d.used = 0;
-  d.disc.clear();
-  d.split.clear();
-  d.on = true;
+void SvdOutcomes::begin() {
+  MPSV_CHECK(ring_ != nullptr, kEinval, "SVD outcome ring not bound");
+  rec_ = Record{};
+  on_ = true;
 }
 
-void svd_defer_end(hipStream_t s) {
-  Deferred& d = defer_of(s);
-  if (!d.on) return;
-  d.on = false;
-  if (d.used == 0) return;
+double* SvdOutcomes::reserve(double* disc, long disc_stride, bool split) {
+  const int slot = rec_.used++;
+  if (disc) {
+    rec_.disc.push_back({disc, slot});
+    rec_.disc_stride.push_back(disc_stride);
+  }
+  rec_.split.push_back(split ? 1 : 0);
+  return ring_ + (long)slot * kInfoWords;
+}
+
+void SvdOutcomes::end(hipStream_t s) {
+  if (!on_) return;
+  on_ = false;
+  if (rec_.used == 0) return;
+  // the used slots of every lock-step instance, one row per instance
+  const int ni = inst_count();
+  const size_t row = (size_t)rec_.used * kInfoWords;
+  std::vector<double> h(row * (size_t)ni);
+  for (int i = 0; i < ni; ++i)
+    MPSV_HIP(hipMemcpyAsync(h.data() + row * i,
+                            shifted(ring_, lanes().first + (long)i * lanes().stride),
+                            row * sizeof(double), hipMemcpyDeviceToHost, s));
   MPSV_HIP(hipStreamSynchronize(s));
   int code = 0;
   std::string msg;
-  for (int i = 0; i < d.used; ++i) {
-    const volatile double* h = d.ring + (long)i * kInfoWords;
-    g_stats.jacobi_sweeps += (long)h[2];
-    if (code) continue;
-    if (d.split[i] && h[5] != 0.0) {
-      code = kEdevice;
-      msg = "Jacobi SVD: the workgroups did not meet in time";
-    } else if (h[3] == 0.0) {
-      code = kEnumeric;
-      msg = "Jacobi SVD did not converge within " +
-            std::to_string(g_max_sweeps) + " sweeps";
+  for (int inst = 0; inst < ni; ++inst) {
+    const double* hi = h.data() + row * inst;
+    for (int i = 0; i < rec_.used; ++i) {
+      const double* w = hi + (long)i * kInfoWords;
+      g_stats.jacobi_sweeps += (long)w[2];
+      if (code) continue;
+      const std::string who = ni > 1 ? "instance " + std::to_string(inst) + ": " : "";
+      if (rec_.split[i] && w[5] != 0.0) {
+        code = kEdevice;
+        msg = who + "Jacobi SVD: the workgroups did not meet in time";
+      } else if (w[3] == 0.0) {
+        code = kEnumeric;
+        msg = who + "Jacobi SVD did not converge within " +
+              std::to_string(g_max_sweeps) + " sweeps";
+      }
     }
+    for (size_t t = 0; t < rec_.disc.size(); ++t)
+      rec_.disc[t].first[inst * rec_.disc_stride[t]] =
+          hi[(long)rec_.disc[t].second * kInfoWords + 1];
   }
-  for (auto& w : d.disc) *w.first = d.ring[(long)w.second * kInfoWords + 1];
-  d.used = 0;
-  d.disc.clear();
-  d.split.clear();
+  rec_ = Record{};
   if (code) throw Error(code, msg);
 }
 
-SvdDeferRecord svd_defer_take(hipStream_t s) {
-  Deferred& d = defer_of(s);
-  SvdDeferRecord r;
-  r.used = d.used;
-  r.disc = d.disc;
-  r.split = d.split;
-  d.on = false;
-  d.used = 0;
-  d.disc.clear();
-  d.split.clear();
+SvdOutcomes::Record SvdOutcomes::take() {
+  Record r = rec_;
+  on_ = false;
+  rec_ = Record{};
   return r;
 }
 
-void svd_defer_resume(hipStream_t s, const SvdDeferRecord& r) {
-  Deferred& d = defer_of(s);
-  MPSV_CHECK(d.ring != nullptr && r.used <= kDeferSlots, kEinval,
+void SvdOutcomes::resume(const Record& r) {
+  MPSV_CHECK(ring_ != nullptr && r.used <= kSlots, kEinval,
              "deferred SVD record without its slots");
-  d.used = r.used;
-  d.disc = r.disc;
-  d.split = r.split;
-  d.on = true;
+  rec_ = r;
+  on_ = true;
 }
 
-void svd_defer_cancel(hipStream_t s) noexcept {
-  Deferred& d = defer_of(s);
-  if (!d.on) return;
-  d.on = false;
+void SvdOutcomes::cancel(hipStream_t s) noexcept {
+  if (!on_) return;
+  on_ = false;
   (void)hipStreamSynchronize(s);
-  d.used = 0;
-  d.disc.clear();
-  d.split.clear();
+  rec_ = Record{};
 }
+
 void set_jacobi_max_sweeps(int n) { g_max_sweeps = n < 1 ? 1 : n; }
 int jacobi_max_sweeps() { return g_max_sweeps; }
 
@@ -403,8 +398,8 @@ void extract_r(hipStream_t s, const double* A, int k, int n, long ld,
                MatView R) {
   if (k <= 0 || n <= 0) return;
   int blocks = std::min(1024, ceil_div((long)k * n, 256));
-  hipLaunchKernelGGL(extract_r_kernel, dim3(blocks), dim3(256), 0, s, A, k, n,
-                     ld, R);
+  hipLaunchKernelGGL(extract_r_kernel, dim3(blocks, 1, inst_count()), dim3(256), 0, s, A, k, n,
+                     ld, R, inst_off());
   MPSV_LAUNCHED();
 }
 
@@ -412,8 +407,8 @@ void chunk_tops(hipStream_t s, double* X, long ld, int crows, int jb, int srows,
                 int nc, double* T, bool gather) {
   if (srows <= 0 || nc <= 0) return;
   int blocks = std::min(1024, ceil_div((long)srows * nc, 256));
-  hipLaunchKernelGGL(chunk_tops_kernel, dim3(blocks), dim3(256), 0, s, X, ld,
-                     crows, jb, srows, nc, T, gather ? 1 : 0);
+  hipLaunchKernelGGL(chunk_tops_kernel, dim3(blocks, 1, inst_count()), dim3(256), 0, s, X, ld,
+                     crows, jb, srows, nc, T, gather ? 1 : 0, inst_off());
   MPSV_LAUNCHED();
 }
 
@@ -421,12 +416,13 @@ void copy_view(hipStream_t s, CMatView in, int rows_in, MatView out, int rows,
                int cols) {
   if (rows <= 0 || cols <= 0) return;
   int blocks = std::min(1024, ceil_div((long)rows * cols, 256));
-  hipLaunchKernelGGL(copy_view_kernel, dim3(blocks), dim3(256), 0, s, in,
-                     rows_in, out, rows, cols);
+  hipLaunchKernelGGL(copy_view_kernel, dim3(blocks, 1, inst_count()), dim3(256), 0, s, in,
+                     rows_in, out, rows, cols, inst_off());
   MPSV_LAUNCHED();
 }
 
-__global__ void fill_ints_kernel(int* x, long n) {
+__global__ void fill_ints_kernel(int* x, long n, InstOff io) {
+  x = shifted(x, io.of(blockIdx.z));
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n;
        e += (long)gridDim.x * blockDim.x)
     x[e] = 0;
@@ -435,12 +431,15 @@ __global__ void fill_ints_kernel(int* x, long n) {
 static void fill_ints(hipStream_t s, int* x, long n) {
   if (n <= 0) return;
   int blocks = std::min(1024, ceil_div(n, 256));
-  hipLaunchKernelGGL(fill_ints_kernel, dim3(blocks), dim3(256), 0, s, x, n);
+  hipLaunchKernelGGL(fill_ints_kernel, dim3(blocks, 1, inst_count()), dim3(256), 0, s, x, n, inst_off());
   MPSV_LAUNCHED();
 }
 
 __global__ void transpose_kernel(const double* A, int rows, int cols, long lda,
-                                 double* B, long ldb) {
+                                 double* B, long ldb, InstOff io) {
+  const long o_ = io.of(blockIdx.z);
+  A = shifted(A, o_);
+  B = shifted(B, o_);
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
        e < (long)rows * cols; e += (long)gridDim.x * blockDim.x) {
     const long i = e % rows, j = e / rows;   // consecutive threads: rows of A
@@ -453,12 +452,15 @@ static void transpose(hipStream_t s, const double* A, int rows, int cols,
                       long lda, double* B, long ldb) {
   if (rows <= 0 || cols <= 0) return;
   int blocks = std::min(1024, ceil_div((long)rows * cols, 256));
-  hipLaunchKernelGGL(transpose_kernel, dim3(blocks), dim3(256), 0, s, A, rows,
-                     cols, lda, B, ldb);
+  hipLaunchKernelGGL(transpose_kernel, dim3(blocks, 1, inst_count()), dim3(256), 0, s, A, rows,
+                     cols, lda, B, ldb, inst_off());
   MPSV_LAUNCHED();
 }
 
-__global__ void copy_rows_kernel(const double* A, long n, double* B) {
+__global__ void copy_rows_kernel(const double* A, long n, double* B, InstOff io) {
+  const long o_ = io.of(blockIdx.z);
+  A = shifted(A, o_);
+  B = shifted(B, o_);
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n;
        e += (long)gridDim.x * blockDim.x)
     B[e] = A[e];
@@ -470,7 +472,7 @@ static void copy_rows(hipStream_t s, const double* A, int rows, int cols,
   const long n = (long)rows * cols;
   if (n <= 0) return;
   int blocks = std::min(1024, ceil_div(n, 256));
-  hipLaunchKernelGGL(copy_rows_kernel, dim3(blocks), dim3(256), 0, s, A, n, B);
+  hipLaunchKernelGGL(copy_rows_kernel, dim3(blocks, 1, inst_count()), dim3(256), 0, s, A, n, B, inst_off());
   MPSV_LAUNCHED();
 }
 
@@ -478,8 +480,8 @@ static void fill_rows_zero(hipStream_t s, double* X, int r0, int r1, int nc,
                            long ld) {
   if (r1 <= r0 || nc <= 0) return;
   int blocks = std::min(1024, ceil_div((long)(r1 - r0) * nc, 256));
-  hipLaunchKernelGGL(fill_rows_zero_kernel, dim3(blocks), dim3(256), 0, s, X,
-                     r0, r1, nc, ld);
+  hipLaunchKernelGGL(fill_rows_zero_kernel, dim3(blocks, 1, inst_count()), dim3(256), 0, s, X,
+                     r0, r1, nc, ld, inst_off());
   MPSV_LAUNCHED();
 }
 
@@ -639,24 +641,20 @@ void qr_apply_q(hipStream_t s, Arena& ws, const QrFactor& f, double* X, int nc,
 
 int svd_truncate(hipStream_t s, Arena& ws, double* X, int m, int c, long ldx,
                  int cap, double tol, double* Vt, double* US, double* sig,
-                 double* discarded) {
+                 double* discarded, SvdOutcomes* out, long disc_stride) {
   set_attrs();
   g_stats.svd_calls++;
   MPSV_CHECK(m >= 1 && c >= 1, kEinval, "svd_truncate: empty matrix");
   ArenaScope sc(ws);
-  // the kernels write their info words straight into pinned host memory
-  // (device-accessible): this stream's block, read after the stream
-  // synchronisation, or a slot of its deferred record
-  Deferred* df = nullptr;
-  int slot_i = -1;
-  if (tol <= 0.0) {
-    Deferred& d = defer_of(s);
-    if (d.on && d.used < kDeferSlots) {
-      df = &d;
-      slot_i = d.used++;
-    }
-  }
-  double* info = df ? df->ring + (long)slot_i * kInfoWords : pinned_info(s);
+  // the kernels write their outcome words to device memory: a slot of the
+  // lane's deferred record, or a block of the workspace read back below
+  const int k0 = std::min(m, c);
+  const bool defer = tol <= 0.0 && out && out->deferring();
+  MPSV_CHECK(defer || inst_count() == 1, kEinval,
+             "lock-step instances need fixed-rank truncations (tol = 0)");
+  double* info = defer ? out->reserve(discarded, disc_stride,
+                                      k0 <= kJacobiMaxCols && jacobi_split(k0) > 0)
+                       : ws.alloc(SvdOutcomes::kInfoWords);
   double* sigbuf = ws.alloc((size_t)3 * std::max(m, c) + 8);
   const int k = std::min(m, c);
   // Preconditioning: Jacobi runs on the transpose of a triangular factor
@@ -738,9 +736,10 @@ int svd_truncate(hipStream_t s, Arena& ws, double* X, int m, int c, long ldx,
     double* Wg = use_lds ? nullptr : ws.alloc((size_t)mb * c);
     double* Jg = use_lds ? nullptr : ws.alloc((size_t)c * c);
     slot = prof_begin(s);
-    hipLaunchKernelGGL(jacobi_svd_kernel, dim3(1), dim3(NT), use_lds ? need : 0,
-                       s, B, mb, c, ldb, Wg, Jg, use_lds, cap, tol, g_max_sweeps,
-                       Vt, US, (long)mb, sigbuf, info);
+    hipLaunchKernelGGL(jacobi_svd_kernel, dim3(1, 1, inst_count()), dim3(NT),
+                       use_lds ? need : 0, s, B, mb, c, ldb, Wg, Jg, use_lds, cap,
+                       tol, g_max_sweeps, Vt, US, (long)mb, sigbuf, info,
+                       inst_off());
     MPSV_LAUNCHED();
   }
   {
@@ -750,14 +749,14 @@ int svd_truncate(hipStream_t s, Arena& ws, double* X, int m, int c, long ldx,
              8.0 * (2.0 * m * c + 2.0 * nn * nn));
   }
   int D;
-  if (df) {
+  if (defer) {
     // fixed rank: the kernels keep min(cap, k) whatever the values
     D = cap < k ? cap : k;
-    df->split.push_back(onchip && jacobi_split(k) > 0 ? 1 : 0);
-    if (discarded) df->disc.push_back({discarded, slot_i});
   } else {
+    double h[SvdOutcomes::kInfoWords];
+    MPSV_HIP(hipMemcpyAsync(h, shifted(info, lanes().first), sizeof(h),
+                            hipMemcpyDeviceToHost, s));
     MPSV_HIP(hipStreamSynchronize(s));
-    const volatile double* h = info;
     D = (int)h[0];
     if (discarded) *discarded = h[1];
     g_stats.jacobi_sweeps += (long)h[2];
@@ -767,10 +766,7 @@ int svd_truncate(hipStream_t s, Arena& ws, double* X, int m, int c, long ldx,
       throw Error(kEnumeric, "Jacobi SVD did not converge within " +
                                  std::to_string(g_max_sweeps) + " sweeps");
   }
-  if (sig) {
-    MPSV_HIP(hipMemcpyAsync(sig, sigbuf, (size_t)k * sizeof(double),
-                            hipMemcpyDeviceToDevice, s));
-  }
+  if (sig) copy_rows(s, sigbuf, 1, k, sig);
   if (onchip) {
     // V = R_1 (... (R_q W_D)) (c x D): the first application reads W_D = Wt^T
     // through a view, the last writes V^T straight into Vt; rows beyond the
@@ -785,7 +781,7 @@ int svd_truncate(hipStream_t s, Arena& ws, double* X, int m, int c, long ldx,
     if (Rf.empty()) copy_view(s, in, k, MatView{Vt, 1, c, 0}, c, D);
     // U Sigma = L_1 (... (L_p (B W_D))): m x D
     gemm(s, k, D, k, 1.0, CMatView{Rk, k, 1, 0}, CMatView{Wt, 1, k, 0}, 0.0,
-         MatView{US, D, 1, 0});
+         MatView{US, D, 1, 0}, 1, 0, &ws);
     for (int i = (int)Lf.size() - 1; i >= 0; --i)
       qr_apply_q_view(s, ws, Lf[i], CMatView{US, D, 1, 0}, k,
                       MatView{US, D, 1, 0}, D);

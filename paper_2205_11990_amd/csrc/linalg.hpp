@@ -69,44 +69,67 @@ void chunk_tops(hipStream_t s, double* X, long ld, int crows, int jb, int srows,
 void copy_view(hipStream_t s, CMatView in, int rows_in, MatView out, int rows,
                int cols);
 
+// Outcome words of the truncated SVDs of one lane (a stream driven by one
+// host thread), owned by whoever drives the lane (an engine keeps one per
+// stream it uses).  Each SVD's kernels write kInfoWords doubles of device
+// memory: [0] kept rank D, [1] relative discarded weight, [2] sweeps, [3]
+// converged, [4] rotation steps, [5] 1 if split workgroups failed to meet.
+//
+// Between begin() and end(), fixed-rank SVDs (tol <= 0, whose rank the host
+// knows in advance) write into a slot of the device ring instead of being
+// read back one by one, so the host never waits inside a compression sweep;
+// end() synchronises the stream, copies the used slots of every lock-step
+// instance back, checks convergence and the rendezvous of each, writes the
+// discarded weights to their host destinations and throws the first
+// failure.  cancel() synchronises and drops the record (error paths).
+// take()/resume() keep a closed record across the replays of a captured
+// graph, which write the same slots.
+class SvdOutcomes {
+ public:
+  static constexpr int kSlots = 4096;
+  static constexpr int kInfoWords = 8;
+  // ring: device, kSlots * kInfoWords doubles (per instance)
+  void bind(double* ring) { ring_ = ring; }
+  bool bound() const { return ring_ != nullptr; }
+  void begin();
+  void end(hipStream_t s);
+  void cancel(hipStream_t s) noexcept;
+  bool deferring() const { return on_ && rec_.used < kSlots; }
+  // reserves the next slot: its device words; the discarded weight goes to
+  // disc + i * disc_stride for instance i (disc may be null)
+  double* reserve(double* disc, long disc_stride, bool split);
+
+  struct Record {
+    int used = 0;
+    std::vector<std::pair<double*, int>> disc;
+    std::vector<long> disc_stride;
+    std::vector<char> split;
+  };
+  Record take();
+  void resume(const Record& r);
+
+ private:
+  double* ring_ = nullptr;
+  bool on_ = false;
+  Record rec_;
+};
+
 // Truncated SVD of the row-major m x c matrix X (leading dimension ldx).
 // Keeps D = min(cap, rank rule(tol)) singular triplets, D >= 1.
 // Outputs (device, row-major):
 //   Vt  : D x c,   rows = right singular vectors of the kept values
 //   US  : m x D,   columns = u_i * sigma_i (leading dimension ldus = D)
 //   sig : (optional, length >= min(m,c)) all singular values, descending
-// Returns D (the stream is synchronised to read it back) and the relative
-// discarded weight sqrt(sum_{i>D} s_i^2 / sum s_i^2) in *discarded.
-// X is overwritten.  Inside a deferred section of the stream (below) a call
-// with tol <= 0 returns without synchronising: D is then min(cap, m, c)
-// whatever the values, and *discarded is written when the section ends.
+// Returns D and the relative discarded weight sqrt(sum_{i>D} s_i^2 /
+// sum s_i^2) in *discarded.  X is overwritten.  With `out` deferring and
+// tol <= 0 the call returns without synchronising: D is then min(cap, m,
+// c) whatever the values and the discarded weight (disc_stride apart for
+// lock-step instances) is written when the deferred section ends.
+// Otherwise the stream is synchronised to read D back (one instance only).
 int svd_truncate(hipStream_t s, Arena& ws, double* X, int m, int c, long ldx,
                  int cap, double tol, double* Vt, double* US, double* sig,
-                 double* discarded);
-
-// Deferred read-back of the SVD outcomes on stream s.  Between begin and
-// end, fixed-rank calls (tol <= 0) only record where their outcome words
-// land (one pinned slot per call), so the host never waits for the device
-// inside a compression sweep.  svd_defer_end synchronises s, checks every
-// recorded call (convergence; the workgroup rendezvous of split launches),
-// writes the recorded discarded weights and throws the first failure.
-// svd_defer_cancel synchronises and drops the record (error paths).  The
-// pointers given as `discarded` must stay valid until the end.
-void svd_defer_begin(hipStream_t s);
-void svd_defer_end(hipStream_t s);
-void svd_defer_cancel(hipStream_t s) noexcept;
-
-// The record of a deferred section, kept across replays of a captured
-// graph: the replay writes the same pinned slots, so the record taken at
-// capture (svd_defer_take, which closes the section without
-// synchronising) is put back before each replay's svd_defer_end.
-struct SvdDeferRecord {
-  int used = 0;
-  std::vector<std::pair<double*, int>> disc;
-  std::vector<char> split;
-};
-SvdDeferRecord svd_defer_take(hipStream_t s);
-void svd_defer_resume(hipStream_t s, const SvdDeferRecord& r);
+                 double* discarded, SvdOutcomes* out = nullptr,
+                 long disc_stride = 0);
 
 // Device-side counters of the last factorisations (for diagnostics/tests).
 struct LinalgStats {

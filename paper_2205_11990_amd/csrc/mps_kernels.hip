@@ -9,6 +9,11 @@
 
 namespace mpsv {
 
+Lanes& lanes() {
+  static thread_local Lanes l;
+  return l;
+}
+
 namespace {
 
 inline int grid_for(long n) {
@@ -23,7 +28,10 @@ inline int grid_for(long n) {
        e += (long)gridDim.x * blockDim.x)
 
 __global__ void swap01_kernel(const double* in, int d0, int d1, long inner,
-                              double* out) {
+                              double* out, InstOff io) {
+  const long o_ = io.of(blockIdx.z);
+  in = shifted(in, o_);
+  out = shifted(out, o_);
   const long n = (long)d0 * d1 * inner;
   GRID_STRIDE(e, n) {
     long k = e % inner;
@@ -36,7 +44,10 @@ __global__ void swap01_kernel(const double* in, int d0, int d1, long inner,
 
 __global__ void copy2d_kernel(int rows, int cols, double alpha,
                               const double* src, long lds, double* dst,
-                              long ldd) {
+                              long ldd, InstOff io) {
+  const long o_ = io.of(blockIdx.z);
+  src = shifted(src, o_);
+  dst = shifted(dst, o_);
   const long n = (long)rows * cols;
   GRID_STRIDE(e, n) {
     long i = e / cols, j = e % cols;
@@ -45,7 +56,10 @@ __global__ void copy2d_kernel(int rows, int cols, double alpha,
 }
 
 __global__ void sum_physical_kernel(const double* in, int l, int r,
-                                    double* out) {
+                                    double* out, InstOff io) {
+  const long o_ = io.of(blockIdx.z);
+  in = shifted(in, o_);
+  out = shifted(out, o_);
   const long n = (long)l * r;
   GRID_STRIDE(e, n) {
     long a = e / r, b = e % r;
@@ -57,7 +71,12 @@ __global__ void sum_physical_kernel(const double* in, int l, int r,
 // for `inverse` 1/x with 0 where x <= d[0] * 1e-200 (d sorted descending, so
 // d[0] is the largest value: a zero of a rank-deficient cut gets 0)
 __global__ void scale_rows_kernel(const double* in, int rows, long len,
-                                  const double* d, int inverse, double* out) {
+                                  const double* d, int inverse, double* out,
+                                  InstOff io) {
+  const long o_ = io.of(blockIdx.z);
+  in = shifted(in, o_);
+  d = shifted(d, o_);
+  out = shifted(out, o_);
   const long n = (long)rows * len;
   const double floor = d[0] * 1e-200;
   GRID_STRIDE(e, n) {
@@ -67,14 +86,18 @@ __global__ void scale_rows_kernel(const double* in, int rows, long len,
   }
 }
 
-__global__ void identity_kernel(double* A, int n) {
+__global__ void identity_kernel(double* A, int n, InstOff io) {
+  A = shifted(A, io.of(blockIdx.z));
   const long total = (long)n * n;
   GRID_STRIDE(e, total) A[e] = (e / n == e % n) ? 1.0 : 0.0;
 }
 
 // out[b][t][a] = in[a][t][b] for an l x 2 x r core
 __global__ void reverse_core_kernel(const double* in, int l, int r,
-                                    double* out) {
+                                    double* out, InstOff io) {
+  const long o_ = io.of(blockIdx.z);
+  in = shifted(in, o_);
+  out = shifted(out, o_);
   const long n = 2L * l * r;
   GRID_STRIDE(e, n) {
     const long a = e % l, t = (e / l) % 2, b = e / (2L * l);
@@ -86,7 +109,10 @@ __global__ void reverse_core_kernel(const double* in, int l, int r,
 // position of (i, j) is the x bits then the v bits, each most significant
 // first, or least significant first for a reversed dimension.
 __global__ void chain_to_grid_kernel(const double* in, int Lx, int Lv, int rx,
-                                     int rv, double* out) {
+                                     int rv, double* out, InstOff io) {
+  const long o_ = io.of(blockIdx.z);
+  in = shifted(in, o_);
+  out = shifted(out, o_);
   const long n = 1L << (Lx + Lv);
   GRID_STRIDE(e, n) {
     const long i = e >> Lv, j = e & ((1L << Lv) - 1);
@@ -104,7 +130,10 @@ __global__ void chain_to_grid_kernel(const double* in, int Lx, int Lv, int rx,
 }
 
 __global__ void kron_embed_kernel(const double* A, int l, int P, int r, int d,
-                                  int mode, double* out) {
+                                  int mode, double* out, InstOff io) {
+  const long o_ = io.of(blockIdx.z);
+  A = shifted(A, o_);
+  out = shifted(out, o_);
   // out shape (l*d) x P x (r*d); write all entries (zeros off the identity)
   const long L = (long)l * d, R = (long)r * d;
   const long n = L * P * R;
@@ -124,7 +153,10 @@ __global__ void kron_embed_kernel(const double* A, int l, int P, int r, int d,
 }
 
 __global__ void diag_mpo_kernel(const double* E, int l, int r, double scale,
-                                double* W) {
+                                double* W, InstOff io) {
+  const long o_ = io.of(blockIdx.z);
+  E = shifted(E, o_);
+  W = shifted(W, o_);
   const long n = (long)l * 4 * r;
   GRID_STRIDE(e, n) {
     long b = e % r;
@@ -137,7 +169,10 @@ __global__ void diag_mpo_kernel(const double* E, int l, int r, double scale,
 }
 
 __global__ void mpo_left_matrix_kernel(const double* W, int wl, int wr,
-                                       double* Wmat) {
+                                       double* Wmat, InstOff io) {
+  const long o_ = io.of(blockIdx.z);
+  W = shifted(W, o_);
+  Wmat = shifted(Wmat, o_);
   const long n = (long)2 * wr * 2 * wl;
   GRID_STRIDE(e, n) {
     long col = e % (2 * wl);   // (b, i)
@@ -148,7 +183,11 @@ __global__ void mpo_left_matrix_kernel(const double* W, int wl, int wr,
   }
 }
 
-__global__ void deinterleave_kernel(const double* in, int L, double* out) {
+__global__ void deinterleave_kernel(const double* in, int L, double* out,
+                                    InstOff io) {
+  const long o_ = io.of(blockIdx.z);
+  in = shifted(in, o_);
+  out = shifted(out, o_);
   const long N = 1L << L;
   const long n = N * N;
   GRID_STRIDE(e, n) {
@@ -163,7 +202,11 @@ __global__ void deinterleave_kernel(const double* in, int L, double* out) {
   }
 }
 
-__global__ void count_nonfinite_kernel(const double* x, long n, int* flag) {
+__global__ void count_nonfinite_kernel(const double* x, long n, int* flag,
+                                       InstOff io) {
+  const long o_ = io.of(blockIdx.z);
+  x = shifted(x, o_);
+  flag = shifted(flag, o_);
   int bad = 0;
   GRID_STRIDE(e, n) {
     if (!isfinite(x[e])) bad = 1;
@@ -172,7 +215,10 @@ __global__ void count_nonfinite_kernel(const double* x, long n, int* flag) {
 }
 
 __global__ void sum_squares_kernel(const double* x, long n, double scale,
-                                   double* out) {
+                                   double* out, InstOff io) {
+  const long o_ = io.of(blockIdx.z);
+  x = shifted(x, o_);
+  out = shifted(out, o_);
   __shared__ double red[256];
   double acc = 0.0;
   for (long e = threadIdx.x; e < n; e += blockDim.x) acc += x[e] * x[e];
@@ -185,10 +231,19 @@ __global__ void sum_squares_kernel(const double* x, long n, double scale,
   if (threadIdx.x == 0) out[0] = scale * red[0];
 }
 
-__global__ void fill_kernel(double* x, long n, double v) {
+__global__ void fill_kernel(double* x, long n, double v, InstOff io) {
+  x = shifted(x, io.of(blockIdx.z));
   GRID_STRIDE(e, n) x[e] = v;
 }
-__global__ void fill_int_kernel(int* x, long n, int v) {
+__global__ void copy_doubles_kernel(double* dst, const double* src, long n,
+                                    InstOff io) {
+  const long o_ = io.of(blockIdx.z);
+  dst = shifted(dst, o_);
+  src = shifted(src, o_);
+  GRID_STRIDE(e, n) dst[e] = src[e];
+}
+__global__ void fill_int_kernel(int* x, long n, int v, InstOff io) {
+  x = shifted(x, io.of(blockIdx.z));
   GRID_STRIDE(e, n) x[e] = v;
 }
 
@@ -198,8 +253,8 @@ void swap01(hipStream_t s, const double* in, int d0, int d1, long inner,
             double* out) {
   long n = (long)d0 * d1 * inner;
   if (n <= 0) return;
-  hipLaunchKernelGGL(swap01_kernel, dim3(grid_for(n)), dim3(256), 0, s, in, d0,
-                     d1, inner, out);
+  hipLaunchKernelGGL(swap01_kernel, dim3(grid_for(n), 1, inst_count()), dim3(256), 0, s, in, d0,
+                     d1, inner, out, inst_off());
   MPSV_LAUNCHED();
 }
 
@@ -207,15 +262,15 @@ void copy2d(hipStream_t s, int rows, int cols, double alpha, const double* src,
             long lds, double* dst, long ldd) {
   long n = (long)rows * cols;
   if (n <= 0) return;
-  hipLaunchKernelGGL(copy2d_kernel, dim3(grid_for(n)), dim3(256), 0, s, rows,
-                     cols, alpha, src, lds, dst, ldd);
+  hipLaunchKernelGGL(copy2d_kernel, dim3(grid_for(n), 1, inst_count()), dim3(256), 0, s, rows,
+                     cols, alpha, src, lds, dst, ldd, inst_off());
   MPSV_LAUNCHED();
 }
 
 void sum_physical(hipStream_t s, const double* in, int l, int r, double* out) {
   long n = (long)l * r;
-  hipLaunchKernelGGL(sum_physical_kernel, dim3(grid_for(n)), dim3(256), 0, s,
-                     in, l, r, out);
+  hipLaunchKernelGGL(sum_physical_kernel, dim3(grid_for(n), 1, inst_count()), dim3(256), 0, s,
+                     in, l, r, out, inst_off());
   MPSV_LAUNCHED();
 }
 
@@ -223,88 +278,95 @@ void scale_rows(hipStream_t s, const double* in, int rows, long len,
                 const double* d, bool inverse, double* out) {
   const long n = (long)rows * len;
   if (n <= 0) return;
-  hipLaunchKernelGGL(scale_rows_kernel, dim3(grid_for(n)), dim3(256), 0, s, in,
-                     rows, len, d, inverse ? 1 : 0, out);
+  hipLaunchKernelGGL(scale_rows_kernel, dim3(grid_for(n), 1, inst_count()), dim3(256), 0, s, in,
+                     rows, len, d, inverse ? 1 : 0, out, inst_off());
   MPSV_LAUNCHED();
 }
 
 void identity(hipStream_t s, double* A, int n) {
   const long total = (long)n * n;
   if (total <= 0) return;
-  hipLaunchKernelGGL(identity_kernel, dim3(grid_for(total)), dim3(256), 0, s, A, n);
+  hipLaunchKernelGGL(identity_kernel, dim3(grid_for(total), 1, inst_count()), dim3(256), 0, s, A, n, inst_off());
   MPSV_LAUNCHED();
 }
 
 void reverse_core(hipStream_t s, const double* in, int l, int r, double* out) {
   const long n = 2L * l * r;
-  hipLaunchKernelGGL(reverse_core_kernel, dim3(grid_for(n)), dim3(256), 0, s,
-                     in, l, r, out);
+  hipLaunchKernelGGL(reverse_core_kernel, dim3(grid_for(n), 1, inst_count()), dim3(256), 0, s,
+                     in, l, r, out, inst_off());
   MPSV_LAUNCHED();
 }
 
 void chain_to_grid(hipStream_t s, const double* in, int Lx, int Lv, bool rx,
                    bool rv, double* out) {
   const long n = 1L << (Lx + Lv);
-  hipLaunchKernelGGL(chain_to_grid_kernel, dim3(grid_for(n)), dim3(256), 0, s,
-                     in, Lx, Lv, rx ? 1 : 0, rv ? 1 : 0, out);
+  hipLaunchKernelGGL(chain_to_grid_kernel, dim3(grid_for(n), 1, inst_count()), dim3(256), 0, s,
+                     in, Lx, Lv, rx ? 1 : 0, rv ? 1 : 0, out, inst_off());
   MPSV_LAUNCHED();
 }
 
 void kron_embed(hipStream_t s, const double* A, int l, int P, int r, int d,
                 int mode, double* out) {
   long n = (long)l * d * P * r * d;
-  hipLaunchKernelGGL(kron_embed_kernel, dim3(grid_for(n)), dim3(256), 0, s, A,
-                     l, P, r, d, mode, out);
+  hipLaunchKernelGGL(kron_embed_kernel, dim3(grid_for(n), 1, inst_count()), dim3(256), 0, s, A,
+                     l, P, r, d, mode, out, inst_off());
   MPSV_LAUNCHED();
 }
 
 void diag_mpo_site(hipStream_t s, const double* E, int l, int r, double scale,
                    double* W) {
   long n = (long)l * 4 * r;
-  hipLaunchKernelGGL(diag_mpo_kernel, dim3(grid_for(n)), dim3(256), 0, s, E, l,
-                     r, scale, W);
+  hipLaunchKernelGGL(diag_mpo_kernel, dim3(grid_for(n), 1, inst_count()), dim3(256), 0, s, E, l,
+                     r, scale, W, inst_off());
   MPSV_LAUNCHED();
 }
 
 void mpo_left_matrix(hipStream_t s, const double* W, int wl, int wr,
                      double* Wmat) {
   long n = (long)4 * wl * wr;
-  hipLaunchKernelGGL(mpo_left_matrix_kernel, dim3(grid_for(n)), dim3(256), 0, s,
-                     W, wl, wr, Wmat);
+  hipLaunchKernelGGL(mpo_left_matrix_kernel, dim3(grid_for(n), 1, inst_count()), dim3(256), 0, s,
+                     W, wl, wr, Wmat, inst_off());
   MPSV_LAUNCHED();
 }
 
 void deinterleave(hipStream_t s, const double* in, int L, double* out) {
   long n = 1L << (2 * L);
-  hipLaunchKernelGGL(deinterleave_kernel, dim3(grid_for(n)), dim3(256), 0, s,
-                     in, L, out);
+  hipLaunchKernelGGL(deinterleave_kernel, dim3(grid_for(n), 1, inst_count()), dim3(256), 0, s,
+                     in, L, out, inst_off());
   MPSV_LAUNCHED();
 }
 
 void count_nonfinite(hipStream_t s, const double* x, long n, int* flag) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(count_nonfinite_kernel, dim3(grid_for(n)), dim3(256), 0,
-                     s, x, n, flag);
+  hipLaunchKernelGGL(count_nonfinite_kernel, dim3(grid_for(n), 1, inst_count()), dim3(256), 0,
+                     s, x, n, flag, inst_off());
   MPSV_LAUNCHED();
 }
 
 void sum_squares(hipStream_t s, const double* x, long n, double scale,
                  double* out) {
-  hipLaunchKernelGGL(sum_squares_kernel, dim3(1), dim3(256), 0, s, x, n, scale,
-                     out);
+  hipLaunchKernelGGL(sum_squares_kernel, dim3(1, 1, inst_count()), dim3(256), 0, s, x, n, scale,
+                     out, inst_off());
   MPSV_LAUNCHED();
 }
 
 void fill(hipStream_t s, double* x, long n, double v) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n)), dim3(256), 0, s, x, n, v);
+  hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n), 1, inst_count()), dim3(256), 0, s, x, n, v, inst_off());
+  MPSV_LAUNCHED();
+}
+
+void copy_doubles(hipStream_t s, double* dst, const double* src, long n) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(copy_doubles_kernel, dim3(grid_for(n), 1, inst_count()), dim3(256), 0,
+                     s, dst, src, n, inst_off());
   MPSV_LAUNCHED();
 }
 
 void fill_int(hipStream_t s, int* x, long n, int v) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(fill_int_kernel, dim3(grid_for(n)), dim3(256), 0, s, x, n,
-                     v);
+  hipLaunchKernelGGL(fill_int_kernel, dim3(grid_for(n), 1, inst_count()), dim3(256), 0, s, x, n,
+                     v, inst_off());
   MPSV_LAUNCHED();
 }
 

@@ -59,6 +59,8 @@ void sum_squares(hipStream_t s, const double* x, long n, double scale,
                  double* out);
 
 void fill(hipStream_t s, double* x, long n, double v);
+// dst[0:n] = src[0:n] (device buffers of the current lanes' instances)
+void copy_doubles(hipStream_t s, double* dst, const double* src, long n);
 void fill_int(hipStream_t s, int* x, long n, int v);
 
 }  // namespace mpsv

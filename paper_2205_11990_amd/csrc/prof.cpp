@@ -48,7 +48,9 @@ void prof_end(hipStream_t s, int slot, int cls, double flops, double bytes) {
   if (slot < 0) return;
   std::lock_guard<std::mutex> lk(g_mu);
   MPSV_HIP(hipEventRecord(g_ev[2 * slot + 1], s));
-  g_rec[slot] = Rec{cls, flops, bytes};
+  // a launch over lock-step instances does the work of each of them
+  const double n = (double)inst_count();
+  g_rec[slot] = Rec{cls, flops * n, bytes * n};
 }
 
 void prof_read(int cls, long* launches, double* ms, double* flops,

@@ -17,7 +17,9 @@ enum KClass : int {
 
 bool prof_enabled();
 void prof_enable(bool on);  // enabling clears previous records
-// Returns an opaque slot (or -1 when disabled); call prof_end with it.
+// Returns an opaque slot (or -1 when disabled); call prof_end with it.  The
+// counts given to prof_end are per instance; a launch over several
+// lock-step instances (Lanes) records them times the instance count.
 int prof_begin(hipStream_t s);
 void prof_end(hipStream_t s, int slot, int cls, double flops, double bytes);
 // Synchronises the device and sums the records of class `cls`.

@@ -174,9 +174,16 @@ __device__ __forceinline__ void factor_block(double (&x)[RPL][CPW], int w,
 template <int CPW, int RPL>
 __global__ __launch_bounds__(FT) void qr_reg_factor_kernel(
     CMatView A, int m, int n, MatView R, double* __restrict__ V,
-    double* __restrict__ tau, Chunks ch) {
+    double* __restrict__ tau, Chunks ch, InstOff io) {
   __shared__ double vb[2 * 64 * RPL];
   __shared__ double tb[2];
+  {
+    const long o_ = io.of(blockIdx.z);
+    A = shifted(A, o_);
+    R = shifted(R, o_);
+    V = shifted(V, o_);
+    tau = shifted(tau, o_);
+  }
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   // workgroup y factors rows [y * ch.rows, ...) of A on its own; its R
   // block goes n rows further down R, its reflectors to its own slots
@@ -222,9 +229,16 @@ __global__ __launch_bounds__(FT) void qr_reg_factor_kernel(
 template <int CPG, int RPT>
 __global__ __launch_bounds__(FT) void qr_g16_factor_kernel(
     CMatView A, int m, int n, MatView R, double* __restrict__ V,
-    double* __restrict__ tau) {
+    double* __restrict__ tau, InstOff io) {
   __shared__ double vb[2 * 16 * RPT];
   __shared__ double tb[2];
+  {
+    const long o_ = io.of(blockIdx.z);
+    A = shifted(A, o_);
+    R = shifted(R, o_);
+    V = shifted(V, o_);
+    tau = shifted(tau, o_);
+  }
   const int tid = threadIdx.x, g = tid >> 4, lig = tid & 15;
   const int k = m < n ? m : n;
   double x[CPG][RPT];
@@ -427,9 +441,16 @@ __device__ __forceinline__ void blk_apply_panel(double (&x)[RPL][8], int p,
 template <int RPL>
 __global__ __launch_bounds__(FT) void qr_blk_factor_kernel(
     CMatView A, int m, int n, MatView R, double* __restrict__ V,
-    double* __restrict__ tau) {
+    double* __restrict__ tau, InstOff io) {
   __shared__ double vb[2 * 8 * 64 * RPL];
   __shared__ double tb[2 * 8];
+  {
+    const long o_ = io.of(blockIdx.z);
+    A = shifted(A, o_);
+    R = shifted(R, o_);
+    V = shifted(V, o_);
+    tau = shifted(tau, o_);
+  }
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   const int k = m < n ? m : n;
   const int npan = (k + 7) / 8;
@@ -466,8 +487,16 @@ __global__ __launch_bounds__(FT) void qr_blk_factor_kernel(
 template <int CPW, int RPL>
 __global__ __launch_bounds__(AT) void qr_reg_apply_kernel(
     const double* __restrict__ V, const double* __restrict__ tau, int m, int k,
-    CMatView Yin, int rows_in, MatView Yout, int p, int trans, Chunks ch) {
+    CMatView Yin, int rows_in, MatView Yout, int p, int trans, Chunks ch,
+    InstOff io) {
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  {
+    const long o_ = io.of(blockIdx.z);
+    V = shifted(V, o_);
+    tau = shifted(tau, o_);
+    Yin = shifted(Yin, o_);
+    Yout = shifted(Yout, o_);
+  }
   // workgroup row y applies the reflectors of chunk y to rows
   // [y * ch.rows, ...) (see qr_reg_factor_chunks)
   {
@@ -721,8 +750,8 @@ int cols_per_wave(int n) {
 template <int CPW, int RPL>
 void launch_factor(hipStream_t s, CMatView A, int m, int n, MatView R,
                    double* V, double* tau, Chunks ch, int nchunks) {
-  hipLaunchKernelGGL((qr_reg_factor_kernel<CPW, RPL>), dim3(1, nchunks), dim3(FT), 0, s,
-                     A, m, n, R, V, tau, ch);
+  hipLaunchKernelGGL((qr_reg_factor_kernel<CPW, RPL>), dim3(1, nchunks, inst_count()),
+                     dim3(FT), 0, s, A, m, n, R, V, tau, ch, inst_off());
 }
 
 template <int CPW, int RPL>
@@ -730,8 +759,9 @@ void launch_apply(hipStream_t s, const double* V, const double* tau, int m,
                   int k, CMatView Yin, int rows_in, MatView Yout, int p,
                   int trans, Chunks ch, int nchunks) {
   const int per_block = (AT / 64) * CPW;
-  hipLaunchKernelGGL((qr_reg_apply_kernel<CPW, RPL>), dim3(ceil_div(p, per_block), nchunks),
-                     dim3(AT), 0, s, V, tau, m, k, Yin, rows_in, Yout, p, trans, ch);
+  hipLaunchKernelGGL((qr_reg_apply_kernel<CPW, RPL>),
+                     dim3(ceil_div(p, per_block), nchunks, inst_count()), dim3(AT), 0, s,
+                     V, tau, m, k, Yin, rows_in, Yout, p, trans, ch, inst_off());
 }
 
 }  // namespace
@@ -768,12 +798,13 @@ void qr_reg_factor(hipStream_t s, CMatView A, int m, int n, MatView R,
   const bool blk = !g16 && m <= 128 && n <= 128;
 #define MPSV_G(C, Rr)                                                   \
   if (g16 && cpg == C && rpt == Rr)                                     \
-    hipLaunchKernelGGL((qr_g16_factor_kernel<C, Rr>), dim3(1), dim3(FT), 0, s, \
-                       A, m, n, R, V, tau); else
+    hipLaunchKernelGGL((qr_g16_factor_kernel<C, Rr>), dim3(1, 1, inst_count()), \
+                       dim3(FT), 0, s, A, m, n, R, V, tau, inst_off()); else
 #define MPSV_F(C, Rr)                                                   \
   if (cpw == C && rpl == Rr) launch_factor<C, Rr>(s, A, m, n, R, V, tau, Chunks{m, n}, 1); else
   if (blk)
-    hipLaunchKernelGGL((qr_blk_factor_kernel<2>), dim3(1), dim3(FT), 0, s, A, m, n, R, V, tau);
+    hipLaunchKernelGGL((qr_blk_factor_kernel<2>), dim3(1, 1, inst_count()), dim3(FT), 0, s,
+                       A, m, n, R, V, tau, inst_off());
   else
   MPSV_G(1, 2) MPSV_G(1, 4) MPSV_G(2, 2) MPSV_G(2, 4)
   MPSV_F(1, 1) MPSV_F(2, 1) MPSV_F(4, 1) MPSV_F(8, 1)
