@@ -23,10 +23,14 @@ Beside the metric line, three measurements of the same JSON object
            the field energy against an FP64 step from the same state.
   chi128   bond cap 128 on a 2^12 x 2^12 two-stream grid (fixed-chi mode):
            FP64 steps/s and the same mixed-precision comparison.
+  batched_metric  the metric's workload as one lock-step batch of 64
+           instances (mps_batch_*: every launch covers all of them):
+           aggregate steps/s against the single instance, and the rate of
+           the dominant kernel class.
   batched  64 Landau instances of a parameter sweep (k, alpha, 2^8..2^11
-           grids, chi in {16, 32, 48, 64}, physics mode) stepped together
-           by mps_step_batched: aggregate steps/s against stepping them one
-           after the other.
+           grids, chi in {16, 32, 48, 64}, fixed rank), one lock-step batch
+           per (grid, chi) shape: aggregate steps/s against stepping them one
+           after the other and against one stream per instance.
   serving  seeded Poisson arrivals (mean 20 requests/s) of Landau and
            two-stream solve requests (grids 2^8..2^10, chi in {32, 64},
            FP32 contraction, tol 1e-6 with every compression capped at chi),
@@ -91,16 +95,37 @@ def _blas_threads():
     return int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
 
 
-def cpu_baseline(w, mode, cores_host):
-    """The CPU MPS oracle, as it stands, timed on a bounded sample: one RK4
-    step of the same workload from the same MPS."""
+def oracle_start(w, mode):
+    """The workload's start state built by the oracle (the profile's product
+    MPS compressed to the problem's cap, plus the seeded perturbation in
+    fixed mode): host cores, handed to the GPU by mps_set_cores."""
     from oracle import mps as omps
+    p = w.problem
+    f = omps.chain_product_mps(omps.vector_mps(w.ax[0]), omps.vector_mps(w.bv[0]),
+                               p.Lx, p.Lv, p.order)
+    f = omps.compress_state(f, p.chi_max, p)
+    if mode == "fixed":
+        amp, cores = perturbation(w)
+        f = omps.compress_state(omps.add([(1.0, f), (amp, cores)]), p.chi_max, p)
+    return f
+
+
+def cpu_baseline(w, mode):
+    """The CPU MPS oracle, as it stands, timed on a bounded sample: one RK4
+    step of the same workload from its start state.  Also returns that start
+    state and the oracle's step from it (f on the grid, E), which the
+    precision leg compares the GPU's one-step results against."""
+    from oracle import mps as omps
+    f0 = oracle_start(w, mode)
     ops = omps.Operators(w.problem)
     t0 = time.perf_counter()
-    omps.rk4_step(cores_host, ops)
+    f1 = omps.rk4_step(f0, ops)
     dt = time.perf_counter() - t0
-    return {"value": 1.0 / dt, "unit": "steps/s", "cores": _blas_threads(), "kind": "oracle",
-            "sample": "1 RK4 step of the same workload from the same MPS (%.1f s of CPU time)" % dt}
+    ref = {"f": omps.to_dense(f1, w.problem), "E": omps.field_dense(f1, ops),
+           "field_energy": omps.moments(f1, ops)["field_energy"]}
+    return ({"value": 1.0 / dt, "unit": "steps/s", "cores": _blas_threads(), "kind": "oracle",
+             "sample": "1 RK4 step of the same workload from its start state "
+                       "(%.1f s of CPU time)" % dt}, f0, ref)
 
 
 # Peak of the unit each kernel class runs on (MI355X, dense FP64).
@@ -197,13 +222,18 @@ def _one_step(binding, problem, w, cores_host, precision):
     return st, p, f, E, sc
 
 
-def mixed_precision(binding, w, cores_host, steps, fp64_steps_per_s=None):
+def mixed_precision(binding, w, cores_host, steps, fp64_steps_per_s=None, oracle=None):
     """Reduced-precision contraction modes on a workload: steps/s from the
     same state, and the error of one step against an FP64 step from it
-    (QR/SVD/Poisson/moments FP64 in every mode)."""
+    (QR/SVD/Poisson/moments FP64 in every mode).  With `oracle` (the CPU MPS
+    oracle's step from the same state: f, E, field energy) every mode's
+    one-step error against the oracle is reported as well."""
     import torch
     ref, _, f64, E64, sc64 = _one_step(binding, w.problem, w, cores_host, 0)
     out = {}
+    if oracle is not None:
+        out["reference"] = "CPU MPS oracle (FP64), one RK4 step from the same state"
+        out["fp64"] = _errors(f64, E64, sc64, oracle)
     if fp64_steps_per_s is None:
         ref.set_cores(cores_host)
         ref.step(1)
@@ -232,7 +262,16 @@ def mixed_precision(binding, w, cores_host, steps, fp64_steps_per_s=None):
             "E_max_rel_err_one_step": float(np.abs(E - E64).max() / np.abs(E64).max()),
             "field_energy_rel_err_one_step": float(abs(sc["field_energy"] - sc64["field_energy"])
                                                    / abs(sc64["field_energy"]))}
+        if oracle is not None:
+            out[{1: "fp32", 2: "bf16"}[prec]]["vs_oracle"] = _errors(f, E, sc, oracle)
     return out
+
+
+def _errors(f, E, sc, ref):
+    return {"f_max_rel_err_one_step": float(np.abs(f - ref["f"]).max() / np.abs(ref["f"]).max()),
+            "E_max_rel_err_one_step": float(np.abs(E - ref["E"]).max() / np.abs(ref["E"]).max()),
+            "field_energy_rel_err_one_step": float(abs(sc["field_energy"] - ref["field_energy"])
+                                                   / abs(ref["field_energy"]))}
 
 
 def chi128_run(binding, steps):
@@ -317,30 +356,127 @@ def buneman_run(binding, steps):
     return out
 
 
-def batched(binding, count, steps):
-    """Aggregate steps/s of a parameter sweep stepped together, against the
-    same instances stepped one after the other."""
+def _class_rates(binding, run, steps):
+    """Per-class launch records of `steps` steps run by run() with HIP
+    events on the launching streams: the dominant class's rate and all
+    classes' (nominal FLOPs over summed launch time)."""
+    import torch
+    torch.cuda.synchronize()
+    binding.profile(True)
+    run()
+    torch.cuda.synchronize()
+    rec = binding.profile_read()
+    binding.profile(False)
+    dom = max(_CLASS_BOUND, key=lambda k: rec[k]["ms"])
+    r = rec[dom]
+    bound, peak = _CLASS_BOUND[dom]
+    ach = r["flops"] / (r["ms"] * 1e-3) / 1e12 if r["ms"] > 0 else 0.0
+    classes = {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
+                   "tflops": round(v["flops"] / (v["ms"] * 1e-3) / 1e12, 4) if v["ms"] > 0 else None}
+               for k, v in rec.items() if k in _CLASS_BOUND}
+    return {"bound": bound, "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+            "frac": ach / peak, "kernel": dom, "launches": r["launches"],
+            "avg_launch_us": 1000.0 * r["ms"] / max(r["launches"], 1),
+            "classes": classes,
+            "step_gflop": sum(v["flops"] for k, v in rec.items() if k in _CLASS_BOUND) / steps / 1e9}
+
+
+def metric_sweep(count):
+    """`count` instances of the metric's workload (two-stream 2^10 x 2^10,
+    interleaved, chi = 64, fixed-chi mode) with amplitudes
+    alpha = 1e-3 (1 + i/10) and the seeded perturbation of seed 2205 + i."""
+    ws = []
+    for i in range(count):
+        w = make_workload("fixed")
+        ax, bv = wl.two_stream_profiles(w.problem, 0.2, 1e-3 * (1 + 0.1 * i))
+        ws.append(wl.Workload("two_stream_%d" % i, w.problem, ax, bv, 10))
+    return ws
+
+
+def batched_metric(binding, count, steps, single_steps_per_s):
+    """The metric's workload as a lock-step batch of `count` instances: every
+    kernel launch covers all of them.  Aggregate steps/s (count x steps over
+    the timed window) against the single instance's, and the rate of the
+    dominant kernel class over the instances of its launches."""
+    import torch
+    ws = metric_sweep(count)
+    p = ws[0].problem
+    bt = binding.Batch([w.problem for w in ws], [(w.ax, w.bv) for w in ws])
+    perts = [wl.random_mps_cores(p.n_sites, p.chi_max, seed=2205 + i) for i in range(count)]
+    amps = [1e-6 * float(np.linalg.norm(w.ax) * np.linalg.norm(w.bv)) for w in ws]
+    bt.add_scaled(amps, perts)
+    bt.step(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bt.step(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    agg = count * steps / el
+    roof = _class_rates(binding, lambda: bt.step(1), 1)
+    roof["workgroups_per_launch_jacobi"] = count
+    out = {"workload": "%d lock-step instances of two-stream 2^10 x 2^10, interleaved, chi=64, "
+                       "C5, tol=0, D_F=4 (amplitudes 1e-3 (1 + i/10), seeded perturbations)" % count,
+           "instances": count, "steps_each": steps, "ms_per_batched_step": 1000.0 * el / steps,
+           "aggregate_steps_per_s": agg, "speedup_vs_single_instance": agg / single_steps_per_s,
+           "device_bytes": bt.instance(0).device_bytes(), "roofline": roof}
+    bt.free()
+    return out
+
+
+def batched_sweep(binding, count, steps):
+    """The 64-instance Landau parameter sweep (k, alpha, grids 2^8..2^11,
+    chi in {16, 32, 48, 64}, seeded) in fixed-rank mode (tol = 0, every
+    point capped): instances of one (grid, chi) shape form a lock-step
+    batch with one dt (the smallest stable one of its members); aggregate
+    steps/s of the batches against the same instances stepped one after
+    the other, and against one stream per instance (mps_step_batched)."""
     import torch
     ws = wl.landau_sweep(count)
+    for w in ws:
+        w.problem.tol, w.problem.level = 0.0, 5
+    groups = {}
+    for w in ws:
+        groups.setdefault((w.problem.Lx, w.problem.chi_max), []).append(w)
+    for g in groups.values():
+        dt = min(w.problem.dt for w in g)
+        for w in g:
+            w.problem.dt = dt
+    batches = [binding.Batch([w.problem for w in g], [(w.ax, w.bv) for w in g])
+               for g in groups.values()]
+    for b in batches:
+        b.step(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for b in batches:
+        b.step(steps)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    for b in batches:
+        b.free()
     states = [binding.MpsState(x.problem, x.ax, x.bv) for x in ws]
-    binding.step_batched(states, 1)  # warm-up (arenas, first factorisations)
+    for st in states:
+        st.step(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for st in states:
+        st.step(steps)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    binding.step_batched(states, 1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     binding.step_batched(states, steps)
     torch.cuda.synchronize()
-    tb = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    for s in states:
-        s.step(steps)
-    torch.cuda.synchronize()
-    ts = time.perf_counter() - t0
-    for s in states:
-        s.free()
-    return {"instances": count, "steps_each": steps,
-            "grids": "2^8..2^11", "chi": "16..64", "mode": "physics (C1, tol=1e-10)",
+    tt = time.perf_counter() - t0
+    for st in states:
+        st.free()
+    return {"instances": count, "steps_each": steps, "grids": "2^8..2^11",
+            "chi": "16, 32, 48, 64", "mode": "fixed rank (C5, tol=0)",
+            "lockstep_batches": len(groups),
             "aggregate_steps_per_s": count * steps / tb,
             "sequential_steps_per_s": count * steps / ts,
-            "speedup": ts / tb}
+            "streams_steps_per_s": count * steps / tt,
+            "speedup_vs_sequential": ts / tb, "speedup_vs_streams": tt / tb}
 
 
 def serving_run(binding, n_req, steps, seed=11990):
@@ -388,6 +524,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--mode", default="fixed", choices=["fixed", "physics"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch", type=int, default=64,
+                    help="instances of the lock-step batch of the metric's workload")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the mixed-precision, batched, serving and chi=128 measurements")
@@ -463,14 +601,22 @@ def main():
         roof["step_tflops"] = roof["step_gflop"] * value / 1e3
         roof["step_frac"] = roof["step_tflops"] / PEAK_FP64_TFLOPS
         print("[bench] roofline %s" % json.dumps(roof), file=sys.stderr, flush=True)
+    oracle_f0, oracle_ref = None, None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(w, args.mode, cores_host)
+        cpu, oracle_f0, oracle_ref = cpu_baseline(w, args.mode)
         print("[bench] cpu baseline %s" % cpu, file=sys.stderr, flush=True)
 
     extras = {}
     if not args.no_extras:
-        extras["mixed"] = mixed_precision(binding, w, cores_host, min(args.steps, 5),
-                                          fp64_steps_per_s=value)
+        extras["batched_metric"] = batched_metric(binding, args.batch, 3, value)
+        print("[bench] batched_metric %s" % json.dumps(extras["batched_metric"]),
+              file=sys.stderr, flush=True)
+        # the precision modes from the oracle's start state, each one-step
+        # result against the oracle's step from it (and against FP64)
+        extras["mixed"] = mixed_precision(binding, w,
+                                          oracle_f0 if oracle_f0 is not None else cores_host,
+                                          min(args.steps, 5), fp64_steps_per_s=value,
+                                          oracle=oracle_ref)
         print("[bench] mixed %s" % json.dumps(extras["mixed"]), file=sys.stderr, flush=True)
         extras["chi128"] = chi128_run(binding, 3)
         print("[bench] chi128 %s" % json.dumps(extras["chi128"]), file=sys.stderr, flush=True)
@@ -478,7 +624,7 @@ def main():
         print("[bench] buneman %s" % json.dumps(extras["buneman"]), file=sys.stderr, flush=True)
         extras["orderings"] = orderings(binding, 3)
         print("[bench] orderings %s" % json.dumps(extras["orderings"]), file=sys.stderr, flush=True)
-        extras["batched"] = batched(binding, 64, 3)
+        extras["batched"] = batched_sweep(binding, 64, 3)
         print("[bench] batched %s" % json.dumps(extras["batched"]), file=sys.stderr, flush=True)
         extras["serving"] = serving_run(binding, 24, 20)
         print("[bench] serving %s" % json.dumps(extras["serving"]), file=sys.stderr, flush=True)

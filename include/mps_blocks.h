@@ -67,11 +67,11 @@ mps_status mpsb_compress(int32_t n, const int32_t* mpo_bonds,
  * steps replay it, without the host work of issuing each launch; the
  * results are the same launches with the same arguments.  enable: 1 on,
  * 0 off, < 0 leaves it unchanged.  captures / replays: host
- * int64 counters or NULL.  Off while kernel timing (mpsb_profile) is on;
- * MPSV_STEP_GRAPH=0 in the environment turns it off for the process.
- * Currently switched off: the default is off and enable = 1 returns
- * MPS_EINVAL (a capture ended the host process with a segmentation fault
- * whose cause has not been found). */
+ * int64 counters or NULL.  Off by default and while kernel timing
+ * (mpsb_profile) is on; MPSV_STEP_GRAPH=0 in the environment turns it off
+ * for the process.  The recording is made on the state's own stream by the
+ * calling thread alone (both lanes), ordered after prior work on `stream`
+ * of mps_step; instances of a batch or plasma species refuse it. */
 mps_status mpsb_step_graph(mps_state* h, int32_t enable, int64_t* captures,
                            int64_t* replays);
 

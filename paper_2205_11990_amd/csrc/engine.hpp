@@ -153,15 +153,10 @@ class Engine {
   // ---- the hot path
   void step(hipStream_t s);
   // Steps of fixed shape (tol = 0, fixed dt) can replay a captured graph of
-  // the step's launches.  Switched off: the first capture on the GPU ended
-  // the host process with a segmentation fault whose cause has not been
-  // found, so enabling it raises an error.
-  void set_step_graph(bool on) {
-    MPSV_CHECK(!on, kEinval,
-               "captured step graphs are switched off (a capture ended the "
-               "process; cause not found)");
-    graph_on_ = on;
-  }
+  // the step's launches: the first step from a state layout runs eagerly
+  // (sizing every workspace), the second is recorded on the instance's own
+  // stream by one host thread (both lanes) and replayed, later ones replay.
+  void set_step_graph(bool on) { graph_on_ = on; }
   long graph_captures() const { return graph_captures_; }
   long graph_replays() const { return graph_replays_; }
   // A stream owned by this instance (batched stepping runs each instance on
