@@ -46,6 +46,22 @@ mps_status mpsb_svd_truncate(int32_t m, int32_t c, double* X, int32_t cap,
                              double tol, double* Vt, double* US, double* sig,
                              int32_t* D, double* discarded, hipStream_t stream);
 
+/* mpsb_svd_truncate without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same arguments, outputs and kernels, with
+ * every workspace taken from a fixed device array of 32 MiB per GPU, held
+ * from the first call on a device until the process ends.  Shapes: m <= 2048,
+ * c <= 2048 and min(m, c) <= 256, else MPS_EINVAL (a shape that still
+ * exceeds the array fails with MPS_ENOMEM).  All calls on one GPU share the
+ * array and would race if they overlapped; the library serialises them
+ * (a call holds the array until its stream has completed).  The array
+ * keeps the last call's contents: nothing in it needs to start at zero
+ * (what must be zero is cleared by the call's own kernels). */
+mps_status mpsb_svd_truncate_noalloc(int32_t m, int32_t c, double* X, int32_t cap,
+                                     double tol, double* Vt, double* US, double* sig,
+                                     int32_t* D, double* discarded,
+                                     hipStream_t stream);
+
 /* Compress an MPS (SI, "Canonicalization and Compression"): QR sweep left
  * to right then truncated SVD sweep right to left.  bonds_in / bonds_out:
  * host int32[n+1]; cores: packed device arrays (see mps_get_cores);

@@ -69,6 +69,7 @@ _SIGS = {
     "mpsb_gemm_prec": [_I32, _I32, _I32, _D, _P, _I64, _P, _I64, _D, _P, _I64, _I32, _P],
     "mpsb_qr": [_I32, _I32, _P, _P, _P],
     "mpsb_svd_truncate": [_I32, _I32, _P, _I32, _D, _P, _P, _P, _PI32, _PD, _P],
+    "mpsb_svd_truncate_noalloc": [_I32, _I32, _P, _I32, _D, _P, _P, _P, _PI32, _PD, _P],
     "mpsb_compress": [_I32, _PI32, _P, _PI32, _P, _I32, _D, _PI32, _P, _I64, _PD, _P],
     "mps_plasma_init": [_I32, _P, _P, _P, _P, _P, _P, _P],
     "mps_plasma_step": [_P, _I32, _P],
@@ -493,6 +494,19 @@ def svd_truncate(X, cap=0, tol=0.0, stream=None):
                                    _stream(stream)))
     d = D.value
     return Vt[:d * c].view(d, c), US[:m * d].view(m, d), sig, disc.value
+
+
+def svd_truncate_noalloc(X, Vt, US, sig, cap=0, tol=0.0, stream=None):
+    """mpsb_svd_truncate_noalloc on caller-allocated device buffers: X (m x c,
+    overwritten), Vt (>= kmax * c), US (>= m * kmax), sig (>= min(m, c)) with
+    kmax = min(m, c, cap); returns (D, discarded)."""
+    m, c = X.shape
+    D = ctypes.c_int32()
+    disc = ctypes.c_double()
+    _check(lib().mpsb_svd_truncate_noalloc(m, c, _ptr(X), int(cap), float(tol), _ptr(Vt),
+                                           _ptr(US), _ptr(sig), ctypes.byref(D),
+                                           ctypes.byref(disc), _stream(stream)))
+    return D.value, disc.value
 
 
 def compress(cores: Sequence[np.ndarray], cap=0, tol=0.0, mpo=None, stream=None):

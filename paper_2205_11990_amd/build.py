@@ -19,7 +19,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libmpsvlasov.so")
 ARCH = os.environ.get("MPSV_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["gemm.hip", "linalg.hip", "mps_kernels.hip", "engine.cpp", "capi.cpp", "prof.cpp", "jacobi.hip", "qr_reg.hip"]
+SOURCES = ["gemm.hip", "linalg.hip", "mps_kernels.hip", "engine.cpp", "capi.cpp", "prof.cpp",
+           "jacobi.hip", "qr_reg.hip", "noalloc.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,

@@ -23,6 +23,11 @@ class Arena {
 
   explicit Arena(size_t chunk_bytes = (size_t)256 << 20, int instances = 1)
       : chunk_(chunk_bytes), inst_(instances < 1 ? 1 : instances) {}
+  // An arena over a caller's device buffer: never allocates, and a request
+  // beyond the buffer fails with kEnomem.
+  Arena(void* base, size_t bytes) : chunk_(bytes), inst_(1), fixed_(true) {
+    chunks_.push_back({base, bytes});
+  }
   ~Arena() { release_all(); }
   Arena(const Arena&) = delete;
   Arena& operator=(const Arena&) = delete;
@@ -44,6 +49,10 @@ class Arena {
       ++cur_;
       off_ = 0;
     }
+    if (fixed_)
+      throw Error(kEnomem, "fixed scratch of " + std::to_string(chunk_) +
+                               " bytes exhausted by a request of " +
+                               std::to_string(bytes) + " bytes");
     if (inst_ > 1 && bytes > chunk_)
       throw Error(kEnomem, "device arena: a request of " + std::to_string(bytes) +
                                " bytes exceeds the per-instance chunk of " +
@@ -82,7 +91,10 @@ class Arena {
     return t * (size_t)inst_;
   }
   // largest single request (one chunk for lock-step instances)
-  size_t max_alloc_bytes() const { return inst_ > 1 ? chunk_ : SIZE_MAX; }
+  size_t max_alloc_bytes() const {
+    if (fixed_) return chunks_[0].size > off_ ? chunks_[0].size - off_ : 0;
+    return inst_ > 1 ? chunk_ : SIZE_MAX;
+  }
   int instances() const { return inst_; }
   // bytes between two instances' copies of a buffer
   long instance_stride() const { return (long)chunk_; }
@@ -96,6 +108,11 @@ class Arena {
     return false;
   }
   void release_all() {
+    if (fixed_) {
+      cur_ = 0;
+      off_ = 0;
+      return;
+    }
     for (auto& c : chunks_) (void)hipFree(c.ptr);
     chunks_.clear();
     cur_ = 0;
@@ -115,6 +132,7 @@ class Arena {
   std::vector<Chunk> chunks_;
   size_t chunk_;
   int inst_;
+  bool fixed_ = false;
   size_t cur_ = 0, off_ = 0, peak_ = 0;
 };
 

@@ -18,6 +18,7 @@
 #include "engine.hpp"
 #include "gemm.hpp"
 #include "linalg.hpp"
+#include "noalloc.hpp"
 #include "prof.hpp"
 
 struct mps_state {
@@ -454,6 +455,31 @@ mps_status mpsb_svd_truncate(int32_t m, int32_t c, double* X, int32_t cap,
     std::lock_guard<std::mutex> lk(g_blocks_mu);
     mpsv::Arena& ws = blocks().scratch();
     mpsv::ArenaScope sc(ws);
+    double dsc = 0;
+    *D = mpsv::svd_truncate(stream, ws, X, m, c, c, cap > 0 ? cap : INT_MAX,
+                            tol, Vt, US, sig, &dsc);
+    if (discarded) *discarded = dsc;
+    MPSV_HIP(hipStreamSynchronize(stream));
+  });
+}
+
+mps_status mpsb_svd_truncate_noalloc(int32_t m, int32_t c, double* X, int32_t cap,
+                                     double tol, double* Vt, double* US, double* sig,
+                                     int32_t* D, double* discarded,
+                                     hipStream_t stream) {
+  return guarded([&] {
+    MPSV_CHECK(m >= 1 && c >= 1 && X && Vt && US && D, mpsv::kEinval,
+               "bad SVD arguments");
+    MPSV_CHECK(tol >= 0, mpsv::kEinval, "tol must be >= 0");
+    MPSV_CHECK(m <= 2048 && c <= 2048 && std::min(m, c) <= 256, mpsv::kEinval,
+               "mpsb_svd_truncate_noalloc takes m, c <= 2048 and min(m, c) <= 256 "
+               "(its fixed device scratch is " +
+                   std::to_string(mpsv::kNoAllocScratchBytes >> 20) + " MiB)");
+    // one call at a time per process: every call on a GPU shares its
+    // scratch, and a call ends only after its stream has completed
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lk(mu);
+    mpsv::Arena ws(mpsv::noalloc_scratch(), mpsv::kNoAllocScratchBytes);
     double dsc = 0;
     *D = mpsv::svd_truncate(stream, ws, X, m, c, c, cap > 0 ? cap : INT_MAX,
                             tol, Vt, US, sig, &dsc);
