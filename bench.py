@@ -393,6 +393,27 @@ def metric_sweep(count):
     return ws
 
 
+def graph_run(binding, w, cores, steps, eager_steps_per_s):
+    """The metric's workload with captured step graphs: the first step from
+    the state runs eagerly, the second is recorded and replayed, the timed
+    ones replay."""
+    import torch
+    st = binding.MpsState(w.problem, w.ax, w.bv)
+    st.set_cores(cores)
+    st.step_graph(True)
+    st.step(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st.step(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    caps, reps = st.step_graph()
+    st.free()
+    return {"steps_per_s": steps / el, "ms_per_step": 1000.0 * el / steps,
+            "speedup_vs_eager": (steps / el) / eager_steps_per_s,
+            "captures": caps, "replays": reps}
+
+
 def batched_metric(binding, count, steps, single_steps_per_s):
     """The metric's workload as a lock-step batch of `count` instances: every
     kernel launch covers all of them.  Aggregate steps/s (count x steps over
@@ -446,9 +467,21 @@ def batched_sweep(binding, count, steps):
     for b in batches:
         b.step(1)
     torch.cuda.synchronize()
+    # the batches of different shapes side by side: one host thread and
+    # stream each
+    import threading
+    streams = [torch.cuda.Stream() for _ in batches]
+
+    def run(b, st):
+        with torch.cuda.stream(st):
+            b.step(steps)
+
     t0 = time.perf_counter()
-    for b in batches:
-        b.step(steps)
+    th = [threading.Thread(target=run, args=(b, st)) for b, st in zip(batches, streams)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
     for b in batches:
@@ -608,6 +641,8 @@ def main():
 
     extras = {}
     if not args.no_extras:
+        extras["graph"] = graph_run(binding, w, cores_host, min(args.steps, 5), value)
+        print("[bench] graph %s" % json.dumps(extras["graph"]), file=sys.stderr, flush=True)
         extras["batched_metric"] = batched_metric(binding, args.batch, 3, value)
         print("[bench] batched_metric %s" % json.dumps(extras["batched_metric"]),
               file=sys.stderr, flush=True)

@@ -29,6 +29,18 @@ mps_status mpsb_gemm_prec(int32_t M, int32_t N, int32_t K, double alpha,
                           int64_t ldb, double beta, double* C, int64_t ldc,
                           int32_t precision, hipStream_t stream);
 
+/* Strided batched GEMM: C[b] = alpha A[b] B[b] + beta C[b] for b < batch,
+ * element (i, j) of operand X[b] at X + b*xbs + i*xrs + j*xcs (device,
+ * strides in elements; A is M x K, B is K x N, C is M x N).  The contraction
+ * kernel of the MPO x MPS products (SI, "Matrix-vector multiplication");
+ * precision as in mpsb_gemm_prec.  Synchronises the stream. */
+mps_status mpsb_gemm_strided(int32_t M, int32_t N, int32_t K, double alpha,
+                             const double* A, int64_t ars, int64_t acs, int64_t abs_,
+                             const double* B, int64_t brs, int64_t bcs, int64_t bbs,
+                             double beta, double* C, int64_t crs, int64_t ccs,
+                             int64_t cbs, int32_t batch, int32_t precision,
+                             hipStream_t stream);
+
 /* Householder QR of A (m x n, device, overwritten): on return the upper
  * trapezoid of A holds R (min(m,n) x n); if Q is not NULL it receives the
  * thin factor Q (m x min(m,n), device).  Used by the QR left sweep (SI,

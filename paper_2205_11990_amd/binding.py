@@ -68,6 +68,8 @@ _SIGS = {
     "mpsb_gemm": [_I32, _I32, _I32, _D, _P, _I64, _P, _I64, _D, _P, _I64, _P],
     "mpsb_gemm_prec": [_I32, _I32, _I32, _D, _P, _I64, _P, _I64, _D, _P, _I64, _I32, _P],
     "mpsb_qr": [_I32, _I32, _P, _P, _P],
+    "mpsb_gemm_strided": [_I32, _I32, _I32, _D, _P, _I64, _I64, _I64, _P, _I64, _I64, _I64,
+                          _D, _P, _I64, _I64, _I64, _I32, _I32, _P],
     "mpsb_svd_truncate": [_I32, _I32, _P, _I32, _D, _P, _P, _P, _PI32, _PD, _P],
     "mpsb_svd_truncate_noalloc": [_I32, _I32, _P, _I32, _D, _P, _P, _P, _PI32, _PD, _P],
     "mpsb_compress": [_I32, _PI32, _P, _PI32, _P, _I32, _D, _PI32, _P, _I64, _PD, _P],
@@ -465,6 +467,16 @@ def gemm(A, B, alpha=1.0, beta=0.0, C=None, stream=None, precision=0):
         C = torch.zeros(M, N, dtype=torch.float64, device="cuda")
     _check(lib().mpsb_gemm_prec(M, N, K, alpha, _ptr(A), K, _ptr(B), N, beta, _ptr(C), N,
                                 int(precision), _stream(stream)))
+    return C
+
+
+def gemm_strided(M, N, K, alpha, A, a_strides, B, b_strides, beta, C, c_strides,
+                 batch=1, precision=0, stream=None):
+    """mpsb_gemm_strided on device tensors; strides (row, col, batch) in
+    elements."""
+    _check(lib().mpsb_gemm_strided(M, N, K, float(alpha), _ptr(A), *a_strides, _ptr(B),
+                                   *b_strides, float(beta), _ptr(C), *c_strides, int(batch),
+                                   int(precision), _stream(stream)))
     return C
 
 

@@ -419,6 +419,26 @@ mps_status mpsb_gemm_prec(int32_t M, int32_t N, int32_t K, double alpha,
   });
 }
 
+mps_status mpsb_gemm_strided(int32_t M, int32_t N, int32_t K, double alpha,
+                             const double* A, int64_t ars, int64_t acs, int64_t abs_,
+                             const double* B, int64_t brs, int64_t bcs, int64_t bbs,
+                             double beta, double* C, int64_t crs, int64_t ccs,
+                             int64_t cbs, int32_t batch, int32_t precision,
+                             hipStream_t stream) {
+  return guarded([&] {
+    MPSV_CHECK(M >= 0 && N >= 0 && K >= 0 && batch >= 0, mpsv::kEinval, "negative size");
+    MPSV_CHECK(A && B && C, mpsv::kEinval, "NULL operand");
+    MPSV_CHECK(precision == MPS_PREC_FP64 || precision == MPS_PREC_FP32_CONTRACT ||
+                   precision == MPS_PREC_BF16_CONTRACT,
+               mpsv::kEinval, "unknown precision");
+    std::lock_guard<std::mutex> lk(g_blocks_mu);
+    mpsv::gemm(stream, M, N, K, alpha, mpsv::CMatView{A, ars, acs, abs_},
+               mpsv::CMatView{B, brs, bcs, bbs}, beta, mpsv::MatView{C, crs, ccs, cbs},
+               batch, (int)precision, &blocks().scratch());
+    MPSV_HIP(hipStreamSynchronize(stream));
+  });
+}
+
 mps_status mpsb_qr(int32_t m, int32_t n, double* A, double* Q,
                    hipStream_t stream) {
   return guarded([&] {

@@ -102,6 +102,126 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(
       }
 }
 
+// Large tiles for the big contractions (the MPO x MPS products of the
+// field term at bond cap 128): a 128 x 128 output tile per workgroup of 256
+// threads, four waves in a 2 x 2 arrangement, each owning 64 x 64 = 4 x 4
+// blocks of v_mfma_f64_16x16x4f64 (16 accumulators, 64 doubles per lane).
+// K advances in steps of 16 through two LDS buffers: the global loads of
+// step t + 1 are in flight while the matrix cores work on step t, and one
+// barrier per step separates the buffers.  AK: A's k index is contiguous
+// (row-major A); BNF: B's n index is contiguous (row-major B); the loads of
+// each thread walk the contiguous index.
+constexpr int TB = 128, TK = 16, TLD = TB + 2;
+
+template <int AK, int BNF>
+__global__ __launch_bounds__(NT, 2) void gemm_f64_t128_kernel(
+    int M, int N, int K, double alpha, const double* __restrict__ A, long ars,
+    long acs, long abs_, const double* __restrict__ B, long brs, long bcs,
+    long bbs, double beta, double* __restrict__ C, long crs, long ccs, long cbs,
+    int nsplit, int kchunk, int zper, InstOff io) {
+  __shared__ double As[2][TK][TLD];
+  __shared__ double Bs[2][TK][TLD];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const long o_ = io.of(blockIdx.z / zper);
+  A = shifted(A, o_);
+  B = shifted(B, o_);
+  C = shifted(C, o_);
+  const int zb = blockIdx.z % zper;
+  const long bz = zb / nsplit;
+  const int split = zb % nsplit;
+  const int m0 = blockIdx.y * TB, n0 = blockIdx.x * TB;
+  A += bz * abs_;
+  B += bz * bbs;
+  C += bz * cbs + (long)split * M * N * (nsplit > 1 ? 1 : 0);
+  const int kbeg = split * kchunk;
+  const int kend = (kbeg + kchunk < K) ? kbeg + kchunk : K;
+  const int nt = (kend - kbeg + TK - 1) / TK;
+
+  // each thread stages 8 values of A and 8 of B per step: along the
+  // contiguous index of its operand, 8 consecutive elements
+  //   A k-fast: row ra = tid / 2, k = (tid % 2) * 8 + e; else k = tid / 16,
+  //   row = (tid % 16) * 8 + e.  B n-fast: k = tid / 16, col = (tid % 16) * 8
+  //   + e; else col = tid / 2, k = (tid % 2) * 8 + e.
+  double ra[8], rb[8];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      int r, k;
+      if (AK) { r = tid >> 1; k = ((tid & 1) << 3) + e; }
+      else { k = tid >> 4; r = ((tid & 15) << 3) + e; }
+      const int gr = m0 + r, gk = k0 + k;
+      ra[e] = (gr < M && gk < kend) ? A[(long)gr * ars + (long)gk * acs] : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      int c, k;
+      if (BNF) { k = tid >> 4; c = ((tid & 15) << 3) + e; }
+      else { c = tid >> 1; k = ((tid & 1) << 3) + e; }
+      const int gc = n0 + c, gk = k0 + k;
+      rb[e] = (gc < N && gk < kend) ? B[(long)gk * brs + (long)gc * bcs] : 0.0;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      if (AK) As[buf][((tid & 1) << 3) + e][tid >> 1] = ra[e];
+      else As[buf][tid >> 4][((tid & 15) << 3) + e] = ra[e];
+      if (BNF) Bs[buf][tid >> 4][((tid & 15) << 3) + e] = rb[e];
+      else Bs[buf][((tid & 1) << 3) + e][tid >> 1] = rb[e];
+    }
+  };
+
+  dbl4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+
+  if (nt > 0) {
+    load(kbeg);
+    store(0);
+  }
+  __syncthreads();
+  for (int t = 0; t < nt; ++t) {
+    const int buf = t & 1;
+    if (t + 1 < nt) load(kbeg + (t + 1) * TK);
+#pragma unroll
+    for (int kk = 0; kk < TK; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[buf][kr][wm * 64 + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[buf][kr][wn * 64 + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (t + 1 < nt) store(buf ^ 1);
+    __syncthreads();
+  }
+
+  // D layout of the 16x16 f64 block: lane l, item r -> row 4*r + l/16, col l%16
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gr = m0 + wm * 64 + i * 16 + 4 * r + (lane >> 4);
+        const int gc = n0 + wn * 64 + j * 16 + (lane & 15);
+        if (gr < M && gc < N) {
+          double* cp = C + (long)gr * crs + (long)gc * ccs;
+          const double v = alpha * acc[i][j][r];
+          *cp = (beta == 0.0) ? v : v + beta * (*cp);
+        }
+      }
+}
+
 // Reduced-precision contraction variants (the MPS problem's precision modes
 // 1 and 2): the FP64 operands are rounded as they are staged in LDS, to
 // FP32 (MODE 1) or to BF16 (MODE 2: to FP32, then to the nearest BF16, ties
@@ -259,14 +379,19 @@ void gemm(hipStream_t s, int M, int N, int K, double alpha, CMatView A,
   }
   const int a_kfast = (A.cs == 1) ? 1 : 0;
   const int b_nfast = (B.cs == 1) ? 1 : 0;
-  const long tiles = (long)ceil_div(N, BN) * ceil_div(M, BM);
   const int ninst = inst_count();
+  // FP64 products with at least two 128 x 128 tiles per compute unit take
+  // the large tiles
+  const bool big = prec == 0 && M >= TB && N >= TB && K >= TK &&
+                   (long)ceil_div(N, TB) * ceil_div(M, TB) * batch >= 512;
+  const int tm = big ? TB : BM, tn = big ? TB : BN;
+  const long tiles = (long)ceil_div(N, tn) * ceil_div(M, tm);
   // split K when the output alone cannot fill the chip; the partial
   // products live in the caller's workspace (none given: no split).  The
   // choice ignores lock-step instances, so that every instance sums in the
   // order a stand-alone state does.
   int nsplit = 1;
-  if (ws && K >= 4 * BK * 4 && tiles * batch < 256) {
+  if (!big && ws && K >= 4 * BK * 4 && tiles * batch < 256) {
     long want = 512 / (tiles * batch);
     long maxk = K / (4 * BK);
     const long fit = (long)(ws->max_alloc_bytes() / sizeof(double)) /
@@ -279,9 +404,18 @@ void gemm(hipStream_t s, int M, int N, int K, double alpha, CMatView A,
   for (int b0 = 0; b0 < batch; b0 += bmax) {
     int nb = batch - b0 < bmax ? batch - b0 : bmax;
     const int zper = nb * nsplit;
-    dim3 grid(ceil_div(N, BN), ceil_div(M, BM), zper * ninst);
+    dim3 grid(ceil_div(N, tn), ceil_div(M, tm), zper * ninst);
     const int slot = prof_begin(s);
-    if (nsplit == 1) {
+    if (big && nsplit == 1) {
+      auto k = a_kfast ? (b_nfast ? gemm_f64_t128_kernel<1, 1> : gemm_f64_t128_kernel<1, 0>)
+                       : (b_nfast ? gemm_f64_t128_kernel<0, 1> : gemm_f64_t128_kernel<0, 0>);
+      hipLaunchKernelGGL(k, grid, dim3(NT), 0, s, M, N, K, alpha,
+                         A.p + (long)b0 * A.bs, A.rs, A.cs, A.bs,
+                         B.p + (long)b0 * B.bs, B.rs, B.cs, B.bs, beta,
+                         C.p + (long)b0 * C.bs, C.rs, C.cs, C.bs, 1, K, zper,
+                         inst_off());
+      MPSV_LAUNCHED();
+    } else if (nsplit == 1) {
       hipLaunchKernelGGL(prec == 2 ? gemm_f32acc_kernel<2>
                          : prec == 1 ? gemm_f32acc_kernel<1> : gemm_f64_kernel, grid,
                          dim3(NT), 0, s, M, N, K, alpha,

@@ -40,6 +40,34 @@ def test_gemm_matches_numpy(B, M, N, K):
     assert np.abs(out - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max()) * np.sqrt(K)
 
 
+@pytest.mark.parametrize("M,N,K,batch,at,bt", [
+    (4096, 2048, 64, 1, False, False), (4100, 2050, 37, 1, False, False),
+    (4096, 2048, 128, 1, True, False), (2049, 4097, 48, 1, False, True),
+    (2048, 2048, 33, 1, True, True), (2048, 1024, 128, 4, False, False),
+    (20480, 256, 128, 1, False, False), (1000, 999, 17, 3, True, True)])
+def test_gemm_strided_matches_numpy(B, M, N, K, batch, at, bt):
+    """Strided batched GEMM with either operand transposed (read through its
+    strides), ragged sizes and several batch entries; shapes with enough
+    128 x 128 tiles take the large-tile kernel."""
+    import torch
+    _say("gemm strided %d %d %d batch %d at=%d bt=%d" % (M, N, K, batch, at, bt))
+    rng = np.random.default_rng(M + N + K + batch)
+    A = rng.standard_normal((batch, M, K))
+    Bm = rng.standard_normal((batch, K, N))
+    C0 = rng.standard_normal((batch, M, N))
+    # stored transposed when asked: the kernel reads element (i, k) of A at
+    # i*ars + k*acs
+    Ad = torch.from_numpy(np.ascontiguousarray(A.transpose(0, 2, 1) if at else A)).cuda()
+    Bd = torch.from_numpy(np.ascontiguousarray(Bm.transpose(0, 2, 1) if bt else Bm)).cuda()
+    Cd = torch.from_numpy(C0.copy()).cuda()
+    a_str = (1, M, M * K) if at else (K, 1, M * K)
+    b_str = (1, K, K * N) if bt else (N, 1, K * N)
+    out = B.gemm_strided(M, N, K, 0.7, Ad, a_str, Bd, b_str, -1.3, Cd, (N, 1, M * N),
+                         batch=batch).cpu().numpy()
+    ref = 0.7 * np.einsum("bik,bkj->bij", A, Bm) - 1.3 * C0
+    assert np.abs(out - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max()) * np.sqrt(K)
+
+
 @pytest.mark.parametrize("M,N,K", [(1, 1, 1), (7, 5, 3), (64, 64, 16), (65, 130, 33),
                                    (300, 17, 129), (16, 1000, 2)])
 def test_gemm_fp32_contract_matches_fp32_rounded_product(B, M, N, K):
