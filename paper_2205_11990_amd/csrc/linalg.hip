@@ -662,9 +662,10 @@ int svd_truncate(hipStream_t s, Arena& ws, double* X, int m, int c, long ldx,
   // X^T (m < c), then alternately of B^T and B, until
   //   X = L_1 ... L_p  B  (R_1 ... R_q)^T,   B upper triangular (k x k).
   // Jacobi on B^T gives W Sigma (W: right singular vectors of B), so
-  //   V = R_1 (... (R_q W)),   U Sigma = L_1 (... (L_p (B W))).
+  //   V = R_1 (... (R_q W)),   U Sigma = L_1 (... (L_p (B W))) = X V.
   // Each extra pair of factorisations moves B closer to diagonal and saves
-  // Jacobi sweeps.  The rotations are never accumulated.
+  // Jacobi sweeps.  The rotations are never accumulated, and U Sigma of the
+  // kept values is formed as X V_D by one GEMM (X is read, not modified).
   const bool onchip = k <= kJacobiMaxCols;
   const int mode = (m >= c) ? 0 : 1;
   QrFactor qf;  // used by the large-matrix path
@@ -682,8 +683,10 @@ int svd_truncate(hipStream_t s, Arena& ws, double* X, int m, int c, long ldx,
     double* Bk = ws.alloc((size_t)k * k);
     double* Bn = ws.alloc((size_t)k * k);
     if (mode == 0) {
+      // read through a view: X itself stays intact for U Sigma = X V below
       Lf.emplace_back();
-      qr_factor(s, ws, X, m, c, ldx, Lf.back(), MatView{Bk, k, 1, 0});
+      qr_factor_view(s, ws, CMatView{X, ldx, 1, 0}, m, c, Lf.back(),
+                     MatView{Bk, k, 1, 0});
       upper = true;
     } else {
       // X^T = Q1 R1 read through a transposed view; B = R1^T (lower)
@@ -779,12 +782,12 @@ int svd_truncate(hipStream_t s, Arena& ws, double* X, int m, int c, long ldx,
       in = CMatView{Y, D, 1, 0};
     }
     if (Rf.empty()) copy_view(s, in, k, MatView{Vt, 1, c, 0}, c, D);
-    // U Sigma = L_1 (... (L_p (B W_D))): m x D
-    gemm(s, k, D, k, 1.0, CMatView{Rk, k, 1, 0}, CMatView{Wt, 1, k, 0}, 0.0,
+    // U Sigma = X V_D (m x D) by one GEMM from the untouched X: the
+    // projection of X on the kept right singular vectors, the same product
+    // as L_1 (... (L_p (B W_D))) without applying the left reflectors (the
+    // left factorisations only serve as preconditioners)
+    gemm(s, m, D, c, 1.0, CMatView{X, ldx, 1, 0}, CMatView{Vt, 1, c, 0}, 0.0,
          MatView{US, D, 1, 0}, 1, 0, &ws);
-    for (int i = (int)Lf.size() - 1; i >= 0; --i)
-      qr_apply_q_view(s, ws, Lf[i], CMatView{US, D, 1, 0}, k,
-                      MatView{US, D, 1, 0}, D);
   } else if (m > c) {
     // US rows [0, c) hold U_R Sigma (leading dimension D): US = Q [U_R Sigma; 0]
     fill_rows_zero(s, US, c, m, D, D);
