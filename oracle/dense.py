@@ -20,10 +20,15 @@ The same scheme the MPS method discretises, evaluated on the full grid:
   "First Derivative, Centered, Zero Gradient Boundary Conditions").
 * Left Riemann sum for integrals (SI, "Integration").
 * Collisions (Methods, "Collision Operator"): the Dougherty operator
-  nu d/dv [(v - v0) f + vth^2 df/dv].  Reading: v0 and vth are fixed
-  parameters of the species (the drift and thermal speed its CFL term
-  uses), not moments recomputed from f, so the operator is linear; both
-  derivatives are the zero-gradient central difference in v.
+  nu d/dv [(v - v0) f + vth^2 df/dv] with v0 the species' average velocity
+  and vth its thermal velocity.  Reading: both are the local moments of f at
+  each x (left Riemann sums like the density): n = dv sum_j f, v0 = dv sum_j
+  v_j f / n, vth^2 = dv sum_j v_j^2 f / n - v0^2, recomputed from every RK
+  stage's state, so the operator conserves density, momentum and energy up
+  to the discretisation; where n = 0 the drift and temperature are taken as
+  0.  A second model (coll_model = 1) keeps v0 and vth as fixed parameters
+  of the species (a linearisation about one Maxwellian).  Both derivatives
+  are the zero-gradient central difference in v.
 * Several species (Methods, the Landau / Buneman / shock set-ups): each
   species s has its own v grid and q_s/m_s and all share x and E; Poisson
   reads Laplacian(phi) = -sum_s q_s n_s (normalised units; the
@@ -120,10 +125,31 @@ def field(F: np.ndarray, p) -> np.ndarray:
     return poisson_field(density(F, p.dv), p.dx)
 
 
-def collision(F: np.ndarray, p) -> np.ndarray:
-    """nu Dv[(v - v0) F + vth^2 Dv F] (Dougherty, fixed v0 and vth)."""
+def collision_moments(F: np.ndarray, p):
+    """Local drift v0(x) and thermal speed squared vth^2(x) of F: n = dv sum
+    F, v0 = dv sum v F / n, vth^2 = dv sum v^2 F / n - v0^2 (0 where n = 0)."""
     v = p.v()
-    G = (v - p.nu_v0)[None, :] * F + p.nu_vth ** 2 * ddv(F, p.dv)
+    n = p.dv * F.sum(axis=1)
+    P = p.dv * (F * v[None, :]).sum(axis=1)
+    W = p.dv * (F * (v * v)[None, :]).sum(axis=1)
+    ok = n != 0.0
+    v0 = np.zeros_like(n)
+    v0[ok] = P[ok] / n[ok]
+    T = np.zeros_like(n)
+    T[ok] = W[ok] / n[ok] - v0[ok] ** 2
+    return v0, T
+
+
+def collision(F: np.ndarray, p) -> np.ndarray:
+    """nu Dv[(v - v0) F + vth^2 Dv F] (Dougherty): v0, vth^2 the local
+    moments of F (coll_model 0), or the species' fixed parameters
+    (coll_model 1)."""
+    v = p.v()
+    if getattr(p, "coll_model", 0) == 1:
+        G = (v - p.nu_v0)[None, :] * F + p.nu_vth ** 2 * ddv(F, p.dv)
+    else:
+        v0, T = collision_moments(F, p)
+        G = (v[None, :] - v0[:, None]) * F + T[:, None] * ddv(F, p.dv)
     return p.nu * ddv(G, p.dv)
 
 

@@ -48,10 +48,18 @@ Readings where the paper is silent or garbled:
   the k's, P4 each k, P5 each term of a k.  Every point truncates with tol;
   level C_l caps P1..P_l at chi (C1: only the final state is capped).
 * The field MPS is compressed with tol and an optional cap D_F.
-* Collisions: the Dougherty operator with the species' fixed drift v0 and
-  thermal speed vth, nu Dv (diag(v - v0) + vth^2 Dv) with Dv the
-  zero-gradient central difference (Methods, Collision Operator); its term
-  of a k is compressed at P5 like the other two.
+* Collisions: the Dougherty operator nu Dv (diag(v - v0) + vth^2 Dv) with
+  Dv the zero-gradient central difference (Methods, Collision Operator).
+  v0 and vth are the species' average and thermal velocity: the local
+  moments of the state at each x, n = <1, g>_v, v0 = <v, g>_v / n,
+  vth^2 = <v^2, g>_v / n - v0^2 (0 where n = 0), taken from the x-MPS of
+  the three contractions on the grid of x, each brought back to an x-MPS
+  (iterated SVD with relative cut 1e-14 when tol > 0, exact when tol = 0)
+  and compressed like the field (cap D_F, tol).  Since v0 and vth do not
+  depend on v, C g = nu Dv diag(v) g - nu (diag(v0) (x) Dv) g +
+  nu (diag(vth^2) (x) Dv Dv) g: three terms of a k, each compressed at P5.
+  The alternative model coll_model = 1 keeps v0 and vth fixed parameters
+  of the species, one term nu Dv (diag(v - v0) + vth^2 Dv) g.
 * Several species: rho = sum_s (-q_s) n_s is formed exactly (direct sum)
   and E = compress(-G rho) uses the first species' D_F and tol.
 * Centre-first compression: the SVD is of the centre site (first v site)
@@ -755,16 +763,29 @@ class Operators:
             # T1 = -(Dx (x) V) f
             self.T1 = chain_mpo(self.Dx, self.V, p.Lx, p.Lv, p.order)
         self.T1[0] = -self.T1[0]
-        # Dougherty collisions with fixed drift and thermal speed (Methods,
-        # Collision Operator): nu Dv (diag(v - v0) + vth^2 Dv), on v sites
+        # Dougherty collisions (Methods, Collision Operator)
         self.T3 = None
+        self.moments = False
         if getattr(p, "nu", 0.0) != 0.0:
-            inner = mpo_sum([diag_mpo(vector_mps(p.v() - p.nu_v0)),
-                             [W * (p.nu_vth ** 2 if j == 0 else 1.0)
-                              for j, W in enumerate(self.Dv)]])
-            Cv = mpo_product(self.Dv, inner)
-            Cv[0] = Cv[0] * p.nu
-            self.T3 = chain_mpo(None, Cv, p.Lx, p.Lv, p.order)
+            if getattr(p, "coll_model", 0) == 1:
+                # fixed drift and thermal speed: nu Dv (diag(v - v0) + vth^2 Dv)
+                inner = mpo_sum([diag_mpo(vector_mps(p.v() - p.nu_v0)),
+                                 [W * (p.nu_vth ** 2 if j == 0 else 1.0)
+                                  for j, W in enumerate(self.Dv)]])
+                Cv = mpo_product(self.Dv, inner)
+                Cv[0] = Cv[0] * p.nu
+                self.T3 = chain_mpo(None, Cv, p.Lx, p.Lv, p.order)
+            else:
+                # moments of the state: nu Dv diag(v) is fixed; the terms with
+                # v0(x) and vth^2(x) are built per stage (rhs_mps)
+                self.moments = True
+                Cv = mpo_product(self.Dv, diag_mpo(vector_mps(p.v())))
+                Cv[0] = Cv[0] * p.nu
+                self.T3 = chain_mpo(None, Cv, p.Lx, p.Lv, p.order)
+                self.DvDv = mpo_product(self.Dv, self.Dv)
+                self.Vw = chain_mpo(None, diag_mpo(vector_mps(p.v())), p.Lx, p.Lv, p.order)
+                self.V2w = chain_mpo(None, diag_mpo(vector_mps(p.v() ** 2)), p.Lx, p.Lv,
+                                     p.order)
 
 
 def field_mps(g: Mps, ops: Operators) -> Mps:
@@ -792,10 +813,36 @@ def caps(p, point: int) -> Optional[int]:
     return p.chi_max if p.level >= point else None
 
 
+def x_field_mps(u: np.ndarray, p) -> Mps:
+    """A function of x on the grid (natural bit order) as an x-MPS: iterated
+    SVD (eq. 4, relative cut 1e-14 when tol > 0, exact when tol = 0), then
+    compressed like the field E (cap D_F, tol)."""
+    m = tt_svd(u, [2] * p.Lx, tol=1e-14 if p.tol > 0 else 0.0)
+    return compress(m, p.df_max if p.df_max > 0 else None, p.tol)
+
+
+def collision_moment_fields(g: Mps, ops: Operators):
+    """x-MPS of the local drift v0(x) and of vth^2(x) of g (the Dougherty
+    operator's average and thermal velocity): the contractions n, <v, g>_v
+    and <v^2, g>_v as x-MPS, evaluated on the grid of x, divided there."""
+    p = ops.p
+    n = to_vector(density_mps(g, p.Lx, p.Lv, p.order, p.dv))
+    P = to_vector(density_mps(apply(ops.Vw, g), p.Lx, p.Lv, p.order, p.dv))
+    W = to_vector(density_mps(apply(ops.V2w, g), p.Lx, p.Lv, p.order, p.dv))
+    ok = n != 0.0
+    v0 = np.zeros_like(n)
+    v0[ok] = P[ok] / n[ok]
+    T = np.zeros_like(n)
+    T[ok] = W[ok] / n[ok] - v0[ok] ** 2
+    return x_field_mps(v0, p), x_field_mps(T, p)
+
+
 def rhs_mps(g: Mps, ops: Operators, E: Optional[Mps] = None) -> Mps:
     """k = R(g): T1 = -(Dx (x) V) g, T2 = -(q/m)(diag(E) (x) Dv) g and, with
-    collisions, T3 = C g, each compressed (P5), then their sum compressed
-    (P4).  E from g alone (one electron species) unless given."""
+    collisions, C g (one term with fixed v0 and vth; three with the moments
+    of g: nu Dv diag(v) g, -nu (diag(v0) (x) Dv) g, nu (diag(vth^2) (x)
+    Dv Dv) g), each compressed (P5), then their sum compressed (P4).  E from
+    g alone (one electron species) unless given."""
     p = ops.p
     if E is None:
         E = field_mps(g, ops)
@@ -806,6 +853,16 @@ def rhs_mps(g: Mps, ops: Operators, E: Optional[Mps] = None) -> Mps:
              compress_state(apply(W2, g), caps(p, 5), p)]
     if ops.T3 is not None:
         terms.append(compress_state(apply(ops.T3, g), caps(p, 5), p))
+    if ops.moments:
+        v0, T = collision_moment_fields(g, ops)
+        Wu = diag_mpo(v0)
+        Wu[0] = Wu[0] * (-p.nu)
+        WT = diag_mpo(T)
+        WT[0] = WT[0] * p.nu
+        terms.append(compress_state(apply(chain_mpo(Wu, ops.Dv, p.Lx, p.Lv, p.order), g),
+                                    caps(p, 5), p))
+        terms.append(compress_state(apply(chain_mpo(WT, ops.DvDv, p.Lx, p.Lv, p.order), g),
+                                    caps(p, 5), p))
     return compress_state(add([(1.0, T) for T in terms]), caps(p, 4), p)
 
 

@@ -2,8 +2,8 @@
 oracles (Methods: Collision Operator; the two-species set-ups; Buneman
 instability).
 
-Collisions, nu d/dv[(v - v0) f + vth^2 df/dv] with fixed v0 and vth, are an
-Ornstein-Uhlenbeck (Fokker-Planck) operator: M(v) He_n((v - v0)/vth), M the
+Collisions with fixed v0 and vth (coll_model 1), nu d/dv[(v - v0) f + vth^2
+df/dv], are an Ornstein-Uhlenbeck (Fokker-Planck) operator: M(v) He_n((v - v0)/vth), M the
 Maxwellian, is an eigenfunction with eigenvalue -n nu (textbook; not from
 the paper).  Two species: identical species of opposite charge leave no
 field; ions at rest with a uniform density reproduce the one-species run on
@@ -21,8 +21,9 @@ from tests._dispersion import root_species
 
 
 def _coll_problem(Lv, nu=1.0, v0=0.5, vth=1.3):
+    # the fixed-parameter model: an Ornstein-Uhlenbeck operator
     return wl.Problem(Lx=2, Lv=Lv, order=0, x_min=0.0, x_max=1.0, v_min=-12.0,
-                      v_max=12.0, nu=nu, nu_v0=v0, nu_vth=vth)
+                      v_max=12.0, nu=nu, nu_v0=v0, nu_vth=vth, coll_model=1)
 
 
 def _hermite_mode(p, n):

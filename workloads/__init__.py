@@ -54,6 +54,7 @@ class Problem:
     nu: float = 0.0         # Dougherty collision rate (0: collisionless)
     nu_v0: float = 0.0      # its drift velocity
     nu_vth: float = 1.0     # its thermal speed
+    coll_model: int = 0     # 0: drift and thermal speed from the moments of f; 1: fixed
 
     @property
     def Nx(self) -> int:
