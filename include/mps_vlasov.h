@@ -146,17 +146,26 @@ typedef struct mps_problem {
   double cfl;               /* > 0: adaptive dt (see below), 0: fixed dt   */
   int32_t compression;      /* mps_compression                             */
   double nu;                /* Dougherty collision rate, >= 0 (0: none)    */
-  double nu_v0, nu_vth;     /* its drift velocity and thermal speed        */
+  double nu_v0, nu_vth;     /* drift and thermal speed of coll_model 1     */
+  int32_t coll_model;       /* 0: v0, vth from the moments of f; 1: fixed  */
 } mps_problem;
 
 /* Collisions (Methods, "Collision Operator"): with nu > 0 the Vlasov
- * right-hand side gains nu d/dv[(v - nu_v0) f + nu_vth^2 df/dv], the Dougherty
- * operator with the species' drift and thermal speed taken as fixed
- * parameters (a linear operator), both derivatives the zero-gradient central
- * difference; as an MPO it is nu Dv (diag(v - nu_v0) + nu_vth^2 Dv) on the v
- * sites, and its term of each k is compressed like the other two (P5).  With
- * cfl > 0 the step adds nu |v|_max / dv + 2 nu nu_vth^2 / dv^2 to the CFL sum
- * (eq. CFL).  The memory model of mps_workspace_bound does not include it. */
+ * right-hand side gains the Dougherty operator
+ * nu d/dv[(v - v0) f + vth^2 df/dv], both derivatives the zero-gradient
+ * central difference.  coll_model 0 (the paper's operator): v0 and vth are
+ * the species' average and thermal velocity at each x, the moments of the
+ * stage's state, v0 = <v, f>_v / n, vth^2 = <v^2, f>_v / n - v0^2 with
+ * n = <1, f>_v (0 where n = 0); the three contractions are formed as x-MPS,
+ * evaluated on the x grid, divided there and brought back to x-MPS by
+ * iterated SVD (relative cut 1e-14 when tol > 0, exact when tol = 0), then
+ * compressed like the field (df_max, tol).  C f is then three terms of each
+ * k, nu Dv diag(v) f, -nu (diag(v0) (x) Dv) f and nu (diag(vth^2) (x) Dv Dv) f,
+ * each compressed like the other terms (P5).  It conserves density,
+ * momentum and energy at every x.  coll_model 1: v0 = nu_v0 and vth = nu_vth
+ * fixed (a linear operator, nu Dv (diag(v - nu_v0) + nu_vth^2 Dv), one term).
+ * With cfl > 0 the step adds nu |v|_max / dv + 2 nu nu_vth^2 / dv^2 to the
+ * CFL sum (eq. CFL) in both models. */
 
 typedef struct mps_state mps_state; /* opaque; owns all device memory */
 

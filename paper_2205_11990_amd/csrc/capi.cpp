@@ -104,6 +104,7 @@ mpsv::Problem convert(const mps_problem* p) {
   q.nu = p->nu;
   q.nu_v0 = p->nu_v0;
   q.nu_vth = p->nu_vth;
+  q.coll_model = p->coll_model;
   MPSV_CHECK(std::isfinite(q.x_min) && std::isfinite(q.x_max) &&
                  std::isfinite(q.v_min) && std::isfinite(q.v_max),
              mpsv::kEinval, "grid bounds must be finite");

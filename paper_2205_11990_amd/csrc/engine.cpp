@@ -593,6 +593,8 @@ void validate_problem(const Problem& p) {
   MPSV_CHECK(std::isfinite(p.nu) && p.nu >= 0 && std::isfinite(p.nu_v0) &&
                  std::isfinite(p.nu_vth),
              kEinval, "collision parameters must be finite, nu >= 0");
+  MPSV_CHECK(p.coll_model == 0 || p.coll_model == 1, kEinval,
+             "unknown collision model");
   MPSV_CHECK(p.compression == 0 || p.compression == 1, kEinval,
              "unknown compression scheme");
   MPSV_CHECK(p.compression == 0 || (p.order != 1 && p.order != 4), kEinval,
@@ -603,8 +605,8 @@ namespace {
 
 // The host-built operators of one problem (exact, FP64).
 struct HostOps {
-  ops::HostMpo T1, G, coll, Dv;
-  std::vector<int> bt1, bg, bcoll, bdv;
+  ops::HostMpo T1, G, coll, Dv, Dv2;
+  std::vector<int> bt1, bg, bcoll, bdv, bdv2;
   std::vector<std::vector<double>> vpoly, v2poly;
   std::vector<int> bpoly, bpoly2;
 };
@@ -630,16 +632,32 @@ HostOps host_operators(const Problem& p) {
   for (auto& x : h.T1[0]) x = -x;  // T1 = -(advection) f
   h.G = ops::poisson_g(p.Lx, p.dx(), -1.0, h.bg);  // E = -G n
   if (p.nu != 0.0) {
-    // Dougherty collisions with the species' fixed drift and thermal speed
-    // (Methods, Collision Operator): nu Dv (diag(v - v0) + vth^2 Dv) on the
-    // v sites, the identity on the x sites
-    std::vector<int> bd, bpd, bin, bcv;
+    // Dougherty collisions (Methods, Collision Operator) on the v sites, the
+    // identity on the x sites
+    std::vector<int> bd, bpd, bcv;
     auto D1 = ops::d1_zero_gradient(p.Lv, p.dv(), bd);
-    auto Vd = ops::poly_diag(p.Lv, p.v_min - p.nu_v0, p.dv(), 0.0, bpd);
-    auto Ds = D1;
-    for (auto& x : Ds[0]) x *= p.nu_vth * p.nu_vth;
-    auto inner = ops::mpo_add(Vd, bpd, Ds, bd, bin);
-    auto Cv = ops::mpo_product(D1, bd, inner, bin, bcv);
+    ops::HostMpo Cv;
+    if (p.coll_model == 1) {
+      // the species' fixed drift and thermal speed: nu Dv (diag(v - v0) +
+      // vth^2 Dv)
+      std::vector<int> bin;
+      auto Vd = ops::poly_diag(p.Lv, p.v_min - p.nu_v0, p.dv(), 0.0, bpd);
+      auto Ds = D1;
+      for (auto& x : Ds[0]) x *= p.nu_vth * p.nu_vth;
+      auto inner = ops::mpo_add(Vd, bpd, Ds, bd, bin);
+      Cv = ops::mpo_product(D1, bd, inner, bin, bcv);
+    } else {
+      // the moments of f: nu Dv diag(v) is fixed; the drift and temperature
+      // terms are built per stage, the latter with Dv Dv
+      auto Vd = ops::poly_diag(p.Lv, p.v_min, p.dv(), 0.0, bpd);
+      Cv = ops::mpo_product(D1, bd, Vd, bpd, bcv);
+      h.Dv2 = ops::mpo_product(D1, bd, D1, bd, h.bdv2);
+      if (p.order == 3) {
+        std::vector<int> brev;
+        h.Dv2 = ops::reverse(h.Dv2, h.bdv2, 4, brev);
+        h.bdv2 = brev;
+      }
+    }
     for (auto& x : Cv[0]) x *= p.nu;
     ops::HostMpo Ix((size_t)p.Lx, std::vector<double>{1.0, 0.0, 0.0, 1.0});
     std::vector<int> bix((size_t)p.Lx + 1, 1);
@@ -679,8 +697,8 @@ void validate_batch(const std::vector<Problem>& ps) {
     MPSV_CHECK(b.tol == 0.0 && b.cfl == 0.0 && b.dt == a.dt && b.qm == a.qm,
                kEinval,
                "lock-step instances need tol = 0, a fixed and common dt and q/m");
-    MPSV_CHECK((b.nu != 0.0) == (a.nu != 0.0), kEinval,
-               "lock-step instances are all collisional or all collisionless");
+    MPSV_CHECK((b.nu != 0.0) == (a.nu != 0.0) && b.coll_model == a.coll_model, kEinval,
+               "lock-step instances are all collisionless or all of one collision model");
   }
 }
 
@@ -729,7 +747,7 @@ Engine::Engine(const std::vector<Problem>& batch)
   for (auto& q : ps_) h.push_back(host_operators(q));
   for (auto& x : h)
     MPSV_CHECK(x.bt1 == h[0].bt1 && x.bg == h[0].bg && x.bcoll == h[0].bcoll &&
-                   x.bdv == h[0].bdv && x.bpoly == h[0].bpoly &&
+                   x.bdv == h[0].bdv && x.bdv2 == h[0].bdv2 && x.bpoly == h[0].bpoly &&
                    x.bpoly2 == h[0].bpoly2,
                kEinval, "lock-step instances need operators of the same bonds");
   auto pick = [&](ops::HostMpo HostOps::*m) {
@@ -740,6 +758,8 @@ Engine::Engine(const std::vector<Problem>& batch)
   t1_ = upload_mpo(pick(&HostOps::T1), h[0].bt1, ops_, s);
   gneg_ = upload_mpo(pick(&HostOps::G), h[0].bg, ops_, s);
   if (p_.nu != 0.0) coll_ = upload_mpo(pick(&HostOps::coll), h[0].bcoll, ops_, s);
+  if (p_.nu != 0.0 && p_.coll_model == 0)
+    dv2_ = upload_mpo(pick(&HostOps::Dv2), h[0].bdv2, ops_, s);
   dv_ = upload_mpo(pick(&HostOps::Dv), h[0].bdv, ops_, s);
   auto upload_chain = [&](std::vector<std::vector<double>> HostOps::*m,
                           const std::vector<int>& bc) {
@@ -1301,16 +1321,29 @@ DMps Engine::copy_mps(const DMps& a, Arena& ar, hipStream_t s) {
 
 // n(x) = dv * sum_j f(x, v_j): each v core summed over its bit (SI,
 // Integration) and absorbed into the neighbouring x core.
-DMps Engine::density(const DMps& g, Arena& ar, hipStream_t s) {
+DMps Engine::density(const DMps& g, Arena& ar, hipStream_t s, const DMps* wt) {
   const auto sites = site_list(p_.Lx, p_.Lv, p_.order);
   DMps xs;
   double* pend = nullptr;
   int pl = 0, pr = 0;
   for (size_t j = 0; j < sites.size(); ++j) {
-    const Core& A = g[j];
-    if (sites[j].first == 1) {
-      double* Ms = ar.alloc((size_t)A.l * A.r);
-      sum_physical(s, A.p, A.l, A.r, Ms);
+    Core A = g[j];
+    const bool vsite = sites[j].first == 1;
+    double* Ms = nullptr;
+    if (wt) {
+      // the weight's bond joins f's (a-major): a v site is summed against
+      // its weight core, an x site keeps its bit
+      const Core& W = (*wt)[j];
+      double* P = ar.alloc((size_t)A.l * W.l * (vsite ? 1 : 2) * A.r * W.r);
+      pair_cores(s, A.p, A.l, A.r, W.p, W.l, W.r, vsite, P);
+      A = Core{P, A.l * W.l, A.r * W.r};
+      if (vsite) Ms = P;
+    }
+    if (vsite) {
+      if (!Ms) {
+        Ms = ar.alloc((size_t)A.l * A.r);
+        sum_physical(s, A.p, A.l, A.r, Ms);
+      }
       if (!xs.empty()) {
         Core& X = xs.back();
         double* Y = ar.alloc((size_t)X.l * 2 * A.r);
@@ -1362,8 +1395,10 @@ DMps Engine::field(const DMps& g, Arena& ar, hipStream_t s) {
                         ar, s);
 }
 
-// Full-chain MPO of -(q/m) diag(E) (x) Dv (SI, Dot Product).
-DMpo Engine::t2_mpo(const DMps& En, Arena& ar, hipStream_t s) {
+// Full-chain MPO of diag(scale X) (x) vop (SI, Dot Product): the field term
+// -(q/m) diag(E) (x) Dv, and the drift and temperature collision terms.
+DMpo Engine::t2_mpo(const DMps& En, Arena& ar, hipStream_t s, double scale,
+                    const DMpo& vop) {
   const auto sites = site_list(p_.Lx, p_.Lv, p_.order);
   // E (natural bit order) and Dv (held in chain order) as visited
   const DMps E = (p_.order == 2) ? reverse_mps(En, ar, s) : En;
@@ -1374,7 +1409,7 @@ DMpo Engine::t2_mpo(const DMps& En, Arena& ar, hipStream_t s) {
     if (sites[j].first == 0) {
       const Core& e = E[ix];
       double* Wd = ar.alloc((size_t)e.l * 4 * e.r);
-      diag_mpo_site(s, e.p, e.l, e.r, ix == 0 ? -p_.qm : 1.0, Wd);
+      diag_mpo_site(s, e.p, e.l, e.r, ix == 0 ? scale : 1.0, Wd);
       ++ix;
       if (cv == 1) {
         m.W = Wd;
@@ -1386,7 +1421,7 @@ DMpo Engine::t2_mpo(const DMps& En, Arena& ar, hipStream_t s) {
       m.wr = e.r * cv;
       cx = e.r;
     } else {
-      const MpoSite& d = dv_[iv++];
+      const MpoSite& d = vop[iv++];
       if (cx == 1) {
         m.W = d.W;
       } else {
@@ -1401,6 +1436,37 @@ DMpo Engine::t2_mpo(const DMps& En, Arena& ar, hipStream_t s) {
     mpo_left_matrix(s, m.W, m.wl, m.wr, m.Wmat);
   }
   return W;
+}
+
+// The collision terms with the drift v0(x) and the temperature vth^2(x) of
+// g (Methods, Collision Operator): the moments <1,g>, <v,g>, <v^2/2,g> as
+// x-MPS, on the x grid, divided there, back to x-MPS (compressed like the
+// field), then -nu (diag(v0) (x) Dv) g and nu (diag(vth^2) (x) Dv Dv) g
+// compressed at P5.
+void Engine::moment_collision_terms(const DMps& g, Arena& out, hipStream_t s,
+                                    DMps& Tu, DMps& Tt) {
+  const long nx = p_.Nx();
+  double* nd = out.alloc((size_t)nx);
+  double* Pd = out.alloc((size_t)nx);
+  double* Hd = out.alloc((size_t)nx);
+  {
+    ArenaScope sc(work());
+    DMps n = density(g, work(), s);
+    dense_of(n, nd, s);
+    DMps P = density(g, work(), s, &vpoly_);
+    dense_of(P, Pd, s);
+    DMps H = density(g, work(), s, &v2poly_);
+    dense_of(H, Hd, s);
+  }
+  double* v0 = out.alloc((size_t)nx);
+  double* T = out.alloc((size_t)nx);
+  dougherty_fields(s, nd, Pd, Hd, nx, v0, T);
+  const double cut = p_.tol > 0 ? 1e-14 : 0.0;
+  const int capf = p_.df_max > 0 ? p_.df_max : INT_MAX;
+  DMps u = compress_mps(vector_mps(v0, p_.Lx, cut, out, s), capf, p_.tol, out, s);
+  DMps t = compress_mps(vector_mps(T, p_.Lx, cut, out, s), capf, p_.tol, out, s);
+  Tu = apply_compress(t2_mpo(u, out, s, -p_.nu, dv_), g, cap_for(5), p_.tol, out, s);
+  Tt = apply_compress(t2_mpo(t, out, s, p_.nu, dv2_), g, cap_for(5), p_.tol, out, s);
 }
 
 // k = R(g) = -v d/dx g - (q/m) E d/dv g  (eq. 1, C = 0)
@@ -1446,12 +1512,13 @@ DMps Engine::rhs(const DMps& g, Arena& out, hipStream_t s, const DMps* Eext) {
   auto join_side = [&] {
     if (side.joinable()) side.join();
   };
-  DMps T2;
+  DMps T2, T3u, T3t;
   try {
     DMps E;
     if (!Eext) E = field(g, tmp_, s);
-    DMpo W2 = t2_mpo(Eext ? *Eext : E, tmp_, s);
+    DMpo W2 = t2_mpo(Eext ? *Eext : E, tmp_, s, -p_.qm, dv_);
     T2 = apply_compress(W2, g, cap_for(5), p_.tol, tmp_, s);
+    if (!dv2_.empty()) moment_collision_terms(g, tmp_, s, T3u, T3t);
   } catch (...) {
     join_side();
     if (!capturing_) (void)hipStreamSynchronize(side_);
@@ -1464,7 +1531,10 @@ DMps Engine::rhs(const DMps& g, Arena& out, hipStream_t s, const DMps* Eext) {
   }
   MPSV_HIP(hipStreamWaitEvent(s, ev_join_, 0));
   if (coll_.empty()) return add_terms({{1.0, &T1}, {1.0, &T2}}, cap_for(4), out, s);
-  return add_terms({{1.0, &T1}, {1.0, &T2}, {1.0, &T3}}, cap_for(4), out, s);
+  if (dv2_.empty())
+    return add_terms({{1.0, &T1}, {1.0, &T2}, {1.0, &T3}}, cap_for(4), out, s);
+  return add_terms({{1.0, &T1}, {1.0, &T2}, {1.0, &T3}, {1.0, &T3u}, {1.0, &T3t}},
+                   cap_for(4), out, s);
 }
 
 void Engine::commit(const DMps& fn, hipStream_t s) {
@@ -1826,6 +1896,34 @@ void Engine::step_stages(double h, hipStream_t s) {
 // f0 = sum_r ax[r] (x) bv[r] as an MPS in the step arena (one instance):
 // each 1-D profile by iterated SVD (eq. 4), then the separable terms
 // merged in chain order and compressed to (chi, tol).
+// Iterated SVD (eq. 4) run from the right end: X = u as 2^(L-1) x 2, SVD,
+// keep V^T as the last core, carry U S; values below `cut` of the norm
+// (relative discarded weight) are dropped, none with cut = 0.  Cores in ar,
+// temporaries in the compression workspace.
+DMps Engine::vector_mps(const double* u, int L, double cut, Arena& ar, hipStream_t s) {
+  DMps m(L);
+  ArenaScope sc(work());
+  double* X = work().alloc((size_t)1 << L);
+  copy_doubles(s, X, u, 1L << L);
+  int rows = 1 << (L - 1), Dr = 1;
+  for (int j = L - 1; j >= 1; --j) {
+    const int c = 2 * Dr;
+    const int Dmax = std::min(rows, c);
+    double* Vt = ar.alloc((size_t)Dmax * c);
+    double* US = work().alloc((size_t)rows * Dmax);
+    const int D = svd_truncate(s, work(), X, rows, c, c, INT_MAX, cut, Vt, US,
+                               nullptr, nullptr, outcomes(s), 0);
+    m[j] = Core{Vt, D, Dr};
+    X = US;
+    rows /= 2;
+    Dr = D;
+  }
+  Core c0{ar.alloc((size_t)2 * Dr), 1, Dr};
+  copy_doubles(s, c0.p, X, 2L * Dr);
+  m[0] = c0;
+  return m;
+}
+
 DMps Engine::initial_state(int rank, const double* ax, const double* bv,
                            hipStream_t s) {
   MPSV_CHECK(rank >= 1, kEinval, "profile rank must be >= 1");
@@ -1846,32 +1944,10 @@ DMps Engine::initial_state(int rank, const double* ax, const double* bv,
   MPSV_HIP(hipStreamSynchronize(s));
   MPSV_CHECK(bad == 0, kEinval, "non-finite values in the initial profiles");
 
-  // 1-D vector -> MPS by iterated SVD (eq. 4), run from the right end:
-  // X = u as 2^(L-1) x 2, SVD, keep V^T as the last core, carry U S.  The
-  // relative floor 1e-14 drops only numerically zero directions (a smooth
-  // profile keeps a handful), whatever the problem's tolerance.
-  auto tt = [&](const double* u, int L) {
-    DMps m(L);
-    double* X = work().alloc((size_t)1 << L);
-    copy_doubles(s, X, u, 1L << L);
-    int rows = 1 << (L - 1), Dr = 1;
-    for (int j = L - 1; j >= 1; --j) {
-      const int c = 2 * Dr;
-      const int Dmax = std::min(rows, c);
-      double* Vt = step_.alloc((size_t)Dmax * c);
-      double* US = work().alloc((size_t)rows * Dmax);
-      const int D = svd_truncate(s, work(), X, rows, c, c, INT_MAX, 1e-14, Vt, US,
-                                 nullptr, nullptr);
-      m[j] = Core{Vt, D, Dr};
-      X = US;
-      rows /= 2;
-      Dr = D;
-    }
-    Core c0{step_.alloc((size_t)2 * Dr), 1, Dr};
-    copy_doubles(s, c0.p, X, 2L * Dr);
-    m[0] = c0;
-    return m;
-  };
+  // 1-D vector -> MPS by iterated SVD (eq. 4).  The relative floor 1e-14
+  // drops only numerically zero directions (a smooth profile keeps a
+  // handful), whatever the problem's tolerance.
+  auto tt = [&](const double* u, int L) { return vector_mps(u, L, 1e-14, step_, s); };
   std::vector<DMps> terms;
   {
     ArenaScope sc(work());

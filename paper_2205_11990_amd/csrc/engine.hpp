@@ -20,6 +20,7 @@ struct Problem {
   double cfl = 0.0;  // > 0: adaptive dt, this fraction of the CFL limit
   int compression = 0;  // 0 sweep, 1 centre-first (sequential orderings)
   double nu = 0.0, nu_v0 = 0.0, nu_vth = 1.0;  // Dougherty collisions
+  int coll_model = 0;  // 0 drift / thermal speed from the moments of f, 1 fixed
   int n() const { return Lx + Lv; }
   long Nx() const { return 1L << Lx; }
   long Nv() const { return 1L << Lv; }
@@ -217,9 +218,21 @@ class Engine {
   }
   void absorb_right(const VSite& v, const double* L, int q, double* N,
                     hipStream_t s);
-  DMps density(const DMps& g, Arena& ar, hipStream_t s);
+  // n(x) = dv <1, g>_v, or dv <w, g>_v with the full-chain weight MPS
+  // 1(x) w(v) (chain order) when wt is given
+  DMps density(const DMps& g, Arena& ar, hipStream_t s, const DMps* wt = nullptr);
+  // a function of x on the grid (device, natural bit order) as an x-MPS:
+  // iterated SVD from the right with relative cut `cut`
+  DMps vector_mps(const double* u, int L, double cut, Arena& ar, hipStream_t s);
+  // the collision terms that depend on the moments of g (coll_model 0):
+  // -nu (diag(v0) (x) Dv) g and nu (diag(vth^2) (x) Dv Dv) g, compressed
+  void moment_collision_terms(const DMps& g, Arena& out, hipStream_t s,
+                              DMps& Tu, DMps& Tt);
   DMps field(const DMps& g, Arena& ar, hipStream_t s);
-  DMpo t2_mpo(const DMps& E, Arena& ar, hipStream_t s);
+  // diag(scale * X) (x) vop as a full-chain MPO, X an x-MPS (natural bit
+  // order), vop a v-site MPO in chain order (the field term: X = E,
+  // scale = -q/m, vop = Dv)
+  DMpo t2_mpo(const DMps& X, Arena& ar, hipStream_t s, double scale, const DMpo& vop);
   DMps rhs(const DMps& g, Arena& out, hipStream_t s, const DMps* Eext = nullptr);
   DMps direct_sum(const std::vector<std::pair<double, const DMps*>>& t, Arena& ar,
                   hipStream_t s);
@@ -282,6 +295,7 @@ class Engine {
   long graph_captures_ = 0, graph_replays_ = 0;
   DMpo t1_, gneg_, dv_;            // T1 chain, -G (x sites), Dv (v sites)
   DMpo coll_;                      // collision operator chain (nu > 0)
+  DMpo dv2_;                       // Dv Dv on the v sites (moment collisions)
   DMps vpoly_, v2poly_;            // moment weights (full chain)
   DMps f_;
   DMps staged_;  // the new state of the step in flight (step_ arena)

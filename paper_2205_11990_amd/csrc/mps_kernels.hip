@@ -235,6 +235,49 @@ __global__ void fill_kernel(double* x, long n, double v, InstOff io) {
   x = shifted(x, io.of(blockIdx.z));
   GRID_STRIDE(e, n) x[e] = v;
 }
+__global__ void pair_cores_kernel(const double* A, int l, int r, const double* W,
+                                  int c, int d, int sum_bit, double* out,
+                                  InstOff io) {
+  const long o_ = io.of(blockIdx.z);
+  A = shifted(A, o_);
+  W = shifted(W, o_);
+  out = shifted(out, o_);
+  const long R = (long)r * d;
+  const long n = (long)l * c * (sum_bit ? 1 : 2) * R;
+  GRID_STRIDE(e, n) {
+    const long col = e % R;
+    const long b = col / d, ee = col % d;
+    long t = e / R;
+    if (sum_bit) {
+      const long a = t / c, cc = t % c;
+      out[e] = A[(a * 2) * r + b] * W[(cc * 2) * d + ee] +
+               A[(a * 2 + 1) * r + b] * W[(cc * 2 + 1) * d + ee];
+    } else {
+      const long bit = t % 2;
+      t /= 2;
+      const long a = t / c, cc = t % c;
+      out[e] = A[(a * 2 + bit) * r + b] * W[(cc * 2 + bit) * d + ee];
+    }
+  }
+}
+
+__global__ void dougherty_fields_kernel(const double* n, const double* P,
+                                        const double* H, long nx, double* v0,
+                                        double* T, InstOff io) {
+  const long o_ = io.of(blockIdx.z);
+  n = shifted(n, o_);
+  P = shifted(P, o_);
+  H = shifted(H, o_);
+  v0 = shifted(v0, o_);
+  T = shifted(T, o_);
+  GRID_STRIDE(e, nx) {
+    const double m = n[e];
+    const double u = (m != 0.0) ? P[e] / m : 0.0;
+    v0[e] = u;
+    T[e] = (m != 0.0) ? 2.0 * H[e] / m - u * u : 0.0;
+  }
+}
+
 __global__ void copy_doubles_kernel(double* dst, const double* src, long n,
                                     InstOff io) {
   const long o_ = io.of(blockIdx.z);
@@ -353,6 +396,23 @@ void sum_squares(hipStream_t s, const double* x, long n, double scale,
 void fill(hipStream_t s, double* x, long n, double v) {
   if (n <= 0) return;
   hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n), 1, inst_count()), dim3(256), 0, s, x, n, v, inst_off());
+  MPSV_LAUNCHED();
+}
+
+void pair_cores(hipStream_t s, const double* A, int l, int r, const double* W,
+                int c, int d, bool sum_bit, double* out) {
+  const long n = (long)l * c * (sum_bit ? 1 : 2) * r * d;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(pair_cores_kernel, dim3(grid_for(n), 1, inst_count()), dim3(256), 0,
+                     s, A, l, r, W, c, d, sum_bit ? 1 : 0, out, inst_off());
+  MPSV_LAUNCHED();
+}
+
+void dougherty_fields(hipStream_t s, const double* n, const double* P,
+                      const double* H, long nx, double* v0, double* T) {
+  if (nx <= 0) return;
+  hipLaunchKernelGGL(dougherty_fields_kernel, dim3(grid_for(nx), 1, inst_count()),
+                     dim3(256), 0, s, n, P, H, nx, v0, T, inst_off());
   MPSV_LAUNCHED();
 }
 

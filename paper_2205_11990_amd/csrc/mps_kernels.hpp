@@ -58,6 +58,19 @@ void count_nonfinite(hipStream_t s, const double* x, long n, int* flag);
 void sum_squares(hipStream_t s, const double* x, long n, double scale,
                  double* out);
 
+// Pair an MPS core A (l x 2 x r) with a weight core W (c x 2 x d) site by
+// site: out[(a,c)][t][(b,e)] = A[a][t][b] W[c][t][e] (sum_bit false), or
+// out[(a,c)][(b,e)] = sum_t A[a][t][b] W[c][t][e] (sum_bit true); fused
+// bonds a-major.
+void pair_cores(hipStream_t s, const double* A, int l, int r, const double* W,
+                int c, int d, bool sum_bit, double* out);
+
+// Local drift and temperature from the moments n = <1,f>, P = <v,f>,
+// H = <v^2/2, f> on nx points: v0 = P / n, T = 2 H / n - v0^2 (both 0 where
+// n = 0).
+void dougherty_fields(hipStream_t s, const double* n, const double* P,
+                      const double* H, long nx, double* v0, double* T);
+
 void fill(hipStream_t s, double* x, long n, double v);
 // dst[0:n] = src[0:n] (device buffers of the current lanes' instances)
 void copy_doubles(hipStream_t s, double* dst, const double* src, long n);

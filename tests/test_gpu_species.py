@@ -28,13 +28,16 @@ def B():
     return binding
 
 
-@pytest.mark.parametrize("order", [0, 1])
-def test_untruncated_collisional_steps_equal_dense_oracle(B, order):
-    _say("untruncated collisions order=%d" % order)
+@pytest.mark.parametrize("order,model", [(0, 0), (1, 0), (2, 0), (3, 0), (0, 1), (1, 1)])
+def test_untruncated_collisional_steps_equal_dense_oracle(B, order, model):
+    """Dougherty collisions, untruncated: model 0 takes the drift and thermal
+    speed from the moments of each stage's state (per x), model 1 keeps the
+    given constants; the MPS steps equal the dense steps."""
+    _say("untruncated collisions order=%d model=%d" % (order, model))
     w = wl.landau_small(L=4, tol=0.0)
     p = w.problem
     p.order, p.chi_max, p.level = order, 1 << 20, 1
-    p.nu, p.nu_v0, p.nu_vth = 0.3, 0.2, 1.1
+    p.nu, p.nu_v0, p.nu_vth, p.coll_model = 0.3, 0.2, 1.1, model
     st = B.MpsState(p, w.ax, w.bv)
     F = odense.initial(w.ax, w.bv)
     for k in range(3):
@@ -45,11 +48,17 @@ def test_untruncated_collisional_steps_equal_dense_oracle(B, order):
     st.free()
 
 
-def test_truncated_collisional_steps_match_mps_oracle(B):
-    _say("truncated collisions C5 chi8 two-stream L=5")
-    w = wl.two_stream(L=5, chi=8, tol=0.0, level=5, df_max=4, dt_cfg=0.05, order=0)
+@pytest.mark.parametrize("order,model,tol", [(0, 0, 0.0), (1, 0, 0.0), (0, 0, 1e-10),
+                                             (0, 1, 0.0)])
+def test_truncated_collisional_steps_match_mps_oracle(B, order, model, tol):
+    """Collisions with every point capped (C5, chi = 8, the moment fields
+    capped at D_F = 4 like E), or the paper's C1/tol schedule: f and E within
+    1e-8 of the MPS oracle after two steps, same bonds."""
+    _say("truncated collisions two-stream L=5 order=%d model=%d tol=%g" % (order, model, tol))
+    w = wl.two_stream(L=5, chi=8, tol=tol, level=5 if tol == 0 else 1, df_max=4,
+                      dt_cfg=0.05, order=order)
     p = w.problem
-    p.nu, p.nu_v0, p.nu_vth = 0.2, 0.0, 1.0
+    p.nu, p.nu_v0, p.nu_vth, p.coll_model = 0.2, 0.0, 1.0, model
     f = S.oracle_start(w, pert_chi=8, amp=1e-3)
     st = S.gpu_state(B, w, f)
     ops = omps.Operators(p)
