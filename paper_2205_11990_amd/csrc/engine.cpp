@@ -520,29 +520,54 @@ MemoryModel memory_model(const Problem& q) {
   // field bond: the cap D_F, at most the full rank of an Lx-site MPS
   const double df = std::min(q.df_max > 0 ? (double)q.df_max : chi,
                              std::ldexp(1.0, q.Lx / 2));
-  // widest MPO: the field term, or the upwind advection term
+  // widest MPO of each lane.  Main lane: the field term, and with the
+  // moment collision model the temperature term diag(vth^2) (x) Dv Dv (the
+  // temperature capped like the field: bond 25 D_F in the interleaved
+  // order).  Side lane: the advection term (central or upwind) and the
+  // fixed collision operator nu Dv (diag(v - v0) + vth^2 Dv) (bond 35 on
+  // the v sites) or the moment model's nu Dv diag(v) (bond 10).
   const bool il = q.order == 1 || q.order == 4;
-  const double w = std::max((il ? 5.0 : 3.0) * df,
-                            q.x_scheme == 1 ? (il ? 24.0 : 8.0) : 0.0);
-  double S = 0, N = 0, I = 0;
+  double wm = (il ? 5.0 : 3.0) * df;
+  double ws = q.x_scheme == 1 ? (il ? 24.0 : 8.0) : (il ? 6.0 : 3.0);
+  if (q.nu != 0.0) {
+    if (q.coll_model == 1) {
+      ws = std::max(ws, 35.0);
+    } else {
+      wm = std::max(wm, il ? 25.0 * df : std::max(25.0, df));
+      ws = std::max(ws, 10.0);
+    }
+  }
+  // bond cap at bond j: chi, or 2 chi inside an IG pair (never cut there)
+  auto cap = [&](int j) { return (q.order == 4 && (j & 1)) ? 2.0 * chi : chi; };
+  double S = 0, N = 0, Ns = 0, I = 0;
   for (int j = 0; j < n; ++j) {
-    const double bl = std::min(chi, full(j)), br = std::min(chi, full(j + 1));
+    const double bl = std::min(cap(j), full(j)), br = std::min(cap(j + 1), full(j + 1));
     S += bl * 2 * br;
-    N = std::max(N, std::min(w * bl, full(j)) * w * 2 * br);
+    N = std::max(N, std::min(wm * bl, full(j)) * wm * 2 * br);
+    Ns = std::max(Ns, std::min(ws * bl, full(j)) * ws * 2 * br);
   }
   if (il) {
     // interleaved initial state: Kronecker products of the x and v cores
-    auto fr = [&](int k) { return std::ldexp(1.0, std::min(k, q.Lx - k)); };
+    // of the profiles' iterated SVDs, whose ranks are taken as at most 32
+    // (smooth profiles keep a handful of values above the 1e-14 cut)
+    auto fr = [&](int k) { return std::min(32.0, std::ldexp(1.0, std::min(k, q.Lx - k))); };
     for (int k = 0; k < q.Lx; ++k)
       I += fr(k) * fr(k) * 2 * fr(k + 1) * fr(k) +
            fr(k) * fr(k + 1) * 2 * fr(k + 1) * fr(k + 1);
   }
   S *= 8.0;
   N *= 8.0;
+  Ns *= 8.0;
   I *= 8.0;
-  const double work = il ? std::max({12.0 * N, 3.5 * I, 60.0 * S}) : 60.0 * S;
+  double work = il ? std::max({12.0 * N, 3.5 * I, 60.0 * S}) : std::max(60.0 * S, 12.0 * N);
+  double work2 = std::max(80.0 * S, 12.0 * Ns);
+  // centre-first: the right half's sweep holds its own blocks beside
+  if (q.compression == 1) {
+    work += 20.0 * S;
+    work2 += 20.0 * S;
+  }
   const double est[7] = {1.0 * (1 << 20), 2.0 * S, 1.5 * I + 12.0 * S, 40.0 * S,
-                         work, 40.0 * S, 80.0 * S};
+                         work, 40.0 * S, work2};
   MemoryModel m;
   m.chunk = (size_t)std::min(64.0 * (1 << 20), std::max(2.0 * (1 << 20), 8.0 * S));
   m.chunk = (m.chunk + 255) & ~(size_t)255;

@@ -923,17 +923,38 @@ void launch_split(hipStream_t s, const double* Xr, int k, long ldx, int cap,
                                  hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)kJacobiMaxLds));
   });
-  MultiWs w;
-  w.xg = ws;
-  w.xn = w.xg + (size_t)S::slots * S::col;
-  w.val = w.xn + S::slots;
-  w.xi = (int*)(w.val + 2 * S::wgs);
-  w.flags = w.xi + S::slots;
-  fill_int(s, w.flags, S::wgs, 0);
-  jacobi_multi_kernel<NLOG, GLOG, RPT><<<dim3(S::wgs, 1, inst_count()), dim3(S::threads),
-                                         split_lds<NLOG, GLOG, RPT>(), s>>>(
-      Xr, k, ldx, max_sweeps, cap, tol, Vt, sigbuf, perm, info, w, inst_off());
-  MPSV_LAUNCHED();
+  // The workgroups of one decomposition wait for each other, so one launch
+  // must never need more workgroups than the device holds at once: lock-step
+  // instances are launched in groups that fit (one workgroup per compute
+  // unit at this kernel's LDS, times the occupancy the runtime reports).
+  static const int capacity = [] {
+    int dev = 0, cus = 0, per = 0;
+    MPSV_HIP(hipGetDevice(&dev));
+    MPSV_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    MPSV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per, (const void*)jacobi_multi_kernel<NLOG, GLOG, RPT>, S::threads,
+        split_lds<NLOG, GLOG, RPT>()));
+    return std::max(1, cus * std::max(1, per));
+  }();
+  MPSV_CHECK(S::wgs <= capacity, kEdevice,
+             "split Jacobi: the device cannot hold the workgroups of one decomposition");
+  const Lanes all = lanes();
+  const int group = std::max(1, capacity / S::wgs);
+  for (int i0 = 0; i0 < all.n; i0 += group) {
+    LanesScope ls(Lanes{std::min(group, all.n - i0), all.first + (long)i0 * all.stride,
+                        all.stride});
+    MultiWs w;
+    w.xg = ws;
+    w.xn = w.xg + (size_t)S::slots * S::col;
+    w.val = w.xn + S::slots;
+    w.xi = (int*)(w.val + 2 * S::wgs);
+    w.flags = w.xi + S::slots;
+    fill_int(s, w.flags, S::wgs, 0);
+    jacobi_multi_kernel<NLOG, GLOG, RPT><<<dim3(S::wgs, 1, inst_count()), dim3(S::threads),
+                                           split_lds<NLOG, GLOG, RPT>(), s>>>(
+        Xr, k, ldx, max_sweeps, cap, tol, Vt, sigbuf, perm, info, w, inst_off());
+    MPSV_LAUNCHED();
+  }
 }
 
 }  // namespace

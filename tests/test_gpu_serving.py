@@ -83,7 +83,10 @@ def test_serving_rejects_request_above_budget(S):
 
 @pytest.mark.parametrize("case", ["landau_6_chi16", "two_stream_8_chi32_C5",
                                   "two_stream_10_chi64_C5", "sweep_11_chi64",
-                                  "two_stream_10_chi64_fp32", "two_stream_12_chi64_df4_C5"])
+                                  "two_stream_10_chi64_fp32", "two_stream_12_chi64_df4_C5",
+                                  "collisions_10_chi64_C5", "collisions_fixed_9_chi32_seq",
+                                  "centre_first_10_chi64", "ig_8_chi32",
+                                  "two_stream_14_chi128_df4_C5"])
 def test_device_bytes_within_workspace_bound(S, case):
     """The admission bound covers what a state holds after steps from a
     state with every bond at chi_max (random perturbation, no tolerance
@@ -96,6 +99,19 @@ def test_device_bytes_within_workspace_bound(S, case):
         w = wl.two_stream(L=8, chi=32, tol=0.0, level=5)
     elif case == "two_stream_12_chi64_df4_C5":
         w = wl.two_stream(L=12, chi=64, tol=0.0, level=5, df_max=4)
+    elif case == "collisions_10_chi64_C5":
+        w = wl.two_stream(L=10, chi=64, tol=0.0, level=5, df_max=4)
+        w.problem.nu = 0.05
+    elif case == "collisions_fixed_9_chi32_seq":
+        w = wl.two_stream(L=9, chi=32, tol=0.0, level=5, df_max=4, order=0)
+        w.problem.nu, w.problem.coll_model = 0.05, 1
+    elif case == "centre_first_10_chi64":
+        w = wl.two_stream(L=10, chi=64, tol=0.0, level=5, df_max=4, order=0)
+        w.problem.compression = 1
+    elif case == "ig_8_chi32":
+        w = wl.two_stream(L=8, chi=32, tol=0.0, level=5, df_max=4, order=4)
+    elif case == "two_stream_14_chi128_df4_C5":
+        w = wl.two_stream(L=14, chi=128, tol=0.0, level=5, df_max=4)
     elif case.startswith("two_stream_10"):
         w = wl.two_stream(L=10, chi=64, tol=0.0, level=5)
         if case.endswith("fp32"):
@@ -116,7 +132,8 @@ def test_device_bytes_within_workspace_bound(S, case):
         bound = binding.workspace_bound(p)
         print("bonds %s held %d bytes, bound %d" % (max(st.info()["bonds"]), used, bound),
               flush=True)
-        assert max(st.info()["bonds"]) == p.chi_max
+        cut = st.info()["bonds"][2:p.n_sites:2] if p.order == 4 else st.info()["bonds"]
+        assert max(cut) == p.chi_max
         assert 0 < used <= bound
     finally:
         st.free()

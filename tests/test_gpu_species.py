@@ -150,6 +150,45 @@ def test_truncated_buneman_plasma_matches_mps_oracle(B, order, comp, nu):
     pl.free()
 
 
+@pytest.mark.parametrize("nu", [0.0, 0.05])
+def test_two_species_landau_real_mass_ratio(B, nu):
+    """The paper's nonlinear Landau set-up with mobile ions at the real mass
+    ratio m_i/m_e = 1836 (ion thermal speed 1/sqrt(1836), A = 0.5,
+    k = 0.75), with and without collisions: untruncated steps equal the
+    dense steps of both species, and capped steps (C5, chi = 8, D_F = 4)
+    match the MPS oracle within 1e-8."""
+    _say("two-species Landau m_i/m_e = 1836 nu=%g" % nu)
+    ws, q = wl.landau_two_species(L=3, Lv=4, chi=1 << 20, tol=0.0, level=1, nu=nu)
+    ps = [w.problem for w in ws]
+    pl = B.Plasma(ps, q, [(w.ax, w.bv) for w in ws])
+    Fs = [odense.initial(w.ax, w.bv) for w in ws]
+    for _ in range(2):
+        pl.step(1)
+        Fs = odense.rk4_step_species(Fs, ps, q, ps[0].dt)
+    for s_, F in enumerate(Fs):
+        G = pl.species(s_).to_dense().cpu().numpy()
+        assert np.abs(G - F).max() <= 1e-11 * np.abs(F).max(), s_
+    pl.free()
+    ws, q = wl.landau_two_species(L=5, chi=8, tol=0.0, level=5, df_max=4, nu=nu)
+    ps = [w.problem for w in ws]
+    pl = B.Plasma(ps, q, [(w.ax, w.bv) for w in ws])
+    fs = [S.oracle_start(ws[0], pert_chi=8, amp=1e-4), S.oracle_start(ws[1])]
+    for s_, (f, p) in enumerate(zip(fs, ps)):
+        pl.species(s_).set_cores(S.binary_cores(f, p))
+    opss = [omps.Operators(p) for p in ps]
+    for _ in range(2):
+        pl.step(1)
+        fs = omps.rk4_step_species(fs, opss, q, ps[0].dt)
+    for s_, (f, p) in enumerate(zip(fs, ps)):
+        G = pl.species(s_).to_dense().cpu().numpy()
+        R = omps.to_dense(f, p)
+        assert np.abs(G - R).max() <= 1e-8 * np.abs(R).max(), s_
+    E, _ = pl.field()
+    Eref = omps.to_vector(omps.field_species_mps(fs, opss, q))
+    assert np.abs(E.cpu().numpy() - Eref).max() <= 1e-8 * np.abs(Eref).max()
+    pl.free()
+
+
 def test_plasma_species_cannot_be_stepped_or_freed_alone(B):
     _say("plasma species handles are owned by the plasma")
     ws, q = wl.buneman(L=3, Lv=4, chi=8)

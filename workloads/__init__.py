@@ -149,6 +149,33 @@ def buneman(L: int = 9, Lv: Optional[int] = None, chi: int = 64, tol: float = 0.
              Workload("buneman_ions_" + tag, pi_, ax_i, bv_i, 2000)], [-1.0, 1.0])
 
 
+def landau_two_species(L: int = 6, Lv: Optional[int] = None, chi: int = 24, tol: float = 0.0,
+                       level: int = 5, df_max: int = 0, order: int = ORDER_SEQ,
+                       k: float = 0.75, A: float = 0.5, mass_ratio: float = 1836.0,
+                       periods: int = 1, dt_cfg: Optional[float] = None, nu: float = 0.0):
+    """Nonlinear Landau damping with mobile ions (Methods): Maxwellian ions
+    and electrons of equal temperature (v_th,i^2 = m_e / m_i), the electrons
+    modulated by (1 + A cos kx); x in [-a pi/k, a pi/k) with a = periods;
+    v in +-6 v_th,s for each species.  Returns ([electrons, ions], [q_e, q_i]
+    = [-1, +1]); both share Lx and dt (the electron CFL limit)."""
+    Lv = L if Lv is None else Lv
+    x0, x1 = -periods * math.pi / k, periods * math.pi / k
+    vth_i = math.sqrt(1.0 / mass_ratio)
+    pe = Problem(Lx=L, Lv=Lv, order=order, x_min=x0, x_max=x1, v_min=-6.0, v_max=6.0,
+                 qm=-1.0, chi_max=chi, level=level, df_max=df_max, tol=tol, nu=nu)
+    pe.dt = stable_dt(pe, dt_cfg)
+    pi_ = Problem(Lx=L, Lv=Lv, order=order, x_min=x0, x_max=x1, v_min=-6.0 * vth_i,
+                  v_max=6.0 * vth_i, qm=1.0 / mass_ratio, dt=pe.dt, chi_max=chi,
+                  level=level, df_max=df_max, tol=tol, nu=nu, nu_vth=vth_i)
+    ax_e = (1.0 + A * np.cos(k * pe.x()))[None, :]
+    bv_e = (np.exp(-0.5 * pe.v() ** 2) / math.sqrt(2.0 * math.pi))[None, :]
+    ax_i = np.ones((1, pe.Nx))
+    bv_i = (np.exp(-0.5 * (pi_.v() / vth_i) ** 2) / math.sqrt(2.0 * math.pi * vth_i ** 2))[None, :]
+    tag = "2^%dx2^%d_chi%d" % (L, Lv, chi)
+    return ([Workload("landau_electrons_" + tag, pe, ax_e, bv_e, 1000),
+             Workload("landau_ions_" + tag, pi_, ax_i, bv_i, 1000)], [-1.0, 1.0])
+
+
 def landau_small(chi: int = 16, tol: float = 1e-10, level: int = 1,
                  L: int = 6, Lv: Optional[int] = None) -> Workload:
     """Landau damping, x in [0, 4 pi) periodic, v in [-6, 6], k=0.5,
