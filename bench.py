@@ -31,6 +31,8 @@ Beside the metric line, three measurements of the same JSON object
            grids, chi in {16, 32, 48, 64}, fixed rank), one lock-step batch
            per (grid, chi) shape: aggregate steps/s against stepping them one
            after the other and against one stream per instance.
+  tuning   the launch-shape table in use (tune.py; its variants give the
+           same bits, so it changes speed only) and its entry count.
   serving  seeded Poisson arrivals (mean 20 requests/s) of Landau and
            two-stream solve requests (grids 2^8..2^10, chi in {32, 64},
            FP32 contraction, tol 1e-6 with every compression capped at chi),
@@ -695,6 +697,10 @@ def main():
                    "dt": p.dt, "sites": p.n_sites, "final_bonds": info["bonds"]},
         "roofline": roof,
         "cpu_baseline": cpu,
+        # launch-shape table in use (bit-identical variants; speed only)
+        "tuning": {"table": "paper_2205_11990_amd/tuning_gfx950.txt"
+                   if os.environ.get("MPSV_TUNING", "") in ("",) else os.environ["MPSV_TUNING"],
+                   "entries": binding.tune_size()},
     }
     out.update(extras)
     print(json.dumps(out))

@@ -168,6 +168,52 @@ mps_status mpsb_profile(int32_t enable);
 mps_status mpsb_profile_read(int32_t cls, int64_t* launches, double* ms,
                              double* flops, double* bytes);
 
+/* ---- Launch-shape table (used by every call above and by mps_step).
+ *
+ * For two launches the library has several kernel variants that give
+ * bit-identical results and differ only in how the work is spread over
+ * workgroups and waves: the output tile of the FP64 GEMM (knob 1: value 0
+ * = 64 x 64, 1 = 128 x 128; used when K is not split) and the columns per
+ * wave of a Householder reflector application (knob 2: value 1, 2 or 4).
+ * A table maps a key of six integers {knob, a, b, c, d, instance class}
+ * to a value; a launch whose exact key is in the table (and whose value is
+ * valid for it) takes that variant, any other the built-in rule.  Keys:
+ *   knob 1: a = M, b = N, c = K, d = 4 * batch + 2 * (A row-major) +
+ *           (B row-major)
+ *   knob 2: a = rows (per row chunk), b = reflectors, c = columns,
+ *           d = 2 * chunks + (1 for Q^T, 0 for Q)
+ * instance class: 0 for one instance, 1 for 2..7 lock-step instances, 2
+ * for 8..31, 3 for 32 or more.  The table is loaded on first use from the
+ * file named by MPSV_TUNING, else tuning_gfx950.txt next to the library
+ * (MPSV_TUNING=none: start empty).  The text format is one entry per line,
+ * "knob a b c d class value", '#' starting a comment line.  The table is
+ * written by paper_2205_11990_amd/tune.py, which times the variants in
+ * real steps.  All calls are host-only except mpsb_tune_records, which
+ * synchronises the device.  Changing the table while steps run on other
+ * threads is allowed; those launches take the old or the new value. */
+mps_status mpsb_tune_clear(void);
+/* value < 0 erases the key; MPS_EINVAL for an unknown knob, a negative key
+ * integer or a value above 31. */
+mps_status mpsb_tune_set(const int32_t* key6, int32_t value);
+/* *found = 1 and *value = the entry, or *found = 0. */
+mps_status mpsb_tune_get(const int32_t* key6, int32_t* value, int32_t* found);
+mps_status mpsb_tune_size(int64_t* n);
+/* Replaces the table with the file's entries (MPS_EINVAL on unreadable or
+ * malformed text, the table unchanged). */
+mps_status mpsb_tune_load(const char* path);
+mps_status mpsb_tune_save(const char* path);
+/* on != 0 clears earlier records and starts recording: every launch with a
+ * key is noted and timed with HIP events on its stream.  Recording costs
+ * two events per such launch. */
+mps_status mpsb_tune_record(int32_t on);
+/* Synchronises the device and returns up to cap records (keys: 6 int32
+ * each; value used last; allowed values as a bit set; launches; summed
+ * event time in ms); *n = the number of records (which may exceed cap).
+ * Host buffers. */
+mps_status mpsb_tune_records(int32_t* keys, int32_t* values, uint32_t* allowed,
+                             int64_t* launches, double* ms, int64_t cap,
+                             int64_t* n);
+
 #ifdef __cplusplus
 }
 #endif

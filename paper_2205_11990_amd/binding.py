@@ -96,6 +96,15 @@ _SIGS = {
     "mpsb_set_jacobi_max_sweeps": [_I32],
     "mpsb_profile": [_I32],
     "mpsb_profile_read": [_I32, _PI64, _PD, _PD, _PD],
+    "mpsb_tune_clear": [],
+    "mpsb_tune_set": [_PI32, _I32],
+    "mpsb_tune_get": [_PI32, _PI32, _PI32],
+    "mpsb_tune_size": [_PI64],
+    "mpsb_tune_load": [ctypes.c_char_p],
+    "mpsb_tune_save": [ctypes.c_char_p],
+    "mpsb_tune_record": [_I32],
+    "mpsb_tune_records": [_PI32, _PI32, ctypes.POINTER(ctypes.c_uint32), _PI64, _PD, _I64,
+                          _PI64],
 }
 
 EXPORTED = sorted(_SIGS)
@@ -633,3 +642,69 @@ def profile_read():
                                        ctypes.byref(by)))
         out[name] = {"launches": n.value, "ms": ms.value, "flops": fl.value, "bytes": by.value}
     return out
+
+
+# ---- launch-shape table (mpsb_tune_*)
+TUNE_GEMM_TILE, TUNE_APPLY_COLS = 1, 2
+
+
+def _key6(key):
+    k = np.ascontiguousarray(np.asarray(key, dtype=np.int32))
+    if k.shape != (6,):
+        raise ValueError("a tuning key has six integers")
+    return k
+
+
+def tune_clear():
+    _check(lib().mpsb_tune_clear())
+
+
+def tune_set(key, value: int):
+    k = _key6(key)
+    _check(lib().mpsb_tune_set(k.ctypes.data_as(_PI32), int(value)))
+
+
+def tune_get(key):
+    k = _key6(key)
+    v, f = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().mpsb_tune_get(k.ctypes.data_as(_PI32), ctypes.byref(v), ctypes.byref(f)))
+    return v.value if f.value else None
+
+
+def tune_size() -> int:
+    n = ctypes.c_int64()
+    _check(lib().mpsb_tune_size(ctypes.byref(n)))
+    return n.value
+
+
+def tune_load(path: str):
+    _check(lib().mpsb_tune_load(os.fsencode(path)))
+
+
+def tune_save(path: str):
+    _check(lib().mpsb_tune_save(os.fsencode(path)))
+
+
+def tune_record(on: bool):
+    _check(lib().mpsb_tune_record(1 if on else 0))
+
+
+def tune_records():
+    """Records since tune_record(True): a list of dicts with the key (six
+    ints), the value used, the allowed values, launches and summed ms."""
+    n = ctypes.c_int64()
+    _check(lib().mpsb_tune_records(None, None, None, None, None, 0, ctypes.byref(n)))
+    cap = n.value
+    keys = np.zeros((max(cap, 1), 6), dtype=np.int32)
+    vals = np.zeros(max(cap, 1), dtype=np.int32)
+    allowed = np.zeros(max(cap, 1), dtype=np.uint32)
+    launches = np.zeros(max(cap, 1), dtype=np.int64)
+    ms = np.zeros(max(cap, 1), dtype=np.float64)
+    _check(lib().mpsb_tune_records(keys.ctypes.data_as(_PI32), vals.ctypes.data_as(_PI32),
+                                   allowed.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                   launches.ctypes.data_as(_PI64), ms.ctypes.data_as(_PD),
+                                   cap, ctypes.byref(n)))
+    m = min(cap, n.value)
+    return [{"key": tuple(int(x) for x in keys[i]), "value": int(vals[i]),
+             "allowed": [b for b in range(32) if (int(allowed[i]) >> b) & 1],
+             "launches": int(launches[i]), "ms": float(ms[i])} for i in range(m)]

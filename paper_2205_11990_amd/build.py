@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libmpsvlasov.so")
 ARCH = os.environ.get("MPSV_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["gemm.hip", "linalg.hip", "mps_kernels.hip", "engine.cpp", "capi.cpp", "prof.cpp",
-           "jacobi.hip", "qr_reg.hip", "noalloc.hip"]
+           "jacobi.hip", "qr_reg.hip", "noalloc.hip", "tune.cpp"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
@@ -58,7 +58,7 @@ def build(verbose: bool = True) -> str:
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [_hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-pthread", "-o", tmp] + objs
+    cmd = [_hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-pthread", "-o", tmp] + objs + ["-ldl"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stderr)

@@ -20,6 +20,7 @@
 #include "linalg.hpp"
 #include "noalloc.hpp"
 #include "prof.hpp"
+#include "tune.hpp"
 
 struct mps_state {
   std::shared_ptr<mpsv::Engine> eng;
@@ -660,6 +661,73 @@ mps_status mpsb_set_jacobi_max_sweeps(int32_t n) {
   return guarded([&] {
     MPSV_CHECK(n >= 1, mpsv::kEinval, "sweep cap must be >= 1");
     mpsv::set_jacobi_max_sweeps(n);
+  });
+}
+
+mps_status mpsb_tune_clear(void) {
+  return guarded([&] { mpsv::tune_clear(); });
+}
+
+static mpsv::TuneKey tune_key(const int32_t* key6) {
+  MPSV_CHECK(key6 != nullptr, mpsv::kEinval, "tuning key missing");
+  mpsv::TuneKey k;
+  for (int i = 0; i < mpsv::kTuneKeyInts; ++i) k.v[i] = key6[i];
+  return k;
+}
+
+mps_status mpsb_tune_set(const int32_t* key6, int32_t value) {
+  return guarded([&] { mpsv::tune_set(tune_key(key6), value); });
+}
+
+mps_status mpsb_tune_get(const int32_t* key6, int32_t* value, int32_t* found) {
+  return guarded([&] {
+    int32_t v = 0;
+    const bool f = mpsv::tune_get(tune_key(key6), &v);
+    if (found) *found = f ? 1 : 0;
+    if (value && f) *value = v;
+  });
+}
+
+mps_status mpsb_tune_size(int64_t* n) {
+  return guarded([&] {
+    MPSV_CHECK(n != nullptr, mpsv::kEinval, "null output");
+    *n = mpsv::tune_size();
+  });
+}
+
+mps_status mpsb_tune_load(const char* path) {
+  return guarded([&] {
+    MPSV_CHECK(path != nullptr, mpsv::kEinval, "null path");
+    mpsv::tune_load(path);
+  });
+}
+
+mps_status mpsb_tune_save(const char* path) {
+  return guarded([&] {
+    MPSV_CHECK(path != nullptr, mpsv::kEinval, "null path");
+    mpsv::tune_save(path);
+  });
+}
+
+mps_status mpsb_tune_record(int32_t on) {
+  return guarded([&] { mpsv::tune_record(on != 0); });
+}
+
+mps_status mpsb_tune_records(int32_t* keys, int32_t* values, uint32_t* allowed,
+                             int64_t* launches, double* ms, int64_t cap,
+                             int64_t* n) {
+  return guarded([&] {
+    MPSV_CHECK(cap >= 0 && n != nullptr, mpsv::kEinval, "bad record buffer");
+    const auto r = mpsv::tune_records();
+    *n = (int64_t)r.size();
+    for (int64_t i = 0; i < (int64_t)r.size() && i < cap; ++i) {
+      if (keys)
+        for (int j = 0; j < mpsv::kTuneKeyInts; ++j) keys[i * mpsv::kTuneKeyInts + j] = r[i].key.v[j];
+      if (values) values[i] = r[i].value;
+      if (allowed) allowed[i] = r[i].allowed;
+      if (launches) launches[i] = r[i].launches;
+      if (ms) ms[i] = r[i].ms;
+    }
   });
 }
 

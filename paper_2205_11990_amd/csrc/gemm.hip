@@ -11,6 +11,7 @@
 
 #include "gemm.hpp"
 #include "prof.hpp"
+#include "tune.hpp"
 
 namespace mpsv {
 
@@ -380,24 +381,34 @@ void gemm(hipStream_t s, int M, int N, int K, double alpha, CMatView A,
   const int a_kfast = (A.cs == 1) ? 1 : 0;
   const int b_nfast = (B.cs == 1) ? 1 : 0;
   const int ninst = inst_count();
-  // FP64 products with at least two 128 x 128 tiles per compute unit take
-  // the large tiles
-  const bool big = prec == 0 && M >= TB && N >= TB && K >= TK &&
-                   (long)ceil_div(N, TB) * ceil_div(M, TB) * batch >= 512;
-  const int tm = big ? TB : BM, tn = big ? TB : BN;
-  const long tiles = (long)ceil_div(N, tn) * ceil_div(M, tm);
-  // split K when the output alone cannot fill the chip; the partial
-  // products live in the caller's workspace (none given: no split).  The
-  // choice ignores lock-step instances, so that every instance sums in the
-  // order a stand-alone state does.
+  // split K when the output alone (in 64 x 64 tiles) cannot fill the chip;
+  // the partial products live in the caller's workspace (none given: no
+  // split).  The choice ignores lock-step instances, so that every instance
+  // sums in the order a stand-alone state does.
+  const long tiles64 = (long)ceil_div(N, BN) * ceil_div(M, BM);
   int nsplit = 1;
-  if (!big && ws && K >= 4 * BK * 4 && tiles * batch < 256) {
-    long want = 512 / (tiles * batch);
+  if (ws && K >= 4 * BK * 4 && tiles64 * batch < 256) {
+    long want = 512 / (tiles64 * batch);
     long maxk = K / (4 * BK);
     const long fit = (long)(ws->max_alloc_bytes() / sizeof(double)) /
                      std::max(1L, (long)batch * M * N);
     nsplit = (int)std::max(1L, std::min(std::min(std::min(want, maxk), 64L), fit));
   }
+  // FP64 products with at least two 128 x 128 tiles per compute unit take
+  // the large tiles, unless the launch-shape table says otherwise for this
+  // shape and instance count (both tiles give the same bits: each output
+  // sums its K products in the same order on the same matrix-core
+  // instruction)
+  bool big = prec == 0 && nsplit == 1 && M >= TB && N >= TB && K >= TK &&
+             (long)ceil_div(N, TB) * ceil_div(M, TB) * batch >= 512;
+  TunePick tp{big ? 1 : 0, -1};
+  if (prec == 0 && nsplit == 1) {
+    const TuneKey key{{kTuneGemmTile, M, N, K, 4 * batch + 2 * a_kfast + b_nfast,
+                       tune_inst_class(ninst)}};
+    tp = tune_pick(s, key, big ? 1 : 0, 3u);
+    big = tp.value == 1;
+  }
+  const int tm = big ? TB : BM, tn = big ? TB : BN;
   const int kchunk = (nsplit > 1) ? ceil_div(ceil_div(K, nsplit), BK) * BK : K;
   if (nsplit > 1) nsplit = ceil_div(K, kchunk);
   const int bmax = std::max(1, 65535 / (nsplit * ninst));
@@ -446,6 +457,7 @@ void gemm(hipStream_t s, int M, int N, int K, double alpha, CMatView A,
     prof_end(s, slot, kClsGemm, 2.0 * M * N * (double)K * nb,
              8.0 * ((double)M * K + (double)K * N + 2.0 * M * N) * nb);
   }
+  tune_end(s, tp.slot);
 }
 
 namespace {

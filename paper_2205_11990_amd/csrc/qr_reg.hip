@@ -26,6 +26,7 @@
 
 #include "prof.hpp"
 #include "qr_reg.hpp"
+#include "tune.hpp"
 #include "wave.hpp"
 
 namespace mpsv {
@@ -825,6 +826,19 @@ void qr_reg_factor(hipStream_t s, CMatView A, int m, int n, MatView R,
            8.0 * (2.0 * m * n + (double)m * k));
 }
 
+// Columns per wave of a reflector application: the built-in rule, or the
+// launch-shape table's choice for this shape and instance count.  Every
+// choice gives the same bits: each column's products and reductions are
+// the same whichever wave carries it.  Up to 32 values of Y per lane.
+static TunePick apply_cols(hipStream_t s, int rows, int k, int p, int nch, int tr, int rpl) {
+  const int dflt = (p >= 128 && rpl < 32) ? 2 : 1;
+  uint32_t allowed = 1u << 1;
+  if (rpl < 32) allowed |= 1u << 2;
+  if (rpl <= 8) allowed |= 1u << 4;
+  const TuneKey key{{kTuneApplyCols, rows, k, p, 2 * nch + tr, tune_inst_class(inst_count())}};
+  return tune_pick(s, key, dflt, allowed);
+}
+
 void qr_reg_apply(hipStream_t s, const double* V, const double* tau, int m,
                   int k, CMatView Yin, int rows_in, MatView Yout, int p,
                   bool trans) {
@@ -832,19 +846,22 @@ void qr_reg_apply(hipStream_t s, const double* V, const double* tau, int m,
   MPSV_CHECK(m >= 1 && m <= 2048 && k <= m && k <= 128, kEinval,
              "qr_reg_apply: bad shape");
   const int rpl = rows_per_lane(m);
-  const int cpw = (p >= 128 && rpl < 32) ? 2 : 1;
-  const int slot = prof_begin(s);
   const int tr = trans ? 1 : 0;
+  const TunePick tp = apply_cols(s, m, k, p, 1, tr, rpl);
+  const int cpw = tp.value;
+  const int slot = prof_begin(s);
 #define MPSV_A(C, Rr)                                                   \
   if (cpw == C && rpl == Rr) launch_apply<C, Rr>(s, V, tau, m, k, Yin, rows_in, Yout, p, tr, Chunks{m, k}, 1); else
-  MPSV_A(1, 1) MPSV_A(2, 1) MPSV_A(1, 2) MPSV_A(2, 2) MPSV_A(1, 4) MPSV_A(2, 4)
-  MPSV_A(1, 8) MPSV_A(2, 8) MPSV_A(1, 16) MPSV_A(2, 16) MPSV_A(1, 32)
+  MPSV_A(1, 1) MPSV_A(2, 1) MPSV_A(4, 1) MPSV_A(1, 2) MPSV_A(2, 2) MPSV_A(4, 2)
+  MPSV_A(1, 4) MPSV_A(2, 4) MPSV_A(4, 4) MPSV_A(1, 8) MPSV_A(2, 8) MPSV_A(4, 8)
+  MPSV_A(1, 16) MPSV_A(2, 16) MPSV_A(1, 32)
   throw Error(kEinval, "qr_reg_apply: no kernel for this shape");
 #undef MPSV_A
   MPSV_LAUNCHED();
   // k reflectors of decreasing length applied to p columns
   prof_end(s, slot, kClsQrApply, 4.0 * p * (double)k * (m - (k - 1) / 2.0),
            8.0 * (2.0 * m * p + (double)m * k));
+  tune_end(s, tp.slot);
 }
 
 void qr_reg_factor_chunks(hipStream_t s, CMatView A, int m, int n, int rows,
@@ -878,19 +895,22 @@ void qr_reg_apply_chunks(hipStream_t s, const double* V, const double* tau,
   MPSV_CHECK(rows >= k && rows <= 2048 && k <= 128, kEinval,
              "qr_reg_apply_chunks: bad shape");
   const int rpl = rows_per_lane(rows);
-  const int cpw = (p >= 128 && rpl < 32) ? 2 : 1;
-  const int slot = prof_begin(s);
   const int tr = trans ? 1 : 0;
+  const TunePick tp = apply_cols(s, rows, k, p, nch, tr, rpl);
+  const int cpw = tp.value;
+  const int slot = prof_begin(s);
   const Chunks ch{rows, k};
   const CMatView Yin{Y.p, Y.rs, Y.cs, 0};
 #define MPSV_A(C, Rr)                                                   \
   if (cpw == C && rpl == Rr) launch_apply<C, Rr>(s, V, tau, m, k, Yin, m, Y, p, tr, ch, nch); else
-  MPSV_A(1, 1) MPSV_A(2, 1) MPSV_A(1, 2) MPSV_A(2, 2) MPSV_A(1, 4) MPSV_A(2, 4)
-  MPSV_A(1, 8) MPSV_A(2, 8) MPSV_A(1, 16) MPSV_A(2, 16) MPSV_A(1, 32)
+  MPSV_A(1, 1) MPSV_A(2, 1) MPSV_A(4, 1) MPSV_A(1, 2) MPSV_A(2, 2) MPSV_A(4, 2)
+  MPSV_A(1, 4) MPSV_A(2, 4) MPSV_A(4, 4) MPSV_A(1, 8) MPSV_A(2, 8) MPSV_A(4, 8)
+  MPSV_A(1, 16) MPSV_A(2, 16) MPSV_A(1, 32)
   throw Error(kEinval, "qr_reg_apply_chunks: no kernel for this shape");
 #undef MPSV_A
   MPSV_LAUNCHED();
   prof_end(s, slot, kClsQrApply, 4.0 * p * (double)k * m, 8.0 * (2.0 * m * p + (double)m * k));
+  tune_end(s, tp.slot);
 }
 
 }  // namespace mpsv
