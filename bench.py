@@ -285,25 +285,39 @@ def _errors(f, E, sc, ref):
                                                    / abs(ref["field_energy"]))}
 
 
-def chi128_run(binding, steps):
+def chi128_run(binding, steps, with_oracle=True):
     """The bond cap 128 workload: two-stream 2^12 x 2^12, interleaved,
     every point capped at 128, D_F = 4, tol = 0, seeded perturbation to
-    bond 128; FP64 steps/s and the reduced-precision modes against it."""
+    bond 128, started from the oracle's state; FP64 steps/s and the
+    reduced-precision modes against it and (with_oracle) against the CPU
+    MPS oracle's step from the same state (about a minute of host time)."""
     import torch
     w = wl.two_stream(L=12, chi=128, tol=0.0, level=5, df_max=4, dt_cfg=0.02)
-    st = start_state(binding, w, "fixed")
+    f0 = oracle_start(w, "fixed")
+    ref = None
+    if with_oracle:
+        from oracle import mps as omps
+        ops = omps.Operators(w.problem)
+        t0 = time.perf_counter()
+        f1 = omps.rk4_step(f0, ops)
+        t_or = time.perf_counter() - t0
+        ref = {"f": omps.to_dense(f1, w.problem), "E": omps.field_dense(f1, ops),
+               "field_energy": omps.moments(f1, ops)["field_energy"]}
+    st = binding.MpsState(w.problem, w.ax, w.bv)
+    st.set_cores(f0)
     st.step(1)
     torch.cuda.synchronize()
-    cores = st.get_cores_host()
     t0 = time.perf_counter()
     st.step(steps)
     torch.cuda.synchronize()
     v = steps / (time.perf_counter() - t0)
     st.free()
     out = {"workload": "two-stream 2^12 x 2^12, interleaved (24 sites), chi=128, C5, tol=0, "
-                       "D_F=4, seeded random-MPS perturbation",
+                       "D_F=4, seeded random-MPS perturbation (start state built by the oracle)",
            "dt": w.problem.dt}
-    out.update(mixed_precision(binding, w, cores, steps, fp64_steps_per_s=v))
+    if ref is not None:
+        out["oracle_s_per_step"] = t_or
+    out.update(mixed_precision(binding, w, f0, steps, fp64_steps_per_s=v, oracle=ref))
     return out
 
 
@@ -711,7 +725,7 @@ def main():
         print("[bench] mixed %s" % json.dumps(extras["mixed"]), file=sys.stderr, flush=True)
         extras["physics"] = physics_run(binding, 5)
         print("[bench] physics %s" % json.dumps(extras["physics"]), file=sys.stderr, flush=True)
-        extras["chi128"] = chi128_run(binding, 3)
+        extras["chi128"] = chi128_run(binding, 3, with_oracle=not args.no_cpu_baseline)
         print("[bench] chi128 %s" % json.dumps(extras["chi128"]), file=sys.stderr, flush=True)
         extras["buneman"] = buneman_run(binding, 3)
         print("[bench] buneman %s" % json.dumps(extras["buneman"]), file=sys.stderr, flush=True)

@@ -60,6 +60,28 @@ def test_serving_results_same_alone_and_in_the_mix(S):
     assert all(r.admitted >= r.arrival - 1e-3 for r in mixed)
 
 
+def test_serving_many_overlapping_requests(S):
+    """48 small requests through 16 slots: more streams are created than
+    torch's stream pool holds (32 per device), so later requests reuse the
+    streams of earlier ones, some of them still running.  Every result is
+    still the one it has alone (the library keeps no state per stream)."""
+    _say("serving 48 requests")
+    reqs = _requests(S, n=48, seed=4)
+    alone = [S.run_alone(r) for r in reqs]
+    mixed = S.Server(budget_bytes=64 << 30, slots=16).run(reqs, realtime=False)
+    for a, m in zip(alone, mixed):
+        assert a.error is None and m.error is None, (a.error, m.error)
+        assert m.bonds == a.bonds
+        assert m.scalars == a.scalars
+    # the slots really overlapped
+    ev = sorted([(r.admitted, 1) for r in mixed] + [(r.finished, -1) for r in mixed])
+    live = peak = 0
+    for _, d in ev:
+        live += d
+        peak = max(peak, live)
+    assert peak >= 8
+
+
 def test_serving_budget_limits_concurrency(S):
     _say("serving budget")
     from paper_2205_11990_amd import binding
