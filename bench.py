@@ -25,10 +25,10 @@ Beside the metric line, three measurements of the same JSON object
            from f0): steps/s, bonds, truncated SVDs (host round trips) per step.
   chi128   bond cap 128 on a 2^12 x 2^12 two-stream grid (fixed-chi mode):
            FP64 steps/s and the same mixed-precision comparison.
-  batched_metric  the metric's workload as one lock-step batch of 64
-           instances (mps_batch_*: every launch covers all of them):
-           aggregate steps/s against the single instance, and the rate of
-           the dominant kernel class.
+  batched_metric  the metric's workload as one lock-step batch of 256
+           instances (--batch; mps_batch_*: every launch covers all of them):
+           aggregate steps/s against the single instance, the rate of the
+           dominant kernel class, and the aggregate rate at 64 and 128.
   batched  64 Landau instances of a parameter sweep (k, alpha, 2^8..2^11
            grids, chi in {16, 32, 48, 64}, fixed rank), one lock-step batch
            per (grid, chi) shape: aggregate steps/s against stepping them one
@@ -464,32 +464,51 @@ def graph_run(binding, w, cores, steps, eager_steps_per_s):
             "captures": caps, "replays": reps}
 
 
-def batched_metric(binding, count, steps, single_steps_per_s):
-    """The metric's workload as a lock-step batch of `count` instances: every
-    kernel launch covers all of them.  Aggregate steps/s (count x steps over
-    the timed window) against the single instance's, and the rate of the
-    dominant kernel class over the instances of its launches."""
-    import torch
+def _metric_batch(binding, count):
     ws = metric_sweep(count)
     p = ws[0].problem
     bt = binding.Batch([w.problem for w in ws], [(w.ax, w.bv) for w in ws])
     perts = [wl.random_mps_cores(p.n_sites, p.chi_max, seed=2205 + i) for i in range(count)]
     amps = [1e-6 * float(np.linalg.norm(w.ax) * np.linalg.norm(w.bv)) for w in ws]
     bt.add_scaled(amps, perts)
+    return bt
+
+
+def _batch_rate(binding, bt, count, steps):
+    import torch
     bt.step(1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     bt.step(steps)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    agg = count * steps / el
+    return count * steps / el, el / steps
+
+
+def batched_metric(binding, count, steps, single_steps_per_s, smaller=(64, 128)):
+    """The metric's workload as a lock-step batch of `count` instances: every
+    kernel launch covers all of them.  Aggregate steps/s (count x steps over
+    the timed window) against the single instance's, the rate of the
+    dominant kernel class over the instances of its launches, and the
+    aggregate rate of smaller batches (2 timed steps each)."""
+    scaling = {}
+    for n in smaller:
+        if n >= count:
+            continue
+        bt = _metric_batch(binding, n)
+        scaling[str(n)] = round(_batch_rate(binding, bt, n, 2)[0], 2)
+        bt.free()
+    bt = _metric_batch(binding, count)
+    agg, sec = _batch_rate(binding, bt, count, steps)
+    scaling[str(count)] = round(agg, 2)
     roof = _class_rates(binding, lambda: bt.step(1), 1)
     roof["workgroups_per_launch_jacobi"] = count
     out = {"workload": "%d lock-step instances of two-stream 2^10 x 2^10, interleaved, chi=64, "
                        "C5, tol=0, D_F=4 (amplitudes 1e-3 (1 + i/10), seeded perturbations)" % count,
-           "instances": count, "steps_each": steps, "ms_per_batched_step": 1000.0 * el / steps,
+           "instances": count, "steps_each": steps, "ms_per_batched_step": 1000.0 * sec,
            "aggregate_steps_per_s": agg,
            "speedup_vs_single_instance": agg / single_steps_per_s if single_steps_per_s else None,
+           "aggregate_steps_per_s_by_instances": scaling,
            "device_bytes": bt.instance(0).device_bytes(), "roofline": roof}
     bt.free()
     return out
@@ -620,7 +639,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--mode", default="fixed", choices=["fixed", "physics"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--batch", type=int, default=64,
+    ap.add_argument("--batch", type=int, default=256,
                     help="instances of the lock-step batch of the metric's workload")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
@@ -671,7 +690,7 @@ def main():
         return
 
     if args.batched_only:
-        print(json.dumps(batched_metric(binding, args.batch, args.steps, None)))
+        print(json.dumps(batched_metric(binding, args.batch, args.steps, None, smaller=())))
         return
 
     w = make_workload(args.mode)

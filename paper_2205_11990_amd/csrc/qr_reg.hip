@@ -23,6 +23,7 @@
 // same application kernel (blocked right-looking QR without a T factor).
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "prof.hpp"
 #include "qr_reg.hpp"
@@ -736,6 +737,135 @@ __global__ __launch_bounds__(AT) void qr_reg_apply_kernel(
     }
 }
 
+// Reflector application with the reflectors shared by the waves of a
+// workgroup through LDS (rows of 257 to 2048, one reflector at a time).
+// Blocks of RB reflectors are loaded once per workgroup, coalesced, into one
+// of two LDS buffers while the other is applied; each of the LT / 64 waves
+// carries CPW columns and reads every reflector from LDS instead of
+// streaming its own copy from L2.  Column by column the arithmetic is that
+// of qr_reg_apply_kernel's one-reflector path (the same products in the same
+// order, the same cross-lane sums), so the two kernels give the same bits.
+// Every wave takes part in the loads and barriers, also one whose columns
+// lie past p.
+constexpr int LT = 512;  // 8 waves
+
+template <int RPL>
+constexpr int lds_block() { return RPL >= 16 ? 4 : 8; }
+
+template <int RPL>
+constexpr size_t lds_apply_bytes() {
+  return (size_t)2 * lds_block<RPL>() * 64 * RPL * sizeof(double);
+}
+
+template <int CPW, int RPL>
+__global__ __launch_bounds__(LT) void qr_lds_apply_kernel(
+    const double* __restrict__ V, const double* __restrict__ tau, int m, int k,
+    CMatView Yin, int rows_in, MatView Yout, int p, int trans, Chunks ch,
+    InstOff io) {
+  constexpr int R = 64 * RPL;             // rows of one reflector slot
+  constexpr int RB = lds_block<RPL>();    // reflectors per block
+  constexpr int PER = RB * R / LT;        // values each thread stages per block
+  static_assert(RB * R % LT == 0, "block must divide over the workgroup");
+  extern __shared__ double vs[];          // [2][RB][R]
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  {
+    const long o_ = io.of(blockIdx.z);
+    V = shifted(V, o_);
+    tau = shifted(tau, o_);
+    Yin = shifted(Yin, o_);
+    Yout = shifted(Yout, o_);
+  }
+  {
+    const int cb = blockIdx.y;
+    const int row0 = cb * ch.rows;
+    const int mc = min(ch.rows, m - row0);
+    V += (long)cb * ch.rows * ch.kstride;
+    tau += (long)cb * ch.kstride;
+    k = min(k, mc);
+    rows_in = min(rows_in - row0, mc);
+    m = mc;
+    Yin.p += (long)row0 * Yin.rs;
+    Yout.p += (long)row0 * Yout.rs;
+  }
+  const int c0 = (blockIdx.x * (LT / 64) + w) * CPW;
+  const bool active = c0 < p;
+  double y[RPL][CPW];
+#pragma unroll
+  for (int a = 0; a < RPL; ++a)
+#pragma unroll
+    for (int b = 0; b < CPW; ++b) {
+      const int i = l + 64 * a;
+      y[a][b] = (active && i < rows_in && c0 + b < p)
+                    ? Yin.p[(long)i * Yin.rs + (long)(c0 + b) * Yin.cs] : 0.0;
+    }
+  const double ta = (l < k) ? tau[l] : 0.0;
+  const double tb = (l + 64 < k) ? tau[l + 64] : 0.0;
+  const int nb = (k + RB - 1) / RB;
+  double st[PER];
+  // element e of block t: reflector step t * RB + e / R, row e % R (rows
+  // past m and steps past k stage zeros)
+  auto fetch = [&](int t) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + q * LT;
+      const int r = e % R;
+      const int sidx = t * RB + e / R;
+      const long j = trans ? sidx : k - 1 - sidx;
+      st[q] = (sidx < k && r < m) ? V[j * m + r] : 0.0;
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) vs[(long)buf * RB * R + tid + q * LT] = st[q];
+  };
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  for (int t = 0; t < nb; ++t) {
+    const int buf = t & 1;
+    if (t + 1 < nb) fetch(t + 1);
+    if (active) {
+      for (int i = 0; i < RB; ++i) {
+        const int sidx = t * RB + i;
+        if (sidx >= k) break;  // uniform
+        const int j = trans ? sidx : k - 1 - sidx;
+        const double tj = wave::read_lane(j < 64 ? ta : tb, j & 63);
+        if (tj == 0.0) continue;
+        const double* vp = vs + ((long)buf * RB + i) * R + l;
+        double v[RPL];
+#pragma unroll
+        for (int a = 0; a < RPL; ++a) v[a] = vp[64 * a];
+        double d[CPW];
+#pragma unroll
+        for (int b = 0; b < CPW; ++b) {
+          double acc = 0.0;
+#pragma unroll
+          for (int a = 0; a < RPL; ++a) acc = fma(v[a], y[a][b], acc);
+          d[b] = acc;
+        }
+        wave::sums<CPW>(d);
+#pragma unroll
+        for (int b = 0; b < CPW; ++b) {
+          const double f = tj * d[b];
+#pragma unroll
+          for (int a = 0; a < RPL; ++a) y[a][b] = fma(-v[a], f, y[a][b]);
+        }
+      }
+    }
+    // buffer buf ^ 1 was last read before the previous barrier
+    if (t + 1 < nb) stash(buf ^ 1);
+    __syncthreads();
+  }
+  if (!active) return;
+#pragma unroll
+  for (int a = 0; a < RPL; ++a)
+#pragma unroll
+    for (int b = 0; b < CPW; ++b) {
+      const int i = l + 64 * a;
+      if (i < m && c0 + b < p) Yout.p[(long)i * Yout.rs + (long)(c0 + b) * Yout.cs] = y[a][b];
+    }
+}
+
 int rows_per_lane(int m) {
   int r = 1;
   while (64 * r < m) r *= 2;
@@ -763,6 +893,23 @@ void launch_apply(hipStream_t s, const double* V, const double* tau, int m,
   hipLaunchKernelGGL((qr_reg_apply_kernel<CPW, RPL>),
                      dim3(ceil_div(p, per_block), nchunks, inst_count()), dim3(AT), 0, s,
                      V, tau, m, k, Yin, rows_in, Yout, p, trans, ch, inst_off());
+}
+
+template <int CPW, int RPL>
+void launch_lds_apply(hipStream_t s, const double* V, const double* tau, int m,
+                      int k, CMatView Yin, int rows_in, MatView Yout, int p,
+                      int trans, Chunks ch, int nchunks) {
+  static std::once_flag once;
+  std::call_once(once, [] {
+    MPSV_HIP(hipFuncSetAttribute((const void*)qr_lds_apply_kernel<CPW, RPL>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)lds_apply_bytes<RPL>()));
+  });
+  const int per_block = (LT / 64) * CPW;
+  hipLaunchKernelGGL((qr_lds_apply_kernel<CPW, RPL>),
+                     dim3(ceil_div(p, per_block), nchunks, inst_count()), dim3(LT),
+                     lds_apply_bytes<RPL>(), s, V, tau, m, k, Yin, rows_in, Yout, p, trans,
+                     ch, inst_off());
 }
 
 }  // namespace
@@ -826,15 +973,21 @@ void qr_reg_factor(hipStream_t s, CMatView A, int m, int n, MatView R,
            8.0 * (2.0 * m * n + (double)m * k));
 }
 
-// Columns per wave of a reflector application: the built-in rule, or the
+// Variant of a reflector application: columns per wave (1, 2 or 4) of the
+// register-streaming kernel, or 8 + columns per wave (1, or 2 up to 1024
+// rows) of the kernel that shares the reflectors through LDS; the built-in rule, or the
 // launch-shape table's choice for this shape and instance count.  Every
 // choice gives the same bits: each column's products and reductions are
-// the same whichever wave carries it.  Up to 32 values of Y per lane.
+// the same whichever wave and kernel carry it.
 static TunePick apply_cols(hipStream_t s, int rows, int k, int p, int nch, int tr, int rpl) {
   const int dflt = (p >= 128 && rpl < 32) ? 2 : 1;
   uint32_t allowed = 1u << 1;
   if (rpl < 32) allowed |= 1u << 2;
   if (rpl <= 8) allowed |= 1u << 4;
+  // reflectors shared through LDS (values 8 + columns per wave), 257 to
+  // 2048 rows
+  if (rpl >= 8) allowed |= 1u << 9;
+  if (rpl >= 8 && rpl < 32) allowed |= 1u << 10;
   const TuneKey key{{kTuneApplyCols, rows, k, p, 2 * nch + tr, tune_inst_class(inst_count())}};
   return tune_pick(s, key, dflt, allowed);
 }
@@ -852,10 +1005,14 @@ void qr_reg_apply(hipStream_t s, const double* V, const double* tau, int m,
   const int slot = prof_begin(s);
 #define MPSV_A(C, Rr)                                                   \
   if (cpw == C && rpl == Rr) launch_apply<C, Rr>(s, V, tau, m, k, Yin, rows_in, Yout, p, tr, Chunks{m, k}, 1); else
+#define MPSV_L(C, Rr)                                                   \
+  if (cpw == 8 + C && rpl == Rr) launch_lds_apply<C, Rr>(s, V, tau, m, k, Yin, rows_in, Yout, p, tr, Chunks{m, k}, 1); else
   MPSV_A(1, 1) MPSV_A(2, 1) MPSV_A(4, 1) MPSV_A(1, 2) MPSV_A(2, 2) MPSV_A(4, 2)
   MPSV_A(1, 4) MPSV_A(2, 4) MPSV_A(4, 4) MPSV_A(1, 8) MPSV_A(2, 8) MPSV_A(4, 8)
   MPSV_A(1, 16) MPSV_A(2, 16) MPSV_A(1, 32)
+  MPSV_L(1, 8) MPSV_L(2, 8) MPSV_L(1, 16) MPSV_L(2, 16) MPSV_L(1, 32)
   throw Error(kEinval, "qr_reg_apply: no kernel for this shape");
+#undef MPSV_L
 #undef MPSV_A
   MPSV_LAUNCHED();
   // k reflectors of decreasing length applied to p columns
@@ -903,10 +1060,14 @@ void qr_reg_apply_chunks(hipStream_t s, const double* V, const double* tau,
   const CMatView Yin{Y.p, Y.rs, Y.cs, 0};
 #define MPSV_A(C, Rr)                                                   \
   if (cpw == C && rpl == Rr) launch_apply<C, Rr>(s, V, tau, m, k, Yin, m, Y, p, tr, ch, nch); else
+#define MPSV_L(C, Rr)                                                   \
+  if (cpw == 8 + C && rpl == Rr) launch_lds_apply<C, Rr>(s, V, tau, m, k, Yin, m, Y, p, tr, ch, nch); else
   MPSV_A(1, 1) MPSV_A(2, 1) MPSV_A(4, 1) MPSV_A(1, 2) MPSV_A(2, 2) MPSV_A(4, 2)
   MPSV_A(1, 4) MPSV_A(2, 4) MPSV_A(4, 4) MPSV_A(1, 8) MPSV_A(2, 8) MPSV_A(4, 8)
   MPSV_A(1, 16) MPSV_A(2, 16) MPSV_A(1, 32)
+  MPSV_L(1, 8) MPSV_L(2, 8) MPSV_L(1, 16) MPSV_L(2, 16) MPSV_L(1, 32)
   throw Error(kEinval, "qr_reg_apply_chunks: no kernel for this shape");
+#undef MPSV_L
 #undef MPSV_A
   MPSV_LAUNCHED();
   prof_end(s, slot, kClsQrApply, 4.0 * p * (double)k * m, 8.0 * (2.0 * m * p + (double)m * k));

@@ -3,7 +3,8 @@
 // Some launches have several kernel variants that compute bit-identical
 // results: they differ only in how the same arithmetic is spread over
 // workgroups and waves (the output tile of the FP64 GEMM; the number of
-// columns one wave carries through a reflector application).  Which one is
+// columns one wave carries through a reflector application, and whether the
+// reflectors reach the waves from L2 or shared through LDS).  Which one is
 // fastest depends on the exact shape and on how many lock-step instances a
 // launch covers.  The table maps (knob, exact shape, instance class) to a
 // variant; an offline tuner (paper_2205_11990_amd/tune.py) times the
@@ -29,7 +30,7 @@ namespace mpsv {
 
 enum TuneKnob : int32_t {
   kTuneGemmTile = 1,   // 0: 64 x 64 output tiles, 1: 128 x 128
-  kTuneApplyCols = 2,  // columns per wave: 1, 2 or 4
+  kTuneApplyCols = 2,  // columns per wave: 1, 2 or 4; LDS-shared: 8 + 1 or 2
 };
 
 constexpr int kTuneKeyInts = 6;

@@ -2,8 +2,10 @@
 
 Two launches of the library have kernel variants that compute the same bits
 and differ only in how the work is spread over the device: the output tile
-of the FP64 GEMM (64 x 64 or 128 x 128) and the columns each wave carries
-through a Householder reflector application (1, 2 or 4).  Which is fastest
+of the FP64 GEMM (64 x 64 or 128 x 128) and, for a Householder reflector
+application, the columns each wave carries (1, 2 or 4) and whether the
+reflectors are streamed into each wave's registers or shared by the waves of
+a workgroup through LDS (values 9 and 10: 1 or 2 columns per wave).  Which is fastest
 depends on the exact shape and on how many lock-step instances a launch
 covers, so the library looks each launch up in a table keyed by both (see
 mps_blocks.h, mpsb_tune_*); this script writes that table.
@@ -15,14 +17,16 @@ of them at once), each launch timed with HIP events on its own stream.  A
 key's value is the one with the least summed launch time, kept only when it
 beats the built-in rule by more than --min-gain and by at least 10 us per
 step; otherwise the key gets no entry.  Last, the whole step is timed with
-and without the table found (alternately, best of two each).
+and without the entries found (alternately, best of two each); they go into
+the table only when the whole step is faster with them (--min-step-gain).
 
 Usage (on the GPU):
   python -m paper_2205_11990_amd.tune [--workloads two_stream_1024,...]
                                       [--reps 3] [--out PATH]
-Workloads: two_stream_1024 (2^10 x 2^10, chi 64, fixed rank), batch64
-(64 lock-step instances of it), two_stream_4096 (2^12 x 2^12, chi 128),
-landau_sweep (the 64-instance Landau sweep in its lock-step groups).
+Workloads: two_stream_1024 (2^10 x 2^10, chi 64, fixed rank), batchN
+(N lock-step instances of it, e.g. batch256), two_stream_4096 (2^12 x 2^12,
+chi 128), landau_sweep (the 64-instance Landau sweep in its lock-step
+groups).
 """
 from __future__ import annotations
 
@@ -54,7 +58,7 @@ def _two_stream(L, chi, amp_scale=1.0, seed=2205):
     return st
 
 
-def _batch64(n=64):
+def _batch(n):
     ws = []
     for i in range(n):
         w = wl.two_stream(L=10, chi=64, tol=0.0, level=5, df_max=4, dt_cfg=0.02)
@@ -92,9 +96,10 @@ def _runners(name):
     if name == "two_stream_4096":
         st = _two_stream(12, 128)
         return [("two-stream 2^12 chi 128", st.step, st.free)]
-    if name == "batch64":
-        bt = _batch64()
-        return [("64 x two-stream 2^10 chi 64", bt.step, bt.free)]
+    if name.startswith("batch"):
+        n = int(name[5:])
+        bt = _batch(n)
+        return [("%d x two-stream 2^10 chi 64" % n, bt.step, bt.free)]
     if name == "landau_sweep":
         return [("landau sweep group %d (%d instances)" % (i, b.count), b.step, b.free)
                 for i, b in enumerate(_landau_groups())]
@@ -178,10 +183,12 @@ def _wall(step, n):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workloads", default="two_stream_1024,batch64,two_stream_4096,landau_sweep")
+    ap.add_argument("--workloads", default="two_stream_1024,batch256,two_stream_4096,landau_sweep")
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--min-gain", type=float, default=0.03)
     ap.add_argument("--wall-steps", type=int, default=3)
+    ap.add_argument("--min-step-gain", type=float, default=0.01,
+                    help="a workload's entries are kept only when its whole step gets this much faster")
     ap.add_argument("--out", default=DEFAULT_OUT)
     args = ap.parse_args()
     import torch
@@ -191,9 +198,9 @@ def main():
     for name in args.workloads.split(","):
         for label, step, free in _runners(name):
             chosen, default = tune_state(label, step, args.reps, args.min_gain, log)
-            table.update(chosen)
             # whole-step wall time: built-in rules against the table found,
-            # measured alternately, the best of two each
+            # measured alternately, the best of two each; the entries are
+            # kept only when the whole step is faster with them
             t_def, t_tun = [], []
             for _ in range(2):
                 for k in default:
@@ -203,8 +210,13 @@ def main():
                     B.tune_set(k, v)
                 t_tun.append(_wall(step, args.wall_steps))
             t_def, t_tun = min(t_def), min(t_tun)
+            kept = t_tun < (1.0 - args.min_step_gain) * t_def
+            if kept:
+                table.update(chosen)
+            for k in default:
+                B.tune_set(k, -1)
             walls.append({"state": label, "ms_per_step_builtin": round(1e3 * t_def, 2),
-                          "ms_per_step_tuned": round(1e3 * t_tun, 2)})
+                          "ms_per_step_tuned": round(1e3 * t_tun, 2), "kept": kept})
             print(json.dumps(walls[-1]), flush=True)
             free()
             _sync()
@@ -221,11 +233,13 @@ def main():
         f.write("# paper_2205_11990_amd/tune.py (--workloads %s --reps %d --min-gain %g).\n"
                 % (args.workloads, args.reps, args.min_gain))
         f.write("# knob 1: FP64 GEMM tile (0: 64x64, 1: 128x128), key M N K 4*batch+layout;\n")
-        f.write("# knob 2: reflector columns per wave, key rows reflectors columns 2*chunks+trans;\n")
+        f.write("# knob 2: reflector application (1, 2, 4 columns per wave; 9, 10: LDS-shared with 1, 2),\n")
+        f.write("#         key rows reflectors columns 2*chunks+trans;\n")
         f.write("# class: lock-step instances (0: 1, 1: 2-7, 2: 8-31, 3: 32+).\n")
         for w in walls:
-            f.write("# %s: %.2f ms/step with the built-in rules, %.2f with this table\n"
-                    % (w["state"], w["ms_per_step_builtin"], w["ms_per_step_tuned"]))
+            f.write("# %s: %.2f ms/step with the built-in rules, %.2f with its entries (%s)\n"
+                    % (w["state"], w["ms_per_step_builtin"], w["ms_per_step_tuned"],
+                       "kept" if w["kept"] else "not kept: under the step-gain threshold"))
         f.write(body)
     print(json.dumps({"entries": len(table), "out": args.out, "walls": walls}), flush=True)
 
