@@ -33,6 +33,9 @@ Beside the metric line, three measurements of the same JSON object
            grids, chi in {16, 32, 48, 64}, fixed rank), one lock-step batch
            per (grid, chi) shape: aggregate steps/s against stepping them one
            after the other and against one stream per instance.
+  The batched legs apply the reflectors of tall blocks as compact-WY blocks
+  on the matrix cores (mps_problem.tall_apply = 1, the throughput choice);
+  the single-instance metric applies them one at a time (the default).
   tuning   the launch-shape table in use (tune.py; its variants give the
            same bits, so it changes speed only) and its entry count.
   serving  seeded Poisson arrivals (mean 20 requests/s) of Landau and
@@ -431,13 +434,16 @@ def _class_rates(binding, run, steps):
             "step_gflop": sum(v["flops"] for k, v in rec.items() if k in _CLASS_BOUND) / steps / 1e9}
 
 
-def metric_sweep(count):
+def metric_sweep(count, tall_apply=1):
     """`count` instances of the metric's workload (two-stream 2^10 x 2^10,
     interleaved, chi = 64, fixed-chi mode) with amplitudes
-    alpha = 1e-3 (1 + i/10) and the seeded perturbation of seed 2205 + i."""
+    alpha = 1e-3 (1 + i/10) and the seeded perturbation of seed 2205 + i;
+    tall blocks apply their reflectors as compact-WY blocks on the matrix
+    cores (tall_apply = 1, the throughput choice for large batches)."""
     ws = []
     for i in range(count):
         w = make_workload("fixed")
+        w.problem.tall_apply = tall_apply
         ax, bv = wl.two_stream_profiles(w.problem, 0.2, 1e-3 * (1 + 0.1 * i))
         ws.append(wl.Workload("two_stream_%d" % i, w.problem, ax, bv, 10))
     return ws
@@ -464,8 +470,8 @@ def graph_run(binding, w, cores, steps, eager_steps_per_s):
             "captures": caps, "replays": reps}
 
 
-def _metric_batch(binding, count):
-    ws = metric_sweep(count)
+def _metric_batch(binding, count, tall_apply=1):
+    ws = metric_sweep(count, tall_apply)
     p = ws[0].problem
     bt = binding.Batch([w.problem for w in ws], [(w.ax, w.bv) for w in ws])
     perts = [wl.random_mps_cores(p.n_sites, p.chi_max, seed=2205 + i) for i in range(count)]
@@ -504,7 +510,8 @@ def batched_metric(binding, count, steps, single_steps_per_s, smaller=(64, 128))
     roof = _class_rates(binding, lambda: bt.step(1), 1)
     roof["workgroups_per_launch_jacobi"] = count
     out = {"workload": "%d lock-step instances of two-stream 2^10 x 2^10, interleaved, chi=64, "
-                       "C5, tol=0, D_F=4 (amplitudes 1e-3 (1 + i/10), seeded perturbations)" % count,
+                       "C5, tol=0, D_F=4 (amplitudes 1e-3 (1 + i/10), seeded perturbations), "
+                       "compact-WY reflector application on tall blocks" % count,
            "instances": count, "steps_each": steps, "ms_per_batched_step": 1000.0 * sec,
            "aggregate_steps_per_s": agg,
            "speedup_vs_single_instance": agg / single_steps_per_s if single_steps_per_s else None,
@@ -520,11 +527,14 @@ def batched_sweep(binding, count, steps):
     point capped): instances of one (grid, chi) shape form a lock-step
     batch with one dt (the smallest stable one of its members); aggregate
     steps/s of the batches against the same instances stepped one after
-    the other, and against one stream per instance (mps_step_batched)."""
+    the other, and against one stream per instance (mps_step_batched).
+    Every instance applies the reflectors of tall blocks as compact-WY
+    blocks (tall_apply = 1) in all three runs."""
     import torch
     ws = wl.landau_sweep(count)
     for w in ws:
         w.problem.tol, w.problem.level = 0.0, 5
+        w.problem.tall_apply = 1  # the throughput choice (also for the sequential runs)
     groups = {}
     for w in ws:
         groups.setdefault((w.problem.Lx, w.problem.chi_max), []).append(w)

@@ -175,9 +175,10 @@ mps_status mpsb_profile_read(int32_t cls, int64_t* launches, double* ms,
  * workgroups and waves: the output tile of the FP64 GEMM (knob 1: value 0
  * = 64 x 64, 1 = 128 x 128; used when K is not split) and the kernel of a
  * Householder reflector application (knob 2: value 1, 2 or 4 columns per
- * wave streaming the reflectors into registers, or 9 or 10 for 1 or 2
- * columns per wave with the reflectors shared by a workgroup through LDS,
- * from 257 rows).
+ * wave streaming the reflectors into registers; 9 or 10 for 1 or 2 columns
+ * per wave with the reflectors shared by a workgroup through LDS, from 257
+ * rows; 17 or 18 for the same with the block of columns also staged
+ * through LDS, read and written row by row).
  * A table maps a key of six integers {knob, a, b, c, d, instance class}
  * to a value; a launch whose exact key is in the table (and whose value is
  * valid for it) takes that variant, any other the built-in rule.  Keys:

@@ -148,7 +148,24 @@ typedef struct mps_problem {
   double nu;                /* Dougherty collision rate, >= 0 (0: none)    */
   double nu_v0, nu_vth;     /* drift and thermal speed of coll_model 1     */
   int32_t coll_model;       /* 0: v0, vth from the moments of f; 1: fixed  */
+  int32_t tall_apply;       /* mps_tall_apply (0: one reflector at a time) */
 } mps_problem;
+
+/* How the QR sweeps apply their Householder reflectors to tall blocks (more
+ * than 512 rows, panels of up to 16 reflectors, at least 32 columns; SI,
+ * Canonicalization and Compression: the QR of each site).  Both are exact
+ * applications of the same orthogonal factor; their results differ at the
+ * rounding level, and a state's results depend on this choice, never on
+ * how many lock-step instances share its launches.
+ *   MPS_TALL_APPLY_REFLECTORS: one reflector at a time, each column in the
+ *     registers of one wave (shortest chain: fastest for one state);
+ *   MPS_TALL_APPLY_WY: the panel's reflectors as one compact-WY block on the
+ *     matrix cores, the block streamed twice (fastest for large lock-step
+ *     batches, where the launches fill the device). */
+typedef enum mps_tall_apply {
+  MPS_TALL_APPLY_REFLECTORS = 0,
+  MPS_TALL_APPLY_WY = 1
+} mps_tall_apply;
 
 /* Collisions (Methods, "Collision Operator"): with nu > 0 the Vlasov
  * right-hand side gains the Dougherty operator

@@ -39,7 +39,7 @@ class CProblem(ctypes.Structure):
         ("precision", ctypes.c_int32), ("x_scheme", ctypes.c_int32),
         ("cfl", ctypes.c_double), ("compression", ctypes.c_int32),
         ("nu", ctypes.c_double), ("nu_v0", ctypes.c_double), ("nu_vth", ctypes.c_double),
-        ("coll_model", ctypes.c_int32),
+        ("coll_model", ctypes.c_int32), ("tall_apply", ctypes.c_int32),
     ]
 
 
@@ -180,6 +180,7 @@ def make_problem(p) -> CProblem:
     c.nu_v0 = float(getattr(p, "nu_v0", 0.0))
     c.nu_vth = float(getattr(p, "nu_vth", 1.0))
     c.coll_model = int(getattr(p, "coll_model", 0))
+    c.tall_apply = int(getattr(p, "tall_apply", 0))
     return c
 
 

@@ -106,6 +106,7 @@ mpsv::Problem convert(const mps_problem* p) {
   q.nu_v0 = p->nu_v0;
   q.nu_vth = p->nu_vth;
   q.coll_model = p->coll_model;
+  q.tall_apply = p->tall_apply;
   MPSV_CHECK(std::isfinite(q.x_min) && std::isfinite(q.x_max) &&
                  std::isfinite(q.v_min) && std::isfinite(q.v_max),
              mpsv::kEinval, "grid bounds must be finite");
@@ -866,6 +867,8 @@ mps_status mps_plasma_init(int32_t n_species, const mps_problem* species,
                  mpsv::kEinval, "species must share the x grid");
       MPSV_CHECK(b.dt == a.dt && b.cfl == 0.0, mpsv::kEinval,
                  "species must share a fixed dt (cfl = 0)");
+      MPSV_CHECK(b.tall_apply == a.tall_apply, mpsv::kEinval,
+                 "species must share the reflector application mode");
       MPSV_CHECK(std::isfinite(charges[i]), mpsv::kEinval, "charge must be finite");
       MPSV_CHECK(ax[i] && bv[i], mpsv::kEinval, "profiles must not be NULL");
     }

@@ -66,6 +66,10 @@ struct Lanes {
   int n = 1;         // instances covered by a launch
   long first = 0;    // bytes: offset of the launch's instance 0
   long stride = 0;   // bytes between consecutive instances
+  // the problem's choice of kernel for reflector applications on tall
+  // blocks (mps_problem.tall_apply): it goes with the lanes so that every
+  // thread issuing one engine's launches makes the same choice
+  int tall_apply = 0;
 };
 // The calling thread's current lanes (one instance, no shift by default).
 Lanes& lanes();

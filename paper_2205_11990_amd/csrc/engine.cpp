@@ -620,6 +620,8 @@ void validate_problem(const Problem& p) {
              kEinval, "collision parameters must be finite, nu >= 0");
   MPSV_CHECK(p.coll_model == 0 || p.coll_model == 1, kEinval,
              "unknown collision model");
+  MPSV_CHECK(p.tall_apply == 0 || p.tall_apply == 1, kEinval,
+             "unknown reflector application mode");
   MPSV_CHECK(p.compression == 0 || p.compression == 1, kEinval,
              "unknown compression scheme");
   MPSV_CHECK(p.compression == 0 || (p.order != 1 && p.order != 4), kEinval,
@@ -717,7 +719,8 @@ void validate_batch(const std::vector<Problem>& ps) {
     MPSV_CHECK(b.Lx == a.Lx && b.Lv == a.Lv && b.order == a.order &&
                    b.chi_max == a.chi_max && b.level == a.level &&
                    b.df_max == a.df_max && b.precision == a.precision &&
-                   b.x_scheme == a.x_scheme && b.compression == a.compression,
+                   b.x_scheme == a.x_scheme && b.compression == a.compression &&
+                   b.tall_apply == a.tall_apply,
                kEinval, "lock-step instances must share the problem shape");
     MPSV_CHECK(b.tol == 0.0 && b.cfl == 0.0 && b.dt == a.dt && b.qm == a.qm,
                kEinval,
@@ -1648,6 +1651,9 @@ void step_species(const std::vector<Engine*>& es, const std::vector<double>& q,
   const size_t S = es.size();
   for (auto* e : es) MPSV_CHECK(!e->f_.empty(), kEinval, "state not initialised");
   Engine& e0 = *es[0];
+  // the species share the reflector-application choice (checked at
+  // creation); its lanes carry it to every launch of the step
+  LanesScope ls(e0.one_lane(0));
   const double h = e0.p_.dt;
   for (auto* e : es) e->step_.reset();
   for (auto* e : es) {

@@ -21,6 +21,7 @@ struct Problem {
   int compression = 0;  // 0 sweep, 1 centre-first (sequential orderings)
   double nu = 0.0, nu_v0 = 0.0, nu_vth = 1.0;  // Dougherty collisions
   int coll_model = 0;  // 0 drift / thermal speed from the moments of f, 1 fixed
+  int tall_apply = 0;  // tall-block reflector application: 0 one at a time, 1 WY
   int n() const { return Lx + Lv; }
   long Nx() const { return 1L << Lx; }
   long Nv() const { return 1L << Lv; }
@@ -257,8 +258,10 @@ class Engine {
   // the SVD outcome record of the lane whose stream is s
   SvdOutcomes* outcomes(hipStream_t s) { return s == side_ ? &out_side_ : &out_main_; }
   // launches over every instance, or over instance i alone
-  Lanes all_lanes() const { return Lanes{nin_, 0, (long)chunk_}; }
-  Lanes one_lane(int i) const { return Lanes{1, (long)i * (long)chunk_, (long)chunk_}; }
+  Lanes all_lanes() const { return Lanes{nin_, 0, (long)chunk_, p_.tall_apply}; }
+  Lanes one_lane(int i) const {
+    return Lanes{1, (long)i * (long)chunk_, (long)chunk_, p_.tall_apply};
+  }
   void check_instance(int i) const;
   // arithmetic of the MPO x MPS contractions: 0 FP64, 1 FP32, 2 BF16 on the
   // matrix cores (precision mode); factorisations, Poisson field and moments

@@ -942,7 +942,7 @@ void launch_split(hipStream_t s, const double* Xr, int k, long ldx, int cap,
   const int group = std::max(1, capacity / S::wgs);
   for (int i0 = 0; i0 < all.n; i0 += group) {
     LanesScope ls(Lanes{std::min(group, all.n - i0), all.first + (long)i0 * all.stride,
-                        all.stride});
+                        all.stride, all.tall_apply});
     MultiWs w;
     w.xg = ws;
     w.xn = w.xg + (size_t)S::slots * S::col;

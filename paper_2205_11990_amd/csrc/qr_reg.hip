@@ -43,6 +43,8 @@ struct Chunks {
 
 namespace {
 
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
 constexpr int FT = 1024;  // factorisation workgroup: 16 waves
 constexpr int AT = 256;   // application workgroup: 4 waves
 
@@ -747,17 +749,27 @@ __global__ __launch_bounds__(AT) void qr_reg_apply_kernel(
 // order, the same cross-lane sums), so the two kernels give the same bits.
 // Every wave takes part in the loads and barriers, also one whose columns
 // lie past p.
+//
+// With STAGE the block of Y the workgroup owns (its LT / 64 * CPW adjacent
+// columns) also moves through LDS, RC rows at a time: loaded row by row,
+// coalesced, and handed to the waves column by column (and back the same way
+// at the end).  A row-major Y read column by column, one column per wave,
+// touches a different cache line in every lane; staged, each row of the
+// block is one contiguous read.
 constexpr int LT = 512;  // 8 waves
+constexpr int RC = 512;  // rows of Y per staging pass
 
 template <int RPL>
 constexpr int lds_block() { return RPL >= 16 ? 4 : 8; }
 
-template <int RPL>
+template <int CPW, int RPL, bool STAGE>
 constexpr size_t lds_apply_bytes() {
-  return (size_t)2 * lds_block<RPL>() * 64 * RPL * sizeof(double);
+  const size_t refl = (size_t)2 * lds_block<RPL>() * 64 * RPL;
+  const size_t stage = STAGE ? (size_t)RC * ((LT / 64) * CPW + 1) : 0;
+  return (refl > stage ? refl : stage) * sizeof(double);
 }
 
-template <int CPW, int RPL>
+template <int CPW, int RPL, bool STAGE>
 __global__ __launch_bounds__(LT) void qr_lds_apply_kernel(
     const double* __restrict__ V, const double* __restrict__ tau, int m, int k,
     CMatView Yin, int rows_in, MatView Yout, int p, int trans, Chunks ch,
@@ -789,15 +801,39 @@ __global__ __launch_bounds__(LT) void qr_lds_apply_kernel(
   }
   const int c0 = (blockIdx.x * (LT / 64) + w) * CPW;
   const bool active = c0 < p;
+  // the workgroup's columns and the row pitch of a staging pass
+  constexpr int NC = (LT / 64) * CPW;
+  constexpr int LDY = NC + 1;
+  const int cw = blockIdx.x * NC;
   double y[RPL][CPW];
+  if constexpr (STAGE) {
 #pragma unroll
-  for (int a = 0; a < RPL; ++a)
+    for (int r0 = 0; r0 < 64 * RPL; r0 += RC) {
+      for (int e = tid; e < RC * NC; e += LT) {
+        const int rr = e / NC, cc = e % NC;
+        const int i = r0 + rr, c = cw + cc;
+        vs[rr * LDY + cc] = (i < rows_in && c < p)
+                                ? Yin.p[(long)i * Yin.rs + (long)c * Yin.cs] : 0.0;
+      }
+      __syncthreads();
 #pragma unroll
-    for (int b = 0; b < CPW; ++b) {
-      const int i = l + 64 * a;
-      y[a][b] = (active && i < rows_in && c0 + b < p)
-                    ? Yin.p[(long)i * Yin.rs + (long)(c0 + b) * Yin.cs] : 0.0;
+      for (int a = 0; a < RPL; ++a)
+        if (64 * a >= r0 && 64 * a < r0 + RC)
+#pragma unroll
+          for (int b = 0; b < CPW; ++b)
+            y[a][b] = vs[(l + 64 * a - r0) * LDY + w * CPW + b];
+      __syncthreads();
     }
+  } else {
+#pragma unroll
+    for (int a = 0; a < RPL; ++a)
+#pragma unroll
+      for (int b = 0; b < CPW; ++b) {
+        const int i = l + 64 * a;
+        y[a][b] = (active && i < rows_in && c0 + b < p)
+                      ? Yin.p[(long)i * Yin.rs + (long)(c0 + b) * Yin.cs] : 0.0;
+      }
+  }
   const double ta = (l < k) ? tau[l] : 0.0;
   const double tb = (l + 64 < k) ? tau[l + 64] : 0.0;
   const int nb = (k + RB - 1) / RB;
@@ -856,6 +892,26 @@ __global__ __launch_bounds__(LT) void qr_lds_apply_kernel(
     if (t + 1 < nb) stash(buf ^ 1);
     __syncthreads();
   }
+  if constexpr (STAGE) {
+    // the last barrier above ends every read of the reflector buffers
+#pragma unroll
+    for (int r0 = 0; r0 < 64 * RPL; r0 += RC) {
+#pragma unroll
+      for (int a = 0; a < RPL; ++a)
+        if (64 * a >= r0 && 64 * a < r0 + RC)
+#pragma unroll
+          for (int b = 0; b < CPW; ++b)
+            vs[(l + 64 * a - r0) * LDY + w * CPW + b] = y[a][b];
+      __syncthreads();
+      for (int e = tid; e < RC * NC; e += LT) {
+        const int rr = e / NC, cc = e % NC;
+        const int i = r0 + rr, c = cw + cc;
+        if (i < m && c < p) Yout.p[(long)i * Yout.rs + (long)c * Yout.cs] = vs[rr * LDY + cc];
+      }
+      __syncthreads();
+    }
+    return;
+  }
   if (!active) return;
 #pragma unroll
   for (int a = 0; a < RPL; ++a)
@@ -864,6 +920,172 @@ __global__ __launch_bounds__(LT) void qr_lds_apply_kernel(
       const int i = l + 64 * a;
       if (i < m && c0 + b < p) Yout.p[(long)i * Yout.rs + (long)(c0 + b) * Yout.cs] = y[a][b];
     }
+}
+
+// Application of up to 16 reflectors in compact-WY form on the matrix
+// cores, for tall blocks (the trailing updates of 16-column panels):
+//   Q = H_0 ... H_{k-1} = I - V T V^T,  T upper triangular (k x k),
+//   T_jj = tau_j,  T_{<j,j} = -tau_j T_{<j,<j} (V_{<j}^T v_j),
+// Q^T Y = Y - V T^T (V^T Y),  Q Y = Y - V T (V^T Y).
+// A workgroup of four waves owns 64 columns of Y (16 per wave) and streams
+// the rows twice, 256 at a time, the reflectors through LDS (loaded
+// coalesced along each reflector), Y straight from memory (16 adjacent
+// columns per row, the loads of 64 rows issued before the matrix-core steps
+// that use them).  Pass 1 accumulates W = V^T Y and the Gram matrix V^T V
+// with v_mfma_f64_16x16x4f64; each wave forms T from the Gram matrix and tau
+// (one lane per row of T) and W' = T^T W (or T W); pass 2 subtracts V W'
+// (four matrix-core steps per 16 rows).  It reads each element of Y twice
+// and writes it once, whatever k, and fills the chip when many lock-step
+// instances share the launch; one state alone does better with the
+// one-reflector-at-a-time kernels (more workgroups, shorter chains), so the
+// problem chooses (mps_problem.tall_apply) and the choice never depends on
+// the instance count.
+constexpr int WY_T = 256;     // 4 waves
+constexpr int WY_RC = 256;    // rows per chunk
+constexpr int WY_LD = 17;     // LDS pitch of a 16-wide row
+
+__global__ __launch_bounds__(WY_T) void qr_wy_apply_kernel(
+    const double* __restrict__ V, const double* __restrict__ tau, int m, int k,
+    CMatView Yin, int rows_in, MatView Yout, int p, int trans, Chunks ch,
+    InstOff io) {
+  __shared__ double Vs[WY_RC * WY_LD];
+  __shared__ double Ms[4][16 * WY_LD];  // per wave: the Gram matrix, then T
+  __shared__ double Wsh[4][16 * WY_LD]; // per wave: its block of V^T Y
+  {
+    const long o_ = io.of(blockIdx.z);
+    V = shifted(V, o_);
+    tau = shifted(tau, o_);
+    Yin = shifted(Yin, o_);
+    Yout = shifted(Yout, o_);
+  }
+  {
+    const int cb = blockIdx.y;
+    const int row0 = cb * ch.rows;
+    const int mc = min(ch.rows, m - row0);
+    V += (long)cb * ch.rows * ch.kstride;
+    tau += (long)cb * ch.kstride;
+    k = min(k, mc);
+    rows_in = min(rows_in - row0, mc);
+    m = mc;
+    Yin.p += (long)row0 * Yin.rs;
+    Yout.p += (long)row0 * Yout.rs;
+  }
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int lr = l & 15, lk = l >> 4;
+  const int col = blockIdx.x * 64 + w * 16 + lr;  // this lane's column (B and D)
+  const bool colok = col < p;
+  double* M = Ms[w];
+  double* Wl = Wsh[w];
+  // stage reflector rows [i0, i0 + WY_RC) (zeros past m and past k)
+  auto stage = [&](int i0) {
+    for (int e = tid; e < WY_RC * 16; e += WY_T) {
+      const int j = e / WY_RC, r = e % WY_RC;
+      const int i = i0 + r;
+      Vs[r * WY_LD + j] = (j < k && i < m) ? V[(long)j * m + i] : 0.0;
+    }
+  };
+  dbl4 accW = {0.0, 0.0, 0.0, 0.0}, accG = {0.0, 0.0, 0.0, 0.0};
+  for (int i0 = 0; i0 < m; i0 += WY_RC) {
+    __syncthreads();
+    stage(i0);
+    __syncthreads();
+    const int nrow = min(WY_RC, m - i0);
+    for (int r64 = 0; r64 < nrow; r64 += 64) {
+      double bb[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int i = i0 + r64 + 4 * q + lk;
+        bb[q] = (colok && i < rows_in) ? Yin.p[(long)i * Yin.rs + (long)col * Yin.cs] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        // A = V^T (row j = lr, k index = chunk row); B = Y rows (k, col)
+        const double a = Vs[(r64 + 4 * q + lk) * WY_LD + lr];
+        accW = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb[q], accW, 0, 0, 0);
+        // the Gram matrix: B = V rows, the same element as A
+        accG = __builtin_amdgcn_mfma_f64_16x16x4f64(a, a, accG, 0, 0, 0);
+      }
+    }
+  }
+  // D layout: lane l, item r -> row 4 r + lk, column lr
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    M[(4 * r + lk) * WY_LD + lr] = accG[r];
+    Wl[(4 * r + lk) * WY_LD + lr] = accW[r];
+  }
+  __syncthreads();
+  // T, one lane per row (every wave its own copy): t[c] = T[row][c]
+  double t[16];
+  {
+    const int row = l;  // lanes 16..63 keep zeros
+#pragma unroll
+    for (int c = 0; c < 16; ++c) t[c] = 0.0;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      const double tc = (c < k) ? tau[c] : 0.0;
+      if (row == c) {
+        t[c] = tc;
+      } else if (row < c) {
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+          if (q >= row && q < c) acc = fma(t[q], M[q * WY_LD + c], acc);
+        t[c] = -tc * acc;
+      }
+    }
+  }
+  __syncthreads();
+  if (l < 16) {
+#pragma unroll
+    for (int c = 0; c < 16; ++c) M[l * WY_LD + c] = t[c];
+  }
+  __syncthreads();
+  // W' = T^T W (trans) or T W, as the B operand of pass 2:
+  // step s takes W'[4 s + lk][lr]
+  double bw[4];
+#pragma unroll
+  for (int s4 = 0; s4 < 4; ++s4) {
+    const int row = 4 * s4 + lk;
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const double tq = trans ? M[q * WY_LD + row] : M[row * WY_LD + q];
+      acc = fma(tq, Wl[q * WY_LD + lr], acc);
+    }
+    bw[s4] = acc;
+  }
+  // pass 2: Y -= V W', four tiles of 16 rows per group of 64
+  for (int i0 = 0; i0 < m; i0 += WY_RC) {
+    __syncthreads();
+    stage(i0);
+    __syncthreads();
+    const int nrow = min(WY_RC, m - i0);
+    for (int r64 = 0; r64 < nrow; r64 += 64) {
+      double yy[4][4];
+#pragma unroll
+      for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = i0 + r64 + 16 * tt + 4 * r + lk;
+          yy[tt][r] = (colok && i < rows_in) ? Yin.p[(long)i * Yin.rs + (long)col * Yin.cs] : 0.0;
+        }
+#pragma unroll
+      for (int tt = 0; tt < 4; ++tt) {
+        dbl4 d = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+          // A[row][kk] = V[chunk row r64 + 16 tt + lr][4 s + lk]
+          const double a = Vs[(r64 + 16 * tt + lr) * WY_LD + 4 * s4 + lk];
+          d = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bw[s4], d, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = i0 + r64 + 16 * tt + 4 * r + lk;
+          if (colok && i < m) Yout.p[(long)i * Yout.rs + (long)col * Yout.cs] = yy[tt][r] - d[r];
+        }
+      }
+    }
+  }
 }
 
 int rows_per_lane(int m) {
@@ -895,21 +1117,21 @@ void launch_apply(hipStream_t s, const double* V, const double* tau, int m,
                      V, tau, m, k, Yin, rows_in, Yout, p, trans, ch, inst_off());
 }
 
-template <int CPW, int RPL>
+template <int CPW, int RPL, bool STAGE>
 void launch_lds_apply(hipStream_t s, const double* V, const double* tau, int m,
                       int k, CMatView Yin, int rows_in, MatView Yout, int p,
                       int trans, Chunks ch, int nchunks) {
   static std::once_flag once;
   std::call_once(once, [] {
-    MPSV_HIP(hipFuncSetAttribute((const void*)qr_lds_apply_kernel<CPW, RPL>,
+    MPSV_HIP(hipFuncSetAttribute((const void*)qr_lds_apply_kernel<CPW, RPL, STAGE>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)lds_apply_bytes<RPL>()));
+                                 (int)lds_apply_bytes<CPW, RPL, STAGE>()));
   });
   const int per_block = (LT / 64) * CPW;
-  hipLaunchKernelGGL((qr_lds_apply_kernel<CPW, RPL>),
-                     dim3(ceil_div(p, per_block), nchunks, inst_count()), dim3(LT),
-                     lds_apply_bytes<RPL>(), s, V, tau, m, k, Yin, rows_in, Yout, p, trans,
-                     ch, inst_off());
+  const size_t lds = lds_apply_bytes<CPW, RPL, STAGE>();
+  hipLaunchKernelGGL((qr_lds_apply_kernel<CPW, RPL, STAGE>),
+                     dim3(ceil_div(p, per_block), nchunks, inst_count()), dim3(LT), lds, s,
+                     V, tau, m, k, Yin, rows_in, Yout, p, trans, ch, inst_off());
 }
 
 }  // namespace
@@ -974,11 +1196,31 @@ void qr_reg_factor(hipStream_t s, CMatView A, int m, int n, MatView R,
 }
 
 // Variant of a reflector application: columns per wave (1, 2 or 4) of the
-// register-streaming kernel, or 8 + columns per wave (1, or 2 up to 1024
-// rows) of the kernel that shares the reflectors through LDS; the built-in rule, or the
-// launch-shape table's choice for this shape and instance count.  Every
+// register-streaming kernel, 8 + columns per wave (1, or 2 up to 1024 rows)
+// of the kernel that shares the reflectors through LDS, or 16 + columns per
+// wave of the same kernel with Y staged through LDS as well; the built-in
+// rule, or the launch-shape table's choice for this shape and instance
+// count.  Every
 // choice gives the same bits: each column's products and reductions are
 // the same whichever wave and kernel carry it.
+// Reflector applications that take the compact-WY matrix-core kernel: when
+// the problem asks for it (carried with the lanes of its launches), tall
+// blocks (more than 512 rows per chunk), at most 16 reflectors, at least 32
+// columns.  The choice depends on the problem and the shape, never on the
+// number of lock-step instances.
+static bool wy_shape(int rows, int k, int p) {
+  return lanes().tall_apply == 1 && rows > 512 && k <= 16 && p >= 32;
+}
+
+static void launch_wy(hipStream_t s, const double* V, const double* tau, int m, int k,
+                      CMatView Yin, int rows_in, MatView Yout, int p, int tr, Chunks ch,
+                      int nchunks) {
+  hipLaunchKernelGGL(qr_wy_apply_kernel, dim3(ceil_div(p, 64), nchunks, inst_count()),
+                     dim3(WY_T), 0, s, V, tau, m, k, Yin, rows_in, Yout, p, tr, ch,
+                     inst_off());
+  MPSV_LAUNCHED();
+}
+
 static TunePick apply_cols(hipStream_t s, int rows, int k, int p, int nch, int tr, int rpl) {
   const int dflt = (p >= 128 && rpl < 32) ? 2 : 1;
   uint32_t allowed = 1u << 1;
@@ -986,8 +1228,8 @@ static TunePick apply_cols(hipStream_t s, int rows, int k, int p, int nch, int t
   if (rpl <= 8) allowed |= 1u << 4;
   // reflectors shared through LDS (values 8 + columns per wave), 257 to
   // 2048 rows
-  if (rpl >= 8) allowed |= 1u << 9;
-  if (rpl >= 8 && rpl < 32) allowed |= 1u << 10;
+  if (rpl >= 8) allowed |= (1u << 9) | (1u << 17);
+  if (rpl >= 8 && rpl < 32) allowed |= (1u << 10) | (1u << 18);
   const TuneKey key{{kTuneApplyCols, rows, k, p, 2 * nch + tr, tune_inst_class(inst_count())}};
   return tune_pick(s, key, dflt, allowed);
 }
@@ -1000,18 +1242,29 @@ void qr_reg_apply(hipStream_t s, const double* V, const double* tau, int m,
              "qr_reg_apply: bad shape");
   const int rpl = rows_per_lane(m);
   const int tr = trans ? 1 : 0;
+  if (wy_shape(m, k, p)) {
+    const int slot = prof_begin(s);
+    launch_wy(s, V, tau, m, k, Yin, rows_in, Yout, p, tr, Chunks{m, k}, 1);
+    prof_end(s, slot, kClsQrApply, 4.0 * p * (double)k * (m - (k - 1) / 2.0),
+             8.0 * (3.0 * m * p + 2.0 * (double)m * k));
+    return;
+  }
   const TunePick tp = apply_cols(s, m, k, p, 1, tr, rpl);
   const int cpw = tp.value;
   const int slot = prof_begin(s);
 #define MPSV_A(C, Rr)                                                   \
   if (cpw == C && rpl == Rr) launch_apply<C, Rr>(s, V, tau, m, k, Yin, rows_in, Yout, p, tr, Chunks{m, k}, 1); else
 #define MPSV_L(C, Rr)                                                   \
-  if (cpw == 8 + C && rpl == Rr) launch_lds_apply<C, Rr>(s, V, tau, m, k, Yin, rows_in, Yout, p, tr, Chunks{m, k}, 1); else
+  if (cpw == 8 + C && rpl == Rr) launch_lds_apply<C, Rr, false>(s, V, tau, m, k, Yin, rows_in, Yout, p, tr, Chunks{m, k}, 1); else
+#define MPSV_S(C, Rr)                                                   \
+  if (cpw == 16 + C && rpl == Rr) launch_lds_apply<C, Rr, true>(s, V, tau, m, k, Yin, rows_in, Yout, p, tr, Chunks{m, k}, 1); else
   MPSV_A(1, 1) MPSV_A(2, 1) MPSV_A(4, 1) MPSV_A(1, 2) MPSV_A(2, 2) MPSV_A(4, 2)
   MPSV_A(1, 4) MPSV_A(2, 4) MPSV_A(4, 4) MPSV_A(1, 8) MPSV_A(2, 8) MPSV_A(4, 8)
   MPSV_A(1, 16) MPSV_A(2, 16) MPSV_A(1, 32)
   MPSV_L(1, 8) MPSV_L(2, 8) MPSV_L(1, 16) MPSV_L(2, 16) MPSV_L(1, 32)
+  MPSV_S(1, 8) MPSV_S(2, 8) MPSV_S(1, 16) MPSV_S(2, 16) MPSV_S(1, 32)
   throw Error(kEinval, "qr_reg_apply: no kernel for this shape");
+#undef MPSV_S
 #undef MPSV_L
 #undef MPSV_A
   MPSV_LAUNCHED();
@@ -1053,6 +1306,13 @@ void qr_reg_apply_chunks(hipStream_t s, const double* V, const double* tau,
              "qr_reg_apply_chunks: bad shape");
   const int rpl = rows_per_lane(rows);
   const int tr = trans ? 1 : 0;
+  if (wy_shape(rows, k, p)) {
+    const int slot = prof_begin(s);
+    launch_wy(s, V, tau, m, k, CMatView{Y.p, Y.rs, Y.cs, 0}, m, Y, p, tr, Chunks{rows, k}, nch);
+    prof_end(s, slot, kClsQrApply, 4.0 * p * (double)k * m,
+             8.0 * (3.0 * m * p + 2.0 * (double)m * k));
+    return;
+  }
   const TunePick tp = apply_cols(s, rows, k, p, nch, tr, rpl);
   const int cpw = tp.value;
   const int slot = prof_begin(s);
@@ -1061,12 +1321,16 @@ void qr_reg_apply_chunks(hipStream_t s, const double* V, const double* tau,
 #define MPSV_A(C, Rr)                                                   \
   if (cpw == C && rpl == Rr) launch_apply<C, Rr>(s, V, tau, m, k, Yin, m, Y, p, tr, ch, nch); else
 #define MPSV_L(C, Rr)                                                   \
-  if (cpw == 8 + C && rpl == Rr) launch_lds_apply<C, Rr>(s, V, tau, m, k, Yin, m, Y, p, tr, ch, nch); else
+  if (cpw == 8 + C && rpl == Rr) launch_lds_apply<C, Rr, false>(s, V, tau, m, k, Yin, m, Y, p, tr, ch, nch); else
+#define MPSV_S(C, Rr)                                                   \
+  if (cpw == 16 + C && rpl == Rr) launch_lds_apply<C, Rr, true>(s, V, tau, m, k, Yin, m, Y, p, tr, ch, nch); else
   MPSV_A(1, 1) MPSV_A(2, 1) MPSV_A(4, 1) MPSV_A(1, 2) MPSV_A(2, 2) MPSV_A(4, 2)
   MPSV_A(1, 4) MPSV_A(2, 4) MPSV_A(4, 4) MPSV_A(1, 8) MPSV_A(2, 8) MPSV_A(4, 8)
   MPSV_A(1, 16) MPSV_A(2, 16) MPSV_A(1, 32)
   MPSV_L(1, 8) MPSV_L(2, 8) MPSV_L(1, 16) MPSV_L(2, 16) MPSV_L(1, 32)
+  MPSV_S(1, 8) MPSV_S(2, 8) MPSV_S(1, 16) MPSV_S(2, 16) MPSV_S(1, 32)
   throw Error(kEinval, "qr_reg_apply_chunks: no kernel for this shape");
+#undef MPSV_S
 #undef MPSV_L
 #undef MPSV_A
   MPSV_LAUNCHED();

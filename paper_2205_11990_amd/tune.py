@@ -5,7 +5,9 @@ and differ only in how the work is spread over the device: the output tile
 of the FP64 GEMM (64 x 64 or 128 x 128) and, for a Householder reflector
 application, the columns each wave carries (1, 2 or 4) and whether the
 reflectors are streamed into each wave's registers or shared by the waves of
-a workgroup through LDS (values 9 and 10: 1 or 2 columns per wave).  Which is fastest
+a workgroup through LDS (values 9 and 10: 1 or 2 columns per wave; 17 and 18:
+the same with the workgroup's block of columns staged through LDS too, read
+and written row by row).  Which is fastest
 depends on the exact shape and on how many lock-step instances a launch
 covers, so the library looks each launch up in a table keyed by both (see
 mps_blocks.h, mpsb_tune_*); this script writes that table.
@@ -62,6 +64,7 @@ def _batch(n):
     ws = []
     for i in range(n):
         w = wl.two_stream(L=10, chi=64, tol=0.0, level=5, df_max=4, dt_cfg=0.02)
+        w.problem.tall_apply = 1  # the throughput choice for large batches
         ax, bv = wl.two_stream_profiles(w.problem, 0.2, 1e-3 * (1 + 0.1 * i))
         ws.append(wl.Workload("two_stream_%d" % i, w.problem, ax, bv, 10))
     bt = B.Batch([w.problem for w in ws], [(w.ax, w.bv) for w in ws])
@@ -76,6 +79,7 @@ def _landau_groups(count=64):
     ws = wl.landau_sweep(count)
     for w in ws:
         w.problem.tol, w.problem.level = 0.0, 5
+        w.problem.tall_apply = 1
     groups = {}
     for w in ws:
         groups.setdefault((w.problem.Lx, w.problem.chi_max), []).append(w)
@@ -233,7 +237,8 @@ def main():
         f.write("# paper_2205_11990_amd/tune.py (--workloads %s --reps %d --min-gain %g).\n"
                 % (args.workloads, args.reps, args.min_gain))
         f.write("# knob 1: FP64 GEMM tile (0: 64x64, 1: 128x128), key M N K 4*batch+layout;\n")
-        f.write("# knob 2: reflector application (1, 2, 4 columns per wave; 9, 10: LDS-shared with 1, 2),\n")
+        f.write("# knob 2: reflector application (1, 2, 4 columns per wave; 9, 10: LDS-shared with 1, 2;\n")
+        f.write("#         17, 18: LDS-shared with the columns staged),\n")
         f.write("#         key rows reflectors columns 2*chunks+trans;\n")
         f.write("# class: lock-step instances (0: 1, 1: 2-7, 2: 8-31, 3: 32+).\n")
         for w in walls:

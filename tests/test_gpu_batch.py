@@ -75,6 +75,45 @@ def test_batch_equals_solo_bit_for_bit(B, order, comp):
     bt.free()
 
 
+def test_wy_reflectors_batch_equals_solo_and_oracle(B):
+    """Compact-WY reflector application on tall blocks (tall_apply = 1;
+    two-stream 2^9, chi = 16, D_F = 4: the field term's blocks reach 640
+    rows): three instances in one batch equal the same three stand-alone
+    states with the same mode bit for bit after two steps; each is within
+    1e-8 of the oracle and differs from the one-reflector mode only at the
+    rounding level."""
+    _say("batch == solo, compact-WY reflectors")
+    ws = _sweep(3, L=9, chi=16)
+    for w in ws:
+        w.problem.tall_apply = 1
+    starts = [S.oracle_start(w, pert_chi=16, amp=1e-3, seed=70 + i) for i, w in enumerate(ws)]
+    bt = B.Batch([w.problem for w in ws], [(w.ax, w.bv) for w in ws])
+    bt.set_cores(starts)
+    bt.step(2)
+    for i, w in enumerate(ws):
+        st = S.gpu_state(B, w, starts[i])
+        st.step(2)
+        a, b = bt.instance(i).get_cores_host(), st.get_cores_host()
+        assert [x.shape for x in a] == [x.shape for x in b], i
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y), i
+        G = st.to_dense().cpu().numpy()
+        st.free()
+        ops = omps.Operators(w.problem)
+        R = omps.to_dense(omps.rk4_step(omps.rk4_step(starts[i], ops), ops), w.problem)
+        assert np.abs(G - R).max() <= 1e-8 * np.abs(R).max(), i
+        w.problem.tall_apply = 0
+        st0 = S.gpu_state(B, w, starts[i])
+        st0.step(2)
+        G0 = st0.to_dense().cpu().numpy()
+        st0.free()
+        w.problem.tall_apply = 1
+        # the two modes are different arithmetic of the same factor
+        assert not np.array_equal(G, G0), i
+        assert np.abs(G - G0).max() <= 1e-11 * np.abs(G0).max(), i
+    bt.free()
+
+
 def test_batch_matches_mps_oracle(B):
     """Three instances, C5, chi = 8: each instance's f and E within 1e-8 of
     the CPU MPS oracle after two steps from the same state, same bonds."""
@@ -136,6 +175,11 @@ def test_batch_parameter_checks(B):
         B.Batch([w.problem for w in ws], [(w.ax, w.bv) for w in ws])
     assert e.value.status == B.MPS_EINVAL
     ws[1].problem.tol = 0.0
+    ws[1].problem.tall_apply = 1
+    with pytest.raises(B.MpsError) as e:
+        B.Batch([w.problem for w in ws], [(w.ax, w.bv) for w in ws])
+    assert e.value.status == B.MPS_EINVAL
+    ws[1].problem.tall_apply = 0
     ws[1].problem.dt *= 0.5
     with pytest.raises(B.MpsError) as e:
         B.Batch([w.problem for w in ws], [(w.ax, w.bv) for w in ws])

@@ -316,16 +316,19 @@ def test_errors_leave_state_unchanged(B):
     assert st.info()["steps"] == 1
 
 
-def test_full_size_bench_workload_matches_mps_oracle(B):
+@pytest.mark.parametrize("tall_apply", [0, 1])
+def test_full_size_bench_workload_matches_mps_oracle(B, tall_apply):
     """The benchmarked configuration itself: two-stream 2^10 x 2^10,
     interleaved, chi = 64, every compression capped (C5), D_F = 4, from the
     perturbed state the benchmark uses, stepped exactly as bench.py steps
-    it (side-stream T1).  One RK4 step on the GPU and in the CPU MPS oracle
-    from the same cores: reconstructed f and E within 1e-8 (observed
-    ~3e-13 and ~4e-12), identical bond dimensions."""
-    _say("full size two-stream 2^10 chi64 C5")
+    it (side-stream T1), with either reflector application on tall blocks.
+    One RK4 step on the GPU and in the CPU MPS oracle from the same cores:
+    reconstructed f and E within 1e-8 (observed ~3e-13 and ~4e-12),
+    identical bond dimensions."""
+    _say("full size two-stream 2^10 chi64 C5 tall_apply=%d" % tall_apply)
     w = wl.two_stream(L=10, chi=64, tol=0.0, level=5, df_max=4, dt_cfg=0.02)
     p = w.problem
+    p.tall_apply = tall_apply
     f0 = S.oracle_start(w, pert_chi=64,
                         amp=1e-6 * float(np.linalg.norm(w.ax) * np.linalg.norm(w.bv)))
     st = S.gpu_state(B, w, f0)

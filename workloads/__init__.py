@@ -55,6 +55,7 @@ class Problem:
     nu_v0: float = 0.0      # its drift velocity
     nu_vth: float = 1.0     # its thermal speed
     coll_model: int = 0     # 0: drift and thermal speed from the moments of f; 1: fixed
+    tall_apply: int = 0     # library only: 0 one reflector at a time, 1 compact WY (tall blocks)
 
     @property
     def Nx(self) -> int:
