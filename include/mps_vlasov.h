@@ -148,7 +148,7 @@ typedef struct mps_problem {
   double nu;                /* Dougherty collision rate, >= 0 (0: none)    */
   double nu_v0, nu_vth;     /* drift and thermal speed of coll_model 1     */
   int32_t coll_model;       /* 0: v0, vth from the moments of f; 1: fixed  */
-  int32_t tall_apply;       /* mps_tall_apply (0: one reflector at a time) */
+  int32_t tall_apply;       /* mps_tall_apply, 0: one reflector at a time  */
 } mps_problem;
 
 /* How the QR sweeps apply their Householder reflectors to tall blocks (more
