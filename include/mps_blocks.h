@@ -161,12 +161,19 @@ mps_status mpsb_set_jacobi_max_sweeps(int32_t n);
 /* Per-kernel-class timing with HIP events on the launching stream (off by
  * default).  enable != 0 clears and starts recording; classes: 0 GEMM,
  * 1 Householder QR factorisation, 2 Jacobi SVD, 3 other, 4 application of
- * Householder reflectors.  mpsb_profile_read synchronises the
+ * Householder reflectors, 5 the same as compact-WY blocks (tall_apply = 1;
+ * its byte count is the algorithmic traffic: Y read twice and written
+ * once, the reflectors read twice).  mpsb_profile_read synchronises the
  * device and returns, for one class, the number of launches, the summed
  * event time (ms) and the summed nominal FLOPs and bytes (host outputs). */
 mps_status mpsb_profile(int32_t enable);
 mps_status mpsb_profile_read(int32_t cls, int64_t* launches, double* ms,
                              double* flops, double* bytes);
+/* The part of a class's FLOPs recorded by launches inside a truncated SVD
+ * (its QRs, reflector applications and GEMM); the SVD's own record (class
+ * 2) counts the nominal 6 m n^2 + 20 n^3 of the whole decomposition, so a
+ * total over classes subtracts this part.  Synchronises the device. */
+mps_status mpsb_profile_nested_flops(int32_t cls, double* flops);
 
 /* ---- Launch-shape table (used by every call above and by mps_step).
  *

@@ -96,6 +96,7 @@ _SIGS = {
     "mpsb_set_jacobi_max_sweeps": [_I32],
     "mpsb_profile": [_I32],
     "mpsb_profile_read": [_I32, _PI64, _PD, _PD, _PD],
+    "mpsb_profile_nested_flops": [_I32, _PD],
     "mpsb_tune_clear": [],
     "mpsb_tune_set": [_PI32, _I32],
     "mpsb_tune_get": [_PI32, _PI32, _PI32],
@@ -628,7 +629,7 @@ def set_jacobi_max_sweeps(n: int):
     _check(lib().mpsb_set_jacobi_max_sweeps(int(n)))
 
 
-KERNEL_CLASSES = ("gemm_f64", "qr_factor", "jacobi_svd", "other", "qr_apply")
+KERNEL_CLASSES = ("gemm_f64", "qr_factor", "jacobi_svd", "other", "qr_apply", "qr_wy")
 
 
 def profile(enable: bool):
@@ -641,7 +642,10 @@ def profile_read():
         n, ms, fl, by = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
         _check(lib().mpsb_profile_read(c, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(fl),
                                        ctypes.byref(by)))
-        out[name] = {"launches": n.value, "ms": ms.value, "flops": fl.value, "bytes": by.value}
+        nf = ctypes.c_double()
+        _check(lib().mpsb_profile_nested_flops(c, ctypes.byref(nf)))
+        out[name] = {"launches": n.value, "ms": ms.value, "flops": fl.value, "bytes": by.value,
+                     "nested_flops": nf.value}
     return out
 
 

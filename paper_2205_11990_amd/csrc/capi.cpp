@@ -736,6 +736,14 @@ mps_status mpsb_profile(int32_t enable) {
   return guarded([&] { mpsv::prof_enable(enable != 0); });
 }
 
+mps_status mpsb_profile_nested_flops(int32_t cls, double* flops) {
+  return guarded([&] {
+    MPSV_CHECK(cls >= 0 && cls < mpsv::kClsCount, mpsv::kEinval, "bad class");
+    MPSV_CHECK(flops != nullptr, mpsv::kEinval, "null output");
+    *flops = mpsv::prof_nested_flops(cls);
+  });
+}
+
 mps_status mpsb_profile_read(int32_t cls, int64_t* launches, double* ms,
                              double* flops, double* bytes) {
   return guarded([&] {

@@ -16,6 +16,7 @@
 // truncation rule (cap chi, relative discarded weight tol, eq. 5) are
 // evaluated on the device.
 #include <algorithm>
+#include <optional>
 #include <cmath>
 #include <cstdlib>
 #include <mutex>
@@ -646,6 +647,10 @@ int svd_truncate(hipStream_t s, Arena& ws, double* X, int m, int c, long ldx,
   g_stats.svd_calls++;
   MPSV_CHECK(m >= 1 && c >= 1, kEinval, "svd_truncate: empty matrix");
   ArenaScope sc(ws);
+  // the launches of the decomposition are nested in its record (the
+  // Jacobi launch, which carries the nominal work of the whole SVD)
+  std::optional<ProfNested> nest;
+  nest.emplace();
   // the kernels write their outcome words to device memory: a slot of the
   // lane's deferred record, or a block of the workspace read back below
   const int k0 = std::min(m, c);
@@ -719,6 +724,7 @@ int svd_truncate(hipStream_t s, Arena& ws, double* X, int m, int c, long ldx,
     int* perm = ws.alloc_int((size_t)k);
     const size_t jws = jacobi_ws_doubles(k);
     double* jw = jws ? ws.alloc(jws) : nullptr;
+    nest.reset();
     slot = prof_begin(s);
     jacobi_svd(s, Rk, k, k, cap, tol, g_max_sweeps, Wt, sigbuf, perm, info, jw);
   } else {
@@ -738,6 +744,7 @@ int svd_truncate(hipStream_t s, Arena& ws, double* X, int m, int c, long ldx,
     const int use_lds = need <= kJacobiLds ? 1 : 0;
     double* Wg = use_lds ? nullptr : ws.alloc((size_t)mb * c);
     double* Jg = use_lds ? nullptr : ws.alloc((size_t)c * c);
+    nest.reset();
     slot = prof_begin(s);
     hipLaunchKernelGGL(jacobi_svd_kernel, dim3(1, 1, inst_count()), dim3(NT),
                        use_lds ? need : 0, s, B, mb, c, ldb, Wg, Jg, use_lds, cap,
@@ -751,6 +758,7 @@ int svd_truncate(hipStream_t s, Arena& ws, double* X, int m, int c, long ldx,
     prof_end(s, slot, kClsJacobi, 6.0 * mm * nn * nn + 20.0 * nn * nn * nn,
              8.0 * (2.0 * m * c + 2.0 * nn * nn));
   }
+  nest.emplace();
   int D;
   if (defer) {
     // fixed rank: the kernels keep min(cap, k) whatever the values

@@ -9,7 +9,9 @@ namespace {
 struct Rec {
   int cls;
   double flops, bytes;
+  bool nested;
 };
+thread_local int t_nested = 0;
 std::mutex g_mu;
 bool g_on = false;
 std::vector<hipEvent_t> g_ev;  // pairs: 2*slot, 2*slot+1
@@ -39,7 +41,7 @@ int prof_begin(hipStream_t s) {
     }
   }
   const int slot = (int)g_used++;
-  g_rec.push_back(Rec{kClsOther, 0.0, 0.0});
+  g_rec.push_back(Rec{kClsOther, 0.0, 0.0, false});
   MPSV_HIP(hipEventRecord(g_ev[2 * slot], s));
   return slot;
 }
@@ -50,7 +52,19 @@ void prof_end(hipStream_t s, int slot, int cls, double flops, double bytes) {
   MPSV_HIP(hipEventRecord(g_ev[2 * slot + 1], s));
   // a launch over lock-step instances does the work of each of them
   const double n = (double)inst_count();
-  g_rec[slot] = Rec{cls, flops * n, bytes * n};
+  g_rec[slot] = Rec{cls, flops * n, bytes * n, t_nested > 0};
+}
+
+ProfNested::ProfNested() { ++t_nested; }
+ProfNested::~ProfNested() { --t_nested; }
+
+double prof_nested_flops(int cls) {
+  MPSV_HIP(hipDeviceSynchronize());
+  std::lock_guard<std::mutex> lk(g_mu);
+  double f = 0.0;
+  for (size_t i = 0; i < g_used; ++i)
+    if (g_rec[i].cls == cls && g_rec[i].nested) f += g_rec[i].flops;
+  return f;
 }
 
 void prof_read(int cls, long* launches, double* ms, double* flops,

@@ -12,7 +12,8 @@ enum KClass : int {
   kClsJacobi = 2,
   kClsOther = 3,
   kClsQrApply = 4,
-  kClsCount = 5
+  kClsQrWy = 5,  // compact-WY reflector application (HBM-bound streams of Y)
+  kClsCount = 6
 };
 
 bool prof_enabled();
@@ -25,5 +26,20 @@ void prof_end(hipStream_t s, int slot, int cls, double flops, double bytes);
 // Synchronises the device and sums the records of class `cls`.
 void prof_read(int cls, long* launches, double* ms, double* flops,
                double* bytes);
+// The FLOPs of class `cls` recorded inside a truncated SVD (its
+// preconditioning QRs, reflector applications and GEMM): the SVD's own record
+// already counts the nominal work of the whole decomposition, so a sum over
+// classes subtracts these.
+double prof_nested_flops(int cls);
+
+// Marks the calling thread's launches as nested in a truncated SVD for its
+// lifetime (the SVD's own record is taken outside it).
+class ProfNested {
+ public:
+  ProfNested();
+  ~ProfNested();
+  ProfNested(const ProfNested&) = delete;
+  ProfNested& operator=(const ProfNested&) = delete;
+};
 
 }  // namespace mpsv

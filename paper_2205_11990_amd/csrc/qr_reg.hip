@@ -1245,7 +1245,9 @@ void qr_reg_apply(hipStream_t s, const double* V, const double* tau, int m,
   if (wy_shape(m, k, p)) {
     const int slot = prof_begin(s);
     launch_wy(s, V, tau, m, k, Yin, rows_in, Yout, p, tr, Chunks{m, k}, 1);
-    prof_end(s, slot, kClsQrApply, 4.0 * p * (double)k * (m - (k - 1) / 2.0),
+    // algorithmic bytes: Y read twice and written once, the reflectors
+    // read twice
+    prof_end(s, slot, kClsQrWy, 4.0 * p * (double)k * (m - (k - 1) / 2.0),
              8.0 * (3.0 * m * p + 2.0 * (double)m * k));
     return;
   }
@@ -1309,7 +1311,7 @@ void qr_reg_apply_chunks(hipStream_t s, const double* V, const double* tau,
   if (wy_shape(rows, k, p)) {
     const int slot = prof_begin(s);
     launch_wy(s, V, tau, m, k, CMatView{Y.p, Y.rs, Y.cs, 0}, m, Y, p, tr, Chunks{rows, k}, nch);
-    prof_end(s, slot, kClsQrApply, 4.0 * p * (double)k * m,
+    prof_end(s, slot, kClsQrWy, 4.0 * p * (double)k * m,
              8.0 * (3.0 * m * p + 2.0 * (double)m * k));
     return;
   }

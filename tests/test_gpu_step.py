@@ -189,33 +189,40 @@ def test_chi128_metric_size_step_matches_mps_oracle(B):
     2^12 x 2^12, interleaved (24 sites), every point capped at 128 (C5),
     D_F = 4, tol = 0, from the seeded state perturbed to bonds of 128.  Its
     field term meets QR blocks taller than 2048 rows (the TSQR panels) and
-    SVDs of 256 columns inside the step.  One RK4 step on the GPU and in
-    the CPU MPS oracle (about a minute of CPU time) from the same state: f
-    on 4096 sampled grid points, the whole field E and the moments within
-    1e-8, identical bonds."""
+    SVDs of 256 columns inside the step.  One RK4 step on the GPU, with
+    each reflector application on tall blocks (one at a time; compact WY
+    on the matrix cores), and in the CPU MPS oracle
+    (about a minute of CPU time) from the same state: f on 4096 sampled grid
+    points, the whole field E and the moments within 1e-8, identical
+    bonds."""
     _say("two-stream 2^12 chi128 C5 against the oracle (slow)")
     w = wl.two_stream(L=12, chi=128, tol=0.0, level=5, df_max=4, dt_cfg=0.02)
     p = w.problem
     f0 = S.oracle_start(w, pert_chi=128,
                         amp=1e-6 * float(np.linalg.norm(w.ax) * np.linalg.norm(w.bv)))
-    st = S.gpu_state(B, w, f0)
-    st.step(1)
-    g = st.get_cores_host()
-    _, E = st.density_field()
-    _, _, sc = st.moments()
     ops = omps.Operators(p)
     f = omps.rk4_step(f0, ops)
-    assert st.info()["bonds"][1:-1] == omps.bond_dims(f)
     rng = np.random.default_rng(4096)
     pts = list(zip(rng.integers(0, p.Nx, 4096), rng.integers(0, p.Nv, 4096)))
-    a, r = _sample_if(g, p, pts), _sample_if(f, p, pts)
-    assert np.abs(a - r).max() <= 1e-8 * np.abs(r).max()
+    r = _sample_if(f, p, pts)
     Eref = omps.field_dense(f, ops)
-    assert np.abs(E.cpu().numpy() - Eref).max() <= 1e-8 * np.abs(Eref).max()
     ref = omps.moments(f, ops)
-    for k in ("mass", "momentum", "kinetic"):
-        assert abs(sc[k] - ref[k]) <= 1e-9 * max(abs(ref["mass"]), 1.0), k
-    st.free()
+    for mode in (0, 1):
+        _say("  tall_apply=%d" % mode)
+        p.tall_apply = mode
+        st = S.gpu_state(B, w, f0)
+        st.step(1)
+        g = st.get_cores_host()
+        _, E = st.density_field()
+        _, _, sc = st.moments()
+        assert st.info()["bonds"][1:-1] == omps.bond_dims(f), mode
+        a = _sample_if(g, p, pts)
+        assert np.abs(a - r).max() <= 1e-8 * np.abs(r).max(), mode
+        assert np.abs(E.cpu().numpy() - Eref).max() <= 1e-8 * np.abs(Eref).max(), mode
+        for k in ("mass", "momentum", "kinetic"):
+            assert abs(sc[k] - ref[k]) <= 1e-9 * max(abs(ref["mass"]), 1.0), (mode, k)
+        st.free()
+    p.tall_apply = 0
 
 
 def _sample_if(cores, p, pts):
