@@ -333,10 +333,30 @@ def chi128_run(binding, steps, with_oracle=True):
     st.step(steps)
     torch.cuda.synchronize()
     v = steps / (time.perf_counter() - t0)
+    # the kernel classes of one more step (the contraction GEMMs' rate at
+    # bond cap 128 among them), and the largest GEMM shapes of a step with
+    # their own rates (launch times from the launch-shape records)
+    rates = _class_rates(binding, lambda: st.step(1), 1)
+    torch.cuda.synchronize()
+    binding.tune_record(True)
+    st.step(1)
+    recs = binding.tune_records()
+    binding.tune_record(False)
+    gemms = []
+    for r in recs:
+        k = r["key"]
+        if k[0] != binding.TUNE_GEMM_TILE or r["ms"] <= 0:
+            continue
+        fl = 2.0 * k[1] * k[2] * k[3] * (k[4] // 4) * r["launches"]
+        gemms.append({"M": k[1], "N": k[2], "K": k[3], "batch": k[4] // 4,
+                      "tile": 128 if r["value"] == 1 else 64, "launches": r["launches"],
+                      "ms": round(r["ms"], 3), "tflops": round(fl / (r["ms"] * 1e-3) / 1e12, 2),
+                      "frac_fp64_peak": round(fl / (r["ms"] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 3)})
+    gemms.sort(key=lambda g: -g["ms"])
     st.free()
     out = {"workload": "two-stream 2^12 x 2^12, interleaved (24 sites), chi=128, C5, tol=0, "
                        "D_F=4, seeded random-MPS perturbation (start state built by the oracle)",
-           "dt": w.problem.dt}
+           "dt": w.problem.dt, "classes": rates["classes"], "largest_gemms": gemms[:4]}
     if ref is not None:
         out["oracle_s_per_step"] = t_or
     out.update(mixed_precision(binding, w, f0, steps, fp64_steps_per_s=v, oracle=ref))

@@ -928,20 +928,21 @@ __global__ __launch_bounds__(LT) void qr_lds_apply_kernel(
 //   T_jj = tau_j,  T_{<j,j} = -tau_j T_{<j,<j} (V_{<j}^T v_j),
 // Q^T Y = Y - V T^T (V^T Y),  Q Y = Y - V T (V^T Y).
 // A workgroup of four waves owns 64 columns of Y (16 per wave) and streams
-// the rows twice, 256 at a time, the reflectors through LDS (loaded
+// the rows twice, 128 at a time, the reflectors through LDS (loaded
 // coalesced along each reflector), Y straight from memory (16 adjacent
-// columns per row, the loads of 64 rows issued before the matrix-core steps
+// columns per row, the loads of 32 rows issued before the matrix-core steps
 // that use them).  Pass 1 accumulates W = V^T Y and the Gram matrix V^T V
-// with v_mfma_f64_16x16x4f64; each wave forms T from the Gram matrix and tau
-// (one lane per row of T) and W' = T^T W (or T W); pass 2 subtracts V W'
-// (four matrix-core steps per 16 rows).  It reads each element of Y twice
+// with v_mfma_f64_16x16x4f64; wave 0 forms T from the Gram matrix and tau
+// (one lane per row of T) and every wave W' = T^T W (or T W); pass 2
+// subtracts V W' (four matrix-core steps per 16 rows).  Small register and
+// LDS footprints keep four workgroups on a compute unit.  It reads each element of Y twice
 // and writes it once, whatever k, and fills the chip when many lock-step
 // instances share the launch; one state alone does better with the
 // one-reflector-at-a-time kernels (more workgroups, shorter chains), so the
 // problem chooses (mps_problem.tall_apply) and the choice never depends on
 // the instance count.
 constexpr int WY_T = 256;     // 4 waves
-constexpr int WY_RC = 256;    // rows per chunk
+constexpr int WY_RC = 128;    // rows per chunk
 constexpr int WY_LD = 17;     // LDS pitch of a 16-wide row
 
 __global__ __launch_bounds__(WY_T) void qr_wy_apply_kernel(
@@ -949,7 +950,8 @@ __global__ __launch_bounds__(WY_T) void qr_wy_apply_kernel(
     CMatView Yin, int rows_in, MatView Yout, int p, int trans, Chunks ch,
     InstOff io) {
   __shared__ double Vs[WY_RC * WY_LD];
-  __shared__ double Ms[4][16 * WY_LD];  // per wave: the Gram matrix, then T
+  __shared__ double Gs[16 * WY_LD];     // the Gram matrix V^T V (from wave 0)
+  __shared__ double Ts[16 * WY_LD];     // T
   __shared__ double Wsh[4][16 * WY_LD]; // per wave: its block of V^T Y
   {
     const long o_ = io.of(blockIdx.z);
@@ -974,7 +976,6 @@ __global__ __launch_bounds__(WY_T) void qr_wy_apply_kernel(
   const int lr = l & 15, lk = l >> 4;
   const int col = blockIdx.x * 64 + w * 16 + lr;  // this lane's column (B and D)
   const bool colok = col < p;
-  double* M = Ms[w];
   double* Wl = Wsh[w];
   // stage reflector rows [i0, i0 + WY_RC) (zeros past m and past k)
   auto stage = [&](int i0) {
@@ -990,54 +991,49 @@ __global__ __launch_bounds__(WY_T) void qr_wy_apply_kernel(
     stage(i0);
     __syncthreads();
     const int nrow = min(WY_RC, m - i0);
-    for (int r64 = 0; r64 < nrow; r64 += 64) {
-      double bb[16];
+    // 32 rows per group: the 8 loads of Y are issued before the 16
+    // matrix-core steps that use them (rows past m load and stage zeros)
+    for (int r32 = 0; r32 < nrow; r32 += 32) {
+      double bb[8];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int i = i0 + r64 + 4 * q + lk;
+      for (int q = 0; q < 8; ++q) {
+        const int i = i0 + r32 + 4 * q + lk;
         bb[q] = (colok && i < rows_in) ? Yin.p[(long)i * Yin.rs + (long)col * Yin.cs] : 0.0;
       }
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
+      for (int q = 0; q < 8; ++q) {
         // A = V^T (row j = lr, k index = chunk row); B = Y rows (k, col)
-        const double a = Vs[(r64 + 4 * q + lk) * WY_LD + lr];
+        const double a = Vs[(r32 + 4 * q + lk) * WY_LD + lr];
         accW = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb[q], accW, 0, 0, 0);
         // the Gram matrix: B = V rows, the same element as A
         accG = __builtin_amdgcn_mfma_f64_16x16x4f64(a, a, accG, 0, 0, 0);
       }
     }
   }
-  // D layout: lane l, item r -> row 4 r + lk, column lr
+  // D layout: lane l, item r -> row 4 r + lk, column lr (every wave has the
+  // same Gram matrix; wave 0's is kept)
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    M[(4 * r + lk) * WY_LD + lr] = accG[r];
+    if (w == 0) Gs[(4 * r + lk) * WY_LD + lr] = accG[r];
     Wl[(4 * r + lk) * WY_LD + lr] = accW[r];
   }
   __syncthreads();
-  // T, one lane per row (every wave its own copy): t[c] = T[row][c]
-  double t[16];
-  {
-    const int row = l;  // lanes 16..63 keep zeros
-#pragma unroll
-    for (int c = 0; c < 16; ++c) t[c] = 0.0;
-#pragma unroll
+  // T by wave 0, one lane per row, column after column; each lane reads
+  // back only the entries of its own row
+  if (w == 0 && l < 16) {
+    const int row = l;
     for (int c = 0; c < 16; ++c) {
       const double tc = (c < k) ? tau[c] : 0.0;
+      double v = 0.0;
       if (row == c) {
-        t[c] = tc;
+        v = tc;
       } else if (row < c) {
         double acc = 0.0;
-#pragma unroll
-        for (int q = 0; q < 16; ++q)
-          if (q >= row && q < c) acc = fma(t[q], M[q * WY_LD + c], acc);
-        t[c] = -tc * acc;
+        for (int q = row; q < c; ++q) acc = fma(Ts[row * WY_LD + q], Gs[q * WY_LD + c], acc);
+        v = -tc * acc;
       }
+      Ts[row * WY_LD + c] = v;
     }
-  }
-  __syncthreads();
-  if (l < 16) {
-#pragma unroll
-    for (int c = 0; c < 16; ++c) M[l * WY_LD + c] = t[c];
   }
   __syncthreads();
   // W' = T^T W (trans) or T W, as the B operand of pass 2:
@@ -1049,38 +1045,38 @@ __global__ __launch_bounds__(WY_T) void qr_wy_apply_kernel(
     double acc = 0.0;
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-      const double tq = trans ? M[q * WY_LD + row] : M[row * WY_LD + q];
+      const double tq = trans ? Ts[q * WY_LD + row] : Ts[row * WY_LD + q];
       acc = fma(tq, Wl[q * WY_LD + lr], acc);
     }
     bw[s4] = acc;
   }
-  // pass 2: Y -= V W', four tiles of 16 rows per group of 64
+  // pass 2: Y -= V W', two tiles of 16 rows per group of 32
   for (int i0 = 0; i0 < m; i0 += WY_RC) {
     __syncthreads();
     stage(i0);
     __syncthreads();
     const int nrow = min(WY_RC, m - i0);
-    for (int r64 = 0; r64 < nrow; r64 += 64) {
-      double yy[4][4];
+    for (int r32 = 0; r32 < nrow; r32 += 32) {
+      double yy[2][4];
 #pragma unroll
-      for (int tt = 0; tt < 4; ++tt)
+      for (int tt = 0; tt < 2; ++tt)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int i = i0 + r64 + 16 * tt + 4 * r + lk;
+          const int i = i0 + r32 + 16 * tt + 4 * r + lk;
           yy[tt][r] = (colok && i < rows_in) ? Yin.p[(long)i * Yin.rs + (long)col * Yin.cs] : 0.0;
         }
 #pragma unroll
-      for (int tt = 0; tt < 4; ++tt) {
+      for (int tt = 0; tt < 2; ++tt) {
         dbl4 d = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int s4 = 0; s4 < 4; ++s4) {
-          // A[row][kk] = V[chunk row r64 + 16 tt + lr][4 s + lk]
-          const double a = Vs[(r64 + 16 * tt + lr) * WY_LD + 4 * s4 + lk];
+          // A[row][kk] = V[chunk row r32 + 16 tt + lr][4 s + lk]
+          const double a = Vs[(r32 + 16 * tt + lr) * WY_LD + 4 * s4 + lk];
           d = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bw[s4], d, 0, 0, 0);
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int i = i0 + r64 + 16 * tt + 4 * r + lk;
+          const int i = i0 + r32 + 16 * tt + 4 * r + lk;
           if (colok && i < m) Yout.p[(long)i * Yout.rs + (long)col * Yout.cs] = yy[tt][r] - d[r];
         }
       }
