@@ -349,7 +349,7 @@ def chi128_run(binding, steps, with_oracle=True):
             continue
         fl = 2.0 * k[1] * k[2] * k[3] * (k[4] // 4) * r["launches"]
         gemms.append({"M": k[1], "N": k[2], "K": k[3], "batch": k[4] // 4,
-                      "tile": 128 if r["value"] == 1 else 64, "launches": r["launches"],
+                      "tile": {0: "64x64", 1: "128x128", 2: "128x64"}[r["value"]], "launches": r["launches"],
                       "ms": round(r["ms"], 3), "tflops": round(fl / (r["ms"] * 1e-3) / 1e12, 2),
                       "frac_fp64_peak": round(fl / (r["ms"] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 3)})
     gemms.sort(key=lambda g: -g["ms"])

@@ -180,7 +180,8 @@ mps_status mpsb_profile_nested_flops(int32_t cls, double* flops);
  * For two launches the library has several kernel variants that give
  * bit-identical results and differ only in how the work is spread over
  * workgroups and waves: the output tile of the FP64 GEMM (knob 1: value 0
- * = 64 x 64, 1 = 128 x 128; used when K is not split) and the kernel of a
+ * = 64 x 64, 1 = 128 x 128, 2 = 128 x 64; used when K is not split) and the
+ * kernel of a
  * Householder reflector application (knob 2: value 1, 2 or 4 columns per
  * wave streaming the reflectors into registers; 9 or 10 for 1 or 2 columns
  * per wave with the reflectors shared by a workgroup through LDS, from 257

@@ -111,17 +111,26 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(
 // step t + 1 are in flight while the matrix cores work on step t, and one
 // barrier per step separates the buffers.  AK: A's k index is contiguous
 // (row-major A); BNF: B's n index is contiguous (row-major B); the loads of
-// each thread walk the contiguous index.
+// each thread walk the contiguous index.  TN = 64 gives 128 x 64 output
+// tiles (each wave 64 x 32, 4 x 2 blocks): twice the tiles of a product, for
+// shapes whose 128 x 128 tiles leave the last round of compute units mostly
+// idle.  Every output sums its K products in the same order on the same
+// instruction in all three tilings (64 x 64, 128 x 128, 128 x 64), so they
+// give the same bits.
 constexpr int TB = 128, TK = 16, TLD = TB + 2;
 
-template <int AK, int BNF>
+template <int AK, int BNF, int TN = 128>
 __global__ __launch_bounds__(NT, 2) void gemm_f64_t128_kernel(
     int M, int N, int K, double alpha, const double* __restrict__ A, long ars,
     long acs, long abs_, const double* __restrict__ B, long brs, long bcs,
     long bbs, double beta, double* __restrict__ C, long crs, long ccs, long cbs,
     int nsplit, int kchunk, int zper, InstOff io) {
+  static_assert(TN == 128 || TN == 64, "tile width 128 or 64");
+  constexpr int PB = TN / 16;        // B values each thread stages per step
+  constexpr int TPC = TK / PB;       // threads per column of a k-major B tile
+  constexpr int NJ = TN / 32;        // 16-wide blocks per wave along n
   __shared__ double As[2][TK][TLD];
-  __shared__ double Bs[2][TK][TLD];
+  __shared__ double Bs[2][TK][TN + 2];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
@@ -132,7 +141,7 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_t128_kernel(
   const int zb = blockIdx.z % zper;
   const long bz = zb / nsplit;
   const int split = zb % nsplit;
-  const int m0 = blockIdx.y * TB, n0 = blockIdx.x * TB;
+  const int m0 = blockIdx.y * TB, n0 = blockIdx.x * TN;
   A += bz * abs_;
   B += bz * bbs;
   C += bz * cbs + (long)split * M * N * (nsplit > 1 ? 1 : 0);
@@ -145,7 +154,7 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_t128_kernel(
   //   A k-fast: row ra = tid / 2, k = (tid % 2) * 8 + e; else k = tid / 16,
   //   row = (tid % 16) * 8 + e.  B n-fast: k = tid / 16, col = (tid % 16) * 8
   //   + e; else col = tid / 2, k = (tid % 2) * 8 + e.
-  double ra[8], rb[8];
+  double ra[8], rb[PB];
   auto load = [&](int k0) {
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
@@ -156,10 +165,10 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_t128_kernel(
       ra[e] = (gr < M && gk < kend) ? A[(long)gr * ars + (long)gk * acs] : 0.0;
     }
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
+    for (int e = 0; e < PB; ++e) {
       int c, k;
-      if (BNF) { k = tid >> 4; c = ((tid & 15) << 3) + e; }
-      else { c = tid >> 1; k = ((tid & 1) << 3) + e; }
+      if (BNF) { k = tid >> 4; c = (tid & 15) * PB + e; }
+      else { c = tid / TPC; k = (tid % TPC) * PB + e; }
       const int gc = n0 + c, gk = k0 + k;
       rb[e] = (gc < N && gk < kend) ? B[(long)gk * brs + (long)gc * bcs] : 0.0;
     }
@@ -169,16 +178,19 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_t128_kernel(
     for (int e = 0; e < 8; ++e) {
       if (AK) As[buf][((tid & 1) << 3) + e][tid >> 1] = ra[e];
       else As[buf][tid >> 4][((tid & 15) << 3) + e] = ra[e];
-      if (BNF) Bs[buf][tid >> 4][((tid & 15) << 3) + e] = rb[e];
-      else Bs[buf][((tid & 1) << 3) + e][tid >> 1] = rb[e];
+    }
+#pragma unroll
+    for (int e = 0; e < PB; ++e) {
+      if (BNF) Bs[buf][tid >> 4][(tid & 15) * PB + e] = rb[e];
+      else Bs[buf][(tid % TPC) * PB + e][tid / TPC] = rb[e];
     }
   };
 
-  dbl4 acc[4][4];
+  dbl4 acc[4][NJ];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < NJ; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
 
   if (nt > 0) {
     load(kbeg);
@@ -191,15 +203,15 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_t128_kernel(
 #pragma unroll
     for (int kk = 0; kk < TK; kk += 4) {
       const int kr = kk + (lane >> 4);
-      double a[4], b[4];
+      double a[4], b[NJ];
 #pragma unroll
       for (int i = 0; i < 4; ++i) a[i] = As[buf][kr][wm * 64 + i * 16 + (lane & 15)];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[buf][kr][wn * 64 + j * 16 + (lane & 15)];
+      for (int j = 0; j < NJ; ++j) b[j] = Bs[buf][kr][wn * (TN / 2) + j * 16 + (lane & 15)];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < NJ; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     if (t + 1 < nt) store(buf ^ 1);
@@ -210,11 +222,11 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_t128_kernel(
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < NJ; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int gr = m0 + wm * 64 + i * 16 + 4 * r + (lane >> 4);
-        const int gc = n0 + wn * 64 + j * 16 + (lane & 15);
+        const int gc = n0 + wn * (TN / 2) + j * 16 + (lane & 15);
         if (gr < M && gc < N) {
           double* cp = C + (long)gr * crs + (long)gc * ccs;
           const double v = alpha * acc[i][j][r];
@@ -401,14 +413,16 @@ void gemm(hipStream_t s, int M, int N, int K, double alpha, CMatView A,
   // instruction)
   bool big = prec == 0 && nsplit == 1 && M >= TB && N >= TB && K >= TK &&
              (long)ceil_div(N, TB) * ceil_div(M, TB) * batch >= 512;
+  // tiling: 0 = 64 x 64, 1 = 128 x 128, 2 = 128 x 64
   TunePick tp{big ? 1 : 0, -1};
   if (prec == 0 && nsplit == 1) {
     const TuneKey key{{kTuneGemmTile, M, N, K, 4 * batch + 2 * a_kfast + b_nfast,
                        tune_inst_class(ninst)}};
-    tp = tune_pick(s, key, big ? 1 : 0, 3u);
-    big = tp.value == 1;
+    tp = tune_pick(s, key, big ? 1 : 0, 7u);
+    big = tp.value != 0;
   }
-  const int tm = big ? TB : BM, tn = big ? TB : BN;
+  const bool half = big && tp.value == 2;
+  const int tm = big ? TB : BM, tn = big ? (half ? TB / 2 : TB) : BN;
   const int kchunk = (nsplit > 1) ? ceil_div(ceil_div(K, nsplit), BK) * BK : K;
   if (nsplit > 1) nsplit = ceil_div(K, kchunk);
   const int bmax = std::max(1, 65535 / (nsplit * ninst));
@@ -418,8 +432,10 @@ void gemm(hipStream_t s, int M, int N, int K, double alpha, CMatView A,
     dim3 grid(ceil_div(N, tn), ceil_div(M, tm), zper * ninst);
     const int slot = prof_begin(s);
     if (big && nsplit == 1) {
-      auto k = a_kfast ? (b_nfast ? gemm_f64_t128_kernel<1, 1> : gemm_f64_t128_kernel<1, 0>)
-                       : (b_nfast ? gemm_f64_t128_kernel<0, 1> : gemm_f64_t128_kernel<0, 0>);
+      auto k = half ? (a_kfast ? (b_nfast ? gemm_f64_t128_kernel<1, 1, 64> : gemm_f64_t128_kernel<1, 0, 64>)
+                               : (b_nfast ? gemm_f64_t128_kernel<0, 1, 64> : gemm_f64_t128_kernel<0, 0, 64>))
+                    : (a_kfast ? (b_nfast ? gemm_f64_t128_kernel<1, 1> : gemm_f64_t128_kernel<1, 0>)
+                               : (b_nfast ? gemm_f64_t128_kernel<0, 1> : gemm_f64_t128_kernel<0, 0>));
       hipLaunchKernelGGL(k, grid, dim3(NT), 0, s, M, N, K, alpha,
                          A.p + (long)b0 * A.bs, A.rs, A.cs, A.bs,
                          B.p + (long)b0 * B.bs, B.rs, B.cs, B.bs, beta,

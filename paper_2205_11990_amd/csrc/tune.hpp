@@ -29,7 +29,7 @@
 namespace mpsv {
 
 enum TuneKnob : int32_t {
-  kTuneGemmTile = 1,   // 0: 64 x 64 output tiles, 1: 128 x 128
+  kTuneGemmTile = 1,   // 0: 64 x 64 output tiles, 1: 128 x 128, 2: 128 x 64
   kTuneApplyCols = 2,  // columns per wave: 1, 2 or 4; LDS-shared: 8 + 1 or 2;
                        // LDS-shared with staged columns: 16 + 1 or 2
 };

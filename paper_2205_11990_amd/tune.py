@@ -2,7 +2,7 @@
 
 Two launches of the library have kernel variants that compute the same bits
 and differ only in how the work is spread over the device: the output tile
-of the FP64 GEMM (64 x 64 or 128 x 128) and, for a Householder reflector
+of the FP64 GEMM (64 x 64, 128 x 128 or 128 x 64) and, for a Householder reflector
 application, the columns each wave carries (1, 2 or 4) and whether the
 reflectors are streamed into each wave's registers or shared by the waves of
 a workgroup through LDS (values 9 and 10: 1 or 2 columns per wave; 17 and 18:
@@ -236,7 +236,7 @@ def main():
         f.write("# Launch-shape table of libmpsvlasov for gfx950, written by\n")
         f.write("# paper_2205_11990_amd/tune.py (--workloads %s --reps %d --min-gain %g).\n"
                 % (args.workloads, args.reps, args.min_gain))
-        f.write("# knob 1: FP64 GEMM tile (0: 64x64, 1: 128x128), key M N K 4*batch+layout;\n")
+        f.write("# knob 1: FP64 GEMM tile (0: 64x64, 1: 128x128, 2: 128x64), key M N K 4*batch+layout;\n")
         f.write("# knob 2: reflector application (1, 2, 4 columns per wave; 9, 10: LDS-shared with 1, 2;\n")
         f.write("#         17, 18: LDS-shared with the columns staged),\n")
         f.write("#         key rows reflectors columns 2*chunks+trans;\n")

@@ -66,9 +66,9 @@ def test_gemm_tiles_give_identical_bits(B, M, N, K, at, bt):
     assert len(recs) == 1
     key = recs[0]["key"]
     assert key[1:4] == (M, N, K) and key[4] == 4 + 2 * (0 if at else 1) + (0 if bt else 1)
-    assert key[5] == 0 and recs[0]["allowed"] == [0, 1]
+    assert key[5] == 0 and recs[0]["allowed"] == [0, 1, 2]
     base = run()
-    for v in (0, 1):
+    for v in (0, 1, 2):
         B.tune_set(key, v)
         got = run()
         assert np.array_equal(got, base), v

@@ -116,7 +116,7 @@ def test_committed_table_is_the_default_and_well_formed(B):
         f = [int(x) for x in line.split()]
         assert len(f) == 7 and f[0] in (1, 2) and 0 <= f[5] <= 3
         if f[0] == 1:
-            assert f[6] in (0, 1)
+            assert f[6] in (0, 1, 2)
         else:
             assert f[6] in (1, 2, 4, 9, 10, 17, 18)
         n += 1
