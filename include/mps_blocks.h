@@ -48,6 +48,16 @@ mps_status mpsb_gemm_strided(int32_t M, int32_t N, int32_t K, double alpha,
 mps_status mpsb_qr(int32_t m, int32_t n, double* A, double* Q,
                    hipStream_t stream);
 
+/* mpsb_qr with the reflector-application mode of a problem, tall_apply as
+ * in mps_problem.tall_apply (0 or 1, else MPS_EINVAL).  With 1 a block of
+ * more than 512 rows is factored in groups of four 16-column panels: each
+ * panel updates only the rest of its group, and the group's 64 reflectors
+ * reach the trailing columns (and later products with Q) as one compact-WY
+ * block.  The same factorisation as mpsb_qr up to rounding (SI,
+ * "Canonicalization and Compression"). */
+mps_status mpsb_qr_tall(int32_t m, int32_t n, double* A, double* Q,
+                        int32_t tall_apply, hipStream_t stream);
+
 /* Truncated SVD of X (m x c, device, overwritten) with the rank rule of the
  * compression sweep: D = min(cap, smallest D' with relative discarded weight
  * <= tol), cap <= 0 meaning no cap (eq. 5).  Outputs (device): Vt (D x c),

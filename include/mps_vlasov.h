@@ -159,9 +159,14 @@ typedef struct mps_problem {
  * how many lock-step instances share its launches.
  *   MPS_TALL_APPLY_REFLECTORS: one reflector at a time, each column in the
  *     registers of one wave (shortest chain: fastest for one state);
- *   MPS_TALL_APPLY_WY: the panel's reflectors as one compact-WY block on the
- *     matrix cores, the block streamed twice (fastest for large lock-step
- *     batches, where the launches fill the device). */
+ *   MPS_TALL_APPLY_WY: blocks of 16-column panels are factored in groups
+ *     of four, each panel updating only the rest of its group, and a
+ *     group's 64 reflectors reach the trailing columns, and later products
+ *     with Q, as one compact-WY block on the matrix cores (the block
+ *     streamed twice per group); the remaining applications of up to 16
+ *     reflectors to at least 32 columns take a compact-WY block of their
+ *     own (fastest for large lock-step batches, where the launches fill
+ *     the device). */
 typedef enum mps_tall_apply {
   MPS_TALL_APPLY_REFLECTORS = 0,
   MPS_TALL_APPLY_WY = 1

@@ -69,6 +69,7 @@ _SIGS = {
     "mpsb_gemm": [_I32, _I32, _I32, _D, _P, _I64, _P, _I64, _D, _P, _I64, _P],
     "mpsb_gemm_prec": [_I32, _I32, _I32, _D, _P, _I64, _P, _I64, _D, _P, _I64, _I32, _P],
     "mpsb_qr": [_I32, _I32, _P, _P, _P],
+    "mpsb_qr_tall": [_I32, _I32, _P, _P, _I32, _P],
     "mpsb_gemm_strided": [_I32, _I32, _I32, _D, _P, _I64, _I64, _I64, _P, _I64, _I64, _I64,
                           _D, _P, _I64, _I64, _I64, _I32, _I32, _P],
     "mpsb_svd_truncate": [_I32, _I32, _P, _I32, _D, _P, _P, _P, _PI32, _PD, _P],
@@ -493,14 +494,18 @@ def gemm_strided(M, N, K, alpha, A, a_strides, B, b_strides, beta, C, c_strides,
     return C
 
 
-def qr(A, stream=None):
-    """Returns (R upper-trapezoid k x n, Q thin m x k) as device tensors."""
+def qr(A, stream=None, tall_apply=None):
+    """Returns (R upper-trapezoid k x n, Q thin m x k) as device tensors;
+    tall_apply selects the reflector-application mode (mpsb_qr_tall)."""
     torch = _torch()
     A = _dev(A).clone()
     m, n = A.shape
     k = min(m, n)
     Q = torch.empty(m, k, dtype=torch.float64, device="cuda")
-    _check(lib().mpsb_qr(m, n, _ptr(A), _ptr(Q), _stream(stream)))
+    if tall_apply is None:
+        _check(lib().mpsb_qr(m, n, _ptr(A), _ptr(Q), _stream(stream)))
+    else:
+        _check(lib().mpsb_qr_tall(m, n, _ptr(A), _ptr(Q), int(tall_apply), _stream(stream)))
     return torch.triu(A[:k]), Q
 
 

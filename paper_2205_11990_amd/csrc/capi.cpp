@@ -444,8 +444,18 @@ mps_status mpsb_gemm_strided(int32_t M, int32_t N, int32_t K, double alpha,
 
 mps_status mpsb_qr(int32_t m, int32_t n, double* A, double* Q,
                    hipStream_t stream) {
+  return mpsb_qr_tall(m, n, A, Q, MPS_TALL_APPLY_REFLECTORS, stream);
+}
+
+mps_status mpsb_qr_tall(int32_t m, int32_t n, double* A, double* Q,
+                        int32_t tall_apply, hipStream_t stream) {
   return guarded([&] {
     MPSV_CHECK(m >= 1 && n >= 1 && A, mpsv::kEinval, "bad QR arguments");
+    MPSV_CHECK(tall_apply == MPS_TALL_APPLY_REFLECTORS || tall_apply == MPS_TALL_APPLY_WY,
+               mpsv::kEinval, "tall_apply must be 0 or 1");
+    mpsv::Lanes l;
+    l.tall_apply = tall_apply;
+    mpsv::LanesScope ls(l);
     std::lock_guard<std::mutex> lk(g_blocks_mu);
     mpsv::Arena& ws = blocks().scratch();
     mpsv::ArenaScope sc(ws);

@@ -93,6 +93,36 @@ struct InstOff {
 inline InstOff inst_off() { return InstOff{lanes().first, lanes().stride}; }
 inline int inst_count() { return lanes().n; }
 
+// Page-locked host buffer that only grows (released with its owner): the
+// read-backs of all lock-step instances land in it as one transfer.
+class PinnedBuf {
+ public:
+  PinnedBuf() = default;
+  ~PinnedBuf() {
+    if (p_) (void)hipHostFree(p_);
+  }
+  PinnedBuf(const PinnedBuf&) = delete;
+  PinnedBuf& operator=(const PinnedBuf&) = delete;
+  void* get(size_t bytes) {
+    if (bytes > cap_) {
+      if (p_) (void)hipHostFree(p_);
+      p_ = nullptr;
+      cap_ = 0;
+      MPSV_HIP(hipHostMalloc(&p_, bytes, hipHostMallocDefault));
+      cap_ = bytes;
+    }
+    return p_;
+  }
+
+ private:
+  void* p_ = nullptr;
+  size_t cap_ = 0;
+};
+
+// `bytes` bytes at d of every instance of the calling thread's lanes into
+// h (instance i's at h + i * bytes) on stream s: one strided transfer.
+void lanes_d2h(hipStream_t s, void* h, const void* d, size_t bytes);
+
 template <class T>
 __host__ __device__ inline T* shifted(T* p, long off) {
   return reinterpret_cast<T*>(reinterpret_cast<char*>(p) + off);

@@ -558,6 +558,12 @@ MemoryModel memory_model(const Problem& q) {
   S *= 8.0;
   N *= 8.0;
   Ns *= 8.0;
+  // compact-WY mode: a 64 x 64 T beside each group of 64 reflectors of a
+  // block over 512 rows (under 1/7 of the group's reflector storage)
+  if (q.tall_apply == 1) {
+    N *= 1.15;
+    Ns *= 1.15;
+  }
   I *= 8.0;
   double work = il ? std::max({12.0 * N, 3.5 * I, 60.0 * S}) : std::max(60.0 * S, 12.0 * N);
   double work2 = std::max(80.0 * S, 12.0 * Ns);
@@ -1576,10 +1582,8 @@ void Engine::check_finite(const DMps& fn, hipStream_t s) {
   for (auto& c : fn) count_nonfinite(s, c.p, c.size(), dflag_);
   // one flag per instance of the lanes
   const int ni = inst_count();
-  std::vector<int> bad((size_t)ni, 0);
-  for (int i = 0; i < ni; ++i)
-    MPSV_HIP(hipMemcpyAsync(&bad[i], shifted(dflag_, lanes().first + (long)i * lanes().stride),
-                            sizeof(int), hipMemcpyDeviceToHost, s));
+  int* bad = (int*)flags_host_.get((size_t)ni * sizeof(int));
+  lanes_d2h(s, bad, dflag_, sizeof(int));
   MPSV_HIP(hipStreamSynchronize(s));
   for (int i = 0; i < ni; ++i)
     if (bad[i])

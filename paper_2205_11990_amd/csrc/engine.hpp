@@ -306,6 +306,7 @@ class Engine {
   double t_ = 0.0;
   long steps_ = 0;
   int* dflag_ = nullptr;
+  PinnedBuf flags_host_;  // the finiteness flags of every instance
   // a kIdent x kIdent identity (device), for the exact gauges of the sweep
   static constexpr int kIdent = 256;
   double* ident_ = nullptr;

@@ -339,29 +339,26 @@ void SvdOutcomes::end(hipStream_t s) {
   // the used slots of every lock-step instance, one row per instance
   const int ni = inst_count();
   const size_t row = (size_t)rec_.used * kInfoWords;
-  std::vector<double> h(row * (size_t)ni);
-  for (int i = 0; i < ni; ++i)
-    MPSV_HIP(hipMemcpyAsync(h.data() + row * i,
-                            shifted(ring_, lanes().first + (long)i * lanes().stride),
-                            row * sizeof(double), hipMemcpyDeviceToHost, s));
+  double* h = (double*)host_.get(row * (size_t)ni * sizeof(double));
+  lanes_d2h(s, h, ring_, row * sizeof(double));
   MPSV_HIP(hipStreamSynchronize(s));
   int code = 0;
   std::string msg;
   for (int inst = 0; inst < ni; ++inst) {
-    const double* hi = h.data() + row * inst;
+    const double* hi = h + row * inst;
     for (int i = 0; i < rec_.used; ++i) {
       const double* w = hi + (long)i * kInfoWords;
       g_stats.jacobi_sweeps += (long)w[2];
       if (code) continue;
-      const std::string who = ni > 1 ? "instance " + std::to_string(inst) + ": " : "";
       if (rec_.split[i] && w[5] != 0.0) {
         code = kEdevice;
-        msg = who + "Jacobi SVD: the workgroups did not meet in time";
+        msg = "Jacobi SVD: the workgroups did not meet in time";
       } else if (w[3] == 0.0) {
         code = kEnumeric;
-        msg = who + "Jacobi SVD did not converge within " +
-              std::to_string(g_max_sweeps) + " sweeps";
+        msg = "Jacobi SVD did not converge within " + std::to_string(g_max_sweeps) +
+              " sweeps";
       }
+      if (code && ni > 1) msg = "instance " + std::to_string(inst) + ": " + msg;
     }
     for (size_t t = 0; t < rec_.disc.size(); ++t)
       rec_.disc[t].first[inst * rec_.disc_stride[t]] =
@@ -486,6 +483,14 @@ static void fill_rows_zero(hipStream_t s, double* X, int r0, int r1, int nc,
   MPSV_LAUNCHED();
 }
 
+// Panel groups of the compact-WY mode: blocks of more than 512 rows whose
+// register panels are 16 columns wide, with more than one panel left.
+constexpr int kGroupCols = 64;
+static bool group_panels(int rows, int ncols) {
+  return lanes().tall_apply == 1 && rows > 512 && qr_reg_panel_cols(rows) == 16 &&
+         ncols > 16;
+}
+
 void qr_factor(hipStream_t s, Arena& ws, double* A, int m, int n, long ld,
                QrFactor& f, MatView R) {
   set_attrs();
@@ -502,6 +507,38 @@ void qr_factor(hipStream_t s, Arena& ws, double* A, int m, int n, long ld,
     double* P = A + (long)k0 * ld + k0;
     QrPanel pn;
     pn.k0 = k0;
+    if (rows <= 2048 && group_panels(rows, n - k0)) {
+      // compact-WY mode: up to four 16-column panels factored in turn, each
+      // updating only the group's columns right of it; the group's
+      // reflectors then reach the trailing columns as one block
+      const int kg = std::min(kGroupCols, n - k0);
+      const int np = ceil_div(kg, 16);
+      pn.jb = kg;
+      pn.reg = true;
+      pn.grp = np;
+      pn.V = ws.alloc((size_t)qr_group_voff(rows, np));
+      pn.tau = ws.alloc((size_t)kGroupCols);
+      pn.T = ws.alloc((size_t)kGroupCols * kGroupCols);
+      for (int t = 0; t < np; ++t) {
+        const int c0 = 16 * t, jb = std::min(16, kg - c0), r = rows - c0;
+        double* Pt = P + (long)c0 * ld + c0;
+        double* Vp = pn.V + qr_group_voff(rows, t);
+        qr_reg_factor(s, CMatView{Pt, ld, 1, 0}, r, jb, MatView{Pt, ld, 1, 0}, Vp,
+                      pn.tau + c0);
+        const int nin = kg - c0 - jb;
+        if (nin > 0)
+          qr_reg_apply(s, Vp, pn.tau + c0, r, jb, CMatView{Pt + jb, ld, 1, 0}, r,
+                       MatView{Pt + jb, ld, 1, 0}, nin, true);
+      }
+      qr_wy_group_t(s, pn.V, pn.tau, rows, kg, pn.T);
+      const int n2 = n - k0 - kg;
+      if (n2 > 0)
+        qr_wy_group_apply(s, pn.V, pn.T, rows, kg, CMatView{P + kg, ld, 1, 0}, rows,
+                          MatView{P + kg, ld, 1, 0}, n2, true);
+      f.panels.push_back(pn);
+      k0 += kg;
+      continue;
+    }
     if (rows <= 2048) {
       // register-resident panel; the trailing columns are updated by the
       // reflector-application kernel
@@ -598,7 +635,10 @@ void qr_apply_q_view(hipStream_t s, Arena& ws, const QrFactor& f, CMatView Yin,
   if (nc <= 0) return;
   if (f.panels.size() == 1 && f.panels[0].reg) {
     const QrPanel& pn = f.panels[0];
-    qr_reg_apply(s, pn.V, pn.tau, f.m, pn.jb, Yin, rows_in, Yout, nc, false);
+    if (pn.grp)
+      qr_wy_group_apply(s, pn.V, pn.T, f.m, pn.jb, Yin, rows_in, Yout, nc, false);
+    else
+      qr_reg_apply(s, pn.V, pn.tau, f.m, pn.jb, Yin, rows_in, Yout, nc, false);
     return;
   }
   if (Yout.cs != 1) {
@@ -622,6 +662,11 @@ void qr_apply_q(hipStream_t s, Arena& ws, const QrFactor& f, double* X, int nc,
     const QrPanel& pn = f.panels[p];
     const int rows = f.m - pn.k0;
     double* X2 = X + (long)pn.k0 * ldx;
+    if (pn.grp) {
+      qr_wy_group_apply(s, pn.V, pn.T, rows, pn.jb, CMatView{X2, ldx, 1, 0}, rows,
+                        MatView{X2, ldx, 1, 0}, nc, false);
+      continue;
+    }
     if (pn.reg) {
       qr_reg_apply(s, pn.V, pn.tau, rows, pn.jb, CMatView{X2, ldx, 1, 0}, rows,
                    MatView{X2, ldx, 1, 0}, nc, false);

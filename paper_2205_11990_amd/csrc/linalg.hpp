@@ -18,9 +18,14 @@ namespace mpsv {
 // panel: chunks of crows rows with their own reflectors (V at c*crows*jb,
 // tau at c*jb) and the reflectors Vt, taut of the stacked chunk factors
 // (srows rows, chunk c's at rows c*jb).
+// A group (grp > 0, the compact-WY mode on blocks over 512 rows) is grp
+// register panels of 16 columns whose jb reflectors act as one block: V in
+// the storage of qr_wy_group_apply, tau in order and its T (64 x 64).
 struct QrPanel {
   int k0 = 0, jb = 0;
   bool reg = false;
+  int grp = 0;
+  double* T = nullptr;
   double* V = nullptr;
   double* tau = nullptr;
   int crows = 0, srows = 0;
@@ -112,6 +117,7 @@ class SvdOutcomes {
   double* ring_ = nullptr;
   bool on_ = false;
   Record rec_;
+  PinnedBuf host_;  // the read-back of every instance's used slots
 };
 
 // Truncated SVD of the row-major m x c matrix X (leading dimension ldx).

@@ -14,6 +14,18 @@ Lanes& lanes() {
   return l;
 }
 
+void lanes_d2h(hipStream_t s, void* h, const void* d, size_t bytes) {
+  const int ni = inst_count();
+  const void* src = shifted(d, lanes().first);
+  if (ni == 1) {
+    MPSV_HIP(hipMemcpyAsync(h, src, bytes, hipMemcpyDeviceToHost, s));
+    return;
+  }
+  MPSV_CHECK((size_t)lanes().stride >= bytes, kEinval, "lanes_d2h: rows overlap");
+  MPSV_HIP(hipMemcpy2DAsync(h, bytes, src, (size_t)lanes().stride, bytes, (size_t)ni,
+                            hipMemcpyDeviceToHost, s));
+}
+
 namespace {
 
 inline int grid_for(long n) {

@@ -978,11 +978,20 @@ __global__ __launch_bounds__(WY_T) void qr_wy_apply_kernel(
   const bool colok = col < p;
   double* Wl = Wsh[w];
   // stage reflector rows [i0, i0 + WY_RC) (zeros past m and past k)
+  // (all eight loads of a thread issued before the first store)
   auto stage = [&](int i0) {
-    for (int e = tid; e < WY_RC * 16; e += WY_T) {
+    double v[WY_RC * 16 / WY_T];
+#pragma unroll
+    for (int it = 0; it < WY_RC * 16 / WY_T; ++it) {
+      const int e = tid + it * WY_T;
       const int j = e / WY_RC, r = e % WY_RC;
       const int i = i0 + r;
-      Vs[r * WY_LD + j] = (j < k && i < m) ? V[(long)j * m + i] : 0.0;
+      v[it] = (j < k && i < m) ? V[(long)j * m + i] : 0.0;
+    }
+#pragma unroll
+    for (int it = 0; it < WY_RC * 16 / WY_T; ++it) {
+      const int e = tid + it * WY_T;
+      Vs[(e % WY_RC) * WY_LD + e / WY_RC] = v[it];
     }
   };
   dbl4 accW = {0.0, 0.0, 0.0, 0.0}, accG = {0.0, 0.0, 0.0, 0.0};
@@ -1080,6 +1089,271 @@ __global__ __launch_bounds__(WY_T) void qr_wy_apply_kernel(
           if (colok && i < m) Yout.p[(long)i * Yout.rs + (long)col * Yout.cs] = yy[tt][r] - d[r];
         }
       }
+    }
+  }
+}
+
+// Groups of up to four 16-column panels of a tall block applied as one
+// compact-WY block, Q_g = H_0 ... H_{k-1} = I - V T V^T (k <= 64), in the
+// compact-WY mode: the trailing columns of the block are read and written
+// once per 64 reflectors instead of once per 16.  The group's reflectors
+// are kept panel after panel: panel t (reflectors 16 t .. 16 t + 15,
+// starting at row 16 t of the group's m rows) column-major over its own
+// m - 16 t rows, unit diagonal and zeros above, at offset
+// group_voff(m, t); the rows above 16 t are zero and are not stored.
+constexpr int WG_T = 256;   // 4 waves
+constexpr int WG_RC = 64;   // rows per staged chunk
+constexpr int WG_P1 = 72;   // LDS pitch of V read along the reflectors
+constexpr int WG_P2 = 68;   // LDS pitch of V read down the rows
+
+__host__ __device__ inline long group_voff(int m, int t) {
+  return 16L * ((long)t * m - 8L * t * (t - 1));
+}
+
+// Rows [i0, i0 + WG_RC) of the group's m x 64 reflector matrix, as 16
+// values per thread (zeros past m, above each panel's first row and past
+// k): thread tid takes reflector 16 t + (tid >> 4) of panel t = it & 3 and
+// row 16 (it >> 2) + (tid & 15), so a wave reads 16 consecutive rows of 4
+// reflectors (128 bytes each).  All 16 loads are issued before any is
+// used; group_store puts them into LDS (pitch P) once they have arrived.
+__device__ inline void group_load(double (&v)[16], const double* __restrict__ V, int m,
+                                  int k, int i0, int tid) {
+  const int rl = tid & 15, jj = tid >> 4;
+#pragma unroll
+  for (int it = 0; it < 16; ++it) {
+    const int t = it & 3, j = 16 * t + jj;
+    const int i = i0 + 16 * (it >> 2) + rl;
+    // every lane loads (element 0 where the value is zero), so no branch
+    // separates the loads
+    const bool ok = j < k && i < m && i >= 16 * t;
+    const long idx = ok ? group_voff(m, t) + (long)jj * (m - 16 * t) + (i - 16 * t) : 0;
+    const double x = V[idx];
+    v[it] = ok ? x : 0.0;
+  }
+}
+
+template <int P>
+__device__ inline void group_store(double* Vs, const double (&v)[16], int tid) {
+  const int rl = tid & 15, jj = tid >> 4;
+#pragma unroll
+  for (int it = 0; it < 16; ++it) Vs[(16 * (it >> 2) + rl) * P + 16 * (it & 3) + jj] = v[it];
+}
+
+// T of one group (one workgroup per instance): the Gram matrix V^T V on
+// the matrix cores (its upper block triangle, each wave taking 16 rows of
+// every staged chunk, the four partial sums added through LDS), then the
+// recurrence T_jj = tau_j, T_{<j,j} = -tau_j T_{<j,<j} (V_{<j}^T v_j), one
+// lane per row of T (a lane reads only its own row, so the lanes do not
+// wait on each other).  T is written whole (64 x 64, row-major, zeros
+// below the diagonal and past k).  The next chunk's reflector rows are in
+// flight while the current chunk is multiplied.
+__global__ __launch_bounds__(WG_T) void qr_wy_group_t_kernel(
+    const double* __restrict__ V, const double* __restrict__ tau, int m, int k,
+    double* __restrict__ T, InstOff io) {
+  __shared__ double Vs[WG_RC * WG_P1];
+  __shared__ double Gs[64 * 65];
+  {
+    const long o_ = io.of(blockIdx.z);
+    V = shifted(V, o_);
+    tau = shifted(tau, o_);
+    T = shifted(T, o_);
+  }
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int lr = l & 15, lk = l >> 4;
+  // the ten blocks (a, b), a <= b, of the upper block triangle (V is zero
+  // past k, and so are those blocks)
+  dbl4 acc[10];
+#pragma unroll
+  for (int x = 0; x < 10; ++x) acc[x] = dbl4{0.0, 0.0, 0.0, 0.0};
+  double vn[16];
+  group_load(vn, V, m, k, 0, tid);
+  for (int i0 = 0; i0 < m; i0 += WG_RC) {
+    __syncthreads();
+    group_store<WG_P1>(Vs, vn, tid);
+    __syncthreads();
+    if (i0 + WG_RC < m) group_load(vn, V, m, k, i0 + WG_RC, tid);
+#pragma unroll
+    for (int q4 = 0; q4 < 4; ++q4) {
+      const double* row = Vs + (16 * w + 4 * q4 + lk) * WG_P1 + lr;
+      double a[4];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) a[b] = row[16 * b];
+      int x = 0;
+#pragma unroll
+      for (int a0 = 0; a0 < 4; ++a0)
+#pragma unroll
+        for (int b = a0; b < 4; ++b, ++x)
+          acc[x] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[a0], a[b], acc[x], 0, 0, 0);
+    }
+  }
+  // D layout: item r of lane (lk, lr) is row 4 r + lk, column lr of a
+  // block; the waves' partial sums are added in turn
+  for (int ww = 0; ww < 4; ++ww) {
+    if (w == ww) {
+      int x = 0;
+#pragma unroll
+      for (int a0 = 0; a0 < 4; ++a0)
+#pragma unroll
+        for (int b = a0; b < 4; ++b, ++x)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              double* g = &Gs[(16 * a0 + 4 * r + lk) * 65 + 16 * b + lr];
+              *g = (ww == 0 ? 0.0 : *g) + acc[x][r];
+            }
+    }
+    __syncthreads();
+  }
+  if (w == 0) {
+    double* Ts = Vs;  // pitch 65
+    const int row = l;
+    for (int c = 0; c < 64; ++c) {
+      const double tc = (c < k) ? tau[c] : 0.0;
+      double v = 0.0;
+      if (row == c) {
+        v = tc;
+      } else if (row < c && c < k) {
+        double a0 = 0.0, a1 = 0.0;
+        int q = row;
+        for (; q + 1 < c; q += 2) {
+          a0 = fma(Ts[row * 65 + q], Gs[q * 65 + c], a0);
+          a1 = fma(Ts[row * 65 + q + 1], Gs[(q + 1) * 65 + c], a1);
+        }
+        if (q < c) a0 = fma(Ts[row * 65 + q], Gs[q * 65 + c], a0);
+        v = -tc * (a0 + a1);
+      }
+      Ts[row * 65 + c] = v;
+    }
+    for (int c = 0; c < 64; ++c) T[(long)row * 64 + c] = Ts[row * 65 + c];
+  }
+}
+
+// Yout <- Q_g^T Yin (trans) or Q_g Yin = Yin - V T' (V^T Yin), T' = T^T or
+// T.  A workgroup of four waves owns 64 columns (16 per wave) and streams
+// the rows twice, 64 at a time, the reflectors staged through LDS in the
+// layout each pass reads without bank conflicts; the next chunk's rows of
+// Y and of the reflectors are loaded while the current chunk is on the
+// matrix cores.  Pass 1 accumulates W = V^T Y (64 x 16 per wave, four
+// 16 x 16 blocks); T' W comes from T staged through LDS with the blocks of
+// W as B operands; pass 2 subtracts V (T' W) sixteen rows at a time.
+__global__ __launch_bounds__(WG_T) void qr_wy_group_apply_kernel(
+    const double* __restrict__ V, const double* __restrict__ T, int m, int k,
+    CMatView Yin, int rows_in, MatView Yout, int p, int trans, InstOff io) {
+  __shared__ double Vs[WG_RC * WG_P1];
+  {
+    const long o_ = io.of(blockIdx.z);
+    V = shifted(V, o_);
+    T = shifted(T, o_);
+    Yin = shifted(Yin, o_);
+    Yout = shifted(Yout, o_);
+  }
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int lr = l & 15, lk = l >> 4;
+  const int col = blockIdx.x * 64 + w * 16 + lr;
+  const bool colok = col < p;
+  const double* yin = Yin.p + (long)(colok ? col : 0) * Yin.cs;
+  double* yout = Yout.p + (long)(colok ? col : 0) * Yout.cs;
+  // pass 1: element e of a chunk's Y registers is row 4 e + lk
+  // (loads of rows and columns outside Y read its element (0, 0) and are
+  // replaced by zeros: no branch between the loads)
+  auto load_y1 = [&](double (&y)[16], int i0) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int i = i0 + 4 * e + lk;
+      const bool ok = colok && i < rows_in;
+      const double x = yin[(long)(ok ? i : 0) * Yin.rs];
+      y[e] = ok ? x : 0.0;
+    }
+  };
+  dbl4 acc[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) acc[b] = dbl4{0.0, 0.0, 0.0, 0.0};
+  double vn[16], yn[16];
+  group_load(vn, V, m, k, 0, tid);
+  load_y1(yn, 0);
+  for (int i0 = 0; i0 < m; i0 += WG_RC) {
+    double bb[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) bb[e] = yn[e];
+    __syncthreads();
+    group_store<WG_P1>(Vs, vn, tid);
+    __syncthreads();
+    if (i0 + WG_RC < m) {
+      group_load(vn, V, m, k, i0 + WG_RC, tid);
+      load_y1(yn, i0 + WG_RC);
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const double* row = Vs + (4 * q + lk) * WG_P1 + lr;
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(row[16 * b], bb[q], acc[b], 0, 0, 0);
+      // at most four steps' LDS operands in flight (register budget)
+      if ((q & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  // T' W: block bo of the result takes the blocks bi of W on T's nonzero
+  // side (bi <= bo for T^T, bi >= bo for T); the B operand of step s of
+  // block bi is item s of acc[bi]
+  __syncthreads();
+  for (int e = tid; e < 64 * 64; e += WG_T) Vs[(e >> 6) * 65 + (e & 63)] = T[e];
+  // the first chunk of pass 2 in flight meanwhile
+  auto load_y2 = [&](double (&y)[16], int i0) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int i = i0 + 16 * (e >> 2) + 4 * (e & 3) + lk;
+      const bool ok = colok && i < rows_in;
+      const double x = yin[(long)(ok ? i : 0) * Yin.rs];
+      y[e] = ok ? x : 0.0;
+    }
+  };
+  group_load(vn, V, m, k, 0, tid);
+  load_y2(yn, 0);
+  __syncthreads();
+  dbl4 wp[4];
+#pragma unroll
+  for (int bo = 0; bo < 4; ++bo) {
+    wp[bo] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi) {
+      if (trans ? bi <= bo : bi >= bo) {
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+          const int jr = 16 * bo + lr, kq = 16 * bi + 4 * s4 + lk;
+          const double a = trans ? Vs[kq * 65 + jr] : Vs[jr * 65 + kq];
+          wp[bo] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, acc[bi][s4], wp[bo], 0, 0, 0);
+        }
+      }
+    }
+  }
+  // pass 2: Y -= V (T' W); step u of a 16-row tile takes reflectors
+  // 4 u .. 4 u + 3, its B operand item u & 3 of wp[u >> 2]; element e of a
+  // chunk's Y registers is row 16 (e >> 2) + 4 (e & 3) + lk
+  for (int i0 = 0; i0 < m; i0 += WG_RC) {
+    double yy[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) yy[e] = yn[e];
+    __syncthreads();
+    group_store<WG_P2>(Vs, vn, tid);
+    __syncthreads();
+    if (i0 + WG_RC < m) {
+      group_load(vn, V, m, k, i0 + WG_RC, tid);
+      load_y2(yn, i0 + WG_RC);
+    }
+#pragma unroll
+    for (int tt = 0; tt < 4; ++tt) {
+      if (i0 + 16 * tt < m) {
+        dbl4 d = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          d = __builtin_amdgcn_mfma_f64_16x16x4f64(Vs[(16 * tt + lr) * WG_P2 + 4 * u + lk],
+                                                   wp[u >> 2][u & 3], d, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = i0 + 16 * tt + 4 * r + lk;
+          if (colok && i < m) yout[(long)i * Yout.rs] = yy[4 * tt + r] - d[r];
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
 }
@@ -1270,6 +1544,40 @@ void qr_reg_apply(hipStream_t s, const double* V, const double* tau, int m,
   prof_end(s, slot, kClsQrApply, 4.0 * p * (double)k * (m - (k - 1) / 2.0),
            8.0 * (2.0 * m * p + (double)m * k));
   tune_end(s, tp.slot);
+}
+
+long qr_group_voff(int m, int t) { return group_voff(m, t); }
+
+void qr_wy_group_t(hipStream_t s, const double* V, const double* tau, int m, int k,
+                   double* T) {
+  MPSV_CHECK(k >= 1 && k <= 64 && k <= m, kEinval, "qr_wy_group_t: bad shape");
+  const int slot = prof_begin(s);
+  hipLaunchKernelGGL(qr_wy_group_t_kernel, dim3(1, 1, inst_count()), dim3(WG_T), 0, s, V,
+                     tau, m, k, T, inst_off());
+  MPSV_LAUNCHED();
+  // the Gram matrix's upper block triangle (10 of 16 blocks for four
+  // panels) and the recurrence; V read once, T written
+  const int np = (k + 15) / 16;
+  prof_end(s, slot, kClsQrWy, 2.0 * m * 256.0 * np * (np + 1) / 2.0 + k * (double)k * k / 3.0,
+           8.0 * ((double)m * k + 64.0 * 64.0));
+}
+
+void qr_wy_group_apply(hipStream_t s, const double* V, const double* T, int m, int k,
+                       CMatView Yin, int rows_in, MatView Yout, int p, bool trans) {
+  if (p <= 0 || k <= 0) return;
+  MPSV_CHECK(k <= 64 && k <= m && rows_in >= 1, kEinval, "qr_wy_group_apply: bad shape");
+  rows_in = std::min(rows_in, m);
+  const int slot = prof_begin(s);
+  hipLaunchKernelGGL(qr_wy_group_apply_kernel, dim3(ceil_div(p, 64), 1, inst_count()),
+                     dim3(WG_T), 0, s, V, T, m, k, Yin, rows_in, Yout, p, trans ? 1 : 0,
+                     inst_off());
+  MPSV_LAUNCHED();
+  // the two products with V (k reflectors of decreasing length) and T' W;
+  // algorithmic bytes: Y read twice and written once, the reflectors read
+  // twice
+  prof_end(s, slot, kClsQrWy,
+           4.0 * p * (double)k * (m - (k - 1) / 2.0) + 2.0 * (double)k * k * p,
+           8.0 * (3.0 * m * p + 2.0 * (double)m * k));
 }
 
 void qr_reg_factor_chunks(hipStream_t s, CMatView A, int m, int n, int rows,

@@ -29,6 +29,23 @@ void qr_reg_apply(hipStream_t s, const double* V, const double* tau, int m,
                   int k, CMatView Yin, int rows_in, MatView Yout, int p,
                   bool trans);
 
+// Groups of up to four 16-column panels (at most 64 reflectors over m
+// rows) applied as one compact-WY block Q_g = H_0 ... H_{k-1} = I - V T V^T
+// (the compact-WY mode's factorisation of blocks over 512 rows).  The
+// group's reflectors are stored panel after panel: panel t (reflectors
+// 16 t .. 16 t + 15) column-major over its own m - 16 t rows (it starts at
+// row 16 t of the group; unit diagonal, zeros above), at offset
+// qr_group_voff(m, t); tau holds the k scalars in order.
+long qr_group_voff(int m, int t);
+// T of the group: 64 x 64 row-major, upper triangular, zero past k.
+void qr_wy_group_t(hipStream_t s, const double* V, const double* tau, int m, int k,
+                   double* T);
+// Yout <- Q_g Yin (trans = false) or Q_g^T Yin (m x p blocks, any strides;
+// rows >= rows_in of Yin taken as zero).  Yout may alias Yin with the same
+// strides.
+void qr_wy_group_apply(hipStream_t s, const double* V, const double* T, int m, int k,
+                       CMatView Yin, int rows_in, MatView Yout, int p, bool trans);
+
 // Row-chunked factorisation of a tall panel (the first step of a TSQR): A
 // (m x n) is cut into chunks of `rows` rows (the last one may be shorter;
 // rows >= n, rows <= 2048, n <= qr_reg_panel_cols(rows)), each factored on

@@ -152,6 +152,36 @@ def test_qr_with_zero_and_repeated_columns(B, m, n):
     assert np.allclose(np.tril(R, -1), 0)
 
 
+@pytest.mark.parametrize("m,n,rankdef", [(600, 100, False), (1024, 512, False), (2048, 512, False),
+                                          (1100, 300, True), (700, 64, False), (2048, 40, True),
+                                          (530, 530, False), (1500, 70, False), (513, 33, True)])
+def test_qr_panel_groups_of_the_compact_wy_mode(B, m, n, rankdef):
+    """Blocks over 512 rows in the compact-WY mode are factored in groups of
+    four 16-column panels whose 64 reflectors reach the trailing columns and
+    the products with Q as one block (last groups of fewer panels and a
+    last panel of fewer columns included): the same factorisation as the
+    one-reflector mode up to rounding, Q orthogonal and QR = A."""
+    _say("qr panel groups %d x %d" % (m, n))
+    A = wl.random_matrix(m, n, seed=3 * m + n, decay=3.0)
+    if rankdef:
+        A[:, 5] = 0.0
+        A[:, 20] = A[:, 19]
+    R1, Q1 = B.qr(A, tall_apply=1)
+    R0, Q0 = B.qr(A, tall_apply=0)
+    R1, Q1, R0, Q0 = (x.cpu().numpy() for x in (R1, Q1, R0, Q0))
+    k = min(m, n)
+    scale = np.abs(A).max()
+    assert np.abs(Q1.T @ Q1 - np.eye(k)).max() < 1e-13 * np.sqrt(m)
+    assert np.abs(Q1 @ R1 - A).max() < 1e-13 * scale * np.sqrt(m)
+    assert np.allclose(np.tril(R1, -1), 0)
+    # the same reflectors (LAPACK signs) in both modes: R and Q agree to
+    # rounding while the columns are independent (a duplicated column's
+    # reflector is built from rounding noise, so rows from it on differ)
+    lead = 20 if rankdef else k
+    assert np.abs(R1[:lead] - R0[:lead]).max() < 1e-11 * scale * np.sqrt(m)
+    assert np.abs(Q1[:, :lead] - Q0[:, :lead]).max() < 1e-10
+
+
 @pytest.mark.parametrize("m,c,cap,tol,decay", [
     (2, 2, 0, 0.0, 0), (10, 4, 0, 0.0, 0), (4, 10, 0, 0.0, 0), (64, 64, 0, 0.0, 6),
     (96, 96, 40, 0.0, 8), (128, 128, 64, 0.0, 8), (500, 128, 64, 0.0, 12),
