@@ -39,19 +39,19 @@ inline int grid_for(long n) {
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < (n);      \
        e += (long)gridDim.x * blockDim.x)
 
+// out[j][i][k] = in[i][j][k]: block row y is the pair t = j d0 + i, the
+// inner index runs along x (coalesced on both sides)
 __global__ void swap01_kernel(const double* in, int d0, int d1, long inner,
                               double* out, InstOff io) {
   const long o_ = io.of(blockIdx.z);
   in = shifted(in, o_);
   out = shifted(out, o_);
-  const long n = (long)d0 * d1 * inner;
-  GRID_STRIDE(e, n) {
-    long k = e % inner;
-    long t = e / inner;
-    long i = t % d0;   // out index order: [j][i][k]
-    long j = t / d0;
-    out[e] = in[(i * d1 + j) * inner + k];
-  }
+  const int t = blockIdx.y, i = t % d0, j = t / d0;
+  const double* src = in + ((long)i * d1 + j) * inner;
+  double* dst = out + (long)t * inner;
+  for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < inner;
+       k += (long)gridDim.x * blockDim.x)
+    dst[k] = src[k];
 }
 
 __global__ void copy2d_kernel(int rows, int cols, double alpha,
@@ -308,7 +308,9 @@ void swap01(hipStream_t s, const double* in, int d0, int d1, long inner,
             double* out) {
   long n = (long)d0 * d1 * inner;
   if (n <= 0) return;
-  hipLaunchKernelGGL(swap01_kernel, dim3(grid_for(n), 1, inst_count()), dim3(256), 0, s, in, d0,
+  MPSV_CHECK((long)d0 * d1 <= 65535, kEinval, "swap01: too many index pairs");
+  const int gx = std::min(64, ceil_div(inner, 256));
+  hipLaunchKernelGGL(swap01_kernel, dim3(gx, d0 * d1, inst_count()), dim3(256), 0, s, in, d0,
                      d1, inner, out, inst_off());
   MPSV_LAUNCHED();
 }

@@ -986,7 +986,9 @@ __global__ __launch_bounds__(WY_T) void qr_wy_apply_kernel(
       const int e = tid + it * WY_T;
       const int j = e / WY_RC, r = e % WY_RC;
       const int i = i0 + r;
-      v[it] = (j < k && i < m) ? V[(long)j * m + i] : 0.0;
+      const bool ok = j < k && i < m;
+      const double x = V[ok ? (long)j * m + i : 0];
+      v[it] = ok ? x : 0.0;
     }
 #pragma unroll
     for (int it = 0; it < WY_RC * 16 / WY_T; ++it) {
@@ -1007,7 +1009,9 @@ __global__ __launch_bounds__(WY_T) void qr_wy_apply_kernel(
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const int i = i0 + r32 + 4 * q + lk;
-        bb[q] = (colok && i < rows_in) ? Yin.p[(long)i * Yin.rs + (long)col * Yin.cs] : 0.0;
+        const bool ok = colok && i < rows_in;
+        const double y = Yin.p[ok ? (long)i * Yin.rs + (long)col * Yin.cs : 0];
+        bb[q] = ok ? y : 0.0;
       }
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
@@ -1072,7 +1076,9 @@ __global__ __launch_bounds__(WY_T) void qr_wy_apply_kernel(
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int i = i0 + r32 + 16 * tt + 4 * r + lk;
-          yy[tt][r] = (colok && i < rows_in) ? Yin.p[(long)i * Yin.rs + (long)col * Yin.cs] : 0.0;
+          const bool ok = colok && i < rows_in;
+          const double y = Yin.p[ok ? (long)i * Yin.rs + (long)col * Yin.cs : 0];
+          yy[tt][r] = ok ? y : 0.0;
         }
 #pragma unroll
       for (int tt = 0; tt < 2; ++tt) {
@@ -1513,6 +1519,8 @@ void qr_reg_apply(hipStream_t s, const double* V, const double* tau, int m,
   const int rpl = rows_per_lane(m);
   const int tr = trans ? 1 : 0;
   if (wy_shape(m, k, p)) {
+    // (the kernel's out-of-range lanes load element (0, 0) of Yin)
+    MPSV_CHECK(rows_in >= 1, kEinval, "qr_reg_apply: no input rows");
     const int slot = prof_begin(s);
     launch_wy(s, V, tau, m, k, Yin, rows_in, Yout, p, tr, Chunks{m, k}, 1);
     // algorithmic bytes: Y read twice and written once, the reflectors
