@@ -809,8 +809,12 @@ int svd_truncate(hipStream_t s, Arena& ws, double* X, int m, int c, long ldx,
     // fixed rank: the kernels keep min(cap, k) whatever the values
     D = cap < k ? cap : k;
   } else {
-    double h[SvdOutcomes::kInfoWords];
-    MPSV_HIP(hipMemcpyAsync(h, shifted(info, lanes().first), sizeof(h),
+    // the rank read-back: into the lane's page-locked words when there is
+    // a lane record
+    double hs[SvdOutcomes::kInfoWords];
+    double* h = out ? out->host_words(SvdOutcomes::kInfoWords) : hs;
+    MPSV_HIP(hipMemcpyAsync(h, shifted(info, lanes().first),
+                            SvdOutcomes::kInfoWords * sizeof(double),
                             hipMemcpyDeviceToHost, s));
     MPSV_HIP(hipStreamSynchronize(s));
     D = (int)h[0];

@@ -112,6 +112,8 @@ class SvdOutcomes {
   };
   Record take();
   void resume(const Record& r);
+  // page-locked host words for a read-back on this lane (shared with end())
+  double* host_words(size_t n) { return (double*)host_.get(n * sizeof(double)); }
 
  private:
   double* ring_ = nullptr;

@@ -1145,19 +1145,23 @@ __device__ inline void group_store(double* Vs, const double (&v)[16], int tid) {
   for (int it = 0; it < 16; ++it) Vs[(16 * (it >> 2) + rl) * P + 16 * (it & 3) + jj] = v[it];
 }
 
-// T of one group (one workgroup per instance): the Gram matrix V^T V on
-// the matrix cores (its upper block triangle, each wave taking 16 rows of
-// every staged chunk, the four partial sums added through LDS), then the
-// recurrence T_jj = tau_j, T_{<j,j} = -tau_j T_{<j,<j} (V_{<j}^T v_j), one
-// lane per row of T (a lane reads only its own row, so the lanes do not
-// wait on each other).  T is written whole (64 x 64, row-major, zeros
-// below the diagonal and past k).  The next chunk's reflector rows are in
-// flight while the current chunk is multiplied.
+// T of one group (one workgroup per instance).  The Gram matrix G = V^T V
+// on the matrix cores: its ten blocks of the upper block triangle, each
+// wave taking 16 rows of every staged chunk (two chunks of reflector rows
+// in flight), the four partial sums added through LDS.  Then T by blocks
+// of 16: the diagonal blocks T_bb by the recurrence T_jj = tau_j,
+// T_{<j,j} = -tau_j T_{<j,<j} (V_{<j}^T v_j) within the block (one wave
+// per block, one lane per row; a lane reads only its own row), and block
+// column J from the ones before it, T_{<J,J} = -T_{<J,<J} G_{<J,J} T_JJ
+// (the product of the first J blocks' reflectors with block J's), on the
+// matrix cores.  T is written whole (64 x 64, row-major, zeros below the
+// diagonal and past k).
 __global__ __launch_bounds__(WG_T) void qr_wy_group_t_kernel(
     const double* __restrict__ V, const double* __restrict__ tau, int m, int k,
     double* __restrict__ T, InstOff io) {
-  __shared__ double Vs[WG_RC * WG_P1];
+  __shared__ double Vs[WG_RC * WG_P1];  // staged reflector rows, later T (pitch 65)
   __shared__ double Gs[64 * 65];
+  __shared__ double Ys[4][16 * 17];
   {
     const long o_ = io.of(blockIdx.z);
     V = shifted(V, o_);
@@ -1171,25 +1175,36 @@ __global__ __launch_bounds__(WG_T) void qr_wy_group_t_kernel(
   dbl4 acc[10];
 #pragma unroll
   for (int x = 0; x < 10; ++x) acc[x] = dbl4{0.0, 0.0, 0.0, 0.0};
-  double vn[16];
-  group_load(vn, V, m, k, 0, tid);
-  for (int i0 = 0; i0 < m; i0 += WG_RC) {
-    __syncthreads();
-    group_store<WG_P1>(Vs, vn, tid);
-    __syncthreads();
-    if (i0 + WG_RC < m) group_load(vn, V, m, k, i0 + WG_RC, tid);
+  auto gram_chunk = [&]() {
 #pragma unroll
     for (int q4 = 0; q4 < 4; ++q4) {
       const double* row = Vs + (16 * w + 4 * q4 + lk) * WG_P1 + lr;
       double a[4];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) a[b] = row[16 * b];
+      for (int bb = 0; bb < 4; ++bb) a[bb] = row[16 * bb];
       int x = 0;
 #pragma unroll
       for (int a0 = 0; a0 < 4; ++a0)
 #pragma unroll
-        for (int b = a0; b < 4; ++b, ++x)
-          acc[x] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[a0], a[b], acc[x], 0, 0, 0);
+        for (int bb = a0; bb < 4; ++bb, ++x)
+          acc[x] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[a0], a[bb], acc[x], 0, 0, 0);
+    }
+  };
+  double va[16], vb[16];
+  group_load(va, V, m, k, 0, tid);
+  if (WG_RC < m) group_load(vb, V, m, k, WG_RC, tid);
+  for (int i0 = 0; i0 < m; i0 += 2 * WG_RC) {
+    __syncthreads();
+    group_store<WG_P1>(Vs, va, tid);
+    __syncthreads();
+    if (i0 + 2 * WG_RC < m) group_load(va, V, m, k, i0 + 2 * WG_RC, tid);
+    gram_chunk();
+    if (i0 + WG_RC < m) {
+      __syncthreads();
+      group_store<WG_P1>(Vs, vb, tid);
+      __syncthreads();
+      if (i0 + 3 * WG_RC < m) group_load(vb, V, m, k, i0 + 3 * WG_RC, tid);
+      gram_chunk();
     }
   }
   // D layout: item r of lane (lk, lr) is row 4 r + lk, column lr of a
@@ -1200,37 +1215,68 @@ __global__ __launch_bounds__(WG_T) void qr_wy_group_t_kernel(
 #pragma unroll
       for (int a0 = 0; a0 < 4; ++a0)
 #pragma unroll
-        for (int b = a0; b < 4; ++b, ++x)
+        for (int bb = a0; bb < 4; ++bb, ++x)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              double* g = &Gs[(16 * a0 + 4 * r + lk) * 65 + 16 * b + lr];
-              *g = (ww == 0 ? 0.0 : *g) + acc[x][r];
-            }
+          for (int r = 0; r < 4; ++r) {
+            double* g = &Gs[(16 * a0 + 4 * r + lk) * 65 + 16 * bb + lr];
+            *g = (ww == 0 ? 0.0 : *g) + acc[x][r];
+          }
     }
     __syncthreads();
   }
-  if (w == 0) {
-    double* Ts = Vs;  // pitch 65
-    const int row = l;
-    for (int c = 0; c < 64; ++c) {
-      const double tc = (c < k) ? tau[c] : 0.0;
+  double* Ts = Vs;  // pitch 65
+  for (int e = tid; e < 64 * 64; e += WG_T) Ts[(e >> 6) * 65 + (e & 63)] = 0.0;
+  __syncthreads();
+  // diagonal blocks: wave w takes block w, lane lr its row
+  if (lk == 0) {
+    const int b0 = 16 * w, row = b0 + lr;
+    for (int c = 0; c < 16; ++c) {
+      const int j = b0 + c;
+      const double tc = (j < k) ? tau[j] : 0.0;
       double v = 0.0;
-      if (row == c) {
+      if (lr == c) {
         v = tc;
-      } else if (row < c && c < k) {
+      } else if (lr < c && j < k) {
         double a0 = 0.0, a1 = 0.0;
         int q = row;
-        for (; q + 1 < c; q += 2) {
-          a0 = fma(Ts[row * 65 + q], Gs[q * 65 + c], a0);
-          a1 = fma(Ts[row * 65 + q + 1], Gs[(q + 1) * 65 + c], a1);
+        for (; q + 1 < j; q += 2) {
+          a0 = fma(Ts[row * 65 + q], Gs[q * 65 + j], a0);
+          a1 = fma(Ts[row * 65 + q + 1], Gs[(q + 1) * 65 + j], a1);
         }
-        if (q < c) a0 = fma(Ts[row * 65 + q], Gs[q * 65 + c], a0);
+        if (q < j) a0 = fma(Ts[row * 65 + q], Gs[q * 65 + j], a0);
         v = -tc * (a0 + a1);
       }
-      Ts[row * 65 + c] = v;
+      Ts[row * 65 + j] = v;
     }
-    for (int c = 0; c < 64; ++c) T[(long)row * 64 + c] = Ts[row * 65 + c];
   }
+  __syncthreads();
+  // block columns: wave i < J forms T_iJ = -(sum_{l=i}^{J-1} T_il G_lJ) T_JJ
+  for (int J = 1; J < 4; ++J) {
+    if (w < J) {
+      dbl4 y = {0.0, 0.0, 0.0, 0.0};
+      for (int lb = w; lb < J; ++lb)
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4)
+          y = __builtin_amdgcn_mfma_f64_16x16x4f64(
+              Ts[(16 * w + lr) * 65 + 16 * lb + 4 * s4 + lk],
+              Gs[(16 * lb + 4 * s4 + lk) * 65 + 16 * J + lr], y, 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Ys[w][(4 * r + lk) * 17 + lr] = y[r];
+    }
+    __syncthreads();
+    if (w < J) {
+      dbl4 t = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4)
+        t = __builtin_amdgcn_mfma_f64_16x16x4f64(
+            Ys[w][lr * 17 + 4 * s4 + lk], Ts[(16 * J + 4 * s4 + lk) * 65 + 16 * J + lr], t, 0,
+            0, 0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Ts[(16 * w + 4 * r + lk) * 65 + 16 * J + lr] = -t[r];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < 64 * 64; e += WG_T) T[e] = Ts[(e >> 6) * 65 + (e & 63)];
 }
 
 // Yout <- Q_g^T Yin (trans) or Q_g Yin = Yin - V T' (V^T Yin), T' = T^T or
