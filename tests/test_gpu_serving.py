@@ -108,7 +108,7 @@ def test_serving_rejects_request_above_budget(S):
                                   "two_stream_10_chi64_fp32", "two_stream_12_chi64_df4_C5",
                                   "collisions_10_chi64_C5", "collisions_fixed_9_chi32_seq",
                                   "centre_first_10_chi64", "ig_8_chi32",
-                                  "two_stream_14_chi128_df4_C5"])
+                                  "two_stream_14_chi128_df4_C5", "two_stream_10_chi64_C5_wy"])
 def test_device_bytes_within_workspace_bound(S, case):
     """The admission bound covers what a state holds after steps from a
     state with every bond at chi_max (random perturbation, no tolerance
@@ -134,6 +134,10 @@ def test_device_bytes_within_workspace_bound(S, case):
         w = wl.two_stream(L=8, chi=32, tol=0.0, level=5, df_max=4, order=4)
     elif case == "two_stream_14_chi128_df4_C5":
         w = wl.two_stream(L=14, chi=128, tol=0.0, level=5, df_max=4)
+    elif case == "two_stream_10_chi64_C5_wy":
+        # compact-WY mode: the panel groups keep a T beside their reflectors
+        w = wl.two_stream(L=10, chi=64, tol=0.0, level=5, df_max=4)
+        w.problem.tall_apply = 1
     elif case.startswith("two_stream_10"):
         w = wl.two_stream(L=10, chi=64, tol=0.0, level=5)
         if case.endswith("fp32"):
