@@ -697,6 +697,11 @@ def main():
     ap.add_argument("--batched-only", action="store_true",
                     help="only time the lock-step batch of --batch instances of the metric's "
                          "workload (for profiling)")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="only run the serving workload: --serving-requests of its seeded "
+                         "arrivals, --serving-steps steps each")
+    ap.add_argument("--serving-requests", type=int, default=40)
+    ap.add_argument("--serving-steps", type=int, default=20)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (calibrates "
                          "the FETCH_SIZE / WRITE_SIZE counters)")
@@ -739,6 +744,10 @@ def main():
 
     if args.batched_only:
         print(json.dumps(batched_metric(binding, args.batch, args.steps, None, smaller=())))
+        return
+
+    if args.serving_only:
+        print(json.dumps(serving_run(binding, args.serving_requests, args.serving_steps)))
         return
 
     w = make_workload(args.mode)
@@ -801,7 +810,7 @@ def main():
         print("[bench] buneman %s" % json.dumps(extras["buneman"]), file=sys.stderr, flush=True)
         extras["orderings"] = orderings(binding, 3)
         print("[bench] orderings %s" % json.dumps(extras["orderings"]), file=sys.stderr, flush=True)
-        extras["serving"] = serving_run(binding, 40, 20)
+        extras["serving"] = serving_run(binding, args.serving_requests, args.serving_steps)
         print("[bench] serving %s" % json.dumps(extras["serving"]), file=sys.stderr, flush=True)
 
     out = {
