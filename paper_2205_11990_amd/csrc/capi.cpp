@@ -463,15 +463,15 @@ mps_status mpsb_qr_tall(int32_t m, int32_t n, double* A, double* Q,
     mpsv::qr_factor(stream, ws, A, m, n, n, f);
     if (Q) {
       const int k = std::min(m, n);
-      // Q = H_0 ... H_{k-1} [I_k; 0]
-      double* E = ws.alloc((size_t)m * k);
-      std::vector<double> h((size_t)m * k, 0.0);
+      // Q = H_0 ... H_{k-1} [I_k; 0], the identity read through a view
+      // (rows past k enter as zeros), as the compression sweeps apply Q
+      double* E = ws.alloc((size_t)k * k);
+      std::vector<double> h((size_t)k * k, 0.0);
       for (int i = 0; i < k; ++i) h[(size_t)i * k + i] = 1.0;
       MPSV_HIP(hipMemcpy(E, h.data(), h.size() * sizeof(double),
                          hipMemcpyHostToDevice));
-      mpsv::qr_apply_q(stream, ws, f, E, k, k);
-      MPSV_HIP(hipMemcpyAsync(Q, E, h.size() * sizeof(double),
-                              hipMemcpyDeviceToDevice, stream));
+      mpsv::qr_apply_q_view(stream, ws, f, mpsv::CMatView{E, k, 1, 0}, k,
+                            mpsv::MatView{Q, k, 1, 0}, k);
     }
     MPSV_HIP(hipStreamSynchronize(stream));
   });
