@@ -21,6 +21,65 @@ namespace {
 
 constexpr int BM = 64, BN = 64, BK = 16, NT = 256;
 
+// Products with few rows and a short contraction, FP64: the MPO factor W
+// (at most 48 x 48, shared by every batch entry) times many blocks.  They
+// are bound by streaming B and C, and the 64 x 64 tiles of the matrix-core
+// kernel would stay mostly empty.  One thread per column of one batch
+// entry keeps the MM sums in registers and reads W from LDS (every lane the
+// same word); loads of B and stores of C run along the columns.  Each
+// output sums its K products in order, k = 0 .. K-1, whatever the instance
+// count.
+constexpr int SM_MAX = 48;
+template <int MM>
+__global__ __launch_bounds__(NT) void gemm_small_kernel(
+    int M, int N, int K, double alpha, const double* __restrict__ A, long ars, long acs,
+    const double* __restrict__ B, long brs, long bcs, long bbs, double beta,
+    double* __restrict__ C, long crs, long ccs, long cbs, int nb, InstOff io) {
+  __shared__ double Ws[MM * SM_MAX];
+  {
+    const long o_ = io.of(blockIdx.z);
+    A = shifted(A, o_);
+    B = shifted(B, o_);
+    C = shifted(C, o_);
+  }
+  for (int e = threadIdx.x; e < MM * K; e += NT) {
+    const int m = e / K, k = e - m * K;
+    Ws[m * SM_MAX + k] = (m < M) ? A[(long)m * ars + (long)k * acs] : 0.0;
+  }
+  __syncthreads();
+  const long t = (long)blockIdx.x * NT + threadIdx.x;
+  if (t >= (long)nb * N) return;
+  const int b = (int)(t / N), n = (int)(t - (long)b * N);
+  const double* bp = B + (long)b * bbs + (long)n * bcs;
+  double* cp = C + (long)b * cbs + (long)n * ccs;
+  double acc[MM];
+#pragma unroll
+  for (int m = 0; m < MM; ++m) acc[m] = 0.0;
+  // eight loads of B in flight before their products (a state alone has
+  // too few waves to hide one load per step)
+  int k = 0;
+  for (; k + 8 <= K; k += 8) {
+    double z[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) z[u] = bp[(long)(k + u) * brs];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int m = 0; m < MM; ++m) acc[m] = fma(Ws[m * SM_MAX + k + u], z[u], acc[m]);
+  }
+  for (; k < K; ++k) {
+    const double z = bp[(long)k * brs];
+#pragma unroll
+    for (int m = 0; m < MM; ++m) acc[m] = fma(Ws[m * SM_MAX + k], z, acc[m]);
+  }
+#pragma unroll
+  for (int m = 0; m < MM; ++m)
+    if (m < M) {
+      double* o = cp + (long)m * crs;
+      *o = (beta == 0.0) ? alpha * acc[m] : fma(beta, *o, alpha * acc[m]);
+    }
+}
+
 // blockIdx.z = batch * nsplit + split; split covers K range
 // [split*kchunk, min(K, (split+1)*kchunk)).
 __global__ __launch_bounds__(NT) void gemm_f64_kernel(
@@ -393,6 +452,24 @@ void gemm(hipStream_t s, int M, int N, int K, double alpha, CMatView A,
   const int a_kfast = (A.cs == 1) ? 1 : 0;
   const int b_nfast = (B.cs == 1) ? 1 : 0;
   const int ninst = inst_count();
+  if (prec == 0 && M <= SM_MAX && K <= SM_MAX && A.bs == 0 && (long)batch * N >= 4 * NT) {
+    // a small shared factor times many columns: the streaming kernel
+    const int slot = prof_begin(s);
+    const long cols = (long)batch * N;
+    const dim3 grid(ceil_div(cols, NT), 1, ninst);
+    if (M <= 16)
+      hipLaunchKernelGGL(gemm_small_kernel<16>, grid, dim3(NT), 0, s, M, N, K, alpha, A.p, A.rs,
+                         A.cs, B.p, B.rs, B.cs, B.bs, beta, C.p, C.rs, C.cs, C.bs, batch,
+                         inst_off());
+    else
+      hipLaunchKernelGGL(gemm_small_kernel<SM_MAX>, grid, dim3(NT), 0, s, M, N, K, alpha, A.p,
+                         A.rs, A.cs, B.p, B.rs, B.cs, B.bs, beta, C.p, C.rs, C.cs, C.bs, batch,
+                         inst_off());
+    MPSV_LAUNCHED();
+    prof_end(s, slot, kClsGemm, 2.0 * M * N * (double)K * batch,
+             8.0 * ((double)M * K + ((double)K * N + 2.0 * M * N) * batch));
+    return;
+  }
   // split K when the output alone (in 64 x 64 tiles) cannot fill the chip;
   // the partial products live in the caller's workspace (none given: no
   // split).  The choice ignores lock-step instances, so that every instance

@@ -68,6 +68,31 @@ def test_gemm_strided_matches_numpy(B, M, N, K, batch, at, bt):
     assert np.abs(out - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max()) * np.sqrt(K)
 
 
+@pytest.mark.parametrize("M,N,K,batch,bt,beta", [
+    (12, 64, 12, 384, False, 0.0), (40, 512, 40, 64, False, -1.3), (40, 64, 40, 512, True, 0.5),
+    (33, 100, 7, 50, False, 2.0), (16, 1030, 48, 1, False, 0.0), (48, 64, 1, 40, True, -1.0),
+    (1, 2000, 5, 3, False, 0.25)])
+def test_gemm_small_shared_factor_matches_numpy(B, M, N, K, batch, bt, beta):
+    """A small factor (at most 48 x 48) shared by every batch entry (A's
+    batch stride 0) times many columns, as the MPO applications multiply:
+    the streaming kernel, against numpy, with B read transposed through its
+    strides and beta applied to C."""
+    import torch
+    _say("gemm small shared %d %d %d batch %d bt=%d" % (M, N, K, batch, bt))
+    rng = np.random.default_rng(M * 7 + N + K + batch)
+    A = rng.standard_normal((M, K))
+    Bm = rng.standard_normal((batch, K, N))
+    C0 = rng.standard_normal((batch, M, N))
+    Ad = torch.from_numpy(A.copy()).cuda()
+    Bd = torch.from_numpy(np.ascontiguousarray(Bm.transpose(0, 2, 1) if bt else Bm)).cuda()
+    Cd = torch.from_numpy(C0.copy()).cuda()
+    b_str = (1, K, K * N) if bt else (N, 1, K * N)
+    out = B.gemm_strided(M, N, K, 0.7, Ad, (K, 1, 0), Bd, b_str, beta, Cd, (N, 1, M * N),
+                         batch=batch).cpu().numpy()
+    ref = 0.7 * np.einsum("ik,bkj->bij", A, Bm) + beta * C0
+    assert np.abs(out - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max()) * np.sqrt(K)
+
+
 @pytest.mark.parametrize("M,N,K", [(1, 1, 1), (7, 5, 3), (64, 64, 16), (65, 130, 33),
                                    (300, 17, 129), (16, 1000, 2)])
 def test_gemm_fp32_contract_matches_fp32_rounded_product(B, M, N, K):
