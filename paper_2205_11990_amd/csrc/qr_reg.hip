@@ -1281,8 +1281,9 @@ __global__ __launch_bounds__(WG_T) void qr_wy_group_t_kernel(
 
 // Yout <- Q_g^T Yin (trans) or Q_g Yin = Yin - V T' (V^T Yin), T' = T^T or
 // T.  A workgroup of four waves owns 64 columns (16 per wave) and streams
-// the rows twice, 64 at a time, the reflectors staged through LDS in the
-// layout each pass reads without bank conflicts; the next chunk's rows of
+// the rows twice, 64 at a time, the reflectors staged through LDS with a
+// row pitch chosen for each pass's reads (two lanes per bank pair, the
+// least 64 lanes of doubles allow); the next chunk's rows of
 // Y and of the reflectors are loaded while the current chunk is on the
 // matrix cores.  Pass 1 accumulates W = V^T Y (64 x 16 per wave, four
 // 16 x 16 blocks); T' W comes from T staged through LDS with the blocks of
