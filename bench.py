@@ -547,6 +547,19 @@ def batched_metric(binding, count, steps, single_steps_per_s, smaller=(64, 128))
     scaling[str(count)] = round(agg, 2)
     roof = _class_rates(binding, lambda: bt.step(1), 1)
     roof["workgroups_per_launch_jacobi"] = count
+    # the same batched steps replayed from a captured graph (an ordinary
+    # step from the layout, the capture, then the timed replays)
+    import torch
+    bt.step_graph(True)
+    bt.step(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bt.step(steps)
+    torch.cuda.synchronize()
+    gsec = (time.perf_counter() - t0) / steps
+    caps, reps = bt.step_graph()
+    graph = {"ms_per_batched_step": 1000.0 * gsec, "aggregate_steps_per_s": count / gsec,
+             "speedup_vs_eager": sec / gsec, "captures": caps, "replays": reps}
     out = {"workload": "%d lock-step instances of two-stream 2^10 x 2^10, interleaved, chi=64, "
                        "C5, tol=0, D_F=4 (amplitudes 1e-3 (1 + i/10), seeded perturbations), "
                        "compact-WY reflector application on tall blocks" % count,
@@ -554,7 +567,7 @@ def batched_metric(binding, count, steps, single_steps_per_s, smaller=(64, 128))
            "aggregate_steps_per_s": agg,
            "speedup_vs_single_instance": agg / single_steps_per_s if single_steps_per_s else None,
            "aggregate_steps_per_s_by_instances": scaling,
-           "device_bytes": bt.instance(0).device_bytes(), "roofline": roof}
+           "device_bytes": bt.instance(0).device_bytes(), "roofline": roof, "graph": graph}
     bt.free()
     return out
 

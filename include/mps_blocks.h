@@ -113,6 +113,15 @@ mps_status mpsb_compress(int32_t n, const int32_t* mpo_bonds,
 mps_status mpsb_step_graph(mps_state* h, int32_t enable, int64_t* captures,
                            int64_t* replays);
 
+/* mpsb_step_graph for a lock-step batch (mps_batch_*): the recording holds
+ * the launches of a step of every instance (each launch covers them all)
+ * and is replayed by later mps_batch_step calls while the layout of the
+ * instances' states is unchanged; the same conditions (tol = 0, fixed dt,
+ * timing off) and the same results, bit for bit, as the batch's ordinary
+ * steps.  MPS_EINVAL for a NULL batch. */
+mps_status mpsb_batch_step_graph(mps_batch* b, int32_t enable, int64_t* captures,
+                                 int64_t* replays);
+
 /* Centre-first compression (SI, "Modified Compression Scheme") of an MPS
  * cut at the bond between sites centre-1 and centre (1 <= centre <= n-1):
  * the cut is truncated first from the mixed canonical form around it, then

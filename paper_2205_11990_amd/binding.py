@@ -87,6 +87,8 @@ _SIGS = {
     "mps_batch_instance": [_P, _I32],
     "mps_batch_free": [_P],
     "mpsb_step_graph": [_P, _I32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
+    "mpsb_batch_step_graph": [_P, _I32, ctypes.POINTER(ctypes.c_int64),
+                              ctypes.POINTER(ctypes.c_int64)],
     "mpsb_compress_centre": [_I32, _I32, _PI32, _P, _I32, _D, _PI32, _P, _I64, _PD, _P],
     "mpsb_add_compress": [_I32, _I32, _PD, _PI32, ctypes.POINTER(_P), _I32, _D,
                           _PI32, _P, _I64, _P],
@@ -372,6 +374,14 @@ class Batch:
         al = (ctypes.c_double * len(alphas))(*[float(a) for a in alphas])
         _check(lib().mps_batch_add_scaled(self._h, al, b.ctypes.data_as(_PI32),
                                           ctypes.cast(ptrs, _P), _stream(stream)))
+
+    def step_graph(self, enable=None):
+        """Turn captured step graphs of the batch on/off (None: unchanged);
+        returns (captures, replays)."""
+        c, r = ctypes.c_int64(), ctypes.c_int64()
+        e = -1 if enable is None else int(bool(enable))
+        _check(lib().mpsb_batch_step_graph(self._h, e, ctypes.byref(c), ctypes.byref(r)))
+        return c.value, r.value
 
     def instance(self, i: int) -> "MpsState":
         """Instance i as a state owned by the batch (read-only: dense

@@ -848,6 +848,16 @@ mps_status mps_batch_step(mps_batch* b, int32_t nsteps, hipStream_t stream) {
   });
 }
 
+mps_status mpsb_batch_step_graph(mps_batch* b, int32_t enable, int64_t* captures,
+                                 int64_t* replays) {
+  return guarded([&] {
+    mpsv::Engine& e = batch_engine(b);
+    if (enable >= 0) e.set_step_graph(enable != 0);
+    if (captures) *captures = e.graph_captures();
+    if (replays) *replays = e.graph_replays();
+  });
+}
+
 mps_state* mps_batch_instance(mps_batch* b, int32_t i) {
   if (!b || i < 0 || i >= (int32_t)b->views.size()) return nullptr;
   return b->views[(size_t)i];

@@ -114,6 +114,39 @@ def test_wy_reflectors_batch_equals_solo_and_oracle(B):
     bt.free()
 
 
+@pytest.mark.parametrize("L,chi,tall", [(6, 16, 0), (9, 16, 1)])
+def test_batch_step_graph_replays_equal_eager_steps(B, L, chi, tall):
+    """A lock-step batch (three instances) stepped from a captured graph: after
+    each of five steps, with moments read in between, every instance's
+    cores equal those of the same batch stepped launch by launch, bit for
+    bit (the one-reflector mode, and the compact-WY mode with panel groups
+    of 640-row blocks).  The first step runs eagerly, the second captures,
+    the rest replay."""
+    _say("batch step graph L=%d chi=%d tall_apply=%d" % (L, chi, tall))
+    ws = _sweep(3, L=L, chi=chi)
+    for w in ws:
+        w.problem.tall_apply = tall
+    starts = [S.oracle_start(w, pert_chi=chi, amp=1e-3, seed=90 + i) for i, w in enumerate(ws)]
+    a = B.Batch([w.problem for w in ws], [(w.ax, w.bv) for w in ws])
+    b = B.Batch([w.problem for w in ws], [(w.ax, w.bv) for w in ws])
+    a.set_cores(starts)
+    b.set_cores(starts)
+    a.step_graph(True)
+    for k in range(5):
+        a.step(1)
+        b.step(1)
+        for i in range(3):
+            ca, cb = a.instance(i).get_cores_host(), b.instance(i).get_cores_host()
+            assert [x.shape for x in ca] == [x.shape for x in cb], (k, i)
+            for x, y in zip(ca, cb):
+                assert np.array_equal(x, y), (k, i)
+        a.instance(k % 3).moments()
+    assert a.step_graph() == (1, 4)
+    assert b.step_graph() == (0, 0)
+    a.free()
+    b.free()
+
+
 def test_batch_matches_mps_oracle(B):
     """Three instances, C5, chi = 8: each instance's f and E within 1e-8 of
     the CPU MPS oracle after two steps from the same state, same bonds."""
