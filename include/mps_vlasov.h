@@ -100,7 +100,7 @@ typedef enum { MPS_X_CENTRAL = 0, MPS_X_UPWIND = 1 } mps_x_scheme;
  * the largest, an exact zero of a rank-deficient cut, gets 0).  The result
  * is not in canonical form.  The field and the entanglement diagnostic
  * keep the sweep.  The centre-first scheme also holds the untruncated right
- * half in its workspace, which mps_workspace_bound does not model. */
+ * half in its workspace (mps_workspace_bound adds an allowance for it). */
 typedef enum {
   MPS_COMPRESS_SWEEP = 0,
   MPS_COMPRESS_CENTRE_FIRST = 1
@@ -253,10 +253,13 @@ mps_status mps_add_scaled(mps_state* h, double alpha, const int32_t* bond_dims,
  * arena, from the chi-capped state, the widest contraction of the field
  * term and the interleaved initial state at full rank, with coefficients
  * that envelope measured peaks (grids 2^6..2^13, chi 16..128, both
- * orderings), plus chunk rounding and a fixed allowance; it assumes every
- * compression point stays within chi_max (level 5, or lower levels whose
- * tolerance keeps the bonds there).  EINVAL for every problem that mps_init
- * rejects on its parameters (the same checks). */
+ * orderings), plus chunk rounding and a fixed allowance; the collision
+ * terms, the IG ordering, the centre-first scheme and the compact-WY mode's
+ * panel groups are included.  It assumes every compression point stays
+ * within chi_max (level 5, or lower levels whose tolerance keeps the bonds
+ * there).  A plasma of several species holds one such state per species;
+ * a lock-step batch about one per instance.  EINVAL for every problem that
+ * mps_init rejects on its parameters (the same checks). */
 mps_status mps_workspace_bound(const mps_problem* p, size_t* bytes);
 
 /* Device bytes the state h holds right now (all of its arenas: operators,
