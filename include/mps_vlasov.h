@@ -257,9 +257,12 @@ mps_status mps_add_scaled(mps_state* h, double alpha, const int32_t* bond_dims,
  * terms, the IG ordering, the centre-first scheme and the compact-WY mode's
  * panel groups are included.  It assumes every compression point stays
  * within chi_max (level 5, or lower levels whose tolerance keeps the bonds
- * there).  A plasma of several species holds one such state per species;
- * a lock-step batch about one per instance.  EINVAL for every problem that
- * mps_init rejects on its parameters (the same checks). */
+ * there).  A plasma of several species holds one such state per species.
+ * A lock-step batch rounds its arena chunks for all instances at once and
+ * may exceed the sum of its instances' bounds by a little (512 against 508
+ * MiB per instance for 256 instances at 2^10 x 2^10, chi = 64); allow a
+ * few percent more.  EINVAL for every problem that mps_init rejects on its
+ * parameters (the same checks). */
 mps_status mps_workspace_bound(const mps_problem* p, size_t* bytes);
 
 /* Device bytes the state h holds right now (all of its arenas: operators,
