@@ -508,8 +508,10 @@ def graph_run(binding, w, cores, steps, eager_steps_per_s):
             "captures": caps, "replays": reps}
 
 
-def _metric_batch(binding, count, tall_apply=1):
+def _metric_batch(binding, count, tall_apply=1, precision=0):
     ws = metric_sweep(count, tall_apply)
+    for w in ws:
+        w.problem.precision = precision
     p = ws[0].problem
     bt = binding.Batch([w.problem for w in ws], [(w.ax, w.bv) for w in ws])
     perts = [wl.random_mps_cores(p.n_sites, p.chi_max, seed=2205 + i) for i in range(count)]
@@ -529,7 +531,7 @@ def _batch_rate(binding, bt, count, steps):
     return count * steps / el, el / steps
 
 
-def batched_metric(binding, count, steps, single_steps_per_s, smaller=(64, 128)):
+def batched_metric(binding, count, steps, single_steps_per_s, smaller=(64, 128), extras=True):
     """The metric's workload as a lock-step batch of `count` instances: every
     kernel launch covers all of them.  Aggregate steps/s (count x steps over
     the timed window) against the single instance's, the rate of the
@@ -547,9 +549,18 @@ def batched_metric(binding, count, steps, single_steps_per_s, smaller=(64, 128))
     scaling[str(count)] = round(agg, 2)
     roof = _class_rates(binding, lambda: bt.step(1), 1)
     roof["workgroups_per_launch_jacobi"] = count
+    import torch
+    dev_bytes = bt.instance(0).device_bytes()
+    if not extras:
+        bt.free()
+        return {"workload": "%d lock-step instances of two-stream 2^10 x 2^10, interleaved, "
+                            "chi=64, C5, tol=0, D_F=4, compact-WY reflector application on tall "
+                            "blocks" % count,
+                "instances": count, "steps_each": steps, "ms_per_batched_step": 1000.0 * sec,
+                "aggregate_steps_per_s": agg, "aggregate_steps_per_s_by_instances": scaling,
+                "device_bytes": dev_bytes, "roofline": roof}
     # the same batched steps replayed from a captured graph (an ordinary
     # step from the layout, the capture, then the timed replays)
-    import torch
     bt.step_graph(True)
     bt.step(2)
     torch.cuda.synchronize()
@@ -560,6 +571,17 @@ def batched_metric(binding, count, steps, single_steps_per_s, smaller=(64, 128))
     caps, reps = bt.step_graph()
     graph = {"ms_per_batched_step": 1000.0 * gsec, "aggregate_steps_per_s": count / gsec,
              "speedup_vs_eager": sec / gsec, "captures": caps, "replays": reps}
+    bt.free()
+    torch.cuda.synchronize()
+    # the batch with FP32 / BF16 contractions (QR, SVD, Poisson and moments
+    # FP64; their one-step errors are those of the single state, leg `mixed`),
+    # one batch on the device at a time
+    mixed = {}
+    for name, prec in (("fp32", 1), ("bf16", 2)):
+        bm = _metric_batch(binding, count, precision=prec)
+        a, _ = _batch_rate(binding, bm, count, 2)
+        bm.free()
+        mixed[name] = {"aggregate_steps_per_s": a, "speedup_vs_fp64": a / agg}
     out = {"workload": "%d lock-step instances of two-stream 2^10 x 2^10, interleaved, chi=64, "
                        "C5, tol=0, D_F=4 (amplitudes 1e-3 (1 + i/10), seeded perturbations), "
                        "compact-WY reflector application on tall blocks" % count,
@@ -567,8 +589,8 @@ def batched_metric(binding, count, steps, single_steps_per_s, smaller=(64, 128))
            "aggregate_steps_per_s": agg,
            "speedup_vs_single_instance": agg / single_steps_per_s if single_steps_per_s else None,
            "aggregate_steps_per_s_by_instances": scaling,
-           "device_bytes": bt.instance(0).device_bytes(), "roofline": roof, "graph": graph}
-    bt.free()
+           "device_bytes": dev_bytes, "roofline": roof, "graph": graph,
+           "contraction_precision": mixed}
     return out
 
 
@@ -756,7 +778,8 @@ def main():
         return
 
     if args.batched_only:
-        print(json.dumps(batched_metric(binding, args.batch, args.steps, None, smaller=())))
+        print(json.dumps(batched_metric(binding, args.batch, args.steps, None, smaller=(),
+                                        extras=False)))
         return
 
     if args.serving_only:
