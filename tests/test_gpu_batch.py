@@ -114,6 +114,36 @@ def test_wy_reflectors_batch_equals_solo_and_oracle(B):
     bt.free()
 
 
+def test_forty_instances_equal_solo_in_the_compact_wy_mode(B):
+    """Forty lock-step instances (the launch-shape table's class of 32 or
+    more; two-stream 2^9, chi = 16, compact-WY mode with panel groups on its
+    640-row blocks) after two steps: instances 0, 17 and 39 equal the same
+    problems stepped alone, bit for bit."""
+    _say("batch of 40 == solo, compact-WY")
+    ws = []
+    for i in range(40):
+        w = wl.two_stream(L=9, chi=16, tol=0.0, level=5, df_max=4, dt_cfg=0.05)
+        w.problem.tall_apply = 1
+        ax, bv = wl.two_stream_profiles(w.problem, 0.2, 1e-3 * (1 + 0.05 * i))
+        ws.append(wl.Workload("forty_%d" % i, w.problem, ax, bv, 2))
+    bt = B.Batch([w.problem for w in ws], [(w.ax, w.bv) for w in ws])
+    p = ws[0].problem
+    perts = [wl.random_mps_cores(p.n_sites, 16, seed=400 + i) for i in range(40)]
+    amps = [1e-3] * 40
+    bt.add_scaled(amps, perts)
+    starts = [bt.instance(i).get_cores_host() for i in (0, 17, 39)]
+    bt.step(2)
+    for j, i in enumerate((0, 17, 39)):
+        st = S.gpu_state(B, ws[i], starts[j])
+        st.step(2)
+        a, b = bt.instance(i).get_cores_host(), st.get_cores_host()
+        assert [x.shape for x in a] == [x.shape for x in b], i
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y), i
+        st.free()
+    bt.free()
+
+
 @pytest.mark.parametrize("L,chi,tall", [(6, 16, 0), (9, 16, 1)])
 def test_batch_step_graph_replays_equal_eager_steps(B, L, chi, tall):
     """A lock-step batch (three instances) stepped from a captured graph: after
