@@ -102,6 +102,21 @@ def test_library_operator_bonds():
     assert [w.shape[3] for w in binding.operator(3, 6, 0, 1.0)[:-1]] == [2] * 5
 
 
+def test_qr_mode_and_batch_graph_arguments_are_rejected_without_a_gpu():
+    """mpsb_qr_tall refuses a reflector-application mode other than 0 or 1
+    and mpsb_batch_step_graph a NULL batch, before any device work."""
+    import ctypes
+    from paper_2205_11990_amd import binding
+    L = binding.lib()
+    fake = ctypes.c_void_p(8)  # never dereferenced: the checks come first
+    assert L.mpsb_qr_tall(4, 4, fake, None, 2, None) == binding.MPS_EINVAL
+    assert L.mpsb_qr_tall(4, 4, fake, None, -1, None) == binding.MPS_EINVAL
+    assert L.mpsb_qr_tall(0, 4, fake, None, 0, None) == binding.MPS_EINVAL
+    c, r = ctypes.c_int64(), ctypes.c_int64()
+    assert L.mpsb_batch_step_graph(None, 1, ctypes.byref(c), ctypes.byref(r)) == binding.MPS_EINVAL
+    assert "NULL" in L.mps_last_error().decode()
+
+
 def test_invalid_arguments_are_rejected_without_a_gpu():
     from paper_2205_11990_amd import binding
     with pytest.raises(binding.MpsError) as e:
