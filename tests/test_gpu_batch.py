@@ -271,6 +271,8 @@ def test_batch_failure_is_all_or_none(B):
         with pytest.raises(B.MpsError) as e:
             bt.step(1)
         assert e.value.status == B.MPS_ENUMERIC
+        # the message names the first failing instance
+        assert "instance 0: Jacobi SVD did not converge" in str(e.value)
     finally:
         B.set_jacobi_max_sweeps(60)
     for i in range(3):
